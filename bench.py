@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of the ambient-occlusion ray caster on one MI355X.
+
+Workload: the 26,318-object protein-like scene (13,159 spheres + 13,159
+cylinders, seeded random walk in a ball of radius 40) rendered at 3860x4548
+(17.6 MP, the paper's high-resolution case; Sec. 2, Table 3) with 16 AO
+samples per hit pixel, light rescale 0.3 and sky light 1.0, FP32 intersection
+with FP64 re-solve of grazing hits.
+
+One step = one pass of the whole hot path on the resident scene: the uniform
+grid rebuilt on the GPU from the resident FP64 arrays (bounds, count, scan,
+scatter, sort -- the "Preprocess" phase of Table 5) and the frame rendered
+(the "Ray Tracing" phase).  value = (primary + AO) rays per second over the
+timed steps.  The line also carries frames/s, p50/p99 frame latency, the plain
+FP64 GPU path on the same frame, the render kernel's roofline position and
+the CPU oracle's rate on a sample of the frame.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic flop model of the grid method (FP32-equivalent operations; FMA
+# = 2; add, mul, min, max, compare, sqrt, rcp, sin, cos = 1), per counted event.
+FLOP_COST = dict(ray_setup=40, cell=4, sph_test=22, sph_hit=4, cyl_test=45, cyl_hit=12,
+                 primary_gen=20, normal=10, per_light=8, onb=12, ao_dir=23, shade=10)
+PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # without packed-FP32 issue
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_flops(st: dict, n_lights: int, ao_on: bool) -> float:
+    c = FLOP_COST
+    return float(c["ray_setup"] * st["rays_traced"] + c["cell"] * st["cells"]
+                 + c["sph_test"] * st["sph_tests"] + c["sph_hit"] * st["sph_hits"]
+                 + c["cyl_test"] * st["cyl_tests"] + c["cyl_hit"] * st["cyl_hits"]
+                 + c["primary_gen"] * st["pixels"] + c["normal"] * st["hit_pixels"]
+                 + c["per_light"] * st["hit_pixels"] * n_lights
+                 + (c["onb"] * st["hit_pixels"] if ao_on else 0)
+                 + c["ao_dir"] * st["ao_rays"] + c["shade"] * st["pixels"])
+
+
+def cpu_baseline(scene, cam, params, target_s: float = 15.0) -> dict:
+    """The oracle, as it stands, on a bounded sample of the same frame: evenly
+    spaced full rows, sized to about target_s seconds of CPU work."""
+    import numpy as np
+
+    import oracle
+    oracle.build(force=False)
+    grid = oracle.Grid(scene, 4.0)
+    W, H = cam.width, cam.height
+    threads = oracle.max_threads()
+    # calibrate on a few rows
+    rows = np.arange(0, H, max(H // 16, 1))[:16]
+    pix = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
+    t0 = time.perf_counter()
+    r = oracle.render(scene, cam, params, grid=grid, pix=pix)
+    dt = time.perf_counter() - t0
+    per_row = dt / len(rows)
+    n_rows = int(min(H, max(len(rows), target_s / max(per_row, 1e-9))))
+    rows = np.unique(np.linspace(0, H - 1, n_rows).round().astype(np.int64))
+    pix = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
+    t0 = time.perf_counter()
+    r = oracle.render(scene, cam, params, grid=grid, pix=pix)
+    dt = time.perf_counter() - t0
+    cnt = r["counters"]
+    rays = cnt["primary_rays"] + cnt["ao_rays"]
+    return {"value": rays / dt, "unit": "rays/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d of %d rows (every ~%d-th row, %d pixels) of the same 3860x4548 frame, "
+                      "FP64, OpenMP over pixels, %.1f s" % (len(rows), H, max(H // len(rows), 1),
+                                                            len(pix), dt),
+            "seconds": dt, "rays": rays, "shadow_rays": cnt["shadow_rays"]}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64-frames", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--autotune", action="store_true", help="autotune the launch shape first")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(pixels would shard by interleaved tiles with one frame gather; not built).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_0801_1500_amd as tr
+    import scenegen
+
+    torch.cuda.set_device(0)
+    scene = scenegen.protein_scene(seed=2)
+    cam = scenegen.protein_camera(scenegen.RES_17MP)
+    params = scenegen.Params(ao_samples=16, seed=2)
+    prec = "fp32_resolve"
+    gs = tr.Scene(scene)
+    stream = torch.cuda.current_stream()
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    log("scene built", gs.grid_info()[2].tolist(), "refs", gs.grid_info()[3])
+
+    tune = None
+    tune_ms = None
+    if args.autotune:
+        tune, tune_ms = tr.autotune(gs, cam, params, precision=prec)
+        print("autotuned", tune, "%.2f ms" % tune_ms, file=sys.stderr, flush=True)
+    used_tune = dict(tune) if tune else tr.default_tune()
+
+    # exact algorithmic op counts of this frame (one counting launch)
+    cnt_frame = tr.alloc_frame(cam, ("rgb",), stats=True)
+    tr.render_into(gs, cam, params, cnt_frame, prec, tune=dict(used_tune, count_ops=1))
+    torch.cuda.synchronize()
+    st = dict(zip(tr.STAT_NAMES, cnt_frame["stats"].cpu().tolist()))
+    del cnt_frame
+    ao_on = params.ao_samples > 0 and params.skylight > 0
+    flops_frame = algorithmic_flops(st, scene.n_lights, ao_on)
+    rays_frame = st["pixels"] + st["ao_rays"]
+
+    log("counting launch done", st)
+    frame = tr.alloc_frame(cam, ("rgb",), stats=True)
+
+    def step():
+        gs.rebuild()
+        tr.render_into(gs, cam, params, frame, prec, tune=tune)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    frame["stats"].zero_()
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        ev[k][0].record(stream)
+        gs.rebuild()
+        ev[k][1].record(stream)
+        tr.render_into(gs, cam, params, frame, prec, tune=tune)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log("timed %d steps in %.3f s" % (K, wall))
+    step_ms = np.array([ev[k][0].elapsed_time(ev[k][2]) for k in range(K)])
+    build_ms = np.array([ev[k][0].elapsed_time(ev[k][1]) for k in range(K)])
+    render_ms = np.array([ev[k][1].elapsed_time(ev[k][2]) for k in range(K)])
+    tst = dict(zip(tr.STAT_NAMES, frame["stats"].cpu().tolist()))
+    rays_timed = tst["pixels"] + tst["ao_rays"]
+    assert rays_timed == K * rays_frame, (rays_timed, K * rays_frame)
+    ms_per_step = wall * 1000.0 / K
+    value = rays_timed / wall
+
+    achieved = flops_frame / (render_ms.mean() * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+                "kernel": "k_render_wave", "kernel_ms": float(render_ms.mean()),
+                "flop_per_frame": flops_frame, "flop_per_counted_ray": flops_frame / rays_frame}
+
+    # plain FP64 GPU path on the same frame
+    fp64 = None
+    if args.fp64_frames > 0:
+        f64 = tr.alloc_frame(cam, ("rgb",))
+        tr.render_into(gs, cam, params, f64, "fp64")
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.fp64_frames):
+            tr.render_into(gs, cam, params, f64, "fp64")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms64 = e0.elapsed_time(e1) / args.fp64_frames
+        fp64 = {"render_ms": ms64, "rays_per_s": rays_frame / (ms64 * 1e-3),
+                "speedup_fp32_over_fp64": ms64 / float(render_ms.mean())}
+        del f64
+        log("fp64 plain path", fp64)
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(scene, cam, params)
+        log("cpu baseline", cpu["value"], "rays/s on", cpu["cores"], "threads")
+
+    out = {
+        "metric": "rays/sec (primary+AO) and frames/s at 17.6 MP AO; p50/p99 frame latency",
+        "value": value, "unit": "rays/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "protein-like random walk, 13,159 spheres + 13,159 cylinders, "
+                               "3860x4548, 16 AO samples, light rescale 0.3, sky light 1.0, "
+                               "FP32 + FP64 re-solve; step = grid rebuild + render",
+                   "width": cam.width, "height": cam.height, "ao_samples": params.ao_samples,
+                   "precision": prec, "tune": used_tune, "parallelism": "1 GPU"},
+        "fps": 1000.0 / ms_per_step,
+        "frame_latency_ms_p50": float(np.percentile(step_ms, 50)),
+        "frame_latency_ms_p99": float(np.percentile(step_ms, 99)),
+        "render_ms_mean": float(render_ms.mean()), "build_ms_mean": float(build_ms.mean()),
+        "rays_per_frame": rays_frame, "shadow_rays_per_frame": st["shadow_rays"],
+        "hit_pixels": st["hit_pixels"], "op_counts": st,
+        "render_only_rays_per_s": rays_frame / (render_ms.mean() * 1e-3),
+        "fp64_plain": fp64,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "paper_context": "Tachyon on 6144 Blue Gene/L processors: 2.6416 s per 17.6 MP AO frame "
+                         "(0.379 frames/s), 822x a 3 GHz Pentium IV (Table 3)",
+    }
+    if tune_ms is not None:
+        out["autotune_ms"] = tune_ms
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

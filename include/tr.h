@@ -1,0 +1,283 @@
+/*
+ * tr.h -- C ABI of the MI355X (gfx950) ambient-occlusion ray caster.
+ *
+ * The calls follow the paper's statement of the problem (McGuigan, "Toward
+ * the Graphics Turing Scale on a Blue Gene Supercomputer", Sec. 2, Strong
+ * scaling): a molecular scene of spheres and cylinders, an image resolution
+ * given as width x height (the -res option), a rescale factor for the
+ * scene's direct lights (-rescale_lights), the strength of ambient-occlusion
+ * sky lighting computed by Monte Carlo sampling (-add_skylight), and an RGB
+ * frame out (the "Image I/O" phase of Table 5).  The acceleration build is
+ * the "Preprocess" phase and rendering is the "Ray Tracing" phase (Table 5).
+ *
+ * Conventions for every call:
+ *  - Plain C types only; no exception crosses the ABI.  Every call returns a
+ *    tr_status (or a value documented below) and records a message readable
+ *    through tr_last_error() on the calling thread.
+ *  - Host pointers are read only during the call and are copied; the caller
+ *    keeps ownership.  Device pointers (frame buffers, stats) are owned by
+ *    the caller, must be allocated on the current HIP device, and must stay
+ *    valid until the work enqueued on the given stream has completed.
+ *  - `hip_stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Render calls validate synchronously, enqueue, and return without
+ *    waiting; a device fault surfaces as TR_EDEVICE on a later call or on a
+ *    stream synchronisation.
+ *  - Results depend only on (scene, camera, params, pixel): never on batch
+ *    composition, tile shape, queue depth, cells per primitive, or the
+ *    order of primitive references (a determinism contract).
+ */
+#ifndef TR_H
+#define TR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TR_ABI_VERSION 1
+
+typedef enum {
+  TR_OK = 0,
+  TR_EINVAL = -1,        /* an argument failed validation; nothing enqueued */
+  TR_ENOMEM = -2,        /* device or host allocation failed                */
+  TR_EDEVICE = -3,       /* a HIP call failed (message has the HIP error)   */
+  TR_EUNSUPPORTED = -4   /* a valid request this build does not implement   */
+} tr_status;
+
+/* Arithmetic of the render.  The paper's renderer computes in double
+ * precision throughout (Sec. 2).  TR_PREC_FP64 is that plain FP64 path on
+ * the GPU (one thread per pixel).  TR_PREC_FP32 intersects and shades in
+ * FP32 in the persistent-wavefront kernel; TR_PREC_FP32_RESOLVE adds an
+ * FP64 re-solve of near-grazing sphere/cylinder tests (the default). */
+typedef enum {
+  TR_PREC_FP64 = 0,
+  TR_PREC_FP32 = 1,
+  TR_PREC_FP32_RESOLVE = 2
+} tr_precision;
+
+/* Opaque scene: primitives, albedo, lights and the uniform grid, resident on
+ * the device it was built on.  Immutable after build except through
+ * tr_scene_rebuild (which rebuilds the grid from the resident arrays). */
+typedef struct tr_scene tr_scene;
+
+/* Scene description (Sec. 2: the 26,318 "objects" of the molecular scene
+ * are spheres and cylinders).  Global primitive id: spheres [0, n_spheres),
+ * cylinders [n_spheres, n_spheres + n_cylinders).  Arrays are row-major
+ * xyz triples.  Any count may be 0 (an empty scene renders background). */
+typedef struct {
+  int64_t n_spheres;
+  const double *sph_center;  /* [n_spheres*3]                               */
+  const double *sph_radius;  /* [n_spheres], > 0                            */
+  const float *sph_rgb;      /* [n_spheres*3] albedo                        */
+  int64_t n_cylinders;
+  const double *cyl_a;       /* [n_cylinders*3] first end point             */
+  const double *cyl_b;       /* [n_cylinders*3] second end point, != cyl_a  */
+  const double *cyl_radius;  /* [n_cylinders], > 0                          */
+  const float *cyl_rgb;      /* [n_cylinders*3] albedo                      */
+  int32_t n_lights;          /* 0..8 directional lights                     */
+  const double *light_dir;   /* [n_lights*3] toward the light; normalised by the library */
+  const double *light_rgb;   /* [n_lights*3] intensity                      */
+  double cells_per_prim;     /* grid density lambda; 0 => 4.  Speed only.   */
+} tr_scene_desc;
+
+/* Pinhole camera, one ray through each pixel centre.  width = horizontal
+ * pixel count, height = vertical (the -res W H option, Sec. 2).  Row 0 of
+ * the frame is the top of the image, column 0 the left. */
+typedef struct {
+  double eye[3], lookat[3], up[3];
+  double fovy_deg;           /* vertical field of view, (0, 180)            */
+  int32_t width, height;     /* > 0, width*height <= 2^31 - 1               */
+} tr_camera;
+
+typedef struct {
+  double light_rescale;      /* -rescale_lights (paper: 0.3)                */
+  double skylight;           /* -add_skylight   (paper: 1.0); AO is cast only if > 0 */
+  int32_t ao_samples;        /* AO rays per hit pixel, 0..65535             */
+  double ao_maxdist;         /* AO ray length, > 0; INFINITY = unbounded    */
+  uint64_t seed;             /* Philox key (low word, high word)            */
+  uint32_t view_id;          /* third Philox counter word (frame / view)    */
+  int32_t precision;         /* tr_precision                                */
+  float background[3];       /* colour of pixels whose primary ray misses   */
+} tr_params;
+
+/* Device output buffers, caller-owned.  Only rgb is required.
+ *  rgb        float  [height][width][3], linear, clamped to [0, 1]
+ *  hit_id     int32  [height][width], global primitive id or -1 (miss)
+ *  ao_mask    uint32 [height][width], bit s = AO sample s occluded (needs
+ *             ao_samples <= 32 when non-NULL)
+ *  light_mask uint8  [height][width], bit l = light l cast a shadow ray and
+ *             it was blocked
+ *  stats      uint64 [TR_STAT_COUNT], counts ADDED atomically (zero it
+ *             first); NULL = no counting. */
+typedef struct {
+  float *rgb;
+  int32_t *hit_id;
+  uint32_t *ao_mask;
+  uint8_t *light_mask;
+  uint64_t *stats;
+} tr_frame;
+
+/* Indices into tr_frame.stats.  The first five are always exact; the
+ * traversal counters (cells onward) are filled only by precise-counting
+ * renders (tr_tune.count_ops = 1 or the FP64 path). */
+enum {
+  TR_STAT_PIXELS = 0,        /* primary rays                                */
+  TR_STAT_HIT_PIXELS,        /* primary rays that hit                       */
+  TR_STAT_AO_RAYS,           /* AO rays cast                                */
+  TR_STAT_SHADOW_RAYS,       /* light shadow rays cast (N.L > 0)            */
+  TR_STAT_RAYS_TRACED,       /* all rays handed to a traversal              */
+  TR_STAT_CELLS,             /* grid cells visited                          */
+  TR_STAT_SPH_TESTS,
+  TR_STAT_SPH_HITS,
+  TR_STAT_CYL_TESTS,
+  TR_STAT_CYL_HITS,
+  TR_STAT_RESOLVES,          /* FP64 re-solves of near-grazing tests        */
+  TR_STAT_COUNT
+};
+
+/* Launch shape of the persistent-wavefront kernel.  Any valid choice gives
+ * bit-identical frames; only speed changes.  Zero fields take defaults. */
+typedef struct {
+  int32_t tile_w;            /* tile width in pixels: 4, 8, 16 or 32; tiles hold 64 pixels */
+  int32_t banks;             /* pixel banks (tiles in flight) per wave: 2 or 3 (queue depth) */
+  int32_t waves_per_cu;      /* persistent waves launched per compute unit, 1..32 */
+  int32_t refill_below;      /* refill when fewer than this many lanes are busy, 1..64 */
+  int32_t count_ops;         /* 1 = also fill the traversal counters of tr_frame.stats */
+} tr_tune;
+
+/* ---------------------------------------------------------------- scenes */
+
+/* Validate the description, copy the arrays to the device (FP64 and packed
+ * FP32 structure-of-arrays), and build the uniform grid on the GPU: bounds
+ * reduction, per-cell counting, exclusive prefix scan, scatter of primitive
+ * references and an in-cell sort (the "Preprocess" phase, Table 5).  Blocks
+ * on the stream once to read back the scene bounds.  *out receives the new
+ * scene; TR_EINVAL on a NULL required pointer, negative count, non-finite
+ * coordinate, radius <= 0, zero-length cylinder, n_lights outside 0..8 or
+ * cells_per_prim < 0. */
+tr_status tr_scene_build(const tr_scene_desc *desc, void *hip_stream, tr_scene **out);
+
+/* Rebuild the grid from the resident device arrays (same result as the
+ * build's grid), with cells_per_prim (0 = keep the current value). */
+tr_status tr_scene_rebuild(tr_scene *scene, double cells_per_prim, void *hip_stream);
+
+/* Device bytes held by the scene (arrays + grid). */
+tr_status tr_scene_footprint(const tr_scene *scene, size_t *bytes);
+
+/* Grid shape: lo/hi bounds, resolution, reference count, and the grid's
+ * cells-per-primitive value. */
+tr_status tr_scene_grid_info(const tr_scene *scene, double lo[3], double hi[3], int32_t res[3],
+                             int64_t *n_refs);
+
+/* Copy the grid arrays to HOST buffers: cell_begin [n_cells+1] and refs
+ * [n_refs] (either may be NULL).  Synchronises the stream. */
+tr_status tr_scene_grid_arrays(const tr_scene *scene, uint32_t *cell_begin, uint32_t *refs,
+                               void *hip_stream);
+
+/* Free the scene's device memory.  The caller guarantees no enqueued work
+ * still uses it (the call synchronises the device before freeing). */
+void tr_scene_destroy(tr_scene *scene);
+
+/* ---------------------------------------------------------------- render */
+
+/* Render one frame (the "Ray Tracing" phase, Table 5): per pixel, the
+ * nearest hit of the camera ray; on a hit, the viewer-facing normal, one
+ * shadow ray per light with N.L > 0, and params->ao_samples AO rays drawn
+ * from the cosine-weighted hemisphere with Philox4x32-10 uniforms keyed by
+ * (pixel, sample, view_id) and seed; colour = clamp(albedo * (light_rescale
+ * * sum_l I_l (N.L_l) V_l + skylight * AO), 0, 1).  Enqueued on the
+ * stream.  TR_EINVAL on a NULL scene/camera/params/frame->rgb, width or
+ * height <= 0 or width*height >= 2^31, fovy outside (0, 180), eye == lookat,
+ * up parallel to the view direction, non-finite camera, ao_samples outside
+ * 0..65535, ao_maxdist <= 0, ao_mask requested with ao_samples > 32, or an
+ * unknown precision. */
+tr_status tr_render(const tr_scene *scene, const tr_camera *cam, const tr_params *params,
+                    const tr_frame *frame, void *hip_stream);
+
+/* tr_render with an explicit launch shape (NULL = the tuned or default
+ * shape).  TR_EINVAL on an invalid tune field. */
+tr_status tr_render_tuned(const tr_scene *scene, const tr_camera *cam, const tr_params *params,
+                          const tr_frame *frame, const tr_tune *tune, void *hip_stream);
+
+/* Render n frames in ONE persistent launch whose tile queue spans all n
+ * jobs (scenes may differ; job i uses scenes[i], cams[i], params[i],
+ * frames[i]).  All jobs must use an FP32 precision; TR_PREC_FP64 jobs are
+ * rendered one launch each.  1 <= n <= 4096. */
+tr_status tr_render_batch(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,
+                          const tr_params *params, const tr_frame *frames, void *hip_stream);
+
+/* Number of 64-pixel tiles of a width x height frame for tile width tile_w
+ * (0 = default).  Returns -1 on invalid arguments. */
+int64_t tr_tile_count(int32_t width, int32_t height, int32_t tile_w);
+
+/* Batch render restricted to tiles [tile_begin[i], tile_end[i]) of each
+ * job (row-major tile order for the given tile width), so a serving loop can
+ * advance many frames a bounded step at a time.  Pixels outside the ranges
+ * are left untouched.  FP32 precisions only. */
+tr_status tr_render_batch_tiles(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,
+                                const tr_params *params, const tr_frame *frames,
+                                const int64_t *tile_begin, const int64_t *tile_end,
+                                const tr_tune *tune, void *hip_stream);
+
+/* Bytes of device memory a frame of this camera needs for the outputs named
+ * by frame_flags (bit 0 rgb, bit 1 hit_id, bit 2 ao_mask, bit 3 light_mask);
+ * 0 on invalid arguments. */
+size_t tr_frame_footprint(const tr_camera *cam, const tr_params *params, uint32_t frame_flags);
+
+/* ------------------------------------------------ graphs (batched views) */
+
+/* A captured, replayable batch render: the tile-counter reset and the
+ * persistent launch recorded once into a hipGraph.  Cameras live in a
+ * device job table, so tr_graph_set_cameras changes views without
+ * re-capturing.  Same restrictions as tr_render_batch. */
+typedef struct tr_graph tr_graph;
+
+tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,
+                          const tr_params *params, const tr_frame *frames, const tr_tune *tune,
+                          void *hip_stream, tr_graph **out);
+/* Update the n cameras (same resolutions as at creation) and/or params
+ * (either may be NULL); the job table upload is enqueued on the stream
+ * before any later tr_graph_launch on that stream. */
+tr_status tr_graph_update(tr_graph *g, const tr_camera *cams, const tr_params *params,
+                          void *hip_stream);
+tr_status tr_graph_launch(tr_graph *g, void *hip_stream);
+void tr_graph_destroy(tr_graph *g);
+
+/* ----------------------------------------------------------- autotuning */
+
+/* Time the candidate launch shapes on this (scene, camera, params) and keep
+ * the fastest in a process-wide cache keyed by (device, primitive-count
+ * bucket, resolution, AO samples, precision); later renders with a NULL tune
+ * use it.  Checks that every candidate gives a bit-identical frame
+ * (TR_EDEVICE with a message if not).  *best (may be NULL) receives the
+ * choice; *best_ms (may be NULL) its time.  Synchronises the stream. */
+tr_status tr_autotune(const tr_scene *scene, const tr_camera *cam, const tr_params *params,
+                      void *hip_stream, tr_tune *best, double *best_ms);
+
+/* Default launch shape for the current device. */
+tr_status tr_default_tune(tr_tune *out);
+
+/* ---------------------------------------------------------------- debug */
+
+/* Philox4x32-10 on the device, for bit-identity checks: out[4i..4i+3] =
+ * Philox(ctr[4i..4i+3], key[2i..2i+1]).  Device pointers, n >= 0. */
+tr_status tr_debug_philox(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out,
+                          void *hip_stream);
+
+/* AO directions as the FP32 kernel draws them: for each i, normal
+ * n[3i..3i+2] (unit), pixel pix[i], sample s[i] -> w[3i..3i+2].  Device
+ * pointers. */
+tr_status tr_debug_ao_dirs(int64_t n, const float *normals, const uint32_t *pix,
+                           const uint32_t *sample, uint32_t view_id, uint64_t seed, float *w,
+                           void *hip_stream);
+
+/* Thread-local message for the last failing call on this thread. */
+const char *tr_last_error(void);
+int32_t tr_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TR_H */

@@ -263,20 +263,3 @@ def render(scene, cam, params, grid=None, pix: Optional[np.ndarray] = None,
 
 def max_threads() -> int:
     return int(lib().or_max_threads())
-
-
-# Algorithmic flop model: FP32-equivalent operation costs per counted event
-# (FMA = 2; add, mul, min, max, compare, sqrt, rcp, sin, cos = 1).
-FLOP_COST = dict(ray_setup=40, cell=4, sph_test=22, sph_hit=4, cyl_test=45, cyl_hit=12,
-                 primary_gen=20, normal=10, per_light=8, onb=12, ao_dir=23, shade=10)
-
-
-def algorithmic_flops(cnt: dict, n_lights: int, ao_on: bool) -> float:
-    c = FLOP_COST
-    return float(c["ray_setup"] * cnt["rays_traced"] + c["cell"] * cnt["cells"]
-                 + c["sph_test"] * cnt["sph_tests"] + c["sph_hit"] * cnt["sph_hits"]
-                 + c["cyl_test"] * cnt["cyl_tests"] + c["cyl_hit"] * cnt["cyl_hits"]
-                 + c["primary_gen"] * cnt["primary_rays"] + c["normal"] * cnt["hit_pixels"]
-                 + c["per_light"] * cnt["hit_pixels"] * n_lights
-                 + (c["onb"] * cnt["hit_pixels"] if ao_on else 0)
-                 + c["ao_dir"] * cnt["ao_rays"] + c["shade"] * cnt["pixels"])

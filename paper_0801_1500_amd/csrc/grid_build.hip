@@ -1,0 +1,383 @@
+// grid_build.hip -- GPU build of the uniform grid (the "Preprocess" phase of
+// the paper's Table 5): FP64 scene packing, bounds reduction, per-cell
+// counting, exclusive prefix scan, scatter of primitive references, and an
+// in-cell sort that makes the reference order deterministic.
+//
+// Compiled with -ffp-contract=off: the cell lists must equal, bit for bit,
+// those of the grid definition (primitive boxes widened by delta, spheres
+// kept only where their centre lies within r of the widened cell box).
+#include "tr_internal.h"
+
+namespace {
+
+using namespace trd;
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ void prim_box(const trh::BuildArgs &a, int64_t k, double lo[3],
+                                         double hi[3]) {
+  if (k < a.n_s) {
+    const double4 s = a.sph64[k];
+    lo[0] = s.x - s.w; lo[1] = s.y - s.w; lo[2] = s.z - s.w;
+    hi[0] = s.x + s.w; hi[1] = s.y + s.w; hi[2] = s.z + s.w;
+  } else {
+    const int64_t m = k - a.n_s;
+    const double4 A = a.cylA64[m], B = a.cylB64[m];
+    const double av[3] = {A.x, A.y, A.z}, bv[3] = {B.x, B.y, B.z};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double mn = av[q] < bv[q] ? av[q] : bv[q];
+      const double mx = av[q] < bv[q] ? bv[q] : av[q];
+      lo[q] = mn - A.w;
+      hi[q] = mx + A.w;
+    }
+  }
+}
+
+__device__ __forceinline__ int32_t cell_coord(const trh::BuildArgs &a, int q, double x) {
+  const double f = floor((x - a.lo[q]) * a.inv[q]);
+  if (!(f >= 0.0)) return 0;
+  if (f > (double)(a.res[q] - 1)) return a.res[q] - 1;
+  return (int32_t)f;
+}
+
+__device__ __forceinline__ bool sphere_in_cell(const trh::BuildArgs &a, const double4 s,
+                                               int32_t ix, int32_t iy, int32_t iz) {
+  const int32_t idx[3] = {ix, iy, iz};
+  const double c[3] = {s.x, s.y, s.z};
+  double d2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double cl = (a.lo[q] + (double)idx[q] * a.h[q]) - a.delta;
+    const double ch = (a.lo[q] + (double)(idx[q] + 1) * a.h[q]) + a.delta;
+    double e = 0.0;
+    if (c[q] < cl) e = cl - c[q];
+    else if (c[q] > ch) e = c[q] - ch;
+    d2 = d2 + e * e;
+  }
+  return d2 <= s.w * s.w;
+}
+
+// Visit every cell primitive k is listed in.
+template <class F>
+__device__ __forceinline__ void for_prim_cells(const trh::BuildArgs &a, int64_t k, F &&visit) {
+  double lo[3], hi[3];
+  prim_box(a, k, lo, hi);
+  int32_t c0[3], c1[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    c0[q] = cell_coord(a, q, lo[q] - a.delta);
+    c1[q] = cell_coord(a, q, hi[q] + a.delta);
+  }
+  const bool sph = k < a.n_s;
+  double4 s = make_double4(0, 0, 0, 0);
+  if (sph) s = a.sph64[k];
+  for (int32_t iz = c0[2]; iz <= c1[2]; ++iz)
+    for (int32_t iy = c0[1]; iy <= c1[1]; ++iy)
+      for (int32_t ix = c0[0]; ix <= c1[0]; ++ix) {
+        if (sph && !sphere_in_cell(a, s, ix, iy, iz)) continue;
+        visit((uint32_t)(((int64_t)iz * a.res[1] + iy) * a.res[0] + ix));
+      }
+}
+
+__global__ void k_pack(int64_t n_s, int64_t n_c, const double *sc, const double *sr,
+                       const float *srgb, const double *ca, const double *cb, const double *cr,
+                       const float *crgb, double4 *sph64, double4 *cylA64, double4 *cylW64,
+                       double4 *cylB64, float4 *albedo) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_s) {
+    sph64[k] = make_double4(sc[3 * k], sc[3 * k + 1], sc[3 * k + 2], sr[k]);
+    albedo[k] = make_float4(srgb[3 * k], srgb[3 * k + 1], srgb[3 * k + 2], 0.0f);
+  } else if (k < n_s + n_c) {
+    const int64_t m = k - n_s;
+    const double a[3] = {ca[3 * m], ca[3 * m + 1], ca[3 * m + 2]};
+    const double b[3] = {cb[3 * m], cb[3 * m + 1], cb[3 * m + 2]};
+    const double ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double L = sqrt((ab[0] * ab[0] + ab[1] * ab[1]) + ab[2] * ab[2]);
+    cylA64[m] = make_double4(a[0], a[1], a[2], cr[m]);
+    cylW64[m] = make_double4(ab[0] / L, ab[1] / L, ab[2] / L, L);
+    cylB64[m] = make_double4(b[0], b[1], b[2], 0.0);
+    albedo[k] = make_float4(crgb[3 * m], crgb[3 * m + 1], crgb[3 * m + 2], 0.0f);
+  }
+}
+
+__global__ void k_pack32(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
+                         const double4 *cylW64, float4 *sph32, float4 *cylA32, float4 *cylW32) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_s) {
+    const double4 s = sph64[k];
+    sph32[k] = make_float4((float)s.x, (float)s.y, (float)s.z, (float)s.w);
+  } else if (k < n_s + n_c) {
+    const int64_t m = k - n_s;
+    const double4 a = cylA64[m], w = cylW64[m];
+    cylA32[m] = make_float4((float)a.x, (float)a.y, (float)a.z, (float)a.w);
+    cylW32[m] = make_float4((float)w.x, (float)w.y, (float)w.z, (float)w.w);
+  }
+}
+
+// Per-block min/max of primitive boxes -> scratch[block*6 .. +6].
+__global__ __launch_bounds__(kBlock) void k_bounds_partial(int64_t n_s, int64_t n_c,
+                                                           const double4 *sph64,
+                                                           const double4 *cylA64,
+                                                           const double4 *cylB64, double *part) {
+  __shared__ double red[6][kBlock];
+  trh::BuildArgs a{};
+  a.n_s = (int32_t)n_s;
+  a.n_c = (int32_t)n_c;
+  a.sph64 = sph64;
+  a.cylA64 = cylA64;
+  a.cylB64 = cylB64;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  const int64_t N = n_s + n_c;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < N;
+       k += (int64_t)gridDim.x * kBlock) {
+    double bl[3], bh[3];
+    prim_box(a, k, bl, bh);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      lo[q] = bl[q] < lo[q] ? bl[q] : lo[q];
+      hi[q] = bh[q] > hi[q] ? bh[q] : hi[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    red[q][threadIdx.x] = lo[q];
+    red[3 + q][threadIdx.x] = hi[q];
+  }
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double x = red[q][threadIdx.x + s];
+        if (x < red[q][threadIdx.x]) red[q][threadIdx.x] = x;
+        const double y = red[3 + q][threadIdx.x + s];
+        if (y > red[3 + q][threadIdx.x]) red[3 + q][threadIdx.x] = y;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[(int64_t)blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_bounds_final(const double *part, int32_t n_part,
+                                                         double *out6) {
+  __shared__ double red[6][kBlock];
+  double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int32_t b = threadIdx.x; b < n_part; b += kBlock) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double x = part[(int64_t)b * 6 + q];
+      const double y = part[(int64_t)b * 6 + 3 + q];
+      v[q] = x < v[q] ? x : v[q];
+      v[3 + q] = y > v[3 + q] ? y : v[3 + q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) red[q][threadIdx.x] = v[q];
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double x = red[q][threadIdx.x + s];
+        if (x < red[q][threadIdx.x]) red[q][threadIdx.x] = x;
+        const double y = red[3 + q][threadIdx.x + s];
+        if (y > red[3 + q][threadIdx.x]) red[3 + q][threadIdx.x] = y;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) out6[threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_count(trh::BuildArgs a, uint32_t *count) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)a.n_s + a.n_c) return;
+  for_prim_cells(a, k, [&](uint32_t c) { atomicAdd(&count[c], 1u); });
+}
+
+__global__ void k_scatter(trh::BuildArgs a, const uint32_t *cell_begin, uint32_t *cursor,
+                          uint32_t *refs) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)a.n_s + a.n_c) return;
+  for_prim_cells(a, k, [&](uint32_t c) {
+    const uint32_t pos = atomicAdd(&cursor[c], 1u);
+    refs[cell_begin[c] + pos] = (uint32_t)k;
+  });
+}
+
+// Insertion sort inside each cell (lists are short).
+__global__ void k_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32_t *refs) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  const uint32_t b = cell_begin[c], e = cell_begin[c + 1];
+  for (uint32_t i = b + 1; i < e; ++i) {
+    const uint32_t v = refs[i];
+    uint32_t j = i;
+    while (j > b && refs[j - 1] > v) {
+      refs[j] = refs[j - 1];
+      --j;
+    }
+    refs[j] = v;
+  }
+}
+
+// ---- exclusive scan: blocks of kScanItems, block sums scanned recursively
+constexpr int kScanPer = 4;
+constexpr int kScanItems = kBlock * kScanPer;
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
+  // Hillis-Steele over kBlock values in shared memory
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const uint32_t add = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  total = sh[kBlock - 1];
+  const uint32_t incl = sh[threadIdx.x];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_block(uint32_t *data, int64_t n, uint32_t *sums) {
+  __shared__ uint32_t sh[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * kScanPer;
+  uint32_t v[kScanPer];
+  uint32_t run = 0;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    v[q] = base + q < n ? data[base + q] : 0u;
+    run += v[q];
+  }
+  uint32_t total;
+  uint32_t off = block_excl_scan(run, sh, total);
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    if (base + q < n) data[base + q] = off;
+    off += v[q];
+  }
+  if (threadIdx.x == 0 && sums) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t *data, int64_t n,
+                                                     const uint32_t *offs) {
+  const uint32_t add = offs[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * kScanPer;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q)
+    if (base + q < n) data[base + q] += add;
+}
+
+inline unsigned blocks_for(int64_t n, int b = kBlock) {
+  return (unsigned)((n + b - 1) / b);
+}
+
+}  // namespace
+
+namespace trh {
+
+hipError_t launch_pack(int64_t n_s, int64_t n_c, const double *sc, const double *sr,
+                       const float *srgb, const double *ca, const double *cb, const double *cr,
+                       const float *crgb, double4 *sph64, double4 *cylA64, double4 *cylW64,
+                       double4 *cylB64, float4 *albedo, hipStream_t st) {
+  const int64_t N = n_s + n_c;
+  if (N == 0) return hipSuccess;
+  k_pack<<<blocks_for(N), kBlock, 0, st>>>(n_s, n_c, sc, sr, srgb, ca, cb, cr, crgb, sph64, cylA64,
+                                           cylW64, cylB64, albedo);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack32(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
+                         const double4 *cylW64, float4 *sph32, float4 *cylA32, float4 *cylW32,
+                         hipStream_t st) {
+  const int64_t N = n_s + n_c;
+  if (N == 0) return hipSuccess;
+  k_pack32<<<blocks_for(N), kBlock, 0, st>>>(n_s, n_c, sph64, cylA64, cylW64, sph32, cylA32,
+                                             cylW32);
+  return hipGetLastError();
+}
+
+static int32_t bounds_blocks(int64_t N) {
+  int64_t b = (N + kBlock * 8 - 1) / (kBlock * 8);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int32_t)b;
+}
+
+int64_t bounds_scratch_doubles(int64_t n_prims) { return 6 * (int64_t)bounds_blocks(n_prims); }
+
+hipError_t launch_bounds(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
+                         const double4 *cylB64, double *scratch, double *out6, hipStream_t st) {
+  const int32_t nb = bounds_blocks(n_s + n_c);
+  k_bounds_partial<<<nb, kBlock, 0, st>>>(n_s, n_c, sph64, cylA64, cylB64, scratch);
+  k_bounds_final<<<1, kBlock, 0, st>>>(scratch, nb, out6);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t b = blocks_for(n);
+  if (b > 65536) b = 65536;
+  k_fill_u32<<<(unsigned)b, kBlock, 0, st>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_count(const BuildArgs &a, uint32_t *count, hipStream_t st) {
+  const int64_t N = (int64_t)a.n_s + a.n_c;
+  if (N == 0) return hipSuccess;
+  k_count<<<blocks_for(N), kBlock, 0, st>>>(a, count);
+  return hipGetLastError();
+}
+
+int64_t scan_scratch_u32(int64_t n) {
+  int64_t total = 0;
+  while (n > kScanItems) {
+    n = (n + kScanItems - 1) / kScanItems;
+    total += n;
+  }
+  return total + 1;
+}
+
+hipError_t launch_scan(uint32_t *data, int64_t n, uint32_t *scratch, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (n <= kScanItems) {
+    k_scan_block<<<1, kBlock, 0, st>>>(data, n, nullptr);
+    return hipGetLastError();
+  }
+  const int64_t nb = (n + kScanItems - 1) / kScanItems;
+  uint32_t *sums = scratch;
+  k_scan_block<<<(unsigned)nb, kBlock, 0, st>>>(data, n, sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_scan(sums, nb, scratch + nb, st);
+  if (e != hipSuccess) return e;
+  k_scan_add<<<(unsigned)nb, kBlock, 0, st>>>(data, n, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const BuildArgs &a, const uint32_t *cell_begin, uint32_t *cursor,
+                          uint32_t *refs, hipStream_t st) {
+  const int64_t N = (int64_t)a.n_s + a.n_c;
+  if (N == 0) return hipSuccess;
+  k_scatter<<<blocks_for(N), kBlock, 0, st>>>(a, cell_begin, cursor, refs);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32_t *refs,
+                             hipStream_t st) {
+  if (n_cells <= 0) return hipSuccess;
+  k_sort_cells<<<blocks_for(n_cells), kBlock, 0, st>>>(cell_begin, n_cells, refs);
+  return hipGetLastError();
+}
+
+}  // namespace trh

@@ -1,0 +1,253 @@
+// render_plain.hip -- the plain double-precision GPU path: one thread per
+// pixel, every step in FP64, no queues.  This is the GPU counterpart of the
+// paper's renderer as it was built ("double precision option for all
+// calculations", Sec. 2) and the baseline the FP32 wavefront kernel is
+// measured against.
+//
+// Compiled with -ffp-contract=off and written in the same expression order
+// as the definition of the method (camera, intersections, normals,
+// sampling, shading), so that primary hits reproduce bit for bit.
+#include "tr_internal.h"
+
+namespace {
+
+using namespace trd;
+
+constexpr double kEps = 1e-4;  // secondary-ray t_min (world units)
+
+struct Cnt {
+  uint32_t rays, cells, st, sh, ct, ch;
+};
+
+__device__ __forceinline__ int32_t cell_coord(const SceneDev &S, int q, double x) {
+  const double f = floor((x - S.lo[q]) * S.inv[q]);
+  if (!(f >= 0.0)) return 0;
+  if (f > (double)(S.res[q] - 1)) return S.res[q] - 1;
+  return (int32_t)f;
+}
+
+__device__ __forceinline__ double boundary_t(const SceneDev &S, int q, int32_t idx, int step,
+                                             const double o[3], const double d[3]) {
+  const int32_t plane = step > 0 ? idx + 1 : idx;
+  return ((S.lo[q] + (double)plane * S.h[q]) - o[q]) / d[q];
+}
+
+// Nearest hit (lexicographic min of (t, id)) or any hit with t in
+// (tmin, tmax], walking the grid cells along the ray (3D-DDA).
+template <bool ANY>
+__device__ int trace_f64(const SceneDev &S, const double o[3], const double d[3], double tmin,
+                         double tmax, int32_t skip, double &bt, int32_t &bk, Cnt &c) {
+  c.rays++;
+  bool found = false;
+  bt = INFINITY;
+  bk = -1;
+  double t0 = tmin, t1 = tmax;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (d[q] != 0.0) {
+      double ta = (S.lo[q] - o[q]) / d[q];
+      double tb = (S.hi[q] - o[q]) / d[q];
+      if (ta > tb) {
+        const double x = ta;
+        ta = tb;
+        tb = x;
+      }
+      if (ta > t0) t0 = ta;
+      if (tb < t1) t1 = tb;
+    } else if (o[q] < S.lo[q] || o[q] > S.hi[q]) {
+      return 0;
+    }
+  }
+  if (t0 > t1) return 0;
+  int32_t idx[3], step[3];
+  double tn[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    idx[q] = cell_coord(S, q, o[q] + t0 * d[q]);
+    if (d[q] > 0.0) {
+      step[q] = 1;
+      tn[q] = boundary_t(S, q, idx[q], 1, o, d);
+    } else if (d[q] < 0.0) {
+      step[q] = -1;
+      tn[q] = boundary_t(S, q, idx[q], -1, o, d);
+    } else {
+      step[q] = 0;
+      tn[q] = INFINITY;
+    }
+  }
+  for (;;) {
+    c.cells++;
+    const int64_t cell = ((int64_t)idx[2] * S.res[1] + idx[1]) * S.res[0] + idx[0];
+    const uint32_t e = S.cell_begin[cell + 1];
+    for (uint32_t r = S.cell_begin[cell]; r < e; ++r) {
+      const int32_t k = (int32_t)S.refs[r];
+      if (k == skip) continue;
+      double t;
+      int h;
+      if (k < S.n_s) {
+        c.st++;
+        h = hit_sphere_f64(S.sph64[k], o, d, tmin, tmax, t);
+        c.sh += h;
+      } else {
+        c.ct++;
+        h = hit_cylinder_f64(S.cylA64[k - S.n_s], S.cylW64[k - S.n_s], o, d, tmin, tmax, t);
+        c.ch += h;
+      }
+      if (h) {
+        if (ANY) {
+          bt = t;
+          bk = k;
+          return 1;
+        }
+        if (!found || t < bt || (t == bt && k < bk)) {
+          found = true;
+          bt = t;
+          bk = k;
+        }
+      }
+    }
+    int a = 0;
+    if (tn[1] < tn[a]) a = 1;
+    if (tn[2] < tn[a]) a = 2;
+    const double t_exit = tn[a] < t1 ? tn[a] : t1;
+    if (!ANY && found && bt <= t_exit) return 1;
+    if (tn[a] >= t1) return found;
+    idx[a] += step[a];
+    if (idx[a] < 0 || idx[a] >= S.res[a]) return found;
+    tn[a] = boundary_t(S, a, idx[a], step[a], o, d);
+  }
+}
+
+__device__ __forceinline__ void normal_f64(const SceneDev &S, int32_t k, const double o[3],
+                                           const double d[3], double t, double n[3]) {
+  if (k < S.n_s) {
+    const double4 s = S.sph64[k];
+    const double P[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+    n[0] = (P[0] - s.x) / s.w;
+    n[1] = (P[1] - s.y) / s.w;
+    n[2] = (P[2] - s.z) / s.w;
+  } else {
+    const double4 a = S.cylA64[k - S.n_s], w4 = S.cylW64[k - S.n_s];
+    const double w[3] = {w4.x, w4.y, w4.z};
+    const double D[3] = {o[0] - a.x, o[1] - a.y, o[2] - a.z};
+    const double sax = dot3d(D, w) + t * dot3d(d, w);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) n[q] = ((D[q] + t * d[q]) - sax * w[q]) / a.w;
+  }
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64_t *stats) {
+  __shared__ uint32_t red[TR_STAT_COUNT];
+  if (STATS) {
+    if (threadIdx.x < TR_STAT_COUNT) red[threadIdx.x] = 0;
+    __syncthreads();
+  }
+  const int32_t i = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int32_t j = blockIdx.y * 16 + (threadIdx.x >> 4);
+  Cnt c{0, 0, 0, 0, 0, 0};
+  uint32_t n_hit = 0, n_ao = 0, n_sh = 0;
+  if (i < J.W && j < J.H) {
+    const SceneDev &S = J.sc;
+    const int64_t pid = (int64_t)j * J.W + i;
+    double o[3], d[3];
+    primary_ray_f64(J, i, j, o, d);
+    double t;
+    int32_t k;
+    const int hit = trace_f64<false>(S, o, d, 0.0, INFINITY, -1, t, k, c);
+    double col[3] = {(double)J.bg[0], (double)J.bg[1], (double)J.bg[2]};
+    uint32_t amask = 0;
+    uint32_t lmask = 0;
+    if (hit) {
+      n_hit = 1;
+      double N[3], P[3];
+      normal_f64(S, k, o, d, t, N);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) P[q] = o[q] + t * d[q];
+      const bool front = dot3d(N, d) < 0.0;
+      if (!front) {
+        N[0] = -N[0];
+        N[1] = -N[1];
+        N[2] = -N[2];
+      }
+      const int32_t skip = front ? k : -1;
+      double D[3] = {0.0, 0.0, 0.0};
+      for (int l = 0; l < J.n_lights; ++l) {
+        const double cl = dot3d(N, J.ldir[l]);
+        if (!(cl > 0.0)) continue;
+        n_sh++;
+        double tt;
+        int32_t kk;
+        if (trace_f64<true>(S, P, J.ldir[l], kEps, INFINITY, skip, tt, kk, c)) {
+          lmask |= 1u << l;
+        } else {
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) D[ch] += J.lcol[l][ch] * cl;
+        }
+      }
+      double ao = 1.0;
+      if (J.S > 0) {
+        int32_t aocc = 0;
+        for (int s = 0; s < J.S; ++s) {
+          uint32_t b1, b2;
+          ao_uniform_bits((uint32_t)pid, (uint32_t)s, J.view_id, J.key0, J.key1, b1, b2);
+          double w[3];
+          ao_dir_f64(N, b1, b2, w);
+          n_ao++;
+          double tt;
+          int32_t kk;
+          if (trace_f64<true>(S, P, w, kEps, J.ao_maxdist, skip, tt, kk, c)) {
+            aocc++;
+            if (s < 32) amask |= 1u << s;
+          }
+        }
+        ao = (double)(J.S - aocc) / (double)J.S;
+      }
+      const float4 alb = S.albedo[k];
+      const double albv[3] = {(double)alb.x, (double)alb.y, (double)alb.z};
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const double v = albv[ch] * (D[ch] + J.sky * ao);
+        col[ch] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+      }
+    }
+    J.rgb[pid * 3 + 0] = (float)col[0];
+    J.rgb[pid * 3 + 1] = (float)col[1];
+    J.rgb[pid * 3 + 2] = (float)col[2];
+    if (J.hit_id) J.hit_id[pid] = hit ? k : -1;
+    if (J.ao_mask) J.ao_mask[pid] = amask;
+    if (J.light_mask) J.light_mask[pid] = (uint8_t)lmask;
+    if (STATS) {
+      atomicAdd(&red[TR_STAT_PIXELS], 1u);
+      atomicAdd(&red[TR_STAT_HIT_PIXELS], n_hit);
+      atomicAdd(&red[TR_STAT_AO_RAYS], n_ao);
+      atomicAdd(&red[TR_STAT_SHADOW_RAYS], n_sh);
+      atomicAdd(&red[TR_STAT_RAYS_TRACED], c.rays);
+      atomicAdd(&red[TR_STAT_CELLS], c.cells);
+      atomicAdd(&red[TR_STAT_SPH_TESTS], c.st);
+      atomicAdd(&red[TR_STAT_SPH_HITS], c.sh);
+      atomicAdd(&red[TR_STAT_CYL_TESTS], c.ct);
+      atomicAdd(&red[TR_STAT_CYL_HITS], c.ch);
+    }
+  }
+  if (STATS) {
+    __syncthreads();
+    if (threadIdx.x < TR_STAT_COUNT && red[threadIdx.x])
+      atomicAdd((unsigned long long *)&stats[threadIdx.x], (unsigned long long)red[threadIdx.x]);
+  }
+}
+
+}  // namespace
+
+namespace trh {
+
+hipError_t launch_render_plain_f64(const trd::JobDev &job, uint64_t *stats, hipStream_t st) {
+  dim3 grid((unsigned)((job.W + 15) / 16), (unsigned)((job.H + 15) / 16));
+  if (stats)
+    k_render_plain_f64<true><<<grid, 256, 0, st>>>(job, stats);
+  else
+    k_render_plain_f64<false><<<grid, 256, 0, st>>>(job, nullptr);
+  return hipGetLastError();
+}
+
+}  // namespace trh

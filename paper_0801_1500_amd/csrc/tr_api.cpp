@@ -1,0 +1,1037 @@
+// tr_api.cpp -- the C ABI (include/tr.h): validation, scene build
+// orchestration, job tables, launches, graphs and the autotuner.
+//
+// Host arithmetic that feeds bit-exact device work (camera basis, light
+// normalisation, grid parameters) is compiled with -ffp-contract=off and
+// written in the order of the method's definition.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "tr_internal.h"
+
+using trd::JobDev;
+using trd::SceneDev;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static tr_status fail(tr_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? TR_ENOMEM : TR_EDEVICE, "%s: %s (%s)",    \
+                  #expr, hipGetErrorName(e_), hipGetErrorString(e_));                  \
+  } while (0)
+
+static bool finite3(const double *v) {
+  return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+// ------------------------------------------------------------------ scene
+struct tr_scene {
+  int device = 0;
+  int32_t key = 0;
+  int64_t n_s = 0, n_c = 0;
+  int32_t n_lights = 0;
+  double ldir[8][3] = {};
+  double lrgb[8][3] = {};
+  double lambda = 4.0;
+  // device arrays
+  double4 *sph64 = nullptr, *cylA64 = nullptr, *cylW64 = nullptr, *cylB64 = nullptr;
+  float4 *sph32 = nullptr, *cylA32 = nullptr, *cylW32 = nullptr, *albedo = nullptr;
+  uint32_t *cell_begin = nullptr, *refs = nullptr, *count = nullptr, *scan_scratch = nullptr;
+  double *bounds_scratch = nullptr, *bounds = nullptr;
+  int64_t cap_cells = 0, cap_refs = 0, cap_scan = 0;
+  size_t bytes_arrays = 0;
+  // pinned readback
+  double *h_bounds = nullptr;
+  uint32_t *h_total = nullptr;
+  trh::GridParams gp{};
+  int64_t n_refs = 0;
+  SceneDev dev{};
+};
+
+static int32_t g_scene_key = 0;
+static std::mutex g_mu;
+
+static void free_scene_arrays(tr_scene *s) {
+  void *ptrs[] = {s->sph64, s->cylA64, s->cylW64, s->cylB64, s->sph32,       s->cylA32,
+                  s->cylW32, s->albedo, s->cell_begin, s->refs, s->count, s->scan_scratch,
+                  s->bounds_scratch, s->bounds};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (s->h_bounds) (void)hipHostFree(s->h_bounds);
+  if (s->h_total) (void)hipHostFree(s->h_total);
+}
+
+template <class T>
+static hipError_t dmalloc(T **p, int64_t n) {
+  if (n <= 0) n = 1;
+  return hipMalloc((void **)p, (size_t)n * sizeof(T));
+}
+
+// Grid parameters from the scene bounds (same definition as documented in
+// the grid build: widened box, cube-root resolution rule, margins).
+static void grid_params(const double lo_in[3], const double hi_in[3], int64_t N, double lambda,
+                        trh::GridParams &g) {
+  double m = 0.0;
+  for (int a = 0; a < 3; ++a)
+    if (hi_in[a] - lo_in[a] > m) m = hi_in[a] - lo_in[a];
+  const double pad = 1e-4 * m + 1e-6;
+  double ext[3];
+  for (int a = 0; a < 3; ++a) {
+    g.lo[a] = lo_in[a] - pad;
+    g.hi[a] = hi_in[a] + pad;
+    ext[a] = g.hi[a] - g.lo[a];
+  }
+  double mext = ext[0];
+  if (ext[1] > mext) mext = ext[1];
+  if (ext[2] > mext) mext = ext[2];
+  const double V = ext[0] * ext[1] * ext[2];
+  const double kk = std::cbrt((lambda * (double)N) / V);
+  double hmin = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    double r = std::ceil(ext[a] * kk);
+    if (!(r >= 1.0)) r = 1.0;
+    if (r > 512.0) r = 512.0;
+    g.res[a] = (int32_t)r;
+    g.h[a] = ext[a] / (double)g.res[a];
+    g.inv[a] = (double)g.res[a] / ext[a];
+    if (g.h[a] < hmin) hmin = g.h[a];
+  }
+  g.delta = hmin / 1024.0 + mext / 65536.0;
+  g.n_cells = (int64_t)g.res[0] * g.res[1] * g.res[2];
+}
+
+static void fill_scene_dev(tr_scene *s) {
+  SceneDev &d = s->dev;
+  d.n_s = (int32_t)s->n_s;
+  d.n_c = (int32_t)s->n_c;
+  d.sph64 = s->sph64;
+  d.cylA64 = s->cylA64;
+  d.cylW64 = s->cylW64;
+  d.sph32 = s->sph32;
+  d.cylA32 = s->cylA32;
+  d.cylW32 = s->cylW32;
+  d.albedo = s->albedo;
+  d.cell_begin = s->cell_begin;
+  d.refs = s->refs;
+  for (int a = 0; a < 3; ++a) {
+    d.lo[a] = s->gp.lo[a];
+    d.hi[a] = s->gp.hi[a];
+    d.h[a] = s->gp.h[a];
+    d.inv[a] = s->gp.inv[a];
+    d.lo32[a] = (float)s->gp.lo[a];
+    d.hi32[a] = (float)s->gp.hi[a];
+    d.h32[a] = (float)s->gp.h[a];
+    d.inv32[a] = (float)s->gp.inv[a];
+    d.res[a] = s->gp.res[a];
+  }
+}
+
+// Bounds -> parameters -> count -> scan -> scatter -> sort, from the resident
+// FP64 arrays.  Two blocking readbacks (bounds, reference total).
+static tr_status build_grid(tr_scene *s, hipStream_t st) {
+  const int64_t N = s->n_s + s->n_c;
+  HIP_TRY(trh::launch_pack32(s->n_s, s->n_c, s->sph64, s->cylA64, s->cylW64, s->sph32, s->cylA32,
+                             s->cylW32, st));
+  if (N == 0) {
+    double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+    for (int a = 0; a < 3; ++a) {
+      s->gp.lo[a] = lo[a];
+      s->gp.hi[a] = hi[a];
+      s->gp.h[a] = 1.0;
+      s->gp.inv[a] = 1.0;
+      s->gp.res[a] = 1;
+    }
+    s->gp.delta = 0.0;
+    s->gp.n_cells = 1;
+  } else {
+    HIP_TRY(trh::launch_bounds(s->n_s, s->n_c, s->sph64, s->cylA64, s->cylB64, s->bounds_scratch,
+                               s->bounds, st));
+    HIP_TRY(hipMemcpyAsync(s->h_bounds, s->bounds, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    grid_params(s->h_bounds, s->h_bounds + 3, N, s->lambda, s->gp);
+  }
+  const int64_t nc = s->gp.n_cells;
+  if (nc + 1 > s->cap_cells) {
+    if (s->cell_begin) (void)hipFree(s->cell_begin);
+    if (s->count) (void)hipFree(s->count);
+    s->cell_begin = s->count = nullptr;
+    HIP_TRY(dmalloc(&s->cell_begin, nc + 1));
+    HIP_TRY(dmalloc(&s->count, nc + 1));
+    s->cap_cells = nc + 1;
+  }
+  const int64_t need_scan = trh::scan_scratch_u32(nc + 1);
+  if (need_scan > s->cap_scan) {
+    if (s->scan_scratch) (void)hipFree(s->scan_scratch);
+    s->scan_scratch = nullptr;
+    HIP_TRY(dmalloc(&s->scan_scratch, need_scan));
+    s->cap_scan = need_scan;
+  }
+  trh::BuildArgs a{};
+  a.n_s = (int32_t)s->n_s;
+  a.n_c = (int32_t)s->n_c;
+  a.sph64 = s->sph64;
+  a.cylA64 = s->cylA64;
+  a.cylB64 = s->cylB64;
+  for (int q = 0; q < 3; ++q) {
+    a.lo[q] = s->gp.lo[q];
+    a.h[q] = s->gp.h[q];
+    a.inv[q] = s->gp.inv[q];
+    a.res[q] = s->gp.res[q];
+  }
+  a.delta = s->gp.delta;
+  HIP_TRY(trh::launch_fill_u32(s->cell_begin, nc + 1, 0u, st));
+  HIP_TRY(trh::launch_count(a, s->cell_begin, st));
+  HIP_TRY(trh::launch_scan(s->cell_begin, nc + 1, s->scan_scratch, st));
+  HIP_TRY(hipMemcpyAsync(s->h_total, s->cell_begin + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const int64_t R = (int64_t)*s->h_total;
+  if (R > s->cap_refs) {
+    if (s->refs) (void)hipFree(s->refs);
+    s->refs = nullptr;
+    HIP_TRY(dmalloc(&s->refs, R));
+    s->cap_refs = R > 0 ? R : 1;
+  }
+  s->n_refs = R;
+  HIP_TRY(trh::launch_fill_u32(s->count, nc, 0u, st));
+  HIP_TRY(trh::launch_scatter(a, s->cell_begin, s->count, s->refs, st));
+  HIP_TRY(trh::launch_sort_cells(s->cell_begin, nc, s->refs, st));
+  fill_scene_dev(s);
+  return TR_OK;
+}
+
+extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr_scene **out) {
+  if (!d || !out) return fail(TR_EINVAL, "tr_scene_build: NULL desc or out");
+  *out = nullptr;
+  if (d->n_spheres < 0 || d->n_cylinders < 0) return fail(TR_EINVAL, "negative primitive count");
+  if (d->n_spheres + d->n_cylinders > INT32_MAX - 1) return fail(TR_EINVAL, "too many primitives");
+  if (d->n_lights < 0 || d->n_lights > 8) return fail(TR_EINVAL, "n_lights must be 0..8");
+  if (!(d->cells_per_prim >= 0.0) || !std::isfinite(d->cells_per_prim))
+    return fail(TR_EINVAL, "cells_per_prim must be finite and >= 0");
+  if (d->n_spheres > 0 && (!d->sph_center || !d->sph_radius || !d->sph_rgb))
+    return fail(TR_EINVAL, "NULL sphere array");
+  if (d->n_cylinders > 0 && (!d->cyl_a || !d->cyl_b || !d->cyl_radius || !d->cyl_rgb))
+    return fail(TR_EINVAL, "NULL cylinder array");
+  if (d->n_lights > 0 && (!d->light_dir || !d->light_rgb)) return fail(TR_EINVAL, "NULL light array");
+  for (int64_t k = 0; k < d->n_spheres; ++k) {
+    if (!finite3(d->sph_center + 3 * k) || !std::isfinite(d->sph_radius[k]))
+      return fail(TR_EINVAL, "sphere %lld: non-finite value", (long long)k);
+    if (!(d->sph_radius[k] > 0.0)) return fail(TR_EINVAL, "sphere %lld: radius <= 0", (long long)k);
+  }
+  for (int64_t k = 0; k < d->n_cylinders; ++k) {
+    const double *a = d->cyl_a + 3 * k, *b = d->cyl_b + 3 * k;
+    if (!finite3(a) || !finite3(b) || !std::isfinite(d->cyl_radius[k]))
+      return fail(TR_EINVAL, "cylinder %lld: non-finite value", (long long)k);
+    if (!(d->cyl_radius[k] > 0.0)) return fail(TR_EINVAL, "cylinder %lld: radius <= 0", (long long)k);
+    if (a[0] == b[0] && a[1] == b[1] && a[2] == b[2])
+      return fail(TR_EINVAL, "cylinder %lld: zero length", (long long)k);
+  }
+  for (int l = 0; l < d->n_lights; ++l) {
+    const double *v = d->light_dir + 3 * l;
+    if (!finite3(v) || !finite3(d->light_rgb + 3 * l)) return fail(TR_EINVAL, "light %d: non-finite", l);
+    if (v[0] == 0.0 && v[1] == 0.0 && v[2] == 0.0) return fail(TR_EINVAL, "light %d: zero direction", l);
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  tr_scene *s = new tr_scene();
+  (void)hipGetDevice(&s->device);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    s->key = ++g_scene_key;
+  }
+  s->n_s = d->n_spheres;
+  s->n_c = d->n_cylinders;
+  s->n_lights = d->n_lights;
+  s->lambda = d->cells_per_prim > 0.0 ? d->cells_per_prim : 4.0;
+  for (int l = 0; l < d->n_lights; ++l) {
+    const double *v = d->light_dir + 3 * l;
+    const double n = std::sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    for (int a = 0; a < 3; ++a) {
+      s->ldir[l][a] = v[a] / n;
+      s->lrgb[l][a] = d->light_rgb[3 * l + a];
+    }
+  }
+  auto bail = [&](tr_status stt) {
+    std::string msg = g_err;
+    free_scene_arrays(s);
+    delete s;
+    g_err = msg;
+    return stt;
+  };
+  const int64_t N = s->n_s + s->n_c;
+  hipError_t e = hipSuccess;
+#define ALLOC(p, n)                                                      \
+  if (e == hipSuccess) e = dmalloc(&(p), (n));
+  ALLOC(s->sph64, s->n_s);
+  ALLOC(s->sph32, s->n_s);
+  ALLOC(s->cylA64, s->n_c);
+  ALLOC(s->cylW64, s->n_c);
+  ALLOC(s->cylB64, s->n_c);
+  ALLOC(s->cylA32, s->n_c);
+  ALLOC(s->cylW32, s->n_c);
+  ALLOC(s->albedo, N);
+  ALLOC(s->bounds_scratch, trh::bounds_scratch_doubles(N));
+  ALLOC(s->bounds, 6);
+#undef ALLOC
+  if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_bounds, 6 * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_total, sizeof(uint32_t), hipHostMallocDefault);
+  if (e != hipSuccess)
+    return bail(fail(e == hipErrorOutOfMemory ? TR_ENOMEM : TR_EDEVICE, "scene allocation: %s",
+                     hipGetErrorString(e)));
+  s->bytes_arrays = (size_t)s->n_s * (32 + 16) + (size_t)s->n_c * (3 * 32 + 2 * 16) + (size_t)N * 16;
+  // upload the caller's arrays (temporary device copies), then pack
+  double *t_sc = nullptr, *t_sr = nullptr, *t_ca = nullptr, *t_cb = nullptr, *t_cr = nullptr;
+  float *t_srgb = nullptr, *t_crgb = nullptr;
+  auto free_tmp = [&]() {
+    void *p[] = {t_sc, t_sr, t_ca, t_cb, t_cr, t_srgb, t_crgb};
+    for (void *q : p)
+      if (q) (void)hipFree(q);
+  };
+  if (N > 0) {
+    e = hipSuccess;
+    if (s->n_s > 0) {
+      if (e == hipSuccess) e = dmalloc(&t_sc, 3 * s->n_s);
+      if (e == hipSuccess) e = dmalloc(&t_sr, s->n_s);
+      if (e == hipSuccess) e = dmalloc(&t_srgb, 3 * s->n_s);
+      if (e == hipSuccess) e = hipMemcpyAsync(t_sc, d->sph_center, 24 * s->n_s, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(t_sr, d->sph_radius, 8 * s->n_s, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(t_srgb, d->sph_rgb, 12 * s->n_s, hipMemcpyHostToDevice, st);
+    }
+    if (s->n_c > 0) {
+      if (e == hipSuccess) e = dmalloc(&t_ca, 3 * s->n_c);
+      if (e == hipSuccess) e = dmalloc(&t_cb, 3 * s->n_c);
+      if (e == hipSuccess) e = dmalloc(&t_cr, s->n_c);
+      if (e == hipSuccess) e = dmalloc(&t_crgb, 3 * s->n_c);
+      if (e == hipSuccess) e = hipMemcpyAsync(t_ca, d->cyl_a, 24 * s->n_c, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(t_cb, d->cyl_b, 24 * s->n_c, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(t_cr, d->cyl_radius, 8 * s->n_c, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(t_crgb, d->cyl_rgb, 12 * s->n_c, hipMemcpyHostToDevice, st);
+    }
+    if (e == hipSuccess)
+      e = trh::launch_pack(s->n_s, s->n_c, t_sc, t_sr, t_srgb, t_ca, t_cb, t_cr, t_crgb, s->sph64,
+                           s->cylA64, s->cylW64, s->cylB64, s->albedo, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    free_tmp();
+    if (e != hipSuccess)
+      return bail(fail(e == hipErrorOutOfMemory ? TR_ENOMEM : TR_EDEVICE, "scene upload: %s",
+                       hipGetErrorString(e)));
+  }
+  tr_status rc = build_grid(s, st);
+  if (rc != TR_OK) return bail(rc);
+  *out = s;
+  return TR_OK;
+}
+
+extern "C" tr_status tr_scene_rebuild(tr_scene *s, double cells_per_prim, void *hip_stream) {
+  if (!s) return fail(TR_EINVAL, "tr_scene_rebuild: NULL scene");
+  if (!(cells_per_prim >= 0.0) || !std::isfinite(cells_per_prim))
+    return fail(TR_EINVAL, "cells_per_prim must be finite and >= 0");
+  if (cells_per_prim > 0.0) s->lambda = cells_per_prim;
+  return build_grid(s, (hipStream_t)hip_stream);
+}
+
+extern "C" tr_status tr_scene_footprint(const tr_scene *s, size_t *bytes) {
+  if (!s || !bytes) return fail(TR_EINVAL, "tr_scene_footprint: NULL argument");
+  *bytes = s->bytes_arrays + (size_t)s->cap_cells * 8 + (size_t)s->cap_refs * 4 +
+           (size_t)s->cap_scan * 4;
+  return TR_OK;
+}
+
+extern "C" tr_status tr_scene_grid_info(const tr_scene *s, double lo[3], double hi[3],
+                                        int32_t res[3], int64_t *n_refs) {
+  if (!s) return fail(TR_EINVAL, "tr_scene_grid_info: NULL scene");
+  for (int a = 0; a < 3; ++a) {
+    if (lo) lo[a] = s->gp.lo[a];
+    if (hi) hi[a] = s->gp.hi[a];
+    if (res) res[a] = s->gp.res[a];
+  }
+  if (n_refs) *n_refs = s->n_refs;
+  return TR_OK;
+}
+
+extern "C" tr_status tr_scene_grid_arrays(const tr_scene *s, uint32_t *cell_begin, uint32_t *refs,
+                                          void *hip_stream) {
+  if (!s) return fail(TR_EINVAL, "tr_scene_grid_arrays: NULL scene");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (cell_begin)
+    HIP_TRY(hipMemcpyAsync(cell_begin, s->cell_begin, (size_t)(s->gp.n_cells + 1) * 4,
+                           hipMemcpyDeviceToHost, st));
+  if (refs && s->n_refs > 0)
+    HIP_TRY(hipMemcpyAsync(refs, s->refs, (size_t)s->n_refs * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return TR_OK;
+}
+
+extern "C" void tr_scene_destroy(tr_scene *s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  free_scene_arrays(s);
+  delete s;
+}
+
+// ------------------------------------------------------------------- jobs
+static bool valid_tile_w(int32_t w) { return w == 4 || w == 8 || w == 16 || w == 32; }
+
+static tr_status default_tune(tr_tune *t) {
+  t->tile_w = 8;
+  t->banks = 2;
+  t->waves_per_cu = 20;
+  t->refill_below = 40;
+  t->count_ops = 0;
+  return TR_OK;
+}
+
+static tr_status check_tune(const tr_tune &t) {
+  if (!valid_tile_w(t.tile_w)) return fail(TR_EINVAL, "tune.tile_w must be 4, 8, 16 or 32");
+  if (t.banks != 2 && t.banks != 3) return fail(TR_EINVAL, "tune.banks must be 2 or 3");
+  if (t.waves_per_cu < 1 || t.waves_per_cu > 32) return fail(TR_EINVAL, "tune.waves_per_cu must be 1..32");
+  if (t.refill_below < 1 || t.refill_below > 64) return fail(TR_EINVAL, "tune.refill_below must be 1..64");
+  return TR_OK;
+}
+
+static tr_status check_camera(const tr_camera *c) {
+  if (!c) return fail(TR_EINVAL, "NULL camera");
+  if (c->width <= 0 || c->height <= 0) return fail(TR_EINVAL, "width and height must be > 0");
+  if ((int64_t)c->width * c->height > (int64_t)INT32_MAX - 1)
+    return fail(TR_EINVAL, "width*height must be < 2^31");
+  if (!finite3(c->eye) || !finite3(c->lookat) || !finite3(c->up) || !std::isfinite(c->fovy_deg))
+    return fail(TR_EINVAL, "non-finite camera");
+  if (!(c->fovy_deg > 0.0 && c->fovy_deg < 180.0)) return fail(TR_EINVAL, "fovy must be in (0, 180)");
+  return TR_OK;
+}
+
+static tr_status check_params(const tr_params *p, const tr_frame *f) {
+  if (!p) return fail(TR_EINVAL, "NULL params");
+  if (!f || !f->rgb) return fail(TR_EINVAL, "NULL frame or frame->rgb");
+  if (p->ao_samples < 0 || p->ao_samples > 65535) return fail(TR_EINVAL, "ao_samples must be 0..65535");
+  if (!(p->ao_maxdist > 0.0)) return fail(TR_EINVAL, "ao_maxdist must be > 0");
+  if (f->ao_mask && p->ao_samples > 32) return fail(TR_EINVAL, "ao_mask needs ao_samples <= 32");
+  if (p->precision < TR_PREC_FP64 || p->precision > TR_PREC_FP32_RESOLVE)
+    return fail(TR_EINVAL, "unknown precision %d", p->precision);
+  if (!std::isfinite(p->light_rescale) || !std::isfinite(p->skylight))
+    return fail(TR_EINVAL, "non-finite light_rescale or skylight");
+  return TR_OK;
+}
+
+static void cross3(const double a[3], const double b[3], double r[3]) {
+  r[0] = a[1] * b[2] - a[2] * b[1];
+  r[1] = a[2] * b[0] - a[0] * b[2];
+  r[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double a[3], const double b[3]) {
+  return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+
+static tr_status make_job(const tr_scene *s, const tr_camera *c, const tr_params *p,
+                          const tr_frame *f, int32_t tile_w, JobDev &J) {
+  tr_status rc = check_camera(c);
+  if (rc != TR_OK) return rc;
+  rc = check_params(p, f);
+  if (rc != TR_OK) return rc;
+  if (!s) return fail(TR_EINVAL, "NULL scene");
+  std::memset(&J, 0, sizeof J);
+  J.sc = s->dev;
+  double fw[3] = {c->lookat[0] - c->eye[0], c->lookat[1] - c->eye[1], c->lookat[2] - c->eye[2]};
+  const double nf = std::sqrt(dot3(fw, fw));
+  if (!(nf > 0.0)) return fail(TR_EINVAL, "eye == lookat");
+  for (int a = 0; a < 3; ++a) J.f[a] = fw[a] / nf;
+  double rr[3];
+  cross3(J.f, c->up, rr);
+  const double nr = std::sqrt(dot3(rr, rr));
+  const double nu = std::sqrt(dot3(c->up, c->up));
+  if (!(nr > 1e-12 * nu)) return fail(TR_EINVAL, "up is zero or parallel to the view direction");
+  for (int a = 0; a < 3; ++a) J.r[a] = rr[a] / nr;
+  cross3(J.r, J.f, J.u);
+  J.th = std::tan((c->fovy_deg * M_PI) / 360.0);
+  J.aspect = (double)c->width / (double)c->height;
+  for (int a = 0; a < 3; ++a) {
+    J.eye[a] = c->eye[a];
+    J.eye32[a] = (float)c->eye[a];
+    J.f32[a] = (float)J.f[a];
+    J.r32[a] = (float)J.r[a];
+    J.u32[a] = (float)J.u[a];
+  }
+  J.th32 = (float)J.th;
+  J.aspect32 = (float)J.aspect;
+  J.W = c->width;
+  J.H = c->height;
+  J.S = (p->ao_samples > 0 && p->skylight > 0.0) ? p->ao_samples : 0;
+  J.n_lights = s->n_lights;
+  for (int l = 0; l < s->n_lights; ++l)
+    for (int a = 0; a < 3; ++a) {
+      J.ldir[l][a] = s->ldir[l][a];
+      J.lcol[l][a] = p->light_rescale * s->lrgb[l][a];
+      J.ldir32[l][a] = (float)J.ldir[l][a];
+      J.lcol32[l][a] = (float)J.lcol[l][a];
+    }
+  J.sky = p->skylight;
+  J.sky32 = (float)p->skylight;
+  J.ao_maxdist = p->ao_maxdist;
+  J.ao_maxdist32 = (float)p->ao_maxdist;
+  J.key0 = (uint32_t)(p->seed & 0xFFFFFFFFull);
+  J.key1 = (uint32_t)(p->seed >> 32);
+  J.view_id = p->view_id;
+  J.resolve = p->precision == TR_PREC_FP32_RESOLVE;
+  for (int a = 0; a < 3; ++a) J.bg[a] = p->background[a];
+  J.rgb = f->rgb;
+  J.hit_id = f->hit_id;
+  J.ao_mask = f->ao_mask;
+  J.light_mask = f->light_mask;
+  J.tile_w = tile_w;
+  J.tile_h = 64 / tile_w;
+  J.tiles_x = (c->width + tile_w - 1) / tile_w;
+  J.tiles_y = (c->height + J.tile_h - 1) / J.tile_h;
+  J.tile_begin = 0;
+  J.tile_end = (int64_t)J.tiles_x * J.tiles_y;
+  J.scene_key = s->key;
+  return TR_OK;
+}
+
+// ------------------------------------------------------ launch resources
+// Per-stream ring of job tables: pinned staging + device table + tile
+// counter, each slot reusable once the launch that used it has completed.
+struct LaunchSlot {
+  JobDev *h_jobs = nullptr;
+  JobDev *d_jobs = nullptr;
+  uint32_t *d_counter = nullptr;  // [0] tile counter, [1] stall flag
+  int32_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool used = false;
+};
+struct StreamRing {
+  LaunchSlot slot[4];
+  int next = 0;
+};
+static std::map<std::pair<int, hipStream_t>, StreamRing> g_rings;
+
+static int g_num_cus = 0;
+
+static int num_cus() {
+  if (g_num_cus == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) g_num_cus = prop.multiProcessorCount;
+    if (g_num_cus <= 0) g_num_cus = 256;
+  }
+  return g_num_cus;
+}
+
+static tr_status acquire_slot(hipStream_t st, int32_t n, LaunchSlot **out) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  StreamRing &ring = g_rings[{dev, st}];
+  LaunchSlot &ls = ring.slot[ring.next];
+  ring.next = (ring.next + 1) % 4;
+  if (ls.used) HIP_TRY(hipEventSynchronize(ls.done));
+  if (!ls.done) HIP_TRY(hipEventCreateWithFlags(&ls.done, hipEventDisableTiming));
+  if (ls.cap < n) {
+    if (ls.h_jobs) (void)hipHostFree(ls.h_jobs);
+    if (ls.d_jobs) (void)hipFree(ls.d_jobs);
+    ls.h_jobs = nullptr;
+    ls.d_jobs = nullptr;
+    int32_t cap = std::max(n, 8);
+    HIP_TRY(hipHostMalloc((void **)&ls.h_jobs, sizeof(JobDev) * cap, hipHostMallocDefault));
+    HIP_TRY(hipMalloc((void **)&ls.d_jobs, sizeof(JobDev) * cap));
+    ls.cap = cap;
+  }
+  if (!ls.d_counter) HIP_TRY(hipMalloc((void **)&ls.d_counter, 2 * sizeof(uint32_t)));
+  ls.used = true;
+  *out = &ls;
+  return TR_OK;
+}
+
+// The tuned-shape cache.
+struct TuneKey {
+  int dev;
+  int n_bucket;
+  int32_t W, H, S, prec;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(dev, n_bucket, W, H, S, prec) < std::tie(o.dev, o.n_bucket, o.W, o.H, o.S, o.prec);
+  }
+};
+static std::map<TuneKey, tr_tune> g_tune_cache;
+
+static TuneKey tune_key(const tr_scene *s, const tr_camera *c, const tr_params *p) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int64_t N = s->n_s + s->n_c;
+  int b = 0;
+  while ((int64_t(1) << b) < N + 1) ++b;
+  return TuneKey{dev, b, c->width, c->height, p->ao_samples, p->precision};
+}
+
+static tr_tune pick_tune(const tr_scene *s, const tr_camera *c, const tr_params *p,
+                         const tr_tune *explicit_tune) {
+  tr_tune t;
+  default_tune(&t);
+  if (explicit_tune) {
+    t = *explicit_tune;
+    tr_tune d;
+    default_tune(&d);
+    if (!t.tile_w) t.tile_w = d.tile_w;
+    if (!t.banks) t.banks = d.banks;
+    if (!t.waves_per_cu) t.waves_per_cu = d.waves_per_cu;
+    if (!t.refill_below) t.refill_below = d.refill_below;
+    return t;
+  }
+  if (s && c && p) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tune_cache.find(tune_key(s, c, p));
+    if (it != g_tune_cache.end()) t = it->second;
+  }
+  return t;
+}
+
+// Launch the wavefront kernel over the jobs (already filled, tiles set).
+static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, uint64_t *stats,
+                                  hipStream_t st) {
+  int64_t total = 0;
+  for (auto &J : jobs) {
+    J.queue_begin = total;
+    total += J.tile_end - J.tile_begin;
+  }
+  if (total == 0) return TR_OK;
+  if (total > (int64_t)UINT32_MAX - 1) return fail(TR_EINVAL, "too many tiles in one launch");
+  LaunchSlot *ls = nullptr;
+  tr_status rc = acquire_slot(st, (int32_t)jobs.size(), &ls);
+  if (rc != TR_OK) return rc;
+  std::memcpy(ls->h_jobs, jobs.data(), sizeof(JobDev) * jobs.size());
+  HIP_TRY(hipMemcpyAsync(ls->d_jobs, ls->h_jobs, sizeof(JobDev) * jobs.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(trh::launch_fill_u32(ls->d_counter, 2, 0u, st));
+  trh::WaveLaunch L{};
+  L.jobs = ls->d_jobs;
+  L.n_jobs = (int32_t)jobs.size();
+  L.n_tiles = total;
+  L.tile_counter = ls->d_counter;
+  L.stats = stats;
+  L.tile_w = t.tile_w;
+  L.banks = t.banks;
+  L.refill_below = t.refill_below;
+  L.count_ops = t.count_ops;
+  int64_t waves = (int64_t)num_cus() * t.waves_per_cu;
+  if (waves > total) waves = total;
+  L.n_waves = (int32_t)waves;
+  L.resolve = jobs[0].resolve;
+  HIP_TRY(trh::launch_render_wave(L, st));
+  HIP_TRY(hipEventRecord(ls->done, st));
+  return TR_OK;
+}
+
+// --------------------------------------------------------------- renders
+extern "C" tr_status tr_render_tuned(const tr_scene *s, const tr_camera *c, const tr_params *p,
+                                     const tr_frame *f, const tr_tune *tune, void *hip_stream) {
+  if (!s) return fail(TR_EINVAL, "tr_render: NULL scene");
+  tr_tune t = pick_tune(s, c, p, tune);
+  tr_status rc = check_tune(t);
+  if (rc != TR_OK) return rc;
+  JobDev J;
+  rc = make_job(s, c, p, f, t.tile_w, J);
+  if (rc != TR_OK) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (p->precision == TR_PREC_FP64) {
+    HIP_TRY(trh::launch_render_plain_f64(J, f->stats, st));
+    return TR_OK;
+  }
+  std::vector<JobDev> jobs(1, J);
+  return launch_wave_jobs(jobs, t, f->stats, st);
+}
+
+extern "C" tr_status tr_render(const tr_scene *s, const tr_camera *c, const tr_params *p,
+                               const tr_frame *f, void *hip_stream) {
+  return tr_render_tuned(s, c, p, f, nullptr, hip_stream);
+}
+
+extern "C" int64_t tr_tile_count(int32_t width, int32_t height, int32_t tile_w) {
+  if (tile_w == 0) tile_w = 8;
+  if (!valid_tile_w(tile_w) || width <= 0 || height <= 0) return -1;
+  const int32_t th = 64 / tile_w;
+  return (int64_t)((width + tile_w - 1) / tile_w) * ((height + th - 1) / th);
+}
+
+static tr_status batch_impl(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,
+                            const tr_params *params, const tr_frame *frames, const int64_t *tb,
+                            const int64_t *te, const tr_tune *tune, hipStream_t st) {
+  if (n < 1 || n > 4096) return fail(TR_EINVAL, "batch size must be 1..4096");
+  if (!scenes || !cams || !params || !frames) return fail(TR_EINVAL, "NULL batch array");
+  tr_tune t = pick_tune(scenes[0], &cams[0], &params[0], tune);
+  tr_status rc = check_tune(t);
+  if (rc != TR_OK) return rc;
+  const int res = params[0].precision == TR_PREC_FP32_RESOLVE;
+  std::vector<JobDev> jobs;
+  jobs.reserve(n);
+  uint64_t *stats = frames[0].stats;
+  for (int32_t i = 0; i < n; ++i) {
+    JobDev J;
+    rc = make_job(scenes[i], &cams[i], &params[i], &frames[i], t.tile_w, J);
+    if (rc != TR_OK) return fail(rc, "job %d: %s", i, g_err.c_str());
+    if (params[i].precision == TR_PREC_FP64) {
+      if (tb) return fail(TR_EUNSUPPORTED, "tile ranges need an FP32 precision");
+      HIP_TRY(trh::launch_render_plain_f64(J, frames[i].stats, st));
+      continue;
+    }
+    if ((params[i].precision == TR_PREC_FP32_RESOLVE) != (res != 0))
+      return fail(TR_EINVAL, "all FP32 jobs of one batch must use the same precision");
+    if (frames[i].stats != stats) return fail(TR_EINVAL, "all jobs of one batch must share one stats buffer");
+    if (tb) {
+      if (!te) return fail(TR_EINVAL, "NULL tile_end");
+      if (tb[i] < 0 || te[i] < tb[i] || te[i] > J.tile_end)
+        return fail(TR_EINVAL, "job %d: tile range [%lld, %lld) outside [0, %lld)", i,
+                    (long long)tb[i], (long long)te[i], (long long)J.tile_end);
+      J.tile_begin = tb[i];
+      J.tile_end = te[i];
+    }
+    jobs.push_back(J);
+  }
+  if (jobs.empty()) return TR_OK;
+  // keep jobs of one scene adjacent so waves rarely switch scenes
+  std::stable_sort(jobs.begin(), jobs.end(),
+                   [](const JobDev &a, const JobDev &b) { return a.scene_key < b.scene_key; });
+  return launch_wave_jobs(jobs, t, stats, st);
+}
+
+extern "C" tr_status tr_render_batch(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,
+                                     const tr_params *params, const tr_frame *frames, void *hip_stream) {
+  return batch_impl(n, scenes, cams, params, frames, nullptr, nullptr, nullptr, (hipStream_t)hip_stream);
+}
+
+extern "C" tr_status tr_render_batch_tiles(int32_t n, const tr_scene *const *scenes,
+                                           const tr_camera *cams, const tr_params *params,
+                                           const tr_frame *frames, const int64_t *tile_begin,
+                                           const int64_t *tile_end, const tr_tune *tune,
+                                           void *hip_stream) {
+  if (!tile_begin || !tile_end) return fail(TR_EINVAL, "NULL tile range");
+  return batch_impl(n, scenes, cams, params, frames, tile_begin, tile_end, tune,
+                    (hipStream_t)hip_stream);
+}
+
+extern "C" size_t tr_frame_footprint(const tr_camera *c, const tr_params *p, uint32_t flags) {
+  if (!c || c->width <= 0 || c->height <= 0) return 0;
+  (void)p;
+  const size_t px = (size_t)c->width * (size_t)c->height;
+  size_t b = 0;
+  if (flags & 1u) b += px * 12;
+  if (flags & 2u) b += px * 4;
+  if (flags & 4u) b += px * 4;
+  if (flags & 8u) b += px;
+  return b;
+}
+
+// ----------------------------------------------------------------- graphs
+struct tr_graph {
+  int32_t n = 0;
+  std::vector<JobDev> jobs;  // host copy (queue offsets filled)
+  std::vector<const tr_scene *> scenes;
+  std::vector<tr_frame> frames;
+  std::vector<tr_camera> cams;
+  std::vector<tr_params> params;
+  tr_tune tune{};
+  JobDev *h_jobs = nullptr, *d_jobs = nullptr;
+  uint32_t *d_counter = nullptr;
+  hipEvent_t staged = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t total_tiles = 0;
+};
+
+static void free_graph(tr_graph *g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->h_jobs) (void)hipHostFree(g->h_jobs);
+  if (g->d_jobs) (void)hipFree(g->d_jobs);
+  if (g->d_counter) (void)hipFree(g->d_counter);
+  if (g->staged) (void)hipEventDestroy(g->staged);
+  delete g;
+}
+
+static tr_status graph_upload(tr_graph *g, hipStream_t st) {
+  HIP_TRY(hipEventSynchronize(g->staged));  // previous staging copy has run
+  std::memcpy(g->h_jobs, g->jobs.data(), sizeof(JobDev) * g->jobs.size());
+  HIP_TRY(hipMemcpyAsync(g->d_jobs, g->h_jobs, sizeof(JobDev) * g->jobs.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(g->staged, st));
+  return TR_OK;
+}
+
+extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,
+                                     const tr_params *params, const tr_frame *frames,
+                                     const tr_tune *tune, void *hip_stream, tr_graph **out) {
+  if (!out) return fail(TR_EINVAL, "NULL out");
+  *out = nullptr;
+  if (n < 1 || n > 4096) return fail(TR_EINVAL, "graph batch size must be 1..4096");
+  if (!scenes || !cams || !params || !frames) return fail(TR_EINVAL, "NULL batch array");
+  tr_graph *g = new tr_graph();
+  g->n = n;
+  g->tune = pick_tune(scenes[0], &cams[0], &params[0], tune);
+  tr_status rc = check_tune(g->tune);
+  if (rc != TR_OK) {
+    free_graph(g);
+    return rc;
+  }
+  int64_t total = 0;
+  const int res = params[0].precision == TR_PREC_FP32_RESOLVE;
+  for (int32_t i = 0; i < n; ++i) {
+    JobDev J;
+    rc = make_job(scenes[i], &cams[i], &params[i], &frames[i], g->tune.tile_w, J);
+    if (rc == TR_OK && params[i].precision == TR_PREC_FP64)
+      rc = fail(TR_EUNSUPPORTED, "graphs need an FP32 precision");
+    if (rc == TR_OK && (params[i].precision == TR_PREC_FP32_RESOLVE) != (res != 0))
+      rc = fail(TR_EINVAL, "all jobs of one graph must use the same precision");
+    if (rc == TR_OK && frames[i].stats != frames[0].stats)
+      rc = fail(TR_EINVAL, "all jobs of one graph must share one stats buffer");
+    if (rc != TR_OK) {
+      free_graph(g);
+      return rc;
+    }
+    J.queue_begin = total;
+    total += J.tile_end;
+    g->jobs.push_back(J);
+    g->scenes.push_back(scenes[i]);
+    g->frames.push_back(frames[i]);
+    g->cams.push_back(cams[i]);
+    g->params.push_back(params[i]);
+  }
+  g->total_tiles = total;
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = hipHostMalloc((void **)&g->h_jobs, sizeof(JobDev) * n, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void **)&g->d_jobs, sizeof(JobDev) * n);
+  if (e == hipSuccess) e = hipMalloc((void **)&g->d_counter, 2 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&g->staged, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(g->staged, st);
+  if (e != hipSuccess) {
+    free_graph(g);
+    return fail(TR_EDEVICE, "graph resources: %s", hipGetErrorString(e));
+  }
+  rc = graph_upload(g, st);
+  if (rc != TR_OK) {
+    free_graph(g);
+    return rc;
+  }
+  // capture: counter reset (a kernel, not a memset node) + persistent launch
+  hipStream_t cap = nullptr;
+  e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    e = trh::launch_fill_u32(g->d_counter, 2, 0u, cap);
+    trh::WaveLaunch L{};
+    L.jobs = g->d_jobs;
+    L.n_jobs = n;
+    L.n_tiles = total;
+    L.tile_counter = g->d_counter;
+    L.stats = frames[0].stats;
+    L.tile_w = g->tune.tile_w;
+    L.banks = g->tune.banks;
+    L.refill_below = g->tune.refill_below;
+    L.count_ops = g->tune.count_ops;
+    int64_t waves = (int64_t)num_cus() * g->tune.waves_per_cu;
+    if (waves > total) waves = total;
+    L.n_waves = (int32_t)std::max<int64_t>(waves, 1);
+    L.resolve = res;
+    if (e == hipSuccess) e = trh::launch_render_wave(L, cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &g->graph);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (cap) (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    free_graph(g);
+    return fail(TR_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  }
+  *out = g;
+  return TR_OK;
+}
+
+extern "C" tr_status tr_graph_update(tr_graph *g, const tr_camera *cams, const tr_params *params,
+                                     void *hip_stream) {
+  if (!g) return fail(TR_EINVAL, "NULL graph");
+  if (!cams && !params) return TR_OK;
+  std::vector<JobDev> nj(g->n);
+  for (int32_t i = 0; i < g->n; ++i) {
+    const tr_camera &c = cams ? cams[i] : g->cams[i];
+    const tr_params &p = params ? params[i] : g->params[i];
+    if (c.width != g->cams[i].width || c.height != g->cams[i].height)
+      return fail(TR_EINVAL, "job %d: resolution differs from the captured one", i);
+    if (p.precision != g->params[i].precision)
+      return fail(TR_EINVAL, "job %d: precision differs from the captured one", i);
+    tr_status rc = make_job(g->scenes[i], &c, &p, &g->frames[i], g->tune.tile_w, nj[i]);
+    if (rc != TR_OK) return fail(rc, "job %d: %s", i, g_err.c_str());
+    nj[i].queue_begin = g->jobs[i].queue_begin;
+  }
+  for (int32_t i = 0; i < g->n; ++i) {
+    if (cams) g->cams[i] = cams[i];
+    if (params) g->params[i] = params[i];
+  }
+  g->jobs = nj;
+  return graph_upload(g, (hipStream_t)hip_stream);
+}
+
+extern "C" tr_status tr_graph_launch(tr_graph *g, void *hip_stream) {
+  if (!g) return fail(TR_EINVAL, "NULL graph");
+  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)hip_stream));
+  return TR_OK;
+}
+
+extern "C" void tr_graph_destroy(tr_graph *g) {
+  if (!g) return;
+  (void)hipDeviceSynchronize();
+  free_graph(g);
+}
+
+// ---------------------------------------------------------------- autotune
+extern "C" tr_status tr_default_tune(tr_tune *out) {
+  if (!out) return fail(TR_EINVAL, "NULL out");
+  return default_tune(out);
+}
+
+extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr_params *p,
+                                 void *hip_stream, tr_tune *best, double *best_ms) {
+  if (!s || !c || !p) return fail(TR_EINVAL, "tr_autotune: NULL argument");
+  tr_status rc = check_camera(c);
+  if (rc != TR_OK) return rc;
+  if (p->precision == TR_PREC_FP64) {
+    tr_tune d;
+    default_tune(&d);
+    if (best) *best = d;
+    if (best_ms) *best_ms = 0.0;
+    return TR_OK;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t px = (size_t)c->width * c->height;
+  float *rgb_ref = nullptr, *rgb = nullptr;
+  int32_t *hid_ref = nullptr, *hid = nullptr;
+  HIP_TRY(hipMalloc((void **)&rgb_ref, px * 12));
+  HIP_TRY(hipMalloc((void **)&rgb, px * 12));
+  HIP_TRY(hipMalloc((void **)&hid_ref, px * 4));
+  HIP_TRY(hipMalloc((void **)&hid, px * 4));
+  std::vector<float> h_a(px * 3), h_b(px * 3);
+  std::vector<int32_t> i_a(px), i_b(px);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  auto cleanup = [&]() {
+    (void)hipFree(rgb_ref);
+    (void)hipFree(rgb);
+    (void)hipFree(hid_ref);
+    (void)hipFree(hid);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  };
+  auto run = [&](const tr_tune &t, float *out_rgb, int32_t *out_hid, double &ms) -> tr_status {
+    tr_frame fr{out_rgb, out_hid, nullptr, nullptr, nullptr};
+    tr_status r = tr_render_tuned(s, c, p, &fr, &t, st);  // warm-up
+    if (r != TR_OK) return r;
+    std::vector<double> times;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIP_TRY(hipEventRecord(e0, st));
+      r = tr_render_tuned(s, c, p, &fr, &t, st);
+      if (r != TR_OK) return r;
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float f = 0;
+      HIP_TRY(hipEventElapsedTime(&f, e0, e1));
+      times.push_back(f);
+    }
+    std::sort(times.begin(), times.end());
+    ms = times[1];
+    return TR_OK;
+  };
+  tr_tune cur;
+  default_tune(&cur);
+  double cur_ms = 0;
+  rc = run(cur, rgb_ref, hid_ref, cur_ms);
+  if (rc != TR_OK) {
+    cleanup();
+    return rc;
+  }
+  if (hipMemcpy(h_a.data(), rgb_ref, px * 12, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(i_a.data(), hid_ref, px * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+    cleanup();
+    return fail(TR_EDEVICE, "autotune readback failed");
+  }
+  // coordinate descent over the launch-shape axes
+  const std::vector<std::vector<int32_t>> axes = {
+      {4, 8, 16, 32}, {2, 3}, {8, 12, 16, 20, 24, 32}, {16, 24, 32, 40, 48, 56}};
+  for (int pass = 0; pass < 2; ++pass) {
+    for (size_t ax = 0; ax < axes.size(); ++ax) {
+      for (int32_t v : axes[ax]) {
+        tr_tune t = cur;
+        int32_t *field = ax == 0 ? &t.tile_w : ax == 1 ? &t.banks : ax == 2 ? &t.waves_per_cu : &t.refill_below;
+        if (*field == v) continue;
+        *field = v;
+        double ms = 0;
+        rc = run(t, rgb, hid, ms);
+        if (rc != TR_OK) {
+          cleanup();
+          return rc;
+        }
+        if (hipMemcpy(h_b.data(), rgb, px * 12, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(i_b.data(), hid, px * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+          cleanup();
+          return fail(TR_EDEVICE, "autotune readback failed");
+        }
+        if (std::memcmp(h_a.data(), h_b.data(), px * 12) != 0 ||
+            std::memcmp(i_a.data(), i_b.data(), px * 4) != 0) {
+          cleanup();
+          return fail(TR_EDEVICE, "autotune: launch shape (%d,%d,%d,%d) changed the frame", t.tile_w,
+                      t.banks, t.waves_per_cu, t.refill_below);
+        }
+        if (ms < cur_ms) {
+          cur_ms = ms;
+          cur = t;
+        }
+      }
+    }
+  }
+  cleanup();
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tune_cache[tune_key(s, c, p)] = cur;
+  }
+  if (best) *best = cur;
+  if (best_ms) *best_ms = cur_ms;
+  return TR_OK;
+}
+
+// ------------------------------------------------------------------ debug
+extern "C" tr_status tr_debug_philox(int64_t n, const uint32_t *ctr, const uint32_t *key,
+                                     uint32_t *out, void *hip_stream) {
+  if (n < 0 || (n > 0 && (!ctr || !key || !out))) return fail(TR_EINVAL, "tr_debug_philox: bad arguments");
+  HIP_TRY(trh::launch_debug_philox(n, ctr, key, out, (hipStream_t)hip_stream));
+  return TR_OK;
+}
+
+extern "C" tr_status tr_debug_ao_dirs(int64_t n, const float *normals, const uint32_t *pix,
+                                      const uint32_t *sample, uint32_t view_id, uint64_t seed,
+                                      float *w, void *hip_stream) {
+  if (n < 0 || (n > 0 && (!normals || !pix || !sample || !w)))
+    return fail(TR_EINVAL, "tr_debug_ao_dirs: bad arguments");
+  HIP_TRY(trh::launch_debug_ao_dirs(n, normals, pix, sample, view_id, (uint32_t)(seed & 0xFFFFFFFFull),
+                                    (uint32_t)(seed >> 32), w, (hipStream_t)hip_stream));
+  return TR_OK;
+}
+
+extern "C" const char *tr_last_error(void) { return g_err.c_str(); }
+extern "C" int32_t tr_abi_version(void) { return TR_ABI_VERSION; }

@@ -1,0 +1,213 @@
+// tr_device.h -- device data layout and small device helpers of the HIP path.
+//
+// Layout in HBM (one scene):
+//   sph64  double4[n_s]  (cx, cy, cz, r)          FP64 copy (grid build, FP64 path, re-solve)
+//   cylA64 double4[n_c]  (ax, ay, az, rho)
+//   cylW64 double4[n_c]  (wx, wy, wz, L)           unit axis and length, w = (b - a) / L
+//   cylB64 double4[n_c]  (bx, by, bz, 0)           second end point (grid rebuild)
+//   sph32  float4[n_s]   rounded copies for the FP32 traversal: one 16-byte load per sphere
+//   cylA32 float4[n_c], cylW32 float4[n_c]         two 16-byte loads per cylinder
+//   albedo float4[N]     (r, g, b, 0) by global id
+//   cell_begin uint32[n_cells + 1], refs uint32[n_refs]   the uniform grid
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trd {
+
+// ----------------------------------------------------------------- scene
+struct SceneDev {
+  int32_t n_s, n_c;
+  const double4 *sph64, *cylA64, *cylW64;
+  const float4 *sph32, *cylA32, *cylW32;
+  const float4 *albedo;
+  const uint32_t *cell_begin, *refs;
+  double lo[3], hi[3], h[3], inv[3];
+  float lo32[3], hi32[3], h32[3], inv32[3];
+  int32_t res[3];
+  int32_t pad_;
+};
+
+// One render job: scene + camera + parameters + outputs + its tile range.
+struct JobDev {
+  SceneDev sc;
+  double eye[3], f[3], r[3], u[3];
+  double th, aspect;
+  float eye32[3], f32[3], r32[3], u32[3];
+  float th32, aspect32;
+  int32_t W, H;
+  int32_t S;            // AO rays per hit pixel (0 when AO is off)
+  int32_t n_lights;
+  double ldir[8][3];    // unit, toward the light
+  double lcol[8][3];    // light_rescale * intensity
+  float ldir32[8][3];
+  float lcol32[8][3];
+  double sky;           // skylight
+  double ao_maxdist;
+  float sky32, ao_maxdist32;
+  uint32_t key0, key1, view_id;
+  int32_t resolve;      // FP64 re-solve of near-grazing tests
+  float bg[3];
+  float *rgb;
+  int32_t *hit_id;
+  uint32_t *ao_mask;
+  uint8_t *light_mask;
+  // tiles: 64-pixel tiles of tile_w x (64 / tile_w) pixels, row-major
+  int32_t tile_w, tile_h, tiles_x, tiles_y;
+  int64_t tile_begin, tile_end;  // range rendered by this launch
+  int64_t queue_begin;           // index of this job's first tile in the launch's tile queue
+  int32_t scene_key;             // jobs with equal keys share one scene
+  int32_t pad2_;
+};
+
+// --------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
+// 32x32->64-bit multiplies whose high halves are xored into the other two
+// words with the round key; the key advances by two Weyl constants.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+    uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+    uint4 n;
+    n.x = hi1 ^ c.y ^ k0;
+    n.y = lo1;
+    n.z = hi0 ^ c.w ^ k1;
+    n.w = lo0;
+    c = n;
+    k0 += W0;
+    k1 += W1;
+  }
+  return c;
+}
+
+// 24-bit uniforms of AO sample s of pixel pix: exact in float and double.
+__device__ __forceinline__ void ao_uniform_bits(uint32_t pix, uint32_t s, uint32_t view,
+                                                uint32_t k0, uint32_t k1, uint32_t &b1,
+                                                uint32_t &b2) {
+  uint4 x = philox4x32_10(make_uint4(pix, s, view, 0u), k0, k1);
+  b1 = x.x >> 8;
+  b2 = x.y >> 8;
+}
+
+// Cosine-weighted hemisphere direction around unit n (Malley: uniform disc
+// point lifted to the hemisphere), basis of Duff et al. (JCGT 2017).
+// FP32 version: sin/cos of 2*pi*u2 by the hardware's revolution-scaled
+// sine and cosine, which take u2 in [0, 1) directly.
+__device__ __forceinline__ void ao_dir_f32(float nx, float ny, float nz, uint32_t b1, uint32_t b2,
+                                           float &wx, float &wy, float &wz) {
+  const float u1 = (float)b1 * (1.0f / 16777216.0f);
+  const float u2 = (float)b2 * (1.0f / 16777216.0f);
+  const float rr = __builtin_sqrtf(u1);
+  const float lx = rr * __builtin_amdgcn_cosf(u2);
+  const float ly = rr * __builtin_amdgcn_sinf(u2);
+  const float lz = __builtin_sqrtf(1.0f - u1);
+  const float sg = __builtin_copysignf(1.0f, nz);
+  const float a = -1.0f / (sg + nz);
+  const float b = nx * ny * a;
+  const float tx = 1.0f + sg * nx * nx * a, ty = sg * b, tz = -sg * nx;
+  const float bx = b, by = sg + ny * ny * a, bz = -ny;
+  wx = lx * tx + ly * bx + lz * nx;
+  wy = lx * ty + ly * by + lz * ny;
+  wz = lx * tz + ly * bz + lz * nz;
+}
+
+// FP64 version in the operation order of the plain double-precision path.
+__device__ __forceinline__ void ao_dir_f64(const double n[3], uint32_t b1, uint32_t b2,
+                                           double w[3]) {
+  const double u1 = (double)b1 * (1.0 / 16777216.0);
+  const double u2 = (double)b2 * (1.0 / 16777216.0);
+  const double rr = sqrt(u1);
+  const double phi = 6.283185307179586 * u2;
+  double sn, cs;
+  sincos(phi, &sn, &cs);
+  const double lx = rr * cs, ly = rr * sn, lz = sqrt(1.0 - u1);
+  const double sg = copysign(1.0, n[2]);
+  const double a = -1.0 / (sg + n[2]);
+  const double b = n[0] * n[1] * a;
+  const double tx[3] = {1.0 + sg * n[0] * n[0] * a, sg * b, -sg * n[0]};
+  const double bx[3] = {b, sg + n[1] * n[1] * a, -n[1]};
+  w[0] = (lx * tx[0] + ly * bx[0]) + lz * n[0];
+  w[1] = (lx * tx[1] + ly * bx[1]) + lz * n[1];
+  w[2] = (lx * tx[2] + ly * bx[2]) + lz * n[2];
+}
+
+// --------------------------------------------------------------- camera
+__device__ __forceinline__ double dot3d(const double a[3], const double b[3]) {
+  return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+
+// FP64 primary ray through the centre of pixel (i, j); row 0 at the top.
+__device__ __forceinline__ void primary_ray_f64(const JobDev &J, int32_t i, int32_t j,
+                                                double o[3], double d[3]) {
+  const double x = (((2.0 * ((double)i + 0.5)) / (double)J.W) - 1.0) * J.th * J.aspect;
+  const double y = (1.0 - (2.0 * ((double)j + 0.5)) / (double)J.H) * J.th;
+  double v[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) v[a] = (J.f[a] + x * J.r[a]) + y * J.u[a];
+  const double n = sqrt(dot3d(v, v));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    d[a] = v[a] / n;
+    o[a] = J.eye[a];
+  }
+}
+
+// ------------------------------------------------------- FP64 intersections
+// Sphere (centre-to-ray perpendicular form, unit d): smallest root in
+// (tmin, tmax], 1 on a hit.
+__device__ __forceinline__ int hit_sphere_f64(const double4 s, const double o[3], const double d[3],
+                                              double tmin, double tmax, double &t) {
+  const double q[3] = {s.x - o[0], s.y - o[1], s.z - o[2]};
+  const double b = dot3d(q, d);
+  const double l[3] = {q[0] - b * d[0], q[1] - b * d[1], q[2] - b * d[2]};
+  const double disc = s.w * s.w - dot3d(l, l);
+  if (disc < 0.0) return 0;
+  const double sq = sqrt(disc);
+  const double t0 = b - sq, t1 = b + sq;
+  if (t0 > tmin && t0 <= tmax) { t = t0; return 1; }
+  if (t1 > tmin && t1 <= tmax) { t = t1; return 1; }
+  return 0;
+}
+
+// Open cylinder: A t^2 + 2 B t + C = 0 on the perpendicular components, stable
+// roots q/A and C/q, axial coordinate in [0, L].
+__device__ __forceinline__ int hit_cylinder_f64(const double4 aa, const double4 ww, const double o[3],
+                                                const double d[3], double tmin, double tmax,
+                                                double &t) {
+  const double w[3] = {ww.x, ww.y, ww.z};
+  const double D[3] = {o[0] - aa.x, o[1] - aa.y, o[2] - aa.z};
+  const double dw = dot3d(d, w);
+  const double Dw = dot3d(D, w);
+  double dp[3], Dp[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    dp[k] = d[k] - dw * w[k];
+    Dp[k] = D[k] - Dw * w[k];
+  }
+  const double A = dot3d(dp, dp);
+  const double B = dot3d(dp, Dp);
+  const double C = dot3d(Dp, Dp) - aa.w * aa.w;
+  if (A <= 1e-12 * dot3d(d, d)) return 0;
+  const double disc = B * B - A * C;
+  if (disc < 0.0) return 0;
+  const double sq = sqrt(disc);
+  const double qq = -(B + (B >= 0.0 ? sq : -sq));
+  if (qq == 0.0) return 0;
+  const double r0 = qq / A, r1 = C / qq;
+  const double tl = r0 < r1 ? r0 : r1;
+  const double th = r0 < r1 ? r1 : r0;
+  if (tl > tmin && tl <= tmax) {
+    const double s = Dw + tl * dw;
+    if (s >= 0.0 && s <= ww.w) { t = tl; return 1; }
+  }
+  if (th > tmin && th <= tmax) {
+    const double s = Dw + th * dw;
+    if (s >= 0.0 && s <= ww.w) { t = th; return 1; }
+  }
+  return 0;
+}
+
+}  // namespace trd

@@ -1,0 +1,72 @@
+// tr_internal.h -- host-side internals shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/tr.h"
+#include "tr_device.h"
+
+namespace trh {
+
+// Uniform-grid parameters, computed on the host from the device bounds.
+struct GridParams {
+  double lo[3], hi[3], h[3], inv[3];
+  double delta;
+  int32_t res[3];
+  int64_t n_cells;
+};
+
+// Inputs of the count / scatter kernels.
+struct BuildArgs {
+  int32_t n_s, n_c;
+  const double4 *sph64, *cylA64, *cylB64;
+  double lo[3], h[3], inv[3], delta;
+  int32_t res[3];
+};
+
+// ---- grid build launchers (grid_build.hip) ----
+hipError_t launch_pack(int64_t n_s, int64_t n_c, const double *sc, const double *sr,
+                       const float *srgb, const double *ca, const double *cb, const double *cr,
+                       const float *crgb, double4 *sph64, double4 *cylA64, double4 *cylW64,
+                       double4 *cylB64, float4 *albedo, hipStream_t st);
+hipError_t launch_pack32(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
+                         const double4 *cylW64, float4 *sph32, float4 *cylA32, float4 *cylW32,
+                         hipStream_t st);
+// bounds: out6 = (lo xyz, hi xyz); scratch >= bounds_scratch_doubles(N) doubles
+int64_t bounds_scratch_doubles(int64_t n_prims);
+hipError_t launch_bounds(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
+                         const double4 *cylB64, double *scratch, double *out6, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_count(const BuildArgs &a, uint32_t *count, hipStream_t st);
+// exclusive scan of n+1 entries in place (data[n] must be 0 on entry)
+int64_t scan_scratch_u32(int64_t n);
+hipError_t launch_scan(uint32_t *data, int64_t n_plus_1, uint32_t *scratch, hipStream_t st);
+hipError_t launch_scatter(const BuildArgs &a, const uint32_t *cell_begin, uint32_t *cursor,
+                          uint32_t *refs, hipStream_t st);
+hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32_t *refs,
+                             hipStream_t st);
+
+// ---- render launchers ----
+hipError_t launch_render_plain_f64(const trd::JobDev &job, uint64_t *stats, hipStream_t st);
+
+struct WaveLaunch {
+  const trd::JobDev *jobs;   // device array
+  int32_t n_jobs;
+  int64_t n_tiles;           // total tiles in the queue
+  uint32_t *tile_counter;    // device, zeroed before the launch
+  uint64_t *stats;           // device or null
+  int32_t tile_w, banks, refill_below, count_ops;
+  int32_t n_waves;           // persistent waves launched
+  int32_t resolve;
+};
+hipError_t launch_render_wave(const WaveLaunch &L, hipStream_t st);
+hipError_t launch_zero_counter(uint32_t *p, hipStream_t st);
+
+hipError_t launch_debug_philox(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out,
+                               hipStream_t st);
+hipError_t launch_debug_ao_dirs(int64_t n, const float *nrm, const uint32_t *pix,
+                                const uint32_t *smp, uint32_t view, uint32_t k0, uint32_t k1,
+                                float *w, hipStream_t st);
+
+}  // namespace trh

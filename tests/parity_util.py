@@ -1,0 +1,84 @@
+"""Parity metrics between a GPU frame and the oracle's frame.
+
+Tolerance reading for the FP32 path (render precision differs from the
+oracle's double precision): a flipped visibility decision moves a pixel by a
+whole AO step (albedo * skylight / S ~ 0.05), so colour error is bounded only
+on pixels whose hit id and every secondary-ray decision agree; the decisions
+themselves are bounded by agreement rates.
+"""
+import numpy as np
+
+# FP32 path bounds (hit-index agreement, decision agreement, colour on agreeing pixels)
+HIT_AGREE_MIN = 0.9999
+DECISION_AGREE_MIN = 0.9999
+MAX_ABS = 1e-3
+RMS = 1e-4
+
+
+def popcount32(x: np.ndarray) -> np.ndarray:
+    x = x.astype(np.uint64)
+    c = np.zeros(x.shape, dtype=np.int64)
+    for b in range(32):
+        c += ((x >> np.uint64(b)) & np.uint64(1)).astype(np.int64)
+    return c
+
+
+def compare(gpu: dict, ref: dict, ao_samples: int, n_lights: int) -> dict:
+    """gpu/ref: flat arrays (same pixel order) rgb [n,3], hit_id [n],
+    ao_mask [n] (uint32 bits), light_mask [n]."""
+    g_hit = np.asarray(gpu["hit_id"]).reshape(-1).astype(np.int64)
+    r_hit = np.asarray(ref["hit_id"]).reshape(-1).astype(np.int64)
+    n = r_hit.size
+    hit_eq = g_hit == r_hit
+    g_ao = np.asarray(gpu["ao_mask"]).reshape(-1).astype(np.int64) & 0xFFFFFFFF
+    r_ao = np.asarray(ref["ao_mask"]).reshape(-1).astype(np.int64) & 0xFFFFFFFF
+    g_l = np.asarray(gpu["light_mask"]).reshape(-1).astype(np.int64)
+    r_l = np.asarray(ref["light_mask"]).reshape(-1).astype(np.int64)
+    both_hit = hit_eq & (r_hit >= 0)
+    s_bits = min(ao_samples, 32)
+    ao_diff = popcount32(np.where(both_hit, g_ao ^ r_ao, 0))
+    l_diff = popcount32(np.where(both_hit, g_l ^ r_l, 0))
+    n_sec = int(both_hit.sum()) * (s_bits + n_lights)
+    flips = int(ao_diff.sum() + l_diff.sum())
+    agree = hit_eq & (g_ao == r_ao) & (g_l == r_l)
+    g_rgb = np.asarray(gpu["rgb"], dtype=np.float64).reshape(-1, 3)
+    r_rgb = np.asarray(ref["rgb"], dtype=np.float64).reshape(-1, 3)
+    err = np.abs(g_rgb - r_rgb)
+    ea = err[agree]
+    return dict(
+        n=n, hit_agree=float(hit_eq.mean()) if n else 1.0,
+        hit_mismatch=int((~hit_eq).sum()),
+        decisions=n_sec, decision_flips=flips,
+        decision_agree=1.0 - flips / n_sec if n_sec else 1.0,
+        agree_pixels=int(agree.sum()),
+        max_abs_agree=float(ea.max()) if ea.size else 0.0,
+        rms_agree=float(np.sqrt((ea ** 2).mean())) if ea.size else 0.0,
+        max_abs_all=float(err.max()) if err.size else 0.0,
+        rms_all=float(np.sqrt((err ** 2).mean())) if err.size else 0.0)
+
+
+def assert_fp32_parity(m: dict):
+    assert m["hit_agree"] >= HIT_AGREE_MIN, m
+    assert m["decision_agree"] >= DECISION_AGREE_MIN, m
+    assert m["max_abs_agree"] <= MAX_ABS, m
+    assert m["rms_agree"] <= RMS, m
+
+
+def frame_to_numpy(fr: dict) -> dict:
+    out = {}
+    for k, v in fr.items():
+        a = v.cpu().numpy()
+        if k == "ao_mask":
+            a = a.view(np.uint32)
+        out[k] = a
+    return out
+
+
+def flat_at(fr: dict, pix: np.ndarray) -> dict:
+    """Pick pixels (j*W+i) out of full GPU frames."""
+    out = {}
+    for k in ("rgb", "hit_id", "ao_mask", "light_mask"):
+        if k in fr:
+            a = fr[k]
+            out[k] = a.reshape(-1, 3)[pix] if k == "rgb" else a.reshape(-1)[pix]
+    return out

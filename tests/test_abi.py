@@ -1,0 +1,112 @@
+"""The C-ABI library loads and exports every function include/tr.h declares,
+and argument validation rejects bad input before any device work (no GPU
+needed for these calls)."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tr.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tr_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def tr():
+    import paper_0801_1500_amd as tr
+    if not os.path.exists(tr.LIB_PATH):
+        from paper_0801_1500_amd import build
+        build.build()
+    return tr
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("tr_scene_build", "tr_render", "tr_render_batch", "tr_scene_destroy",
+              "tr_last_error", "tr_abi_version"):
+        assert n in names
+
+
+def test_every_declared_symbol_exported(tr):
+    L = tr.lib()
+    for n in _declared():
+        assert hasattr(L, n), n
+    assert tr.abi_version() == 1
+
+
+def test_tile_count(tr):
+    assert tr.tile_count(128, 128) == 256
+    assert tr.tile_count(3860, 4548, 8) == 483 * 569
+    assert tr.tile_count(65, 9, 16) == 5 * 3
+    with pytest.raises(ValueError):
+        tr.tile_count(10, 10, 7)
+
+
+def test_frame_footprint(tr):
+    import scenegen
+    c = scenegen.protein_camera(scenegen.RES_17MP)
+    p = scenegen.Params()
+    assert tr.frame_footprint(c, p, 1) == 3860 * 4548 * 12
+    assert tr.frame_footprint(c, p, 15) == 3860 * 4548 * 21
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_scene_validation_rejects(tr):
+    L = tr.lib()
+    good_c = np.zeros((1, 3)); good_r = np.ones(1); rgb = np.ones((1, 3), np.float32)
+    bad_r = np.array([0.0]); nan_c = np.array([[math.nan, 0.0, 0.0]])
+
+    def build(center, radius, n_lights=0, cells=0.0, cyl=None):
+        args = [1, center.ctypes.data, radius.ctypes.data, rgb.ctypes.data]
+        if cyl is None:
+            args += [0, None, None, None, None]
+        else:
+            a, b = cyl
+            args += [1, a.ctypes.data, b.ctypes.data, good_r.ctypes.data, rgb.ctypes.data]
+        ld = np.array([[0.0, 0.0, 1.0]] * max(n_lights, 1))
+        args += [n_lights, ld.ctypes.data, ld.ctypes.data, cells]
+        d = tr.SceneDesc(*args)
+        h = C.c_void_p()
+        return L.tr_scene_build(C.byref(d), None, C.byref(h))
+
+    assert build(good_c, bad_r) == tr.TR_EINVAL
+    assert b"radius" in L.tr_last_error()
+    assert build(nan_c, good_r) == tr.TR_EINVAL
+    assert build(good_c, good_r, n_lights=9) == tr.TR_EINVAL
+    assert build(good_c, good_r, cells=-1.0) == tr.TR_EINVAL
+    z = np.zeros((1, 3))
+    assert build(good_c, good_r, cyl=(z, z)) == tr.TR_EINVAL
+    assert b"zero length" in L.tr_last_error()
+    h = C.c_void_p()
+    assert L.tr_scene_build(None, None, C.byref(h)) == tr.TR_EINVAL
+
+
+def test_render_validation_rejects(tr):
+    import scenegen
+    L = tr.lib()
+    c = tr.make_camera(scenegen.protein_camera())
+    p = tr.make_params(scenegen.Params())
+    f = tr.Frame(None, None, None, None, None)
+    # NULL scene / frame->rgb, checked before any device call
+    assert L.tr_render(None, C.byref(c), C.byref(p), C.byref(f), None) == tr.TR_EINVAL
+    assert L.tr_render_batch(0, None, None, None, None, None) == tr.TR_EINVAL
+    assert L.tr_render_batch_tiles(1, None, None, None, None, None, None, None, None) == tr.TR_EINVAL
+    assert L.tr_graph_launch(None, None) == tr.TR_EINVAL
+    assert L.tr_debug_philox(-1, None, None, None, None) == tr.TR_EINVAL
+    assert L.tr_autotune(None, None, None, None, None, None) == tr.TR_EINVAL
+
+
+def test_default_tune(tr):
+    t = tr.default_tune()
+    assert t["tile_w"] in (4, 8, 16, 32) and t["banks"] in (2, 3)
