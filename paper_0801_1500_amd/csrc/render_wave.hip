@@ -10,7 +10,8 @@
 //   finish   lanes whose ray ended hand in the result: a primary hit writes
 //            its slot and queues the slot on the wave's LDS FIFO; a shadow or
 //            AO ray sets its occlusion bit; the last ray of a pixel shades it
-//            and writes the frame;
+//            and writes the frame.  Lanes paused on a near-grazing test are
+//            re-solved in FP64 just before this phase and resume;
 //   refill   idle lanes are compacted (ballot + mbcnt) onto the next
 //            secondary rays of the FIFO, then onto fresh primary rays, and a
 //            new tile is fetched when a bank frees;
@@ -21,10 +22,13 @@
 // Secondary rays are not stored: a FIFO entry is a slot, and a lane rebuilds
 // ray s of that slot from the slot's hit point and normal (the AO direction
 // from Philox keyed by pixel and sample), so the queue costs one byte per
-// pixel.  Intersection and shading run in FP32; a sphere or cylinder test
-// whose discriminant is within 2^-12 of its scale, or whose axial hit is
-// within 2^-12 L of a cylinder end, is re-solved in FP64 with the FP64
-// primitive (primary rays are regenerated in FP64 from their pixel).
+// pixel.  Intersection and shading run in FP32.  A sphere or cylinder test
+// whose discriminant is within 2^-12 of its scale, or whose axial hit lies
+// within 2^-12 L of a cylinder end, pauses the lane; the re-solve phase
+// repeats it in FP64 with the FP64 primitive (primary rays regenerated in
+// FP64 from their pixel) and the walk resumes.  Keeping all FP64 code out of
+// the traversal loop keeps the loop's register footprint, and so the
+// occupancy, that of the FP32 path.
 #include "tr_internal.h"
 
 namespace {
@@ -36,6 +40,16 @@ constexpr float kKappa = 1.0f / 4096.0f;
 constexpr double kEpsD = 1e-4;
 
 enum : int32_t { kIdle = 0, kPrimary = 1, kShadow = 2, kAO = 3 };
+
+// Per-bank copy of the job fields secondary rays and shading need.
+struct BankInfo {
+  int32_t job, x0, y0, vw, n, done;
+  int32_t W, S, n_lights;
+  uint32_t key0, key1, view;
+  float maxd, sky;
+  float ldir[8][3];
+  float lcol[8][3];
+};
 
 template <int BANKS>
 struct Lds {
@@ -51,8 +65,8 @@ struct Lds {
   int32_t aocnt[NS];
   uint32_t lmask[NS];
   uint8_t fifo[NS];
-  int32_t bank_job[BANKS], bank_x0[BANKS], bank_y0[BANKS], bank_vw[BANKS], bank_n[BANKS];
-  int32_t bank_done[BANKS];
+  BankInfo bank[BANKS];
+  uint32_t cnt[4];
 };
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
@@ -70,7 +84,7 @@ struct Ray {
   float ox, oy, oz, dx, dy, dz;
   float tmin, tmax;  // t interval of accepted hits
   float t1;          // exit of the grid box (clipped to tmax)
-  float bx, by, bz;  // plane t = base + plane_index * hid  (per axis)
+  float bx, by, bz;  // boundary plane i of axis a is crossed at t = b_a + i * h_a
   float hx, hy, hz;
   float tnx, tny, tnz;
   int32_t cx, cy, cz;
@@ -81,10 +95,47 @@ struct Ray {
   int32_t skip;
 };
 
+// Scene fields used by the traversal, loaded (wave-uniform) from the job
+// table at the start of each phase.
+struct SceneHot {
+  const uint32_t *refs, *cell_begin;
+  const float4 *sph32, *cylA32, *cylW32;
+  int32_t n_s;
+  int32_t res[3];
+  float lo32[3], hi32[3], inv32[3], h32[3];
+};
+
+__device__ __forceinline__ SceneHot load_hot(const JobDev *J) {
+  SceneHot H;
+  H.refs = J->sc.refs;
+  H.cell_begin = J->sc.cell_begin;
+  H.sph32 = J->sc.sph32;
+  H.cylA32 = J->sc.cylA32;
+  H.cylW32 = J->sc.cylW32;
+  H.n_s = J->sc.n_s;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    H.res[q] = J->sc.res[q];
+    H.lo32[q] = J->sc.lo32[q];
+    H.hi32[q] = J->sc.hi32[q];
+    H.inv32[q] = J->sc.inv32[q];
+    H.h32[q] = J->sc.h32[q];
+  }
+  return H;
+}
+
+__device__ __forceinline__ void load_cell(Ray &R, const SceneHot &S) {
+  const uint32_t cell = ((uint32_t)R.cz * (uint32_t)S.res[1] + (uint32_t)R.cy) * (uint32_t)S.res[0] +
+                        (uint32_t)R.cx;
+  uint2 be;
+  __builtin_memcpy(&be, S.cell_begin + cell, sizeof be);
+  R.rc = be.x;
+  R.re = be.y;
+}
+
 // Clip to the grid box and position the walk at the entry cell.
 // Returns false when the ray misses the box.
-template <class SC>
-__device__ __forceinline__ bool ray_setup(Ray &R, const SC &S) {
+__device__ __forceinline__ bool ray_setup(Ray &R, const SceneHot &S) {
   const float ix = rcpf(R.dx), iy = rcpf(R.dy), iz = rcpf(R.dz);
   float t0 = R.tmin, t1 = R.tmax;
   {
@@ -122,37 +173,8 @@ __device__ __forceinline__ bool ray_setup(Ray &R, const SC &S) {
   R.tnx = R.sx ? fmaf((float)(R.cx + (R.sx > 0)), R.hx, R.bx) : INFINITY;
   R.tny = R.sy ? fmaf((float)(R.cy + (R.sy > 0)), R.hy, R.by) : INFINITY;
   R.tnz = R.sz ? fmaf((float)(R.cz + (R.sz > 0)), R.hz, R.bz) : INFINITY;
-  const uint32_t cell = ((uint32_t)R.cz * (uint32_t)S.res[1] + (uint32_t)R.cy) * (uint32_t)S.res[0] +
-                        (uint32_t)R.cx;
-  R.rc = S.cell_begin[cell];
-  R.re = S.cell_begin[cell + 1];
+  load_cell(R, S);
   return true;
-}
-
-// FP64 re-solve of one sphere / cylinder test.
-__device__ __noinline__ int resolve_f64(const SceneDev &S, int32_t k, const double o[3],
-                                        const double d[3], double tmin, double tmax, double &t) {
-  if (k < S.n_s) return hit_sphere_f64(S.sph64[k], o, d, tmin, tmax, t);
-  return hit_cylinder_f64(S.cylA64[k - S.n_s], S.cylW64[k - S.n_s], o, d, tmin, tmax, t);
-}
-
-// The lane's ray promoted to FP64: primary rays are regenerated exactly from
-// their pixel; secondary rays promote the FP32 origin and renormalise the
-// direction.
-__device__ __noinline__ void ray_f64(const Ray &R, bool primary, const JobDev *job, int32_t pi,
-                                     int32_t pj, double o[3], double d[3]) {
-  if (primary) {
-    primary_ray_f64(*job, pi, pj, o, d);
-    return;
-  }
-  o[0] = R.ox;
-  o[1] = R.oy;
-  o[2] = R.oz;
-  const double v[3] = {(double)R.dx, (double)R.dy, (double)R.dz};
-  const double n = sqrt(dot3d(v, v));
-  d[0] = v[0] / n;
-  d[1] = v[1] / n;
-  d[2] = v[2] / n;
 }
 
 struct WaveArgs {
@@ -174,45 +196,15 @@ __device__ __forceinline__ int32_t find_job(const JobDev *jobs, int32_t n, int64
   return lo;
 }
 
-// Scene fields used by the traversal, loaded (wave-uniform) from the job
-// table at the start of each phase.
-struct SceneHot {
-  const uint32_t *refs, *cell_begin;
-  const float4 *sph32, *cylA32, *cylW32;
-  int32_t n_s;
-  int32_t res[3];
-  float lo32[3], hi32[3], inv32[3], h32[3];
-};
-
-__device__ __forceinline__ SceneHot load_hot(const JobDev *J) {
-  SceneHot H;
-  H.refs = J->sc.refs;
-  H.cell_begin = J->sc.cell_begin;
-  H.sph32 = J->sc.sph32;
-  H.cylA32 = J->sc.cylA32;
-  H.cylW32 = J->sc.cylW32;
-  H.n_s = J->sc.n_s;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    H.res[q] = J->sc.res[q];
-    H.lo32[q] = J->sc.lo32[q];
-    H.hi32[q] = J->sc.hi32[q];
-    H.inv32[q] = J->sc.inv32[q];
-    H.h32[q] = J->sc.h32[q];
-  }
-  return H;
-}
-
 template <int BANKS, bool RESOLVE, bool COUNT>
 __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
   __shared__ Lds<BANKS> L;
-  __shared__ uint32_t cnt_sh[4];
   constexpr int NS = BANKS * 64;
   constexpr int kMinIters = 2;
   const int32_t lane = threadIdx.x;
   const int32_t TW = A.tile_w;
   const int32_t TH = 64 / TW;
-  if (lane < 4) cnt_sh[lane] = 0;
+  if (lane < 4) L.cnt[lane] = 0;
 
   // ---- wave-uniform control state
   int32_t q_head = 0, q_tail = 0, head_issued = 0;
@@ -226,21 +218,66 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
   int32_t issue_job = 0;  // job of issue_bank
   int32_t idle_rounds = 0;
 
-  // ---- counters
+  // ---- counters (wave-uniform)
   uint64_t c_cells = 0, c_st = 0, c_sh = 0, c_ct = 0, c_ch = 0, c_res = 0, c_rays = 0;
-  uint32_t l_pix = 0, l_hit = 0, l_ao = 0, l_shadow = 0;  // per lane
 
   // ---- per-lane state
   int32_t kind = kIdle;
   bool done = false;
+  bool paused = false;  // waiting for an FP64 re-solve of primitive gk
+  int32_t gk = 0;
   int32_t slot = 0, ridx = 0;
-  int32_t pi = 0, pj = 0;  // pixel of the lane's ray
+  uint32_t l_pix = 0, l_hit = 0, l_ao = 0, l_shadow = 0;
   Ray R;
   R.bk = -1;
   R.rc = R.re = 0;
   __syncthreads();
 
   for (;;) {
+    // ============================================================ re-solve
+    if (RESOLVE && __ballot(paused)) {
+      if (paused) {
+        const int32_t bk = slot >> 6;
+        const JobDev *J = &A.jobs[L.bank[bk].job];
+        const SceneDev &S = J->sc;
+        double o[3], d[3];
+        if (kind == kPrimary) {
+          const int32_t q = slot & 63;
+          const int32_t vw = L.bank[bk].vw;
+          primary_ray_f64(*J, L.bank[bk].x0 + q % vw, L.bank[bk].y0 + q / vw, o, d);
+        } else {
+          o[0] = R.ox;
+          o[1] = R.oy;
+          o[2] = R.oz;
+          const double v[3] = {(double)R.dx, (double)R.dy, (double)R.dz};
+          const double n = sqrt(dot3d(v, v));
+          d[0] = v[0] / n;
+          d[1] = v[1] / n;
+          d[2] = v[2] / n;
+        }
+        const double tmin = kind == kPrimary ? 0.0 : kEpsD;
+        const double tmax = kind == kAO ? J->ao_maxdist : INFINITY;
+        double t = 0.0;
+        int h;
+        if (gk < S.n_s)
+          h = hit_sphere_f64(S.sph64[gk], o, d, tmin, tmax, t);
+        else
+          h = hit_cylinder_f64(S.cylA64[gk - S.n_s], S.cylW64[gk - S.n_s], o, d, tmin, tmax, t);
+        if (h) {
+          const float tf = (float)t;
+          if (kind != kPrimary) {
+            R.bk = gk;
+            R.bt = tf;
+            done = true;
+          } else if (tf < R.bt || (tf == R.bt && gk < R.bk)) {
+            R.bt = tf;
+            R.bk = gk;
+          }
+        }
+        paused = false;
+      }
+    }
+
     // ================================================================ finish
     if (__ballot(kind != kIdle && done)) {
       const bool fin = kind != kIdle && done;
@@ -249,7 +286,8 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
       bool finalize = fin_prim_miss;
       uint32_t nr = 0;
       if (fin_prim_hit) {
-        const JobDev *jb = &A.jobs[L.bank_job[slot >> 6]];
+        const int32_t bk = slot >> 6;
+        const JobDev *jb = &A.jobs[L.bank[bk].job];
         const SceneDev &S = jb->sc;
         const int32_t k = R.bk;
         const float t = R.bt;
@@ -279,12 +317,12 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
           Nz = -Nz;
         }
         uint32_t lv = 0;
-        const int32_t nl = jb->n_lights;
+        const int32_t nl = L.bank[bk].n_lights;
         for (int l = 0; l < nl; ++l) {
-          const float cl = Nx * jb->ldir32[l][0] + Ny * jb->ldir32[l][1] + Nz * jb->ldir32[l][2];
+          const float cl = Nx * L.bank[bk].ldir[l][0] + Ny * L.bank[bk].ldir[l][1] + Nz * L.bank[bk].ldir[l][2];
           if (cl > 0.0f) lv |= 1u << l;
         }
-        nr = (uint32_t)jb->S + (uint32_t)__popc(lv);
+        nr = (uint32_t)L.bank[bk].S + (uint32_t)__popc(lv);
         L.px[slot] = Px;
         L.py[slot] = Py;
         L.pz[slot] = Pz;
@@ -322,12 +360,13 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
       __syncthreads();
       if (finalize) {
         const int32_t bk = slot >> 6;
+        const BankInfo &B = L.bank[bk];
         const int32_t q = slot & 63;
-        const int32_t vw = L.bank_vw[bk];
-        const int32_t x = L.bank_x0[bk] + q % vw;
-        const int32_t y = L.bank_y0[bk] + q / vw;
-        const JobDev *J = &A.jobs[L.bank_job[bk]];
-        const int64_t pid = (int64_t)y * J->W + x;
+        const int32_t vw = B.vw;
+        const int32_t x = B.x0 + q % vw;
+        const int32_t y = B.y0 + q / vw;
+        const JobDev *J = &A.jobs[B.job];
+        const int64_t pid = (int64_t)y * B.W + x;
         float cr = J->bg[0], cg = J->bg[1], cb = J->bg[2];
         int32_t hid = -1;
         uint32_t am = 0, lm = 0;
@@ -340,22 +379,22 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
           lm = L.lmask[slot];
           am = L.aomask[slot];
           float Dr = 0.0f, Dg = 0.0f, Db = 0.0f;
-          for (int l = 0; l < J->n_lights; ++l) {
+          for (int l = 0; l < B.n_lights; ++l) {
             if (!((lv >> l) & 1u) || ((lm >> l) & 1u)) continue;
-            const float cl = Nx * J->ldir32[l][0] + Ny * J->ldir32[l][1] + Nz * J->ldir32[l][2];
-            Dr += J->lcol32[l][0] * cl;
-            Dg += J->lcol32[l][1] * cl;
-            Db += J->lcol32[l][2] * cl;
+            const float cl = Nx * B.ldir[l][0] + Ny * B.ldir[l][1] + Nz * B.ldir[l][2];
+            Dr += B.lcol[l][0] * cl;
+            Dg += B.lcol[l][1] * cl;
+            Db += B.lcol[l][2] * cl;
           }
           float ao = 1.0f;
-          if (J->S > 0) ao = (float)(J->S - L.aocnt[slot]) / (float)J->S;
+          if (B.S > 0) ao = (float)(B.S - L.aocnt[slot]) / (float)B.S;
           const float4 alb = J->sc.albedo[k];
-          const float sk = J->sky32 * ao;
+          const float sk = B.sky * ao;
           cr = fminf(fmaxf(alb.x * (Dr + sk), 0.0f), 1.0f);
           cg = fminf(fmaxf(alb.y * (Dg + sk), 0.0f), 1.0f);
           cb = fminf(fmaxf(alb.z * (Db + sk), 0.0f), 1.0f);
           ++l_hit;
-          l_ao += (uint32_t)J->S;
+          l_ao += (uint32_t)B.S;
           l_shadow += (uint32_t)__popc(lv);
         }
         J->rgb[pid * 3 + 0] = cr;
@@ -364,15 +403,16 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
         if (J->hit_id) J->hit_id[pid] = hid;
         if (J->ao_mask) J->ao_mask[pid] = am;
         if (J->light_mask) J->light_mask[pid] = (uint8_t)lm;
-        atomicAdd(&L.bank_done[bk], 1);
+        atomicAdd(&L.bank[bk].done, 1);
       }
       if (fin) kind = kIdle;
       __syncthreads();
       // free banks whose pixels are all shaded
       for (int b = 0; b < BANKS; ++b) {
         if (!((bank_busy >> b) & 1u)) continue;
-        const bool all_issued = issue_bank != b || issue_next == L.bank_n[b];
-        if (all_issued && uni(L.bank_done[b]) == uni(L.bank_n[b])) {
+        const int32_t n_b = uni(L.bank[b].n);
+        const bool all_issued = issue_bank != b || issue_next == n_b;
+        if (all_issued && uni(L.bank[b].done) == n_b) {
           bank_busy &= ~(1u << b);
           if (issue_bank == b) issue_bank = -1;
         }
@@ -397,34 +437,30 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
           if (me_idle && rank >= assigned && rank < assigned + take) {
             slot = s;
             ridx = head_issued + (rank - assigned);
-            const int32_t bk = s >> 6;
-            const JobDev *J = &A.jobs[L.bank_job[bk]];
-            const int32_t q = s & 63;
-            const int32_t vw = L.bank_vw[bk];
-            pi = L.bank_x0[bk] + q % vw;
-            pj = L.bank_y0[bk] + q / vw;
+            const BankInfo &B = L.bank[s >> 6];
             R.ox = L.px[s];
             R.oy = L.py[s];
             R.oz = L.pz[s];
             R.skip = L.skip[s];
             R.tmin = kEps;
-            const int32_t S_ao = J->S;
-            if (ridx < S_ao) {
+            if (ridx < B.S) {
               kind = kAO;
+              const int32_t q = s & 63;
+              const int32_t vw = B.vw;
+              const uint32_t pid = (uint32_t)((B.y0 + q / vw) * B.W + B.x0 + q % vw);
               uint32_t b1, b2;
-              ao_uniform_bits((uint32_t)((int64_t)pj * J->W + pi), (uint32_t)ridx, J->view_id,
-                              J->key0, J->key1, b1, b2);
+              ao_uniform_bits(pid, (uint32_t)ridx, B.view, B.key0, B.key1, b1, b2);
               ao_dir_f32(L.nx[s], L.ny[s], L.nz[s], b1, b2, R.dx, R.dy, R.dz);
-              R.tmax = J->ao_maxdist32;
+              R.tmax = B.maxd;
             } else {
               kind = kShadow;
               uint32_t lv = L.lvalid[s];  // the (ridx - S)-th light with N.L > 0
-              for (int32_t n = ridx - S_ao; n > 0; --n) lv &= lv - 1;
+              for (int32_t n = ridx - B.S; n > 0; --n) lv &= lv - 1;
               const int32_t l = __ffs(lv) - 1;
               ridx = l;
-              R.dx = J->ldir32[l][0];
-              R.dy = J->ldir32[l][1];
-              R.dz = J->ldir32[l][2];
+              R.dx = B.ldir[l][0];
+              R.dy = B.ldir[l][1];
+              R.dz = B.ldir[l][2];
               R.tmax = INFINITY;
             }
             setup_ok = ray_setup(R, H);
@@ -440,7 +476,7 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
       }
       // primary rays
       while (assigned < n_idle) {
-        if (issue_bank < 0 || issue_next == uni(L.bank_n[issue_bank])) {
+        if (issue_bank < 0 || issue_next == uni(L.bank[issue_bank].n)) {
           issue_bank = -1;
           const uint32_t free_banks = ~bank_busy & ((1u << BANKS) - 1u);
           if (!free_banks) break;
@@ -469,12 +505,26 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
           const int32_t x0 = tx * TW, y0 = ty * TH;
           const int32_t vw = min(TW, J->W - x0), vh = min(TH, J->H - y0);
           if (lane == 0) {
-            L.bank_job[b] = held_job;
-            L.bank_x0[b] = x0;
-            L.bank_y0[b] = y0;
-            L.bank_vw[b] = vw;
-            L.bank_n[b] = vw * vh;
-            L.bank_done[b] = 0;
+            BankInfo &B = L.bank[b];
+            B.job = held_job;
+            B.x0 = x0;
+            B.y0 = y0;
+            B.vw = vw;
+            B.n = vw * vh;
+            B.done = 0;
+            B.W = J->W;
+            B.S = J->S;
+            B.n_lights = J->n_lights;
+            B.key0 = J->key0;
+            B.key1 = J->key1;
+            B.view = J->view_id;
+            B.maxd = J->ao_maxdist32;
+            B.sky = J->sky32;
+          }
+          if (lane < 24) {
+            const int32_t l = lane / 3, a = lane % 3;
+            L.bank[b].ldir[l][a] = J->ldir32[l][a];
+            L.bank[b].lcol[l][a] = J->lcol32[l][a];
           }
           __syncthreads();
           bank_busy |= 1u << b;
@@ -483,16 +533,16 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
           issue_next = 0;
           held_tile = -1;
         }
-        const int32_t nvalid = uni(L.bank_n[issue_bank]);
+        const int32_t nvalid = uni(L.bank[issue_bank].n);
         const int32_t take = min(nvalid - issue_next, n_idle - assigned);
         if (me_idle && rank >= assigned && rank < assigned + take) {
           const int32_t q = issue_next + (rank - assigned);
           slot = issue_bank * 64 + q;
           const JobDev *J = &A.jobs[issue_job];
           const SceneHot H = load_hot(J);
-          const int32_t vw = L.bank_vw[issue_bank];
-          pi = L.bank_x0[issue_bank] + q % vw;
-          pj = L.bank_y0[issue_bank] + q / vw;
+          const int32_t vw = L.bank[issue_bank].vw;
+          const int32_t pi = L.bank[issue_bank].x0 + q % vw;
+          const int32_t pj = L.bank[issue_bank].y0 + q / vw;
           kind = kPrimary;
           const float x = ((2.0f * ((float)pi + 0.5f)) / (float)J->W - 1.0f) * J->th32 * J->aspect32;
           const float y = (1.0f - (2.0f * ((float)pj + 0.5f)) / (float)J->H) * J->th32;
@@ -537,18 +587,18 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
     {
       const uint32_t free_banks = ~bank_busy & ((1u << BANKS) - 1u);
       const bool can_refill =
-          q_head != q_tail || (issue_bank >= 0 && issue_next < uni(L.bank_n[issue_bank])) ||
+          q_head != q_tail || (issue_bank >= 0 && issue_next < uni(L.bank[issue_bank].n)) ||
           (free_banks && ((held_tile < 0 && tiles_left) || (held_tile >= 0 && (held_key == cur_key || !bank_busy))));
       const SceneHot H = load_hot(&A.jobs[scene_job]);
-      const JobDev *const jobs = A.jobs;
+      const int32_t thresh = can_refill ? A.refill_below : 1;
+      const bool anyhit = kind != kPrimary;
       for (int32_t it = 0;; ++it) {
-        const bool work = kind != kIdle && !done;
+        const bool work = kind != kIdle && !done && !paused;
         const int32_t nwork = __popcll(__ballot(work));
         if (nwork == 0) break;
         if (it >= kMinIters) {
-          if (can_refill && nwork < A.refill_below) break;
-          // finished primaries would queue new rays
-          if (nwork < A.refill_below && __ballot(kind == kPrimary && done)) break;
+          if (nwork < thresh) break;
+          if (RESOLVE && nwork < A.refill_below && __ballot(paused)) break;
         }
         if (work) {
           if (R.rc < R.re) {
@@ -556,9 +606,8 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
             const int32_t k = (int32_t)H.refs[R.rc];
             ++R.rc;
             if (k != R.skip) {
-              float t = 0.0f;
-              bool hit = false;
-              bool graze = false;
+              float t;
+              bool hit, graze;
               if (k < H.n_s) {
                 if (COUNT) c_st += __popcll(__ballot(true));
                 const float4 s = H.sph32[k];
@@ -568,22 +617,20 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
                 const float ll = lx * lx + ly * ly + lz * lz;
                 const float rr = s.w * s.w;
                 const float disc = rr - ll;
-                if (RESOLVE && fabsf(disc) <= kKappa * (rr + ll)) {
-                  graze = true;
-                } else if (disc >= 0.0f) {
-                  const float sq = sqrtf_fast(disc);
-                  const float t0 = b - sq, t1 = b + sq;
-                  if (t0 > R.tmin && t0 <= R.tmax) {
-                    t = t0;
-                    hit = true;
-                  } else if (t1 > R.tmin && t1 <= R.tmax) {
-                    t = t1;
-                    hit = true;
-                  }
-                }
+                graze = RESOLVE && fabsf(disc) <= kKappa * (rr + ll);
+                const float sq = sqrtf_fast(fmaxf(disc, 0.0f));
+                const float t0 = b - sq, t1 = b + sq;
+                const bool ok = disc >= 0.0f && !graze;
+                const bool h0 = ok && t0 > R.tmin && t0 <= R.tmax;
+                const bool h1 = ok && t1 > R.tmin && t1 <= R.tmax;
+                hit = h0 || h1;
+                t = h0 ? t0 : t1;
                 if (COUNT) c_sh += __popcll(__ballot(hit));
               } else {
                 if (COUNT) c_ct += __popcll(__ballot(true));
+                hit = false;
+                graze = false;
+                t = 0.0f;
                 const float4 a = H.cylA32[k - H.n_s];
                 const float4 w = H.cylW32[k - H.n_s];
                 const float Dx = R.ox - a.x, Dy = R.oy - a.y, Dz = R.oz - a.z;
@@ -594,35 +641,27 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
                 const float Aq = dpx * dpx + dpy * dpy + dpz * dpz;
                 const float Bq = dpx * Dpx + dpy * Dpy + dpz * Dpz;
                 const float Cq = (Dpx * Dpx + Dpy * Dpy + Dpz * Dpz) - a.w * a.w;
+                const float disc = Bq * Bq - Aq * Cq;
                 if (Aq > 1e-12f) {
-                  const float disc = Bq * Bq - Aq * Cq;
-                  if (RESOLVE && fabsf(disc) <= kKappa * (Bq * Bq + fabsf(Aq * Cq))) {
-                    graze = true;
-                  } else if (disc >= 0.0f) {
+                  graze = RESOLVE && fabsf(disc) <= kKappa * (Bq * Bq + fabsf(Aq * Cq));
+                  if (!graze && disc >= 0.0f) {
                     const float sq = sqrtf_fast(disc);
                     const float qq = -(Bq + __builtin_copysignf(sq, Bq));
                     if (qq != 0.0f) {
                       const float r0 = qq * rcpf(Aq), r1 = Cq * rcpf(qq);
                       const float tl = fminf(r0, r1), th = fmaxf(r0, r1);
                       const float kL = kKappa * w.w;
-                      if (tl > R.tmin && tl <= R.tmax) {
-                        const float sa = Dw + tl * dw;
-                        if (RESOLVE && (fabsf(sa) <= kL || fabsf(sa - w.w) <= kL)) {
-                          graze = true;
-                        } else if (sa >= 0.0f && sa <= w.w) {
-                          t = tl;
-                          hit = true;
-                        }
-                      }
-                      if (!hit && !graze && th > R.tmin && th <= R.tmax) {
-                        const float sa = Dw + th * dw;
-                        if (RESOLVE && (fabsf(sa) <= kL || fabsf(sa - w.w) <= kL)) {
-                          graze = true;
-                        } else if (sa >= 0.0f && sa <= w.w) {
-                          t = th;
-                          hit = true;
-                        }
-                      }
+                      const float sl = Dw + tl * dw, sh = Dw + th * dw;
+                      const bool inl = tl > R.tmin && tl <= R.tmax;
+                      const bool inh = th > R.tmin && th <= R.tmax;
+                      const bool gl = RESOLVE && inl && (fabsf(sl) <= kL || fabsf(sl - w.w) <= kL);
+                      const bool gh = RESOLVE && inh && (fabsf(sh) <= kL || fabsf(sh - w.w) <= kL);
+                      const bool hl = inl && !gl && sl >= 0.0f && sl <= w.w;
+                      const bool hh = inh && !gh && sh >= 0.0f && sh <= w.w;
+                      // the near root decides first; an undecidable root defers to FP64
+                      graze = gl || (!hl && gh);
+                      hit = !graze && (hl || hh);
+                      t = hl ? tl : th;
                     }
                   }
                 }
@@ -630,18 +669,10 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
               }
               if (RESOLVE && graze) {
                 if (COUNT) c_res += __popcll(__ballot(true));
-                double o64[3], d64[3], t64 = 0.0;
-                const JobDev *jr = &jobs[L.bank_job[slot >> 6]];
-                ray_f64(R, kind == kPrimary, jr, pi, pj, o64, d64);
-                const double tmin64 = kind == kPrimary ? 0.0 : kEpsD;
-                const double tmax64 = kind == kAO ? jr->ao_maxdist : INFINITY;
-                if (resolve_f64(jr->sc, k, o64, d64, tmin64, tmax64, t64)) {
-                  hit = true;
-                  t = (float)t64;
-                }
-              }
-              if (hit) {
-                if (kind != kPrimary) {
+                paused = true;
+                gk = k;
+              } else if (hit) {
+                if (anyhit) {
                   R.bk = k;
                   R.bt = t;
                   done = true;
@@ -654,55 +685,47 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
           } else {
             // ---- cell exhausted: stop, or step to the next cell
             const float tn = fminf(R.tnx, fminf(R.tny, R.tnz));
-            const float t_exit = fminf(tn, R.t1);
-            if ((R.bk >= 0 && R.bt <= t_exit) || !(tn < R.t1)) {
+            if ((R.bk >= 0 && R.bt <= fminf(tn, R.t1)) || !(tn < R.t1)) {
               done = true;
             } else {
-              int32_t st;
-              if (R.tnx == tn) {
-                st = R.sx;
-                R.cx += R.sx;
-                R.tnx = fmaf((float)(R.cx + (R.sx > 0)), R.hx, R.bx);
-              } else if (R.tny == tn) {
-                st = R.sy;
-                R.cy += R.sy;
-                R.tny = fmaf((float)(R.cy + (R.sy > 0)), R.hy, R.by);
-              } else {
-                st = R.sz;
-                R.cz += R.sz;
-                R.tnz = fmaf((float)(R.cz + (R.sz > 0)), R.hz, R.bz);
-              }
+              const bool ax = R.tnx == tn;
+              const bool ay = !ax && R.tny == tn;
+              const bool az = !ax && !ay;
+              R.cx += ax ? R.sx : 0;
+              R.cy += ay ? R.sy : 0;
+              R.cz += az ? R.sz : 0;
+              const int32_t st = ax ? R.sx : (ay ? R.sy : R.sz);
+              R.tnx = ax ? fmaf((float)(R.cx + (R.sx > 0)), R.hx, R.bx) : R.tnx;
+              R.tny = ay ? fmaf((float)(R.cy + (R.sy > 0)), R.hy, R.by) : R.tny;
+              R.tnz = az ? fmaf((float)(R.cz + (R.sz > 0)), R.hz, R.bz) : R.tnz;
               if (st == 0 || (uint32_t)R.cx >= (uint32_t)H.res[0] ||
                   (uint32_t)R.cy >= (uint32_t)H.res[1] || (uint32_t)R.cz >= (uint32_t)H.res[2]) {
                 done = true;
               } else {
                 if (COUNT) c_cells += __popcll(__ballot(true));
-                const uint32_t cell =
-                    ((uint32_t)R.cz * (uint32_t)H.res[1] + (uint32_t)R.cy) * (uint32_t)H.res[0] +
-                    (uint32_t)R.cx;
-                R.rc = H.cell_begin[cell];
-                R.re = H.cell_begin[cell + 1];
+                load_cell(R, H);
               }
             }
           }
         }
       }
+      (void)anyhit;
     }
   }
 
   // ---- counters
   if (A.stats) {
-    atomicAdd(&cnt_sh[0], l_pix);
-    atomicAdd(&cnt_sh[1], l_hit);
-    atomicAdd(&cnt_sh[2], l_ao);
-    atomicAdd(&cnt_sh[3], l_shadow);
+    atomicAdd(&L.cnt[0], l_pix);
+    atomicAdd(&L.cnt[1], l_hit);
+    atomicAdd(&L.cnt[2], l_ao);
+    atomicAdd(&L.cnt[3], l_shadow);
     __syncthreads();
     if (lane == 0) {
       unsigned long long *st = (unsigned long long *)A.stats;
-      atomicAdd(&st[TR_STAT_PIXELS], (unsigned long long)cnt_sh[0]);
-      atomicAdd(&st[TR_STAT_HIT_PIXELS], (unsigned long long)cnt_sh[1]);
-      atomicAdd(&st[TR_STAT_AO_RAYS], (unsigned long long)cnt_sh[2]);
-      atomicAdd(&st[TR_STAT_SHADOW_RAYS], (unsigned long long)cnt_sh[3]);
+      atomicAdd(&st[TR_STAT_PIXELS], (unsigned long long)L.cnt[0]);
+      atomicAdd(&st[TR_STAT_HIT_PIXELS], (unsigned long long)L.cnt[1]);
+      atomicAdd(&st[TR_STAT_AO_RAYS], (unsigned long long)L.cnt[2]);
+      atomicAdd(&st[TR_STAT_SHADOW_RAYS], (unsigned long long)L.cnt[3]);
       atomicAdd(&st[TR_STAT_RAYS_TRACED], (unsigned long long)c_rays);
       if (COUNT) {
         atomicAdd(&st[TR_STAT_CELLS], (unsigned long long)c_cells);
