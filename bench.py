@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 
 # Algorithmic flop model of the grid method (FP32-equivalent operations; FMA
 # = 2; add, mul, min, max, compare, sqrt, rcp, sin, cos = 1), per counted event.
-FLOP_COST = dict(ray_setup=40, cell=4, sph_test=22, sph_hit=4, cyl_test=45, cyl_hit=12,
+FLOP_COST = dict(ray_setup=40, cell=4, jump=16, sph_test=22, sph_hit=4, cyl_test=45, cyl_hit=12,
                  primary_gen=20, normal=10, per_light=8, onb=12, ao_dir=23, shade=10)
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6  # without packed-FP32 issue
@@ -38,6 +38,7 @@ PEAK_HBM_GBS = 8000.0
 def algorithmic_flops(st: dict, n_lights: int, ao_on: bool) -> float:
     c = FLOP_COST
     return float(c["ray_setup"] * st["rays_traced"] + c["cell"] * st["cells"]
+                 + c["jump"] * st.get("jumps", 0)
                  + c["sph_test"] * st["sph_tests"] + c["sph_hit"] * st["sph_hits"]
                  + c["cyl_test"] * st["cyl_tests"] + c["cyl_hit"] * st["cyl_hits"]
                  + c["primary_gen"] * st["pixels"] + c["normal"] * st["hit_pixels"]

@@ -79,7 +79,7 @@ typedef struct {
   int32_t n_lights;          /* 0..8 directional lights                     */
   const double *light_dir;   /* [n_lights*3] toward the light; normalised by the library */
   const double *light_rgb;   /* [n_lights*3] intensity                      */
-  double cells_per_prim;     /* grid density lambda; 0 => 4.  Speed only.   */
+  double cells_per_prim;     /* grid density lambda; 0 => 16.  Speed only.  */
 } tr_scene_desc;
 
 /* Pinhole camera, one ray through each pixel centre.  width = horizontal
@@ -128,12 +128,16 @@ enum {
   TR_STAT_AO_RAYS,           /* AO rays cast                                */
   TR_STAT_SHADOW_RAYS,       /* light shadow rays cast (N.L > 0)            */
   TR_STAT_RAYS_TRACED,       /* all rays handed to a traversal              */
-  TR_STAT_CELLS,             /* grid cells visited                          */
+  TR_STAT_CELLS,             /* grid cells visited (the FP32 walk skips runs of empty cells) */
   TR_STAT_SPH_TESTS,
   TR_STAT_SPH_HITS,
   TR_STAT_CYL_TESTS,
   TR_STAT_CYL_HITS,
   TR_STAT_RESOLVES,          /* FP64 re-solves of near-grazing tests        */
+  TR_STAT_WAVE_ITERS,        /* wavefront kernel: traversal-loop iterations (per wave) */
+  TR_STAT_LANE_ITERS,        /* wavefront kernel: busy lanes summed over those iterations */
+  TR_STAT_REFILLS,           /* wavefront kernel: finish/refill rounds (per wave) */
+  TR_STAT_JUMPS,             /* wavefront kernel: empty-space jumps over more than one cell */
   TR_STAT_COUNT
 };
 
@@ -145,6 +149,9 @@ typedef struct {
   int32_t waves_per_cu;      /* persistent waves launched per compute unit, 1..32 */
   int32_t refill_below;      /* refill when fewer than this many lanes are busy, 1..64 */
   int32_t count_ops;         /* 1 = also fill the traversal counters of tr_frame.stats */
+  int32_t cyl_wait;          /* cylinder tests run when at least busy/cyl_wait lanes need one, 1..64 */
+  int32_t mix;               /* a work type (step, sphere test, cylinder test) runs in an iteration
+                                when its lanes are >= mix/64 of the largest type's, 1..64 */
 } tr_tune;
 
 /* ---------------------------------------------------------------- scenes */

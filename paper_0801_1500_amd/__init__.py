@@ -22,7 +22,8 @@ PREC_FP64, PREC_FP32, PREC_FP32_RESOLVE = 0, 1, 2
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "fp32_resolve": PREC_FP32_RESOLVE}
 
 STAT_NAMES = ["pixels", "hit_pixels", "ao_rays", "shadow_rays", "rays_traced", "cells",
-              "sph_tests", "sph_hits", "cyl_tests", "cyl_hits", "resolves"]
+              "sph_tests", "sph_hits", "cyl_tests", "cyl_hits", "resolves", "wave_iters",
+              "lane_iters", "refills", "jumps"]
 STAT_COUNT = len(STAT_NAMES)
 
 
@@ -60,7 +61,8 @@ class Frame(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("banks", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("refill_below", C.c_int32), ("count_ops", C.c_int32)]
+                ("refill_below", C.c_int32), ("count_ops", C.c_int32), ("cyl_wait", C.c_int32),
+                ("mix", C.c_int32)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -155,7 +157,8 @@ def make_tune(tune) -> Optional[Tune]:
         return tune
     return Tune(int(tune.get("tile_w", 0)), int(tune.get("banks", 0)),
                 int(tune.get("waves_per_cu", 0)), int(tune.get("refill_below", 0)),
-                int(tune.get("count_ops", 0)))
+                int(tune.get("count_ops", 0)), int(tune.get("cyl_wait", 0)),
+                int(tune.get("mix", 0)))
 
 
 class Scene:

@@ -229,6 +229,51 @@ __global__ void k_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32
   }
 }
 
+// ---- empty-space distance field for the FP32 traversal
+// dist(c) = Chebyshev distance, in cells, from c to the nearest occupied
+// cell, capped at kDistCap (0 for occupied cells).  Computed as three
+// separable passes g(x) = min_r max(|r|, g(x + r e_axis)): the L-infinity
+// distance is the min over occupied y of max over axes of |x_a - y_a|, and
+// max distributes over min, so the axes can be taken one at a time.
+constexpr int kDistCap = 32;
+
+__global__ void k_dist_init(const uint32_t *cell_begin, int64_t n_cells, uint8_t *d) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  d[c] = cell_begin[c + 1] > cell_begin[c] ? 0 : kDistCap;
+}
+
+__global__ void k_dist_pass(const uint8_t *in, uint8_t *out, int32_t rx, int32_t ry, int32_t rz,
+                            int axis) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)rx * ry * rz;
+  if (c >= n) return;
+  const int32_t ix = (int32_t)(c % rx);
+  const int32_t iy = (int32_t)((c / rx) % ry);
+  const int32_t iz = (int32_t)(c / ((int64_t)rx * ry));
+  const int32_t p = axis == 0 ? ix : (axis == 1 ? iy : iz);
+  const int32_t len = axis == 0 ? rx : (axis == 1 ? ry : rz);
+  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? (int64_t)rx : (int64_t)rx * ry);
+  int32_t best = in[c];
+  for (int32_t r = 1; r < best; ++r) {  // a neighbour r away can only give >= r
+    const int32_t a = p - r >= 0 ? (int32_t)in[c - r * stride] : kDistCap;
+    const int32_t b = p + r < len ? (int32_t)in[c + r * stride] : kDistCap;
+    const int32_t v = max(r, min(a, b));
+    best = min(best, v);
+  }
+  out[c] = (uint8_t)best;
+}
+
+// Traversal view of a cell: (begin, end) of its references, or (dist, 0)
+// for an empty cell, so one 8-byte load tells the walk both.
+__global__ void k_cellinfo(const uint32_t *cell_begin, const uint8_t *d, int64_t n_cells,
+                           uint2 *info) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  const uint32_t b = cell_begin[c], e = cell_begin[c + 1];
+  info[c] = b < e ? make_uint2(b, e) : make_uint2(max((uint32_t)d[c], 1u), 0u);
+}
+
 // ---- exclusive scan: blocks of kScanItems, block sums scanned recursively
 constexpr int kScanPer = 4;
 constexpr int kScanItems = kBlock * kScanPer;
@@ -377,6 +422,19 @@ hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32
                              hipStream_t st) {
   if (n_cells <= 0) return hipSuccess;
   k_sort_cells<<<blocks_for(n_cells), kBlock, 0, st>>>(cell_begin, n_cells, refs);
+  return hipGetLastError();
+}
+
+hipError_t launch_cellinfo(const uint32_t *cell_begin, const int32_t res[3], uint8_t *d0, uint8_t *d1,
+                           uint2 *info, hipStream_t st) {
+  const int64_t n = (int64_t)res[0] * res[1] * res[2];
+  if (n <= 0) return hipSuccess;
+  const unsigned nb = blocks_for(n);
+  k_dist_init<<<nb, kBlock, 0, st>>>(cell_begin, n, d0);
+  k_dist_pass<<<nb, kBlock, 0, st>>>(d0, d1, res[0], res[1], res[2], 0);
+  k_dist_pass<<<nb, kBlock, 0, st>>>(d1, d0, res[0], res[1], res[2], 1);
+  k_dist_pass<<<nb, kBlock, 0, st>>>(d0, d1, res[0], res[1], res[2], 2);
+  k_cellinfo<<<nb, kBlock, 0, st>>>(cell_begin, d1, n, info);
   return hipGetLastError();
 }
 

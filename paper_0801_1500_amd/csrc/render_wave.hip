@@ -66,7 +66,7 @@ struct Lds {
   uint32_t lmask[NS];
   uint8_t fifo[NS];
   BankInfo bank[BANKS];
-  uint32_t cnt[4];
+  uint32_t cnt[11];
 };
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
@@ -86,10 +86,10 @@ struct Ray {
   float t1;          // exit of the grid box (clipped to tmax)
   float bx, by, bz;  // boundary plane i of axis a is crossed at t = b_a + i * h_a
   float hx, hy, hz;
-  float tnx, tny, tnz;
   int32_t cx, cy, cz;
   int32_t sx, sy, sz;  // step signs
-  uint32_t rc, re;     // reference cursor / end in the current cell
+  uint32_t rc, re;     // reference cursor / end in the current cell; (dist, 0) if empty
+  int32_t nk;          // refs[rc] when rc < re, else -1 (loaded one iteration ahead)
   float bt;            // best t
   int32_t bk;          // best id (-1 = none)
   int32_t skip;
@@ -97,9 +97,15 @@ struct Ray {
 
 // Scene fields used by the traversal, loaded (wave-uniform) from the job
 // table at the start of each phase.
+// Hot pointers are in the global address space so loads compile to global
+// (not flat) instructions with a scalar base.
+#define TR_GLOBAL __attribute__((address_space(1)))
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef uint32_t vu2 __attribute__((ext_vector_type(2)));
 struct SceneHot {
-  const uint32_t *refs, *cell_begin;
-  const float4 *sph32, *cylA32, *cylW32;
+  const TR_GLOBAL uint32_t *refs;
+  const TR_GLOBAL vu2 *cellinfo;
+  const TR_GLOBAL vf4 *sph32, *cylA32, *cylW32;
   int32_t n_s;
   int32_t res[3];
   float lo32[3], hi32[3], inv32[3], h32[3];
@@ -107,11 +113,11 @@ struct SceneHot {
 
 __device__ __forceinline__ SceneHot load_hot(const JobDev *J) {
   SceneHot H;
-  H.refs = J->sc.refs;
-  H.cell_begin = J->sc.cell_begin;
-  H.sph32 = J->sc.sph32;
-  H.cylA32 = J->sc.cylA32;
-  H.cylW32 = J->sc.cylW32;
+  H.refs = (const TR_GLOBAL uint32_t *)J->sc.refs;
+  H.cellinfo = (const TR_GLOBAL vu2 *)J->sc.cellinfo;
+  H.sph32 = (const TR_GLOBAL vf4 *)J->sc.sph32;
+  H.cylA32 = (const TR_GLOBAL vf4 *)J->sc.cylA32;
+  H.cylW32 = (const TR_GLOBAL vf4 *)J->sc.cylW32;
   H.n_s = J->sc.n_s;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -127,10 +133,11 @@ __device__ __forceinline__ SceneHot load_hot(const JobDev *J) {
 __device__ __forceinline__ void load_cell(Ray &R, const SceneHot &S) {
   const uint32_t cell = ((uint32_t)R.cz * (uint32_t)S.res[1] + (uint32_t)R.cy) * (uint32_t)S.res[0] +
                         (uint32_t)R.cx;
-  uint2 be;
-  __builtin_memcpy(&be, S.cell_begin + cell, sizeof be);
+  const vu2 be = S.cellinfo[cell];
   R.rc = be.x;
   R.re = be.y;
+  const int32_t v = (int32_t)S.refs[be.x];  // in bounds: refs carries 64 padding entries
+  R.nk = be.x < be.y ? v : -1;
 }
 
 // Clip to the grid box and position the walk at the entry cell.
@@ -170,9 +177,6 @@ __device__ __forceinline__ bool ray_setup(Ray &R, const SceneHot &S) {
   R.hx = S.h32[0] * ix;
   R.hy = S.h32[1] * iy;
   R.hz = S.h32[2] * iz;
-  R.tnx = R.sx ? fmaf((float)(R.cx + (R.sx > 0)), R.hx, R.bx) : INFINITY;
-  R.tny = R.sy ? fmaf((float)(R.cy + (R.sy > 0)), R.hy, R.by) : INFINITY;
-  R.tnz = R.sz ? fmaf((float)(R.cz + (R.sz > 0)), R.hz, R.bz) : INFINITY;
   load_cell(R, S);
   return true;
 }
@@ -183,7 +187,7 @@ struct WaveArgs {
   int64_t n_tiles;
   uint32_t *tile_counter;
   uint64_t *stats;
-  int32_t tile_w, refill_below;
+  int32_t tile_w, refill_below, cyl_wait, mix;
 };
 
 __device__ __forceinline__ int32_t find_job(const JobDev *jobs, int32_t n, int64_t tile) {
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
   const int32_t lane = threadIdx.x;
   const int32_t TW = A.tile_w;
   const int32_t TH = 64 / TW;
-  if (lane < 4) L.cnt[lane] = 0;
+  if (lane < 11) L.cnt[lane] = 0;
 
   // ---- wave-uniform control state
   int32_t q_head = 0, q_tail = 0, head_issued = 0;
@@ -215,28 +219,30 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
   int32_t held_job = 0, held_key = -1;
   int32_t cur_key = -1;   // scene loaded in this wave
   int32_t scene_job = 0;  // a job whose scene is the current one
-  int32_t issue_job = 0;  // job of issue_bank
   int32_t idle_rounds = 0;
 
   // ---- counters (wave-uniform)
-  uint64_t c_cells = 0, c_st = 0, c_sh = 0, c_ct = 0, c_ch = 0, c_res = 0, c_rays = 0;
+  uint64_t c_rays = 0;
+  uint32_t l_cells = 0, l_st = 0, l_sh = 0, l_ct = 0, l_ch = 0, l_res = 0, l_jumps = 0;  // per lane
+  uint64_t c_iters = 0, c_lanes = 0, c_refills = 0;
 
   // ---- per-lane state
   int32_t kind = kIdle;
-  bool done = false;
-  bool paused = false;  // waiting for an FP64 re-solve of primitive gk
+  int32_t done = 0;    // ray finished (kept as an int: per-lane flags stay in VGPRs)
+  int32_t paused = 0;  // waiting for an FP64 re-solve of primitive gk
   int32_t gk = 0;
   int32_t slot = 0, ridx = 0;
   uint32_t l_pix = 0, l_hit = 0, l_ao = 0, l_shadow = 0;
   Ray R;
   R.bk = -1;
   R.rc = R.re = 0;
+  R.nk = -1;
   __syncthreads();
 
   for (;;) {
     // ============================================================ re-solve
-    if (RESOLVE && __ballot(paused)) {
-      if (paused) {
+    if (RESOLVE && __ballot(paused != 0)) {
+      if (paused != 0) {
         const int32_t bk = slot >> 6;
         const JobDev *J = &A.jobs[L.bank[bk].job];
         const SceneDev &S = J->sc;
@@ -268,19 +274,19 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
           if (kind != kPrimary) {
             R.bk = gk;
             R.bt = tf;
-            done = true;
+            done = 1;
           } else if (tf < R.bt || (tf == R.bt && gk < R.bk)) {
             R.bt = tf;
             R.bk = gk;
           }
         }
-        paused = false;
+        paused = 0;
       }
     }
 
     // ================================================================ finish
-    if (__ballot(kind != kIdle && done)) {
-      const bool fin = kind != kIdle && done;
+    if (__ballot(kind != kIdle && done != 0)) {
+      const bool fin = kind != kIdle && done != 0;
       const bool fin_prim_hit = fin && kind == kPrimary && R.bk >= 0;
       const bool fin_prim_miss = fin && kind == kPrimary && R.bk < 0;
       bool finalize = fin_prim_miss;
@@ -426,55 +432,25 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
       const int32_t rank = (int32_t)lane_rank(idle);
       const bool me_idle = kind == kIdle;
       int32_t assigned = 0;
-      bool setup_ok = true;
-      // secondary rays from the FIFO
-      if (q_head != q_tail && n_idle > 0) {
-        const SceneHot H = load_hot(&A.jobs[scene_job]);
-        while (assigned < n_idle && q_head != q_tail) {
-          const int32_t s = uni((int32_t)L.fifo[q_head % NS]);
-          const int32_t nr = uni(L.nrays[s]);
-          const int32_t take = min(nr - head_issued, n_idle - assigned);
-          if (me_idle && rank >= assigned && rank < assigned + take) {
-            slot = s;
-            ridx = head_issued + (rank - assigned);
-            const BankInfo &B = L.bank[s >> 6];
-            R.ox = L.px[s];
-            R.oy = L.py[s];
-            R.oz = L.pz[s];
-            R.skip = L.skip[s];
-            R.tmin = kEps;
-            if (ridx < B.S) {
-              kind = kAO;
-              const int32_t q = s & 63;
-              const int32_t vw = B.vw;
-              const uint32_t pid = (uint32_t)((B.y0 + q / vw) * B.W + B.x0 + q % vw);
-              uint32_t b1, b2;
-              ao_uniform_bits(pid, (uint32_t)ridx, B.view, B.key0, B.key1, b1, b2);
-              ao_dir_f32(L.nx[s], L.ny[s], L.nz[s], b1, b2, R.dx, R.dy, R.dz);
-              R.tmax = B.maxd;
-            } else {
-              kind = kShadow;
-              uint32_t lv = L.lvalid[s];  // the (ridx - S)-th light with N.L > 0
-              for (int32_t n = ridx - B.S; n > 0; --n) lv &= lv - 1;
-              const int32_t l = __ffs(lv) - 1;
-              ridx = l;
-              R.dx = B.ldir[l][0];
-              R.dy = B.ldir[l][1];
-              R.dz = B.ldir[l][2];
-              R.tmax = INFINITY;
-            }
-            setup_ok = ray_setup(R, H);
-            done = !setup_ok;
-          }
-          head_issued += take;
-          assigned += take;
-          if (head_issued == nr) {
-            ++q_head;
-            head_issued = 0;
-          }
+      // pass 1 -- assignment only: secondary rays from the FIFO, then fresh
+      // primary rays; each idle lane learns (kind, slot, ray index)
+      while (assigned < n_idle && q_head != q_tail) {
+        const int32_t s = uni((int32_t)L.fifo[q_head % NS]);
+        const int32_t nr = uni(L.nrays[s]);
+        const int32_t S_s = uni(L.bank[s >> 6].S);
+        const int32_t take = min(nr - head_issued, n_idle - assigned);
+        if (me_idle && rank >= assigned && rank < assigned + take) {
+          slot = s;
+          ridx = head_issued + (rank - assigned);
+          kind = ridx < S_s ? kAO : kShadow;
+        }
+        head_issued += take;
+        assigned += take;
+        if (head_issued == nr) {
+          ++q_head;
+          head_issued = 0;
         }
       }
-      // primary rays
       while (assigned < n_idle) {
         if (issue_bank < 0 || issue_next == uni(L.bank[issue_bank].n)) {
           issue_bank = -1;
@@ -529,44 +505,75 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
           __syncthreads();
           bank_busy |= 1u << b;
           issue_bank = b;
-          issue_job = held_job;
           issue_next = 0;
           held_tile = -1;
         }
         const int32_t nvalid = uni(L.bank[issue_bank].n);
         const int32_t take = min(nvalid - issue_next, n_idle - assigned);
         if (me_idle && rank >= assigned && rank < assigned + take) {
-          const int32_t q = issue_next + (rank - assigned);
-          slot = issue_bank * 64 + q;
-          const JobDev *J = &A.jobs[issue_job];
-          const SceneHot H = load_hot(J);
-          const int32_t vw = L.bank[issue_bank].vw;
-          const int32_t pi = L.bank[issue_bank].x0 + q % vw;
-          const int32_t pj = L.bank[issue_bank].y0 + q / vw;
+          slot = issue_bank * 64 + issue_next + (rank - assigned);
           kind = kPrimary;
-          const float x = ((2.0f * ((float)pi + 0.5f)) / (float)J->W - 1.0f) * J->th32 * J->aspect32;
-          const float y = (1.0f - (2.0f * ((float)pj + 0.5f)) / (float)J->H) * J->th32;
-          const float vx = J->f32[0] + x * J->r32[0] + y * J->u32[0];
-          const float vy = J->f32[1] + x * J->r32[1] + y * J->u32[1];
-          const float vz = J->f32[2] + x * J->r32[2] + y * J->u32[2];
-          const float inv = __builtin_amdgcn_rsqf(vx * vx + vy * vy + vz * vz);
-          R.dx = vx * inv;
-          R.dy = vy * inv;
-          R.dz = vz * inv;
-          R.ox = J->eye32[0];
-          R.oy = J->eye32[1];
-          R.oz = J->eye32[2];
-          R.tmin = 0.0f;
-          R.tmax = INFINITY;
-          R.skip = -1;
-          setup_ok = ray_setup(R, H);
-          done = !setup_ok;
         }
         issue_next += take;
         assigned += take;
       }
+      // pass 2 -- build every newly assigned ray once
+      bool setup_ok = true;
+      if (assigned > 0) {
+        const bool fresh = me_idle && kind != kIdle;
+        if (fresh) {
+          const SceneHot H = load_hot(&A.jobs[scene_job]);
+          const BankInfo &B = L.bank[slot >> 6];
+          const int32_t q = slot & 63;
+          const int32_t vw = B.vw;
+          const int32_t pi = B.x0 + q % vw;
+          const int32_t pj = B.y0 + q / vw;
+          if (kind == kPrimary) {
+            const JobDev *J = &A.jobs[B.job];
+            const float x = ((2.0f * ((float)pi + 0.5f)) / (float)J->W - 1.0f) * J->th32 * J->aspect32;
+            const float y = (1.0f - (2.0f * ((float)pj + 0.5f)) / (float)J->H) * J->th32;
+            const float vx = J->f32[0] + x * J->r32[0] + y * J->u32[0];
+            const float vy = J->f32[1] + x * J->r32[1] + y * J->u32[1];
+            const float vz = J->f32[2] + x * J->r32[2] + y * J->u32[2];
+            const float inv = __builtin_amdgcn_rsqf(vx * vx + vy * vy + vz * vz);
+            R.dx = vx * inv;
+            R.dy = vy * inv;
+            R.dz = vz * inv;
+            R.ox = J->eye32[0];
+            R.oy = J->eye32[1];
+            R.oz = J->eye32[2];
+            R.tmin = 0.0f;
+            R.tmax = INFINITY;
+            R.skip = -1;
+          } else {
+            R.ox = L.px[slot];
+            R.oy = L.py[slot];
+            R.oz = L.pz[slot];
+            R.skip = L.skip[slot];
+            R.tmin = kEps;
+            if (kind == kAO) {
+              uint32_t b1, b2;
+              ao_uniform_bits((uint32_t)(pj * B.W + pi), (uint32_t)ridx, B.view, B.key0, B.key1, b1, b2);
+              ao_dir_f32(L.nx[slot], L.ny[slot], L.nz[slot], b1, b2, R.dx, R.dy, R.dz);
+              R.tmax = B.maxd;
+            } else {
+              uint32_t lv = L.lvalid[slot];  // the (ridx - S)-th light with N.L > 0
+              for (int32_t n = ridx - B.S; n > 0; --n) lv &= lv - 1;
+              const int32_t l = __ffs(lv) - 1;
+              ridx = l;
+              R.dx = B.ldir[l][0];
+              R.dy = B.ldir[l][1];
+              R.dz = B.ldir[l][2];
+              R.tmax = INFINITY;
+            }
+          }
+          setup_ok = ray_setup(R, H);
+          done = setup_ok ? 0 : 1;
+        }
+      }
       c_rays += (uint64_t)assigned;
-      if (COUNT) c_cells += __popcll(__ballot(me_idle && kind != kIdle && setup_ok));
+      if (COUNT) ++c_refills;
+      if (COUNT) l_cells += (me_idle && kind != kIdle && setup_ok) ? 1u : 0u;
     }
 
     // ================================================================ exit
@@ -593,118 +600,163 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
       const int32_t thresh = can_refill ? A.refill_below : 1;
       const bool anyhit = kind != kPrimary;
       for (int32_t it = 0;; ++it) {
-        const bool work = kind != kIdle && !done && !paused;
+        const bool work = kind != kIdle && (done | paused) == 0;
         const int32_t nwork = __popcll(__ballot(work));
         if (nwork == 0) break;
         if (it >= kMinIters) {
           if (nwork < thresh) break;
-          if (RESOLVE && nwork < A.refill_below && __ballot(paused)) break;
+          if (RESOLVE && nwork < A.refill_below && __ballot(paused != 0)) break;
         }
-        if (work) {
-          if (R.rc < R.re) {
-            // ---- test one primitive reference
-            const int32_t k = (int32_t)H.refs[R.rc];
-            ++R.rc;
-            if (k != R.skip) {
-              float t;
-              bool hit, graze;
-              if (k < H.n_s) {
-                if (COUNT) c_st += __popcll(__ballot(true));
-                const float4 s = H.sph32[k];
-                const float qx = s.x - R.ox, qy = s.y - R.oy, qz = s.z - R.oz;
-                const float b = qx * R.dx + qy * R.dy + qz * R.dz;
-                const float lx = qx - b * R.dx, ly = qy - b * R.dy, lz = qz - b * R.dz;
-                const float ll = lx * lx + ly * ly + lz * lz;
-                const float rr = s.w * s.w;
-                const float disc = rr - ll;
-                graze = RESOLVE && fabsf(disc) <= kKappa * (rr + ll);
-                const float sq = sqrtf_fast(fmaxf(disc, 0.0f));
-                const float t0 = b - sq, t1 = b + sq;
-                const bool ok = disc >= 0.0f && !graze;
-                const bool h0 = ok && t0 > R.tmin && t0 <= R.tmax;
-                const bool h1 = ok && t1 > R.tmin && t1 <= R.tmax;
-                hit = h0 || h1;
-                t = h0 ? t0 : t1;
-                if (COUNT) c_sh += __popcll(__ballot(hit));
-              } else {
-                if (COUNT) c_ct += __popcll(__ballot(true));
-                hit = false;
-                graze = false;
-                t = 0.0f;
-                const float4 a = H.cylA32[k - H.n_s];
-                const float4 w = H.cylW32[k - H.n_s];
-                const float Dx = R.ox - a.x, Dy = R.oy - a.y, Dz = R.oz - a.z;
-                const float dw = R.dx * w.x + R.dy * w.y + R.dz * w.z;
-                const float Dw = Dx * w.x + Dy * w.y + Dz * w.z;
-                const float dpx = R.dx - dw * w.x, dpy = R.dy - dw * w.y, dpz = R.dz - dw * w.z;
-                const float Dpx = Dx - Dw * w.x, Dpy = Dy - Dw * w.y, Dpz = Dz - Dw * w.z;
-                const float Aq = dpx * dpx + dpy * dpy + dpz * dpz;
-                const float Bq = dpx * Dpx + dpy * Dpy + dpz * Dpz;
-                const float Cq = (Dpx * Dpx + Dpy * Dpy + Dpz * Dpz) - a.w * a.w;
-                const float disc = Bq * Bq - Aq * Cq;
-                if (Aq > 1e-12f) {
-                  graze = RESOLVE && fabsf(disc) <= kKappa * (Bq * Bq + fabsf(Aq * Cq));
-                  if (!graze && disc >= 0.0f) {
-                    const float sq = sqrtf_fast(disc);
-                    const float qq = -(Bq + __builtin_copysignf(sq, Bq));
-                    if (qq != 0.0f) {
-                      const float r0 = qq * rcpf(Aq), r1 = Cq * rcpf(qq);
-                      const float tl = fminf(r0, r1), th = fmaxf(r0, r1);
-                      const float kL = kKappa * w.w;
-                      const float sl = Dw + tl * dw, sh = Dw + th * dw;
-                      const bool inl = tl > R.tmin && tl <= R.tmax;
-                      const bool inh = th > R.tmin && th <= R.tmax;
-                      const bool gl = RESOLVE && inl && (fabsf(sl) <= kL || fabsf(sl - w.w) <= kL);
-                      const bool gh = RESOLVE && inh && (fabsf(sh) <= kL || fabsf(sh - w.w) <= kL);
-                      const bool hl = inl && !gl && sl >= 0.0f && sl <= w.w;
-                      const bool hh = inh && !gh && sh >= 0.0f && sh <= w.w;
-                      // the near root decides first; an undecidable root defers to FP64
-                      graze = gl || (!hl && gh);
-                      hit = !graze && (hl || hh);
-                      t = hl ? tl : th;
-                    }
-                  }
-                }
-                if (COUNT) c_ch += __popcll(__ballot(hit));
-              }
-              if (RESOLVE && graze) {
-                if (COUNT) c_res += __popcll(__ballot(true));
-                paused = true;
-                gk = k;
-              } else if (hit) {
-                if (anyhit) {
-                  R.bk = k;
-                  R.bt = t;
-                  done = true;
-                } else if (t < R.bt || (t == R.bt && k < R.bk)) {
-                  R.bt = t;
-                  R.bk = k;
-                }
-              }
-            }
-          } else {
-            // ---- cell exhausted: stop, or step to the next cell
-            const float tn = fminf(R.tnx, fminf(R.tny, R.tnz));
-            if ((R.bk >= 0 && R.bt <= fminf(tn, R.t1)) || !(tn < R.t1)) {
-              done = true;
+        if (COUNT) {
+          ++c_iters;
+          c_lanes += (uint64_t)nwork;
+        }
+        // The next reference id is already loaded (R.nk, -1 = cell done), so
+        // each lane knows its unit of work before touching memory.  Cylinder
+        // tests, the long path, run only when enough lanes want one; the
+        // other lanes keep stepping and testing spheres meanwhile.
+        const int32_t nk = R.nk;
+        bool is_sph = work && nk >= 0 && nk < H.n_s;
+        bool is_cyl = work && nk >= H.n_s;
+        bool is_step = work && nk < 0;
+        // Work-type scheduling: a unit type runs this iteration only if enough
+        // lanes want it -- at least `mix`/64 of the largest group (cylinders
+        // also need busy/cyl_wait lanes) -- so the wave does not pay for every
+        // code path each iteration; the other lanes wait.
+        const int32_t n_sph = __popcll(__ballot(is_sph));
+        const int32_t n_cyl = __popcll(__ballot(is_cyl));
+        const int32_t n_step = nwork - n_sph - n_cyl;
+        const int32_t n_max = max(n_step, max(n_sph, n_cyl));
+        const int32_t bar = (n_max * A.mix + 63) >> 6;
+        const bool run_cyl = n_cyl > 0 && n_cyl >= bar && n_cyl * A.cyl_wait >= nwork;
+        is_sph = is_sph && n_sph >= bar;
+        is_step = is_step && n_step >= bar;
+        is_cyl = is_cyl && (run_cyl || (n_sph < bar && n_step < bar));
+        bool tested = false, hit = false, graze = false;
+        float t = 0.0f;
+        if (is_sph) {
+          tested = true;
+          const vf4 s = H.sph32[nk];
+          const float qx = s.x - R.ox, qy = s.y - R.oy, qz = s.z - R.oz;
+          const float b = qx * R.dx + qy * R.dy + qz * R.dz;
+          const float lx = qx - b * R.dx, ly = qy - b * R.dy, lz = qz - b * R.dz;
+          const float ll = lx * lx + ly * ly + lz * lz;
+          const float rr = s.w * s.w;
+          const float disc = rr - ll;
+          graze = RESOLVE && fabsf(disc) <= kKappa * (rr + ll);
+          const float sq = sqrtf_fast(fmaxf(disc, 0.0f));
+          const float t0 = b - sq, t1 = b + sq;
+          const bool ok = disc >= 0.0f && !graze;
+          const bool h0 = ok && t0 > R.tmin && t0 <= R.tmax;
+          const bool h1 = ok && t1 > R.tmin && t1 <= R.tmax;
+          hit = h0 || h1;
+          t = h0 ? t0 : t1;
+        }
+        if (is_cyl) {
+          tested = true;
+          const vf4 a = H.cylA32[nk - H.n_s];
+          const vf4 w = H.cylW32[nk - H.n_s];
+          const float Dx = R.ox - a.x, Dy = R.oy - a.y, Dz = R.oz - a.z;
+          const float dw = R.dx * w.x + R.dy * w.y + R.dz * w.z;
+          const float Dw = Dx * w.x + Dy * w.y + Dz * w.z;
+          const float dpx = R.dx - dw * w.x, dpy = R.dy - dw * w.y, dpz = R.dz - dw * w.z;
+          const float Dpx = Dx - Dw * w.x, Dpy = Dy - Dw * w.y, Dpz = Dz - Dw * w.z;
+          const float Aq = dpx * dpx + dpy * dpy + dpz * dpz;
+          const float Bq = dpx * Dpx + dpy * Dpy + dpz * Dpz;
+          const float Cq = (Dpx * Dpx + Dpy * Dpy + Dpz * Dpz) - a.w * a.w;
+          const float disc = Bq * Bq - Aq * Cq;
+          const bool nonpar = Aq > 1e-12f;
+          const bool g0 = RESOLVE && nonpar && fabsf(disc) <= kKappa * (Bq * Bq + fabsf(Aq * Cq));
+          const float sq = sqrtf_fast(fmaxf(disc, 0.0f));
+          const float qq = -(Bq + __builtin_copysignf(sq, Bq));
+          const bool ok = nonpar && !g0 && disc >= 0.0f && qq != 0.0f;
+          const float r0 = qq * rcpf(Aq), r1 = Cq * rcpf(qq);
+          const float tl = fminf(r0, r1), th = fmaxf(r0, r1);
+          const float kL = kKappa * w.w;
+          const float sl = Dw + tl * dw, sh = Dw + th * dw;
+          const bool inl = ok && tl > R.tmin && tl <= R.tmax;
+          const bool inh = ok && th > R.tmin && th <= R.tmax;
+          const bool gl = RESOLVE && inl && (fabsf(sl) <= kL || fabsf(sl - w.w) <= kL);
+          const bool gh = RESOLVE && inh && (fabsf(sh) <= kL || fabsf(sh - w.w) <= kL);
+          const bool hl = inl && !gl && sl >= 0.0f && sl <= w.w;
+          const bool hh = inh && !gh && sh >= 0.0f && sh <= w.w;
+          // the near root decides first; an undecidable root defers to FP64
+          graze = g0 || gl || (!hl && gh);
+          hit = !graze && (hl || hh);
+          t = hl ? tl : th;
+        }
+        if (tested) {
+          const bool live = nk != R.skip;
+          hit = hit && live;
+          graze = graze && live;
+          if (COUNT && live) {
+            if (nk < H.n_s) {
+              ++l_st;
+              l_sh += hit;
             } else {
-              const bool ax = R.tnx == tn;
-              const bool ay = !ax && R.tny == tn;
-              const bool az = !ax && !ay;
-              R.cx += ax ? R.sx : 0;
-              R.cy += ay ? R.sy : 0;
-              R.cz += az ? R.sz : 0;
-              const int32_t st = ax ? R.sx : (ay ? R.sy : R.sz);
-              R.tnx = ax ? fmaf((float)(R.cx + (R.sx > 0)), R.hx, R.bx) : R.tnx;
-              R.tny = ay ? fmaf((float)(R.cy + (R.sy > 0)), R.hy, R.by) : R.tny;
-              R.tnz = az ? fmaf((float)(R.cz + (R.sz > 0)), R.hz, R.bz) : R.tnz;
-              if (st == 0 || (uint32_t)R.cx >= (uint32_t)H.res[0] ||
-                  (uint32_t)R.cy >= (uint32_t)H.res[1] || (uint32_t)R.cz >= (uint32_t)H.res[2]) {
-                done = true;
-              } else {
-                if (COUNT) c_cells += __popcll(__ballot(true));
-                load_cell(R, H);
-              }
+              ++l_ct;
+              l_ch += hit;
+            }
+            l_res += graze;
+          }
+          ++R.rc;
+          const int32_t v = (int32_t)H.refs[R.rc];  // refs has one padding entry
+          R.nk = R.rc < R.re ? v : -1;
+          if (RESOLVE && graze) {
+            paused = 1;
+            gk = nk;
+          } else if (hit) {
+            if (anyhit) {
+              R.bk = nk;
+              R.bt = t;
+              done = 1;
+            } else if (t < R.bt || (t == R.bt && nk < R.bk)) {
+              R.bt = t;
+              R.bk = nk;
+            }
+          }
+        }
+        if (is_step) {
+          // ---- cell exhausted: stop, or leave it.  An empty cell carries the
+          // Chebyshev distance k to the nearest occupied cell, so the whole
+          // cube of half-size k-1 around it is empty and the walk jumps to
+          // where the ray leaves that cube (k = 1: an ordinary DDA step).
+          const int32_t kk = R.re == 0 ? (int32_t)R.rc : 1;
+          const int32_t pxi = R.sx > 0 ? R.cx + kk : R.cx - kk + 1;
+          const int32_t pyi = R.sy > 0 ? R.cy + kk : R.cy - kk + 1;
+          const int32_t pzi = R.sz > 0 ? R.cz + kk : R.cz - kk + 1;
+          const float tx = R.sx ? fmaf((float)pxi, R.hx, R.bx) : INFINITY;
+          const float ty = R.sy ? fmaf((float)pyi, R.hy, R.by) : INFINITY;
+          const float tz = R.sz ? fmaf((float)pzi, R.hz, R.bz) : INFINITY;
+          const float tn = fminf(tx, fminf(ty, tz));
+          if ((R.bk >= 0 && R.bt <= fminf(tn, R.t1)) || !(tn < R.t1)) {
+            done = 1;
+          } else {
+            const bool ax = tx == tn;
+            const bool ay = !ax && ty == tn;
+            const bool az = !ax && !ay;
+            int32_t nx = R.cx, ny = R.cy, nz = R.cz;
+            if (kk > 1) {
+              // the other axes land where the ray meets the exit face, inside the cube
+              const int32_t m = kk - 1;
+              const int32_t fx = (int32_t)floorf((fmaf(tn, R.dx, R.ox) - H.lo32[0]) * H.inv32[0]);
+              const int32_t fy = (int32_t)floorf((fmaf(tn, R.dy, R.oy) - H.lo32[1]) * H.inv32[1]);
+              const int32_t fz = (int32_t)floorf((fmaf(tn, R.dz, R.oz) - H.lo32[2]) * H.inv32[2]);
+              nx = min(max(fx, R.cx - m), R.cx + m);
+              ny = min(max(fy, R.cy - m), R.cy + m);
+              nz = min(max(fz, R.cz - m), R.cz + m);
+              if (COUNT) ++l_jumps;
+            }
+            R.cx = ax ? R.cx + R.sx * kk : nx;
+            R.cy = ay ? R.cy + R.sy * kk : ny;
+            R.cz = az ? R.cz + R.sz * kk : nz;
+            const int32_t st = ax ? R.sx : (ay ? R.sy : R.sz);
+            if (st == 0 || (uint32_t)R.cx >= (uint32_t)H.res[0] ||
+                (uint32_t)R.cy >= (uint32_t)H.res[1] || (uint32_t)R.cz >= (uint32_t)H.res[2]) {
+              done = 1;
+            } else {
+              if (COUNT) ++l_cells;
+              load_cell(R, H);
             }
           }
         }
@@ -719,6 +771,15 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
     atomicAdd(&L.cnt[1], l_hit);
     atomicAdd(&L.cnt[2], l_ao);
     atomicAdd(&L.cnt[3], l_shadow);
+    if (COUNT) {
+      atomicAdd(&L.cnt[4], l_cells);
+      atomicAdd(&L.cnt[5], l_st);
+      atomicAdd(&L.cnt[6], l_sh);
+      atomicAdd(&L.cnt[7], l_ct);
+      atomicAdd(&L.cnt[8], l_ch);
+      atomicAdd(&L.cnt[9], l_res);
+      atomicAdd(&L.cnt[10], l_jumps);
+    }
     __syncthreads();
     if (lane == 0) {
       unsigned long long *st = (unsigned long long *)A.stats;
@@ -728,12 +789,16 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
       atomicAdd(&st[TR_STAT_SHADOW_RAYS], (unsigned long long)L.cnt[3]);
       atomicAdd(&st[TR_STAT_RAYS_TRACED], (unsigned long long)c_rays);
       if (COUNT) {
-        atomicAdd(&st[TR_STAT_CELLS], (unsigned long long)c_cells);
-        atomicAdd(&st[TR_STAT_SPH_TESTS], (unsigned long long)c_st);
-        atomicAdd(&st[TR_STAT_SPH_HITS], (unsigned long long)c_sh);
-        atomicAdd(&st[TR_STAT_CYL_TESTS], (unsigned long long)c_ct);
-        atomicAdd(&st[TR_STAT_CYL_HITS], (unsigned long long)c_ch);
-        atomicAdd(&st[TR_STAT_RESOLVES], (unsigned long long)c_res);
+        atomicAdd(&st[TR_STAT_CELLS], (unsigned long long)L.cnt[4]);
+        atomicAdd(&st[TR_STAT_SPH_TESTS], (unsigned long long)L.cnt[5]);
+        atomicAdd(&st[TR_STAT_SPH_HITS], (unsigned long long)L.cnt[6]);
+        atomicAdd(&st[TR_STAT_CYL_TESTS], (unsigned long long)L.cnt[7]);
+        atomicAdd(&st[TR_STAT_CYL_HITS], (unsigned long long)L.cnt[8]);
+        atomicAdd(&st[TR_STAT_RESOLVES], (unsigned long long)L.cnt[9]);
+        atomicAdd(&st[TR_STAT_WAVE_ITERS], (unsigned long long)c_iters);
+        atomicAdd(&st[TR_STAT_LANE_ITERS], (unsigned long long)c_lanes);
+        atomicAdd(&st[TR_STAT_REFILLS], (unsigned long long)c_refills);
+        atomicAdd(&st[TR_STAT_JUMPS], (unsigned long long)L.cnt[10]);
       }
     }
   }
@@ -775,6 +840,8 @@ static hipError_t launch_t(const WaveLaunch &L, hipStream_t st) {
   a.stats = L.stats;
   a.tile_w = L.tile_w;
   a.refill_below = L.refill_below;
+  a.cyl_wait = L.cyl_wait;
+  a.mix = L.mix;
   k_render_wave<BANKS, RES, CNT><<<L.n_waves, 64, 0, st>>>(a);
   return hipGetLastError();
 }

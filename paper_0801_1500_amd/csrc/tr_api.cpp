@@ -56,11 +56,13 @@ struct tr_scene {
   int32_t n_lights = 0;
   double ldir[8][3] = {};
   double lrgb[8][3] = {};
-  double lambda = 4.0;
+  double lambda = 16.0;
   // device arrays
   double4 *sph64 = nullptr, *cylA64 = nullptr, *cylW64 = nullptr, *cylB64 = nullptr;
   float4 *sph32 = nullptr, *cylA32 = nullptr, *cylW32 = nullptr, *albedo = nullptr;
   uint32_t *cell_begin = nullptr, *refs = nullptr, *count = nullptr, *scan_scratch = nullptr;
+  uint2 *cellinfo = nullptr;
+  uint8_t *dist0 = nullptr, *dist1 = nullptr;
   double *bounds_scratch = nullptr, *bounds = nullptr;
   int64_t cap_cells = 0, cap_refs = 0, cap_scan = 0;
   size_t bytes_arrays = 0;
@@ -78,7 +80,7 @@ static std::mutex g_mu;
 static void free_scene_arrays(tr_scene *s) {
   void *ptrs[] = {s->sph64, s->cylA64, s->cylW64, s->cylB64, s->sph32,       s->cylA32,
                   s->cylW32, s->albedo, s->cell_begin, s->refs, s->count, s->scan_scratch,
-                  s->bounds_scratch, s->bounds};
+                  s->bounds_scratch, s->bounds, s->cellinfo, s->dist0, s->dist1};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_bounds) (void)hipHostFree(s->h_bounds);
@@ -137,6 +139,7 @@ static void fill_scene_dev(tr_scene *s) {
   d.albedo = s->albedo;
   d.cell_begin = s->cell_begin;
   d.refs = s->refs;
+  d.cellinfo = s->cellinfo;
   for (int a = 0; a < 3; ++a) {
     d.lo[a] = s->gp.lo[a];
     d.hi[a] = s->gp.hi[a];
@@ -178,9 +181,17 @@ static tr_status build_grid(tr_scene *s, hipStream_t st) {
   if (nc + 1 > s->cap_cells) {
     if (s->cell_begin) (void)hipFree(s->cell_begin);
     if (s->count) (void)hipFree(s->count);
+    if (s->cellinfo) (void)hipFree(s->cellinfo);
+    if (s->dist0) (void)hipFree(s->dist0);
+    if (s->dist1) (void)hipFree(s->dist1);
     s->cell_begin = s->count = nullptr;
+    s->cellinfo = nullptr;
+    s->dist0 = s->dist1 = nullptr;
     HIP_TRY(dmalloc(&s->cell_begin, nc + 1));
     HIP_TRY(dmalloc(&s->count, nc + 1));
+    HIP_TRY(dmalloc(&s->cellinfo, nc + 1));
+    HIP_TRY(dmalloc(&s->dist0, nc + 1));
+    HIP_TRY(dmalloc(&s->dist1, nc + 1));
     s->cap_cells = nc + 1;
   }
   const int64_t need_scan = trh::scan_scratch_u32(nc + 1);
@@ -209,16 +220,21 @@ static tr_status build_grid(tr_scene *s, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(s->h_total, s->cell_begin + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const int64_t R = (int64_t)*s->h_total;
-  if (R > s->cap_refs) {
+  // padding: the FP32 walk reads refs[x] for x <= n_refs (end of a cell) and
+  // for x <= 32 (the distance word of an empty cell) before checking
+  const int64_t R_pad = R + 64;
+  if (R_pad > s->cap_refs) {
     if (s->refs) (void)hipFree(s->refs);
     s->refs = nullptr;
-    HIP_TRY(dmalloc(&s->refs, R));
-    s->cap_refs = R > 0 ? R : 1;
+    HIP_TRY(dmalloc(&s->refs, R_pad));
+    s->cap_refs = R_pad;
   }
+  HIP_TRY(trh::launch_fill_u32(s->refs + R, 64, 0u, st));
   s->n_refs = R;
   HIP_TRY(trh::launch_fill_u32(s->count, nc, 0u, st));
   HIP_TRY(trh::launch_scatter(a, s->cell_begin, s->count, s->refs, st));
   HIP_TRY(trh::launch_sort_cells(s->cell_begin, nc, s->refs, st));
+  HIP_TRY(trh::launch_cellinfo(s->cell_begin, s->gp.res, s->dist0, s->dist1, s->cellinfo, st));
   fill_scene_dev(s);
   return TR_OK;
 }
@@ -264,7 +280,7 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   s->n_s = d->n_spheres;
   s->n_c = d->n_cylinders;
   s->n_lights = d->n_lights;
-  s->lambda = d->cells_per_prim > 0.0 ? d->cells_per_prim : 4.0;
+  s->lambda = d->cells_per_prim > 0.0 ? d->cells_per_prim : 16.0;
   for (int l = 0; l < d->n_lights; ++l) {
     const double *v = d->light_dir + 3 * l;
     const double n = std::sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
@@ -354,7 +370,7 @@ extern "C" tr_status tr_scene_rebuild(tr_scene *s, double cells_per_prim, void *
 
 extern "C" tr_status tr_scene_footprint(const tr_scene *s, size_t *bytes) {
   if (!s || !bytes) return fail(TR_EINVAL, "tr_scene_footprint: NULL argument");
-  *bytes = s->bytes_arrays + (size_t)s->cap_cells * 8 + (size_t)s->cap_refs * 4 +
+  *bytes = s->bytes_arrays + (size_t)s->cap_cells * 18 + (size_t)s->cap_refs * 4 +
            (size_t)s->cap_scan * 4;
   return TR_OK;
 }
@@ -398,8 +414,10 @@ static tr_status default_tune(tr_tune *t) {
   t->tile_w = 8;
   t->banks = 2;
   t->waves_per_cu = 20;
-  t->refill_below = 40;
+  t->refill_below = 32;
   t->count_ops = 0;
+  t->cyl_wait = 64;
+  t->mix = 16;
   return TR_OK;
 }
 
@@ -408,6 +426,8 @@ static tr_status check_tune(const tr_tune &t) {
   if (t.banks != 2 && t.banks != 3) return fail(TR_EINVAL, "tune.banks must be 2 or 3");
   if (t.waves_per_cu < 1 || t.waves_per_cu > 32) return fail(TR_EINVAL, "tune.waves_per_cu must be 1..32");
   if (t.refill_below < 1 || t.refill_below > 64) return fail(TR_EINVAL, "tune.refill_below must be 1..64");
+  if (t.cyl_wait < 1 || t.cyl_wait > 64) return fail(TR_EINVAL, "tune.cyl_wait must be 1..64");
+  if (t.mix < 1 || t.mix > 64) return fail(TR_EINVAL, "tune.mix must be 1..64");
   return TR_OK;
 }
 
@@ -596,6 +616,8 @@ static tr_tune pick_tune(const tr_scene *s, const tr_camera *c, const tr_params 
     if (!t.banks) t.banks = d.banks;
     if (!t.waves_per_cu) t.waves_per_cu = d.waves_per_cu;
     if (!t.refill_below) t.refill_below = d.refill_below;
+    if (!t.cyl_wait) t.cyl_wait = d.cyl_wait;
+    if (!t.mix) t.mix = d.mix;
     return t;
   }
   if (s && c && p) {
@@ -632,6 +654,8 @@ static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, u
   L.banks = t.banks;
   L.refill_below = t.refill_below;
   L.count_ops = t.count_ops;
+  L.cyl_wait = t.cyl_wait;
+  L.mix = t.mix;
   int64_t waves = (int64_t)num_cus() * t.waves_per_cu;
   if (waves > total) waves = total;
   L.n_waves = (int32_t)waves;
@@ -846,6 +870,8 @@ extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, c
     L.banks = g->tune.banks;
     L.refill_below = g->tune.refill_below;
     L.count_ops = g->tune.count_ops;
+    L.cyl_wait = g->tune.cyl_wait;
+    L.mix = g->tune.mix;
     int64_t waves = (int64_t)num_cus() * g->tune.waves_per_cu;
     if (waves > total) waves = total;
     L.n_waves = (int32_t)std::max<int64_t>(waves, 1);
@@ -973,12 +999,17 @@ extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr
   }
   // coordinate descent over the launch-shape axes
   const std::vector<std::vector<int32_t>> axes = {
-      {4, 8, 16, 32}, {2, 3}, {8, 12, 16, 20, 24, 32}, {16, 24, 32, 40, 48, 56}};
+      {4, 8, 16, 32}, {2, 3}, {8, 12, 16, 20, 24, 32}, {16, 24, 32, 40, 48, 56}, {2, 8, 64}, {1, 16, 32, 48, 64}};
   for (int pass = 0; pass < 2; ++pass) {
     for (size_t ax = 0; ax < axes.size(); ++ax) {
       for (int32_t v : axes[ax]) {
         tr_tune t = cur;
-        int32_t *field = ax == 0 ? &t.tile_w : ax == 1 ? &t.banks : ax == 2 ? &t.waves_per_cu : &t.refill_below;
+        int32_t *field = ax == 0   ? &t.tile_w
+                         : ax == 1 ? &t.banks
+                         : ax == 2 ? &t.waves_per_cu
+                         : ax == 3 ? &t.refill_below
+                         : ax == 4 ? &t.cyl_wait
+                                   : &t.mix;
         if (*field == v) continue;
         *field = v;
         double ms = 0;
@@ -995,8 +1026,8 @@ extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr
         if (std::memcmp(h_a.data(), h_b.data(), px * 12) != 0 ||
             std::memcmp(i_a.data(), i_b.data(), px * 4) != 0) {
           cleanup();
-          return fail(TR_EDEVICE, "autotune: launch shape (%d,%d,%d,%d) changed the frame", t.tile_w,
-                      t.banks, t.waves_per_cu, t.refill_below);
+          return fail(TR_EDEVICE, "autotune: launch shape (%d,%d,%d,%d,%d,%d) changed the frame",
+                      t.tile_w, t.banks, t.waves_per_cu, t.refill_below, t.cyl_wait, t.mix);
         }
         if (ms < cur_ms) {
           cur_ms = ms;

@@ -8,7 +8,9 @@
 //   sph32  float4[n_s]   rounded copies for the FP32 traversal: one 16-byte load per sphere
 //   cylA32 float4[n_c], cylW32 float4[n_c]         two 16-byte loads per cylinder
 //   albedo float4[N]     (r, g, b, 0) by global id
-//   cell_begin uint32[n_cells + 1], refs uint32[n_refs]   the uniform grid
+//   cell_begin uint32[n_cells + 1], refs uint32[n_refs + 64]   the uniform grid
+//   cellinfo uint2[n_cells]  (begin, end), or (distance to the nearest occupied
+//                            cell, 0) for empty cells: the FP32 walk's view
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -22,6 +24,7 @@ struct SceneDev {
   const float4 *sph32, *cylA32, *cylW32;
   const float4 *albedo;
   const uint32_t *cell_begin, *refs;
+  const uint2 *cellinfo;  // (begin, end) or (empty-space distance, 0) per cell
   double lo[3], hi[3], h[3], inv[3];
   float lo32[3], hi32[3], h32[3], inv32[3];
   int32_t res[3];

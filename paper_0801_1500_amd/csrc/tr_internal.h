@@ -44,6 +44,9 @@ int64_t scan_scratch_u32(int64_t n);
 hipError_t launch_scan(uint32_t *data, int64_t n_plus_1, uint32_t *scratch, hipStream_t st);
 hipError_t launch_scatter(const BuildArgs &a, const uint32_t *cell_begin, uint32_t *cursor,
                           uint32_t *refs, hipStream_t st);
+// empty-space distance field + per-cell traversal words (d0, d1: n_cells bytes each)
+hipError_t launch_cellinfo(const uint32_t *cell_begin, const int32_t res[3], uint8_t *d0, uint8_t *d1,
+                           uint2 *info, hipStream_t st);
 hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32_t *refs,
                              hipStream_t st);
 
@@ -56,7 +59,7 @@ struct WaveLaunch {
   int64_t n_tiles;           // total tiles in the queue
   uint32_t *tile_counter;    // device, zeroed before the launch
   uint64_t *stats;           // device or null
-  int32_t tile_w, banks, refill_below, count_ops;
+  int32_t tile_w, banks, refill_below, count_ops, cyl_wait, mix;
   int32_t n_waves;           // persistent waves launched
   int32_t resolve;
 };
