@@ -79,6 +79,59 @@ def cpu_baseline(scene, cam, params, target_s: float = 15.0) -> dict:
             "seconds": dt, "rays": rays, "shadow_rays": cnt["shadow_rays"]}
 
 
+def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
+    """64 views of the 1,000,000-object walk scene at 1920x1080, 32 AO
+    samples, captured once into a hipGraph; time graph launches."""
+    scene = scenegen.orbit_scene()
+    gs = tr.Scene(scene)
+    cams = scenegen.orbit_cameras()
+    params = scenegen.orbit_params()
+    frames = [tr.alloc_frame(c, ("rgb",), stats=False) for c in cams]
+    stats = torch.zeros(tr.STAT_COUNT, dtype=torch.int64, device="cuda")
+    for f in frames:
+        f["stats"] = stats
+    g = tr.Graph([gs] * len(cams), cams, params, frames)
+    g.launch()
+    torch.cuda.synchronize()
+    stats.zero_()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(launches):
+        g.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / launches
+    st = dict(zip(tr.STAT_NAMES, stats.cpu().tolist()))
+    rays = (st["pixels"] + st["ao_rays"]) / launches
+    g.destroy()
+    return {"workload": "1,000,000-object walk (ball radius 250), 64 views of 1920x1080 per "
+                        "graph launch, 32 AO samples, FP32 + FP64 re-solve",
+            "ms_per_launch": ms, "views_per_s": 64 * 1000.0 / ms, "rays_per_launch": rays,
+            "rays_per_s": rays / (ms * 1e-3)}
+
+
+def serving_measure(tr, torch, scenegen, seconds: float, rate: float = 50.0) -> dict:
+    """Poisson arrivals (mean `rate` per second) of render jobs over a pool
+    of 16 resident walk scenes of 2k-200k objects, resolutions uniform over
+    {256x256, 965x1137, 1920x1080}, 4-32 AO samples, 64 GB frame budget."""
+    from paper_0801_1500_amd.serve import Job, Server
+    pool = scenegen.serving_pool()
+    gpool = [tr.Scene(s) for s in pool]
+    radii = [scenegen.serving_radius(s.n_prims) for s in pool]
+    n_jobs = int(round(seconds * rate))
+    reqs = scenegen.serving_requests(radii, n_jobs, rate_hz=rate, seed=3)
+    jobs = [Job(i, t, si, cam, p) for i, (t, si, cam, p) in enumerate(reqs)]
+    srv = Server(gpool, hbm_budget=64 << 30)
+    # warm-up on a few jobs, then the timed stream
+    srv.run([Job(-1 - i, 0.0, j.scene, j.camera, j.params) for i, j in enumerate(jobs[:8])],
+            realtime=False)
+    st = srv.run(jobs, realtime=True)
+    out = st.summary()
+    out["workload"] = ("Poisson %.0f req/s, %d jobs, 16 resident scenes of 2k-200k objects, "
+                       "256x256 / 965x1137 / 1920x1080, 4-32 AO samples" % (rate, n_jobs))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +140,9 @@ def main():
     ap.add_argument("--fp64-frames", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape first")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the Poisson serving run (0 = skip)")
+    ap.add_argument("--no-orbit", action="store_true", help="skip the 1M-object orbit run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -185,6 +241,17 @@ def main():
         del f64
         log("fp64 plain path", fp64)
 
+    orbit = None
+    if not args.no_orbit:
+        log("orbit (1M objects, 64 views per graph launch) ...")
+        orbit = orbit_measure(tr, torch, scenegen)
+        log("orbit", orbit)
+    serving = None
+    if args.serve_seconds > 0:
+        log("serving stream ...")
+        serving = serving_measure(tr, torch, scenegen, args.serve_seconds)
+        log("serving", serving)
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -209,6 +276,8 @@ def main():
         "hit_pixels": st["hit_pixels"], "op_counts": st,
         "render_only_rays_per_s": rays_frame / (render_ms.mean() * 1e-3),
         "fp64_plain": fp64,
+        "orbit": orbit,
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_context": "Tachyon on 6144 Blue Gene/L processors: 2.6416 s per 17.6 MP AO frame "

@@ -1,0 +1,40 @@
+"""Host-side serving policies (no GPU): admission by slots and HBM
+footprint in arrival order, and oldest-first tile budgeting."""
+import scenegen
+from paper_0801_1500_amd.serve import Job, admit, plan_step
+
+
+def _job(i, arrival, fp, n_tiles=10):
+    cam = scenegen.Camera((0, 0, 10.0), (0, 0, 0), (0, 1, 0), 50.0, 8, 8)
+    j = Job(i, arrival, 0, cam, scenegen.Params())
+    j.footprint = fp
+    j.n_tiles = n_tiles
+    return j
+
+
+def test_admit_respects_arrival_slots_and_memory():
+    q = [_job(0, 0.0, 40), _job(1, 0.1, 40), _job(2, 0.2, 40), _job(3, 5.0, 1)]
+    assert [j.job_id for j in admit(q, 0, 100, 8, now=1.0)] == [0, 1]   # memory: 2 fit
+    assert [j.job_id for j in admit(q, 0, 1000, 2, now=1.0)] == [0, 1]  # slots
+    assert [j.job_id for j in admit(q, 0, 1000, 8, now=0.15)] == [0, 1]  # arrival time
+    assert admit(q, 0, 39, 8, now=10.0) == []                            # head must fit
+    assert [j.job_id for j in admit(q, 7, 1000, 8, now=10.0)] == [0]
+
+
+def test_admit_keeps_order_behind_a_large_job():
+    # a small later job does not overtake an earlier one waiting for memory
+    q = [_job(0, 0.0, 500), _job(1, 0.1, 1)]
+    assert admit(q, 0, 100, 8, now=1.0) == []
+
+
+def test_plan_step_oldest_first_and_bounded():
+    a = _job(0, 0.0, 1, n_tiles=10)
+    b = _job(1, 1.0, 1, n_tiles=10)
+    c = _job(2, 0.5, 1, n_tiles=10)
+    a.next_tile = 4
+    plan = plan_step([b, a, c], 12)
+    assert [(p[0].job_id, p[1], p[2]) for p in plan] == [(0, 4, 10), (2, 0, 6)]
+    plan = plan_step([b, a, c], 100)
+    assert sum(p[2] - p[1] for p in plan) == 6 + 10 + 10
+    a.next_tile = 10
+    assert [p[0].job_id for p in plan_step([a], 5)] == []
