@@ -47,6 +47,21 @@ def algorithmic_flops(st: dict, n_lights: int, ao_on: bool) -> float:
                  + c["ao_dir"] * st["ao_rays"] + c["shade"] * st["pixels"])
 
 
+def measured_traffic():
+    """HBM bytes per render launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (each scaled by a plain copy's reading), valid only
+    while the kernel source is the one that was profiled; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "render_wave_p17_traffic.json")
+    if not os.path.exists(path):
+        return None
+    prof = json.load(open(path))
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in prof["kernel_source_files"])
+    if hashlib.sha256(src).hexdigest() != prof["kernel_source_sha256"]:
+        return None
+    return prof["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(scene, cam, params, target_s: float = 15.0) -> dict:
     """The oracle, as it stands, on a bounded sample of the same frame: evenly
     spaced full rows, sized to about target_s seconds of CPU work."""
@@ -218,7 +233,7 @@ def main():
 
     achieved = flops_frame / (render_ms.mean() * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
                 "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
                 "kernel": "k_render_wave", "kernel_ms": float(render_ms.mean()),
                 "flop_per_frame": flops_frame, "flop_per_counted_ray": flops_frame / rays_frame}
