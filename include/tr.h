@@ -138,6 +138,8 @@ enum {
   TR_STAT_LANE_ITERS,        /* wavefront kernel: busy lanes summed over those iterations */
   TR_STAT_REFILLS,           /* wavefront kernel: finish/refill rounds (per wave) */
   TR_STAT_JUMPS,             /* wavefront kernel: empty-space jumps over more than one cell */
+  TR_STAT_CYCLES_TRAVERSE,   /* wavefront kernel: shader clocks in the traversal loop (summed over waves) */
+  TR_STAT_CYCLES_TOTAL,      /* wavefront kernel: shader clocks from wave start to end (summed) */
   TR_STAT_COUNT
 };
 

@@ -225,6 +225,8 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
   uint64_t c_rays = 0;
   uint32_t l_cells = 0, l_st = 0, l_sh = 0, l_ct = 0, l_ch = 0, l_res = 0, l_jumps = 0;  // per lane
   uint64_t c_iters = 0, c_lanes = 0, c_refills = 0;
+  uint64_t c_cyc_trav = 0;
+  const uint64_t c_cyc_start = COUNT ? clock64() : 0;
 
   // ---- per-lane state
   int32_t kind = kIdle;
@@ -599,6 +601,7 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
       const SceneHot H = load_hot(&A.jobs[scene_job]);
       const int32_t thresh = can_refill ? A.refill_below : 1;
       const bool anyhit = kind != kPrimary;
+      const uint64_t cyc0 = COUNT ? clock64() : 0;
       for (int32_t it = 0;; ++it) {
         const bool work = kind != kIdle && (done | paused) == 0;
         const int32_t nwork = __popcll(__ballot(work));
@@ -762,6 +765,7 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
         }
       }
       (void)anyhit;
+      if (COUNT) c_cyc_trav += clock64() - cyc0;
     }
   }
 
@@ -799,6 +803,8 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
         atomicAdd(&st[TR_STAT_LANE_ITERS], (unsigned long long)c_lanes);
         atomicAdd(&st[TR_STAT_REFILLS], (unsigned long long)c_refills);
         atomicAdd(&st[TR_STAT_JUMPS], (unsigned long long)L.cnt[10]);
+        atomicAdd(&st[TR_STAT_CYCLES_TRAVERSE], (unsigned long long)c_cyc_trav);
+        atomicAdd(&st[TR_STAT_CYCLES_TOTAL], (unsigned long long)(clock64() - c_cyc_start));
       }
     }
   }
