@@ -164,12 +164,15 @@ typedef struct {
  * references and an in-cell sort (the "Preprocess" phase, Table 5).  Blocks
  * on the stream once to read back the scene bounds.  *out receives the new
  * scene; TR_EINVAL on a NULL required pointer, negative count, non-finite
- * coordinate, radius <= 0, zero-length cylinder, n_lights outside 0..8 or
- * cells_per_prim < 0. */
+ * coordinate, radius <= 0, zero-length cylinder, n_lights outside 0..8,
+ * cells_per_prim < 0 or n_spheres + n_cylinders >= 2^28; TR_EUNSUPPORTED when
+ * the grid would hold more than 2^30 - 64 primitive references. */
 tr_status tr_scene_build(const tr_scene_desc *desc, void *hip_stream, tr_scene **out);
 
 /* Rebuild the grid from the resident device arrays (same result as the
- * build's grid), with cells_per_prim (0 = keep the current value). */
+ * build's grid), with cells_per_prim (0 = keep the current value).  After a
+ * failed rebuild the scene renders nothing (TR_EINVAL) until a rebuild
+ * succeeds. */
 tr_status tr_scene_rebuild(tr_scene *scene, double cells_per_prim, void *hip_stream);
 
 /* Device bytes held by the scene (arrays + grid). */

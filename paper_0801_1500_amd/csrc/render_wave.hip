@@ -76,7 +76,37 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 
 __device__ __forceinline__ int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Lane mask of p over the wave (scalar compare result, no VGPR round trip).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// floor(x) as an integer in one instruction (the compiler emits floor + convert)
+__device__ __forceinline__ int32_t cvt_floor(float x) {
+  int32_t r;
+  asm volatile("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+// IEEE min/max of two floats without the operand canonicalisation the
+// compiler adds to fminf/fmaxf when it cannot see where a value came from
+__device__ __forceinline__ float vminf(float a, float b) {
+  float r;
+  asm volatile("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float vmaxf(float a, float b) {
+  float r;
+  asm volatile("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// median of three: clamp of x to [lo, hi] when lo <= hi
+__device__ __forceinline__ int32_t med3i(int32_t x, int32_t lo, int32_t hi) {
+  int32_t r;
+  asm volatile("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+  return r;
+}
 __device__ __forceinline__ float sqrtf_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Per-lane ray and traversal state.
@@ -84,7 +114,7 @@ struct Ray {
   float ox, oy, oz, dx, dy, dz;
   float tmin, tmax;  // t interval of accepted hits
   float t1;          // exit of the grid box (clipped to tmax)
-  float bx, by, bz;  // boundary plane i of axis a is crossed at t = b_a + i * h_a
+  float bx, by, bz;  // the walk enters cell i of axis a at t = b_a + i * h_a
   float hx, hy, hz;
   int32_t cx, cy, cz;
   int32_t sx, sy, sz;  // step signs
@@ -100,6 +130,7 @@ struct Ray {
 // Hot pointers are in the global address space so loads compile to global
 // (not flat) instructions with a scalar base.
 #define TR_GLOBAL __attribute__((address_space(1)))
+#define TR_CONST __attribute__((address_space(4)))
 typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef uint32_t vu2 __attribute__((ext_vector_type(2)));
 struct SceneHot {
@@ -109,9 +140,14 @@ struct SceneHot {
   int32_t n_s;
   int32_t res[3];
   float lo32[3], hi32[3], inv32[3], h32[3];
+  float org32[3];  // -lo * inv: cell coordinate of x is floor(x * inv + org)
 };
 
-__device__ __forceinline__ SceneHot load_hot(const JobDev *J) {
+// The job table is read-only for the whole launch, so it is read through the
+// constant address space: with a wave-uniform job index the fields are scalar
+// loads and stay in SGPRs.
+__device__ __forceinline__ SceneHot load_hot(const JobDev *Jg) {
+  const TR_CONST JobDev *J = (const TR_CONST JobDev *)Jg;
   SceneHot H;
   H.refs = (const TR_GLOBAL uint32_t *)J->sc.refs;
   H.cellinfo = (const TR_GLOBAL vu2 *)J->sc.cellinfo;
@@ -126,17 +162,27 @@ __device__ __forceinline__ SceneHot load_hot(const JobDev *J) {
     H.hi32[q] = J->sc.hi32[q];
     H.inv32[q] = J->sc.inv32[q];
     H.h32[q] = J->sc.h32[q];
+    H.org32[q] = J->sc.org32[q];
   }
   return H;
 }
 
+// base[i] addressed by a 32-bit byte offset from a wave-uniform base (one
+// global load with a scalar base, no 64-bit address arithmetic).  The host
+// bounds every array this is used on below 2^32 bytes.
+template <class T>
+__device__ __forceinline__ T ldg(const TR_GLOBAL T *base, uint32_t i) {
+  return *(const TR_GLOBAL T *)((const TR_GLOBAL char *)base + i * (uint32_t)sizeof(T));
+}
+
 __device__ __forceinline__ void load_cell(Ray &R, const SceneHot &S) {
-  const uint32_t cell = ((uint32_t)R.cz * (uint32_t)S.res[1] + (uint32_t)R.cy) * (uint32_t)S.res[0] +
-                        (uint32_t)R.cx;
-  const vu2 be = S.cellinfo[cell];
+  // res <= 512 per axis: the products fit the 24-bit multiplier
+  const uint32_t cell = __umul24(__umul24((uint32_t)R.cz, (uint32_t)S.res[1]) + (uint32_t)R.cy,
+                                 (uint32_t)S.res[0]) + (uint32_t)R.cx;
+  const vu2 be = ldg(S.cellinfo, cell);
   R.rc = be.x;
   R.re = be.y;
-  const int32_t v = (int32_t)S.refs[be.x];  // in bounds: refs carries 64 padding entries
+  const int32_t v = (int32_t)ldg(S.refs, be.x);  // in bounds: refs carries 64 padding entries
   R.nk = be.x < be.y ? v : -1;
 }
 
@@ -171,12 +217,16 @@ __device__ __forceinline__ bool ray_setup(Ray &R, const SceneHot &S) {
   R.sx = R.dx > 0.0f ? 1 : (R.dx < 0.0f ? -1 : 0);
   R.sy = R.dy > 0.0f ? 1 : (R.dy < 0.0f ? -1 : 0);
   R.sz = R.dz > 0.0f ? 1 : (R.dz < 0.0f ? -1 : 0);
-  R.bx = (S.lo32[0] - R.ox) * ix;
-  R.by = (S.lo32[1] - R.oy) * iy;
-  R.bz = (S.lo32[2] - R.oz) * iz;
-  R.hx = S.h32[0] * ix;
-  R.hy = S.h32[1] * iy;
-  R.hz = S.h32[2] * iz;
+  // Plane of the grid crossed when the walk enters cell i of axis a: at
+  // b_a + i * h_a, with b_a taken one cell up for negative steps (the plane
+  // between cells i and i + 1).  An axis with d_a = 0 gets b_a = inf, h_a = 0:
+  // its plane is never the next one.
+  R.bx = R.sx > 0 ? (S.lo32[0] - R.ox) * ix : (R.sx < 0 ? (S.lo32[0] + S.h32[0] - R.ox) * ix : INFINITY);
+  R.by = R.sy > 0 ? (S.lo32[1] - R.oy) * iy : (R.sy < 0 ? (S.lo32[1] + S.h32[1] - R.oy) * iy : INFINITY);
+  R.bz = R.sz > 0 ? (S.lo32[2] - R.oz) * iz : (R.sz < 0 ? (S.lo32[2] + S.h32[2] - R.oz) * iz : INFINITY);
+  R.hx = R.sx ? S.h32[0] * ix : 0.0f;
+  R.hy = R.sy ? S.h32[1] * iy : 0.0f;
+  R.hz = R.sz ? S.h32[2] * iz : 0.0f;
   load_cell(R, S);
   return true;
 }
@@ -201,7 +251,7 @@ __device__ __forceinline__ int32_t find_job(const JobDev *jobs, int32_t n, int64
 }
 
 template <int BANKS, bool RESOLVE, bool COUNT>
-__global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ? 5 : 4))) void k_render_wave(const WaveArgs A) {
   __shared__ Lds<BANKS> L;
   constexpr int NS = BANKS * 64;
   constexpr int kMinIters = 2;
@@ -243,7 +293,7 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
 
   for (;;) {
     // ============================================================ re-solve
-    if (RESOLVE && __ballot(paused != 0)) {
+    if (RESOLVE && ballot(paused != 0)) {
       if (paused != 0) {
         const int32_t bk = slot >> 6;
         const JobDev *J = &A.jobs[L.bank[bk].job];
@@ -287,7 +337,7 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
     }
 
     // ================================================================ finish
-    if (__ballot(kind != kIdle && done != 0)) {
+    if (ballot(kind != kIdle && done != 0)) {
       const bool fin = kind != kIdle && done != 0;
       const bool fin_prim_hit = fin && kind == kPrimary && R.bk >= 0;
       const bool fin_prim_miss = fin && kind == kPrimary && R.bk < 0;
@@ -349,7 +399,7 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
       }
       {  // queue hit slots that have secondary rays
         const bool enq = fin_prim_hit && nr > 0;
-        const uint64_t m = __ballot(enq);
+        const uint64_t m = ballot(enq);
         if (enq) L.fifo[(q_tail + (int32_t)lane_rank(m)) % NS] = (uint8_t)slot;
         q_tail += __popcll(m);
       }
@@ -429,7 +479,7 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
 
     // ================================================================ refill
     {
-      const uint64_t idle = __ballot(kind == kIdle);
+      const uint64_t idle = ballot(kind == kIdle);
       const int32_t n_idle = __popcll(idle);
       const int32_t rank = (int32_t)lane_rank(idle);
       const bool me_idle = kind == kIdle;
@@ -524,7 +574,7 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
       if (assigned > 0) {
         const bool fresh = me_idle && kind != kIdle;
         if (fresh) {
-          const SceneHot H = load_hot(&A.jobs[scene_job]);
+          const SceneHot H = load_hot(&A.jobs[uni(scene_job)]);
           const BankInfo &B = L.bank[slot >> 6];
           const int32_t q = slot & 63;
           const int32_t vw = B.vw;
@@ -580,7 +630,7 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
 
     // ================================================================ exit
     {
-      const uint64_t busy = __ballot(kind != kIdle);
+      const uint64_t busy = ballot(kind != kIdle);
       if (!busy) {
         if (!tiles_left && held_tile < 0 && bank_busy == 0 && q_head == q_tail) break;
         if (++idle_rounds > 4) {  // cannot happen when the bookkeeping is right
@@ -598,17 +648,17 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
       const bool can_refill =
           q_head != q_tail || (issue_bank >= 0 && issue_next < uni(L.bank[issue_bank].n)) ||
           (free_banks && ((held_tile < 0 && tiles_left) || (held_tile >= 0 && (held_key == cur_key || !bank_busy))));
-      const SceneHot H = load_hot(&A.jobs[scene_job]);
+      const SceneHot H = load_hot(&A.jobs[uni(scene_job)]);
       const int32_t thresh = can_refill ? A.refill_below : 1;
       const bool anyhit = kind != kPrimary;
       const uint64_t cyc0 = COUNT ? clock64() : 0;
       for (int32_t it = 0;; ++it) {
         const bool work = kind != kIdle && (done | paused) == 0;
-        const int32_t nwork = __popcll(__ballot(work));
+        const int32_t nwork = __popcll(ballot(work));
         if (nwork == 0) break;
         if (it >= kMinIters) {
           if (nwork < thresh) break;
-          if (RESOLVE && nwork < A.refill_below && __ballot(paused != 0)) break;
+          if (RESOLVE && nwork < A.refill_below && ballot(paused != 0)) break;
         }
         if (COUNT) {
           ++c_iters;
@@ -626,8 +676,8 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
         // lanes want it -- at least `mix`/64 of the largest group (cylinders
         // also need busy/cyl_wait lanes) -- so the wave does not pay for every
         // code path each iteration; the other lanes wait.
-        const int32_t n_sph = __popcll(__ballot(is_sph));
-        const int32_t n_cyl = __popcll(__ballot(is_cyl));
+        const int32_t n_sph = __popcll(ballot(is_sph));
+        const int32_t n_cyl = __popcll(ballot(is_cyl));
         const int32_t n_step = nwork - n_sph - n_cyl;
         const int32_t n_max = max(n_step, max(n_sph, n_cyl));
         const int32_t bar = (n_max * A.mix + 63) >> 6;
@@ -639,7 +689,7 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
         float t = 0.0f;
         if (is_sph) {
           tested = true;
-          const vf4 s = H.sph32[nk];
+          const vf4 s = ldg(H.sph32, (uint32_t)nk);
           const float qx = s.x - R.ox, qy = s.y - R.oy, qz = s.z - R.oz;
           const float b = qx * R.dx + qy * R.dy + qz * R.dz;
           const float lx = qx - b * R.dx, ly = qy - b * R.dy, lz = qz - b * R.dz;
@@ -657,8 +707,8 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
         }
         if (is_cyl) {
           tested = true;
-          const vf4 a = H.cylA32[nk - H.n_s];
-          const vf4 w = H.cylW32[nk - H.n_s];
+          const vf4 a = ldg(H.cylA32, (uint32_t)(nk - H.n_s));
+          const vf4 w = ldg(H.cylW32, (uint32_t)(nk - H.n_s));
           const float Dx = R.ox - a.x, Dy = R.oy - a.y, Dz = R.oz - a.z;
           const float dw = R.dx * w.x + R.dy * w.y + R.dz * w.z;
           const float Dw = Dx * w.x + Dy * w.y + Dz * w.z;
@@ -674,7 +724,7 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
           const float qq = -(Bq + __builtin_copysignf(sq, Bq));
           const bool ok = nonpar && !g0 && disc >= 0.0f && qq != 0.0f;
           const float r0 = qq * rcpf(Aq), r1 = Cq * rcpf(qq);
-          const float tl = fminf(r0, r1), th = fmaxf(r0, r1);
+          const float tl = vminf(r0, r1), th = vmaxf(r0, r1);
           const float kL = kKappa * w.w;
           const float sl = Dw + tl * dw, sh = Dw + th * dw;
           const bool inl = ok && tl > R.tmin && tl <= R.tmax;
@@ -703,20 +753,16 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
             l_res += graze;
           }
           ++R.rc;
-          const int32_t v = (int32_t)H.refs[R.rc];  // refs has one padding entry
+          const int32_t v = (int32_t)ldg(H.refs, R.rc);  // refs has padding entries
           R.nk = R.rc < R.re ? v : -1;
-          if (RESOLVE && graze) {
-            paused = 1;
-            gk = nk;
-          } else if (hit) {
-            if (anyhit) {
-              R.bk = nk;
-              R.bt = t;
-              done = 1;
-            } else if (t < R.bt || (t == R.bt && nk < R.bk)) {
-              R.bt = t;
-              R.bk = nk;
-            }
+          // nearest hit (ties to the lower id); any hit ends a shadow/AO ray
+          const bool take = hit && (anyhit || t < R.bt || (t == R.bt && nk < R.bk));
+          R.bt = take ? t : R.bt;
+          R.bk = take ? nk : R.bk;
+          done = (anyhit && hit) ? 1 : done;
+          if (RESOLVE) {
+            paused = graze ? 1 : paused;
+            gk = graze ? nk : gk;
           }
         }
         if (is_step) {
@@ -724,37 +770,35 @@ __global__ __launch_bounds__(64) void k_render_wave(const WaveArgs A) {
           // Chebyshev distance k to the nearest occupied cell, so the whole
           // cube of half-size k-1 around it is empty and the walk jumps to
           // where the ray leaves that cube (k = 1: an ordinary DDA step).
+          // Branch-free: the k = 1 step is the jump with a cube of size 0.
           const int32_t kk = R.re == 0 ? (int32_t)R.rc : 1;
-          const int32_t pxi = R.sx > 0 ? R.cx + kk : R.cx - kk + 1;
-          const int32_t pyi = R.sy > 0 ? R.cy + kk : R.cy - kk + 1;
-          const int32_t pzi = R.sz > 0 ? R.cz + kk : R.cz - kk + 1;
-          const float tx = R.sx ? fmaf((float)pxi, R.hx, R.bx) : INFINITY;
-          const float ty = R.sy ? fmaf((float)pyi, R.hy, R.by) : INFINITY;
-          const float tz = R.sz ? fmaf((float)pzi, R.hz, R.bz) : INFINITY;
+          const int32_t m = kk - 1;
+          // cell just beyond the cube on each axis; its near plane is crossed at
+          // b_a + i * h_a (b_a is shifted one cell for negative steps at setup)
+          const int32_t ix1 = R.cx + __mul24(R.sx, kk);
+          const int32_t iy1 = R.cy + __mul24(R.sy, kk);
+          const int32_t iz1 = R.cz + __mul24(R.sz, kk);
+          const float tx = fmaf((float)ix1, R.hx, R.bx);  // inf when d_x = 0
+          const float ty = fmaf((float)iy1, R.hy, R.by);
+          const float tz = fmaf((float)iz1, R.hz, R.bz);
           const float tn = fminf(tx, fminf(ty, tz));
-          if ((R.bk >= 0 && R.bt <= fminf(tn, R.t1)) || !(tn < R.t1)) {
+          // stop at the box exit, or when the best hit so far is not beyond the plane
+          if (!(tn < vminf(R.t1, R.bt))) {
             done = 1;
           } else {
             const bool ax = tx == tn;
             const bool ay = !ax && ty == tn;
             const bool az = !ax && !ay;
-            int32_t nx = R.cx, ny = R.cy, nz = R.cz;
-            if (kk > 1) {
-              // the other axes land where the ray meets the exit face, inside the cube
-              const int32_t m = kk - 1;
-              const int32_t fx = (int32_t)floorf((fmaf(tn, R.dx, R.ox) - H.lo32[0]) * H.inv32[0]);
-              const int32_t fy = (int32_t)floorf((fmaf(tn, R.dy, R.oy) - H.lo32[1]) * H.inv32[1]);
-              const int32_t fz = (int32_t)floorf((fmaf(tn, R.dz, R.oz) - H.lo32[2]) * H.inv32[2]);
-              nx = min(max(fx, R.cx - m), R.cx + m);
-              ny = min(max(fy, R.cy - m), R.cy + m);
-              nz = min(max(fz, R.cz - m), R.cz + m);
-              if (COUNT) ++l_jumps;
-            }
-            R.cx = ax ? R.cx + R.sx * kk : nx;
-            R.cy = ay ? R.cy + R.sy * kk : ny;
-            R.cz = az ? R.cz + R.sz * kk : nz;
-            const int32_t st = ax ? R.sx : (ay ? R.sy : R.sz);
-            if (st == 0 || (uint32_t)R.cx >= (uint32_t)H.res[0] ||
+            // the other axes land in the cell of the exit point, kept inside the cube
+            const int32_t nx = R.cx + med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], H.org32[0])) - R.cx, -m, m);
+            const int32_t ny = R.cy + med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], H.org32[1])) - R.cy, -m, m);
+            const int32_t nz = R.cz + med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], H.org32[2])) - R.cz, -m, m);
+            if (COUNT && kk > 1) ++l_jumps;
+            R.cx = ax ? ix1 : nx;
+            R.cy = ay ? iy1 : ny;
+            R.cz = az ? iz1 : nz;
+            // (tn < t1 is finite, so the crossed axis has a nonzero step)
+            if ((uint32_t)R.cx >= (uint32_t)H.res[0] ||
                 (uint32_t)R.cy >= (uint32_t)H.res[1] || (uint32_t)R.cz >= (uint32_t)H.res[2]) {
               done = 1;
             } else {

@@ -71,6 +71,7 @@ struct tr_scene {
   uint32_t *h_total = nullptr;
   trh::GridParams gp{};
   int64_t n_refs = 0;
+  bool grid_ok = false;  // false after a failed (re)build: the scene cannot render
   SceneDev dev{};
 };
 
@@ -149,13 +150,14 @@ static void fill_scene_dev(tr_scene *s) {
     d.hi32[a] = (float)s->gp.hi[a];
     d.h32[a] = (float)s->gp.h[a];
     d.inv32[a] = (float)s->gp.inv[a];
+    d.org32[a] = (float)(-s->gp.lo[a] * s->gp.inv[a]);
     d.res[a] = s->gp.res[a];
   }
 }
 
 // Bounds -> parameters -> count -> scan -> scatter -> sort, from the resident
 // FP64 arrays.  Two blocking readbacks (bounds, reference total).
-static tr_status build_grid(tr_scene *s, hipStream_t st) {
+static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
   const int64_t N = s->n_s + s->n_c;
   HIP_TRY(trh::launch_pack32(s->n_s, s->n_c, s->sph64, s->cylA64, s->cylW64, s->sph32, s->cylA32,
                              s->cylW32, st));
@@ -220,6 +222,10 @@ static tr_status build_grid(tr_scene *s, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(s->h_total, s->cell_begin + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const int64_t R = (int64_t)*s->h_total;
+  // references are addressed with 32-bit byte offsets by the traversal
+  if (R + 64 > ((int64_t)1 << 30))
+    return fail(TR_EUNSUPPORTED, "grid has %lld references (limit 2^30 - 64); lower cells_per_prim",
+                (long long)R);
   // padding: the FP32 walk reads refs[x] for x <= n_refs (end of a cell) and
   // for x <= 32 (the distance word of an empty cell) before checking
   const int64_t R_pad = R + 64;
@@ -239,11 +245,20 @@ static tr_status build_grid(tr_scene *s, hipStream_t st) {
   return TR_OK;
 }
 
+static tr_status build_grid(tr_scene *s, hipStream_t st) {
+  s->grid_ok = false;
+  const tr_status rc = build_grid_impl(s, st);
+  s->grid_ok = rc == TR_OK;
+  return rc;
+}
+
 extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr_scene **out) {
   if (!d || !out) return fail(TR_EINVAL, "tr_scene_build: NULL desc or out");
   *out = nullptr;
   if (d->n_spheres < 0 || d->n_cylinders < 0) return fail(TR_EINVAL, "negative primitive count");
-  if (d->n_spheres + d->n_cylinders > INT32_MAX - 1) return fail(TR_EINVAL, "too many primitives");
+  // the traversal addresses primitive records (16 B) with 32-bit byte offsets
+  if (d->n_spheres + d->n_cylinders >= (int64_t)1 << 28)
+    return fail(TR_EINVAL, "too many primitives (limit 2^28 - 1)");
   if (d->n_lights < 0 || d->n_lights > 8) return fail(TR_EINVAL, "n_lights must be 0..8");
   if (!(d->cells_per_prim >= 0.0) || !std::isfinite(d->cells_per_prim))
     return fail(TR_EINVAL, "cells_per_prim must be finite and >= 0");
@@ -471,6 +486,7 @@ static tr_status make_job(const tr_scene *s, const tr_camera *c, const tr_params
   rc = check_params(p, f);
   if (rc != TR_OK) return rc;
   if (!s) return fail(TR_EINVAL, "NULL scene");
+  if (!s->grid_ok) return fail(TR_EINVAL, "scene grid is invalid (its last rebuild failed)");
   std::memset(&J, 0, sizeof J);
   J.sc = s->dev;
   double fw[3] = {c->lookat[0] - c->eye[0], c->lookat[1] - c->eye[1], c->lookat[2] - c->eye[2]};

@@ -27,8 +27,8 @@ struct SceneDev {
   const uint2 *cellinfo;  // (begin, end) or (empty-space distance, 0) per cell
   double lo[3], hi[3], h[3], inv[3];
   float lo32[3], hi32[3], h32[3], inv32[3];
+  float org32[3];  // -lo * inv, rounded once: FP32 cell coordinate = x * inv32 + org32
   int32_t res[3];
-  int32_t pad_;
 };
 
 // One render job: scene + camera + parameters + outputs + its tile range.
@@ -72,8 +72,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
   const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
   for (int rnd = 0; rnd < 10; ++rnd) {
-    uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
-    uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+    // one 32x32->64 multiply gives both halves
+    const uint64_t p0 = (uint64_t)M0 * c.x, p1 = (uint64_t)M1 * c.z;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     uint4 n;
     n.x = hi1 ^ c.y ^ k0;
     n.y = lo1;

@@ -90,6 +90,13 @@ def test_scene_validation_rejects(tr):
     assert b"zero length" in L.tr_last_error()
     h = C.c_void_p()
     assert L.tr_scene_build(None, None, C.byref(h)) == tr.TR_EINVAL
+    # 2^28 primitives exceed the 32-bit byte offsets of the traversal (the count
+    # is checked before any array is read)
+    big = tr.SceneDesc(1 << 27, good_c.ctypes.data, good_r.ctypes.data, rgb.ctypes.data,
+                       1 << 27, good_c.ctypes.data, good_c.ctypes.data, good_r.ctypes.data,
+                       rgb.ctypes.data, 0, None, None, 0.0)
+    assert L.tr_scene_build(C.byref(big), None, C.byref(h)) == tr.TR_EINVAL
+    assert b"too many primitives" in L.tr_last_error()
 
 
 def test_render_validation_rejects(tr):
