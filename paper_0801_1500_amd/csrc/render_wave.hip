@@ -40,6 +40,8 @@ constexpr float kKappa = 1.0f / 4096.0f;
 constexpr double kEpsD = 1e-4;
 
 enum : int32_t { kIdle = 0, kPrimary = 1, kShadow = 2, kAO = 3 };
+// lane state of the ray it holds (an idle lane counts as finished)
+enum : int32_t { kRun = 0, kDone = 1, kPaused = 2 };
 
 // Per-bank copy of the job fields secondary rays and shading need.
 struct BankInfo {
@@ -280,8 +282,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
 
   // ---- per-lane state
   int32_t kind = kIdle;
-  int32_t done = 0;    // ray finished (kept as an int: per-lane flags stay in VGPRs)
-  int32_t paused = 0;  // waiting for an FP64 re-solve of primitive gk
+  int32_t st = kDone;  // kRun, kDone, or kPaused (waiting for an FP64 re-solve of primitive gk)
   int32_t gk = 0;
   int32_t slot = 0, ridx = 0;
   uint32_t l_pix = 0, l_hit = 0, l_ao = 0, l_shadow = 0;
@@ -293,8 +294,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
 
   for (;;) {
     // ============================================================ re-solve
-    if (RESOLVE && ballot(paused != 0)) {
-      if (paused != 0) {
+    if (RESOLVE && ballot(st == kPaused)) {
+      if (st == kPaused) {
         const int32_t bk = slot >> 6;
         const JobDev *J = &A.jobs[L.bank[bk].job];
         const SceneDev &S = J->sc;
@@ -321,24 +322,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
           h = hit_sphere_f64(S.sph64[gk], o, d, tmin, tmax, t);
         else
           h = hit_cylinder_f64(S.cylA64[gk - S.n_s], S.cylW64[gk - S.n_s], o, d, tmin, tmax, t);
+        int32_t nst = kRun;
         if (h) {
           const float tf = (float)t;
           if (kind != kPrimary) {
             R.bk = gk;
             R.bt = tf;
-            done = 1;
+            nst = kDone;
           } else if (tf < R.bt || (tf == R.bt && gk < R.bk)) {
             R.bt = tf;
             R.bk = gk;
           }
         }
-        paused = 0;
+        st = nst;
       }
     }
 
     // ================================================================ finish
-    if (ballot(kind != kIdle && done != 0)) {
-      const bool fin = kind != kIdle && done != 0;
+    if (ballot(kind != kIdle && st == kDone)) {
+      const bool fin = kind != kIdle && st == kDone;
       const bool fin_prim_hit = fin && kind == kPrimary && R.bk >= 0;
       const bool fin_prim_miss = fin && kind == kPrimary && R.bk < 0;
       bool finalize = fin_prim_miss;
@@ -620,7 +622,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
             }
           }
           setup_ok = ray_setup(R, H);
-          done = setup_ok ? 0 : 1;
+          st = setup_ok ? kRun : kDone;
         }
       }
       c_rays += (uint64_t)assigned;
@@ -649,16 +651,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
           q_head != q_tail || (issue_bank >= 0 && issue_next < uni(L.bank[issue_bank].n)) ||
           (free_banks && ((held_tile < 0 && tiles_left) || (held_tile >= 0 && (held_key == cur_key || !bank_busy))));
       const SceneHot H = load_hot(&A.jobs[uni(scene_job)]);
-      const int32_t thresh = can_refill ? A.refill_below : 1;
+      const int32_t thresh = uni(can_refill ? A.refill_below : 1);
       const bool anyhit = kind != kPrimary;
       const uint64_t cyc0 = COUNT ? clock64() : 0;
       for (int32_t it = 0;; ++it) {
-        const bool work = kind != kIdle && (done | paused) == 0;
+        const bool work = st == kRun;
         const int32_t nwork = __popcll(ballot(work));
         if (nwork == 0) break;
         if (it >= kMinIters) {
           if (nwork < thresh) break;
-          if (RESOLVE && nwork < A.refill_below && ballot(paused != 0)) break;
+          if (RESOLVE && nwork < A.refill_below && ballot(st == kPaused)) break;
         }
         if (COUNT) {
           ++c_iters;
@@ -669,7 +671,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
         // tests, the long path, run only when enough lanes want one; the
         // other lanes keep stepping and testing spheres meanwhile.
         const int32_t nk = R.nk;
-        bool is_sph = work && nk >= 0 && nk < H.n_s;
+        bool is_sph = work && (uint32_t)nk < (uint32_t)H.n_s;  // nk = -1 is not a sphere
         bool is_cyl = work && nk >= H.n_s;
         bool is_step = work && nk < 0;
         // Work-type scheduling: a unit type runs this iteration only if enough
@@ -759,9 +761,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
           const bool take = hit && (anyhit || t < R.bt || (t == R.bt && nk < R.bk));
           R.bt = take ? t : R.bt;
           R.bk = take ? nk : R.bk;
-          done = (anyhit && hit) ? 1 : done;
+          st = (anyhit && hit) ? kDone : st;
           if (RESOLVE) {
-            paused = graze ? 1 : paused;
+            st = graze ? kPaused : st;
             gk = graze ? nk : gk;
           }
         }
@@ -784,7 +786,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
           const float tn = fminf(tx, fminf(ty, tz));
           // stop at the box exit, or when the best hit so far is not beyond the plane
           if (!(tn < vminf(R.t1, R.bt))) {
-            done = 1;
+            st = kDone;
           } else {
             const bool ax = tx == tn;
             const bool ay = !ax && ty == tn;
@@ -800,7 +802,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
             // (tn < t1 is finite, so the crossed axis has a nonzero step)
             if ((uint32_t)R.cx >= (uint32_t)H.res[0] ||
                 (uint32_t)R.cy >= (uint32_t)H.res[1] || (uint32_t)R.cz >= (uint32_t)H.res[2]) {
-              done = 1;
+              st = kDone;
             } else {
               if (COUNT) ++l_cells;
               load_cell(R, H);
