@@ -670,23 +670,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
         // each lane knows its unit of work before touching memory.  Cylinder
         // tests, the long path, run only when enough lanes want one; the
         // other lanes keep stepping and testing spheres meanwhile.
+        // Working lanes only from here (an if, not a continue: the lanes must
+        // meet again at the loop head for its ballot).  Ballots inside count
+        // the working lanes.
+        if (work) {
         const int32_t nk = R.nk;
-        bool is_sph = work && (uint32_t)nk < (uint32_t)H.n_s;  // nk = -1 is not a sphere
-        bool is_cyl = work && nk >= H.n_s;
-        bool is_step = work && nk < 0;
         // Work-type scheduling: a unit type runs this iteration only if enough
         // lanes want it -- at least `mix`/64 of the largest group (cylinders
         // also need busy/cyl_wait lanes) -- so the wave does not pay for every
-        // code path each iteration; the other lanes wait.
-        const int32_t n_sph = __popcll(ballot(is_sph));
-        const int32_t n_cyl = __popcll(ballot(is_cyl));
+        // code path each iteration; the other lanes wait.  The decisions are
+        // wave-uniform; each lane's type is one compare.
+        const int32_t n_sph = __popcll(ballot((uint32_t)nk < (uint32_t)H.n_s));  // nk = -1: no
+        const int32_t n_cyl = __popcll(ballot(nk >= H.n_s));
         const int32_t n_step = nwork - n_sph - n_cyl;
         const int32_t n_max = max(n_step, max(n_sph, n_cyl));
         const int32_t bar = (n_max * A.mix + 63) >> 6;
-        const bool run_cyl = n_cyl > 0 && n_cyl >= bar && n_cyl * A.cyl_wait >= nwork;
-        is_sph = is_sph && n_sph >= bar;
-        is_step = is_step && n_step >= bar;
-        is_cyl = is_cyl && (run_cyl || (n_sph < bar && n_step < bar));
+        const bool go_sph = n_sph >= bar;
+        const bool go_step = n_step >= bar;
+        const bool go_cyl = n_cyl > 0 && ((n_cyl >= bar && n_cyl * A.cyl_wait >= nwork) || (!go_sph && !go_step));
+        const bool is_sph = go_sph && (uint32_t)nk < (uint32_t)H.n_s;
+        const bool is_cyl = go_cyl && nk >= H.n_s;
+        const bool is_step = go_step && nk < 0;
         bool tested = false, hit = false, graze = false;
         float t = 0.0f;
         if (is_sph) {
@@ -809,6 +813,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
             }
           }
         }
+        }  // work
       }
       (void)anyhit;
       if (COUNT) c_cyc_trav += clock64() - cyc0;
