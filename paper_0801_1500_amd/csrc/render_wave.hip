@@ -46,12 +46,26 @@ enum : int32_t { kRun = 0, kDone = 1, kPaused = 2 };
 // Per-bank copy of the job fields secondary rays and shading need.
 struct BankInfo {
   int32_t job, x0, y0, vw, n, done;
-  int32_t W, S, n_lights;
+  int32_t vmagic;       // ceil(2^16 / vw): q / vw = (q * vmagic) >> 16 for q < 64
+  int32_t W, H, S, n_lights;
   uint32_t key0, key1, view;
   float maxd, sky;
+  float eye[3], f[3], r[3], u[3], th, aspect;  // FP32 camera
+  float bg[3];
+  float *rgb;
+  int32_t *hit_id;
+  uint32_t *ao_mask;
+  uint8_t *light_mask;
   float ldir[8][3];
   float lcol[8][3];
 };
+
+// Pixel of slot offset q (0..63) in a bank's tile: row-major over vw columns.
+__device__ __forceinline__ void bank_pixel(const BankInfo &B, int32_t q, int32_t &x, int32_t &y) {
+  const int32_t qy = (int32_t)(__umul24((uint32_t)q, (uint32_t)B.vmagic) >> 16);
+  x = B.x0 + q - qy * B.vw;
+  y = B.y0 + qy;
+}
 
 template <int BANKS>
 struct Lds {
@@ -138,7 +152,7 @@ typedef uint32_t vu2 __attribute__((ext_vector_type(2)));
 struct SceneHot {
   const TR_GLOBAL uint32_t *refs;
   const TR_GLOBAL vu2 *cellinfo;
-  const TR_GLOBAL vf4 *sph32, *cylA32, *cylW32;
+  const TR_GLOBAL vf4 *sph32, *cylA32, *cylW32, *albedo;
   int32_t n_s;
   int32_t res[3];
   float lo32[3], hi32[3], inv32[3], h32[3];
@@ -156,6 +170,7 @@ __device__ __forceinline__ SceneHot load_hot(const JobDev *Jg) {
   H.sph32 = (const TR_GLOBAL vf4 *)J->sc.sph32;
   H.cylA32 = (const TR_GLOBAL vf4 *)J->sc.cylA32;
   H.cylW32 = (const TR_GLOBAL vf4 *)J->sc.cylW32;
+  H.albedo = (const TR_GLOBAL vf4 *)J->sc.albedo;
   H.n_s = J->sc.n_s;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
@@ -301,9 +316,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
         const SceneDev &S = J->sc;
         double o[3], d[3];
         if (kind == kPrimary) {
-          const int32_t q = slot & 63;
-          const int32_t vw = L.bank[bk].vw;
-          primary_ray_f64(*J, L.bank[bk].x0 + q % vw, L.bank[bk].y0 + q / vw, o, d);
+          int32_t px, py;
+          bank_pixel(L.bank[bk], slot & 63, px, py);
+          primary_ray_f64(*J, px, py, o, d);
         } else {
           o[0] = R.ox;
           o[1] = R.oy;
@@ -345,21 +360,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
       const bool fin_prim_miss = fin && kind == kPrimary && R.bk < 0;
       bool finalize = fin_prim_miss;
       uint32_t nr = 0;
+      // every bank in flight renders the wave's current scene
+      const SceneHot S = load_hot(&A.jobs[uni(scene_job)]);
       if (fin_prim_hit) {
         const int32_t bk = slot >> 6;
-        const JobDev *jb = &A.jobs[L.bank[bk].job];
-        const SceneDev &S = jb->sc;
         const int32_t k = R.bk;
         const float t = R.bt;
         const float Px = R.ox + t * R.dx, Py = R.oy + t * R.dy, Pz = R.oz + t * R.dz;
         float Nx, Ny, Nz;
         if (k < S.n_s) {
-          const float4 s = S.sph32[k];
+          const vf4 s = ldg(S.sph32, (uint32_t)k);
           Nx = Px - s.x;
           Ny = Py - s.y;
           Nz = Pz - s.z;
         } else {
-          const float4 a = S.cylA32[k - S.n_s], w = S.cylW32[k - S.n_s];
+          const vf4 a = ldg(S.cylA32, (uint32_t)(k - S.n_s)), w = ldg(S.cylW32, (uint32_t)(k - S.n_s));
           const float Dx = R.ox - a.x, Dy = R.oy - a.y, Dz = R.oz - a.z;
           const float sax = (Dx * w.x + Dy * w.y + Dz * w.z) + t * (R.dx * w.x + R.dy * w.y + R.dz * w.z);
           Nx = (Dx + t * R.dx) - sax * w.x;
@@ -421,13 +436,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
       if (finalize) {
         const int32_t bk = slot >> 6;
         const BankInfo &B = L.bank[bk];
-        const int32_t q = slot & 63;
-        const int32_t vw = B.vw;
-        const int32_t x = B.x0 + q % vw;
-        const int32_t y = B.y0 + q / vw;
-        const JobDev *J = &A.jobs[B.job];
+        int32_t x, y;
+        bank_pixel(B, slot & 63, x, y);
         const int64_t pid = (int64_t)y * B.W + x;
-        float cr = J->bg[0], cg = J->bg[1], cb = J->bg[2];
+        float cr = B.bg[0], cg = B.bg[1], cb = B.bg[2];
         int32_t hid = -1;
         uint32_t am = 0, lm = 0;
         ++l_pix;
@@ -448,7 +460,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
           }
           float ao = 1.0f;
           if (B.S > 0) ao = (float)(B.S - L.aocnt[slot]) / (float)B.S;
-          const float4 alb = J->sc.albedo[k];
+          const vf4 alb = ldg(S.albedo, (uint32_t)k);
           const float sk = B.sky * ao;
           cr = fminf(fmaxf(alb.x * (Dr + sk), 0.0f), 1.0f);
           cg = fminf(fmaxf(alb.y * (Dg + sk), 0.0f), 1.0f);
@@ -457,12 +469,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
           l_ao += (uint32_t)B.S;
           l_shadow += (uint32_t)__popc(lv);
         }
-        J->rgb[pid * 3 + 0] = cr;
-        J->rgb[pid * 3 + 1] = cg;
-        J->rgb[pid * 3 + 2] = cb;
-        if (J->hit_id) J->hit_id[pid] = hid;
-        if (J->ao_mask) J->ao_mask[pid] = am;
-        if (J->light_mask) J->light_mask[pid] = (uint8_t)lm;
+        float *rgb = B.rgb + pid * 3;
+        rgb[0] = cr;
+        rgb[1] = cg;
+        rgb[2] = cb;
+        if (B.hit_id) B.hit_id[pid] = hid;
+        if (B.ao_mask) B.ao_mask[pid] = am;
+        if (B.light_mask) B.light_mask[pid] = (uint8_t)lm;
         atomicAdd(&L.bank[bk].done, 1);
       }
       if (fin) kind = kIdle;
@@ -542,7 +555,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
             B.vw = vw;
             B.n = vw * vh;
             B.done = 0;
+            B.vmagic = (65536 + vw - 1) / vw;
             B.W = J->W;
+            B.H = J->H;
+            B.th = J->th32;
+            B.aspect = J->aspect32;
+            B.rgb = J->rgb;
+            B.hit_id = J->hit_id;
+            B.ao_mask = J->ao_mask;
+            B.light_mask = J->light_mask;
             B.S = J->S;
             B.n_lights = J->n_lights;
             B.key0 = J->key0;
@@ -555,6 +576,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
             const int32_t l = lane / 3, a = lane % 3;
             L.bank[b].ldir[l][a] = J->ldir32[l][a];
             L.bank[b].lcol[l][a] = J->lcol32[l][a];
+          } else if (lane < 27) {
+            const int32_t a = lane - 24;
+            L.bank[b].eye[a] = J->eye32[a];
+            L.bank[b].f[a] = J->f32[a];
+            L.bank[b].r[a] = J->r32[a];
+            L.bank[b].u[a] = J->u32[a];
+            L.bank[b].bg[a] = J->bg[a];
           }
           __syncthreads();
           bank_busy |= 1u << b;
@@ -578,24 +606,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
         if (fresh) {
           const SceneHot H = load_hot(&A.jobs[uni(scene_job)]);
           const BankInfo &B = L.bank[slot >> 6];
-          const int32_t q = slot & 63;
-          const int32_t vw = B.vw;
-          const int32_t pi = B.x0 + q % vw;
-          const int32_t pj = B.y0 + q / vw;
+          int32_t pi, pj;
+          bank_pixel(B, slot & 63, pi, pj);
           if (kind == kPrimary) {
-            const JobDev *J = &A.jobs[B.job];
-            const float x = ((2.0f * ((float)pi + 0.5f)) / (float)J->W - 1.0f) * J->th32 * J->aspect32;
-            const float y = (1.0f - (2.0f * ((float)pj + 0.5f)) / (float)J->H) * J->th32;
-            const float vx = J->f32[0] + x * J->r32[0] + y * J->u32[0];
-            const float vy = J->f32[1] + x * J->r32[1] + y * J->u32[1];
-            const float vz = J->f32[2] + x * J->r32[2] + y * J->u32[2];
+            const float x = ((2.0f * ((float)pi + 0.5f)) / (float)B.W - 1.0f) * B.th * B.aspect;
+            const float y = (1.0f - (2.0f * ((float)pj + 0.5f)) / (float)B.H) * B.th;
+            const float vx = B.f[0] + x * B.r[0] + y * B.u[0];
+            const float vy = B.f[1] + x * B.r[1] + y * B.u[1];
+            const float vz = B.f[2] + x * B.r[2] + y * B.u[2];
             const float inv = __builtin_amdgcn_rsqf(vx * vx + vy * vy + vz * vz);
             R.dx = vx * inv;
             R.dy = vy * inv;
             R.dz = vz * inv;
-            R.ox = J->eye32[0];
-            R.oy = J->eye32[1];
-            R.oz = J->eye32[2];
+            R.ox = B.eye[0];
+            R.oy = B.eye[1];
+            R.oz = B.eye[2];
             R.tmin = 0.0f;
             R.tmax = INFINITY;
             R.skip = -1;
