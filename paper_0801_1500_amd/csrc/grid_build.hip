@@ -264,14 +264,25 @@ __global__ void k_dist_pass(const uint8_t *in, uint8_t *out, int32_t rx, int32_t
   out[c] = (uint8_t)best;
 }
 
-// Traversal view of a cell: (begin, end) of its references, or (dist, 0)
-// for an empty cell, so one 8-byte load tells the walk both.
-__global__ void k_cellinfo(const uint32_t *cell_begin, const uint8_t *d, int64_t n_cells,
-                           uint2 *info) {
+// Traversal view of a cell: (begin, end, first reference) of an occupied
+// cell, or (dist, 0, ~0) of an empty one, so one 12-byte load gives the walk
+// the cell's extent and its first unit of work (refs is sorted already).
+__global__ void k_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, const uint8_t *d,
+                           int64_t n_cells, trd::CellInfo *info) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_cells) return;
   const uint32_t b = cell_begin[c], e = cell_begin[c + 1];
-  info[c] = b < e ? make_uint2(b, e) : make_uint2(max((uint32_t)d[c], 1u), 0u);
+  trd::CellInfo r;
+  if (b < e) {
+    r.a = b;
+    r.b = e;
+    r.c = refs[b];
+  } else {
+    r.a = max((uint32_t)d[c], 1u);
+    r.b = 0u;
+    r.c = 0xFFFFFFFFu;
+  }
+  info[c] = r;
 }
 
 // ---- exclusive scan: blocks of kScanItems, block sums scanned recursively
@@ -425,8 +436,8 @@ hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32
   return hipGetLastError();
 }
 
-hipError_t launch_cellinfo(const uint32_t *cell_begin, const int32_t res[3], uint8_t *d0, uint8_t *d1,
-                           uint2 *info, hipStream_t st) {
+hipError_t launch_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, const int32_t res[3],
+                           uint8_t *d0, uint8_t *d1, trd::CellInfo *info, hipStream_t st) {
   const int64_t n = (int64_t)res[0] * res[1] * res[2];
   if (n <= 0) return hipSuccess;
   const unsigned nb = blocks_for(n);
@@ -434,7 +445,7 @@ hipError_t launch_cellinfo(const uint32_t *cell_begin, const int32_t res[3], uin
   k_dist_pass<<<nb, kBlock, 0, st>>>(d0, d1, res[0], res[1], res[2], 0);
   k_dist_pass<<<nb, kBlock, 0, st>>>(d1, d0, res[0], res[1], res[2], 1);
   k_dist_pass<<<nb, kBlock, 0, st>>>(d0, d1, res[0], res[1], res[2], 2);
-  k_cellinfo<<<nb, kBlock, 0, st>>>(cell_begin, d1, n, info);
+  k_cellinfo<<<nb, kBlock, 0, st>>>(cell_begin, refs, d1, n, info);
   return hipGetLastError();
 }
 

@@ -117,6 +117,13 @@ __device__ __forceinline__ float vmaxf(float a, float b) {
   return r;
 }
 
+// a * b + c on the 24-bit multiplier (a, b < 2^24; b wave-uniform)
+__device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm volatile("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  return r;
+}
+
 // median of three: clamp of x to [lo, hi] when lo <= hi
 __device__ __forceinline__ int32_t med3i(int32_t x, int32_t lo, int32_t hi) {
   int32_t r;
@@ -128,8 +135,9 @@ __device__ __forceinline__ float sqrtf_fast(float x) { return __builtin_amdgcn_s
 // Per-lane ray and traversal state.
 struct Ray {
   float ox, oy, oz, dx, dy, dz;
-  float tmin, tmax;  // t interval of accepted hits
-  float t1;          // exit of the grid box (clipped to tmax)
+  float tmin, tmax;  // t interval of accepted hits (tmax is folded into t1 at setup)
+  float t1;          // exit of the grid box clipped to tmax: every primitive lies
+                     // inside the box, so hits are accepted in (tmin, t1]
   float bx, by, bz;  // the walk enters cell i of axis a at t = b_a + i * h_a
   float hx, hy, hz;
   int32_t cx, cy, cz;
@@ -151,7 +159,7 @@ typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef uint32_t vu2 __attribute__((ext_vector_type(2)));
 struct SceneHot {
   const TR_GLOBAL uint32_t *refs;
-  const TR_GLOBAL vu2 *cellinfo;
+  const TR_GLOBAL trd::CellInfo *cellinfo;
   const TR_GLOBAL vf4 *sph32, *cylA32, *cylW32, *albedo;
   int32_t n_s;
   int32_t res[3];
@@ -166,7 +174,7 @@ __device__ __forceinline__ SceneHot load_hot(const JobDev *Jg) {
   const TR_CONST JobDev *J = (const TR_CONST JobDev *)Jg;
   SceneHot H;
   H.refs = (const TR_GLOBAL uint32_t *)J->sc.refs;
-  H.cellinfo = (const TR_GLOBAL vu2 *)J->sc.cellinfo;
+  H.cellinfo = (const TR_GLOBAL trd::CellInfo *)J->sc.cellinfo;
   H.sph32 = (const TR_GLOBAL vf4 *)J->sc.sph32;
   H.cylA32 = (const TR_GLOBAL vf4 *)J->sc.cylA32;
   H.cylW32 = (const TR_GLOBAL vf4 *)J->sc.cylW32;
@@ -194,13 +202,17 @@ __device__ __forceinline__ T ldg(const TR_GLOBAL T *base, uint32_t i) {
 
 __device__ __forceinline__ void load_cell(Ray &R, const SceneHot &S) {
   // res <= 512 per axis: the products fit the 24-bit multiplier
-  const uint32_t cell = __umul24(__umul24((uint32_t)R.cz, (uint32_t)S.res[1]) + (uint32_t)R.cy,
-                                 (uint32_t)S.res[0]) + (uint32_t)R.cx;
-  const vu2 be = ldg(S.cellinfo, cell);
-  R.rc = be.x;
-  R.re = be.y;
-  const int32_t v = (int32_t)ldg(S.refs, be.x);  // in bounds: refs carries 64 padding entries
-  R.nk = be.x < be.y ? v : -1;
+  const uint32_t cell = mad24(mad24((uint32_t)R.cz, (uint32_t)S.res[1], (uint32_t)R.cy),
+                              (uint32_t)S.res[0], (uint32_t)R.cx);
+  // one 12-byte load: extent and first reference (-1 for an empty cell)
+  uint32_t c3;  // 3 * cell by shift-add (the compiler would fold it into a slow 32-bit multiply)
+  asm volatile("v_lshl_add_u32 %0, %1, 1, %1" : "=v"(c3) : "v"(cell));
+  const uint32_t off = c3 << 2;
+  const TR_GLOBAL uint32_t *ci =
+      (const TR_GLOBAL uint32_t *)((const TR_GLOBAL char *)S.cellinfo + off);
+  R.rc = ci[0];
+  R.re = ci[1];
+  R.nk = (int32_t)ci[2];
 }
 
 // Clip to the grid box and position the walk at the entry cell.
@@ -257,7 +269,7 @@ struct WaveArgs {
   int32_t tile_w, refill_below, cyl_wait, mix;
 };
 
-__device__ __forceinline__ int32_t find_job(const JobDev *jobs, int32_t n, int64_t tile) {
+__device__ __forceinline__ int32_t find_job(const TR_CONST JobDev *jobs, int32_t n, int64_t tile) {
   int32_t lo = 0, hi = n - 1;
   while (lo < hi) {
     const int32_t mid = (lo + hi + 1) >> 1;
@@ -268,7 +280,7 @@ __device__ __forceinline__ int32_t find_job(const JobDev *jobs, int32_t n, int64
 }
 
 template <int BANKS, bool RESOLVE, bool COUNT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ? 5 : 4))) void k_render_wave(const WaveArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 && !COUNT ? 5 : 4))) void k_render_wave(const WaveArgs A) {
   __shared__ Lds<BANKS> L;
   constexpr int NS = BANKS * 64;
   constexpr int kMinIters = 2;
@@ -300,7 +312,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
   int32_t st = kDone;  // kRun, kDone, or kPaused (waiting for an FP64 re-solve of primitive gk)
   int32_t gk = 0;
   int32_t slot = 0, ridx = 0;
-  uint32_t l_pix = 0, l_hit = 0, l_ao = 0, l_shadow = 0;
   Ray R;
   R.bk = -1;
   R.rc = R.re = 0;
@@ -442,7 +453,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
         float cr = B.bg[0], cg = B.bg[1], cb = B.bg[2];
         int32_t hid = -1;
         uint32_t am = 0, lm = 0;
-        ++l_pix;
         if (!fin_prim_miss) {
           const int32_t k = L.prim[slot];
           hid = k;
@@ -465,9 +475,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
           cr = fminf(fmaxf(alb.x * (Dr + sk), 0.0f), 1.0f);
           cg = fminf(fmaxf(alb.y * (Dg + sk), 0.0f), 1.0f);
           cb = fminf(fmaxf(alb.z * (Db + sk), 0.0f), 1.0f);
-          ++l_hit;
-          l_ao += (uint32_t)B.S;
-          l_shadow += (uint32_t)__popc(lv);
         }
         float *rgb = B.rgb + pid * 3;
         rgb[0] = cr;
@@ -477,6 +484,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
         if (B.ao_mask) B.ao_mask[pid] = am;
         if (B.light_mask) B.light_mask[pid] = (uint8_t)lm;
         atomicAdd(&L.bank[bk].done, 1);
+      }
+      {  // pixel counters live in LDS (registers are the scarce resource here)
+        const uint32_t n_fin = (uint32_t)__popcll(ballot(finalize));
+        const uint32_t n_hit = (uint32_t)__popcll(ballot(finalize && !fin_prim_miss));
+        if (lane == 0) {
+          L.cnt[0] += n_fin;
+          L.cnt[1] += n_hit;
+        }
       }
       if (fin) kind = kIdle;
       __syncthreads();
@@ -511,6 +526,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
           ridx = head_issued + (rank - assigned);
           kind = ridx < S_s ? kAO : kShadow;
         }
+        const int32_t n_ao = max(0, min(S_s - head_issued, take));  // ray indices < S are AO
+        if (lane == 0) {
+          L.cnt[2] += (uint32_t)n_ao;
+          L.cnt[3] += (uint32_t)(take - n_ao);
+        }
         head_issued += take;
         assigned += take;
         if (head_issued == nr) {
@@ -533,7 +553,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
               break;
             }
             held_tile = t;
-            held_job = uni(find_job(A.jobs, A.n_jobs, held_tile));
+            held_job = uni(find_job((const TR_CONST JobDev *)A.jobs, A.n_jobs, held_tile));
             held_key = uni(A.jobs[held_job].scene_key);
           }
           if (held_key != cur_key) {
@@ -541,10 +561,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
             cur_key = held_key;
             scene_job = held_job;
           }
-          const JobDev *J = &A.jobs[held_job];
+          const TR_CONST JobDev *J = (const TR_CONST JobDev *)&A.jobs[held_job];
           const int32_t b = __ffs(free_banks) - 1;
-          const int64_t tl = held_tile - J->queue_begin + J->tile_begin;
-          const int32_t tx = (int32_t)(tl % J->tiles_x), ty = (int32_t)(tl / J->tiles_x);
+          // tile index within its frame (< 2^31: the frame has < 2^31 pixels)
+          const uint32_t tl = (uint32_t)(held_tile - J->queue_begin + J->tile_begin);
+          const uint32_t txs = (uint32_t)J->tiles_x;
+          const int32_t ty = (int32_t)(tl / txs), tx = (int32_t)(tl - (uint32_t)ty * txs);
           const int32_t x0 = tx * TW, y0 = ty * TH;
           const int32_t vw = min(TW, J->W - x0), vh = min(TH, J->H - y0);
           if (lane == 0) {
@@ -731,8 +753,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
           const float sq = sqrtf_fast(fmaxf(disc, 0.0f));
           const float t0 = b - sq, t1 = b + sq;
           const bool ok = disc >= 0.0f && !graze;
-          const bool h0 = ok && t0 > R.tmin && t0 <= R.tmax;
-          const bool h1 = ok && t1 > R.tmin && t1 <= R.tmax;
+          const bool h0 = ok && t0 > R.tmin && t0 <= R.t1;
+          const bool h1 = ok && t1 > R.tmin && t1 <= R.t1;
           hit = h0 || h1;
           t = h0 ? t0 : t1;
         }
@@ -758,8 +780,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
           const float tl = vminf(r0, r1), th = vmaxf(r0, r1);
           const float kL = kKappa * w.w;
           const float sl = Dw + tl * dw, sh = Dw + th * dw;
-          const bool inl = ok && tl > R.tmin && tl <= R.tmax;
-          const bool inh = ok && th > R.tmin && th <= R.tmax;
+          const bool inl = ok && tl > R.tmin && tl <= R.t1;
+          const bool inh = ok && th > R.tmin && th <= R.t1;
           const bool gl = RESOLVE && inl && (fabsf(sl) <= kL || fabsf(sl - w.w) <= kL);
           const bool gh = RESOLVE && inh && (fabsf(sh) <= kL || fabsf(sh - w.w) <= kL);
           const bool hl = inl && !gl && sl >= 0.0f && sl <= w.w;
@@ -847,10 +869,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 ?
 
   // ---- counters
   if (A.stats) {
-    atomicAdd(&L.cnt[0], l_pix);
-    atomicAdd(&L.cnt[1], l_hit);
-    atomicAdd(&L.cnt[2], l_ao);
-    atomicAdd(&L.cnt[3], l_shadow);
     if (COUNT) {
       atomicAdd(&L.cnt[4], l_cells);
       atomicAdd(&L.cnt[5], l_st);

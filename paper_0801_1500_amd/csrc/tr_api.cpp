@@ -61,7 +61,7 @@ struct tr_scene {
   double4 *sph64 = nullptr, *cylA64 = nullptr, *cylW64 = nullptr, *cylB64 = nullptr;
   float4 *sph32 = nullptr, *cylA32 = nullptr, *cylW32 = nullptr, *albedo = nullptr;
   uint32_t *cell_begin = nullptr, *refs = nullptr, *count = nullptr, *scan_scratch = nullptr;
-  uint2 *cellinfo = nullptr;
+  trd::CellInfo *cellinfo = nullptr;
   uint8_t *dist0 = nullptr, *dist1 = nullptr;
   double *bounds_scratch = nullptr, *bounds = nullptr;
   int64_t cap_cells = 0, cap_refs = 0, cap_scan = 0;
@@ -226,8 +226,8 @@ static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
   if (R + 64 > ((int64_t)1 << 30))
     return fail(TR_EUNSUPPORTED, "grid has %lld references (limit 2^30 - 64); lower cells_per_prim",
                 (long long)R);
-  // padding: the FP32 walk reads refs[x] for x <= n_refs (end of a cell) and
-  // for x <= 32 (the distance word of an empty cell) before checking
+  // padding: the FP32 walk reads refs[x] for x <= n_refs (one past the end of
+  // a cell's list) before checking; the rest keeps the buffer 256-byte sized
   const int64_t R_pad = R + 64;
   if (R_pad > s->cap_refs) {
     if (s->refs) (void)hipFree(s->refs);
@@ -240,7 +240,7 @@ static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
   HIP_TRY(trh::launch_fill_u32(s->count, nc, 0u, st));
   HIP_TRY(trh::launch_scatter(a, s->cell_begin, s->count, s->refs, st));
   HIP_TRY(trh::launch_sort_cells(s->cell_begin, nc, s->refs, st));
-  HIP_TRY(trh::launch_cellinfo(s->cell_begin, s->gp.res, s->dist0, s->dist1, s->cellinfo, st));
+  HIP_TRY(trh::launch_cellinfo(s->cell_begin, s->refs, s->gp.res, s->dist0, s->dist1, s->cellinfo, st));
   fill_scene_dev(s);
   return TR_OK;
 }
@@ -385,7 +385,8 @@ extern "C" tr_status tr_scene_rebuild(tr_scene *s, double cells_per_prim, void *
 
 extern "C" tr_status tr_scene_footprint(const tr_scene *s, size_t *bytes) {
   if (!s || !bytes) return fail(TR_EINVAL, "tr_scene_footprint: NULL argument");
-  *bytes = s->bytes_arrays + (size_t)s->cap_cells * 18 + (size_t)s->cap_refs * 4 +
+  *bytes = s->bytes_arrays + (size_t)s->cap_cells * (8 + sizeof(trd::CellInfo) + 2) +
+           (size_t)s->cap_refs * 4 +
            (size_t)s->cap_scan * 4;
   return TR_OK;
 }

@@ -9,13 +9,22 @@
 //   cylA32 float4[n_c], cylW32 float4[n_c]         two 16-byte loads per cylinder
 //   albedo float4[N]     (r, g, b, 0) by global id
 //   cell_begin uint32[n_cells + 1], refs uint32[n_refs + 64]   the uniform grid
-//   cellinfo uint2[n_cells]  (begin, end), or (distance to the nearest occupied
-//                            cell, 0) for empty cells: the FP32 walk's view
+//   cellinfo CellInfo[n_cells] (begin, end, first reference) of an occupied cell,
+//                            or (distance to the nearest occupied cell, 0, ~0)
+//                            of an empty one: the FP32 walk's view, one load
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace trd {
+
+// Traversal record of one grid cell (12 bytes, read with one load).
+struct CellInfo {
+  uint32_t a;  // occupied: first index into refs; empty: Chebyshev distance (>= 1)
+  uint32_t b;  // occupied: one past the last index; empty: 0
+  uint32_t c;  // occupied: refs[a]; empty: 0xFFFFFFFF
+};
+static_assert(sizeof(CellInfo) == 12, "CellInfo is three words");
 
 // ----------------------------------------------------------------- scene
 struct SceneDev {
@@ -24,7 +33,7 @@ struct SceneDev {
   const float4 *sph32, *cylA32, *cylW32;
   const float4 *albedo;
   const uint32_t *cell_begin, *refs;
-  const uint2 *cellinfo;  // (begin, end) or (empty-space distance, 0) per cell
+  const CellInfo *cellinfo;  // per cell: (begin, end, first ref) or (distance, 0, ~0)
   double lo[3], hi[3], h[3], inv[3];
   float lo32[3], hi32[3], h32[3], inv32[3];
   float org32[3];  // -lo * inv, rounded once: FP32 cell coordinate = x * inv32 + org32
