@@ -264,23 +264,36 @@ __global__ void k_dist_pass(const uint8_t *in, uint8_t *out, int32_t rx, int32_t
   out[c] = (uint8_t)best;
 }
 
-// Traversal view of a cell: (begin, end, first reference) of an occupied
-// cell, or (dist, 0, ~0) of an empty one, so one 12-byte load gives the walk
-// the cell's extent and its first unit of work (refs is sorted already).
-__global__ void k_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, const uint8_t *d,
-                           int64_t n_cells, trd::CellInfo *info) {
+// Walk-list sizes: an occupied cell's references plus one end marker (the
+// extra last entry is 0, so the exclusive scan leaves the total there).
+__global__ void k_walk_sizes(const uint32_t *cell_begin, int64_t n_cells, uint32_t *w) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > n_cells) return;
+  const uint32_t n = c < n_cells ? cell_begin[c + 1] - cell_begin[c] : 0u;
+  w[c] = n ? n + 1u : 0u;
+}
+
+// Traversal view of a cell, after the scan of the walk-list sizes: an
+// occupied cell copies its sorted references to its walk list, appends -1,
+// and records (list start, first reference); an empty cell records
+// (-distance, -1).  One 8-byte load gives the walk the cell's first unit of
+// work, and the end marker ends the list without an end index.
+__global__ void k_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, const uint32_t *wbegin,
+                           const uint8_t *d, int64_t n_cells, uint32_t *wrefs,
+                           trd::CellInfo *info) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_cells) return;
   const uint32_t b = cell_begin[c], e = cell_begin[c + 1];
   trd::CellInfo r;
   if (b < e) {
-    r.a = b;
-    r.b = e;
-    r.c = refs[b];
+    const uint32_t w = wbegin[c];
+    for (uint32_t i = 0; i < e - b; ++i) wrefs[w + i] = refs[b + i];
+    wrefs[w + (e - b)] = 0xFFFFFFFFu;
+    r.a = (int32_t)w;
+    r.c = (int32_t)refs[b];
   } else {
-    r.a = max((uint32_t)d[c], 1u);
-    r.b = 0u;
-    r.c = 0xFFFFFFFFu;
+    r.a = -(int32_t)max((uint32_t)d[c], 1u);
+    r.c = -1;
   }
   info[c] = r;
 }
@@ -437,7 +450,8 @@ hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32
 }
 
 hipError_t launch_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, const int32_t res[3],
-                           uint8_t *d0, uint8_t *d1, trd::CellInfo *info, hipStream_t st) {
+                           uint8_t *d0, uint8_t *d1, uint32_t *wsz, uint32_t *scan_scratch,
+                           uint32_t *wrefs, trd::CellInfo *info, hipStream_t st) {
   const int64_t n = (int64_t)res[0] * res[1] * res[2];
   if (n <= 0) return hipSuccess;
   const unsigned nb = blocks_for(n);
@@ -445,7 +459,12 @@ hipError_t launch_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, con
   k_dist_pass<<<nb, kBlock, 0, st>>>(d0, d1, res[0], res[1], res[2], 0);
   k_dist_pass<<<nb, kBlock, 0, st>>>(d1, d0, res[0], res[1], res[2], 1);
   k_dist_pass<<<nb, kBlock, 0, st>>>(d0, d1, res[0], res[1], res[2], 2);
-  k_cellinfo<<<nb, kBlock, 0, st>>>(cell_begin, refs, d1, n, info);
+  k_walk_sizes<<<blocks_for(n + 1), kBlock, 0, st>>>(cell_begin, n, wsz);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_scan(wsz, n + 1, scan_scratch, st);
+  if (e != hipSuccess) return e;
+  k_cellinfo<<<nb, kBlock, 0, st>>>(cell_begin, refs, wsz, d1, n, wrefs, info);
   return hipGetLastError();
 }
 

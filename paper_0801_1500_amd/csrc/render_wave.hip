@@ -142,8 +142,8 @@ struct Ray {
   float hx, hy, hz;
   int32_t cx, cy, cz;
   int32_t sx, sy, sz;  // step signs
-  uint32_t rc, re;     // reference cursor / end in the current cell; (dist, 0) if empty
-  int32_t nk;          // refs[rc] when rc < re, else -1 (loaded one iteration ahead)
+  int32_t rc;          // cursor into the cell's walk list; -(distance) in an empty cell
+  int32_t nk;          // wrefs[rc]: the next reference, -1 at the list end (loaded ahead)
   float bt;            // best t
   int32_t bk;          // best id (-1 = none)
   int32_t skip;
@@ -173,7 +173,7 @@ struct SceneHot {
 __device__ __forceinline__ SceneHot load_hot(const JobDev *Jg) {
   const TR_CONST JobDev *J = (const TR_CONST JobDev *)Jg;
   SceneHot H;
-  H.refs = (const TR_GLOBAL uint32_t *)J->sc.refs;
+  H.refs = (const TR_GLOBAL uint32_t *)J->sc.wrefs;
   H.cellinfo = (const TR_GLOBAL trd::CellInfo *)J->sc.cellinfo;
   H.sph32 = (const TR_GLOBAL vf4 *)J->sc.sph32;
   H.cylA32 = (const TR_GLOBAL vf4 *)J->sc.cylA32;
@@ -204,15 +204,10 @@ __device__ __forceinline__ void load_cell(Ray &R, const SceneHot &S) {
   // res <= 512 per axis: the products fit the 24-bit multiplier
   const uint32_t cell = mad24(mad24((uint32_t)R.cz, (uint32_t)S.res[1], (uint32_t)R.cy),
                               (uint32_t)S.res[0], (uint32_t)R.cx);
-  // one 12-byte load: extent and first reference (-1 for an empty cell)
-  uint32_t c3;  // 3 * cell by shift-add (the compiler would fold it into a slow 32-bit multiply)
-  asm volatile("v_lshl_add_u32 %0, %1, 1, %1" : "=v"(c3) : "v"(cell));
-  const uint32_t off = c3 << 2;
-  const TR_GLOBAL uint32_t *ci =
-      (const TR_GLOBAL uint32_t *)((const TR_GLOBAL char *)S.cellinfo + off);
-  R.rc = ci[0];
-  R.re = ci[1];
-  R.nk = (int32_t)ci[2];
+  // one 8-byte load: list start (or -distance) and first reference (-1 if empty)
+  const vu2 ci = ldg((const TR_GLOBAL vu2 *)S.cellinfo, cell);
+  R.rc = (int32_t)ci.x;
+  R.nk = (int32_t)ci.y;
 }
 
 // Clip to the grid box and position the walk at the entry cell.
@@ -314,7 +309,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
   int32_t slot = 0, ridx = 0;
   Ray R;
   R.bk = -1;
-  R.rc = R.re = 0;
+  R.rc = 0;
   R.nk = -1;
   __syncthreads();
 
@@ -738,11 +733,60 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
         const bool is_sph = go_sph && (uint32_t)nk < (uint32_t)H.n_s;
         const bool is_cyl = go_cyl && nk >= H.n_s;
         const bool is_step = go_step && nk < 0;
+        // Sphere records are fetched first and the step's arithmetic runs
+        // meanwhile (the two lane sets are disjoint), so the load latency hides
+        // behind it; the step's own cell load is issued last, after the tests
+        // have waited for their data, and is consumed next iteration.
+        vf4 sdat;  // (read only where is_sph)
+        if (is_sph) sdat = ldg(H.sph32, (uint32_t)nk);
+        bool enter = false;  // the step moved into a cell inside the grid
+        if (is_step) {
+          // ---- cell exhausted: stop, or leave it.  An empty cell carries the
+          // Chebyshev distance k to the nearest occupied cell, so the whole
+          // cube of half-size k-1 around it is empty and the walk jumps to
+          // where the ray leaves that cube (k = 1: an ordinary DDA step).
+          // Branch-free: the k = 1 step is the jump with a cube of size 0.
+          const int32_t kk = R.rc < 0 ? -R.rc : 1;
+          const int32_t m = kk - 1;
+          // cell just beyond the cube on each axis; its near plane is crossed at
+          // b_a + i * h_a (b_a is shifted one cell for negative steps at setup)
+          const int32_t ix1 = R.cx + __mul24(R.sx, kk);
+          const int32_t iy1 = R.cy + __mul24(R.sy, kk);
+          const int32_t iz1 = R.cz + __mul24(R.sz, kk);
+          const float tx = fmaf((float)ix1, R.hx, R.bx);  // inf when d_x = 0
+          const float ty = fmaf((float)iy1, R.hy, R.by);
+          const float tz = fmaf((float)iz1, R.hz, R.bz);
+          const float tn = fminf(tx, fminf(ty, tz));
+          // stop at the box exit, or when the best hit so far is not beyond the plane
+          if (!(tn < vminf(R.t1, R.bt))) {
+            st = kDone;
+          } else {
+            const bool ax = tx == tn;
+            const bool ay = !ax && ty == tn;
+            const bool az = !ax && !ay;
+            // the other axes land in the cell of the exit point, kept inside the cube
+            const int32_t nx = R.cx + med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], H.org32[0])) - R.cx, -m, m);
+            const int32_t ny = R.cy + med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], H.org32[1])) - R.cy, -m, m);
+            const int32_t nz = R.cz + med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], H.org32[2])) - R.cz, -m, m);
+            if (COUNT && kk > 1) ++l_jumps;
+            R.cx = ax ? ix1 : nx;
+            R.cy = ay ? iy1 : ny;
+            R.cz = az ? iz1 : nz;
+            // (tn < t1 is finite, so the crossed axis has a nonzero step)
+            if ((uint32_t)R.cx >= (uint32_t)H.res[0] ||
+                (uint32_t)R.cy >= (uint32_t)H.res[1] || (uint32_t)R.cz >= (uint32_t)H.res[2]) {
+              st = kDone;
+            } else {
+              if (COUNT) ++l_cells;
+              enter = true;
+            }
+          }
+        }
         bool tested = false, hit = false, graze = false;
         float t = 0.0f;
         if (is_sph) {
           tested = true;
-          const vf4 s = ldg(H.sph32, (uint32_t)nk);
+          const vf4 s = sdat;
           const float qx = s.x - R.ox, qy = s.y - R.oy, qz = s.z - R.oz;
           const float b = qx * R.dx + qy * R.dy + qz * R.dz;
           const float lx = qx - b * R.dx, ly = qy - b * R.dy, lz = qz - b * R.dz;
@@ -805,9 +849,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
             }
             l_res += graze;
           }
-          ++R.rc;
-          const int32_t v = (int32_t)ldg(H.refs, R.rc);  // refs has padding entries
-          R.nk = R.rc < R.re ? v : -1;
           // nearest hit (ties to the lower id); any hit ends a shadow/AO ray
           const bool take = hit && (anyhit || t < R.bt || (t == R.bt && nk < R.bk));
           R.bt = take ? t : R.bt;
@@ -817,49 +858,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
             st = graze ? kPaused : st;
             gk = graze ? nk : gk;
           }
+          // next reference (after the last use of this one, so the load can land
+          // in its register and stay in flight into the next iteration)
+          ++R.rc;
+          R.nk = (int32_t)ldg(H.refs, (uint32_t)R.rc);  // -1 past the cell's last reference
         }
-        if (is_step) {
-          // ---- cell exhausted: stop, or leave it.  An empty cell carries the
-          // Chebyshev distance k to the nearest occupied cell, so the whole
-          // cube of half-size k-1 around it is empty and the walk jumps to
-          // where the ray leaves that cube (k = 1: an ordinary DDA step).
-          // Branch-free: the k = 1 step is the jump with a cube of size 0.
-          const int32_t kk = R.re == 0 ? (int32_t)R.rc : 1;
-          const int32_t m = kk - 1;
-          // cell just beyond the cube on each axis; its near plane is crossed at
-          // b_a + i * h_a (b_a is shifted one cell for negative steps at setup)
-          const int32_t ix1 = R.cx + __mul24(R.sx, kk);
-          const int32_t iy1 = R.cy + __mul24(R.sy, kk);
-          const int32_t iz1 = R.cz + __mul24(R.sz, kk);
-          const float tx = fmaf((float)ix1, R.hx, R.bx);  // inf when d_x = 0
-          const float ty = fmaf((float)iy1, R.hy, R.by);
-          const float tz = fmaf((float)iz1, R.hz, R.bz);
-          const float tn = fminf(tx, fminf(ty, tz));
-          // stop at the box exit, or when the best hit so far is not beyond the plane
-          if (!(tn < vminf(R.t1, R.bt))) {
-            st = kDone;
-          } else {
-            const bool ax = tx == tn;
-            const bool ay = !ax && ty == tn;
-            const bool az = !ax && !ay;
-            // the other axes land in the cell of the exit point, kept inside the cube
-            const int32_t nx = R.cx + med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], H.org32[0])) - R.cx, -m, m);
-            const int32_t ny = R.cy + med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], H.org32[1])) - R.cy, -m, m);
-            const int32_t nz = R.cz + med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], H.org32[2])) - R.cz, -m, m);
-            if (COUNT && kk > 1) ++l_jumps;
-            R.cx = ax ? ix1 : nx;
-            R.cy = ay ? iy1 : ny;
-            R.cz = az ? iz1 : nz;
-            // (tn < t1 is finite, so the crossed axis has a nonzero step)
-            if ((uint32_t)R.cx >= (uint32_t)H.res[0] ||
-                (uint32_t)R.cy >= (uint32_t)H.res[1] || (uint32_t)R.cz >= (uint32_t)H.res[2]) {
-              st = kDone;
-            } else {
-              if (COUNT) ++l_cells;
-              load_cell(R, H);
-            }
-          }
-        }
+        if (enter) load_cell(R, H);
         }  // work
       }
       (void)anyhit;

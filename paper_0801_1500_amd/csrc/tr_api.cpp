@@ -61,10 +61,11 @@ struct tr_scene {
   double4 *sph64 = nullptr, *cylA64 = nullptr, *cylW64 = nullptr, *cylB64 = nullptr;
   float4 *sph32 = nullptr, *cylA32 = nullptr, *cylW32 = nullptr, *albedo = nullptr;
   uint32_t *cell_begin = nullptr, *refs = nullptr, *count = nullptr, *scan_scratch = nullptr;
+  uint32_t *wrefs = nullptr;  // FP32 walk lists: per occupied cell its references, then -1
   trd::CellInfo *cellinfo = nullptr;
   uint8_t *dist0 = nullptr, *dist1 = nullptr;
   double *bounds_scratch = nullptr, *bounds = nullptr;
-  int64_t cap_cells = 0, cap_refs = 0, cap_scan = 0;
+  int64_t cap_cells = 0, cap_refs = 0, cap_scan = 0, cap_wrefs = 0;
   size_t bytes_arrays = 0;
   // pinned readback
   double *h_bounds = nullptr;
@@ -81,7 +82,7 @@ static std::mutex g_mu;
 static void free_scene_arrays(tr_scene *s) {
   void *ptrs[] = {s->sph64, s->cylA64, s->cylW64, s->cylB64, s->sph32,       s->cylA32,
                   s->cylW32, s->albedo, s->cell_begin, s->refs, s->count, s->scan_scratch,
-                  s->bounds_scratch, s->bounds, s->cellinfo, s->dist0, s->dist1};
+                  s->bounds_scratch, s->bounds, s->cellinfo, s->dist0, s->dist1, s->wrefs};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_bounds) (void)hipHostFree(s->h_bounds);
@@ -140,6 +141,7 @@ static void fill_scene_dev(tr_scene *s) {
   d.albedo = s->albedo;
   d.cell_begin = s->cell_begin;
   d.refs = s->refs;
+  d.wrefs = s->wrefs;
   d.cellinfo = s->cellinfo;
   for (int a = 0; a < 3; ++a) {
     d.lo[a] = s->gp.lo[a];
@@ -222,25 +224,31 @@ static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(s->h_total, s->cell_begin + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const int64_t R = (int64_t)*s->h_total;
-  // references are addressed with 32-bit byte offsets by the traversal
-  if (R + 64 > ((int64_t)1 << 30))
-    return fail(TR_EUNSUPPORTED, "grid has %lld references (limit 2^30 - 64); lower cells_per_prim",
-                (long long)R);
-  // padding: the FP32 walk reads refs[x] for x <= n_refs (one past the end of
-  // a cell's list) before checking; the rest keeps the buffer 256-byte sized
-  const int64_t R_pad = R + 64;
-  if (R_pad > s->cap_refs) {
+  // walk lists (references plus one end marker per occupied cell) are
+  // addressed with 32-bit byte offsets by the traversal
+  const int64_t W = R + nc + 1;  // bound on the walk-list total
+  if (W > ((int64_t)1 << 30))
+    return fail(TR_EUNSUPPORTED,
+                "grid has %lld references and %lld cells (limit 2^30 together); lower cells_per_prim",
+                (long long)R, (long long)nc);
+  if (R > s->cap_refs) {
     if (s->refs) (void)hipFree(s->refs);
     s->refs = nullptr;
-    HIP_TRY(dmalloc(&s->refs, R_pad));
-    s->cap_refs = R_pad;
+    HIP_TRY(dmalloc(&s->refs, R));
+    s->cap_refs = R;
   }
-  HIP_TRY(trh::launch_fill_u32(s->refs + R, 64, 0u, st));
+  if (W > s->cap_wrefs) {
+    if (s->wrefs) (void)hipFree(s->wrefs);
+    s->wrefs = nullptr;
+    HIP_TRY(dmalloc(&s->wrefs, W));
+    s->cap_wrefs = W;
+  }
   s->n_refs = R;
   HIP_TRY(trh::launch_fill_u32(s->count, nc, 0u, st));
   HIP_TRY(trh::launch_scatter(a, s->cell_begin, s->count, s->refs, st));
   HIP_TRY(trh::launch_sort_cells(s->cell_begin, nc, s->refs, st));
-  HIP_TRY(trh::launch_cellinfo(s->cell_begin, s->refs, s->gp.res, s->dist0, s->dist1, s->cellinfo, st));
+  HIP_TRY(trh::launch_cellinfo(s->cell_begin, s->refs, s->gp.res, s->dist0, s->dist1, s->count,
+                               s->scan_scratch, s->wrefs, s->cellinfo, st));
   fill_scene_dev(s);
   return TR_OK;
 }
@@ -386,7 +394,7 @@ extern "C" tr_status tr_scene_rebuild(tr_scene *s, double cells_per_prim, void *
 extern "C" tr_status tr_scene_footprint(const tr_scene *s, size_t *bytes) {
   if (!s || !bytes) return fail(TR_EINVAL, "tr_scene_footprint: NULL argument");
   *bytes = s->bytes_arrays + (size_t)s->cap_cells * (8 + sizeof(trd::CellInfo) + 2) +
-           (size_t)s->cap_refs * 4 +
+           (size_t)s->cap_refs * 4 + (size_t)s->cap_wrefs * 4 +
            (size_t)s->cap_scan * 4;
   return TR_OK;
 }

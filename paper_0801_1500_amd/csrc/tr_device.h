@@ -9,22 +9,24 @@
 //   cylA32 float4[n_c], cylW32 float4[n_c]         two 16-byte loads per cylinder
 //   albedo float4[N]     (r, g, b, 0) by global id
 //   cell_begin uint32[n_cells + 1], refs uint32[n_refs + 64]   the uniform grid
-//   cellinfo CellInfo[n_cells] (begin, end, first reference) of an occupied cell,
-//                            or (distance to the nearest occupied cell, 0, ~0)
-//                            of an empty one: the FP32 walk's view, one load
+//   cellinfo CellInfo[n_cells] (list start, first reference) of an occupied cell,
+//                            or (-distance to the nearest occupied cell, -1) of an
+//                            empty one: the FP32 walk's view, one load
+//   wrefs uint32[n_refs + occupied cells]  per occupied cell its references then -1
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace trd {
 
-// Traversal record of one grid cell (12 bytes, read with one load).
+// Traversal record of one grid cell (8 bytes, read with one load).  The FP32
+// walk reads an occupied cell's references from its own list in wrefs: the
+// cell's sorted references followed by -1, so the walk needs no end index.
 struct CellInfo {
-  uint32_t a;  // occupied: first index into refs; empty: Chebyshev distance (>= 1)
-  uint32_t b;  // occupied: one past the last index; empty: 0
-  uint32_t c;  // occupied: refs[a]; empty: 0xFFFFFFFF
+  int32_t a;  // occupied: index of the cell's list in wrefs; empty: -(Chebyshev distance)
+  int32_t c;  // occupied: the list's first reference; empty: -1
 };
-static_assert(sizeof(CellInfo) == 12, "CellInfo is three words");
+static_assert(sizeof(CellInfo) == 8, "CellInfo is two words");
 
 // ----------------------------------------------------------------- scene
 struct SceneDev {
@@ -33,7 +35,8 @@ struct SceneDev {
   const float4 *sph32, *cylA32, *cylW32;
   const float4 *albedo;
   const uint32_t *cell_begin, *refs;
-  const CellInfo *cellinfo;  // per cell: (begin, end, first ref) or (distance, 0, ~0)
+  const uint32_t *wrefs;  // walk lists (see CellInfo)
+  const CellInfo *cellinfo;  // per cell: (list start, first ref) or (-distance, -1)
   double lo[3], hi[3], h[3], inv[3];
   float lo32[3], hi32[3], h32[3], inv32[3];
   float org32[3];  // -lo * inv, rounded once: FP32 cell coordinate = x * inv32 + org32
