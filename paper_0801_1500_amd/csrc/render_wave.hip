@@ -746,7 +746,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
           // cube of half-size k-1 around it is empty and the walk jumps to
           // where the ray leaves that cube (k = 1: an ordinary DDA step).
           // Branch-free: the k = 1 step is the jump with a cube of size 0.
-          const int32_t kk = R.rc < 0 ? -R.rc : 1;
+          const int32_t kk = max(-R.rc, 1);  // rc = -distance in an empty cell, >= 0 otherwise
           const int32_t m = kk - 1;
           // cell just beyond the cube on each axis; its near plane is crossed at
           // b_a + i * h_a (b_a is shifted one cell for negative steps at setup)
@@ -797,10 +797,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
           const float sq = sqrtf_fast(fmaxf(disc, 0.0f));
           const float t0 = b - sq, t1 = b + sq;
           const bool ok = disc >= 0.0f && !graze;
-          const bool h0 = ok && t0 > R.tmin && t0 <= R.t1;
-          const bool h1 = ok && t1 > R.tmin && t1 <= R.t1;
-          hit = h0 || h1;
-          t = h0 ? t0 : t1;
+          // nearer root if it is past tmin, else the farther (t0 <= t1)
+          t = t0 > R.tmin ? t0 : t1;
+          hit = ok && t > R.tmin && t <= R.t1;
         }
         if (is_cyl) {
           tested = true;
