@@ -101,16 +101,20 @@ __global__ void k_pack(int64_t n_s, int64_t n_c, const double *sc, const double 
   }
 }
 
+// FP32 copies for the wavefront walk, with positions relative to the centre of
+// the grid box (the FP32 frame: the smallest magnitudes, so the least rounding,
+// wherever the scene sits).
 __global__ void k_pack32(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
-                         const double4 *cylW64, float4 *sph32, float4 *cylA32, float4 *cylW32) {
+                         const double4 *cylW64, double ox, double oy, double oz, float4 *sph32,
+                         float4 *cylA32, float4 *cylW32) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n_s) {
     const double4 s = sph64[k];
-    sph32[k] = make_float4((float)s.x, (float)s.y, (float)s.z, (float)s.w);
+    sph32[k] = make_float4((float)(s.x - ox), (float)(s.y - oy), (float)(s.z - oz), (float)s.w);
   } else if (k < n_s + n_c) {
     const int64_t m = k - n_s;
     const double4 a = cylA64[m], w = cylW64[m];
-    cylA32[m] = make_float4((float)a.x, (float)a.y, (float)a.z, (float)a.w);
+    cylA32[m] = make_float4((float)(a.x - ox), (float)(a.y - oy), (float)(a.z - oz), (float)a.w);
     cylW32[m] = make_float4((float)w.x, (float)w.y, (float)w.z, (float)w.w);
   }
 }
@@ -367,12 +371,12 @@ hipError_t launch_pack(int64_t n_s, int64_t n_c, const double *sc, const double 
 }
 
 hipError_t launch_pack32(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
-                         const double4 *cylW64, float4 *sph32, float4 *cylA32, float4 *cylW32,
-                         hipStream_t st) {
+                         const double4 *cylW64, const double origin[3], float4 *sph32,
+                         float4 *cylA32, float4 *cylW32, hipStream_t st) {
   const int64_t N = n_s + n_c;
   if (N == 0) return hipSuccess;
-  k_pack32<<<blocks_for(N), kBlock, 0, st>>>(n_s, n_c, sph64, cylA64, cylW64, sph32, cylA32,
-                                             cylW32);
+  k_pack32<<<blocks_for(N), kBlock, 0, st>>>(n_s, n_c, sph64, cylA64, cylW64, origin[0], origin[1],
+                                             origin[2], sph32, cylA32, cylW32);
   return hipGetLastError();
 }
 

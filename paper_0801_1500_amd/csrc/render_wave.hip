@@ -164,7 +164,7 @@ struct SceneHot {
   int32_t n_s;
   int32_t res[3];
   float lo32[3], hi32[3], inv32[3], h32[3];
-  float org32[3];  // -lo * inv: cell coordinate of x is floor(x * inv + org)
+  float org32[3];  // cell coordinate of the FP32 frame's origin
 };
 
 // The job table is read-only for the whole launch, so it is read through the
@@ -325,10 +325,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
           int32_t px, py;
           bank_pixel(L.bank[bk], slot & 63, px, py);
           primary_ray_f64(*J, px, py, o, d);
-        } else {
-          o[0] = R.ox;
-          o[1] = R.oy;
-          o[2] = R.oz;
+        } else {  // the FP32 origin, back from the FP32 frame
+          o[0] = (double)R.ox + S.org[0];
+          o[1] = (double)R.oy + S.org[1];
+          o[2] = (double)R.oz + S.org[2];
           const double v[3] = {(double)R.dx, (double)R.dy, (double)R.dz};
           const double n = sqrt(dot3d(v, v));
           d[0] = v[0] / n;

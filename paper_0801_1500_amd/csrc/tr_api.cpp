@@ -73,6 +73,7 @@ struct tr_scene {
   trh::GridParams gp{};
   int64_t n_refs = 0;
   bool grid_ok = false;  // false after a failed (re)build: the scene cannot render
+  double org[3] = {0, 0, 0};  // origin of the FP32 frame: centre of the grid box
   SceneDev dev{};
 };
 
@@ -148,11 +149,14 @@ static void fill_scene_dev(tr_scene *s) {
     d.hi[a] = s->gp.hi[a];
     d.h[a] = s->gp.h[a];
     d.inv[a] = s->gp.inv[a];
-    d.lo32[a] = (float)s->gp.lo[a];
-    d.hi32[a] = (float)s->gp.hi[a];
+    // FP32 frame: positions relative to the box centre org (the FP32
+    // primitive copies, the FP32 eye and every FP32 point of the walk)
+    d.org[a] = s->org[a];
+    d.lo32[a] = (float)(s->gp.lo[a] - s->org[a]);
+    d.hi32[a] = (float)(s->gp.hi[a] - s->org[a]);
+    d.org32[a] = (float)((s->org[a] - s->gp.lo[a]) * s->gp.inv[a]);  // cell coordinate of 0
     d.h32[a] = (float)s->gp.h[a];
     d.inv32[a] = (float)s->gp.inv[a];
-    d.org32[a] = (float)(-s->gp.lo[a] * s->gp.inv[a]);
     d.res[a] = s->gp.res[a];
   }
 }
@@ -161,8 +165,6 @@ static void fill_scene_dev(tr_scene *s) {
 // FP64 arrays.  Two blocking readbacks (bounds, reference total).
 static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
   const int64_t N = s->n_s + s->n_c;
-  HIP_TRY(trh::launch_pack32(s->n_s, s->n_c, s->sph64, s->cylA64, s->cylW64, s->sph32, s->cylA32,
-                             s->cylW32, st));
   if (N == 0) {
     double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
     for (int a = 0; a < 3; ++a) {
@@ -181,6 +183,9 @@ static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
     HIP_TRY(hipStreamSynchronize(st));
     grid_params(s->h_bounds, s->h_bounds + 3, N, s->lambda, s->gp);
   }
+  for (int a = 0; a < 3; ++a) s->org[a] = 0.5 * (s->gp.lo[a] + s->gp.hi[a]);
+  HIP_TRY(trh::launch_pack32(s->n_s, s->n_c, s->sph64, s->cylA64, s->cylW64, s->org, s->sph32,
+                             s->cylA32, s->cylW32, st));
   const int64_t nc = s->gp.n_cells;
   if (nc + 1 > s->cap_cells) {
     if (s->cell_begin) (void)hipFree(s->cell_begin);
@@ -513,7 +518,7 @@ static tr_status make_job(const tr_scene *s, const tr_camera *c, const tr_params
   J.aspect = (double)c->width / (double)c->height;
   for (int a = 0; a < 3; ++a) {
     J.eye[a] = c->eye[a];
-    J.eye32[a] = (float)c->eye[a];
+    J.eye32[a] = (float)(c->eye[a] - s->org[a]);  // FP32 frame (relative to the box centre)
     J.f32[a] = (float)J.f[a];
     J.r32[a] = (float)J.r[a];
     J.u32[a] = (float)J.u[a];

@@ -7,6 +7,8 @@
 //   cylB64 double4[n_c]  (bx, by, bz, 0)           second end point (grid rebuild)
 //   sph32  float4[n_s]   rounded copies for the FP32 traversal: one 16-byte load per sphere
 //   cylA32 float4[n_c], cylW32 float4[n_c]         two 16-byte loads per cylinder
+//                        (FP32 positions are relative to org, the centre of the grid
+//                        box: lo32 = lo - org, hi32 = hi - org, eye32 = eye - org)
 //   albedo float4[N]     (r, g, b, 0) by global id
 //   cell_begin uint32[n_cells + 1], refs uint32[n_refs + 64]   the uniform grid
 //   cellinfo CellInfo[n_cells] (list start, first reference) of an occupied cell,
@@ -38,8 +40,9 @@ struct SceneDev {
   const uint32_t *wrefs;  // walk lists (see CellInfo)
   const CellInfo *cellinfo;  // per cell: (list start, first ref) or (-distance, -1)
   double lo[3], hi[3], h[3], inv[3];
+  double org[3];  // origin of the FP32 frame (centre of the grid box)
   float lo32[3], hi32[3], h32[3], inv32[3];
-  float org32[3];  // -lo * inv, rounded once: FP32 cell coordinate = x * inv32 + org32
+  float org32[3];  // (org - lo) * inv: FP32 cell coordinate of x is floor(x * inv32 + org32)
   int32_t res[3];
 };
 

@@ -30,9 +30,10 @@ hipError_t launch_pack(int64_t n_s, int64_t n_c, const double *sc, const double 
                        const float *srgb, const double *ca, const double *cb, const double *cr,
                        const float *crgb, double4 *sph64, double4 *cylA64, double4 *cylW64,
                        double4 *cylB64, float4 *albedo, hipStream_t st);
+// FP32 copies with positions relative to origin (the centre of the grid box)
 hipError_t launch_pack32(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
-                         const double4 *cylW64, float4 *sph32, float4 *cylA32, float4 *cylW32,
-                         hipStream_t st);
+                         const double4 *cylW64, const double origin[3], float4 *sph32,
+                         float4 *cylA32, float4 *cylW32, hipStream_t st);
 // bounds: out6 = (lo xyz, hi xyz); scratch >= bounds_scratch_doubles(N) doubles
 int64_t bounds_scratch_doubles(int64_t n_prims);
 hipError_t launch_bounds(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
