@@ -79,7 +79,7 @@ typedef struct {
   int32_t n_lights;          /* 0..8 directional lights                     */
   const double *light_dir;   /* [n_lights*3] toward the light; normalised by the library */
   const double *light_rgb;   /* [n_lights*3] intensity                      */
-  double cells_per_prim;     /* grid density lambda; 0 => 16.  Speed only.  */
+  double cells_per_prim;     /* grid density lambda; 0 => 24.  Speed only.  */
 } tr_scene_desc;
 
 /* Pinhole camera, one ray through each pixel centre.  width = horizontal

@@ -56,7 +56,7 @@ struct tr_scene {
   int32_t n_lights = 0;
   double ldir[8][3] = {};
   double lrgb[8][3] = {};
-  double lambda = 16.0;
+  double lambda = 24.0;
   // device arrays
   double4 *sph64 = nullptr, *cylA64 = nullptr, *cylW64 = nullptr, *cylB64 = nullptr;
   float4 *sph32 = nullptr, *cylA32 = nullptr, *cylW32 = nullptr, *albedo = nullptr;
@@ -308,7 +308,7 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   s->n_s = d->n_spheres;
   s->n_c = d->n_cylinders;
   s->n_lights = d->n_lights;
-  s->lambda = d->cells_per_prim > 0.0 ? d->cells_per_prim : 16.0;
+  s->lambda = d->cells_per_prim > 0.0 ? d->cells_per_prim : 24.0;
   for (int l = 0; l < d->n_lights; ++l) {
     const double *v = d->light_dir + 3 * l;
     const double n = std::sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
