@@ -51,6 +51,8 @@ struct BankInfo {
   uint32_t key0, key1, view;
   float maxd, sky;
   float eye[3], f[3], r[3], u[3], th, aspect;  // FP32 camera
+  float rw2, rh2;       // 2 / W, 2 / H
+  float rS;             // 1 / S (0 when S = 0)
   float bg[3];
   float *rgb;
   int32_t *hit_id;
@@ -214,30 +216,20 @@ __device__ __forceinline__ void load_cell(Ray &R, const SceneHot &S) {
 // Returns false when the ray misses the box.
 __device__ __forceinline__ bool ray_setup(Ray &R, const SceneHot &S) {
   const float ix = rcpf(R.dx), iy = rcpf(R.dy), iz = rcpf(R.dz);
-  float t0 = R.tmin, t1 = R.tmax;
-  {
-    const float a = (S.lo32[0] - R.ox) * ix, b = (S.hi32[0] - R.ox) * ix;
-    t0 = fmaxf(t0, fminf(a, b));
-    t1 = fminf(t1, fmaxf(a, b));
-  }
-  {
-    const float a = (S.lo32[1] - R.oy) * iy, b = (S.hi32[1] - R.oy) * iy;
-    t0 = fmaxf(t0, fminf(a, b));
-    t1 = fminf(t1, fmaxf(a, b));
-  }
-  {
-    const float a = (S.lo32[2] - R.oz) * iz, b = (S.hi32[2] - R.oz) * iz;
-    t0 = fmaxf(t0, fminf(a, b));
-    t1 = fminf(t1, fmaxf(a, b));
-  }
+  // slab times of the box's lower and upper planes on each axis
+  const float ax = (S.lo32[0] - R.ox) * ix, bx = (S.hi32[0] - R.ox) * ix;
+  const float ay = (S.lo32[1] - R.oy) * iy, by = (S.hi32[1] - R.oy) * iy;
+  const float az = (S.lo32[2] - R.oz) * iz, bz = (S.hi32[2] - R.oz) * iz;
+  const float t0 = fmaxf(R.tmin, fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz)));
+  const float t1 = fminf(R.tmax, fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz)));
   R.t1 = t1;
   R.bt = INFINITY;
   R.bk = -1;
   if (!(t0 <= t1)) return false;
-  const float ex = R.ox + t0 * R.dx, ey = R.oy + t0 * R.dy, ez = R.oz + t0 * R.dz;
-  R.cx = min(max((int32_t)floorf((ex - S.lo32[0]) * S.inv32[0]), 0), S.res[0] - 1);
-  R.cy = min(max((int32_t)floorf((ey - S.lo32[1]) * S.inv32[1]), 0), S.res[1] - 1);
-  R.cz = min(max((int32_t)floorf((ez - S.lo32[2]) * S.inv32[2]), 0), S.res[2] - 1);
+  const float ex = fmaf(t0, R.dx, R.ox), ey = fmaf(t0, R.dy, R.oy), ez = fmaf(t0, R.dz, R.oz);
+  R.cx = min(max(cvt_floor((ex - S.lo32[0]) * S.inv32[0]), 0), S.res[0] - 1);
+  R.cy = min(max(cvt_floor((ey - S.lo32[1]) * S.inv32[1]), 0), S.res[1] - 1);
+  R.cz = min(max(cvt_floor((ez - S.lo32[2]) * S.inv32[2]), 0), S.res[2] - 1);
   R.sx = R.dx > 0.0f ? 1 : (R.dx < 0.0f ? -1 : 0);
   R.sy = R.dy > 0.0f ? 1 : (R.dy < 0.0f ? -1 : 0);
   R.sz = R.dz > 0.0f ? 1 : (R.dz < 0.0f ? -1 : 0);
@@ -245,12 +237,12 @@ __device__ __forceinline__ bool ray_setup(Ray &R, const SceneHot &S) {
   // b_a + i * h_a, with b_a taken one cell up for negative steps (the plane
   // between cells i and i + 1).  An axis with d_a = 0 gets b_a = inf, h_a = 0:
   // its plane is never the next one.
-  R.bx = R.sx > 0 ? (S.lo32[0] - R.ox) * ix : (R.sx < 0 ? (S.lo32[0] + S.h32[0] - R.ox) * ix : INFINITY);
-  R.by = R.sy > 0 ? (S.lo32[1] - R.oy) * iy : (R.sy < 0 ? (S.lo32[1] + S.h32[1] - R.oy) * iy : INFINITY);
-  R.bz = R.sz > 0 ? (S.lo32[2] - R.oz) * iz : (R.sz < 0 ? (S.lo32[2] + S.h32[2] - R.oz) * iz : INFINITY);
   R.hx = R.sx ? S.h32[0] * ix : 0.0f;
   R.hy = R.sy ? S.h32[1] * iy : 0.0f;
   R.hz = R.sz ? S.h32[2] * iz : 0.0f;
+  R.bx = R.sx > 0 ? ax : (R.sx < 0 ? ax + R.hx : INFINITY);
+  R.by = R.sy > 0 ? ay : (R.sy < 0 ? ay + R.hy : INFINITY);
+  R.bz = R.sz > 0 ? az : (R.sz < 0 ? az + R.hz : INFINITY);
   load_cell(R, S);
   return true;
 }
@@ -464,7 +456,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
             Db += B.lcol[l][2] * cl;
           }
           float ao = 1.0f;
-          if (B.S > 0) ao = (float)(B.S - L.aocnt[slot]) / (float)B.S;
+          if (B.S > 0) ao = (float)(B.S - L.aocnt[slot]) * B.rS;
           const vf4 alb = ldg(S.albedo, (uint32_t)k);
           const float sk = B.sky * ao;
           cr = fminf(fmaxf(alb.x * (Dr + sk), 0.0f), 1.0f);
@@ -577,6 +569,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
             B.H = J->H;
             B.th = J->th32;
             B.aspect = J->aspect32;
+            B.rw2 = 2.0f / (float)J->W;
+            B.rS = J->S > 0 ? 1.0f / (float)J->S : 0.0f;
+            B.rh2 = 2.0f / (float)J->H;
             B.rgb = J->rgb;
             B.hit_id = J->hit_id;
             B.ao_mask = J->ao_mask;
@@ -626,8 +621,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
           int32_t pi, pj;
           bank_pixel(B, slot & 63, pi, pj);
           if (kind == kPrimary) {
-            const float x = ((2.0f * ((float)pi + 0.5f)) / (float)B.W - 1.0f) * B.th * B.aspect;
-            const float y = (1.0f - (2.0f * ((float)pj + 0.5f)) / (float)B.H) * B.th;
+            const float x = fmaf((float)pi + 0.5f, B.rw2, -1.0f) * B.th * B.aspect;
+            const float y = fmaf(-((float)pj + 0.5f), B.rh2, 1.0f) * B.th;
             const float vx = B.f[0] + x * B.r[0] + y * B.u[0];
             const float vy = B.f[1] + x * B.r[1] + y * B.u[1];
             const float vz = B.f[2] + x * B.r[2] + y * B.u[2];

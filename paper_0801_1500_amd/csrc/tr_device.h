@@ -125,7 +125,7 @@ __device__ __forceinline__ void ao_dir_f32(float nx, float ny, float nz, uint32_
   const float ly = rr * __builtin_amdgcn_sinf(u2);
   const float lz = __builtin_sqrtf(1.0f - u1);
   const float sg = __builtin_copysignf(1.0f, nz);
-  const float a = -1.0f / (sg + nz);
+  const float a = -__builtin_amdgcn_rcpf(sg + nz);  // |sg + nz| is in [1, 2]
   const float b = nx * ny * a;
   const float tx = 1.0f + sg * nx * nx * a, ty = sg * b, tz = -sg * nx;
   const float bx = b, by = sg + ny * ny * a, bz = -ny;
