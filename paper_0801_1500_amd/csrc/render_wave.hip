@@ -62,10 +62,17 @@ struct BankInfo {
   float lcol[8][3];
 };
 
+// Bank record of a lane's slot (bank index < BANKS): the byte offset by the
+// 24-bit multiplier (the compiler would use a slow 32-bit multiply).
+template <int BANKS>
+__device__ __forceinline__ BankInfo &bank_of(BankInfo (&bank)[BANKS], int32_t bk) {
+  return *(BankInfo *)((char *)bank + __umul24((uint32_t)bk, (uint32_t)sizeof(BankInfo)));
+}
+
 // Pixel of slot offset q (0..63) in a bank's tile: row-major over vw columns.
 __device__ __forceinline__ void bank_pixel(const BankInfo &B, int32_t q, int32_t &x, int32_t &y) {
   const int32_t qy = (int32_t)(__umul24((uint32_t)q, (uint32_t)B.vmagic) >> 16);
-  x = B.x0 + q - qy * B.vw;
+  x = B.x0 + q - (int32_t)__umul24((uint32_t)qy, (uint32_t)B.vw);
   y = B.y0 + qy;
 }
 
@@ -310,12 +317,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
     if (RESOLVE && ballot(st == kPaused)) {
       if (st == kPaused) {
         const int32_t bk = slot >> 6;
-        const JobDev *J = &A.jobs[L.bank[bk].job];
+        const JobDev *J = &A.jobs[bank_of(L.bank, bk).job];
         const SceneDev &S = J->sc;
         double o[3], d[3];
         if (kind == kPrimary) {
           int32_t px, py;
-          bank_pixel(L.bank[bk], slot & 63, px, py);
+          bank_pixel(bank_of(L.bank, bk), slot & 63, px, py);
           primary_ray_f64(*J, px, py, o, d);
         } else {  // the FP32 origin, back from the FP32 frame
           o[0] = (double)R.ox + S.org[0];
@@ -390,12 +397,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
           Nz = -Nz;
         }
         uint32_t lv = 0;
-        const int32_t nl = L.bank[bk].n_lights;
+        const BankInfo &Bk = bank_of(L.bank, bk);
+        const int32_t nl = Bk.n_lights;
         for (int l = 0; l < nl; ++l) {
-          const float cl = Nx * L.bank[bk].ldir[l][0] + Ny * L.bank[bk].ldir[l][1] + Nz * L.bank[bk].ldir[l][2];
+          const float cl = Nx * Bk.ldir[l][0] + Ny * Bk.ldir[l][1] + Nz * Bk.ldir[l][2];
           if (cl > 0.0f) lv |= 1u << l;
         }
-        nr = (uint32_t)L.bank[bk].S + (uint32_t)__popc(lv);
+        nr = (uint32_t)Bk.S + (uint32_t)__popc(lv);
         L.px[slot] = Px;
         L.py[slot] = Py;
         L.pz[slot] = Pz;
@@ -433,7 +441,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
       __syncthreads();
       if (finalize) {
         const int32_t bk = slot >> 6;
-        const BankInfo &B = L.bank[bk];
+        BankInfo &B = bank_of(L.bank, bk);
         int32_t x, y;
         bank_pixel(B, slot & 63, x, y);
         const int64_t pid = (int64_t)y * B.W + x;
@@ -470,12 +478,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
         if (B.hit_id) B.hit_id[pid] = hid;
         if (B.ao_mask) B.ao_mask[pid] = am;
         if (B.light_mask) B.light_mask[pid] = (uint8_t)lm;
-        atomicAdd(&L.bank[bk].done, 1);
+        atomicAdd(&B.done, 1);
       }
       {  // pixel counters live in LDS (registers are the scarce resource here)
         const uint32_t n_fin = (uint32_t)__popcll(ballot(finalize));
         const uint32_t n_hit = (uint32_t)__popcll(ballot(finalize && !fin_prim_miss));
-        if (lane == 0) {
+        if (A.stats && lane == 0) {
           L.cnt[0] += n_fin;
           L.cnt[1] += n_hit;
         }
@@ -503,6 +511,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
       int32_t assigned = 0;
       // pass 1 -- assignment only: secondary rays from the FIFO, then fresh
       // primary rays; each idle lane learns (kind, slot, ray index)
+      int32_t n_ao = 0;  // AO rays among the secondary rays issued this round
       while (assigned < n_idle && q_head != q_tail) {
         const int32_t s = uni((int32_t)L.fifo[q_head % NS]);
         const int32_t nr = uni(L.nrays[s]);
@@ -513,17 +522,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
           ridx = head_issued + (rank - assigned);
           kind = ridx < S_s ? kAO : kShadow;
         }
-        const int32_t n_ao = max(0, min(S_s - head_issued, take));  // ray indices < S are AO
-        if (lane == 0) {
-          L.cnt[2] += (uint32_t)n_ao;
-          L.cnt[3] += (uint32_t)(take - n_ao);
-        }
+        n_ao += max(0, min(S_s - head_issued, take));  // ray indices < S are AO
         head_issued += take;
         assigned += take;
         if (head_issued == nr) {
           ++q_head;
           head_issued = 0;
         }
+      }
+      if (A.stats && lane == 0 && assigned > 0) {  // ray counters live in LDS
+        L.cnt[2] += (uint32_t)n_ao;
+        L.cnt[3] += (uint32_t)(assigned - n_ao);
       }
       while (assigned < n_idle) {
         if (issue_bank < 0 || issue_next == uni(L.bank[issue_bank].n)) {
@@ -617,7 +626,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
         const bool fresh = me_idle && kind != kIdle;
         if (fresh) {
           const SceneHot H = load_hot(&A.jobs[uni(scene_job)]);
-          const BankInfo &B = L.bank[slot >> 6];
+          const BankInfo &B = bank_of(L.bank, slot >> 6);
           int32_t pi, pj;
           bank_pixel(B, slot & 63, pi, pj);
           if (kind == kPrimary) {

@@ -120,10 +120,11 @@ __device__ __forceinline__ void ao_dir_f32(float nx, float ny, float nz, uint32_
                                            float &wx, float &wy, float &wz) {
   const float u1 = (float)b1 * (1.0f / 16777216.0f);
   const float u2 = (float)b2 * (1.0f / 16777216.0f);
-  const float rr = __builtin_sqrtf(u1);
+  // hardware square roots (about 1 ulp; the arguments are >= 2^-24 or 0)
+  const float rr = __builtin_amdgcn_sqrtf(u1);
   const float lx = rr * __builtin_amdgcn_cosf(u2);
   const float ly = rr * __builtin_amdgcn_sinf(u2);
-  const float lz = __builtin_sqrtf(1.0f - u1);
+  const float lz = __builtin_amdgcn_sqrtf(1.0f - u1);
   const float sg = __builtin_copysignf(1.0f, nz);
   const float a = -__builtin_amdgcn_rcpf(sg + nz);  // |sg + nz| is in [1, 2]
   const float b = nx * ny * a;
