@@ -188,6 +188,16 @@ tr_status tr_scene_grid_info(const tr_scene *scene, double lo[3], double hi[3], 
 tr_status tr_scene_grid_arrays(const tr_scene *scene, uint32_t *cell_begin, uint32_t *refs,
                                void *hip_stream);
 
+/* Copy the FP32 walk's view of the grid to HOST buffers (either may be NULL):
+ * cellinfo [2 * n_cells], per cell (start of its list in wrefs, the list's
+ * first reference), or (-distance to the nearest occupied cell, -1) for an
+ * empty cell, the distance Chebyshev in cells, capped at 32; and wrefs
+ * [*n_walk], per occupied cell in cell order its references in ascending id
+ * then 0xFFFFFFFF.  *n_walk (required) receives the wrefs length.  Derived
+ * from the canonical grid of tr_scene_grid_arrays; synchronises the stream. */
+tr_status tr_scene_walk_arrays(const tr_scene *scene, int32_t *cellinfo, uint32_t *wrefs,
+                               int64_t *n_walk, void *hip_stream);
+
 /* Free the scene's device memory.  The caller guarantees no enqueued work
  * still uses it (the call synchronises the device before freeing). */
 void tr_scene_destroy(tr_scene *scene);

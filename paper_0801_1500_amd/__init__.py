@@ -90,6 +90,7 @@ def lib():
         "tr_scene_footprint": ([vp, C.POINTER(C.c_size_t)], st),
         "tr_scene_grid_info": ([vp, vp, vp, vp, C.POINTER(i64)], st),
         "tr_scene_grid_arrays": ([vp, vp, vp, vp], st),
+        "tr_scene_walk_arrays": ([vp, vp, vp, C.POINTER(i64), vp], st),
         "tr_scene_destroy": ([vp], None),
         "tr_render": ([vp, C.POINTER(Camera), C.POINTER(Params), C.POINTER(Frame), vp], st),
         "tr_render_tuned": ([vp, C.POINTER(Camera), C.POINTER(Params), C.POINTER(Frame),
@@ -208,6 +209,18 @@ class Scene:
         _check(lib().tr_scene_grid_arrays(self.handle, cb.ctypes.data, refs.ctypes.data,
                                           _stream(stream)))
         return cb, refs[:n_refs]
+
+    def walk_arrays(self, stream=None):
+        """(cellinfo [n_cells, 2], wrefs) of the FP32 walk (see tr.h)."""
+        lo, hi, res, n_refs = self.grid_info()
+        n_cells = int(res[0]) * int(res[1]) * int(res[2])
+        n = C.c_int64(0)
+        _check(lib().tr_scene_walk_arrays(self.handle, None, None, C.byref(n), _stream(stream)))
+        ci = np.zeros((n_cells, 2), dtype=np.int32)
+        wr = np.zeros(max(n.value, 1), dtype=np.uint32)
+        _check(lib().tr_scene_walk_arrays(self.handle, ci.ctypes.data, wr.ctypes.data, C.byref(n),
+                                          _stream(stream)))
+        return ci, wr[:n.value]
 
     def destroy(self):
         if getattr(self, "handle", None):

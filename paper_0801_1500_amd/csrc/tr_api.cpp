@@ -429,6 +429,25 @@ extern "C" tr_status tr_scene_grid_arrays(const tr_scene *s, uint32_t *cell_begi
   return TR_OK;
 }
 
+extern "C" tr_status tr_scene_walk_arrays(const tr_scene *s, int32_t *cellinfo, uint32_t *wrefs,
+                                          int64_t *n_walk, void *hip_stream) {
+  if (!s || !n_walk) return fail(TR_EINVAL, "tr_scene_walk_arrays: NULL scene or n_walk");
+  if (!s->grid_ok) return fail(TR_EINVAL, "scene grid is invalid (its last rebuild failed)");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t nc = s->gp.n_cells;
+  // the walk-list total is the last entry of the scanned sizes (kept in count)
+  HIP_TRY(hipMemcpyAsync(s->h_total, s->count + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *n_walk = (int64_t)*s->h_total;
+  if (cellinfo)
+    HIP_TRY(hipMemcpyAsync(cellinfo, s->cellinfo, (size_t)nc * sizeof(trd::CellInfo),
+                           hipMemcpyDeviceToHost, st));
+  if (wrefs && *n_walk > 0)
+    HIP_TRY(hipMemcpyAsync(wrefs, s->wrefs, (size_t)*n_walk * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return TR_OK;
+}
+
 extern "C" void tr_scene_destroy(tr_scene *s) {
   if (!s) return;
   (void)hipDeviceSynchronize();

@@ -82,3 +82,24 @@ def flat_at(fr: dict, pix: np.ndarray) -> dict:
             a = fr[k]
             out[k] = a.reshape(-1, 3)[pix] if k == "rgb" else a.reshape(-1)[pix]
     return out
+
+
+def chebyshev_capped(occ, cap=32):
+    """Chebyshev distance (in cells) from each cell to the nearest occupied
+    one, capped at cap: grow the occupied set one 26-neighbourhood shell at a
+    time (plain definition, no separable passes)."""
+    dist = np.where(occ, 0, cap).astype(np.int32)
+    cur = occ.copy()
+    for k in range(1, cap):
+        if cur.all():
+            break
+        grown = cur.copy()
+        p = np.pad(cur, 1)
+        nz, ny, nx = cur.shape
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    grown |= p[1 + dz:1 + dz + nz, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+        dist[grown & ~cur] = k
+        cur = grown
+    return dist

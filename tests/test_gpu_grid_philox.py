@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import scenegen
+from parity_util import chebyshev_capped
 
 pytestmark = pytest.mark.gpu
 
@@ -41,6 +42,39 @@ def test_grid_equals_oracle(tr, oracle_mod, which, lam):
     ocb, orefs = og.arrays()
     assert np.array_equal(cb, ocb)
     assert np.array_equal(refs, orefs)
+
+
+@pytest.mark.parametrize("which,lam", [("tiny", 4.0), ("protein", 4.0), ("protein", 24.0),
+                                       ("cyl", 3.0)])
+def test_walk_view_matches_grid(tr, which, lam):
+    # The FP32 walk's cell records and per-cell lists (with end markers),
+    # rebuilt here from the canonical grid and the empty-space distance.
+    scene = {"tiny": lambda: scenegen.tiny_scene(1), "protein": scenegen.protein_scene,
+             "cyl": _bare_cylinders}[which]()
+    print("walk view case", which, lam, flush=True)
+    gs = tr.Scene(scene, cells_per_prim=lam)
+    lo, hi, res, n_refs = gs.grid_info()
+    cb, refs = gs.grid_arrays()
+    ci, wr = gs.walk_arrays()
+    cnt = np.diff(cb.astype(np.int64))
+    occ = cnt > 0
+    dist = chebyshev_capped(occ.reshape(res[2], res[1], res[0])).ravel()
+    assert len(wr) == n_refs + int(occ.sum())
+    # empty cells: (-distance, -1)
+    assert np.array_equal(ci[~occ, 0], -np.maximum(dist[~occ], 1))
+    assert np.all(ci[~occ, 1] == -1)
+    # occupied cells: list start (exclusive prefix of list lengths + 1) and first id
+    size = np.where(occ, cnt + 1, 0)
+    start = np.cumsum(size) - size
+    assert np.array_equal(ci[occ, 0], start[occ])
+    assert np.array_equal(ci[occ, 1], refs[cb[:-1][occ]].astype(np.int64))
+    # lists: the canonical references in cell order, each list closed by ~0
+    want = np.empty(len(wr), dtype=np.uint32)
+    end = np.zeros(len(wr), dtype=bool)
+    end[(start + cnt)[occ]] = True
+    want[end] = 0xFFFFFFFF
+    want[~end] = refs
+    assert np.array_equal(wr, want)
 
 
 def test_grid_rebuild_changes_density(tr, oracle_mod):
