@@ -91,6 +91,7 @@ def lib():
                                 i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Counters), i32]
         L.or_render.restype = C.c_int
         L.or_max_threads.restype = C.c_int32
+        L.or_quantize_rgb8.argtypes = [i64, vp, vp]
         _lib = L
     return _lib
 
@@ -258,6 +259,14 @@ def render(scene, cam, params, grid=None, pix: Optional[np.ndarray] = None,
         out["rgb"] = out["rgb"].reshape(H, W, 3)
         for key in ("hit_id", "ao_mask", "ao_occluded", "light_mask", "t"):
             out[key] = out[key].reshape(H, W)
+    return out
+
+
+def quantize_rgb8(values: np.ndarray) -> np.ndarray:
+    """8-bit output of float values: floor(clamp(v, 0, 1) * 255 + 1/2), NaN -> 0."""
+    v = np.ascontiguousarray(values, dtype=np.float32)
+    out = np.empty(v.shape, dtype=np.uint8)
+    lib().or_quantize_rgb8(v.size, v.ctypes.data, out.ctypes.data)
     return out
 
 

@@ -667,3 +667,16 @@ int32_t or_max_threads(void) {
   return 1;
 #endif
 }
+
+/* 8-bit output of a frame.  The paper writes its frames as images (the
+ * "Image I/O" phase, Table 5) without stating the conversion; the reading
+ * here: clamp to [0, 1], scale by 255, round half up.  In double the product
+ * of a float and 255 is exact, so the rounding is exact too. */
+void or_quantize_rgb8(int64_t n, const float *in, uint8_t *out) {
+  for (int64_t i = 0; i < n; ++i) {
+    double v = (double)in[i];
+    if (!(v > 0.0)) v = 0.0; /* also NaN */
+    if (v > 1.0) v = 1.0;
+    out[i] = (uint8_t)floor(v * 255.0 + 0.5);
+  }
+}

@@ -116,6 +116,11 @@ int or_render(const or_scene *s, const or_camera *cam, const or_params *p, const
 
 int32_t or_max_threads(void);
 
+/* 8-bit output of a frame (the "Image I/O" phase, Table 5): each value v
+ * becomes floor(min(max(v, 0), 1) * 255 + 1/2) evaluated exactly (in double,
+ * where v * 255 of a float is exact), NaN becoming 0. */
+void or_quantize_rgb8(int64_t n, const float *in, uint8_t *out);
+
 #ifdef __cplusplus
 }
 #endif
