@@ -125,6 +125,39 @@ def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
             "rays_per_s": rays / (ms * 1e-3)}
 
 
+def frame_output_measure(tr, torch, frame, reps: int = 20) -> dict:
+    """8-bit output of the 17.6 MP frame on the GPU (tr_frame_quantize: 12 B
+    read + 3 B written per pixel, HBM-bound), its asynchronous download to
+    pinned host memory, and the host PPM encoding."""
+    rgb = frame["rgb"]
+    q = tr.quantize_rgb8(rgb)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        tr.quantize_rgb8(rgb, out=q)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = rgb.numel() * 4 + q.numel()
+    host = torch.empty(q.shape, dtype=torch.uint8, pin_memory=True)
+    host, ev = tr.frame_to_host_rgb8(frame, host=host)
+    ev.synchronize()
+    d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    d0.record()
+    host.copy_(q, non_blocking=True)
+    d1.record()
+    torch.cuda.synchronize()
+    d2h_ms = d0.elapsed_time(d1)
+    t0 = time.perf_counter()
+    ppm = tr.encode_ppm(host)
+    enc_ms = (time.perf_counter() - t0) * 1e3
+    return {"quantize_ms": ms, "quantize_GBps": nbytes / (ms * 1e-3) / 1e9,
+            "quantize_hbm_frac": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "bytes": nbytes, "d2h_ms": d2h_ms, "d2h_GBps": q.numel() / (d2h_ms * 1e-3) / 1e9,
+            "ppm_encode_ms": enc_ms, "ppm_bytes": len(ppm)}
+
+
 def serving_measure(tr, torch, scenegen, seconds: float, rate: float = 50.0) -> dict:
     """Poisson arrivals (mean `rate` per second) of render jobs over a pool
     of 16 resident walk scenes of 2k-200k objects, resolutions uniform over
@@ -256,6 +289,9 @@ def main():
         del f64
         log("fp64 plain path", fp64)
 
+    frame_out = frame_output_measure(tr, torch, frame)
+    log("frame output", frame_out)
+
     orbit = None
     if not args.no_orbit:
         log("orbit (1M objects, 64 views per graph launch) ...")
@@ -291,6 +327,7 @@ def main():
         "hit_pixels": st["hit_pixels"], "op_counts": st,
         "render_only_rays_per_s": rays_frame / (render_ms.mean() * 1e-3),
         "fp64_plain": fp64,
+        "frame_output": frame_out,
         "orbit": orbit,
         "serving": serving,
         "roofline": roofline,

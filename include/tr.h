@@ -248,6 +248,18 @@ tr_status tr_render_batch_tiles(int32_t n, const tr_scene *const *scenes, const 
  * 0 on invalid arguments. */
 size_t tr_frame_footprint(const tr_camera *cam, const tr_params *params, uint32_t frame_flags);
 
+/* ---------------------------------------------------------- frame output */
+
+/* 8-bit output of a rendered frame, on the GPU (the "Image I/O" phase of
+ * Table 5, whose conversion the paper does not state): out[i] =
+ * floor(min(max(values[i], 0), 1) * 255 + 1/2), computed exactly, NaN -> 0.
+ * values: n device floats (a frame's rgb is n = 3 * W * H, row-major
+ * [H][W][3]); out: n device bytes, same order (an 8-bit RGB image).  Any
+ * alignment (16-byte aligned values and 4-byte aligned out take the
+ * vectorised path).  Enqueued on the stream; the caller owns both buffers.
+ * TR_EINVAL on n < 0 or a NULL pointer with n > 0; n = 0 does nothing. */
+tr_status tr_frame_quantize(const float *values, int64_t n, uint8_t *out, void *hip_stream);
+
 /* ------------------------------------------------ graphs (batched views) */
 
 /* A captured, replayable batch render: the tile-counter reset and the

@@ -91,6 +91,7 @@ def lib():
         "tr_scene_grid_info": ([vp, vp, vp, vp, C.POINTER(i64)], st),
         "tr_scene_grid_arrays": ([vp, vp, vp, vp], st),
         "tr_scene_walk_arrays": ([vp, vp, vp, C.POINTER(i64), vp], st),
+        "tr_frame_quantize": ([vp, i64, vp, vp], st),
         "tr_scene_destroy": ([vp], None),
         "tr_render": ([vp, C.POINTER(Camera), C.POINTER(Params), C.POINTER(Frame), vp], st),
         "tr_render_tuned": ([vp, C.POINTER(Camera), C.POINTER(Params), C.POINTER(Frame),
@@ -255,6 +256,47 @@ def alloc_frame(cam, outputs: Sequence[str] = ("rgb",), stats: bool = False, dev
 def frame_struct(frame: dict) -> Frame:
     g = lambda k: frame[k].data_ptr() if frame.get(k) is not None else None
     return Frame(g("rgb"), g("hit_id"), g("ao_mask"), g("light_mask"), g("stats"))
+
+
+def quantize_rgb8(values, out=None, stream=None):
+    """8-bit image of float values on the GPU (tr_frame_quantize):
+    floor(clamp(v, 0, 1) * 255 + 1/2), NaN -> 0.  values: a CUDA float32
+    tensor (e.g. a frame's rgb [H, W, 3]); returns a uint8 tensor of the same
+    shape (out, if given, must be one)."""
+    torch = _torch()
+    if values.dtype != torch.float32 or not values.is_cuda:
+        raise TypeError("values must be a CUDA float32 tensor")
+    v = values.contiguous()
+    if out is None:
+        out = torch.empty(v.shape, dtype=torch.uint8, device=v.device)
+    elif out.dtype != torch.uint8 or out.numel() != v.numel() or not out.is_contiguous():
+        raise ValueError("out must be a contiguous uint8 tensor of values' size")
+    _check(lib().tr_frame_quantize(v.data_ptr(), v.numel(), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def frame_to_host_rgb8(frame: dict, host=None, stream=None):
+    """Quantise frame["rgb"] on the GPU and start its copy into pinned host
+    memory (asynchronous on the stream).  Returns (host uint8 [H, W, 3],
+    event): wait on the event before reading host."""
+    torch = _torch()
+    dev = quantize_rgb8(frame["rgb"], stream=stream)
+    if host is None:
+        host = torch.empty(dev.shape, dtype=torch.uint8, pin_memory=True)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(s):
+        host.copy_(dev, non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record(s)
+    return host, ev
+
+
+def encode_ppm(rgb8) -> bytes:
+    """Binary PPM (P6) of an 8-bit RGB image [H, W, 3] in host memory."""
+    a = rgb8.numpy() if hasattr(rgb8, "numpy") else np.asarray(rgb8)
+    if a.dtype != np.uint8 or a.ndim != 3 or a.shape[2] != 3:
+        raise ValueError("rgb8 must be uint8 [H, W, 3]")
+    return b"P6\n%d %d\n255\n" % (a.shape[1], a.shape[0]) + np.ascontiguousarray(a).tobytes()
 
 
 def render_into(scene: Scene, cam, params, frame: dict, precision="fp32_resolve", tune=None,

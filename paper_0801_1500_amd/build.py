@@ -23,6 +23,7 @@ SOURCES = {
     "grid_build.hip": ["-ffp-contract=off"],
     "render_plain.hip": ["-ffp-contract=off"],
     "render_wave.hip": ["-ffp-contract=fast"],
+    "frame_out.hip": ["-ffp-contract=off"],
     "tr_api.cpp": ["-ffp-contract=off", "-x", "hip"],
 }
 

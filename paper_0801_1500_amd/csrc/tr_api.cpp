@@ -801,6 +801,15 @@ extern "C" tr_status tr_render_batch_tiles(int32_t n, const tr_scene *const *sce
                     (hipStream_t)hip_stream);
 }
 
+extern "C" tr_status tr_frame_quantize(const float *values, int64_t n, uint8_t *out,
+                                       void *hip_stream) {
+  if (n < 0) return fail(TR_EINVAL, "tr_frame_quantize: n < 0");
+  if (n == 0) return TR_OK;
+  if (!values || !out) return fail(TR_EINVAL, "tr_frame_quantize: NULL buffer");
+  HIP_TRY(trh::launch_quantize_rgb8(values, n, out, (hipStream_t)hip_stream));
+  return TR_OK;
+}
+
 extern "C" size_t tr_frame_footprint(const tr_camera *c, const tr_params *p, uint32_t flags) {
   if (!c || c->width <= 0 || c->height <= 0) return 0;
   (void)p;

@@ -54,6 +54,10 @@ hipError_t launch_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, con
 hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32_t *refs,
                              hipStream_t st);
 
+// ---- frame output (frame_out.hip) ----
+// values -> bytes, floor(clamp(v, 0, 1) * 255 + 1/2); any alignment
+hipError_t launch_quantize_rgb8(const float *in, int64_t n, uint8_t *out, hipStream_t st);
+
 // ---- render launchers ----
 hipError_t launch_render_plain_f64(const trd::JobDev &job, uint64_t *stats, hipStream_t st);
 
