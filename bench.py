@@ -125,6 +125,32 @@ def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
             "rays_per_s": rays / (ms * 1e-3)}
 
 
+def scene_ingest_measure(tr, torch, scene, name: str) -> dict:
+    """Scene ingest (the "Parse" + "Preprocess" phases of Table 5): build from
+    in-memory arrays, save as a binary scene file, and load it back (read +
+    upload + GPU grid build), each timed to completion."""
+    import tempfile
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gs = tr.Scene(scene)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "scene.trs")
+        t0 = time.perf_counter()
+        gs.save(path)
+        save_ms = (time.perf_counter() - t0) * 1e3
+        nbytes = os.path.getsize(path)
+        t0 = time.perf_counter()
+        gl = tr.Scene.load(path)
+        torch.cuda.synchronize()
+        load_ms = (time.perf_counter() - t0) * 1e3
+    del gs, gl
+    return {"scene": name, "objects": scene.n_prims, "file_bytes": nbytes,
+            "build_from_arrays_ms": build_ms, "save_ms": save_ms, "load_ms": load_ms,
+            "load_MBps": nbytes / (load_ms * 1e-3) / 1e6}
+
+
 def frame_output_measure(tr, torch, frame, reps: int = 20) -> dict:
     """8-bit output of the 17.6 MP frame on the GPU (tr_frame_quantize: 12 B
     read + 3 B written per pixel, HBM-bound), its asynchronous download to
@@ -291,6 +317,11 @@ def main():
 
     frame_out = frame_output_measure(tr, torch, frame)
     log("frame output", frame_out)
+    ingest = [scene_ingest_measure(tr, torch, scene, "protein-like 26,318 objects")]
+    if not args.no_orbit:
+        ingest.append(scene_ingest_measure(tr, torch, scenegen.orbit_scene(),
+                                           "1,000,000-object walk"))
+    log("scene ingest", ingest)
 
     orbit = None
     if not args.no_orbit:
@@ -328,6 +359,7 @@ def main():
         "render_only_rays_per_s": rays_frame / (render_ms.mean() * 1e-3),
         "fp64_plain": fp64,
         "frame_output": frame_out,
+        "scene_ingest": ingest,
         "orbit": orbit,
         "serving": serving,
         "roofline": roofline,

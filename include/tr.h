@@ -188,6 +188,22 @@ tr_status tr_scene_grid_info(const tr_scene *scene, double lo[3], double hi[3], 
 tr_status tr_scene_grid_arrays(const tr_scene *scene, uint32_t *cell_begin, uint32_t *refs,
                                void *hip_stream);
 
+/* Binary scene files (the "Parse" phase of Table 5, for which the paper gives
+ * no format).  Little-endian: char magic[8] = "TRSCENE1"; int64 n_spheres,
+ * n_cylinders; int32 n_lights, int32 0; double cells_per_prim; then the
+ * arrays of tr_scene_desc in its order (sph_center, sph_radius, sph_rgb,
+ * cyl_a, cyl_b, cyl_radius, cyl_rgb, light_dir, light_rgb), each padded to a
+ * multiple of 8 bytes.
+ * tr_scene_save writes the description the scene was built from (the FP64
+ * arrays, albedo, the lights as given, the grid density); synchronises the
+ * stream; TR_EINVAL on a NULL argument or a failed write.
+ * tr_scene_load reads a file and builds it with tr_scene_build (same scene as
+ * building that description directly); TR_EINVAL on a NULL argument, an
+ * unreadable file, a bad magic, bad counts or a size that does not match the
+ * counts, and tr_scene_build's errors otherwise. */
+tr_status tr_scene_save(const tr_scene *scene, const char *path, void *hip_stream);
+tr_status tr_scene_load(const char *path, void *hip_stream, tr_scene **out);
+
 /* Copy the FP32 walk's view of the grid to HOST buffers (either may be NULL):
  * cellinfo [2 * n_cells], per cell (start of its list in wrefs, the list's
  * first reference), or (-distance to the nearest occupied cell, -1) for an

@@ -92,6 +92,8 @@ def lib():
         "tr_scene_grid_arrays": ([vp, vp, vp, vp], st),
         "tr_scene_walk_arrays": ([vp, vp, vp, C.POINTER(i64), vp], st),
         "tr_frame_quantize": ([vp, i64, vp, vp], st),
+        "tr_scene_save": ([vp, C.c_char_p, vp], st),
+        "tr_scene_load": ([C.c_char_p, vp, C.POINTER(vp)], st),
         "tr_scene_destroy": ([vp], None),
         "tr_render": ([vp, C.POINTER(Camera), C.POINTER(Params), C.POINTER(Frame), vp], st),
         "tr_render_tuned": ([vp, C.POINTER(Camera), C.POINTER(Params), C.POINTER(Frame),
@@ -186,6 +188,23 @@ class Scene:
     @property
     def n_prims(self):
         return self.n_spheres + self.n_cylinders
+
+    def save(self, path: str, stream=None):
+        """Write the scene as a binary scene file (tr_scene_save)."""
+        _check(lib().tr_scene_save(self.handle, os.fsencode(path), _stream(stream)))
+
+    @classmethod
+    def load(cls, path: str, stream=None) -> "Scene":
+        """Build a scene from a binary scene file (tr_scene_load)."""
+        import struct
+        with open(path, "rb") as f:
+            head = f.read(40)
+        h = C.c_void_p()
+        _check(lib().tr_scene_load(os.fsencode(path), _stream(stream), C.byref(h)))
+        self = cls.__new__(cls)
+        self.handle = h
+        self.n_spheres, self.n_cylinders, self.n_lights = struct.unpack_from("<qqi", head, 8)
+        return self
 
     def rebuild(self, cells_per_prim: float = 0.0, stream=None):
         _check(lib().tr_scene_rebuild(self.handle, float(cells_per_prim), _stream(stream)))

@@ -55,6 +55,7 @@ struct tr_scene {
   int64_t n_s = 0, n_c = 0;
   int32_t n_lights = 0;
   double ldir[8][3] = {};
+  double ldir_in[8][3] = {};  // light directions as given (saved by tr_scene_save)
   double lrgb[8][3] = {};
   double lambda = 24.0;
   // device arrays
@@ -311,6 +312,7 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   s->lambda = d->cells_per_prim > 0.0 ? d->cells_per_prim : 24.0;
   for (int l = 0; l < d->n_lights; ++l) {
     const double *v = d->light_dir + 3 * l;
+    for (int a = 0; a < 3; ++a) s->ldir_in[l][a] = v[a];
     const double n = std::sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
     for (int a = 0; a < 3; ++a) {
       s->ldir[l][a] = v[a] / n;
@@ -427,6 +429,128 @@ extern "C" tr_status tr_scene_grid_arrays(const tr_scene *s, uint32_t *cell_begi
     HIP_TRY(hipMemcpyAsync(refs, s->refs, (size_t)s->n_refs * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return TR_OK;
+}
+
+// ---------------------------------------------------------- scene files
+// Binary scene file, little-endian (the "Parse" phase of Table 5 without a
+// text format): char magic[8] = "TRSCENE1"; int64 n_spheres, n_cylinders;
+// int32 n_lights, int32 0; double cells_per_prim; then the arrays of
+// tr_scene_desc in its order, each padded to 8 bytes.
+static const char kSceneMagic[8] = {'T', 'R', 'S', 'C', 'E', 'N', 'E', '1'};
+
+static int64_t pad8(int64_t b) { return (b + 7) & ~(int64_t)7; }
+
+static int64_t scene_file_bytes(int64_t ns, int64_t nc, int64_t nl) {
+  return 40 + pad8(24 * ns) + pad8(8 * ns) + pad8(12 * ns) + pad8(24 * nc) + pad8(24 * nc) +
+         pad8(8 * nc) + pad8(12 * nc) + 2 * pad8(24 * nl);
+}
+
+extern "C" tr_status tr_scene_save(const tr_scene *s, const char *path, void *hip_stream) {
+  if (!s || !path) return fail(TR_EINVAL, "tr_scene_save: NULL scene or path");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t ns = s->n_s, nc = s->n_c, nl = s->n_lights, N = ns + nc;
+  std::vector<double4> sph(ns), ca(nc), cb(nc);
+  std::vector<float4> alb(N);
+  if (ns) HIP_TRY(hipMemcpyAsync(sph.data(), s->sph64, ns * sizeof(double4), hipMemcpyDeviceToHost, st));
+  if (nc) HIP_TRY(hipMemcpyAsync(ca.data(), s->cylA64, nc * sizeof(double4), hipMemcpyDeviceToHost, st));
+  if (nc) HIP_TRY(hipMemcpyAsync(cb.data(), s->cylB64, nc * sizeof(double4), hipMemcpyDeviceToHost, st));
+  if (N) HIP_TRY(hipMemcpyAsync(alb.data(), s->albedo, N * sizeof(float4), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<char> buf((size_t)scene_file_bytes(ns, nc, nl), 0);
+  char *p = buf.data();
+  std::memcpy(p, kSceneMagic, 8);
+  std::memcpy(p + 8, &ns, 8);
+  std::memcpy(p + 16, &nc, 8);
+  const int32_t nl32 = (int32_t)nl, zero = 0;
+  std::memcpy(p + 24, &nl32, 4);
+  std::memcpy(p + 28, &zero, 4);
+  std::memcpy(p + 32, &s->lambda, 8);
+  int64_t o = 40;
+  auto put_d = [&](int64_t n, auto get) {
+    for (int64_t i = 0; i < n; ++i) {
+      const double v = get(i);
+      std::memcpy(p + o + 8 * i, &v, 8);
+    }
+    o += pad8(8 * n);
+  };
+  auto put_f = [&](int64_t n, auto get) {
+    for (int64_t i = 0; i < n; ++i) {
+      const float v = get(i);
+      std::memcpy(p + o + 4 * i, &v, 4);
+    }
+    o += pad8(4 * n);
+  };
+  auto comp = [](const double4 &v, int64_t a) { return a == 0 ? v.x : (a == 1 ? v.y : v.z); };
+  auto compf = [](const float4 &v, int64_t a) { return a == 0 ? v.x : (a == 1 ? v.y : v.z); };
+  put_d(3 * ns, [&](int64_t i) { return comp(sph[i / 3], i % 3); });
+  put_d(ns, [&](int64_t i) { return sph[i].w; });
+  put_f(3 * ns, [&](int64_t i) { return compf(alb[i / 3], i % 3); });
+  put_d(3 * nc, [&](int64_t i) { return comp(ca[i / 3], i % 3); });
+  put_d(3 * nc, [&](int64_t i) { return comp(cb[i / 3], i % 3); });
+  put_d(nc, [&](int64_t i) { return ca[i].w; });
+  put_f(3 * nc, [&](int64_t i) { return compf(alb[ns + i / 3], i % 3); });
+  put_d(3 * nl, [&](int64_t i) { return s->ldir_in[i / 3][i % 3]; });
+  put_d(3 * nl, [&](int64_t i) { return s->lrgb[i / 3][i % 3]; });
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(TR_EINVAL, "tr_scene_save: cannot open %s for writing", path);
+  const size_t w = std::fwrite(buf.data(), 1, buf.size(), f);
+  const int c = std::fclose(f);
+  if (w != buf.size() || c != 0) return fail(TR_EINVAL, "tr_scene_save: write to %s failed", path);
+  return TR_OK;
+}
+
+extern "C" tr_status tr_scene_load(const char *path, void *hip_stream, tr_scene **out) {
+  if (!path || !out) return fail(TR_EINVAL, "tr_scene_load: NULL path or out");
+  *out = nullptr;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(TR_EINVAL, "tr_scene_load: cannot open %s", path);
+  std::fseek(f, 0, SEEK_END);
+  const long size = std::ftell(f);
+  std::fseek(f, 0, SEEK_SET);
+  if (size < 40) {
+    std::fclose(f);
+    return fail(TR_EINVAL, "tr_scene_load: %s is not a scene file (too short)", path);
+  }
+  std::vector<double> store(((size_t)size + 7) / 8);  // 8-byte aligned
+  char *p = (char *)store.data();
+  const size_t r = std::fread(p, 1, (size_t)size, f);
+  std::fclose(f);
+  if (r != (size_t)size) return fail(TR_EINVAL, "tr_scene_load: read of %s failed", path);
+  if (std::memcmp(p, kSceneMagic, 8) != 0)
+    return fail(TR_EINVAL, "tr_scene_load: %s is not a scene file (bad magic)", path);
+  int64_t ns, nc;
+  int32_t nl;
+  double lambda;
+  std::memcpy(&ns, p + 8, 8);
+  std::memcpy(&nc, p + 16, 8);
+  std::memcpy(&nl, p + 24, 4);
+  std::memcpy(&lambda, p + 32, 8);
+  if (ns < 0 || nc < 0 || ns >= ((int64_t)1 << 28) || nc >= ((int64_t)1 << 28) || nl < 0 || nl > 8)
+    return fail(TR_EINVAL, "tr_scene_load: %s has bad counts", path);
+  if (scene_file_bytes(ns, nc, nl) != (int64_t)size)
+    return fail(TR_EINVAL, "tr_scene_load: %s has %ld bytes, its counts need %lld", path, size,
+                (long long)scene_file_bytes(ns, nc, nl));
+  int64_t o = 40;
+  auto take = [&](int64_t bytes) {
+    const char *q = p + o;
+    o += pad8(bytes);
+    return q;
+  };
+  tr_scene_desc d{};
+  d.n_spheres = ns;
+  d.sph_center = (const double *)take(24 * ns);
+  d.sph_radius = (const double *)take(8 * ns);
+  d.sph_rgb = (const float *)take(12 * ns);
+  d.n_cylinders = nc;
+  d.cyl_a = (const double *)take(24 * nc);
+  d.cyl_b = (const double *)take(24 * nc);
+  d.cyl_radius = (const double *)take(8 * nc);
+  d.cyl_rgb = (const float *)take(12 * nc);
+  d.n_lights = nl;
+  d.light_dir = (const double *)take(24 * nl);
+  d.light_rgb = (const double *)take(24 * nl);
+  d.cells_per_prim = lambda;
+  return tr_scene_build(&d, hip_stream, out);
 }
 
 extern "C" tr_status tr_scene_walk_arrays(const tr_scene *s, int32_t *cellinfo, uint32_t *wrefs,

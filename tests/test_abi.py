@@ -117,3 +117,30 @@ def test_render_validation_rejects(tr):
 def test_default_tune(tr):
     t = tr.default_tune()
     assert t["tile_w"] in (4, 8, 16, 32) and t["banks"] in (2, 3)
+
+
+def test_scene_load_rejects_bad_files(tr, tmp_path):
+    # every check runs before any device call
+    import struct
+    L = tr.lib()
+    h = C.c_void_p()
+    assert L.tr_scene_load(None, None, C.byref(h)) == tr.TR_EINVAL
+    assert L.tr_scene_load(str(tmp_path / "missing.bin").encode(), None, C.byref(h)) == tr.TR_EINVAL
+    short = tmp_path / "short.bin"
+    short.write_bytes(b"TRSCENE1" + b"\0" * 8)
+    assert L.tr_scene_load(str(short).encode(), None, C.byref(h)) == tr.TR_EINVAL
+    assert b"too short" in L.tr_last_error()
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NOTASCN1" + b"\0" * 32)
+    assert L.tr_scene_load(str(bad).encode(), None, C.byref(h)) == tr.TR_EINVAL
+    assert b"bad magic" in L.tr_last_error()
+    # counts that need more bytes than the file has
+    trunc = tmp_path / "trunc.bin"
+    trunc.write_bytes(b"TRSCENE1" + struct.pack("<qqiid", 5, 0, 1, 0, 0.0) + b"\0" * 16)
+    assert L.tr_scene_load(str(trunc).encode(), None, C.byref(h)) == tr.TR_EINVAL
+    assert b"its counts need" in L.tr_last_error()
+    neg = tmp_path / "neg.bin"
+    neg.write_bytes(b"TRSCENE1" + struct.pack("<qqiid", -1, 0, 0, 0, 0.0))
+    assert L.tr_scene_load(str(neg).encode(), None, C.byref(h)) == tr.TR_EINVAL
+    assert b"bad counts" in L.tr_last_error()
+    assert not h.value
