@@ -217,19 +217,55 @@ __global__ void k_scatter(trh::BuildArgs a, const uint32_t *cell_begin, uint32_t
   });
 }
 
-// Insertion sort inside each cell (lists are short).
-__global__ void k_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32_t *refs) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cells) return;
-  const uint32_t b = cell_begin[c], e = cell_begin[c + 1];
-  for (uint32_t i = b + 1; i < e; ++i) {
-    const uint32_t v = refs[i];
-    uint32_t j = i;
-    while (j > b && refs[j - 1] > v) {
-      refs[j] = refs[j - 1];
-      --j;
+// Ascending ids inside each cell (the scatter's atomics leave them in any
+// order).  A block orders the lists of kBlock consecutive cells, whose
+// references are one contiguous range of refs.  The range and the block's cell
+// offsets are staged in LDS with coalesced loads; then every reference, one
+// per thread, finds its cell by binary search over the offsets and goes to
+// the slot given by its rank, the number of smaller ids in the same list (a
+// primitive enters a cell once, so ranks are distinct).  Work per thread is
+// the length of its own list, so the long lists of dense regions do not hold
+// a wave back the way a per-cell sort does.  A block whose range exceeds the
+// stage sorts in place in global memory instead (same result).
+constexpr int kSortStage = 8192;  // refs per block staged in LDS (32 KiB)
+
+__global__ __launch_bounds__(kBlock) void k_sort_cells(const uint32_t *cell_begin, int64_t n_cells,
+                                                       uint32_t *refs) {
+  __shared__ uint32_t stage[kSortStage];
+  __shared__ uint32_t offs[kBlock + 1];
+  const int64_t c0 = (int64_t)blockIdx.x * kBlock;
+  const int64_t c = c0 + threadIdx.x;
+  const int nb = (int)min((int64_t)kBlock, n_cells - c0);  // cells in this block
+  const uint32_t r0 = cell_begin[c0], r1 = cell_begin[c0 + nb];
+  const uint32_t n = r1 - r0;
+  if (n <= (uint32_t)kSortStage) {
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) stage[i] = refs[r0 + i];
+    for (int i = threadIdx.x; i <= nb; i += kBlock) offs[i] = cell_begin[c0 + i] - r0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
+      // last k with offs[k] <= i; offs[0] = 0 <= i < n = offs[nb]
+      int lo = 0, hi = nb;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (offs[mid] <= i) lo = mid; else hi = mid;
+      }
+      const uint32_t b = offs[lo], e = offs[lo + 1];
+      const uint32_t v = stage[i];
+      uint32_t rank = 0;
+      for (uint32_t j = b; j < e; ++j) rank += stage[j] < v ? 1u : 0u;
+      refs[r0 + b + rank] = v;
     }
-    refs[j] = v;
+  } else if (c < n_cells) {
+    const uint32_t b = cell_begin[c], e = cell_begin[c + 1];
+    for (uint32_t i = b + 1; i < e; ++i) {
+      const uint32_t v = refs[i];
+      uint32_t j = i;
+      while (j > b && refs[j - 1] > v) {
+        refs[j] = refs[j - 1];
+        --j;
+      }
+      refs[j] = v;
+    }
   }
 }
 
@@ -449,7 +485,7 @@ hipError_t launch_scatter(const BuildArgs &a, const uint32_t *cell_begin, uint32
 hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32_t *refs,
                              hipStream_t st) {
   if (n_cells <= 0) return hipSuccess;
-  k_sort_cells<<<blocks_for(n_cells), kBlock, 0, st>>>(cell_begin, n_cells, refs);
+  k_sort_cells<<<(unsigned)((n_cells + kBlock - 1) / kBlock), kBlock, 0, st>>>(cell_begin, n_cells, refs);
   return hipGetLastError();
 }
 
