@@ -58,26 +58,40 @@ __device__ __forceinline__ bool sphere_in_cell(const trh::BuildArgs &a, const do
   return d2 <= s.w * s.w;
 }
 
-// Visit every cell primitive k is listed in.
+// Visit every cell primitive k is listed in.  kLanes lanes share a primitive:
+// lane g takes the cells of its box whose linear index (x fastest) is g, g +
+// kLanes, ...  A protein-sized scene has only tens of thousands of primitives,
+// too few for one thread each to fill the chip.
+constexpr int kLanes = 16;
+
 template <class F>
-__device__ __forceinline__ void for_prim_cells(const trh::BuildArgs &a, int64_t k, F &&visit) {
+__device__ __forceinline__ void for_prim_cells(const trh::BuildArgs &a, int64_t k, int g,
+                                               F &&visit) {
   double lo[3], hi[3];
   prim_box(a, k, lo, hi);
-  int32_t c0[3], c1[3];
+  int32_t c0[3], n[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     c0[q] = cell_coord(a, q, lo[q] - a.delta);
-    c1[q] = cell_coord(a, q, hi[q] + a.delta);
+    n[q] = cell_coord(a, q, hi[q] + a.delta) - c0[q] + 1;
   }
   const bool sph = k < a.n_s;
   double4 s = make_double4(0, 0, 0, 0);
   if (sph) s = a.sph64[k];
-  for (int32_t iz = c0[2]; iz <= c1[2]; ++iz)
-    for (int32_t iy = c0[1]; iy <= c1[1]; ++iy)
-      for (int32_t ix = c0[0]; ix <= c1[0]; ++ix) {
-        if (sph && !sphere_in_cell(a, s, ix, iy, iz)) continue;
-        visit((uint32_t)(((int64_t)iz * a.res[1] + iy) * a.res[0] + ix));
-      }
+  // first cell of this lane, then steps of kLanes along x with carries
+  int32_t ix = g, iy = 0, iz = 0;
+  while (ix >= n[0]) { ix -= n[0]; ++iy; }
+  while (iy >= n[1]) { iy -= n[1]; ++iz; }
+  while (iz < n[2]) {
+    const int32_t x = c0[0] + ix, y = c0[1] + iy, z = c0[2] + iz;
+    if (!sph || sphere_in_cell(a, s, x, y, z))
+      visit((uint32_t)(((int64_t)z * a.res[1] + y) * a.res[0] + x));
+    ix += kLanes;
+    while (ix >= n[0]) {
+      ix -= n[0];
+      if (++iy == n[1]) { iy = 0; ++iz; }
+    }
+  }
 }
 
 __global__ void k_pack(int64_t n_s, int64_t n_c, const double *sc, const double *sr,
@@ -202,16 +216,18 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 }
 
 __global__ void k_count(trh::BuildArgs a, uint32_t *count) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = t / kLanes;
   if (k >= (int64_t)a.n_s + a.n_c) return;
-  for_prim_cells(a, k, [&](uint32_t c) { atomicAdd(&count[c], 1u); });
+  for_prim_cells(a, k, (int)(t % kLanes), [&](uint32_t c) { atomicAdd(&count[c], 1u); });
 }
 
 __global__ void k_scatter(trh::BuildArgs a, const uint32_t *cell_begin, uint32_t *cursor,
                           uint32_t *refs) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = t / kLanes;
   if (k >= (int64_t)a.n_s + a.n_c) return;
-  for_prim_cells(a, k, [&](uint32_t c) {
+  for_prim_cells(a, k, (int)(t % kLanes), [&](uint32_t c) {
     const uint32_t pos = atomicAdd(&cursor[c], 1u);
     refs[cell_begin[c] + pos] = (uint32_t)k;
   });
@@ -444,7 +460,7 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
 hipError_t launch_count(const BuildArgs &a, uint32_t *count, hipStream_t st) {
   const int64_t N = (int64_t)a.n_s + a.n_c;
   if (N == 0) return hipSuccess;
-  k_count<<<blocks_for(N), kBlock, 0, st>>>(a, count);
+  k_count<<<blocks_for(N * kLanes), kBlock, 0, st>>>(a, count);
   return hipGetLastError();
 }
 
@@ -478,7 +494,7 @@ hipError_t launch_scatter(const BuildArgs &a, const uint32_t *cell_begin, uint32
                           uint32_t *refs, hipStream_t st) {
   const int64_t N = (int64_t)a.n_s + a.n_c;
   if (N == 0) return hipSuccess;
-  k_scatter<<<blocks_for(N), kBlock, 0, st>>>(a, cell_begin, cursor, refs);
+  k_scatter<<<blocks_for(N * kLanes), kBlock, 0, st>>>(a, cell_begin, cursor, refs);
   return hipGetLastError();
 }
 
