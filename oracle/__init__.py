@@ -58,7 +58,8 @@ class _Camera(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("light_rescale", C.c_double), ("skylight", C.c_double),
                 ("ao_samples", C.c_int32), ("ao_maxdist", C.c_double), ("seed", C.c_uint64),
-                ("view_id", C.c_uint32), ("background", C.c_double * 3)]
+                ("view_id", C.c_uint32), ("background", C.c_double * 3),
+                ("aa_samples", C.c_int32)]
 
 
 def lib():
@@ -72,6 +73,11 @@ def lib():
         L.or_philox_many.argtypes = [i64, vp, vp, vp]
         L.or_ao_uniforms.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64,
                                      C.POINTER(dbl), C.POINTER(dbl)]
+        L.or_ao_uniforms_aa.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                        C.c_uint64, C.POINTER(dbl), C.POINTER(dbl)]
+        L.or_aa_offset.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64,
+                                   C.POINTER(dbl), C.POINTER(dbl)]
+        L.or_camera_ray_at.argtypes = [C.POINTER(_Camera), dbl, dbl, vp, vp]
         L.or_ao_direction.argtypes = [vp, dbl, dbl, vp]
         L.or_camera_ray.argtypes = [C.POINTER(_Camera), i32, i32, vp, vp]
         L.or_hit_sphere.argtypes = [vp, dbl, vp, vp, dbl, dbl, C.POINTER(dbl)]
@@ -136,7 +142,8 @@ def _camera(cam) -> _Camera:
 def _params(p) -> _Params:
     return _Params(float(p.light_rescale), float(p.skylight), int(p.ao_samples),
                    float(p.ao_maxdist), int(p.seed) & ((1 << 64) - 1), int(p.view_id),
-                   (C.c_double * 3)(*[float(x) for x in p.background]))
+                   (C.c_double * 3)(*[float(x) for x in p.background]),
+                   int(getattr(p, "aa_samples", 1)))
 
 
 class Grid:
@@ -182,6 +189,18 @@ def ao_uniforms(pix: int, s: int, view_id: int, seed: int):
     return u1.value, u2.value
 
 
+def ao_uniforms_aa(pix: int, s: int, view_id: int, a: int, seed: int):
+    u1 = C.c_double(); u2 = C.c_double()
+    lib().or_ao_uniforms_aa(pix, s, view_id, a, seed & ((1 << 64) - 1), C.byref(u1), C.byref(u2))
+    return u1.value, u2.value
+
+
+def aa_offset(pix: int, a: int, view_id: int, seed: int):
+    ox = C.c_double(); oy = C.c_double()
+    lib().or_aa_offset(pix, a, view_id, seed & ((1 << 64) - 1), C.byref(ox), C.byref(oy))
+    return ox.value, oy.value
+
+
 def ao_direction(n, u1: float, u2: float) -> np.ndarray:
     n = np.ascontiguousarray(n, dtype=np.float64)
     w = np.zeros(3)
@@ -193,6 +212,14 @@ def camera_ray(cam, i: int, j: int):
     o = np.zeros(3); d = np.zeros(3)
     c = _camera(cam)
     lib().or_camera_ray(C.byref(c), int(i), int(j), _ptr(o), _ptr(d))
+    return o, d
+
+
+def camera_ray_at(cam, px: float, py: float):
+    """Ray through image position (px, py) in pixel units (i + 1/2 = centre)."""
+    o = np.zeros(3); d = np.zeros(3)
+    c = _camera(cam)
+    lib().or_camera_ray_at(C.byref(c), float(px), float(py), _ptr(o), _ptr(d))
     return o, d
 
 

@@ -70,17 +70,46 @@ void or_philox_many(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_
   for (int64_t i = 0; i < n; ++i) or_philox4x32_10(ctr + 4 * i, key + 2 * i, out + 4 * i);
 }
 
-/* AO sample s of pixel pix: counter (pix, s, view, 0), key (seed low, seed
- * high).  The two uniforms keep the top 24 bits of words 0 and 1, so they
- * are exact in both float and double. */
-void or_ao_uniforms(uint32_t pix, uint32_t s, uint32_t view_id, uint64_t seed, double *u1,
-                    double *u2) {
-  uint32_t ctr[4] = {pix, s, view_id, 0u};
+/* Two uniforms on [0, 1) from one Philox draw: the top 24 bits of words 0
+ * and 1, exact in both float and double. */
+static void philox_uniforms(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t seed,
+                            double *u1, double *u2) {
+  uint32_t ctr[4] = {c0, c1, c2, c3};
   uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
   uint32_t x[4];
   or_philox4x32_10(ctr, key, x);
   *u1 = (double)(x[0] >> 8) * (1.0 / 16777216.0);
   *u2 = (double)(x[1] >> 8) * (1.0 / 16777216.0);
+}
+
+/* AO sample s of pixel pix: counter (pix, s, view, 0), key (seed low, seed
+ * high). */
+void or_ao_uniforms(uint32_t pix, uint32_t s, uint32_t view_id, uint64_t seed, double *u1,
+                    double *u2) {
+  philox_uniforms(pix, s, view_id, 0u, seed, u1, u2);
+}
+
+/* With several primary samples per pixel, AO sample s of primary sample a
+ * uses counter (pix, s, view, a): a = 0 is the single-sample stream above,
+ * and every primary sample has its own AO directions. */
+void or_ao_uniforms_aa(uint32_t pix, uint32_t s, uint32_t view_id, uint32_t a, uint64_t seed,
+                       double *u1, double *u2) {
+  philox_uniforms(pix, s, view_id, a, seed, u1, u2);
+}
+
+/* Antialiasing (several primary rays per pixel; the renderer's option, not
+ * used in the paper's runs).  Sample 0 goes through the pixel centre, so one
+ * sample is the plain renderer; sample a >= 1 through a uniform random point
+ * of the pixel square, from counter (pix, a, view, 0xFFFFFFFF), a stream no
+ * AO draw uses (AO counters have word 3 = a primary sample index < 2^31). */
+void or_aa_offset(uint32_t pix, uint32_t a, uint32_t view_id, uint64_t seed, double *ox,
+                  double *oy) {
+  if (a == 0) {
+    *ox = 0.5;
+    *oy = 0.5;
+    return;
+  }
+  philox_uniforms(pix, a, view_id, 0xFFFFFFFFu, seed, ox, oy);
 }
 
 /* Cosine-weighted hemisphere direction around unit normal n (Malley's
@@ -128,19 +157,31 @@ static void camera_basis(const or_camera *c, cam_basis *b) {
   b->H = c->height;
 }
 
-static void basis_ray(const cam_basis *b, int32_t i, int32_t j, double o[3], double d[3]) {
-  double x = (((2.0 * ((double)i + 0.5)) / (double)b->W) - 1.0) * b->th * b->aspect;
-  double y = (1.0 - (2.0 * ((double)j + 0.5)) / (double)b->H) * b->th;
+/* Ray through image position (px, py), in pixel units from the top-left
+ * corner of the image (px = i + 1/2 is the centre of column i). */
+static void basis_ray_at(const cam_basis *b, double px, double py, double o[3], double d[3]) {
+  double x = (((2.0 * px) / (double)b->W) - 1.0) * b->th * b->aspect;
+  double y = (1.0 - (2.0 * py) / (double)b->H) * b->th;
   double v[3];
   for (int a = 0; a < 3; ++a) v[a] = (b->f[a] + x * b->r[a]) + y * b->u[a];
   normalize3(v, d);
   memcpy(o, b->eye, 3 * sizeof(double));
 }
 
+static void basis_ray(const cam_basis *b, int32_t i, int32_t j, double o[3], double d[3]) {
+  basis_ray_at(b, (double)i + 0.5, (double)j + 0.5, o, d);
+}
+
 void or_camera_ray(const or_camera *cam, int32_t i, int32_t j, double o[3], double d[3]) {
   cam_basis b;
   camera_basis(cam, &b);
   basis_ray(&b, i, j, o, d);
+}
+
+void or_camera_ray_at(const or_camera *cam, double px, double py, double o[3], double d[3]) {
+  cam_basis b;
+  camera_basis(cam, &b);
+  basis_ray_at(&b, px, py, o, d);
 }
 
 /* ---------------------------------------------------------- intersections
@@ -566,18 +607,88 @@ static float prim_albedo(const or_scene *s, int64_t k, int ch) {
   return s->cyl_rgb[3 * (k - s->n_spheres) + ch];
 }
 
+/* One primary sample: the ray through image position (px, py), its nearest
+ * hit, direct light with shadow rays and AO, and the clamped colour. */
+typedef struct {
+  double col[3];
+  int hit;
+  int64_t k;
+  double t;
+  uint32_t amask;
+  int32_t aocc;
+  uint8_t lmask;
+} sample_out;
+
+static void shade_sample(const or_scene *s, const or_grid *g, const or_params *p,
+                         const cam_basis *cb, const double ldir[8][3], int64_t pid, uint32_t a,
+                         double px, double py, sample_out *r, or_counters *loc) {
+  const int S = p->ao_samples;
+  const int do_ao = (S > 0 && p->skylight > 0.0);
+  double o[3], d[3];
+  basis_ray_at(cb, px, py, o, d);
+  loc->primary_rays++;
+  double t;
+  int64_t k;
+  int hit = or_trace(s, g, o, d, 0.0, INFINITY, -1, 0, &t, &k, loc);
+  r->col[0] = p->background[0];
+  r->col[1] = p->background[1];
+  r->col[2] = p->background[2];
+  r->hit = hit;
+  r->k = hit ? k : -1;
+  r->t = hit ? t : INFINITY;
+  r->amask = 0;
+  r->aocc = 0;
+  r->lmask = 0;
+  if (!hit) return;
+  loc->hit_pixels++;
+  double N[3], P[3];
+  or_normal(s, k, o, d, t, N);
+  for (int c = 0; c < 3; ++c) P[c] = o[c] + t * d[c];
+  int front = dot3(N, d) < 0.0;
+  if (!front) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; }
+  int64_t skip = front ? k : -1;
+  double D[3] = {0.0, 0.0, 0.0};
+  for (int l = 0; l < s->n_lights; ++l) {
+    double c = dot3(N, ldir[l]);
+    if (!(c > 0.0)) continue;
+    loc->shadow_rays++;
+    if (or_trace(s, g, P, ldir[l], OR_EPS, INFINITY, skip, 1, NULL, NULL, loc)) {
+      r->lmask |= (uint8_t)(1u << l);
+    } else {
+      for (int ch = 0; ch < 3; ++ch) D[ch] += (p->light_rescale * s->light_rgb[3 * l + ch]) * c;
+    }
+  }
+  double ao = 1.0;
+  if (do_ao) {
+    for (int smp = 0; smp < S; ++smp) {
+      double u1, u2, w[3];
+      or_ao_uniforms_aa((uint32_t)pid, (uint32_t)smp, p->view_id, a, p->seed, &u1, &u2);
+      or_ao_direction(N, u1, u2, w);
+      loc->ao_rays++;
+      if (or_trace(s, g, P, w, OR_EPS, p->ao_maxdist, skip, 1, NULL, NULL, loc)) {
+        r->aocc++;
+        if (smp < 32) r->amask |= 1u << smp;
+      }
+    }
+    ao = (double)(S - r->aocc) / (double)S;
+  }
+  for (int ch = 0; ch < 3; ++ch) {
+    double v = (double)prim_albedo(s, k, ch) * (D[ch] + p->skylight * ao);
+    r->col[ch] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+  }
+}
+
 int or_render(const or_scene *s, const or_camera *cam, const or_params *p, const or_grid *g,
               int64_t n_pix, const int64_t *pix, double *rgb, int32_t *hit_id,
               uint32_t *ao_mask, int32_t *ao_occluded, uint8_t *light_mask, double *t_hit,
               or_counters *cnt, int32_t n_threads) {
   if (!s || !cam || !p || cam->width <= 0 || cam->height <= 0) return -1;
-  if (s->n_lights < 0 || s->n_lights > 8 || p->ao_samples < 0) return -1;
+  if (s->n_lights < 0 || s->n_lights > 8 || p->ao_samples < 0 || p->aa_samples < 0) return -1;
   cam_basis cb;
   camera_basis(cam, &cb);
   double ldir[8][3];
   for (int l = 0; l < s->n_lights; ++l) normalize3(s->light_dir + 3 * l, ldir[l]);
-  const int S = p->ao_samples;
-  const int do_ao = (S > 0 && p->skylight > 0.0);
+  const uint32_t A = p->aa_samples > 1 ? (uint32_t)p->aa_samples : 1u;
   const int64_t total = (int64_t)cam->width * cam->height;
   if (!pix) n_pix = total;
   or_counters acc;
@@ -595,61 +706,24 @@ int or_render(const or_scene *s, const or_camera *cam, const or_params *p, const
     for (int64_t q = 0; q < n_pix; ++q) {
       int64_t pid = pix ? pix[q] : q;
       int32_t i = (int32_t)(pid % cam->width), j = (int32_t)(pid / cam->width);
-      double o[3], d[3];
-      basis_ray(&cb, i, j, o, d);
       loc.pixels++;
-      loc.primary_rays++;
-      double t;
-      int64_t k;
-      int hit = or_trace(s, g, o, d, 0.0, INFINITY, -1, 0, &t, &k, &loc);
-      double col[3] = {p->background[0], p->background[1], p->background[2]};
-      uint32_t amask = 0;
-      int32_t aocc = 0;
-      uint8_t lmask = 0;
-      if (hit) {
-        loc.hit_pixels++;
-        double N[3], P[3];
-        or_normal(s, k, o, d, t, N);
-        for (int a = 0; a < 3; ++a) P[a] = o[a] + t * d[a];
-        int front = dot3(N, d) < 0.0;
-        if (!front) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; }
-        int64_t skip = front ? k : -1;
-        double D[3] = {0.0, 0.0, 0.0};
-        for (int l = 0; l < s->n_lights; ++l) {
-          double c = dot3(N, ldir[l]);
-          if (!(c > 0.0)) continue;
-          loc.shadow_rays++;
-          if (or_trace(s, g, P, ldir[l], OR_EPS, INFINITY, skip, 1, NULL, NULL, &loc)) {
-            lmask |= (uint8_t)(1u << l);
-          } else {
-            for (int ch = 0; ch < 3; ++ch) D[ch] += (p->light_rescale * s->light_rgb[3 * l + ch]) * c;
-          }
-        }
-        double ao = 1.0;
-        if (do_ao) {
-          for (int smp = 0; smp < S; ++smp) {
-            double u1, u2, w[3];
-            or_ao_uniforms((uint32_t)pid, (uint32_t)smp, p->view_id, p->seed, &u1, &u2);
-            or_ao_direction(N, u1, u2, w);
-            loc.ao_rays++;
-            if (or_trace(s, g, P, w, OR_EPS, p->ao_maxdist, skip, 1, NULL, NULL, &loc)) {
-              aocc++;
-              if (smp < 32) amask |= 1u << smp;
-            }
-          }
-          ao = (double)(S - aocc) / (double)S;
-        }
-        for (int ch = 0; ch < 3; ++ch) {
-          double v = (double)prim_albedo(s, k, ch) * (D[ch] + p->skylight * ao);
-          col[ch] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
-        }
+      sample_out first, cur;
+      double sum[3] = {0.0, 0.0, 0.0};
+      for (uint32_t a = 0; a < A; ++a) {
+        double ox, oy;
+        or_aa_offset((uint32_t)pid, a, p->view_id, p->seed, &ox, &oy);
+        shade_sample(s, g, p, &cb, ldir, pid, a, (double)i + ox, (double)j + oy,
+                     a == 0 ? &first : &cur, &loc);
+        const sample_out *r = a == 0 ? &first : &cur;
+        for (int ch = 0; ch < 3; ++ch) sum[ch] += r->col[ch];
       }
-      if (rgb) { rgb[3 * q] = col[0]; rgb[3 * q + 1] = col[1]; rgb[3 * q + 2] = col[2]; }
-      if (hit_id) hit_id[q] = hit ? (int32_t)k : -1;
-      if (ao_mask) ao_mask[q] = amask;
-      if (ao_occluded) ao_occluded[q] = aocc;
-      if (light_mask) light_mask[q] = lmask;
-      if (t_hit) t_hit[q] = hit ? t : INFINITY;
+      if (rgb)
+        for (int ch = 0; ch < 3; ++ch) rgb[3 * q + ch] = A == 1 ? sum[ch] : sum[ch] / (double)A;
+      if (hit_id) hit_id[q] = (int32_t)first.k;
+      if (ao_mask) ao_mask[q] = first.amask;
+      if (ao_occluded) ao_occluded[q] = first.aocc;
+      if (light_mask) light_mask[q] = first.lmask;
+      if (t_hit) t_hit[q] = first.t;
     }
 #ifdef _OPENMP
 #pragma omp critical

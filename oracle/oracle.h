@@ -59,6 +59,7 @@ typedef struct {
   uint64_t seed;
   uint32_t view_id;
   double background[3];
+  int32_t aa_samples;    /* primary samples per pixel; 0 or 1 = the pixel centre only */
 } or_params;
 
 /* operation counts, used for the algorithmic flop model */
@@ -82,8 +83,19 @@ void or_philox_many(int64_t n, const uint32_t *ctr /*[n*4]*/, const uint32_t *ke
                     uint32_t *out /*[n*4]*/);
 void or_ao_uniforms(uint32_t pix, uint32_t s, uint32_t view_id, uint64_t seed,
                     double *u1, double *u2);
+/* AO sample s of antialiasing sample a: counter (pix, s, view, a) */
+void or_ao_uniforms_aa(uint32_t pix, uint32_t s, uint32_t view_id, uint32_t a, uint64_t seed,
+                       double *u1, double *u2);
 void or_ao_direction(const double n[3], double u1, double u2, double w[3]);
 void or_camera_ray(const or_camera *cam, int32_t i, int32_t j, double o[3], double d[3]);
+/* Position inside pixel pix of antialiasing sample a, in pixel units from
+ * the pixel's top-left corner: (1/2, 1/2) for a = 0, else two Philox
+ * uniforms drawn with counter (pix, a, view, 0xFFFFFFFF). */
+void or_aa_offset(uint32_t pix, uint32_t a, uint32_t view_id, uint64_t seed, double *ox,
+                  double *oy);
+/* Ray through image position (px, py) in pixel units (px = i + 1/2 is the
+ * centre of column i). */
+void or_camera_ray_at(const or_camera *cam, double px, double py, double o[3], double d[3]);
 int or_hit_sphere(const double c[3], double r, const double o[3], const double d[3],
                   double tmin, double tmax, double *t);
 int or_hit_cylinder(const double a[3], const double b[3], double rho, const double o[3],
@@ -107,6 +119,11 @@ int or_trace(const or_scene *s, const or_grid *g, const double o[3], const doubl
              or_counters *cnt);
 
 /* Render the listed pixels (pix == NULL => all W*H in row-major order).
+ * With A = aa_samples > 1 every pixel is shaded A times, at the positions of
+ * or_aa_offset, and rgb is the mean of the A clamped colours; hit_id, the
+ * masks, ao_occluded and t_hit are those of sample 0 (the pixel centre), and
+ * the counters count every sample's rays (hit_pixels = primary samples that
+ * hit).
  * Outputs are indexed by list position; any output pointer may be NULL.
  * n_threads <= 0 => OpenMP default.  Returns 0, or -1 on bad arguments. */
 int or_render(const or_scene *s, const or_camera *cam, const or_params *p, const or_grid *g,

@@ -94,6 +94,7 @@ class Params:
     seed: int = 2
     view_id: int = 0
     background: tuple = (0.0, 0.0, 0.0)
+    aa_samples: int = 1    # primary samples per pixel (antialiasing); 1 = pixel centre
 
 
 def _empty3(dtype=np.float64):
