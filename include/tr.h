@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define TR_ABI_VERSION 1
+#define TR_ABI_VERSION 2
 
 typedef enum {
   TR_OK = 0,
@@ -82,7 +82,8 @@ typedef struct {
   double cells_per_prim;     /* grid density lambda; 0 => 24.  Speed only.  */
 } tr_scene_desc;
 
-/* Pinhole camera, one ray through each pixel centre.  width = horizontal
+/* Pinhole camera, one ray through each pixel centre (more with
+ * tr_params.aa_samples).  width = horizontal
  * pixel count, height = vertical (the -res W H option, Sec. 2).  Row 0 of
  * the frame is the top of the image, column 0 the left. */
 typedef struct {
@@ -100,6 +101,20 @@ typedef struct {
   uint32_t view_id;          /* third Philox counter word (frame / view)    */
   int32_t precision;         /* tr_precision                                */
   float background[3];       /* colour of pixels whose primary ray misses   */
+  int32_t aa_samples;        /* primary samples per pixel (antialiasing), 0..256;
+                                0 and 1 = the pixel centre only.  With A > 1,
+                                sample 0 is the centre and sample a >= 1 a point
+                                (i + x, j + y) of the pixel square, x and y the top
+                                24 bits of words 0 and 1 of Philox counter (pix, a,
+                                view_id, 0xFFFFFFFF) times 2^-24; AO sample s of
+                                sample a uses counter (pix, s, view_id, a).  rgb is
+                                the mean of the A clamped colours (summed in
+                                sample order, then divided by A); hit_id and the
+                                masks are sample 0's.  Costs (A - 1) * W * H * 12
+                                bytes of library workspace per frame (kept per
+                                stream, grown on demand with a synchronising
+                                hipMalloc); not with tile ranges or graphs.  A
+                                zero-filled struct of ABI 1 means one sample.  */
 } tr_params;
 
 /* Device output buffers, caller-owned.  Only rgb is required.
@@ -229,8 +244,9 @@ void tr_scene_destroy(tr_scene *scene);
  * stream.  TR_EINVAL on a NULL scene/camera/params/frame->rgb, width or
  * height <= 0 or width*height >= 2^31, fovy outside (0, 180), eye == lookat,
  * up parallel to the view direction, non-finite camera, ao_samples outside
- * 0..65535, ao_maxdist <= 0, ao_mask requested with ao_samples > 32, or an
- * unknown precision. */
+ * 0..65535, ao_maxdist <= 0, ao_mask requested with ao_samples > 32,
+ * aa_samples outside 0..256, or an unknown precision; TR_ENOMEM when the
+ * antialiasing workspace cannot be allocated. */
 tr_status tr_render(const tr_scene *scene, const tr_camera *cam, const tr_params *params,
                     const tr_frame *frame, void *hip_stream);
 

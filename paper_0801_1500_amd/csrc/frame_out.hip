@@ -9,6 +9,9 @@
 // and written non-temporally.  The rounding is exact: a float times 255 is
 // exact in double, so the conversion runs in FP64 (two FP64 ops per value
 // are far below the memory time).
+//
+// Also here: the mean over an antialiased frame's sample planes, another
+// streaming pass (A * 4 bytes read and 4 written per value).
 #include "tr_internal.h"
 
 namespace {
@@ -53,9 +56,32 @@ __global__ __launch_bounds__(kThreads) void k_quantize_scalar(const float *__res
   if (i < n) out[i] = (uint8_t)q8(in[i]);
 }
 
+// Mean of an antialiased pixel's samples: sample 0 is already in rgb, samples
+// 1..n_planes in the planes; the sum runs in sample order, so the result
+// does not depend on how the samples were scheduled.
+__global__ __launch_bounds__(kThreads) void k_aa_mean(float *rgb, const float *planes,
+                                                      int32_t n_planes, int64_t n, float count) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    float sum = rgb[i];
+    const float *p = planes + i;
+    for (int32_t a = 0; a < n_planes; ++a, p += n) sum += *p;
+    rgb[i] = sum / count;
+  }
+}
+
 }  // namespace
 
 namespace trh {
+
+hipError_t launch_aa_mean(float *rgb, const float *planes, int32_t n_planes, int64_t n,
+                          hipStream_t st) {
+  if (n <= 0 || n_planes <= 0) return hipSuccess;
+  int64_t blocks = (n + kThreads - 1) / kThreads;
+  if (blocks > 8192) blocks = 8192;  // grid-stride beyond 2M threads
+  k_aa_mean<<<(unsigned)blocks, kThreads, 0, st>>>(rgb, planes, n_planes, n, (float)(n_planes + 1));
+  return hipGetLastError();
+}
 
 hipError_t launch_quantize_rgb8(const float *in, int64_t n, uint8_t *out, hipStream_t st) {
   if (n <= 0) return hipSuccess;

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
         int32_t aocc = 0;
         for (int s = 0; s < J.S; ++s) {
           uint32_t b1, b2;
-          ao_uniform_bits((uint32_t)pid, (uint32_t)s, J.view_id, J.key0, J.key1, b1, b2);
+          ao_uniform_bits((uint32_t)pid, (uint32_t)s, J.view_id, (uint32_t)J.aa, J.key0, J.key1, b1, b2);
           double w[3];
           ao_dir_f64(N, b1, b2, w);
           n_ao++;

@@ -49,6 +49,7 @@ struct BankInfo {
   int32_t vmagic;       // ceil(2^16 / vw): q / vw = (q * vmagic) >> 16 for q < 64
   int32_t W, H, S, n_lights;
   uint32_t key0, key1, view;
+  int32_t aa;           // antialiasing sample index (0 = pixel centre)
   float maxd, sky;
   float eye[3], f[3], r[3], u[3], th, aspect;  // FP32 camera
   float rw2, rh2;       // 2 / W, 2 / H
@@ -590,6 +591,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
             B.key0 = J->key0;
             B.key1 = J->key1;
             B.view = J->view_id;
+            B.aa = J->aa;
             B.maxd = J->ao_maxdist32;
             B.sky = J->sky32;
           }
@@ -630,8 +632,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
           int32_t pi, pj;
           bank_pixel(B, slot & 63, pi, pj);
           if (kind == kPrimary) {
-            const float x = fmaf((float)pi + 0.5f, B.rw2, -1.0f) * B.th * B.aspect;
-            const float y = fmaf(-((float)pj + 0.5f), B.rh2, 1.0f) * B.th;
+            float fx = 0.5f, fy = 0.5f;  // position inside the pixel
+            if (B.aa != 0) {
+              uint32_t bx, by;
+              aa_offset_bits((uint32_t)(pj * B.W + pi), (uint32_t)B.aa, B.view, B.key0, B.key1, bx, by);
+              fx = (float)bx * 0x1p-24f;
+              fy = (float)by * 0x1p-24f;
+            }
+            const float x = fmaf((float)pi + fx, B.rw2, -1.0f) * B.th * B.aspect;
+            const float y = fmaf(-((float)pj + fy), B.rh2, 1.0f) * B.th;
             const float vx = B.f[0] + x * B.r[0] + y * B.u[0];
             const float vy = B.f[1] + x * B.r[1] + y * B.u[1];
             const float vz = B.f[2] + x * B.r[2] + y * B.u[2];
@@ -653,7 +662,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
             R.tmin = kEps;
             if (kind == kAO) {
               uint32_t b1, b2;
-              ao_uniform_bits((uint32_t)(pj * B.W + pi), (uint32_t)ridx, B.view, B.key0, B.key1, b1, b2);
+              ao_uniform_bits((uint32_t)(pj * B.W + pi), (uint32_t)ridx, B.view, (uint32_t)B.aa, B.key0, B.key1, b1, b2);
               ao_dir_f32(L.nx[slot], L.ny[slot], L.nz[slot], b1, b2, R.dx, R.dy, R.dz);
               R.tmax = B.maxd;
             } else {
@@ -929,7 +938,7 @@ __global__ void k_debug_ao_dirs(int64_t n, const float *nrm, const uint32_t *pix
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t b1, b2;
-  ao_uniform_bits(pix[i], smp[i], view, k0, k1, b1, b2);
+  ao_uniform_bits(pix[i], smp[i], view, 0u, k0, k1, b1, b2);
   ao_dir_f32(nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2], b1, b2, w[3 * i], w[3 * i + 1], w[3 * i + 2]);
 }
 

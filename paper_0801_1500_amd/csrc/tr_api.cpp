@@ -614,12 +614,17 @@ static tr_status check_camera(const tr_camera *c) {
   return TR_OK;
 }
 
+static constexpr int32_t kMaxAASamples = 256;
+static int32_t aa_count(const tr_params &p) { return p.aa_samples > 1 ? p.aa_samples : 1; }
+
 static tr_status check_params(const tr_params *p, const tr_frame *f) {
   if (!p) return fail(TR_EINVAL, "NULL params");
   if (!f || !f->rgb) return fail(TR_EINVAL, "NULL frame or frame->rgb");
   if (p->ao_samples < 0 || p->ao_samples > 65535) return fail(TR_EINVAL, "ao_samples must be 0..65535");
   if (!(p->ao_maxdist > 0.0)) return fail(TR_EINVAL, "ao_maxdist must be > 0");
   if (f->ao_mask && p->ao_samples > 32) return fail(TR_EINVAL, "ao_mask needs ao_samples <= 32");
+  if (p->aa_samples < 0 || p->aa_samples > kMaxAASamples)
+    return fail(TR_EINVAL, "aa_samples must be 0..%d", kMaxAASamples);
   if (p->precision < TR_PREC_FP64 || p->precision > TR_PREC_FP32_RESOLVE)
     return fail(TR_EINVAL, "unknown precision %d", p->precision);
   if (!std::isfinite(p->light_rescale) || !std::isfinite(p->skylight))
@@ -801,6 +806,81 @@ static tr_tune pick_tune(const tr_scene *s, const tr_camera *c, const tr_params 
   return t;
 }
 
+// ---------------------------------------------------------- antialiasing
+// A frame with A > 1 primary samples per pixel is A jobs: job 0 (the pixel
+// centres) writes the caller's buffers, and sample a = 1..A-1 writes its
+// colours into plane a - 1 of a per-stream workspace.  After the render,
+// one pass per frame folds the planes into the caller's rgb, summing in
+// sample order (deterministic), and divides by A.
+struct AAWork {
+  float *buf = nullptr;
+  int64_t cap = 0;  // floats
+};
+static std::map<std::pair<int, hipStream_t>, AAWork> g_aa_work;
+
+static tr_status aa_workspace(hipStream_t st, int64_t n_floats, float **out) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  AAWork &w = g_aa_work[{dev, st}];
+  if (w.cap < n_floats) {
+    if (w.buf) {  // earlier work on this stream may still read the old planes
+      HIP_TRY(hipStreamSynchronize(st));
+      HIP_TRY(hipFree(w.buf));
+      w.buf = nullptr;
+      w.cap = 0;
+    }
+    HIP_TRY(hipMalloc((void **)&w.buf, (size_t)n_floats * sizeof(float)));
+    w.cap = n_floats;
+  }
+  *out = w.buf;
+  return TR_OK;
+}
+
+struct AAMean {
+  float *rgb;
+  const float *planes;
+  int32_t n_planes;
+  int64_t n;  // floats per plane (W * H * 3)
+};
+
+// Append the sample jobs 1..A-1 of jobs[i] (A = aa[i]) and list the folds.
+static tr_status expand_aa(std::vector<JobDev> &jobs, const std::vector<int32_t> &aa,
+                           hipStream_t st, std::vector<AAMean> &means) {
+  int64_t total = 0;
+  for (size_t i = 0; i < aa.size(); ++i)
+    if (aa[i] > 1) total += (int64_t)(aa[i] - 1) * jobs[i].W * jobs[i].H * 3;
+  if (total == 0) return TR_OK;
+  float *ws = nullptr;
+  tr_status rc = aa_workspace(st, total, &ws);
+  if (rc != TR_OK) return rc;
+  int64_t off = 0;
+  const size_t n0 = aa.size();
+  for (size_t i = 0; i < n0; ++i) {
+    if (aa[i] <= 1) continue;
+    const JobDev base = jobs[i];
+    const int64_t plane = (int64_t)base.W * base.H * 3;
+    means.push_back(AAMean{base.rgb, ws + off, aa[i] - 1, plane});
+    for (int32_t a = 1; a < aa[i]; ++a) {
+      JobDev J = base;
+      J.aa = a;
+      J.rgb = ws + off;
+      J.hit_id = nullptr;
+      J.ao_mask = nullptr;
+      J.light_mask = nullptr;
+      jobs.push_back(J);
+      off += plane;
+    }
+  }
+  return TR_OK;
+}
+
+static tr_status run_aa_means(const std::vector<AAMean> &means, hipStream_t st) {
+  for (const AAMean &m : means)
+    HIP_TRY(trh::launch_aa_mean(m.rgb, m.planes, m.n_planes, m.n, st));
+  return TR_OK;
+}
+
 // Launch the wavefront kernel over the jobs (already filled, tiles set).
 static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, uint64_t *stats,
                                   hipStream_t st) {
@@ -849,12 +929,17 @@ extern "C" tr_status tr_render_tuned(const tr_scene *s, const tr_camera *c, cons
   rc = make_job(s, c, p, f, t.tile_w, J);
   if (rc != TR_OK) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
-  if (p->precision == TR_PREC_FP64) {
-    HIP_TRY(trh::launch_render_plain_f64(J, f->stats, st));
-    return TR_OK;
-  }
   std::vector<JobDev> jobs(1, J);
-  return launch_wave_jobs(jobs, t, f->stats, st);
+  std::vector<AAMean> means;
+  rc = expand_aa(jobs, std::vector<int32_t>(1, aa_count(*p)), st, means);
+  if (rc != TR_OK) return rc;
+  if (p->precision == TR_PREC_FP64) {
+    for (const JobDev &Js : jobs) HIP_TRY(trh::launch_render_plain_f64(Js, f->stats, st));
+  } else {
+    rc = launch_wave_jobs(jobs, t, f->stats, st);
+    if (rc != TR_OK) return rc;
+  }
+  return run_aa_means(means, st);
 }
 
 extern "C" tr_status tr_render(const tr_scene *s, const tr_camera *c, const tr_params *p,
@@ -879,15 +964,23 @@ static tr_status batch_impl(int32_t n, const tr_scene *const *scenes, const tr_c
   if (rc != TR_OK) return rc;
   const int res = params[0].precision == TR_PREC_FP32_RESOLVE;
   std::vector<JobDev> jobs;
+  std::vector<int32_t> aa;
   jobs.reserve(n);
   uint64_t *stats = frames[0].stats;
   for (int32_t i = 0; i < n; ++i) {
     JobDev J;
     rc = make_job(scenes[i], &cams[i], &params[i], &frames[i], t.tile_w, J);
     if (rc != TR_OK) return fail(rc, "job %d: %s", i, g_err.c_str());
+    if (tb && aa_count(params[i]) > 1) return fail(TR_EUNSUPPORTED, "tile ranges need aa_samples <= 1");
     if (params[i].precision == TR_PREC_FP64) {
       if (tb) return fail(TR_EUNSUPPORTED, "tile ranges need an FP32 precision");
-      HIP_TRY(trh::launch_render_plain_f64(J, frames[i].stats, st));
+      std::vector<JobDev> one(1, J);
+      std::vector<AAMean> means;
+      rc = expand_aa(one, std::vector<int32_t>(1, aa_count(params[i])), st, means);
+      if (rc != TR_OK) return rc;
+      for (const JobDev &Js : one) HIP_TRY(trh::launch_render_plain_f64(Js, frames[i].stats, st));
+      rc = run_aa_means(means, st);
+      if (rc != TR_OK) return rc;
       continue;
     }
     if ((params[i].precision == TR_PREC_FP32_RESOLVE) != (res != 0))
@@ -902,12 +995,18 @@ static tr_status batch_impl(int32_t n, const tr_scene *const *scenes, const tr_c
       J.tile_end = te[i];
     }
     jobs.push_back(J);
+    aa.push_back(aa_count(params[i]));
   }
   if (jobs.empty()) return TR_OK;
+  std::vector<AAMean> means;
+  rc = expand_aa(jobs, aa, st, means);
+  if (rc != TR_OK) return rc;
   // keep jobs of one scene adjacent so waves rarely switch scenes
   std::stable_sort(jobs.begin(), jobs.end(),
                    [](const JobDev &a, const JobDev &b) { return a.scene_key < b.scene_key; });
-  return launch_wave_jobs(jobs, t, stats, st);
+  rc = launch_wave_jobs(jobs, t, stats, st);
+  if (rc != TR_OK) return rc;
+  return run_aa_means(means, st);
 }
 
 extern "C" tr_status tr_render_batch(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,
@@ -1004,6 +1103,8 @@ extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, c
     rc = make_job(scenes[i], &cams[i], &params[i], &frames[i], g->tune.tile_w, J);
     if (rc == TR_OK && params[i].precision == TR_PREC_FP64)
       rc = fail(TR_EUNSUPPORTED, "graphs need an FP32 precision");
+    if (rc == TR_OK && aa_count(params[i]) > 1)
+      rc = fail(TR_EUNSUPPORTED, "graphs need aa_samples <= 1");
     if (rc == TR_OK && (params[i].precision == TR_PREC_FP32_RESOLVE) != (res != 0))
       rc = fail(TR_EINVAL, "all jobs of one graph must use the same precision");
     if (rc == TR_OK && frames[i].stats != frames[0].stats)
@@ -1084,6 +1185,7 @@ extern "C" tr_status tr_graph_update(tr_graph *g, const tr_camera *cams, const t
       return fail(TR_EINVAL, "job %d: resolution differs from the captured one", i);
     if (p.precision != g->params[i].precision)
       return fail(TR_EINVAL, "job %d: precision differs from the captured one", i);
+    if (aa_count(p) > 1) return fail(TR_EUNSUPPORTED, "job %d: graphs need aa_samples <= 1", i);
     tr_status rc = make_job(g->scenes[i], &c, &p, &g->frames[i], g->tune.tile_w, nj[i]);
     if (rc != TR_OK) return fail(rc, "job %d: %s", i, g_err.c_str());
     nj[i].queue_begin = g->jobs[i].queue_begin;

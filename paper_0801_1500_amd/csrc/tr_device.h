@@ -75,7 +75,7 @@ struct JobDev {
   int64_t tile_begin, tile_end;  // range rendered by this launch
   int64_t queue_begin;           // index of this job's first tile in the launch's tile queue
   int32_t scene_key;             // jobs with equal keys share one scene
-  int32_t pad2_;
+  int32_t aa;                    // antialiasing sample index (0 = the pixel centre)
 };
 
 // --------------------------------------------------------------- Philox
@@ -103,13 +103,25 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
   return c;
 }
 
-// 24-bit uniforms of AO sample s of pixel pix: exact in float and double.
+// AO sample s of primary sample aa: counter (pix, s, view, aa).  The two
+// uniforms are the top 24 bits of words 0 and 1 (exact in float and double).
 __device__ __forceinline__ void ao_uniform_bits(uint32_t pix, uint32_t s, uint32_t view,
-                                                uint32_t k0, uint32_t k1, uint32_t &b1,
-                                                uint32_t &b2) {
-  uint4 x = philox4x32_10(make_uint4(pix, s, view, 0u), k0, k1);
+                                                uint32_t aa, uint32_t k0, uint32_t k1,
+                                                uint32_t &b1, uint32_t &b2) {
+  uint4 x = philox4x32_10(make_uint4(pix, s, view, aa), k0, k1);
   b1 = x.x >> 8;
   b2 = x.y >> 8;
+}
+
+// Position of primary sample aa >= 1 inside its pixel square, as 24-bit
+// fractions of a pixel (value = bits * 2^-24): counter (pix, aa, view,
+// 0xFFFFFFFF), which no AO draw uses.  Sample 0 is the pixel centre.
+__device__ __forceinline__ void aa_offset_bits(uint32_t pix, uint32_t aa, uint32_t view,
+                                               uint32_t k0, uint32_t k1, uint32_t &bx,
+                                               uint32_t &by) {
+  uint4 x = philox4x32_10(make_uint4(pix, aa, view, 0xFFFFFFFFu), k0, k1);
+  bx = x.x >> 8;
+  by = x.y >> 8;
 }
 
 // Cosine-weighted hemisphere direction around unit n (Malley: uniform disc
@@ -161,10 +173,20 @@ __device__ __forceinline__ double dot3d(const double a[3], const double b[3]) {
 }
 
 // FP64 primary ray through the centre of pixel (i, j); row 0 at the top.
+// Primary ray of pixel (i, j) for the job's antialiasing sample: through the
+// pixel centre for sample 0, else through the sample's point of the pixel
+// square (i + x offset, j + y offset, exact in double).
 __device__ __forceinline__ void primary_ray_f64(const JobDev &J, int32_t i, int32_t j,
                                                 double o[3], double d[3]) {
-  const double x = (((2.0 * ((double)i + 0.5)) / (double)J.W) - 1.0) * J.th * J.aspect;
-  const double y = (1.0 - (2.0 * ((double)j + 0.5)) / (double)J.H) * J.th;
+  double px = (double)i + 0.5, py = (double)j + 0.5;
+  if (J.aa != 0) {
+    uint32_t bx, by;
+    aa_offset_bits((uint32_t)(j * J.W + i), (uint32_t)J.aa, J.view_id, J.key0, J.key1, bx, by);
+    px = (double)i + (double)bx * 0x1p-24;
+    py = (double)j + (double)by * 0x1p-24;
+  }
+  const double x = (((2.0 * px) / (double)J.W) - 1.0) * J.th * J.aspect;
+  const double y = (1.0 - (2.0 * py) / (double)J.H) * J.th;
   double v[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) v[a] = (J.f[a] + x * J.r[a]) + y * J.u[a];

@@ -57,6 +57,10 @@ hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32
 // ---- frame output (frame_out.hip) ----
 // values -> bytes, floor(clamp(v, 0, 1) * 255 + 1/2); any alignment
 hipError_t launch_quantize_rgb8(const float *in, int64_t n, uint8_t *out, hipStream_t st);
+// rgb[i] = (rgb[i] + planes[0][i] + ... + planes[n_planes - 1][i]) / (n_planes + 1),
+// summed in that order; planes are n floats apart
+hipError_t launch_aa_mean(float *rgb, const float *planes, int32_t n_planes, int64_t n,
+                          hipStream_t st);
 
 // ---- render launchers ----
 hipError_t launch_render_plain_f64(const trd::JobDev &job, uint64_t *stats, hipStream_t st);

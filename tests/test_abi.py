@@ -39,7 +39,7 @@ def test_every_declared_symbol_exported(tr):
     L = tr.lib()
     for n in _declared():
         assert hasattr(L, n), n
-    assert tr.abi_version() == 1
+    assert tr.abi_version() == 2
 
 
 def test_tile_count(tr):
