@@ -59,7 +59,7 @@ class _Params(C.Structure):
     _fields_ = [("light_rescale", C.c_double), ("skylight", C.c_double),
                 ("ao_samples", C.c_int32), ("ao_maxdist", C.c_double), ("seed", C.c_uint64),
                 ("view_id", C.c_uint32), ("background", C.c_double * 3),
-                ("aa_samples", C.c_int32)]
+                ("aa_samples", C.c_int32), ("specular", C.c_double), ("shininess", C.c_double)]
 
 
 def lib():
@@ -143,7 +143,8 @@ def _params(p) -> _Params:
     return _Params(float(p.light_rescale), float(p.skylight), int(p.ao_samples),
                    float(p.ao_maxdist), int(p.seed) & ((1 << 64) - 1), int(p.view_id),
                    (C.c_double * 3)(*[float(x) for x in p.background]),
-                   int(getattr(p, "aa_samples", 1)))
+                   int(getattr(p, "aa_samples", 1)), float(getattr(p, "specular", 0.0)),
+                   float(getattr(p, "shininess", 20.0)))
 
 
 class Grid:

@@ -584,8 +584,13 @@ int or_trace(const or_scene *s, const or_grid *g, const double o[3], const doubl
  * sample the cosine-weighted hemisphere with Philox uniforms keyed by
  * (pixel, sample); secondary rays start at the hit point with t in
  * (1e-4, ...] and skip the hit primitive when it was hit on its outside.
- * Colour = clamp(albedo * (rescale * sum_l I_l (N.L_l) V_l + skylight * AO),
- * 0, 1) per channel, AO = unoccluded fraction (1 if no AO rays are cast). */
+ * Colour = clamp(albedo * (rescale * sum_l I_l (N.L_l) V_l + skylight * AO)
+ * + H, 0, 1) per channel, AO = unoccluded fraction (1 if no AO rays are
+ * cast).  H is the optional Phong highlight (a shading option of the
+ * renderer the paper drives, not used in its runs): rescale * sum_l I_l V_l
+ * k_s max(0, R_l.V)^n over the lights with N.L_l > 0, R_l the light
+ * direction mirrored about N and V = -d the direction back to the eye; it is
+ * white (not scaled by the albedo) and 0 when k_s = 0. */
 #define OR_EPS 1e-4
 
 static void add_counters(or_counters *dst, const or_counters *src) {
@@ -648,6 +653,7 @@ static void shade_sample(const or_scene *s, const or_grid *g, const or_params *p
   if (!front) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; }
   int64_t skip = front ? k : -1;
   double D[3] = {0.0, 0.0, 0.0};
+  double Hs[3] = {0.0, 0.0, 0.0}; /* specular highlights (white, after albedo) */
   for (int l = 0; l < s->n_lights; ++l) {
     double c = dot3(N, ldir[l]);
     if (!(c > 0.0)) continue;
@@ -656,6 +662,17 @@ static void shade_sample(const or_scene *s, const or_grid *g, const or_params *p
       r->lmask |= (uint8_t)(1u << l);
     } else {
       for (int ch = 0; ch < 3; ++ch) D[ch] += (p->light_rescale * s->light_rgb[3 * l + ch]) * c;
+      if (p->specular > 0.0) {
+        /* Phong: mirror the light direction about N, compare with the
+         * direction back to the eye, -d */
+        double R[3], rv;
+        for (int a = 0; a < 3; ++a) R[a] = 2.0 * c * N[a] - ldir[l][a];
+        rv = -dot3(R, d);
+        if (rv > 0.0) {
+          double f = p->specular * pow(rv, p->shininess);
+          for (int ch = 0; ch < 3; ++ch) Hs[ch] += (p->light_rescale * s->light_rgb[3 * l + ch]) * f;
+        }
+      }
     }
   }
   double ao = 1.0;
@@ -673,7 +690,7 @@ static void shade_sample(const or_scene *s, const or_grid *g, const or_params *p
     ao = (double)(S - r->aocc) / (double)S;
   }
   for (int ch = 0; ch < 3; ++ch) {
-    double v = (double)prim_albedo(s, k, ch) * (D[ch] + p->skylight * ao);
+    double v = (double)prim_albedo(s, k, ch) * (D[ch] + p->skylight * ao) + Hs[ch];
     r->col[ch] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
   }
 }

@@ -60,6 +60,8 @@ typedef struct {
   uint32_t view_id;
   double background[3];
   int32_t aa_samples;    /* primary samples per pixel; 0 or 1 = the pixel centre only */
+  double specular;       /* Phong highlight strength k_s >= 0 (0 = none) */
+  double shininess;      /* Phong exponent n > 0 */
 } or_params;
 
 /* operation counts, used for the algorithmic flop model */

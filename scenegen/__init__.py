@@ -95,6 +95,8 @@ class Params:
     view_id: int = 0
     background: tuple = (0.0, 0.0, 0.0)
     aa_samples: int = 1    # primary samples per pixel (antialiasing); 1 = pixel centre
+    specular: float = 0.0  # Phong highlight strength (0 = none)
+    shininess: float = 20.0  # Phong exponent
 
 
 def _empty3(dtype=np.float64):
