@@ -184,12 +184,9 @@ def frame_output_measure(tr, torch, frame, reps: int = 20) -> dict:
             "ppm_encode_ms": enc_ms, "ppm_bytes": len(ppm)}
 
 
-def antialias_measure(tr, torch, gs, cam, params, prec, aa: int = 4, frames: int = 3) -> dict:
-    """The 17.6 MP frame with `aa` primary samples per pixel (each with its
-    own 16 AO rays): aa sample jobs in one wavefront launch, then the mean
-    over the sample planes."""
-    import dataclasses
-    p = dataclasses.replace(params, aa_samples=aa)
+def variant_measure(tr, torch, gs, cam, p, prec, workload: str, frames: int = 3) -> dict:
+    """The 17.6 MP frame with a shading variant on (antialiasing, Phong
+    highlight): ms per frame and counted (primary + AO) rays per second."""
     fr = tr.alloc_frame(cam, ("rgb",), stats=True)
     tr.render_into(gs, cam, p, fr, prec)
     torch.cuda.synchronize()
@@ -203,9 +200,7 @@ def antialias_measure(tr, torch, gs, cam, params, prec, aa: int = 4, frames: int
     ms = e0.elapsed_time(e1) / frames
     st = dict(zip(tr.STAT_NAMES, fr["stats"].cpu().tolist()))
     rays = (st["pixels"] + st["ao_rays"]) / frames
-    return {"workload": "protein-like 26,318 objects, 3860x4548, %d primary samples per pixel, "
-                        "16 AO samples each, FP32 + FP64 re-solve" % aa,
-            "aa_samples": aa, "ms_per_frame": ms, "frames_per_s": 1000.0 / ms,
+    return {"workload": workload, "ms_per_frame": ms, "frames_per_s": 1000.0 / ms,
             "rays_per_frame": rays, "rays_per_s": rays / (ms * 1e-3)}
 
 
@@ -340,8 +335,17 @@ def main():
         del f64
         log("fp64 plain path", fp64)
 
-    aa = antialias_measure(tr, torch, gs, cam, params, prec)
+    import dataclasses
+    aa = variant_measure(tr, torch, gs, cam, dataclasses.replace(params, aa_samples=4), prec,
+                         "protein-like 26,318 objects, 3860x4548, 4 primary samples per pixel, "
+                         "16 AO samples each, FP32 + FP64 re-solve")
+    aa["aa_samples"] = 4
     log("antialiased frame", aa)
+    spec = variant_measure(tr, torch, gs, cam,
+                           dataclasses.replace(params, specular=0.3, shininess=30.0), prec,
+                           "protein-like 26,318 objects, 3860x4548, 16 AO samples, Phong "
+                           "highlight k_s 0.3, n 30, FP32 + FP64 re-solve")
+    log("highlight frame", spec)
 
     frame_out = frame_output_measure(tr, torch, frame)
     log("frame output", frame_out)
@@ -387,6 +391,7 @@ def main():
         "render_only_rays_per_s": rays_frame / (render_ms.mean() * 1e-3),
         "fp64_plain": fp64,
         "antialias": aa,
+        "specular": spec,
         "frame_output": frame_out,
         "scene_ingest": ingest,
         "orbit": orbit,

@@ -115,6 +115,15 @@ typedef struct {
                                 stream, grown on demand with a synchronising
                                 hipMalloc); not with tile ranges or graphs.  A
                                 zero-filled struct of ABI 1 means one sample.  */
+  double specular;           /* Phong highlight strength k_s, finite, >= 0 (0 = none) */
+  double shininess;          /* Phong exponent n, finite, > 0 (read only if k_s > 0).
+                                The highlight (a shading option of the renderer
+                                the paper drives, not used in its runs) adds
+                                light_rescale * sum_l I_l V_l k_s max(0, R_l.V)^n,
+                                white, to the albedo-scaled colour before the
+                                clamp; R_l is the light direction mirrored about
+                                N, V the unit direction back to the eye, and the
+                                sum runs over the lights with N.L_l > 0. */
 } tr_params;
 
 /* Device output buffers, caller-owned.  Only rgb is required.
@@ -240,12 +249,14 @@ void tr_scene_destroy(tr_scene *scene);
  * shadow ray per light with N.L > 0, and params->ao_samples AO rays drawn
  * from the cosine-weighted hemisphere with Philox4x32-10 uniforms keyed by
  * (pixel, sample, view_id) and seed; colour = clamp(albedo * (light_rescale
- * * sum_l I_l (N.L_l) V_l + skylight * AO), 0, 1).  Enqueued on the
+ * * sum_l I_l (N.L_l) V_l + skylight * AO) + highlight, 0, 1) (highlight:
+ * tr_params.specular).  Enqueued on the
  * stream.  TR_EINVAL on a NULL scene/camera/params/frame->rgb, width or
  * height <= 0 or width*height >= 2^31, fovy outside (0, 180), eye == lookat,
  * up parallel to the view direction, non-finite camera, ao_samples outside
  * 0..65535, ao_maxdist <= 0, ao_mask requested with ao_samples > 32,
- * aa_samples outside 0..256, or an unknown precision; TR_ENOMEM when the
+ * aa_samples outside 0..256, specular negative or not finite, shininess not
+ * finite and > 0 while specular > 0, or an unknown precision; TR_ENOMEM when the
  * antialiasing workspace cannot be allocated. */
 tr_status tr_render(const tr_scene *scene, const tr_camera *cam, const tr_params *params,
                     const tr_frame *frame, void *hip_stream);

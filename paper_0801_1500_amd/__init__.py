@@ -52,7 +52,7 @@ class Params(C.Structure):
     _fields_ = [("light_rescale", C.c_double), ("skylight", C.c_double),
                 ("ao_samples", C.c_int32), ("ao_maxdist", C.c_double), ("seed", C.c_uint64),
                 ("view_id", C.c_uint32), ("precision", C.c_int32), ("background", C.c_float * 3),
-                ("aa_samples", C.c_int32)]
+                ("aa_samples", C.c_int32), ("specular", C.c_double), ("shininess", C.c_double)]
 
 
 class Frame(C.Structure):
@@ -153,7 +153,8 @@ def make_params(p, precision="fp32_resolve") -> Params:
     return Params(float(p.light_rescale), float(p.skylight), int(p.ao_samples),
                   float(p.ao_maxdist), int(p.seed) & ((1 << 64) - 1), int(p.view_id) & 0xFFFFFFFF,
                   prec, (C.c_float * 3)(*map(float, p.background)),
-                  int(getattr(p, "aa_samples", 1)))
+                  int(getattr(p, "aa_samples", 1)), float(getattr(p, "specular", 0.0)),
+                  float(getattr(p, "shininess", 20.0)))
 
 
 def make_tune(tune) -> Optional[Tune]:

@@ -172,6 +172,7 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
       }
       const int32_t skip = front ? k : -1;
       double D[3] = {0.0, 0.0, 0.0};
+      double Hs[3] = {0.0, 0.0, 0.0};  // Phong highlight (white, after the albedo)
       for (int l = 0; l < J.n_lights; ++l) {
         const double cl = dot3d(N, J.ldir[l]);
         if (!(cl > 0.0)) continue;
@@ -183,6 +184,18 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
         } else {
 #pragma unroll
           for (int ch = 0; ch < 3; ++ch) D[ch] += J.lcol[l][ch] * cl;
+          if (J.ks > 0.0) {
+            // light direction mirrored about N, against the way back to the eye
+            double R[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) R[q] = 2.0 * cl * N[q] - J.ldir[l][q];
+            const double rv = -dot3d(R, d);
+            if (rv > 0.0) {
+              const double f = J.ks * pow(rv, J.shin);
+#pragma unroll
+              for (int ch = 0; ch < 3; ++ch) Hs[ch] += J.lcol[l][ch] * f;
+            }
+          }
         }
       }
       double ao = 1.0;
@@ -207,7 +220,7 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
       const double albv[3] = {(double)alb.x, (double)alb.y, (double)alb.z};
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
-        const double v = albv[ch] * (D[ch] + J.sky * ao);
+        const double v = albv[ch] * (D[ch] + J.sky * ao) + Hs[ch];
         col[ch] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
       }
     }

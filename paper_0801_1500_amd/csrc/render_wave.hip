@@ -51,6 +51,7 @@ struct BankInfo {
   uint32_t key0, key1, view;
   int32_t aa;           // antialiasing sample index (0 = pixel centre)
   float maxd, sky;
+  float ks, shin;       // Phong highlight strength (0 = none) and exponent
   float eye[3], f[3], r[3], u[3], th, aspect;  // FP32 camera
   float rw2, rh2;       // 2 / W, 2 / H
   float rS;             // 1 / S (0 when S = 0)
@@ -457,20 +458,38 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
           lm = L.lmask[slot];
           am = L.aomask[slot];
           float Dr = 0.0f, Dg = 0.0f, Db = 0.0f;
+          float Hr = 0.0f, Hg = 0.0f, Hb = 0.0f;  // Phong highlight (white, after the albedo)
           for (int l = 0; l < B.n_lights; ++l) {
             if (!((lv >> l) & 1u) || ((lm >> l) & 1u)) continue;
             const float cl = Nx * B.ldir[l][0] + Ny * B.ldir[l][1] + Nz * B.ldir[l][2];
             Dr += B.lcol[l][0] * cl;
             Dg += B.lcol[l][1] * cl;
             Db += B.lcol[l][2] * cl;
+            if (B.ks > 0.0f) {
+              // light direction mirrored about N, against the way back to the eye
+              const float vx = B.eye[0] - L.px[slot], vy = B.eye[1] - L.py[slot],
+                          vz = B.eye[2] - L.pz[slot];
+              const float rv = ((2.0f * cl * Nx - B.ldir[l][0]) * vx +
+                                (2.0f * cl * Ny - B.ldir[l][1]) * vy +
+                                (2.0f * cl * Nz - B.ldir[l][2]) * vz) *
+                               __builtin_amdgcn_rsqf(vx * vx + vy * vy + vz * vz);
+              if (rv > 0.0f) {
+                // rv^n as 2^(n log2 rv) on the hardware log and exp (about
+                // 1 ulp each; rv <= 1, so the error is ~ n |log2 rv| ulp)
+                const float f = B.ks * __builtin_amdgcn_exp2f(B.shin * __builtin_amdgcn_logf(rv));
+                Hr += B.lcol[l][0] * f;
+                Hg += B.lcol[l][1] * f;
+                Hb += B.lcol[l][2] * f;
+              }
+            }
           }
           float ao = 1.0f;
           if (B.S > 0) ao = (float)(B.S - L.aocnt[slot]) * B.rS;
           const vf4 alb = ldg(S.albedo, (uint32_t)k);
           const float sk = B.sky * ao;
-          cr = fminf(fmaxf(alb.x * (Dr + sk), 0.0f), 1.0f);
-          cg = fminf(fmaxf(alb.y * (Dg + sk), 0.0f), 1.0f);
-          cb = fminf(fmaxf(alb.z * (Db + sk), 0.0f), 1.0f);
+          cr = fminf(fmaxf(alb.x * (Dr + sk) + Hr, 0.0f), 1.0f);
+          cg = fminf(fmaxf(alb.y * (Dg + sk) + Hg, 0.0f), 1.0f);
+          cb = fminf(fmaxf(alb.z * (Db + sk) + Hb, 0.0f), 1.0f);
         }
         float *rgb = B.rgb + pid * 3;
         rgb[0] = cr;
@@ -592,6 +611,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
             B.key1 = J->key1;
             B.view = J->view_id;
             B.aa = J->aa;
+            B.ks = J->ks32;
+            B.shin = J->shin32;
             B.maxd = J->ao_maxdist32;
             B.sky = J->sky32;
           }
@@ -631,14 +652,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
           const BankInfo &B = bank_of(L.bank, slot >> 6);
           int32_t pi, pj;
           bank_pixel(B, slot & 63, pi, pj);
+          // One Philox draw serves both uses (one inlined copy keeps register
+          // pressure down): an AO ray's direction, counter (pix, s, view, aa),
+          // or an antialiasing sample's position, counter (pix, aa, view,
+          // 0xFFFFFFFF); the two uniforms are the top 24 bits of words 0, 1.
+          uint32_t b1 = 0, b2 = 0;
+          if (kind == kAO || (kind == kPrimary && B.aa != 0)) {
+            const uint32_t pix = (uint32_t)(pj * B.W + pi);
+            const bool ao = kind == kAO;
+            const uint4 x = philox4x32_10(
+                make_uint4(pix, ao ? (uint32_t)ridx : (uint32_t)B.aa, B.view,
+                           ao ? (uint32_t)B.aa : 0xFFFFFFFFu),
+                B.key0, B.key1);
+            b1 = x.x >> 8;
+            b2 = x.y >> 8;
+          }
           if (kind == kPrimary) {
-            float fx = 0.5f, fy = 0.5f;  // position inside the pixel
-            if (B.aa != 0) {
-              uint32_t bx, by;
-              aa_offset_bits((uint32_t)(pj * B.W + pi), (uint32_t)B.aa, B.view, B.key0, B.key1, bx, by);
-              fx = (float)bx * 0x1p-24f;
-              fy = (float)by * 0x1p-24f;
-            }
+            // position inside the pixel: the centre for sample 0
+            const float fx = B.aa != 0 ? (float)b1 * 0x1p-24f : 0.5f;
+            const float fy = B.aa != 0 ? (float)b2 * 0x1p-24f : 0.5f;
             const float x = fmaf((float)pi + fx, B.rw2, -1.0f) * B.th * B.aspect;
             const float y = fmaf(-((float)pj + fy), B.rh2, 1.0f) * B.th;
             const float vx = B.f[0] + x * B.r[0] + y * B.u[0];
@@ -661,8 +693,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
             R.skip = L.skip[slot];
             R.tmin = kEps;
             if (kind == kAO) {
-              uint32_t b1, b2;
-              ao_uniform_bits((uint32_t)(pj * B.W + pi), (uint32_t)ridx, B.view, (uint32_t)B.aa, B.key0, B.key1, b1, b2);
               ao_dir_f32(L.nx[slot], L.ny[slot], L.nz[slot], b1, b2, R.dx, R.dy, R.dz);
               R.tmax = B.maxd;
             } else {

@@ -625,6 +625,10 @@ static tr_status check_params(const tr_params *p, const tr_frame *f) {
   if (f->ao_mask && p->ao_samples > 32) return fail(TR_EINVAL, "ao_mask needs ao_samples <= 32");
   if (p->aa_samples < 0 || p->aa_samples > kMaxAASamples)
     return fail(TR_EINVAL, "aa_samples must be 0..%d", kMaxAASamples);
+  if (!(p->specular >= 0.0) || !std::isfinite(p->specular))
+    return fail(TR_EINVAL, "specular must be finite and >= 0");
+  if (p->specular > 0.0 && !(p->shininess > 0.0 && std::isfinite(p->shininess)))
+    return fail(TR_EINVAL, "shininess must be finite and > 0 when specular > 0");
   if (p->precision < TR_PREC_FP64 || p->precision > TR_PREC_FP32_RESOLVE)
     return fail(TR_EINVAL, "unknown precision %d", p->precision);
   if (!std::isfinite(p->light_rescale) || !std::isfinite(p->skylight))
@@ -688,6 +692,10 @@ static tr_status make_job(const tr_scene *s, const tr_camera *c, const tr_params
   J.sky32 = (float)p->skylight;
   J.ao_maxdist = p->ao_maxdist;
   J.ao_maxdist32 = (float)p->ao_maxdist;
+  J.ks = p->specular;
+  J.shin = p->specular > 0.0 ? p->shininess : 1.0;
+  J.ks32 = (float)J.ks;
+  J.shin32 = (float)J.shin;
   J.key0 = (uint32_t)(p->seed & 0xFFFFFFFFull);
   J.key1 = (uint32_t)(p->seed >> 32);
   J.view_id = p->view_id;

@@ -62,7 +62,9 @@ struct JobDev {
   float lcol32[8][3];
   double sky;           // skylight
   double ao_maxdist;
+  double ks, shin;      // Phong highlight strength (0 = none) and exponent
   float sky32, ao_maxdist32;
+  float ks32, shin32;
   uint32_t key0, key1, view_id;
   int32_t resolve;      // FP64 re-solve of near-grazing tests
   float bg[3];
