@@ -47,7 +47,8 @@ class _Scene(C.Structure):
         ("sph_rgb", C.c_void_p),
         ("n_cylinders", C.c_int64), ("cyl_a", C.c_void_p), ("cyl_b", C.c_void_p),
         ("cyl_radius", C.c_void_p), ("cyl_rgb", C.c_void_p),
-        ("n_lights", C.c_int32), ("light_dir", C.c_void_p), ("light_rgb", C.c_void_p)]
+        ("n_lights", C.c_int32), ("light_dir", C.c_void_p), ("light_rgb", C.c_void_p),
+        ("sph_opacity", C.c_void_p), ("cyl_opacity", C.c_void_p)]
 
 
 class _Camera(C.Structure):
@@ -59,7 +60,8 @@ class _Params(C.Structure):
     _fields_ = [("light_rescale", C.c_double), ("skylight", C.c_double),
                 ("ao_samples", C.c_int32), ("ao_maxdist", C.c_double), ("seed", C.c_uint64),
                 ("view_id", C.c_uint32), ("background", C.c_double * 3),
-                ("aa_samples", C.c_int32), ("specular", C.c_double), ("shininess", C.c_double)]
+                ("aa_samples", C.c_int32), ("specular", C.c_double), ("shininess", C.c_double),
+                ("max_layers", C.c_int32)]
 
 
 def lib():
@@ -120,13 +122,17 @@ class OScene:
             cyl_radius=f64(scene.cyl_radius), cyl_rgb=f32(scene.cyl_rgb).reshape(-1, 3),
             light_dir=f64(scene.light_dir).reshape(-1, 3),
             light_rgb=f64(scene.light_rgb).reshape(-1, 3))
+        for key in ("sph_opacity", "cyl_opacity"):
+            v = getattr(scene, key, None)
+            self.arrays[key] = None if v is None else f32(v).reshape(-1)
         a = self.arrays
         self.n_spheres = a["sph_radius"].shape[0]
         self.n_cylinders = a["cyl_radius"].shape[0]
         self.c = _Scene(self.n_spheres, _ptr(a["sph_center"]), _ptr(a["sph_radius"]),
                         _ptr(a["sph_rgb"]), self.n_cylinders, _ptr(a["cyl_a"]), _ptr(a["cyl_b"]),
                         _ptr(a["cyl_radius"]), _ptr(a["cyl_rgb"]), a["light_dir"].shape[0],
-                        _ptr(a["light_dir"]), _ptr(a["light_rgb"]))
+                        _ptr(a["light_dir"]), _ptr(a["light_rgb"]),
+                        _ptr(a["sph_opacity"]), _ptr(a["cyl_opacity"]))
 
 
 def _as_oscene(scene) -> OScene:
@@ -144,7 +150,7 @@ def _params(p) -> _Params:
                    float(p.ao_maxdist), int(p.seed) & ((1 << 64) - 1), int(p.view_id),
                    (C.c_double * 3)(*[float(x) for x in p.background]),
                    int(getattr(p, "aa_samples", 1)), float(getattr(p, "specular", 0.0)),
-                   float(getattr(p, "shininess", 20.0)))
+                   float(getattr(p, "shininess", 20.0)), int(getattr(p, "max_layers", 0)))
 
 
 class Grid:

@@ -612,8 +612,17 @@ static float prim_albedo(const or_scene *s, int64_t k, int ch) {
   return s->cyl_rgb[3 * (k - s->n_spheres) + ch];
 }
 
-/* One primary sample: the ray through image position (px, py), its nearest
- * hit, direct light with shadow rays and AO, and the clamped colour. */
+/* Opacity of primitive k (1 = opaque; no array = all opaque). */
+static double prim_opacity(const or_scene *s, int64_t k) {
+  if (k < s->n_spheres) return s->sph_opacity ? (double)s->sph_opacity[k] : 1.0;
+  return s->cyl_opacity ? (double)s->cyl_opacity[k - s->n_spheres] : 1.0;
+}
+
+/* One primary sample: the ray through image position (px, py) and the
+ * clamped colour of what it sees.  Without transparency (max_layers <= 1)
+ * that is one surface: its nearest hit, direct light with shadow rays and
+ * AO.  With it, the ray composites up to max_layers surfaces front to back
+ * (see or_render); hit id, t and masks are those of the first surface. */
 typedef struct {
   double col[3];
   int hit;
@@ -624,34 +633,27 @@ typedef struct {
   uint8_t lmask;
 } sample_out;
 
-static void shade_sample(const or_scene *s, const or_grid *g, const or_params *p,
-                         const cam_basis *cb, const double ldir[8][3], int64_t pid, uint32_t a,
-                         double px, double py, sample_out *r, or_counters *loc) {
+/* Colour of the surface hit at t by the ray (o, d): shading normal facing
+ * the viewer, shadow rays, AO rays (counter word 1 = s + 2^16 * layer), the
+ * optional highlight; clamped.  Returns the masks and the hit point,
+ * normal and facing through the pointers. */
+static void shade_surface(const or_scene *s, const or_grid *g, const or_params *p,
+                          const double ldir[8][3], int64_t pid, uint32_t a, uint32_t layer,
+                          const double o[3], const double d[3], double t, int64_t k,
+                          double col[3], uint32_t *amask, int32_t *aocc, uint8_t *lmask,
+                          double P[3], int *front_out, or_counters *loc) {
   const int S = p->ao_samples;
   const int do_ao = (S > 0 && p->skylight > 0.0);
-  double o[3], d[3];
-  basis_ray_at(cb, px, py, o, d);
-  loc->primary_rays++;
-  double t;
-  int64_t k;
-  int hit = or_trace(s, g, o, d, 0.0, INFINITY, -1, 0, &t, &k, loc);
-  r->col[0] = p->background[0];
-  r->col[1] = p->background[1];
-  r->col[2] = p->background[2];
-  r->hit = hit;
-  r->k = hit ? k : -1;
-  r->t = hit ? t : INFINITY;
-  r->amask = 0;
-  r->aocc = 0;
-  r->lmask = 0;
-  if (!hit) return;
-  loc->hit_pixels++;
-  double N[3], P[3];
+  double N[3];
   or_normal(s, k, o, d, t, N);
   for (int c = 0; c < 3; ++c) P[c] = o[c] + t * d[c];
   int front = dot3(N, d) < 0.0;
   if (!front) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; }
+  *front_out = front;
   int64_t skip = front ? k : -1;
+  *amask = 0;
+  *aocc = 0;
+  *lmask = 0;
   double D[3] = {0.0, 0.0, 0.0};
   double Hs[3] = {0.0, 0.0, 0.0}; /* specular highlights (white, after albedo) */
   for (int l = 0; l < s->n_lights; ++l) {
@@ -659,14 +661,14 @@ static void shade_sample(const or_scene *s, const or_grid *g, const or_params *p
     if (!(c > 0.0)) continue;
     loc->shadow_rays++;
     if (or_trace(s, g, P, ldir[l], OR_EPS, INFINITY, skip, 1, NULL, NULL, loc)) {
-      r->lmask |= (uint8_t)(1u << l);
+      *lmask |= (uint8_t)(1u << l);
     } else {
       for (int ch = 0; ch < 3; ++ch) D[ch] += (p->light_rescale * s->light_rgb[3 * l + ch]) * c;
       if (p->specular > 0.0) {
         /* Phong: mirror the light direction about N, compare with the
          * direction back to the eye, -d */
         double R[3], rv;
-        for (int a = 0; a < 3; ++a) R[a] = 2.0 * c * N[a] - ldir[l][a];
+        for (int q = 0; q < 3; ++q) R[q] = 2.0 * c * N[q] - ldir[l][q];
         rv = -dot3(R, d);
         if (rv > 0.0) {
           double f = p->specular * pow(rv, p->shininess);
@@ -679,20 +681,75 @@ static void shade_sample(const or_scene *s, const or_grid *g, const or_params *p
   if (do_ao) {
     for (int smp = 0; smp < S; ++smp) {
       double u1, u2, w[3];
-      or_ao_uniforms_aa((uint32_t)pid, (uint32_t)smp, p->view_id, a, p->seed, &u1, &u2);
+      or_ao_uniforms_aa((uint32_t)pid, (uint32_t)smp + (layer << 16), p->view_id, a, p->seed,
+                        &u1, &u2);
       or_ao_direction(N, u1, u2, w);
       loc->ao_rays++;
       if (or_trace(s, g, P, w, OR_EPS, p->ao_maxdist, skip, 1, NULL, NULL, loc)) {
-        r->aocc++;
-        if (smp < 32) r->amask |= 1u << smp;
+        (*aocc)++;
+        if (smp < 32) *amask |= 1u << smp;
       }
     }
-    ao = (double)(S - r->aocc) / (double)S;
+    ao = (double)(S - *aocc) / (double)S;
   }
   for (int ch = 0; ch < 3; ++ch) {
     double v = (double)prim_albedo(s, k, ch) * (D[ch] + p->skylight * ao) + Hs[ch];
-    r->col[ch] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+    col[ch] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
   }
+}
+
+static void shade_sample(const or_scene *s, const or_grid *g, const or_params *p,
+                         const cam_basis *cb, const double ldir[8][3], int64_t pid, uint32_t a,
+                         double px, double py, sample_out *r, or_counters *loc) {
+  const int layers = p->max_layers > 1 ? p->max_layers : 1;
+  double o[3], d[3];
+  basis_ray_at(cb, px, py, o, d);
+  loc->primary_rays++;
+  r->hit = 0;
+  r->k = -1;
+  r->t = INFINITY;
+  r->amask = 0;
+  r->aocc = 0;
+  r->lmask = 0;
+  double acc[3] = {0.0, 0.0, 0.0};
+  double T = 1.0; /* transmittance in front of the current surface */
+  double tmin = 0.0;
+  int64_t skip = -1;
+  int layer = 0;
+  for (; layer < layers; ++layer) {
+    double t;
+    int64_t k;
+    if (!or_trace(s, g, o, d, tmin, INFINITY, skip, 0, &t, &k, loc)) break;
+    double col[3], P[3];
+    uint32_t am;
+    int32_t ac;
+    uint8_t lm;
+    int front;
+    shade_surface(s, g, p, ldir, pid, a, (uint32_t)layer, o, d, t, k, col, &am, &ac, &lm, P,
+                  &front, loc);
+    if (layer == 0) {
+      loc->hit_pixels++;
+      r->hit = 1;
+      r->k = k;
+      r->t = t;
+      r->amask = am;
+      r->aocc = ac;
+      r->lmask = lm;
+    }
+    const double alpha = layers > 1 ? prim_opacity(s, k) : 1.0;
+    for (int ch = 0; ch < 3; ++ch) acc[ch] += T * alpha * col[ch];
+    T *= 1.0 - alpha;
+    if (!(alpha < 1.0)) break;
+    /* continue through the surface: from the hit point, on the same line;
+     * an outward ray cannot re-enter the convex primitive it leaves, an
+     * inward one meets its far side */
+    for (int c = 0; c < 3; ++c) o[c] = P[c];
+    tmin = OR_EPS;
+    skip = front ? -1 : k;
+  }
+  /* what the last surface lets through (a miss, or the layer limit) is
+   * background */
+  for (int ch = 0; ch < 3; ++ch) r->col[ch] = acc[ch] + T * p->background[ch];
 }
 
 int or_render(const or_scene *s, const or_camera *cam, const or_params *p, const or_grid *g,

@@ -43,6 +43,8 @@ typedef struct {
   int32_t n_lights;
   const double *light_dir;  /* [n_lights*3] toward the light, any length */
   const double *light_rgb;  /* [n_lights*3] */
+  const float *sph_opacity; /* [n_spheres] in (0, 1], or NULL = opaque */
+  const float *cyl_opacity; /* [n_cylinders] in (0, 1], or NULL = opaque */
 } or_scene;
 
 typedef struct {
@@ -62,6 +64,8 @@ typedef struct {
   int32_t aa_samples;    /* primary samples per pixel; 0 or 1 = the pixel centre only */
   double specular;       /* Phong highlight strength k_s >= 0 (0 = none) */
   double shininess;      /* Phong exponent n > 0 */
+  int32_t max_layers;    /* transparency: surfaces composited per primary ray;
+                            0 or 1 = opaque rendering (opacities ignored) */
 } or_params;
 
 /* operation counts, used for the algorithmic flop model */
@@ -126,6 +130,15 @@ int or_trace(const or_scene *s, const or_grid *g, const double o[3], const doubl
  * masks, ao_occluded and t_hit are those of sample 0 (the pixel centre), and
  * the counters count every sample's rays (hit_pixels = primary samples that
  * hit).
+ * Transparency (max_layers = L > 1; the -trans_vmd option of the paper's
+ * rendering commands, Sec. 2): a primary ray that hits a primitive of
+ * opacity alpha < 1 continues through it from the hit point (t > 1e-4, on
+ * the same line; it skips that primitive only when leaving it), up to L
+ * surfaces.  Each surface is shaded as an opaque one (shadow and AO rays see
+ * every primitive as opaque; AO counter word 1 = s + 2^16 * layer), and the
+ * colour is sum_i (prod_{j<i} (1 - alpha_j)) alpha_i C_i plus the remaining
+ * transmittance times the background.  Hit id, t and masks are the first
+ * surface's.
  * Outputs are indexed by list position; any output pointer may be NULL.
  * n_threads <= 0 => OpenMP default.  Returns 0, or -1 on bad arguments. */
 int or_render(const or_scene *s, const or_camera *cam, const or_params *p, const or_grid *g,

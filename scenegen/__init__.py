@@ -46,6 +46,8 @@ class Scene:
     cyl_rgb: np.ndarray      # float32 [n_c, 3]
     light_dir: np.ndarray    # float64 [n_l, 3]  toward the light
     light_rgb: np.ndarray    # float64 [n_l, 3]
+    sph_opacity: Optional[np.ndarray] = None  # float32 [n_s] in (0, 1]; None = opaque
+    cyl_opacity: Optional[np.ndarray] = None  # float32 [n_c] in (0, 1]; None = opaque
 
     @property
     def n_spheres(self) -> int:
@@ -66,7 +68,7 @@ class Scene:
     def contiguous(self) -> "Scene":
         f = {}
         for k, v in dataclasses.asdict(self).items():
-            f[k] = np.ascontiguousarray(v)
+            f[k] = None if v is None else np.ascontiguousarray(v)
         return Scene(**f)
 
 
@@ -97,6 +99,7 @@ class Params:
     aa_samples: int = 1    # primary samples per pixel (antialiasing); 1 = pixel centre
     specular: float = 0.0  # Phong highlight strength (0 = none)
     shininess: float = 20.0  # Phong exponent
+    max_layers: int = 0    # transparency: surfaces per primary ray (0, 1 = opaque rendering)
 
 
 def _empty3(dtype=np.float64):
