@@ -346,6 +346,14 @@ def main():
                            "protein-like 26,318 objects, 3860x4548, 16 AO samples, Phong "
                            "highlight k_s 0.3, n 30, FP32 + FP64 re-solve")
     log("highlight frame", spec)
+    glass = tr.Scene(scenegen.Scene(**{**scene.__dict__, "sph_opacity":
+                                       np.full(scene.n_spheres, 0.5, np.float32)}))
+    trans = variant_measure(tr, torch, glass, cam, dataclasses.replace(params, max_layers=4), prec,
+                            "protein-like 26,318 objects, spheres at opacity 0.5 (cylinders "
+                            "opaque), up to 4 surfaces per pixel, 3860x4548, 16 AO samples per "
+                            "surface, FP32 + FP64 re-solve")
+    del glass
+    log("transparent frame", trans)
 
     frame_out = frame_output_measure(tr, torch, frame)
     log("frame output", frame_out)
@@ -392,6 +400,7 @@ def main():
         "fp64_plain": fp64,
         "antialias": aa,
         "specular": spec,
+        "transparency": trans,
         "frame_output": frame_out,
         "scene_ingest": ingest,
         "orbit": orbit,

@@ -80,6 +80,9 @@ typedef struct {
   const double *light_dir;   /* [n_lights*3] toward the light; normalised by the library */
   const double *light_rgb;   /* [n_lights*3] intensity                      */
   double cells_per_prim;     /* grid density lambda; 0 => 24.  Speed only.  */
+  const float *sph_opacity;  /* [n_spheres] opacity in (0, 1], or NULL = opaque */
+  const float *cyl_opacity;  /* [n_cylinders] opacity in (0, 1], or NULL = opaque;
+                                used only by renders with tr_params.max_layers > 1 */
 } tr_scene_desc;
 
 /* Pinhole camera, one ray through each pixel centre (more with
@@ -124,6 +127,18 @@ typedef struct {
                                 clamp; R_l is the light direction mirrored about
                                 N, V the unit direction back to the eye, and the
                                 sum runs over the lights with N.L_l > 0. */
+  int32_t max_layers;        /* transparency (the -trans_vmd option, Sec. 2),
+                                0..64; 0 and 1 = opaque rendering.  With L > 1 a
+                                primary ray that hits a primitive of opacity
+                                alpha < 1 continues through it from the hit
+                                point (t > 1e-4, same line, skipping it only when
+                                leaving it), up to L surfaces; each surface is
+                                shaded as an opaque one (shadow and AO rays see
+                                all primitives as opaque; AO counter word 1 =
+                                s + 2^16 * layer) and the pixel is
+                                sum_i (prod_{j<i} (1 - alpha_j)) alpha_i C_i plus
+                                the remaining transmittance times background.
+                                hit_id and the masks are the first surface's. */
 } tr_params;
 
 /* Device output buffers, caller-owned.  Only rgb is required.
@@ -214,10 +229,12 @@ tr_status tr_scene_grid_arrays(const tr_scene *scene, uint32_t *cell_begin, uint
 
 /* Binary scene files (the "Parse" phase of Table 5, for which the paper gives
  * no format).  Little-endian: char magic[8] = "TRSCENE1"; int64 n_spheres,
- * n_cylinders; int32 n_lights, int32 0; double cells_per_prim; then the
+ * n_cylinders; int32 n_lights, int32 flags; double cells_per_prim; then the
  * arrays of tr_scene_desc in its order (sph_center, sph_radius, sph_rgb,
  * cyl_a, cyl_b, cyl_radius, cyl_rgb, light_dir, light_rgb), each padded to a
- * multiple of 8 bytes.
+ * multiple of 8 bytes; with flags bit 0 (written when some opacity is below
+ * 1) then sph_opacity and cyl_opacity, padded likewise.  Other flag bits
+ * must be 0.
  * tr_scene_save writes the description the scene was built from (the FP64
  * arrays, albedo, the lights as given, the grid density); synchronises the
  * stream; TR_EINVAL on a NULL argument or a failed write.

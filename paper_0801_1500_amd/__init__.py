@@ -40,7 +40,7 @@ class SceneDesc(C.Structure):
         ("n_cylinders", C.c_int64), ("cyl_a", C.c_void_p), ("cyl_b", C.c_void_p),
         ("cyl_radius", C.c_void_p), ("cyl_rgb", C.c_void_p),
         ("n_lights", C.c_int32), ("light_dir", C.c_void_p), ("light_rgb", C.c_void_p),
-        ("cells_per_prim", C.c_double)]
+        ("cells_per_prim", C.c_double), ("sph_opacity", C.c_void_p), ("cyl_opacity", C.c_void_p)]
 
 
 class Camera(C.Structure):
@@ -52,7 +52,8 @@ class Params(C.Structure):
     _fields_ = [("light_rescale", C.c_double), ("skylight", C.c_double),
                 ("ao_samples", C.c_int32), ("ao_maxdist", C.c_double), ("seed", C.c_uint64),
                 ("view_id", C.c_uint32), ("precision", C.c_int32), ("background", C.c_float * 3),
-                ("aa_samples", C.c_int32), ("specular", C.c_double), ("shininess", C.c_double)]
+                ("aa_samples", C.c_int32), ("specular", C.c_double), ("shininess", C.c_double),
+                ("max_layers", C.c_int32)]
 
 
 class Frame(C.Structure):
@@ -154,7 +155,7 @@ def make_params(p, precision="fp32_resolve") -> Params:
                   float(p.ao_maxdist), int(p.seed) & ((1 << 64) - 1), int(p.view_id) & 0xFFFFFFFF,
                   prec, (C.c_float * 3)(*map(float, p.background)),
                   int(getattr(p, "aa_samples", 1)), float(getattr(p, "specular", 0.0)),
-                  float(getattr(p, "shininess", 20.0)))
+                  float(getattr(p, "shininess", 20.0)), int(getattr(p, "max_layers", 0)))
 
 
 def make_tune(tune) -> Optional[Tune]:
@@ -177,10 +178,13 @@ class Scene:
         arrs = [f64(scene.sph_center), f64(scene.sph_radius), f32(scene.sph_rgb),
                 f64(scene.cyl_a), f64(scene.cyl_b), f64(scene.cyl_radius), f32(scene.cyl_rgb),
                 f64(scene.light_dir), f64(scene.light_rgb)]
+        ops = [getattr(scene, k, None) for k in ("sph_opacity", "cyl_opacity")]
+        ops = [None if o is None else f32(o).reshape(-1) for o in ops]
+        arrs += [o if o is not None else np.zeros(0, np.float32) for o in ops]
         p = [a.ctypes.data if a.size else None for a in arrs]
         desc = SceneDesc(int(arrs[1].shape[0]), p[0], p[1], p[2], int(arrs[5].shape[0]), p[3],
                          p[4], p[5], p[6], int(arrs[7].reshape(-1, 3).shape[0]), p[7], p[8],
-                         float(cells_per_prim))
+                         float(cells_per_prim), p[9], p[10])
         h = C.c_void_p()
         _check(lib().tr_scene_build(C.byref(desc), _stream(stream), C.byref(h)))
         self.handle = h

@@ -95,13 +95,13 @@ __device__ __forceinline__ void for_prim_cells(const trh::BuildArgs &a, int64_t 
 }
 
 __global__ void k_pack(int64_t n_s, int64_t n_c, const double *sc, const double *sr,
-                       const float *srgb, const double *ca, const double *cb, const double *cr,
-                       const float *crgb, double4 *sph64, double4 *cylA64, double4 *cylW64,
-                       double4 *cylB64, float4 *albedo) {
+                       const float *srgb, const float *sop, const double *ca, const double *cb,
+                       const double *cr, const float *crgb, const float *cop, double4 *sph64,
+                       double4 *cylA64, double4 *cylW64, double4 *cylB64, float4 *albedo) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n_s) {
     sph64[k] = make_double4(sc[3 * k], sc[3 * k + 1], sc[3 * k + 2], sr[k]);
-    albedo[k] = make_float4(srgb[3 * k], srgb[3 * k + 1], srgb[3 * k + 2], 0.0f);
+    albedo[k] = make_float4(srgb[3 * k], srgb[3 * k + 1], srgb[3 * k + 2], sop ? sop[k] : 1.0f);
   } else if (k < n_s + n_c) {
     const int64_t m = k - n_s;
     const double a[3] = {ca[3 * m], ca[3 * m + 1], ca[3 * m + 2]};
@@ -111,7 +111,7 @@ __global__ void k_pack(int64_t n_s, int64_t n_c, const double *sc, const double 
     cylA64[m] = make_double4(a[0], a[1], a[2], cr[m]);
     cylW64[m] = make_double4(ab[0] / L, ab[1] / L, ab[2] / L, L);
     cylB64[m] = make_double4(b[0], b[1], b[2], 0.0);
-    albedo[k] = make_float4(crgb[3 * m], crgb[3 * m + 1], crgb[3 * m + 2], 0.0f);
+    albedo[k] = make_float4(crgb[3 * m], crgb[3 * m + 1], crgb[3 * m + 2], cop ? cop[m] : 1.0f);
   }
 }
 
@@ -412,13 +412,14 @@ inline unsigned blocks_for(int64_t n, int b = kBlock) {
 namespace trh {
 
 hipError_t launch_pack(int64_t n_s, int64_t n_c, const double *sc, const double *sr,
-                       const float *srgb, const double *ca, const double *cb, const double *cr,
-                       const float *crgb, double4 *sph64, double4 *cylA64, double4 *cylW64,
-                       double4 *cylB64, float4 *albedo, hipStream_t st) {
+                       const float *srgb, const float *sop, const double *ca, const double *cb,
+                       const double *cr, const float *crgb, const float *cop, double4 *sph64,
+                       double4 *cylA64, double4 *cylW64, double4 *cylB64, float4 *albedo,
+                       hipStream_t st) {
   const int64_t N = n_s + n_c;
   if (N == 0) return hipSuccess;
-  k_pack<<<blocks_for(N), kBlock, 0, st>>>(n_s, n_c, sc, sr, srgb, ca, cb, cr, crgb, sph64, cylA64,
-                                           cylW64, cylB64, albedo);
+  k_pack<<<blocks_for(N), kBlock, 0, st>>>(n_s, n_c, sc, sr, srgb, sop, ca, cb, cr, crgb, cop,
+                                           sph64, cylA64, cylW64, cylB64, albedo);
   return hipGetLastError();
 }
 

@@ -152,14 +152,27 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
     const int64_t pid = (int64_t)j * J.W + i;
     double o[3], d[3];
     primary_ray_f64(J, i, j, o, d);
-    double t;
-    int32_t k;
-    const int hit = trace_f64<false>(S, o, d, 0.0, INFINITY, -1, t, k, c);
-    double col[3] = {(double)J.bg[0], (double)J.bg[1], (double)J.bg[2]};
+    // Surfaces along the primary ray, front to back: one for opaque
+    // rendering; with layers, the ray continues through a primitive of
+    // opacity < 1 from the hit point (skipping it only when leaving it) and
+    // the colours composite by the transmittance in front of each surface.
+    double acc[3] = {0.0, 0.0, 0.0};
+    double T = 1.0;
+    double tmin = 0.0;
+    int32_t pskip = -1;
+    int hit = 0;
+    int32_t k0 = -1;
     uint32_t amask = 0;
     uint32_t lmask = 0;
-    if (hit) {
-      n_hit = 1;
+    for (int32_t layer = 0; layer < J.layers; ++layer) {
+      double t;
+      int32_t k;
+      if (!trace_f64<false>(S, o, d, tmin, INFINITY, pskip, t, k, c)) break;
+      if (layer == 0) {
+        hit = 1;
+        k0 = k;
+        n_hit = 1;
+      }
       double N[3], P[3];
       normal_f64(S, k, o, d, t, N);
 #pragma unroll
@@ -171,6 +184,7 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
         N[2] = -N[2];
       }
       const int32_t skip = front ? k : -1;
+      uint32_t am = 0, lm = 0;
       double D[3] = {0.0, 0.0, 0.0};
       double Hs[3] = {0.0, 0.0, 0.0};  // Phong highlight (white, after the albedo)
       for (int l = 0; l < J.n_lights; ++l) {
@@ -180,7 +194,7 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
         double tt;
         int32_t kk;
         if (trace_f64<true>(S, P, J.ldir[l], kEps, INFINITY, skip, tt, kk, c)) {
-          lmask |= 1u << l;
+          lm |= 1u << l;
         } else {
 #pragma unroll
           for (int ch = 0; ch < 3; ++ch) D[ch] += J.lcol[l][ch] * cl;
@@ -203,7 +217,8 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
         int32_t aocc = 0;
         for (int s = 0; s < J.S; ++s) {
           uint32_t b1, b2;
-          ao_uniform_bits((uint32_t)pid, (uint32_t)s, J.view_id, (uint32_t)J.aa, J.key0, J.key1, b1, b2);
+          ao_uniform_bits((uint32_t)pid, (uint32_t)s + ((uint32_t)layer << 16), J.view_id,
+                          (uint32_t)J.aa, J.key0, J.key1, b1, b2);
           double w[3];
           ao_dir_f64(N, b1, b2, w);
           n_ao++;
@@ -211,23 +226,37 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
           int32_t kk;
           if (trace_f64<true>(S, P, w, kEps, J.ao_maxdist, skip, tt, kk, c)) {
             aocc++;
-            if (s < 32) amask |= 1u << s;
+            if (s < 32) am |= 1u << s;
           }
         }
         ao = (double)(J.S - aocc) / (double)J.S;
       }
+      if (layer == 0) {
+        amask = am;
+        lmask = lm;
+      }
       const float4 alb = S.albedo[k];
       const double albv[3] = {(double)alb.x, (double)alb.y, (double)alb.z};
+      const double alpha = J.layers > 1 ? (double)alb.w : 1.0;
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         const double v = albv[ch] * (D[ch] + J.sky * ao) + Hs[ch];
-        col[ch] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+        acc[ch] += T * alpha * (v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v));
       }
+      T *= 1.0 - alpha;
+      if (!(alpha < 1.0)) break;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) o[q] = P[q];
+      tmin = kEps;
+      pskip = front ? -1 : k;
     }
+    double col[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) col[ch] = acc[ch] + T * (double)J.bg[ch];
     J.rgb[pid * 3 + 0] = (float)col[0];
     J.rgb[pid * 3 + 1] = (float)col[1];
     J.rgb[pid * 3 + 2] = (float)col[2];
-    if (J.hit_id) J.hit_id[pid] = hit ? k : -1;
+    if (J.hit_id) J.hit_id[pid] = hit ? k0 : -1;
     if (J.ao_mask) J.ao_mask[pid] = amask;
     if (J.light_mask) J.light_mask[pid] = (uint8_t)lmask;
     if (STATS) {

@@ -39,7 +39,9 @@ constexpr float kEps = 1e-4f;
 constexpr float kKappa = 1.0f / 4096.0f;
 constexpr double kEpsD = 1e-4;
 
-enum : int32_t { kIdle = 0, kPrimary = 1, kShadow = 2, kAO = 3 };
+// Ray kinds.  kCont continues a primary ray through a transparent surface
+// (nearest hit, from the hit point); kinds >= kShadow are any-hit rays.
+enum : int32_t { kIdle = 0, kPrimary = 1, kCont = 2, kShadow = 3, kAO = 4 };
 // lane state of the ray it holds (an idle lane counts as finished)
 enum : int32_t { kRun = 0, kDone = 1, kPaused = 2 };
 
@@ -52,6 +54,7 @@ struct BankInfo {
   int32_t aa;           // antialiasing sample index (0 = pixel centre)
   float maxd, sky;
   float ks, shin;       // Phong highlight strength (0 = none) and exponent
+  int32_t layers;       // surfaces composited per primary ray (1 = opaque)
   float eye[3], f[3], r[3], u[3], th, aspect;  // FP32 camera
   float rw2, rh2;       // 2 / W, 2 / H
   float rS;             // 1 / S (0 when S = 0)
@@ -78,9 +81,10 @@ __device__ __forceinline__ void bank_pixel(const BankInfo &B, int32_t q, int32_t
   y = B.y0 + qy;
 }
 
-template <int BANKS>
+template <int BANKS, bool TRANS>
 struct Lds {
   static constexpr int NS = BANKS * 64;
+  static constexpr int NT = TRANS ? NS : 1;  // transparency state only when compositing
   float px[NS], py[NS], pz[NS];
   float nx[NS], ny[NS], nz[NS];
   int32_t prim[NS];     // hit primitive
@@ -94,6 +98,11 @@ struct Lds {
   uint8_t fifo[NS];
   BankInfo bank[BANKS];
   uint32_t cnt[11];
+  // compositing across surfaces: colour so far, transmittance in front of the
+  // current surface, its index, and whether the FIFO entry is a continuation
+  float acc_r[NT], acc_g[NT], acc_b[NT], trn[NT];
+  uint8_t layer[NT];
+  uint8_t cont[NT];
 };
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
@@ -275,9 +284,11 @@ __device__ __forceinline__ int32_t find_job(const TR_CONST JobDev *jobs, int32_t
   return lo;
 }
 
-template <int BANKS, bool RESOLVE, bool COUNT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 && !COUNT ? 5 : 4))) void k_render_wave(const WaveArgs A) {
-  __shared__ Lds<BANKS> L;
+template <int BANKS, bool RESOLVE, bool COUNT, bool TRANS>
+// Occupancy targets: 5 waves per SIMD for the plain two-bank kernel (96
+// VGPRs); compositing adds LDS state that allows fewer waves anyway.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : (BANKS == 2 && !COUNT ? 5 : 4)))) void k_render_wave(const WaveArgs A) {
+  __shared__ Lds<BANKS, TRANS> L;
   constexpr int NS = BANKS * 64;
   constexpr int kMinIters = 2;
   const int32_t lane = threadIdx.x;
@@ -347,7 +358,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
         int32_t nst = kRun;
         if (h) {
           const float tf = (float)t;
-          if (kind != kPrimary) {
+          if (kind >= kShadow) {
             R.bk = gk;
             R.bt = tf;
             nst = kDone;
@@ -363,8 +374,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
     // ================================================================ finish
     if (ballot(kind != kIdle && st == kDone)) {
       const bool fin = kind != kIdle && st == kDone;
-      const bool fin_prim_hit = fin && kind == kPrimary && R.bk >= 0;
-      const bool fin_prim_miss = fin && kind == kPrimary && R.bk < 0;
+      const bool nearest = kind == kPrimary || kind == kCont;
+      const bool fin_prim_hit = fin && nearest && R.bk >= 0;
+      const bool fin_prim_miss = fin && nearest && R.bk < 0;
       bool finalize = fin_prim_miss;
       uint32_t nr = 0;
       // every bank in flight renders the wave's current scene
@@ -420,6 +432,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
         L.aomask[slot] = 0;
         L.aocnt[slot] = 0;
         L.lmask[slot] = 0;
+        if (TRANS) L.cont[slot] = 0;
         if (nr == 0) finalize = true;
       }
       {  // queue hit slots that have secondary rays
@@ -441,7 +454,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
         if (old == 1) finalize = true;
       }
       __syncthreads();
+      bool cont_next = false;  // the pixel goes on through a transparent surface
+      int32_t layer = 0;
       if (finalize) {
+        float alpha = 1.0f;
         const int32_t bk = slot >> 6;
         BankInfo &B = bank_of(L.bank, bk);
         int32_t x, y;
@@ -490,19 +506,59 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
           cr = fminf(fmaxf(alb.x * (Dr + sk) + Hr, 0.0f), 1.0f);
           cg = fminf(fmaxf(alb.y * (Dg + sk) + Hg, 0.0f), 1.0f);
           cb = fminf(fmaxf(alb.z * (Db + sk) + Hb, 0.0f), 1.0f);
+          if (TRANS && B.layers > 1) alpha = alb.w;
         }
-        float *rgb = B.rgb + pid * 3;
-        rgb[0] = cr;
-        rgb[1] = cg;
-        rgb[2] = cb;
-        if (B.hit_id) B.hit_id[pid] = hid;
-        if (B.ao_mask) B.ao_mask[pid] = am;
-        if (B.light_mask) B.light_mask[pid] = (uint8_t)lm;
-        atomicAdd(&B.done, 1);
+        if (TRANS) layer = L.layer[slot];
+        if (!TRANS || layer == 0) {  // hit id and masks: the first surface's
+          if (B.hit_id) B.hit_id[pid] = hid;
+          if (B.ao_mask) B.ao_mask[pid] = am;
+          if (B.light_mask) B.light_mask[pid] = (uint8_t)lm;
+        }
+        if (TRANS) {
+          // composite front to back; what is left after the last surface (a
+          // miss counts as an opaque background surface) shows the background
+          const float T = layer ? L.trn[slot] : 1.0f;
+          float ar = layer ? L.acc_r[slot] : 0.0f, ag = layer ? L.acc_g[slot] : 0.0f,
+                ab = layer ? L.acc_b[slot] : 0.0f;
+          ar += T * alpha * cr;
+          ag += T * alpha * cg;
+          ab += T * alpha * cb;
+          const float Tn = T * (1.0f - alpha);
+          if (alpha < 1.0f && layer + 1 < B.layers) {
+            // continue through the surface: one more nearest-hit ray from the
+            // hit point, skipping the primitive only when leaving it
+            L.acc_r[slot] = ar;
+            L.acc_g[slot] = ag;
+            L.acc_b[slot] = ab;
+            L.trn[slot] = Tn;
+            L.layer[slot] = (uint8_t)(layer + 1);
+            L.skip[slot] = L.skip[slot] >= 0 ? -1 : L.prim[slot];
+            L.nrays[slot] = 1;
+            L.pending[slot] = 1;
+            L.cont[slot] = 1;
+            cont_next = true;
+          } else {
+            cr = ar + Tn * B.bg[0];
+            cg = ag + Tn * B.bg[1];
+            cb = ab + Tn * B.bg[2];
+          }
+        }
+        if (!cont_next) {
+          float *rgb = B.rgb + pid * 3;
+          rgb[0] = cr;
+          rgb[1] = cg;
+          rgb[2] = cb;
+          atomicAdd(&B.done, 1);
+        }
+      }
+      if (TRANS) {  // continuations join the FIFO like slots with secondary rays
+        const uint64_t m = ballot(cont_next);
+        if (cont_next) L.fifo[(q_tail + (int32_t)lane_rank(m)) % NS] = (uint8_t)slot;
+        q_tail += __popcll(m);
       }
       {  // pixel counters live in LDS (registers are the scarce resource here)
-        const uint32_t n_fin = (uint32_t)__popcll(ballot(finalize));
-        const uint32_t n_hit = (uint32_t)__popcll(ballot(finalize && !fin_prim_miss));
+        const uint32_t n_fin = (uint32_t)__popcll(ballot(finalize && !cont_next));
+        const uint32_t n_hit = (uint32_t)__popcll(ballot(finalize && !fin_prim_miss && layer == 0));
         if (A.stats && lane == 0) {
           L.cnt[0] += n_fin;
           L.cnt[1] += n_hit;
@@ -531,17 +587,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
       int32_t assigned = 0;
       // pass 1 -- assignment only: secondary rays from the FIFO, then fresh
       // primary rays; each idle lane learns (kind, slot, ray index)
-      int32_t n_ao = 0;  // AO rays among the secondary rays issued this round
+      int32_t n_ao = 0;    // AO rays among the secondary rays issued this round
+      int32_t n_cont = 0;  // continuations through transparent surfaces
       while (assigned < n_idle && q_head != q_tail) {
         const int32_t s = uni((int32_t)L.fifo[q_head % NS]);
         const int32_t nr = uni(L.nrays[s]);
-        const int32_t S_s = uni(L.bank[s >> 6].S);
+        const bool cs = TRANS && uni((int32_t)L.cont[s]) != 0;
+        const int32_t S_s = cs ? 0 : uni(L.bank[s >> 6].S);
         const int32_t take = min(nr - head_issued, n_idle - assigned);
         if (me_idle && rank >= assigned && rank < assigned + take) {
           slot = s;
           ridx = head_issued + (rank - assigned);
-          kind = ridx < S_s ? kAO : kShadow;
+          kind = cs ? kCont : (ridx < S_s ? kAO : kShadow);
         }
+        if (cs) n_cont += take;
         n_ao += max(0, min(S_s - head_issued, take));  // ray indices < S are AO
         head_issued += take;
         assigned += take;
@@ -552,7 +611,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
       }
       if (A.stats && lane == 0 && assigned > 0) {  // ray counters live in LDS
         L.cnt[2] += (uint32_t)n_ao;
-        L.cnt[3] += (uint32_t)(assigned - n_ao);
+        L.cnt[3] += (uint32_t)(assigned - n_ao - n_cont);
       }
       while (assigned < n_idle) {
         if (issue_bank < 0 || issue_next == uni(L.bank[issue_bank].n)) {
@@ -613,6 +672,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
             B.aa = J->aa;
             B.ks = J->ks32;
             B.shin = J->shin32;
+            B.layers = J->layers;
             B.maxd = J->ao_maxdist32;
             B.sky = J->sky32;
           }
@@ -657,17 +717,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
           // or an antialiasing sample's position, counter (pix, aa, view,
           // 0xFFFFFFFF); the two uniforms are the top 24 bits of words 0, 1.
           uint32_t b1 = 0, b2 = 0;
-          if (kind == kAO || (kind == kPrimary && B.aa != 0)) {
+          const bool cam_dir = kind == kPrimary || kind == kCont;  // along the camera ray
+          if (kind == kAO || (cam_dir && B.aa != 0)) {
             const uint32_t pix = (uint32_t)(pj * B.W + pi);
             const bool ao = kind == kAO;
+            // AO streams of later surfaces: word 1 = s + 2^16 * layer
+            const uint32_t s_ao = (uint32_t)ridx + (TRANS ? (uint32_t)L.layer[slot] << 16 : 0u);
             const uint4 x = philox4x32_10(
-                make_uint4(pix, ao ? (uint32_t)ridx : (uint32_t)B.aa, B.view,
+                make_uint4(pix, ao ? s_ao : (uint32_t)B.aa, B.view,
                            ao ? (uint32_t)B.aa : 0xFFFFFFFFu),
                 B.key0, B.key1);
             b1 = x.x >> 8;
             b2 = x.y >> 8;
           }
-          if (kind == kPrimary) {
+          if (cam_dir) {
             // position inside the pixel: the centre for sample 0
             const float fx = B.aa != 0 ? (float)b1 * 0x1p-24f : 0.5f;
             const float fy = B.aa != 0 ? (float)b2 * 0x1p-24f : 0.5f;
@@ -680,12 +743,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
             R.dx = vx * inv;
             R.dy = vy * inv;
             R.dz = vz * inv;
-            R.ox = B.eye[0];
-            R.oy = B.eye[1];
-            R.oz = B.eye[2];
-            R.tmin = 0.0f;
             R.tmax = INFINITY;
-            R.skip = -1;
+            if (TRANS && kind == kCont) {  // on from the surface it went through
+              R.ox = L.px[slot];
+              R.oy = L.py[slot];
+              R.oz = L.pz[slot];
+              R.tmin = kEps;
+              R.skip = L.skip[slot];
+            } else {
+              R.ox = B.eye[0];
+              R.oy = B.eye[1];
+              R.oz = B.eye[2];
+              R.tmin = 0.0f;
+              R.skip = -1;
+              if (TRANS) L.layer[slot] = 0;
+            }
           } else {
             R.ox = L.px[slot];
             R.oy = L.py[slot];
@@ -737,7 +809,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BANKS == 2 &
           (free_banks && ((held_tile < 0 && tiles_left) || (held_tile >= 0 && (held_key == cur_key || !bank_busy))));
       const SceneHot H = load_hot(&A.jobs[uni(scene_job)]);
       const int32_t thresh = uni(can_refill ? A.refill_below : 1);
-      const bool anyhit = kind != kPrimary;
+      const bool anyhit = kind >= kShadow;
       const uint64_t cyc0 = COUNT ? clock64() : 0;
       for (int32_t it = 0;; ++it) {
         const bool work = st == kRun;
@@ -976,7 +1048,7 @@ __global__ void k_debug_ao_dirs(int64_t n, const float *nrm, const uint32_t *pix
 
 namespace trh {
 
-template <int BANKS, bool RES, bool CNT>
+template <int BANKS, bool RES, bool CNT, bool TRANS>
 static hipError_t launch_t(const WaveLaunch &L, hipStream_t st) {
   WaveArgs a;
   a.jobs = L.jobs;
@@ -988,15 +1060,21 @@ static hipError_t launch_t(const WaveLaunch &L, hipStream_t st) {
   a.refill_below = L.refill_below;
   a.cyl_wait = L.cyl_wait;
   a.mix = L.mix;
-  k_render_wave<BANKS, RES, CNT><<<L.n_waves, 64, 0, st>>>(a);
+  k_render_wave<BANKS, RES, CNT, TRANS><<<L.n_waves, 64, 0, st>>>(a);
   return hipGetLastError();
+}
+
+template <int BANKS, bool TRANS>
+static hipError_t launch_bt(const WaveLaunch &L, hipStream_t st) {
+  const bool cnt = L.count_ops != 0 && L.stats != nullptr;
+  if (L.resolve)
+    return cnt ? launch_t<BANKS, true, true, TRANS>(L, st) : launch_t<BANKS, true, false, TRANS>(L, st);
+  return cnt ? launch_t<BANKS, false, true, TRANS>(L, st) : launch_t<BANKS, false, false, TRANS>(L, st);
 }
 
 template <int BANKS>
 static hipError_t launch_b(const WaveLaunch &L, hipStream_t st) {
-  const bool cnt = L.count_ops != 0 && L.stats != nullptr;
-  if (L.resolve) return cnt ? launch_t<BANKS, true, true>(L, st) : launch_t<BANKS, true, false>(L, st);
-  return cnt ? launch_t<BANKS, false, true>(L, st) : launch_t<BANKS, false, false>(L, st);
+  return L.trans ? launch_bt<BANKS, true>(L, st) : launch_bt<BANKS, false>(L, st);
 }
 
 hipError_t launch_render_wave(const WaveLaunch &L, hipStream_t st) {

@@ -74,6 +74,7 @@ struct tr_scene {
   trh::GridParams gp{};
   int64_t n_refs = 0;
   bool grid_ok = false;  // false after a failed (re)build: the scene cannot render
+  bool has_trans = false;  // some primitive has opacity < 1 (kept in albedo.w)
   double org[3] = {0, 0, 0};  // origin of the FP32 frame: centre of the grid box
   SceneDev dev{};
 };
@@ -294,6 +295,15 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
     if (a[0] == b[0] && a[1] == b[1] && a[2] == b[2])
       return fail(TR_EINVAL, "cylinder %lld: zero length", (long long)k);
   }
+  bool has_trans = false;
+  for (int64_t k = 0; k < d->n_spheres + d->n_cylinders; ++k) {
+    const float *op = k < d->n_spheres ? d->sph_opacity : d->cyl_opacity;
+    if (!op) continue;
+    const float a = op[k < d->n_spheres ? k : k - d->n_spheres];
+    if (!(a > 0.0f && a <= 1.0f))
+      return fail(TR_EINVAL, "primitive %lld: opacity must be in (0, 1]", (long long)k);
+    has_trans |= a < 1.0f;
+  }
   for (int l = 0; l < d->n_lights; ++l) {
     const double *v = d->light_dir + 3 * l;
     if (!finite3(v) || !finite3(d->light_rgb + 3 * l)) return fail(TR_EINVAL, "light %d: non-finite", l);
@@ -309,6 +319,7 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   s->n_s = d->n_spheres;
   s->n_c = d->n_cylinders;
   s->n_lights = d->n_lights;
+  s->has_trans = has_trans;
   s->lambda = d->cells_per_prim > 0.0 ? d->cells_per_prim : 24.0;
   for (int l = 0; l < d->n_lights; ++l) {
     const double *v = d->light_dir + 3 * l;
@@ -349,9 +360,9 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   s->bytes_arrays = (size_t)s->n_s * (32 + 16) + (size_t)s->n_c * (3 * 32 + 2 * 16) + (size_t)N * 16;
   // upload the caller's arrays (temporary device copies), then pack
   double *t_sc = nullptr, *t_sr = nullptr, *t_ca = nullptr, *t_cb = nullptr, *t_cr = nullptr;
-  float *t_srgb = nullptr, *t_crgb = nullptr;
+  float *t_srgb = nullptr, *t_crgb = nullptr, *t_sop = nullptr, *t_cop = nullptr;
   auto free_tmp = [&]() {
-    void *p[] = {t_sc, t_sr, t_ca, t_cb, t_cr, t_srgb, t_crgb};
+    void *p[] = {t_sc, t_sr, t_ca, t_cb, t_cr, t_srgb, t_crgb, t_sop, t_cop};
     for (void *q : p)
       if (q) (void)hipFree(q);
   };
@@ -364,6 +375,10 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
       if (e == hipSuccess) e = hipMemcpyAsync(t_sc, d->sph_center, 24 * s->n_s, hipMemcpyHostToDevice, st);
       if (e == hipSuccess) e = hipMemcpyAsync(t_sr, d->sph_radius, 8 * s->n_s, hipMemcpyHostToDevice, st);
       if (e == hipSuccess) e = hipMemcpyAsync(t_srgb, d->sph_rgb, 12 * s->n_s, hipMemcpyHostToDevice, st);
+      if (d->sph_opacity) {
+        if (e == hipSuccess) e = dmalloc(&t_sop, s->n_s);
+        if (e == hipSuccess) e = hipMemcpyAsync(t_sop, d->sph_opacity, 4 * s->n_s, hipMemcpyHostToDevice, st);
+      }
     }
     if (s->n_c > 0) {
       if (e == hipSuccess) e = dmalloc(&t_ca, 3 * s->n_c);
@@ -374,10 +389,14 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
       if (e == hipSuccess) e = hipMemcpyAsync(t_cb, d->cyl_b, 24 * s->n_c, hipMemcpyHostToDevice, st);
       if (e == hipSuccess) e = hipMemcpyAsync(t_cr, d->cyl_radius, 8 * s->n_c, hipMemcpyHostToDevice, st);
       if (e == hipSuccess) e = hipMemcpyAsync(t_crgb, d->cyl_rgb, 12 * s->n_c, hipMemcpyHostToDevice, st);
+      if (d->cyl_opacity) {
+        if (e == hipSuccess) e = dmalloc(&t_cop, s->n_c);
+        if (e == hipSuccess) e = hipMemcpyAsync(t_cop, d->cyl_opacity, 4 * s->n_c, hipMemcpyHostToDevice, st);
+      }
     }
     if (e == hipSuccess)
-      e = trh::launch_pack(s->n_s, s->n_c, t_sc, t_sr, t_srgb, t_ca, t_cb, t_cr, t_crgb, s->sph64,
-                           s->cylA64, s->cylW64, s->cylB64, s->albedo, st);
+      e = trh::launch_pack(s->n_s, s->n_c, t_sc, t_sr, t_srgb, t_sop, t_ca, t_cb, t_cr, t_crgb,
+                           t_cop, s->sph64, s->cylA64, s->cylW64, s->cylB64, s->albedo, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     free_tmp();
     if (e != hipSuccess)
@@ -434,15 +453,19 @@ extern "C" tr_status tr_scene_grid_arrays(const tr_scene *s, uint32_t *cell_begi
 // ---------------------------------------------------------- scene files
 // Binary scene file, little-endian (the "Parse" phase of Table 5 without a
 // text format): char magic[8] = "TRSCENE1"; int64 n_spheres, n_cylinders;
-// int32 n_lights, int32 0; double cells_per_prim; then the arrays of
-// tr_scene_desc in its order, each padded to 8 bytes.
+// int32 n_lights, int32 flags; double cells_per_prim; then the arrays of
+// tr_scene_desc in its order, each padded to 8 bytes (the opacities only
+// with flags bit 0).
 static const char kSceneMagic[8] = {'T', 'R', 'S', 'C', 'E', 'N', 'E', '1'};
 
 static int64_t pad8(int64_t b) { return (b + 7) & ~(int64_t)7; }
 
-static int64_t scene_file_bytes(int64_t ns, int64_t nc, int64_t nl) {
+static constexpr int32_t kFileOpacity = 1;  // flags bit: opacity arrays follow
+
+static int64_t scene_file_bytes(int64_t ns, int64_t nc, int64_t nl, int32_t flags) {
   return 40 + pad8(24 * ns) + pad8(8 * ns) + pad8(12 * ns) + pad8(24 * nc) + pad8(24 * nc) +
-         pad8(8 * nc) + pad8(12 * nc) + 2 * pad8(24 * nl);
+         pad8(8 * nc) + pad8(12 * nc) + 2 * pad8(24 * nl) +
+         ((flags & kFileOpacity) ? pad8(4 * ns) + pad8(4 * nc) : 0);
 }
 
 extern "C" tr_status tr_scene_save(const tr_scene *s, const char *path, void *hip_stream) {
@@ -456,14 +479,15 @@ extern "C" tr_status tr_scene_save(const tr_scene *s, const char *path, void *hi
   if (nc) HIP_TRY(hipMemcpyAsync(cb.data(), s->cylB64, nc * sizeof(double4), hipMemcpyDeviceToHost, st));
   if (N) HIP_TRY(hipMemcpyAsync(alb.data(), s->albedo, N * sizeof(float4), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  std::vector<char> buf((size_t)scene_file_bytes(ns, nc, nl), 0);
+  const int32_t flags = s->has_trans ? kFileOpacity : 0;
+  std::vector<char> buf((size_t)scene_file_bytes(ns, nc, nl, flags), 0);
   char *p = buf.data();
   std::memcpy(p, kSceneMagic, 8);
   std::memcpy(p + 8, &ns, 8);
   std::memcpy(p + 16, &nc, 8);
-  const int32_t nl32 = (int32_t)nl, zero = 0;
+  const int32_t nl32 = (int32_t)nl;
   std::memcpy(p + 24, &nl32, 4);
-  std::memcpy(p + 28, &zero, 4);
+  std::memcpy(p + 28, &flags, 4);
   std::memcpy(p + 32, &s->lambda, 8);
   int64_t o = 40;
   auto put_d = [&](int64_t n, auto get) {
@@ -491,6 +515,10 @@ extern "C" tr_status tr_scene_save(const tr_scene *s, const char *path, void *hi
   put_f(3 * nc, [&](int64_t i) { return compf(alb[ns + i / 3], i % 3); });
   put_d(3 * nl, [&](int64_t i) { return s->ldir_in[i / 3][i % 3]; });
   put_d(3 * nl, [&](int64_t i) { return s->lrgb[i / 3][i % 3]; });
+  if (flags & kFileOpacity) {
+    put_f(ns, [&](int64_t i) { return alb[i].w; });
+    put_f(nc, [&](int64_t i) { return alb[ns + i].w; });
+  }
   FILE *f = std::fopen(path, "wb");
   if (!f) return fail(TR_EINVAL, "tr_scene_save: cannot open %s for writing", path);
   const size_t w = std::fwrite(buf.data(), 1, buf.size(), f);
@@ -519,17 +547,19 @@ extern "C" tr_status tr_scene_load(const char *path, void *hip_stream, tr_scene 
   if (std::memcmp(p, kSceneMagic, 8) != 0)
     return fail(TR_EINVAL, "tr_scene_load: %s is not a scene file (bad magic)", path);
   int64_t ns, nc;
-  int32_t nl;
+  int32_t nl, flags;
   double lambda;
   std::memcpy(&ns, p + 8, 8);
   std::memcpy(&nc, p + 16, 8);
   std::memcpy(&nl, p + 24, 4);
+  std::memcpy(&flags, p + 28, 4);
   std::memcpy(&lambda, p + 32, 8);
+  if (flags & ~kFileOpacity) return fail(TR_EINVAL, "tr_scene_load: %s has unknown flags", path);
   if (ns < 0 || nc < 0 || ns >= ((int64_t)1 << 28) || nc >= ((int64_t)1 << 28) || nl < 0 || nl > 8)
     return fail(TR_EINVAL, "tr_scene_load: %s has bad counts", path);
-  if (scene_file_bytes(ns, nc, nl) != (int64_t)size)
+  if (scene_file_bytes(ns, nc, nl, flags) != (int64_t)size)
     return fail(TR_EINVAL, "tr_scene_load: %s has %ld bytes, its counts need %lld", path, size,
-                (long long)scene_file_bytes(ns, nc, nl));
+                (long long)scene_file_bytes(ns, nc, nl, flags));
   int64_t o = 40;
   auto take = [&](int64_t bytes) {
     const char *q = p + o;
@@ -550,6 +580,10 @@ extern "C" tr_status tr_scene_load(const char *path, void *hip_stream, tr_scene 
   d.light_dir = (const double *)take(24 * nl);
   d.light_rgb = (const double *)take(24 * nl);
   d.cells_per_prim = lambda;
+  if (flags & kFileOpacity) {
+    d.sph_opacity = (const float *)take(4 * ns);
+    d.cyl_opacity = (const float *)take(4 * nc);
+  }
   return tr_scene_build(&d, hip_stream, out);
 }
 
@@ -615,6 +649,7 @@ static tr_status check_camera(const tr_camera *c) {
 }
 
 static constexpr int32_t kMaxAASamples = 256;
+static constexpr int32_t kMaxLayers = 64;
 static int32_t aa_count(const tr_params &p) { return p.aa_samples > 1 ? p.aa_samples : 1; }
 
 static tr_status check_params(const tr_params *p, const tr_frame *f) {
@@ -625,6 +660,8 @@ static tr_status check_params(const tr_params *p, const tr_frame *f) {
   if (f->ao_mask && p->ao_samples > 32) return fail(TR_EINVAL, "ao_mask needs ao_samples <= 32");
   if (p->aa_samples < 0 || p->aa_samples > kMaxAASamples)
     return fail(TR_EINVAL, "aa_samples must be 0..%d", kMaxAASamples);
+  if (p->max_layers < 0 || p->max_layers > kMaxLayers)
+    return fail(TR_EINVAL, "max_layers must be 0..%d", kMaxLayers);
   if (!(p->specular >= 0.0) || !std::isfinite(p->specular))
     return fail(TR_EINVAL, "specular must be finite and >= 0");
   if (p->specular > 0.0 && !(p->shininess > 0.0 && std::isfinite(p->shininess)))
@@ -696,6 +733,7 @@ static tr_status make_job(const tr_scene *s, const tr_camera *c, const tr_params
   J.shin = p->specular > 0.0 ? p->shininess : 1.0;
   J.ks32 = (float)J.ks;
   J.shin32 = (float)J.shin;
+  J.layers = (p->max_layers > 1 && s->has_trans) ? p->max_layers : 1;
   J.key0 = (uint32_t)(p->seed & 0xFFFFFFFFull);
   J.key1 = (uint32_t)(p->seed >> 32);
   J.view_id = p->view_id;
@@ -921,6 +959,8 @@ static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, u
   if (waves > total) waves = total;
   L.n_waves = (int32_t)waves;
   L.resolve = jobs[0].resolve;
+  L.trans = 0;
+  for (const JobDev &J : jobs) L.trans |= J.layers > 1;
   HIP_TRY(trh::launch_render_wave(L, st));
   HIP_TRY(hipEventRecord(ls->done, st));
   return TR_OK;

@@ -9,7 +9,7 @@
 //   cylA32 float4[n_c], cylW32 float4[n_c]         two 16-byte loads per cylinder
 //                        (FP32 positions are relative to org, the centre of the grid
 //                        box: lo32 = lo - org, hi32 = hi - org, eye32 = eye - org)
-//   albedo float4[N]     (r, g, b, 0) by global id
+//   albedo float4[N]     (r, g, b, opacity) by global id
 //   cell_begin uint32[n_cells + 1], refs uint32[n_refs + 64]   the uniform grid
 //   cellinfo CellInfo[n_cells] (list start, first reference) of an occupied cell,
 //                            or (-distance to the nearest occupied cell, -1) of an
@@ -78,6 +78,8 @@ struct JobDev {
   int64_t queue_begin;           // index of this job's first tile in the launch's tile queue
   int32_t scene_key;             // jobs with equal keys share one scene
   int32_t aa;                    // antialiasing sample index (0 = the pixel centre)
+  int32_t layers;                // surfaces composited per primary ray (1 = opaque)
+  int32_t pad3_;
 };
 
 // --------------------------------------------------------------- Philox

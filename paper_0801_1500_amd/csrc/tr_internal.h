@@ -26,10 +26,12 @@ struct BuildArgs {
 };
 
 // ---- grid build launchers (grid_build.hip) ----
+// albedo = (r, g, b, opacity); sop / cop may be null (opaque)
 hipError_t launch_pack(int64_t n_s, int64_t n_c, const double *sc, const double *sr,
-                       const float *srgb, const double *ca, const double *cb, const double *cr,
-                       const float *crgb, double4 *sph64, double4 *cylA64, double4 *cylW64,
-                       double4 *cylB64, float4 *albedo, hipStream_t st);
+                       const float *srgb, const float *sop, const double *ca, const double *cb,
+                       const double *cr, const float *crgb, const float *cop, double4 *sph64,
+                       double4 *cylA64, double4 *cylW64, double4 *cylB64, float4 *albedo,
+                       hipStream_t st);
 // FP32 copies with positions relative to origin (the centre of the grid box)
 hipError_t launch_pack32(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
                          const double4 *cylW64, const double origin[3], float4 *sph32,
@@ -74,6 +76,7 @@ struct WaveLaunch {
   int32_t tile_w, banks, refill_below, count_ops, cyl_wait, mix;
   int32_t n_waves;           // persistent waves launched
   int32_t resolve;
+  int32_t trans;             // some job composites transparent layers
 };
 hipError_t launch_render_wave(const WaveLaunch &L, hipStream_t st);
 hipError_t launch_zero_counter(uint32_t *p, hipStream_t st);
