@@ -35,7 +35,7 @@ def build(force: bool = True) -> str:
 class Counters(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "pixels", "primary_rays", "hit_pixels", "shadow_rays", "ao_rays", "rays_traced",
-        "cells", "sph_tests", "sph_hits", "cyl_tests", "cyl_hits")]
+        "cells", "sph_tests", "sph_hits", "cyl_tests", "cyl_hits", "tri_tests", "tri_hits")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -48,7 +48,9 @@ class _Scene(C.Structure):
         ("n_cylinders", C.c_int64), ("cyl_a", C.c_void_p), ("cyl_b", C.c_void_p),
         ("cyl_radius", C.c_void_p), ("cyl_rgb", C.c_void_p),
         ("n_lights", C.c_int32), ("light_dir", C.c_void_p), ("light_rgb", C.c_void_p),
-        ("sph_opacity", C.c_void_p), ("cyl_opacity", C.c_void_p)]
+        ("sph_opacity", C.c_void_p), ("cyl_opacity", C.c_void_p),
+        ("n_triangles", C.c_int64), ("tri_v0", C.c_void_p), ("tri_v1", C.c_void_p),
+        ("tri_v2", C.c_void_p), ("tri_rgb", C.c_void_p), ("tri_opacity", C.c_void_p)]
 
 
 class _Camera(C.Structure):
@@ -86,6 +88,8 @@ def lib():
         L.or_hit_sphere.restype = C.c_int
         L.or_hit_cylinder.argtypes = [vp, vp, dbl, vp, vp, dbl, dbl, C.POINTER(dbl)]
         L.or_hit_cylinder.restype = C.c_int
+        L.or_hit_triangle.argtypes = [vp, vp, vp, vp, vp, dbl, dbl, C.POINTER(dbl)]
+        L.or_hit_triangle.restype = C.c_int
         L.or_normal.argtypes = [C.POINTER(_Scene), i64, vp, vp, dbl, vp]
         L.or_grid_new.argtypes = [C.POINTER(_Scene), dbl]
         L.or_grid_new.restype = vp
@@ -122,9 +126,17 @@ class OScene:
             cyl_radius=f64(scene.cyl_radius), cyl_rgb=f32(scene.cyl_rgb).reshape(-1, 3),
             light_dir=f64(scene.light_dir).reshape(-1, 3),
             light_rgb=f64(scene.light_rgb).reshape(-1, 3))
-        for key in ("sph_opacity", "cyl_opacity"):
+        for key in ("sph_opacity", "cyl_opacity", "tri_opacity"):
             v = getattr(scene, key, None)
             self.arrays[key] = None if v is None else f32(v).reshape(-1)
+        tv = getattr(scene, "tri_v", None)  # [n_t, 3, 3]
+        tv = np.zeros((0, 3, 3)) if tv is None else f64(tv).reshape(-1, 3, 3)
+        for q in range(3):
+            self.arrays["tri_v%d" % q] = np.ascontiguousarray(tv[:, q, :])
+        trgb = getattr(scene, "tri_rgb", None)
+        self.arrays["tri_rgb"] = (np.zeros((0, 3), np.float32) if trgb is None
+                                  else f32(trgb).reshape(-1, 3))
+        self.n_triangles = tv.shape[0]
         a = self.arrays
         self.n_spheres = a["sph_radius"].shape[0]
         self.n_cylinders = a["cyl_radius"].shape[0]
@@ -132,7 +144,9 @@ class OScene:
                         _ptr(a["sph_rgb"]), self.n_cylinders, _ptr(a["cyl_a"]), _ptr(a["cyl_b"]),
                         _ptr(a["cyl_radius"]), _ptr(a["cyl_rgb"]), a["light_dir"].shape[0],
                         _ptr(a["light_dir"]), _ptr(a["light_rgb"]),
-                        _ptr(a["sph_opacity"]), _ptr(a["cyl_opacity"]))
+                        _ptr(a["sph_opacity"]), _ptr(a["cyl_opacity"]), self.n_triangles,
+                        _ptr(a["tri_v0"]), _ptr(a["tri_v1"]), _ptr(a["tri_v2"]),
+                        _ptr(a["tri_rgb"]), _ptr(a["tri_opacity"]))
 
 
 def _as_oscene(scene) -> OScene:
@@ -241,6 +255,14 @@ def hit_cylinder(a, b, rho, o, d, tmin=0.0, tmax=math.inf):
     a, b, o, d = (np.ascontiguousarray(x, dtype=np.float64) for x in (a, b, o, d))
     t = C.c_double()
     h = lib().or_hit_cylinder(_ptr(a), _ptr(b), float(rho), _ptr(o), _ptr(d), tmin, tmax,
+                              C.byref(t))
+    return t.value if h else None
+
+
+def hit_triangle(v0, v1, v2, o, d, tmin=0.0, tmax=math.inf):
+    v0, v1, v2, o, d = (np.ascontiguousarray(x, dtype=np.float64) for x in (v0, v1, v2, o, d))
+    t = C.c_double()
+    h = lib().or_hit_triangle(_ptr(v0), _ptr(v1), _ptr(v2), _ptr(o), _ptr(d), tmin, tmax,
                               C.byref(t))
     return t.value if h else None
 

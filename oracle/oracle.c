@@ -259,6 +259,32 @@ int or_hit_cylinder(const double a[3], const double b[3], double rho, const doub
   return hit_cyl_frame(&cf, o, d, tmin, tmax, t);
 }
 
+/* Triangle (v0, v1, v2), two-sided, by the method of Moller and Trumbore
+ * (JGT 1997): with e1 = v1 - v0, e2 = v2 - v0, P = d x e2, det = e1.P,
+ * T = o - v0, Q = T x e1, the barycentric coordinates are u = T.P / det and
+ * v = d.Q / det and the distance t = e2.Q / det.  A hit needs det != 0,
+ * u >= 0, v >= 0, u + v <= 1 (edges belong to the triangle) and t in
+ * (tmin, tmax]. */
+int or_hit_triangle(const double v0[3], const double v1[3], const double v2[3],
+                    const double o[3], const double d[3], double tmin, double tmax, double *t) {
+  double e1[3], e2[3], P[3], T[3], Q[3];
+  sub3(v1, v0, e1);
+  sub3(v2, v0, e2);
+  cross3(d, e2, P);
+  double det = dot3(e1, P);
+  if (det == 0.0) return 0;
+  sub3(o, v0, T);
+  double u = dot3(T, P) / det;
+  if (!(u >= 0.0 && u <= 1.0)) return 0;
+  cross3(T, e1, Q);
+  double v = dot3(d, Q) / det;
+  if (!(v >= 0.0 && u + v <= 1.0)) return 0;
+  double tt = dot3(e2, Q) / det;
+  if (!(tt > tmin && tt <= tmax)) return 0;
+  *t = tt;
+  return 1;
+}
+
 /* Geometric normal of primitive k at the hit point o + t d (not flipped). */
 void or_normal(const or_scene *s, int64_t k, const double o[3], const double d[3], double t,
                double n[3]) {
@@ -268,6 +294,14 @@ void or_normal(const or_scene *s, int64_t k, const double o[3], const double d[3
     const double *c = s->sph_center + 3 * k;
     double r = s->sph_radius[k];
     for (int a = 0; a < 3; ++a) n[a] = (P[a] - c[a]) / r;
+  } else if (k >= s->n_spheres + s->n_cylinders) {
+    /* triangle: the unit normal of its plane, e1 x e2 */
+    int64_t m = k - s->n_spheres - s->n_cylinders;
+    double e1[3], e2[3], c[3];
+    sub3(s->tri_v1 + 3 * m, s->tri_v0 + 3 * m, e1);
+    sub3(s->tri_v2 + 3 * m, s->tri_v0 + 3 * m, e2);
+    cross3(e1, e2, c);
+    normalize3(c, n);
   } else {
     int64_t m = k - s->n_spheres;
     cyl_frame cf;
@@ -288,6 +322,14 @@ static int hit_prim(const or_scene *s, int64_t k, const double o[3], const doubl
     if (h && cnt) cnt->sph_hits++;
     return h;
   }
+  if (k >= s->n_spheres + s->n_cylinders) {
+    int64_t m = k - s->n_spheres - s->n_cylinders;
+    if (cnt) cnt->tri_tests++;
+    int h = or_hit_triangle(s->tri_v0 + 3 * m, s->tri_v1 + 3 * m, s->tri_v2 + 3 * m, o, d, tmin,
+                            tmax, t);
+    if (h && cnt) cnt->tri_hits++;
+    return h;
+  }
   int64_t m = k - s->n_spheres;
   if (cnt) cnt->cyl_tests++;
   int h = or_hit_cylinder(s->cyl_a + 3 * m, s->cyl_b + 3 * m, s->cyl_radius[m], o, d, tmin,
@@ -300,7 +342,7 @@ static int hit_prim(const or_scene *s, int64_t k, const double o[3], const doubl
  * Definition of the grid (shared by contract, not by code, with the GPU
  * build, which must produce the identical cell lists):
  *   primitive boxes: sphere [c - r, c + r]; cylinder [min(a,b) - rho,
- *     max(a,b) + rho], per axis;
+ *     max(a,b) + rho]; triangle [min, max] of its vertices, per axis;
  *   scene box [Lo, Hi] = union of primitive boxes, widened on every side by
  *     pad = 1e-4 * m + 1e-6, m = largest extent of the union;
  *   resolution res_a = clamp(ceil(ext_a * cbrt(lambda * N / V)), 1, 512),
@@ -329,6 +371,18 @@ static void prim_box(const or_scene *s, int64_t k, double lo[3], double hi[3]) {
     const double *c = s->sph_center + 3 * k;
     double r = s->sph_radius[k];
     for (int a = 0; a < 3; ++a) { lo[a] = c[a] - r; hi[a] = c[a] + r; }
+  } else if (k >= s->n_spheres + s->n_cylinders) {
+    int64_t m = k - s->n_spheres - s->n_cylinders;
+    const double *v[3] = {s->tri_v0 + 3 * m, s->tri_v1 + 3 * m, s->tri_v2 + 3 * m};
+    for (int a = 0; a < 3; ++a) {
+      double mn = v[0][a], mx = v[0][a];
+      for (int q = 1; q < 3; ++q) {
+        mn = v[q][a] < mn ? v[q][a] : mn;
+        mx = v[q][a] > mx ? v[q][a] : mx;
+      }
+      lo[a] = mn;
+      hi[a] = mx;
+    }
   } else {
     int64_t m = k - s->n_spheres;
     const double *A = s->cyl_a + 3 * m, *B = s->cyl_b + 3 * m;
@@ -390,7 +444,7 @@ static int64_t prim_cells(const or_scene *s, const or_grid *g, int64_t k, uint32
 or_grid *or_grid_new(const or_scene *s, double lambda) {
   or_grid *g = (or_grid *)calloc(1, sizeof(or_grid));
   if (!g) return NULL;
-  int64_t N = s->n_spheres + s->n_cylinders;
+  int64_t N = s->n_spheres + s->n_cylinders + s->n_triangles;
   if (lambda <= 0.0) lambda = 4.0;
   if (N == 0) {
     for (int a = 0; a < 3; ++a) { g->lo[a] = 0.0; g->hi[a] = 1.0; g->res[a] = 1; g->h[a] = 1.0; g->inv[a] = 1.0; }
@@ -567,7 +621,7 @@ int or_trace(const or_scene *s, const or_grid *g, const double o[3], const doubl
   if (g) {
     grid_walk(s, g, o, d, tmin, tmax, &hs, cnt);
   } else {
-    int64_t N = s->n_spheres + s->n_cylinders;
+    int64_t N = s->n_spheres + s->n_cylinders + s->n_triangles;
     for (int64_t q = 0; q < N; ++q) {
       consider(s, q, o, d, tmin, tmax, &hs, cnt);
       if (any_hit && hs.found) break;
@@ -605,16 +659,24 @@ static void add_counters(or_counters *dst, const or_counters *src) {
   dst->sph_hits += src->sph_hits;
   dst->cyl_tests += src->cyl_tests;
   dst->cyl_hits += src->cyl_hits;
+  dst->tri_tests += src->tri_tests;
+  dst->tri_hits += src->tri_hits;
 }
 
 static float prim_albedo(const or_scene *s, int64_t k, int ch) {
   if (k < s->n_spheres) return s->sph_rgb[3 * k + ch];
+  if (k >= s->n_spheres + s->n_cylinders)
+    return s->tri_rgb[3 * (k - s->n_spheres - s->n_cylinders) + ch];
   return s->cyl_rgb[3 * (k - s->n_spheres) + ch];
 }
 
 /* Opacity of primitive k (1 = opaque; no array = all opaque). */
 static double prim_opacity(const or_scene *s, int64_t k) {
   if (k < s->n_spheres) return s->sph_opacity ? (double)s->sph_opacity[k] : 1.0;
+  if (k >= s->n_spheres + s->n_cylinders) {
+    int64_t m = k - s->n_spheres - s->n_cylinders;
+    return s->tri_opacity ? (double)s->tri_opacity[m] : 1.0;
+  }
   return s->cyl_opacity ? (double)s->cyl_opacity[k - s->n_spheres] : 1.0;
 }
 

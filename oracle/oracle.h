@@ -45,6 +45,12 @@ typedef struct {
   const double *light_rgb;  /* [n_lights*3] */
   const float *sph_opacity; /* [n_spheres] in (0, 1], or NULL = opaque */
   const float *cyl_opacity; /* [n_cylinders] in (0, 1], or NULL = opaque */
+  int64_t n_triangles;      /* ids n_spheres + n_cylinders + [0, n_triangles) */
+  const double *tri_v0;     /* [n_triangles*3] vertices */
+  const double *tri_v1;
+  const double *tri_v2;
+  const float *tri_rgb;     /* [n_triangles*3] */
+  const float *tri_opacity; /* [n_triangles] in (0, 1], or NULL = opaque */
 } or_scene;
 
 typedef struct {
@@ -79,6 +85,7 @@ typedef struct {
   uint64_t cells;        /* grid cells visited */
   uint64_t sph_tests, sph_hits;
   uint64_t cyl_tests, cyl_hits;
+  uint64_t tri_tests, tri_hits;
 } or_counters;
 
 typedef struct or_grid or_grid;
@@ -106,6 +113,8 @@ int or_hit_sphere(const double c[3], double r, const double o[3], const double d
                   double tmin, double tmax, double *t);
 int or_hit_cylinder(const double a[3], const double b[3], double rho, const double o[3],
                     const double d[3], double tmin, double tmax, double *t);
+int or_hit_triangle(const double v0[3], const double v1[3], const double v2[3],
+                    const double o[3], const double d[3], double tmin, double tmax, double *t);
 void or_normal(const or_scene *s, int64_t k, const double o[3], const double d[3], double t,
                double n[3]);
 

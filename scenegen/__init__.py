@@ -36,7 +36,7 @@ LIGHT1 = (1.0, 2.0, 0.5)
 @dataclasses.dataclass
 class Scene:
     """Host arrays of one scene.  Global primitive ids: spheres [0, n_s),
-    cylinders [n_s, n_s + n_c)."""
+    cylinders [n_s, n_s + n_c), triangles [n_s + n_c, n_s + n_c + n_t)."""
     sph_center: np.ndarray   # float64 [n_s, 3]
     sph_radius: np.ndarray   # float64 [n_s]
     sph_rgb: np.ndarray      # float32 [n_s, 3]
@@ -48,6 +48,9 @@ class Scene:
     light_rgb: np.ndarray    # float64 [n_l, 3]
     sph_opacity: Optional[np.ndarray] = None  # float32 [n_s] in (0, 1]; None = opaque
     cyl_opacity: Optional[np.ndarray] = None  # float32 [n_c] in (0, 1]; None = opaque
+    tri_v: Optional[np.ndarray] = None        # float64 [n_t, 3, 3] triangle vertices
+    tri_rgb: Optional[np.ndarray] = None      # float32 [n_t, 3]
+    tri_opacity: Optional[np.ndarray] = None  # float32 [n_t] in (0, 1]; None = opaque
 
     @property
     def n_spheres(self) -> int:
@@ -58,8 +61,12 @@ class Scene:
         return int(self.cyl_radius.shape[0])
 
     @property
+    def n_triangles(self) -> int:
+        return 0 if self.tri_v is None else int(np.asarray(self.tri_v).reshape(-1, 9).shape[0])
+
+    @property
     def n_prims(self) -> int:
-        return self.n_spheres + self.n_cylinders
+        return self.n_spheres + self.n_cylinders + self.n_triangles
 
     @property
     def n_lights(self) -> int:
@@ -177,6 +184,89 @@ def random_walk_scene(n_spheres: int, ball_radius: float, seed: int,
     ld, lc = _lights(n_lights)
     return Scene(centres, radii, srgb, ca, cb,
                  np.full(n_cylinders, cyl_radius, dtype=np.float64), crgb, ld, lc)
+
+
+def icosphere(subdiv: int):
+    """Unit icosphere: the icosahedron's 20 faces, each split into 4 by edge
+    midpoints (pushed to the sphere) `subdiv` times.  Returns (vertices
+    [V, 3], faces [F, 3]) with F = 20 * 4^subdiv, faces counter-clockwise
+    seen from outside."""
+    g = (1.0 + math.sqrt(5.0)) / 2.0
+    v = [(-1, g, 0), (1, g, 0), (-1, -g, 0), (1, -g, 0), (0, -1, g), (0, 1, g),
+         (0, -1, -g), (0, 1, -g), (g, 0, -1), (g, 0, 1), (-g, 0, -1), (-g, 0, 1)]
+    verts = [np.array(x, dtype=np.float64) / math.sqrt(1.0 + g * g) for x in v]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4),
+             (11, 10, 2), (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8),
+             (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(subdiv):
+        mid = {}
+
+        def midpoint(i, j):
+            key = (min(i, j), max(i, j))
+            if key not in mid:
+                m = verts[i] + verts[j]
+                verts.append(m / np.linalg.norm(m))
+                mid[key] = len(verts) - 1
+            return mid[key]
+
+        nf = []
+        for a, b, c in faces:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+    return np.array(verts), np.array(faces, dtype=np.int64)
+
+
+def blob_mesh(centres: np.ndarray, radius: float, subdiv: int) -> np.ndarray:
+    """Closed icosphere meshes of the given radius around each centre:
+    triangle vertices [n * F, 3, 3]."""
+    verts, faces = icosphere(subdiv)
+    unit = verts[faces]  # [F, 3, 3]
+    c = np.asarray(centres, dtype=np.float64).reshape(-1, 1, 1, 3)
+    return (c + radius * unit[None]).reshape(-1, 3, 3)
+
+
+def with_triangles(scene: Scene, tri_v: np.ndarray, tri_rgb=None, tri_opacity=None) -> Scene:
+    tri_v = np.ascontiguousarray(tri_v, dtype=np.float64).reshape(-1, 3, 3)
+    if tri_rgb is None:
+        tri_rgb = PALETTE[np.arange(tri_v.shape[0]) % 4]
+    return Scene(**{**scene.__dict__, "tri_v": tri_v,
+                    "tri_rgb": np.ascontiguousarray(tri_rgb, dtype=np.float32).reshape(-1, 3),
+                    "tri_opacity": tri_opacity})
+
+
+def mixed_tiny_scene(seed: int = 5) -> Scene:
+    """Small scene with all three primitive types: 24 spheres and 12
+    cylinders in a ball of radius 10, four icosphere blobs (80 triangles
+    each) and a two-triangle floor under them."""
+    rng = np.random.default_rng(seed)
+    base = tiny_scene(seed=seed, n=24)
+    ca = rng.uniform(-8, 8, (12, 3))
+    cb = ca + 3.0 * _unit_gaussian(rng, 12)
+    blobs = blob_mesh(rng.uniform(-7, 7, (4, 3)), 2.5, 1)
+    floor = np.array([[[-14, -11, -14], [14, -11, -14], [14, -11, 14]],
+                      [[-14, -11, -14], [14, -11, 14], [-14, -11, 14]]], dtype=np.float64)
+    s = Scene(**{**base.__dict__, "cyl_a": ca, "cyl_b": cb,
+                 "cyl_radius": rng.uniform(0.3, 0.6, 12),
+                 "cyl_rgb": PALETTE[np.arange(12) % 4].astype(np.float32)})
+    return with_triangles(s, np.concatenate([blobs, floor]))
+
+
+def surface_scene(seed: int = 2, every: int = 160, radius: float = 4.0,
+                  subdiv: int = 2) -> Scene:
+    """Molecular-surface stand-in: closed icosphere blobs (320 triangles at
+    subdivision 2) of radius 4 around every 160th position of the protein
+    walk -- 83 blobs, 26,560 triangles, about the protein scene's object
+    count -- with the protein scene's two lights."""
+    pos, _ = random_walk(PROTEIN_SPHERES + 1, PROTEIN_RADIUS, seed)
+    tri = blob_mesh(pos[::every], radius, subdiv)
+    ld, lc = _lights(2)
+    e3 = _empty3()
+    s = Scene(e3, np.zeros(0), _empty3(np.float32), e3.copy(), e3.copy(), np.zeros(0),
+              _empty3(np.float32), ld, lc)
+    per = 20 * 4 ** subdiv
+    rgb = PALETTE[(np.arange(tri.shape[0]) // per) % 4]
+    return with_triangles(s, tri, rgb)
 
 
 # ---------------------------------------------------------------------------
