@@ -63,9 +63,10 @@ typedef enum {
 typedef struct tr_scene tr_scene;
 
 /* Scene description (Sec. 2: the 26,318 "objects" of the molecular scene
- * are spheres and cylinders).  Global primitive id: spheres [0, n_spheres),
- * cylinders [n_spheres, n_spheres + n_cylinders).  Arrays are row-major
- * xyz triples.  Any count may be 0 (an empty scene renders background). */
+ * are spheres and cylinders; triangles carry surface representations).
+ * Global primitive id: spheres [0, n_spheres), cylinders [n_spheres,
+ * n_spheres + n_cylinders), then triangles.  Arrays are row-major xyz
+ * triples.  Any count may be 0 (an empty scene renders background). */
 typedef struct {
   int64_t n_spheres;
   const double *sph_center;  /* [n_spheres*3]                               */
@@ -83,6 +84,16 @@ typedef struct {
   const float *sph_opacity;  /* [n_spheres] opacity in (0, 1], or NULL = opaque */
   const float *cyl_opacity;  /* [n_cylinders] opacity in (0, 1], or NULL = opaque;
                                 used only by renders with tr_params.max_layers > 1 */
+  int64_t n_triangles;       /* triangles (surface representations), ids
+                                n_spheres + n_cylinders + [0, n_triangles);
+                                n_spheres + n_cylinders + n_triangles < 2^28   */
+  const double *tri_v0;      /* [n_triangles*3] vertices, finite; two-sided,
+                                hit by the Moller-Trumbore test with the edges
+                                inside; a zero-area triangle is never hit     */
+  const double *tri_v1;
+  const double *tri_v2;
+  const float *tri_rgb;      /* [n_triangles*3] albedo                      */
+  const float *tri_opacity;  /* [n_triangles] opacity in (0, 1], or NULL     */
 } tr_scene_desc;
 
 /* Pinhole camera, one ray through each pixel centre (more with
@@ -179,6 +190,8 @@ enum {
   TR_STAT_JUMPS,             /* wavefront kernel: empty-space jumps over more than one cell */
   TR_STAT_CYCLES_TRAVERSE,   /* wavefront kernel: shader clocks in the traversal loop (summed over waves) */
   TR_STAT_CYCLES_TOTAL,      /* wavefront kernel: shader clocks from wave start to end (summed) */
+  TR_STAT_TRI_TESTS,
+  TR_STAT_TRI_HITS,
   TR_STAT_COUNT
 };
 
@@ -203,8 +216,9 @@ typedef struct {
  * references and an in-cell sort (the "Preprocess" phase, Table 5).  Blocks
  * on the stream once to read back the scene bounds.  *out receives the new
  * scene; TR_EINVAL on a NULL required pointer, negative count, non-finite
- * coordinate, radius <= 0, zero-length cylinder, n_lights outside 0..8,
- * cells_per_prim < 0 or n_spheres + n_cylinders >= 2^28; TR_EUNSUPPORTED when
+ * coordinate, radius <= 0, zero-length cylinder, n_lights outside 0..8, an
+ * opacity outside (0, 1], cells_per_prim < 0 or n_spheres + n_cylinders +
+ * n_triangles >= 2^28; TR_EUNSUPPORTED when
  * the grid would hold more than 2^30 - 64 primitive references. */
 tr_status tr_scene_build(const tr_scene_desc *desc, void *hip_stream, tr_scene **out);
 
@@ -232,9 +246,10 @@ tr_status tr_scene_grid_arrays(const tr_scene *scene, uint32_t *cell_begin, uint
  * n_cylinders; int32 n_lights, int32 flags; double cells_per_prim; then the
  * arrays of tr_scene_desc in its order (sph_center, sph_radius, sph_rgb,
  * cyl_a, cyl_b, cyl_radius, cyl_rgb, light_dir, light_rgb), each padded to a
- * multiple of 8 bytes; with flags bit 0 (written when some opacity is below
- * 1) then sph_opacity and cyl_opacity, padded likewise.  Other flag bits
- * must be 0.
+ * multiple of 8 bytes; with flags bit 1 (written when there are triangles)
+ * then int64 n_triangles, tri_v0, tri_v1, tri_v2, tri_rgb; with flags bit 0
+ * (written when some opacity is below 1) then sph_opacity, cyl_opacity and,
+ * with bit 1, tri_opacity, padded likewise.  Other flag bits must be 0.
  * tr_scene_save writes the description the scene was built from (the FP64
  * arrays, albedo, the lights as given, the grid density); synchronises the
  * stream; TR_EINVAL on a NULL argument or a failed write.

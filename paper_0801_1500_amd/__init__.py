@@ -23,7 +23,8 @@ PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "fp32_resolve": PREC_FP32_RE
 
 STAT_NAMES = ["pixels", "hit_pixels", "ao_rays", "shadow_rays", "rays_traced", "cells",
               "sph_tests", "sph_hits", "cyl_tests", "cyl_hits", "resolves", "wave_iters",
-              "lane_iters", "refills", "jumps", "cycles_traverse", "cycles_total"]
+              "lane_iters", "refills", "jumps", "cycles_traverse", "cycles_total", "tri_tests",
+              "tri_hits"]
 STAT_COUNT = len(STAT_NAMES)
 
 
@@ -40,7 +41,9 @@ class SceneDesc(C.Structure):
         ("n_cylinders", C.c_int64), ("cyl_a", C.c_void_p), ("cyl_b", C.c_void_p),
         ("cyl_radius", C.c_void_p), ("cyl_rgb", C.c_void_p),
         ("n_lights", C.c_int32), ("light_dir", C.c_void_p), ("light_rgb", C.c_void_p),
-        ("cells_per_prim", C.c_double), ("sph_opacity", C.c_void_p), ("cyl_opacity", C.c_void_p)]
+        ("cells_per_prim", C.c_double), ("sph_opacity", C.c_void_p), ("cyl_opacity", C.c_void_p),
+        ("n_triangles", C.c_int64), ("tri_v0", C.c_void_p), ("tri_v1", C.c_void_p),
+        ("tri_v2", C.c_void_p), ("tri_rgb", C.c_void_p), ("tri_opacity", C.c_void_p)]
 
 
 class Camera(C.Structure):
@@ -178,23 +181,32 @@ class Scene:
         arrs = [f64(scene.sph_center), f64(scene.sph_radius), f32(scene.sph_rgb),
                 f64(scene.cyl_a), f64(scene.cyl_b), f64(scene.cyl_radius), f32(scene.cyl_rgb),
                 f64(scene.light_dir), f64(scene.light_rgb)]
-        ops = [getattr(scene, k, None) for k in ("sph_opacity", "cyl_opacity")]
+        ops = [getattr(scene, k, None) for k in ("sph_opacity", "cyl_opacity", "tri_opacity")]
         ops = [None if o is None else f32(o).reshape(-1) for o in ops]
-        arrs += [o if o is not None else np.zeros(0, np.float32) for o in ops]
+        tv = getattr(scene, "tri_v", None)
+        tv = np.zeros((0, 3, 3)) if tv is None else f64(tv).reshape(-1, 3, 3)
+        trgb = getattr(scene, "tri_rgb", None)
+        trgb = np.zeros((0, 3), np.float32) if trgb is None else f32(trgb).reshape(-1, 3)
+        n_t = int(tv.shape[0])
+        arrs += [o if o is not None else np.zeros(0, np.float32) for o in ops[:2]]
+        arrs += [np.ascontiguousarray(tv[:, q, :]) for q in range(3)] + [trgb]
+        arrs += [ops[2] if ops[2] is not None else np.zeros(0, np.float32)]
         p = [a.ctypes.data if a.size else None for a in arrs]
         desc = SceneDesc(int(arrs[1].shape[0]), p[0], p[1], p[2], int(arrs[5].shape[0]), p[3],
                          p[4], p[5], p[6], int(arrs[7].reshape(-1, 3).shape[0]), p[7], p[8],
-                         float(cells_per_prim), p[9], p[10])
+                         float(cells_per_prim), p[9], p[10], n_t, p[11], p[12], p[13], p[14],
+                         p[15])
         h = C.c_void_p()
         _check(lib().tr_scene_build(C.byref(desc), _stream(stream), C.byref(h)))
         self.handle = h
         self.n_spheres = int(arrs[1].shape[0])
         self.n_cylinders = int(arrs[5].shape[0])
         self.n_lights = int(arrs[7].reshape(-1, 3).shape[0])
+        self.n_triangles = n_t
 
     @property
     def n_prims(self):
-        return self.n_spheres + self.n_cylinders
+        return self.n_spheres + self.n_cylinders + self.n_triangles
 
     def save(self, path: str, stream=None):
         """Write the scene as a binary scene file (tr_scene_save)."""
@@ -210,7 +222,16 @@ class Scene:
         _check(lib().tr_scene_load(os.fsencode(path), _stream(stream), C.byref(h)))
         self = cls.__new__(cls)
         self.handle = h
-        self.n_spheres, self.n_cylinders, self.n_lights = struct.unpack_from("<qqi", head, 8)
+        self.n_spheres, self.n_cylinders, self.n_lights, flags = struct.unpack_from("<qqii", head, 8)
+        self.n_triangles = 0
+        if flags & 2:  # triangle count right after the light arrays
+            pad8 = lambda b: (b + 7) & ~7
+            ns, nc, nl = self.n_spheres, self.n_cylinders, self.n_lights
+            at = (40 + pad8(24 * ns) + pad8(8 * ns) + pad8(12 * ns) + 2 * pad8(24 * nc) +
+                  pad8(8 * nc) + pad8(12 * nc) + 2 * pad8(24 * nl))
+            with open(path, "rb") as f:
+                f.seek(at)
+                self.n_triangles = struct.unpack("<q", f.read(8))[0]
         return self
 
     def rebuild(self, cells_per_prim: float = 0.0, stream=None):

@@ -20,6 +20,20 @@ __device__ __forceinline__ void prim_box(const trh::BuildArgs &a, int64_t k, dou
     const double4 s = a.sph64[k];
     lo[0] = s.x - s.w; lo[1] = s.y - s.w; lo[2] = s.z - s.w;
     hi[0] = s.x + s.w; hi[1] = s.y + s.w; hi[2] = s.z + s.w;
+  } else if (k >= (int64_t)a.n_s + a.n_c) {  // triangle: min/max of its vertices
+    const int64_t m = k - a.n_s - a.n_c;
+    const double4 A = a.triA64[m], B = a.triB64[m], C = a.triC64[m];
+    const double av[3] = {A.x, A.y, A.z}, bv[3] = {B.x, B.y, B.z}, cv[3] = {C.x, C.y, C.z};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double mn = av[q], mx = av[q];
+      mn = bv[q] < mn ? bv[q] : mn;
+      mx = bv[q] > mx ? bv[q] : mx;
+      mn = cv[q] < mn ? cv[q] : mn;
+      mx = cv[q] > mx ? cv[q] : mx;
+      lo[q] = mn;
+      hi[q] = mx;
+    }
   } else {
     const int64_t m = k - a.n_s;
     const double4 A = a.cylA64[m], B = a.cylB64[m];
@@ -94,11 +108,21 @@ __device__ __forceinline__ void for_prim_cells(const trh::BuildArgs &a, int64_t 
   }
 }
 
-__global__ void k_pack(int64_t n_s, int64_t n_c, const double *sc, const double *sr,
-                       const float *srgb, const float *sop, const double *ca, const double *cb,
-                       const double *cr, const float *crgb, const float *cop, double4 *sph64,
-                       double4 *cylA64, double4 *cylW64, double4 *cylB64, float4 *albedo) {
+__global__ void k_pack(const trh::PackArgs P) {
+  const int64_t n_s = P.n_s, n_c = P.n_c;
+  const double *sc = P.sc, *sr = P.sr, *ca = P.ca, *cb = P.cb, *cr = P.cr;
+  const float *srgb = P.srgb, *sop = P.sop, *crgb = P.crgb, *cop = P.cop;
+  double4 *sph64 = P.sph64, *cylA64 = P.cylA64, *cylW64 = P.cylW64, *cylB64 = P.cylB64;
+  float4 *albedo = P.albedo;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_s + n_c && k < n_s + n_c + P.n_t) {
+    const int64_t m = k - n_s - n_c;
+    P.triA64[m] = make_double4(P.tv0[3 * m], P.tv0[3 * m + 1], P.tv0[3 * m + 2], 0.0);
+    P.triB64[m] = make_double4(P.tv1[3 * m], P.tv1[3 * m + 1], P.tv1[3 * m + 2], 0.0);
+    P.triC64[m] = make_double4(P.tv2[3 * m], P.tv2[3 * m + 1], P.tv2[3 * m + 2], 0.0);
+    albedo[k] = make_float4(P.trgb[3 * m], P.trgb[3 * m + 1], P.trgb[3 * m + 2],
+                            P.top ? P.top[m] : 1.0f);
+  }
   if (k < n_s) {
     sph64[k] = make_double4(sc[3 * k], sc[3 * k + 1], sc[3 * k + 2], sr[k]);
     albedo[k] = make_float4(srgb[3 * k], srgb[3 * k + 1], srgb[3 * k + 2], sop ? sop[k] : 1.0f);
@@ -118,10 +142,27 @@ __global__ void k_pack(int64_t n_s, int64_t n_c, const double *sc, const double 
 // FP32 copies for the wavefront walk, with positions relative to the centre of
 // the grid box (the FP32 frame: the smallest magnitudes, so the least rounding,
 // wherever the scene sits).
-__global__ void k_pack32(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
-                         const double4 *cylW64, double ox, double oy, double oz, float4 *sph32,
-                         float4 *cylA32, float4 *cylW32) {
+__global__ void k_pack32(const trh::BuildArgs a, const double4 *cylW64, double ox, double oy,
+                         double oz, float4 *sph32, float4 *cylA32, float4 *cylW32, float4 *triV32,
+                         float4 *triE1_32, float4 *triE2_32) {
+  const int64_t n_s = a.n_s, n_c = a.n_c;
+  const double4 *sph64 = a.sph64, *cylA64 = a.cylA64;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_s + n_c && k < n_s + n_c + a.n_t) {
+    // triangle: v0 in the FP32 frame, its edges (differences taken in FP64),
+    // and |e1 x e2| (the scale of the determinant) in v0's fourth word
+    const int64_t m = k - n_s - n_c;
+    const double4 A = a.triA64[m], B = a.triB64[m], C = a.triC64[m];
+    const double e1[3] = {B.x - A.x, B.y - A.y, B.z - A.z};
+    const double e2[3] = {C.x - A.x, C.y - A.y, C.z - A.z};
+    const double nx = e1[1] * e2[2] - e1[2] * e2[1];
+    const double ny = e1[2] * e2[0] - e1[0] * e2[2];
+    const double nz = e1[0] * e2[1] - e1[1] * e2[0];
+    triV32[m] = make_float4((float)(A.x - ox), (float)(A.y - oy), (float)(A.z - oz),
+                            (float)sqrt((nx * nx + ny * ny) + nz * nz));
+    triE1_32[m] = make_float4((float)e1[0], (float)e1[1], (float)e1[2], 0.0f);
+    triE2_32[m] = make_float4((float)e2[0], (float)e2[1], (float)e2[2], 0.0f);
+  }
   if (k < n_s) {
     const double4 s = sph64[k];
     sph32[k] = make_float4((float)(s.x - ox), (float)(s.y - oy), (float)(s.z - oz), (float)s.w);
@@ -134,19 +175,10 @@ __global__ void k_pack32(int64_t n_s, int64_t n_c, const double4 *sph64, const d
 }
 
 // Per-block min/max of primitive boxes -> scratch[block*6 .. +6].
-__global__ __launch_bounds__(kBlock) void k_bounds_partial(int64_t n_s, int64_t n_c,
-                                                           const double4 *sph64,
-                                                           const double4 *cylA64,
-                                                           const double4 *cylB64, double *part) {
+__global__ __launch_bounds__(kBlock) void k_bounds_partial(const trh::BuildArgs a, double *part) {
   __shared__ double red[6][kBlock];
-  trh::BuildArgs a{};
-  a.n_s = (int32_t)n_s;
-  a.n_c = (int32_t)n_c;
-  a.sph64 = sph64;
-  a.cylA64 = cylA64;
-  a.cylB64 = cylB64;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  const int64_t N = n_s + n_c;
+  const int64_t N = (int64_t)a.n_s + a.n_c + a.n_t;
   for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < N;
        k += (int64_t)gridDim.x * kBlock) {
     double bl[3], bh[3];
@@ -218,7 +250,7 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 __global__ void k_count(trh::BuildArgs a, uint32_t *count) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t k = t / kLanes;
-  if (k >= (int64_t)a.n_s + a.n_c) return;
+  if (k >= (int64_t)a.n_s + a.n_c + a.n_t) return;
   for_prim_cells(a, k, (int)(t % kLanes), [&](uint32_t c) { atomicAdd(&count[c], 1u); });
 }
 
@@ -226,7 +258,7 @@ __global__ void k_scatter(trh::BuildArgs a, const uint32_t *cell_begin, uint32_t
                           uint32_t *refs) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t k = t / kLanes;
-  if (k >= (int64_t)a.n_s + a.n_c) return;
+  if (k >= (int64_t)a.n_s + a.n_c + a.n_t) return;
   for_prim_cells(a, k, (int)(t % kLanes), [&](uint32_t c) {
     const uint32_t pos = atomicAdd(&cursor[c], 1u);
     refs[cell_begin[c] + pos] = (uint32_t)k;
@@ -411,25 +443,20 @@ inline unsigned blocks_for(int64_t n, int b = kBlock) {
 
 namespace trh {
 
-hipError_t launch_pack(int64_t n_s, int64_t n_c, const double *sc, const double *sr,
-                       const float *srgb, const float *sop, const double *ca, const double *cb,
-                       const double *cr, const float *crgb, const float *cop, double4 *sph64,
-                       double4 *cylA64, double4 *cylW64, double4 *cylB64, float4 *albedo,
-                       hipStream_t st) {
-  const int64_t N = n_s + n_c;
+hipError_t launch_pack(const PackArgs &p, hipStream_t st) {
+  const int64_t N = p.n_s + p.n_c + p.n_t;
   if (N == 0) return hipSuccess;
-  k_pack<<<blocks_for(N), kBlock, 0, st>>>(n_s, n_c, sc, sr, srgb, sop, ca, cb, cr, crgb, cop,
-                                           sph64, cylA64, cylW64, cylB64, albedo);
+  k_pack<<<blocks_for(N), kBlock, 0, st>>>(p);
   return hipGetLastError();
 }
 
-hipError_t launch_pack32(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
-                         const double4 *cylW64, const double origin[3], float4 *sph32,
-                         float4 *cylA32, float4 *cylW32, hipStream_t st) {
-  const int64_t N = n_s + n_c;
+hipError_t launch_pack32(const BuildArgs &a, const double4 *cylW64, const double origin[3],
+                         float4 *sph32, float4 *cylA32, float4 *cylW32, float4 *triV32,
+                         float4 *triE1_32, float4 *triE2_32, hipStream_t st) {
+  const int64_t N = (int64_t)a.n_s + a.n_c + a.n_t;
   if (N == 0) return hipSuccess;
-  k_pack32<<<blocks_for(N), kBlock, 0, st>>>(n_s, n_c, sph64, cylA64, cylW64, origin[0], origin[1],
-                                             origin[2], sph32, cylA32, cylW32);
+  k_pack32<<<blocks_for(N), kBlock, 0, st>>>(a, cylW64, origin[0], origin[1], origin[2], sph32,
+                                             cylA32, cylW32, triV32, triE1_32, triE2_32);
   return hipGetLastError();
 }
 
@@ -442,10 +469,9 @@ static int32_t bounds_blocks(int64_t N) {
 
 int64_t bounds_scratch_doubles(int64_t n_prims) { return 6 * (int64_t)bounds_blocks(n_prims); }
 
-hipError_t launch_bounds(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
-                         const double4 *cylB64, double *scratch, double *out6, hipStream_t st) {
-  const int32_t nb = bounds_blocks(n_s + n_c);
-  k_bounds_partial<<<nb, kBlock, 0, st>>>(n_s, n_c, sph64, cylA64, cylB64, scratch);
+hipError_t launch_bounds(const BuildArgs &a, double *scratch, double *out6, hipStream_t st) {
+  const int32_t nb = bounds_blocks((int64_t)a.n_s + a.n_c + a.n_t);
+  k_bounds_partial<<<nb, kBlock, 0, st>>>(a, scratch);
   k_bounds_final<<<1, kBlock, 0, st>>>(scratch, nb, out6);
   return hipGetLastError();
 }
@@ -459,7 +485,7 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
 }
 
 hipError_t launch_count(const BuildArgs &a, uint32_t *count, hipStream_t st) {
-  const int64_t N = (int64_t)a.n_s + a.n_c;
+  const int64_t N = (int64_t)a.n_s + a.n_c + a.n_t;
   if (N == 0) return hipSuccess;
   k_count<<<blocks_for(N * kLanes), kBlock, 0, st>>>(a, count);
   return hipGetLastError();
@@ -493,7 +519,7 @@ hipError_t launch_scan(uint32_t *data, int64_t n, uint32_t *scratch, hipStream_t
 
 hipError_t launch_scatter(const BuildArgs &a, const uint32_t *cell_begin, uint32_t *cursor,
                           uint32_t *refs, hipStream_t st) {
-  const int64_t N = (int64_t)a.n_s + a.n_c;
+  const int64_t N = (int64_t)a.n_s + a.n_c + a.n_t;
   if (N == 0) return hipSuccess;
   k_scatter<<<blocks_for(N * kLanes), kBlock, 0, st>>>(a, cell_begin, cursor, refs);
   return hipGetLastError();

@@ -16,7 +16,7 @@ using namespace trd;
 constexpr double kEps = 1e-4;  // secondary-ray t_min (world units)
 
 struct Cnt {
-  uint32_t rays, cells, st, sh, ct, ch;
+  uint32_t rays, cells, st, sh, ct, ch, tt, th;
 };
 
 __device__ __forceinline__ int32_t cell_coord(const SceneDev &S, int q, double x) {
@@ -88,6 +88,11 @@ __device__ int trace_f64(const SceneDev &S, const double o[3], const double d[3]
         c.st++;
         h = hit_sphere_f64(S.sph64[k], o, d, tmin, tmax, t);
         c.sh += h;
+      } else if (k >= S.n_s + S.n_c) {
+        const int32_t m = k - S.n_s - S.n_c;
+        c.tt++;
+        h = hit_triangle_f64(S.triA64[m], S.triB64[m], S.triC64[m], o, d, tmin, tmax, t);
+        c.th += h;
       } else {
         c.ct++;
         h = hit_cylinder_f64(S.cylA64[k - S.n_s], S.cylW64[k - S.n_s], o, d, tmin, tmax, t);
@@ -126,6 +131,9 @@ __device__ __forceinline__ void normal_f64(const SceneDev &S, int32_t k, const d
     n[0] = (P[0] - s.x) / s.w;
     n[1] = (P[1] - s.y) / s.w;
     n[2] = (P[2] - s.z) / s.w;
+  } else if (k >= S.n_s + S.n_c) {
+    const int32_t m = k - S.n_s - S.n_c;
+    triangle_normal_f64(S.triA64[m], S.triB64[m], S.triC64[m], n);
   } else {
     const double4 a = S.cylA64[k - S.n_s], w4 = S.cylW64[k - S.n_s];
     const double w[3] = {w4.x, w4.y, w4.z};
@@ -145,7 +153,7 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
   }
   const int32_t i = blockIdx.x * 16 + (threadIdx.x & 15);
   const int32_t j = blockIdx.y * 16 + (threadIdx.x >> 4);
-  Cnt c{0, 0, 0, 0, 0, 0};
+  Cnt c{0, 0, 0, 0, 0, 0, 0, 0};
   uint32_t n_hit = 0, n_ao = 0, n_sh = 0;
   if (i < J.W && j < J.H) {
     const SceneDev &S = J.sc;
@@ -270,6 +278,8 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
       atomicAdd(&red[TR_STAT_SPH_HITS], c.sh);
       atomicAdd(&red[TR_STAT_CYL_TESTS], c.ct);
       atomicAdd(&red[TR_STAT_CYL_HITS], c.ch);
+      atomicAdd(&red[TR_STAT_TRI_TESTS], c.tt);
+      atomicAdd(&red[TR_STAT_TRI_HITS], c.th);
     }
   }
   if (STATS) {

@@ -97,7 +97,7 @@ struct Lds {
   uint32_t lmask[NS];
   uint8_t fifo[NS];
   BankInfo bank[BANKS];
-  uint32_t cnt[11];
+  uint32_t cnt[13];
   // compositing across surfaces: colour so far, transmittance in front of the
   // current surface, its index, and whether the FIFO entry is a continuation
   float acc_r[NT], acc_g[NT], acc_b[NT], trn[NT];
@@ -181,7 +181,9 @@ struct SceneHot {
   const TR_GLOBAL uint32_t *refs;
   const TR_GLOBAL trd::CellInfo *cellinfo;
   const TR_GLOBAL vf4 *sph32, *cylA32, *cylW32, *albedo;
+  const TR_GLOBAL vf4 *triV32, *triE1_32, *triE2_32;
   int32_t n_s;
+  int32_t n_sc;  // first triangle id (spheres + cylinders)
   int32_t res[3];
   float lo32[3], hi32[3], inv32[3], h32[3];
   float org32[3];  // cell coordinate of the FP32 frame's origin
@@ -199,7 +201,11 @@ __device__ __forceinline__ SceneHot load_hot(const JobDev *Jg) {
   H.cylA32 = (const TR_GLOBAL vf4 *)J->sc.cylA32;
   H.cylW32 = (const TR_GLOBAL vf4 *)J->sc.cylW32;
   H.albedo = (const TR_GLOBAL vf4 *)J->sc.albedo;
+  H.triV32 = (const TR_GLOBAL vf4 *)J->sc.triV32;
+  H.triE1_32 = (const TR_GLOBAL vf4 *)J->sc.triE1_32;
+  H.triE2_32 = (const TR_GLOBAL vf4 *)J->sc.triE2_32;
   H.n_s = J->sc.n_s;
+  H.n_sc = J->sc.n_s + J->sc.n_c;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     H.res[q] = J->sc.res[q];
@@ -284,7 +290,7 @@ __device__ __forceinline__ int32_t find_job(const TR_CONST JobDev *jobs, int32_t
   return lo;
 }
 
-template <int BANKS, bool RESOLVE, bool COUNT, bool TRANS>
+template <int BANKS, bool RESOLVE, bool COUNT, bool TRANS, bool TRI>
 // Occupancy targets: 5 waves per SIMD for the plain two-bank kernel (96
 // VGPRs); compositing adds LDS state that allows fewer waves anyway.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : (BANKS == 2 && !COUNT ? 5 : 4)))) void k_render_wave(const WaveArgs A) {
@@ -294,7 +300,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
   const int32_t lane = threadIdx.x;
   const int32_t TW = A.tile_w;
   const int32_t TH = 64 / TW;
-  if (lane < 11) L.cnt[lane] = 0;
+  if (lane < 13) L.cnt[lane] = 0;
 
   // ---- wave-uniform control state
   int32_t q_head = 0, q_tail = 0, head_issued = 0;
@@ -310,6 +316,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
   // ---- counters (wave-uniform)
   uint64_t c_rays = 0;
   uint32_t l_cells = 0, l_st = 0, l_sh = 0, l_ct = 0, l_ch = 0, l_res = 0, l_jumps = 0;  // per lane
+  uint32_t l_tt = 0, l_th = 0;
   uint64_t c_iters = 0, c_lanes = 0, c_refills = 0;
   uint64_t c_cyc_trav = 0;
   const uint64_t c_cyc_start = COUNT ? clock64() : 0;
@@ -353,6 +360,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
         int h;
         if (gk < S.n_s)
           h = hit_sphere_f64(S.sph64[gk], o, d, tmin, tmax, t);
+        else if (TRI && gk >= S.n_s + S.n_c)
+          h = hit_triangle_f64(S.triA64[gk - S.n_s - S.n_c], S.triB64[gk - S.n_s - S.n_c],
+                               S.triC64[gk - S.n_s - S.n_c], o, d, tmin, tmax, t);
         else
           h = hit_cylinder_f64(S.cylA64[gk - S.n_s], S.cylW64[gk - S.n_s], o, d, tmin, tmax, t);
         int32_t nst = kRun;
@@ -392,6 +402,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
           Nx = Px - s.x;
           Ny = Py - s.y;
           Nz = Pz - s.z;
+        } else if (TRI && k >= S.n_sc) {  // triangle: e1 x e2
+          const vf4 e1 = ldg(S.triE1_32, (uint32_t)(k - S.n_sc));
+          const vf4 e2 = ldg(S.triE2_32, (uint32_t)(k - S.n_sc));
+          Nx = e1.y * e2.z - e1.z * e2.y;
+          Ny = e1.z * e2.x - e1.x * e2.z;
+          Nz = e1.x * e2.y - e1.y * e2.x;
         } else {
           const vf4 a = ldg(S.cylA32, (uint32_t)(k - S.n_s)), w = ldg(S.cylW32, (uint32_t)(k - S.n_s));
           const float Dx = R.ox - a.x, Dy = R.oy - a.y, Dz = R.oz - a.z;
@@ -916,7 +932,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
           t = t0 > R.tmin ? t0 : t1;
           hit = ok && t > R.tmin && t <= R.t1;
         }
-        if (is_cyl) {
+        if (TRI && is_cyl && nk >= H.n_sc) {
+          // ---- triangle (two-sided, Moller-Trumbore).  Undecidable in FP32,
+          // and so re-solved in FP64: a ray within 2^-12 of the triangle's
+          // plane (|det| against |e1 x e2|), or a hit point within 2^-12 of an
+          // edge in barycentric terms.
+          tested = true;
+          const uint32_t m = (uint32_t)(nk - H.n_sc);
+          const vf4 V = ldg(H.triV32, m), E1 = ldg(H.triE1_32, m), E2 = ldg(H.triE2_32, m);
+          const float Px = R.dy * E2.z - R.dz * E2.y, Py = R.dz * E2.x - R.dx * E2.z,
+                      Pz = R.dx * E2.y - R.dy * E2.x;
+          const float det = E1.x * Px + E1.y * Py + E1.z * Pz;
+          const float Tx = R.ox - V.x, Ty = R.oy - V.y, Tz = R.oz - V.z;
+          const float Qx = Ty * E1.z - Tz * E1.y, Qy = Tz * E1.x - Tx * E1.z,
+                      Qz = Tx * E1.y - Ty * E1.x;
+          const float id = rcpf(det);
+          const float u = (Tx * Px + Ty * Py + Tz * Pz) * id;
+          const float v = (R.dx * Qx + R.dy * Qy + R.dz * Qz) * id;
+          const float w = 1.0f - u - v;
+          t = (E2.x * Qx + E2.y * Qy + E2.z * Qz) * id;
+          const bool in_t = t > R.tmin && t <= R.t1;
+          const bool par = fabsf(det) <= kKappa * V.w;
+          const bool edge = u >= -kKappa && v >= -kKappa && w >= -kKappa &&
+                            (fabsf(u) <= kKappa || fabsf(v) <= kKappa || fabsf(w) <= kKappa);
+          graze = RESOLVE && (par || (edge && in_t));
+          hit = !graze && det != 0.0f && u >= 0.0f && v >= 0.0f && w >= 0.0f && in_t;
+        } else if (is_cyl) {
           tested = true;
           const vf4 a = ldg(H.cylA32, (uint32_t)(nk - H.n_s));
           const vf4 w = ldg(H.cylW32, (uint32_t)(nk - H.n_s));
@@ -957,6 +998,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
             if (nk < H.n_s) {
               ++l_st;
               l_sh += hit;
+            } else if (TRI && nk >= H.n_sc) {
+              ++l_tt;
+              l_th += hit;
             } else {
               ++l_ct;
               l_ch += hit;
@@ -995,6 +1039,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
       atomicAdd(&L.cnt[8], l_ch);
       atomicAdd(&L.cnt[9], l_res);
       atomicAdd(&L.cnt[10], l_jumps);
+      if (TRI) {
+        atomicAdd(&L.cnt[11], l_tt);
+        atomicAdd(&L.cnt[12], l_th);
+      }
     }
     __syncthreads();
     if (lane == 0) {
@@ -1015,6 +1063,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
         atomicAdd(&st[TR_STAT_LANE_ITERS], (unsigned long long)c_lanes);
         atomicAdd(&st[TR_STAT_REFILLS], (unsigned long long)c_refills);
         atomicAdd(&st[TR_STAT_JUMPS], (unsigned long long)L.cnt[10]);
+        atomicAdd(&st[TR_STAT_TRI_TESTS], (unsigned long long)L.cnt[11]);
+        atomicAdd(&st[TR_STAT_TRI_HITS], (unsigned long long)L.cnt[12]);
         atomicAdd(&st[TR_STAT_CYCLES_TRAVERSE], (unsigned long long)c_cyc_trav);
         atomicAdd(&st[TR_STAT_CYCLES_TOTAL], (unsigned long long)(clock64() - c_cyc_start));
       }
@@ -1048,7 +1098,7 @@ __global__ void k_debug_ao_dirs(int64_t n, const float *nrm, const uint32_t *pix
 
 namespace trh {
 
-template <int BANKS, bool RES, bool CNT, bool TRANS>
+template <int BANKS, bool RES, bool CNT, bool TRANS, bool TRI>
 static hipError_t launch_t(const WaveLaunch &L, hipStream_t st) {
   WaveArgs a;
   a.jobs = L.jobs;
@@ -1060,21 +1110,26 @@ static hipError_t launch_t(const WaveLaunch &L, hipStream_t st) {
   a.refill_below = L.refill_below;
   a.cyl_wait = L.cyl_wait;
   a.mix = L.mix;
-  k_render_wave<BANKS, RES, CNT, TRANS><<<L.n_waves, 64, 0, st>>>(a);
+  k_render_wave<BANKS, RES, CNT, TRANS, TRI><<<L.n_waves, 64, 0, st>>>(a);
   return hipGetLastError();
 }
 
-template <int BANKS, bool TRANS>
+template <int BANKS, bool TRANS, bool TRI>
 static hipError_t launch_bt(const WaveLaunch &L, hipStream_t st) {
   const bool cnt = L.count_ops != 0 && L.stats != nullptr;
   if (L.resolve)
-    return cnt ? launch_t<BANKS, true, true, TRANS>(L, st) : launch_t<BANKS, true, false, TRANS>(L, st);
-  return cnt ? launch_t<BANKS, false, true, TRANS>(L, st) : launch_t<BANKS, false, false, TRANS>(L, st);
+    return cnt ? launch_t<BANKS, true, true, TRANS, TRI>(L, st)
+               : launch_t<BANKS, true, false, TRANS, TRI>(L, st);
+  return cnt ? launch_t<BANKS, false, true, TRANS, TRI>(L, st)
+             : launch_t<BANKS, false, false, TRANS, TRI>(L, st);
 }
 
+// Variants: compositing (transparency) and triangles are compiled in only
+// for launches that need them, so the common kernel keeps its registers.
 template <int BANKS>
 static hipError_t launch_b(const WaveLaunch &L, hipStream_t st) {
-  return L.trans ? launch_bt<BANKS, true>(L, st) : launch_bt<BANKS, false>(L, st);
+  if (L.trans) return L.tri ? launch_bt<BANKS, true, true>(L, st) : launch_bt<BANKS, true, false>(L, st);
+  return L.tri ? launch_bt<BANKS, false, true>(L, st) : launch_bt<BANKS, false, false>(L, st);
 }
 
 hipError_t launch_render_wave(const WaveLaunch &L, hipStream_t st) {

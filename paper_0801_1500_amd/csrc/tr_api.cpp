@@ -52,7 +52,7 @@ static bool finite3(const double *v) {
 struct tr_scene {
   int device = 0;
   int32_t key = 0;
-  int64_t n_s = 0, n_c = 0;
+  int64_t n_s = 0, n_c = 0, n_t = 0;
   int32_t n_lights = 0;
   double ldir[8][3] = {};
   double ldir_in[8][3] = {};  // light directions as given (saved by tr_scene_save)
@@ -61,6 +61,8 @@ struct tr_scene {
   // device arrays
   double4 *sph64 = nullptr, *cylA64 = nullptr, *cylW64 = nullptr, *cylB64 = nullptr;
   float4 *sph32 = nullptr, *cylA32 = nullptr, *cylW32 = nullptr, *albedo = nullptr;
+  double4 *triA64 = nullptr, *triB64 = nullptr, *triC64 = nullptr;
+  float4 *triV32 = nullptr, *triE1_32 = nullptr, *triE2_32 = nullptr;
   uint32_t *cell_begin = nullptr, *refs = nullptr, *count = nullptr, *scan_scratch = nullptr;
   uint32_t *wrefs = nullptr;  // FP32 walk lists: per occupied cell its references, then -1
   trd::CellInfo *cellinfo = nullptr;
@@ -85,7 +87,8 @@ static std::mutex g_mu;
 static void free_scene_arrays(tr_scene *s) {
   void *ptrs[] = {s->sph64, s->cylA64, s->cylW64, s->cylB64, s->sph32,       s->cylA32,
                   s->cylW32, s->albedo, s->cell_begin, s->refs, s->count, s->scan_scratch,
-                  s->bounds_scratch, s->bounds, s->cellinfo, s->dist0, s->dist1, s->wrefs};
+                  s->bounds_scratch, s->bounds, s->cellinfo, s->dist0, s->dist1, s->wrefs,
+                  s->triA64, s->triB64, s->triC64, s->triV32, s->triE1_32, s->triE2_32};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_bounds) (void)hipHostFree(s->h_bounds);
@@ -135,6 +138,13 @@ static void fill_scene_dev(tr_scene *s) {
   SceneDev &d = s->dev;
   d.n_s = (int32_t)s->n_s;
   d.n_c = (int32_t)s->n_c;
+  d.n_t = (int32_t)s->n_t;
+  d.triA64 = s->triA64;
+  d.triB64 = s->triB64;
+  d.triC64 = s->triC64;
+  d.triV32 = s->triV32;
+  d.triE1_32 = s->triE1_32;
+  d.triE2_32 = s->triE2_32;
   d.sph64 = s->sph64;
   d.cylA64 = s->cylA64;
   d.cylW64 = s->cylW64;
@@ -166,7 +176,17 @@ static void fill_scene_dev(tr_scene *s) {
 // Bounds -> parameters -> count -> scan -> scatter -> sort, from the resident
 // FP64 arrays.  Two blocking readbacks (bounds, reference total).
 static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
-  const int64_t N = s->n_s + s->n_c;
+  const int64_t N = s->n_s + s->n_c + s->n_t;
+  trh::BuildArgs a{};
+  a.n_s = (int32_t)s->n_s;
+  a.n_c = (int32_t)s->n_c;
+  a.n_t = (int32_t)s->n_t;
+  a.sph64 = s->sph64;
+  a.cylA64 = s->cylA64;
+  a.cylB64 = s->cylB64;
+  a.triA64 = s->triA64;
+  a.triB64 = s->triB64;
+  a.triC64 = s->triC64;
   if (N == 0) {
     double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
     for (int a = 0; a < 3; ++a) {
@@ -179,15 +199,14 @@ static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
     s->gp.delta = 0.0;
     s->gp.n_cells = 1;
   } else {
-    HIP_TRY(trh::launch_bounds(s->n_s, s->n_c, s->sph64, s->cylA64, s->cylB64, s->bounds_scratch,
-                               s->bounds, st));
+    HIP_TRY(trh::launch_bounds(a, s->bounds_scratch, s->bounds, st));
     HIP_TRY(hipMemcpyAsync(s->h_bounds, s->bounds, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     grid_params(s->h_bounds, s->h_bounds + 3, N, s->lambda, s->gp);
   }
   for (int a = 0; a < 3; ++a) s->org[a] = 0.5 * (s->gp.lo[a] + s->gp.hi[a]);
-  HIP_TRY(trh::launch_pack32(s->n_s, s->n_c, s->sph64, s->cylA64, s->cylW64, s->org, s->sph32,
-                             s->cylA32, s->cylW32, st));
+  HIP_TRY(trh::launch_pack32(a, s->cylW64, s->org, s->sph32, s->cylA32, s->cylW32, s->triV32,
+                             s->triE1_32, s->triE2_32, st));
   const int64_t nc = s->gp.n_cells;
   if (nc + 1 > s->cap_cells) {
     if (s->cell_begin) (void)hipFree(s->cell_begin);
@@ -212,12 +231,6 @@ static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
     HIP_TRY(dmalloc(&s->scan_scratch, need_scan));
     s->cap_scan = need_scan;
   }
-  trh::BuildArgs a{};
-  a.n_s = (int32_t)s->n_s;
-  a.n_c = (int32_t)s->n_c;
-  a.sph64 = s->sph64;
-  a.cylA64 = s->cylA64;
-  a.cylB64 = s->cylB64;
   for (int q = 0; q < 3; ++q) {
     a.lo[q] = s->gp.lo[q];
     a.h[q] = s->gp.h[q];
@@ -270,10 +283,11 @@ static tr_status build_grid(tr_scene *s, hipStream_t st) {
 extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr_scene **out) {
   if (!d || !out) return fail(TR_EINVAL, "tr_scene_build: NULL desc or out");
   *out = nullptr;
-  if (d->n_spheres < 0 || d->n_cylinders < 0) return fail(TR_EINVAL, "negative primitive count");
+  if (d->n_spheres < 0 || d->n_cylinders < 0 || d->n_triangles < 0)
+    return fail(TR_EINVAL, "negative primitive count");
+  const int64_t n_all = d->n_spheres + d->n_cylinders + d->n_triangles;
   // the traversal addresses primitive records (16 B) with 32-bit byte offsets
-  if (d->n_spheres + d->n_cylinders >= (int64_t)1 << 28)
-    return fail(TR_EINVAL, "too many primitives (limit 2^28 - 1)");
+  if (n_all >= (int64_t)1 << 28) return fail(TR_EINVAL, "too many primitives (limit 2^28 - 1)");
   if (d->n_lights < 0 || d->n_lights > 8) return fail(TR_EINVAL, "n_lights must be 0..8");
   if (!(d->cells_per_prim >= 0.0) || !std::isfinite(d->cells_per_prim))
     return fail(TR_EINVAL, "cells_per_prim must be finite and >= 0");
@@ -282,6 +296,11 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   if (d->n_cylinders > 0 && (!d->cyl_a || !d->cyl_b || !d->cyl_radius || !d->cyl_rgb))
     return fail(TR_EINVAL, "NULL cylinder array");
   if (d->n_lights > 0 && (!d->light_dir || !d->light_rgb)) return fail(TR_EINVAL, "NULL light array");
+  if (d->n_triangles > 0 && (!d->tri_v0 || !d->tri_v1 || !d->tri_v2 || !d->tri_rgb))
+    return fail(TR_EINVAL, "NULL triangle array");
+  for (int64_t k = 0; k < d->n_triangles; ++k)
+    if (!finite3(d->tri_v0 + 3 * k) || !finite3(d->tri_v1 + 3 * k) || !finite3(d->tri_v2 + 3 * k))
+      return fail(TR_EINVAL, "triangle %lld: non-finite vertex", (long long)k);
   for (int64_t k = 0; k < d->n_spheres; ++k) {
     if (!finite3(d->sph_center + 3 * k) || !std::isfinite(d->sph_radius[k]))
       return fail(TR_EINVAL, "sphere %lld: non-finite value", (long long)k);
@@ -296,10 +315,11 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
       return fail(TR_EINVAL, "cylinder %lld: zero length", (long long)k);
   }
   bool has_trans = false;
-  for (int64_t k = 0; k < d->n_spheres + d->n_cylinders; ++k) {
-    const float *op = k < d->n_spheres ? d->sph_opacity : d->cyl_opacity;
+  for (int64_t k = 0; k < n_all; ++k) {
+    const int64_t nsc = d->n_spheres + d->n_cylinders;
+    const float *op = k < d->n_spheres ? d->sph_opacity : (k < nsc ? d->cyl_opacity : d->tri_opacity);
     if (!op) continue;
-    const float a = op[k < d->n_spheres ? k : k - d->n_spheres];
+    const float a = op[k < d->n_spheres ? k : (k < nsc ? k - d->n_spheres : k - nsc)];
     if (!(a > 0.0f && a <= 1.0f))
       return fail(TR_EINVAL, "primitive %lld: opacity must be in (0, 1]", (long long)k);
     has_trans |= a < 1.0f;
@@ -318,6 +338,7 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   }
   s->n_s = d->n_spheres;
   s->n_c = d->n_cylinders;
+  s->n_t = d->n_triangles;
   s->n_lights = d->n_lights;
   s->has_trans = has_trans;
   s->lambda = d->cells_per_prim > 0.0 ? d->cells_per_prim : 24.0;
@@ -337,7 +358,7 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
     g_err = msg;
     return stt;
   };
-  const int64_t N = s->n_s + s->n_c;
+  const int64_t N = s->n_s + s->n_c + s->n_t;
   hipError_t e = hipSuccess;
 #define ALLOC(p, n)                                                      \
   if (e == hipSuccess) e = dmalloc(&(p), (n));
@@ -349,6 +370,12 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   ALLOC(s->cylA32, s->n_c);
   ALLOC(s->cylW32, s->n_c);
   ALLOC(s->albedo, N);
+  ALLOC(s->triA64, s->n_t);
+  ALLOC(s->triB64, s->n_t);
+  ALLOC(s->triC64, s->n_t);
+  ALLOC(s->triV32, s->n_t);
+  ALLOC(s->triE1_32, s->n_t);
+  ALLOC(s->triE2_32, s->n_t);
   ALLOC(s->bounds_scratch, trh::bounds_scratch_doubles(N));
   ALLOC(s->bounds, 6);
 #undef ALLOC
@@ -357,12 +384,16 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   if (e != hipSuccess)
     return bail(fail(e == hipErrorOutOfMemory ? TR_ENOMEM : TR_EDEVICE, "scene allocation: %s",
                      hipGetErrorString(e)));
-  s->bytes_arrays = (size_t)s->n_s * (32 + 16) + (size_t)s->n_c * (3 * 32 + 2 * 16) + (size_t)N * 16;
+  s->bytes_arrays = (size_t)s->n_s * (32 + 16) + (size_t)s->n_c * (3 * 32 + 2 * 16) +
+                    (size_t)s->n_t * (3 * 32 + 3 * 16) + (size_t)N * 16;
   // upload the caller's arrays (temporary device copies), then pack
   double *t_sc = nullptr, *t_sr = nullptr, *t_ca = nullptr, *t_cb = nullptr, *t_cr = nullptr;
   float *t_srgb = nullptr, *t_crgb = nullptr, *t_sop = nullptr, *t_cop = nullptr;
+  double *t_tv0 = nullptr, *t_tv1 = nullptr, *t_tv2 = nullptr;
+  float *t_trgb = nullptr, *t_top = nullptr;
   auto free_tmp = [&]() {
-    void *p[] = {t_sc, t_sr, t_ca, t_cb, t_cr, t_srgb, t_crgb, t_sop, t_cop};
+    void *p[] = {t_sc, t_sr, t_ca, t_cb, t_cr, t_srgb, t_crgb, t_sop, t_cop,
+                 t_tv0, t_tv1, t_tv2, t_trgb, t_top};
     for (void *q : p)
       if (q) (void)hipFree(q);
   };
@@ -394,9 +425,48 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
         if (e == hipSuccess) e = hipMemcpyAsync(t_cop, d->cyl_opacity, 4 * s->n_c, hipMemcpyHostToDevice, st);
       }
     }
-    if (e == hipSuccess)
-      e = trh::launch_pack(s->n_s, s->n_c, t_sc, t_sr, t_srgb, t_sop, t_ca, t_cb, t_cr, t_crgb,
-                           t_cop, s->sph64, s->cylA64, s->cylW64, s->cylB64, s->albedo, st);
+    if (s->n_t > 0) {
+      const int64_t nt = s->n_t;
+      if (e == hipSuccess) e = dmalloc(&t_tv0, 3 * nt);
+      if (e == hipSuccess) e = dmalloc(&t_tv1, 3 * nt);
+      if (e == hipSuccess) e = dmalloc(&t_tv2, 3 * nt);
+      if (e == hipSuccess) e = dmalloc(&t_trgb, 3 * nt);
+      if (e == hipSuccess) e = hipMemcpyAsync(t_tv0, d->tri_v0, 24 * nt, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(t_tv1, d->tri_v1, 24 * nt, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(t_tv2, d->tri_v2, 24 * nt, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(t_trgb, d->tri_rgb, 12 * nt, hipMemcpyHostToDevice, st);
+      if (d->tri_opacity) {
+        if (e == hipSuccess) e = dmalloc(&t_top, nt);
+        if (e == hipSuccess) e = hipMemcpyAsync(t_top, d->tri_opacity, 4 * nt, hipMemcpyHostToDevice, st);
+      }
+    }
+    trh::PackArgs pk{};
+    pk.n_s = s->n_s;
+    pk.n_c = s->n_c;
+    pk.n_t = s->n_t;
+    pk.sc = t_sc;
+    pk.sr = t_sr;
+    pk.ca = t_ca;
+    pk.cb = t_cb;
+    pk.cr = t_cr;
+    pk.tv0 = t_tv0;
+    pk.tv1 = t_tv1;
+    pk.tv2 = t_tv2;
+    pk.srgb = t_srgb;
+    pk.sop = t_sop;
+    pk.crgb = t_crgb;
+    pk.cop = t_cop;
+    pk.trgb = t_trgb;
+    pk.top = t_top;
+    pk.sph64 = s->sph64;
+    pk.cylA64 = s->cylA64;
+    pk.cylW64 = s->cylW64;
+    pk.cylB64 = s->cylB64;
+    pk.triA64 = s->triA64;
+    pk.triB64 = s->triB64;
+    pk.triC64 = s->triC64;
+    pk.albedo = s->albedo;
+    if (e == hipSuccess) e = trh::launch_pack(pk, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     free_tmp();
     if (e != hipSuccess)
@@ -454,33 +524,46 @@ extern "C" tr_status tr_scene_grid_arrays(const tr_scene *s, uint32_t *cell_begi
 // Binary scene file, little-endian (the "Parse" phase of Table 5 without a
 // text format): char magic[8] = "TRSCENE1"; int64 n_spheres, n_cylinders;
 // int32 n_lights, int32 flags; double cells_per_prim; then the arrays of
-// tr_scene_desc in its order, each padded to 8 bytes (the opacities only
-// with flags bit 0).
+// tr_scene_desc in its order, each padded to 8 bytes: spheres, cylinders,
+// lights; with flags bit 1 an int64 triangle count and the triangle arrays;
+// with flags bit 0 the opacities (of the triangles too with bit 1).
 static const char kSceneMagic[8] = {'T', 'R', 'S', 'C', 'E', 'N', 'E', '1'};
 
 static int64_t pad8(int64_t b) { return (b + 7) & ~(int64_t)7; }
 
-static constexpr int32_t kFileOpacity = 1;  // flags bit: opacity arrays follow
+static constexpr int32_t kFileOpacity = 1;    // flags bit: opacity arrays follow
+static constexpr int32_t kFileTriangles = 2;  // flags bit: triangle section follows
 
-static int64_t scene_file_bytes(int64_t ns, int64_t nc, int64_t nl, int32_t flags) {
+// bytes up to the end of the lights (where the triangle count sits)
+static int64_t scene_file_head(int64_t ns, int64_t nc, int64_t nl) {
   return 40 + pad8(24 * ns) + pad8(8 * ns) + pad8(12 * ns) + pad8(24 * nc) + pad8(24 * nc) +
-         pad8(8 * nc) + pad8(12 * nc) + 2 * pad8(24 * nl) +
-         ((flags & kFileOpacity) ? pad8(4 * ns) + pad8(4 * nc) : 0);
+         pad8(8 * nc) + pad8(12 * nc) + 2 * pad8(24 * nl);
+}
+
+static int64_t scene_file_bytes(int64_t ns, int64_t nc, int64_t nl, int32_t flags, int64_t nt) {
+  int64_t b = scene_file_head(ns, nc, nl);
+  if (flags & kFileTriangles) b += 8 + 3 * pad8(24 * nt) + pad8(12 * nt);
+  if (flags & kFileOpacity)
+    b += pad8(4 * ns) + pad8(4 * nc) + ((flags & kFileTriangles) ? pad8(4 * nt) : 0);
+  return b;
 }
 
 extern "C" tr_status tr_scene_save(const tr_scene *s, const char *path, void *hip_stream) {
   if (!s || !path) return fail(TR_EINVAL, "tr_scene_save: NULL scene or path");
   hipStream_t st = (hipStream_t)hip_stream;
-  const int64_t ns = s->n_s, nc = s->n_c, nl = s->n_lights, N = ns + nc;
-  std::vector<double4> sph(ns), ca(nc), cb(nc);
+  const int64_t ns = s->n_s, nc = s->n_c, nt = s->n_t, nl = s->n_lights, N = ns + nc + nt;
+  std::vector<double4> sph(ns), ca(nc), cb(nc), ta(nt), tb(nt), tc(nt);
   std::vector<float4> alb(N);
+  if (nt) HIP_TRY(hipMemcpyAsync(ta.data(), s->triA64, nt * sizeof(double4), hipMemcpyDeviceToHost, st));
+  if (nt) HIP_TRY(hipMemcpyAsync(tb.data(), s->triB64, nt * sizeof(double4), hipMemcpyDeviceToHost, st));
+  if (nt) HIP_TRY(hipMemcpyAsync(tc.data(), s->triC64, nt * sizeof(double4), hipMemcpyDeviceToHost, st));
   if (ns) HIP_TRY(hipMemcpyAsync(sph.data(), s->sph64, ns * sizeof(double4), hipMemcpyDeviceToHost, st));
   if (nc) HIP_TRY(hipMemcpyAsync(ca.data(), s->cylA64, nc * sizeof(double4), hipMemcpyDeviceToHost, st));
   if (nc) HIP_TRY(hipMemcpyAsync(cb.data(), s->cylB64, nc * sizeof(double4), hipMemcpyDeviceToHost, st));
   if (N) HIP_TRY(hipMemcpyAsync(alb.data(), s->albedo, N * sizeof(float4), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  const int32_t flags = s->has_trans ? kFileOpacity : 0;
-  std::vector<char> buf((size_t)scene_file_bytes(ns, nc, nl, flags), 0);
+  const int32_t flags = (s->has_trans ? kFileOpacity : 0) | (nt > 0 ? kFileTriangles : 0);
+  std::vector<char> buf((size_t)scene_file_bytes(ns, nc, nl, flags, nt), 0);
   char *p = buf.data();
   std::memcpy(p, kSceneMagic, 8);
   std::memcpy(p + 8, &ns, 8);
@@ -515,9 +598,18 @@ extern "C" tr_status tr_scene_save(const tr_scene *s, const char *path, void *hi
   put_f(3 * nc, [&](int64_t i) { return compf(alb[ns + i / 3], i % 3); });
   put_d(3 * nl, [&](int64_t i) { return s->ldir_in[i / 3][i % 3]; });
   put_d(3 * nl, [&](int64_t i) { return s->lrgb[i / 3][i % 3]; });
+  if (flags & kFileTriangles) {
+    std::memcpy(p + o, &nt, 8);
+    o += 8;
+    put_d(3 * nt, [&](int64_t i) { return comp(ta[i / 3], i % 3); });
+    put_d(3 * nt, [&](int64_t i) { return comp(tb[i / 3], i % 3); });
+    put_d(3 * nt, [&](int64_t i) { return comp(tc[i / 3], i % 3); });
+    put_f(3 * nt, [&](int64_t i) { return compf(alb[ns + nc + i / 3], i % 3); });
+  }
   if (flags & kFileOpacity) {
     put_f(ns, [&](int64_t i) { return alb[i].w; });
     put_f(nc, [&](int64_t i) { return alb[ns + i].w; });
+    if (flags & kFileTriangles) put_f(nt, [&](int64_t i) { return alb[ns + nc + i].w; });
   }
   FILE *f = std::fopen(path, "wb");
   if (!f) return fail(TR_EINVAL, "tr_scene_save: cannot open %s for writing", path);
@@ -554,12 +646,22 @@ extern "C" tr_status tr_scene_load(const char *path, void *hip_stream, tr_scene 
   std::memcpy(&nl, p + 24, 4);
   std::memcpy(&flags, p + 28, 4);
   std::memcpy(&lambda, p + 32, 8);
-  if (flags & ~kFileOpacity) return fail(TR_EINVAL, "tr_scene_load: %s has unknown flags", path);
+  if (flags & ~(kFileOpacity | kFileTriangles))
+    return fail(TR_EINVAL, "tr_scene_load: %s has unknown flags", path);
   if (ns < 0 || nc < 0 || ns >= ((int64_t)1 << 28) || nc >= ((int64_t)1 << 28) || nl < 0 || nl > 8)
     return fail(TR_EINVAL, "tr_scene_load: %s has bad counts", path);
-  if (scene_file_bytes(ns, nc, nl, flags) != (int64_t)size)
+  int64_t nt = 0;
+  if (flags & kFileTriangles) {
+    const int64_t at = scene_file_head(ns, nc, nl);
+    if (at + 8 > (int64_t)size)
+      return fail(TR_EINVAL, "tr_scene_load: %s has %ld bytes, its counts need more", path, size);
+    std::memcpy(&nt, p + at, 8);
+    if (nt < 0 || nt >= ((int64_t)1 << 28))
+      return fail(TR_EINVAL, "tr_scene_load: %s has bad counts", path);
+  }
+  if (scene_file_bytes(ns, nc, nl, flags, nt) != (int64_t)size)
     return fail(TR_EINVAL, "tr_scene_load: %s has %ld bytes, its counts need %lld", path, size,
-                (long long)scene_file_bytes(ns, nc, nl, flags));
+                (long long)scene_file_bytes(ns, nc, nl, flags, nt));
   int64_t o = 40;
   auto take = [&](int64_t bytes) {
     const char *q = p + o;
@@ -580,9 +682,18 @@ extern "C" tr_status tr_scene_load(const char *path, void *hip_stream, tr_scene 
   d.light_dir = (const double *)take(24 * nl);
   d.light_rgb = (const double *)take(24 * nl);
   d.cells_per_prim = lambda;
+  if (flags & kFileTriangles) {
+    take(8);
+    d.n_triangles = nt;
+    d.tri_v0 = (const double *)take(24 * nt);
+    d.tri_v1 = (const double *)take(24 * nt);
+    d.tri_v2 = (const double *)take(24 * nt);
+    d.tri_rgb = (const float *)take(12 * nt);
+  }
   if (flags & kFileOpacity) {
     d.sph_opacity = (const float *)take(4 * ns);
     d.cyl_opacity = (const float *)take(4 * nc);
+    if (flags & kFileTriangles) d.tri_opacity = (const float *)take(4 * nt);
   }
   return tr_scene_build(&d, hip_stream, out);
 }
@@ -822,7 +933,7 @@ static std::map<TuneKey, tr_tune> g_tune_cache;
 static TuneKey tune_key(const tr_scene *s, const tr_camera *c, const tr_params *p) {
   int dev = 0;
   (void)hipGetDevice(&dev);
-  const int64_t N = s->n_s + s->n_c;
+  const int64_t N = s->n_s + s->n_c + s->n_t;
   int b = 0;
   while ((int64_t(1) << b) < N + 1) ++b;
   return TuneKey{dev, b, c->width, c->height, p->ao_samples, p->precision};
@@ -960,7 +1071,11 @@ static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, u
   L.n_waves = (int32_t)waves;
   L.resolve = jobs[0].resolve;
   L.trans = 0;
-  for (const JobDev &J : jobs) L.trans |= J.layers > 1;
+  L.tri = 0;
+  for (const JobDev &J : jobs) {
+    L.trans |= J.layers > 1;
+    L.tri |= J.sc.n_t > 0;
+  }
   HIP_TRY(trh::launch_render_wave(L, st));
   HIP_TRY(hipEventRecord(ls->done, st));
   return TR_OK;
@@ -1153,6 +1268,8 @@ extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, c
       rc = fail(TR_EUNSUPPORTED, "graphs need an FP32 precision");
     if (rc == TR_OK && aa_count(params[i]) > 1)
       rc = fail(TR_EUNSUPPORTED, "graphs need aa_samples <= 1");
+    if (rc == TR_OK && J.layers > 1)
+      rc = fail(TR_EUNSUPPORTED, "graphs render opaque frames (max_layers <= 1)");
     if (rc == TR_OK && (params[i].precision == TR_PREC_FP32_RESOLVE) != (res != 0))
       rc = fail(TR_EINVAL, "all jobs of one graph must use the same precision");
     if (rc == TR_OK && frames[i].stats != frames[0].stats)
@@ -1207,6 +1324,9 @@ extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, c
     if (waves > total) waves = total;
     L.n_waves = (int32_t)std::max<int64_t>(waves, 1);
     L.resolve = res;
+    L.trans = 0;
+    L.tri = 0;
+    for (int32_t i = 0; i < n; ++i) L.tri |= g->jobs[i].sc.n_t > 0;
     if (e == hipSuccess) e = trh::launch_render_wave(L, cap);
     hipError_t e2 = hipStreamEndCapture(cap, &g->graph);
     if (e == hipSuccess) e = e2;
@@ -1236,6 +1356,8 @@ extern "C" tr_status tr_graph_update(tr_graph *g, const tr_camera *cams, const t
     if (aa_count(p) > 1) return fail(TR_EUNSUPPORTED, "job %d: graphs need aa_samples <= 1", i);
     tr_status rc = make_job(g->scenes[i], &c, &p, &g->frames[i], g->tune.tile_w, nj[i]);
     if (rc != TR_OK) return fail(rc, "job %d: %s", i, g_err.c_str());
+    if (nj[i].layers > 1)
+      return fail(TR_EUNSUPPORTED, "job %d: graphs render opaque frames (max_layers <= 1)", i);
     nj[i].queue_begin = g->jobs[i].queue_begin;
   }
   for (int32_t i = 0; i < g->n; ++i) {

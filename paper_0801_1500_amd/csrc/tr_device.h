@@ -7,6 +7,8 @@
 //   cylB64 double4[n_c]  (bx, by, bz, 0)           second end point (grid rebuild)
 //   sph32  float4[n_s]   rounded copies for the FP32 traversal: one 16-byte load per sphere
 //   cylA32 float4[n_c], cylW32 float4[n_c]         two 16-byte loads per cylinder
+//   triA64/triB64/triC64 double4[n_t]  triangle vertices (FP64)
+//   triV32, triE1_32, triE2_32 float4[n_t]  (v0, |e1 x e2|), e1, e2: three loads per triangle
 //                        (FP32 positions are relative to org, the centre of the grid
 //                        box: lo32 = lo - org, hi32 = hi - org, eye32 = eye - org)
 //   albedo float4[N]     (r, g, b, opacity) by global id
@@ -32,9 +34,11 @@ static_assert(sizeof(CellInfo) == 8, "CellInfo is two words");
 
 // ----------------------------------------------------------------- scene
 struct SceneDev {
-  int32_t n_s, n_c;
+  int32_t n_s, n_c, n_t;  // ids: spheres, then cylinders, then triangles
   const double4 *sph64, *cylA64, *cylW64;
+  const double4 *triA64, *triB64, *triC64;  // triangle vertices (FP64)
   const float4 *sph32, *cylA32, *cylW32;
+  const float4 *triV32, *triE1_32, *triE2_32;  // (v0 - org, |e1 x e2|), (e1, 0), (e2, 0)
   const float4 *albedo;
   const uint32_t *cell_begin, *refs;
   const uint32_t *wrefs;  // walk lists (see CellInfo)
@@ -255,6 +259,50 @@ __device__ __forceinline__ int hit_cylinder_f64(const double4 aa, const double4 
     if (s >= 0.0 && s <= ww.w) { t = th; return 1; }
   }
   return 0;
+}
+
+// Triangle (two-sided), Moller and Trumbore: e1 = B - A, e2 = C - A,
+// P = d x e2, det = e1.P, T = o - A, Q = T x e1; u = T.P / det,
+// v = d.Q / det, t = e2.Q / det; a hit needs det != 0, u >= 0, v >= 0,
+// u + v <= 1 and t in (tmin, tmax].
+__device__ __forceinline__ void cross3d(const double a[3], const double b[3], double r[3]) {
+  r[0] = a[1] * b[2] - a[2] * b[1];
+  r[1] = a[2] * b[0] - a[0] * b[2];
+  r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ __forceinline__ int hit_triangle_f64(const double4 A, const double4 B, const double4 C,
+                                                const double o[3], const double d[3], double tmin,
+                                                double tmax, double &t) {
+  const double e1[3] = {B.x - A.x, B.y - A.y, B.z - A.z};
+  const double e2[3] = {C.x - A.x, C.y - A.y, C.z - A.z};
+  double P[3], Q[3];
+  cross3d(d, e2, P);
+  const double det = dot3d(e1, P);
+  if (det == 0.0) return 0;
+  const double T[3] = {o[0] - A.x, o[1] - A.y, o[2] - A.z};
+  const double u = dot3d(T, P) / det;
+  if (!(u >= 0.0 && u <= 1.0)) return 0;
+  cross3d(T, e1, Q);
+  const double v = dot3d(d, Q) / det;
+  if (!(v >= 0.0 && u + v <= 1.0)) return 0;
+  const double tt = dot3d(e2, Q) / det;
+  if (!(tt > tmin && tt <= tmax)) return 0;
+  t = tt;
+  return 1;
+}
+
+// Unit normal e1 x e2 of triangle (A, B, C), not flipped.
+__device__ __forceinline__ void triangle_normal_f64(const double4 A, const double4 B,
+                                                    const double4 C, double n[3]) {
+  const double e1[3] = {B.x - A.x, B.y - A.y, B.z - A.z};
+  const double e2[3] = {C.x - A.x, C.y - A.y, C.z - A.z};
+  double c[3];
+  cross3d(e1, e2, c);
+  const double m = sqrt(dot3d(c, c));
+  n[0] = c[0] / m;
+  n[1] = c[1] / m;
+  n[2] = c[2] / m;
 }
 
 }  // namespace trd

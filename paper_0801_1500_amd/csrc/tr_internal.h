@@ -19,27 +19,30 @@ struct GridParams {
 
 // Inputs of the count / scatter kernels.
 struct BuildArgs {
-  int32_t n_s, n_c;
+  int32_t n_s, n_c, n_t;
   const double4 *sph64, *cylA64, *cylB64;
+  const double4 *triA64, *triB64, *triC64;
   double lo[3], h[3], inv[3], delta;
   int32_t res[3];
 };
 
 // ---- grid build launchers (grid_build.hip) ----
-// albedo = (r, g, b, opacity); sop / cop may be null (opaque)
-hipError_t launch_pack(int64_t n_s, int64_t n_c, const double *sc, const double *sr,
-                       const float *srgb, const float *sop, const double *ca, const double *cb,
-                       const double *cr, const float *crgb, const float *cop, double4 *sph64,
-                       double4 *cylA64, double4 *cylW64, double4 *cylB64, float4 *albedo,
-                       hipStream_t st);
+// albedo = (r, g, b, opacity); sop / cop / top may be null (opaque)
+struct PackArgs {
+  int64_t n_s, n_c, n_t;
+  const double *sc, *sr, *ca, *cb, *cr, *tv0, *tv1, *tv2;
+  const float *srgb, *sop, *crgb, *cop, *trgb, *top;
+  double4 *sph64, *cylA64, *cylW64, *cylB64, *triA64, *triB64, *triC64;
+  float4 *albedo;
+};
+hipError_t launch_pack(const PackArgs &p, hipStream_t st);
 // FP32 copies with positions relative to origin (the centre of the grid box)
-hipError_t launch_pack32(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
-                         const double4 *cylW64, const double origin[3], float4 *sph32,
-                         float4 *cylA32, float4 *cylW32, hipStream_t st);
+hipError_t launch_pack32(const BuildArgs &a, const double4 *cylW64, const double origin[3],
+                         float4 *sph32, float4 *cylA32, float4 *cylW32, float4 *triV32,
+                         float4 *triE1_32, float4 *triE2_32, hipStream_t st);
 // bounds: out6 = (lo xyz, hi xyz); scratch >= bounds_scratch_doubles(N) doubles
 int64_t bounds_scratch_doubles(int64_t n_prims);
-hipError_t launch_bounds(int64_t n_s, int64_t n_c, const double4 *sph64, const double4 *cylA64,
-                         const double4 *cylB64, double *scratch, double *out6, hipStream_t st);
+hipError_t launch_bounds(const BuildArgs &a, double *scratch, double *out6, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_count(const BuildArgs &a, uint32_t *count, hipStream_t st);
 // exclusive scan of n+1 entries in place (data[n] must be 0 on entry)
@@ -77,6 +80,7 @@ struct WaveLaunch {
   int32_t n_waves;           // persistent waves launched
   int32_t resolve;
   int32_t trans;             // some job composites transparent layers
+  int32_t tri;               // some job's scene has triangles
 };
 hipError_t launch_render_wave(const WaveLaunch &L, hipStream_t st);
 hipError_t launch_zero_counter(uint32_t *p, hipStream_t st);

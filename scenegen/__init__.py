@@ -217,13 +217,27 @@ def icosphere(subdiv: int):
     return np.array(verts), np.array(faces, dtype=np.int64)
 
 
-def blob_mesh(centres: np.ndarray, radius: float, subdiv: int) -> np.ndarray:
-    """Closed icosphere meshes of the given radius around each centre:
-    triangle vertices [n * F, 3, 3]."""
+def _random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n uniformly random rotation matrices (QR of Gaussian matrices with the
+    signs fixed)."""
+    q, r = np.linalg.qr(rng.normal(size=(n, 3, 3)))
+    q = q * np.sign(np.diagonal(r, axis1=1, axis2=2))[:, None, :]
+    q[np.linalg.det(q) < 0, :, 0] *= -1.0
+    return q
+
+
+def blob_mesh(centres: np.ndarray, radius: float, subdiv: int, seed: int = 0) -> np.ndarray:
+    """Closed icosphere meshes of the given radius around each centre, each
+    turned by its own random rotation (the icosahedron's symmetric faces
+    would otherwise have normals with exact zero components or exactly
+    perpendicular to a light, where a whole face's decisions hang on
+    rounding): triangle vertices [n * F, 3, 3]."""
     verts, faces = icosphere(subdiv)
     unit = verts[faces]  # [F, 3, 3]
     c = np.asarray(centres, dtype=np.float64).reshape(-1, 1, 1, 3)
-    return (c + radius * unit[None]).reshape(-1, 3, 3)
+    rot = _random_rotations(np.random.default_rng(seed), c.shape[0])
+    turned = np.einsum("nij,fvj->nfvi", rot, unit)
+    return (c + radius * turned).reshape(-1, 3, 3)
 
 
 def with_triangles(scene: Scene, tri_v: np.ndarray, tri_rgb=None, tri_opacity=None) -> Scene:
@@ -243,7 +257,7 @@ def mixed_tiny_scene(seed: int = 5) -> Scene:
     base = tiny_scene(seed=seed, n=24)
     ca = rng.uniform(-8, 8, (12, 3))
     cb = ca + 3.0 * _unit_gaussian(rng, 12)
-    blobs = blob_mesh(rng.uniform(-7, 7, (4, 3)), 2.5, 1)
+    blobs = blob_mesh(rng.uniform(-7, 7, (4, 3)), 2.5, 1, seed=seed)
     floor = np.array([[[-14, -11, -14], [14, -11, -14], [14, -11, 14]],
                       [[-14, -11, -14], [14, -11, 14], [-14, -11, 14]]], dtype=np.float64)
     s = Scene(**{**base.__dict__, "cyl_a": ca, "cyl_b": cb,
@@ -259,7 +273,7 @@ def surface_scene(seed: int = 2, every: int = 160, radius: float = 4.0,
     walk -- 83 blobs, 26,560 triangles, about the protein scene's object
     count -- with the protein scene's two lights."""
     pos, _ = random_walk(PROTEIN_SPHERES + 1, PROTEIN_RADIUS, seed)
-    tri = blob_mesh(pos[::every], radius, subdiv)
+    tri = blob_mesh(pos[::every], radius, subdiv, seed=seed)
     ld, lc = _lights(2)
     e3 = _empty3()
     s = Scene(e3, np.zeros(0), _empty3(np.float32), e3.copy(), e3.copy(), np.zeros(0),

@@ -144,9 +144,17 @@ def test_scene_load_rejects_bad_files(tr, tmp_path):
     assert L.tr_scene_load(str(neg).encode(), None, C.byref(h)) == tr.TR_EINVAL
     assert b"bad counts" in L.tr_last_error()
     flags = tmp_path / "flags.bin"
-    flags.write_bytes(b"TRSCENE1" + struct.pack("<qqiid", 0, 0, 0, 2, 0.0))
+    flags.write_bytes(b"TRSCENE1" + struct.pack("<qqiid", 0, 0, 0, 4, 0.0))
     assert L.tr_scene_load(str(flags).encode(), None, C.byref(h)) == tr.TR_EINVAL
     assert b"unknown flags" in L.tr_last_error()
+    # a triangle section announced by flag bit 1 but missing, or too short
+    tri = tmp_path / "tri.bin"
+    tri.write_bytes(b"TRSCENE1" + struct.pack("<qqiid", 0, 0, 0, 2, 0.0))
+    assert L.tr_scene_load(str(tri).encode(), None, C.byref(h)) == tr.TR_EINVAL
+    assert b"its counts need" in L.tr_last_error()
+    tri.write_bytes(b"TRSCENE1" + struct.pack("<qqiidq", 0, 0, 0, 2, 0.0, 3) + b"\0" * 8)
+    assert L.tr_scene_load(str(tri).encode(), None, C.byref(h)) == tr.TR_EINVAL
+    assert b"its counts need" in L.tr_last_error()
     # opacity arrays announced by flag bit 0 but missing
     opq = tmp_path / "opq.bin"
     opq.write_bytes(b"TRSCENE1" + struct.pack("<qqiid", 1, 0, 0, 1, 0.0) + b"\0" * 48)
