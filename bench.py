@@ -204,6 +204,40 @@ def variant_measure(tr, torch, gs, cam, p, prec, workload: str, frames: int = 3)
             "rays_per_frame": rays, "rays_per_s": rays / (ms * 1e-3)}
 
 
+def variants_measure(tr, torch, scenegen, np, gs, scene, cam, params, prec, log):
+    """The shading-variant frames (antialiasing, highlight, transparency) and
+    the triangle surface frame, each at 17.6 MP."""
+    import dataclasses
+    aa = variant_measure(tr, torch, gs, cam, dataclasses.replace(params, aa_samples=4), prec,
+                         "protein-like 26,318 objects, 3860x4548, 4 primary samples per pixel, "
+                         "16 AO samples each, FP32 + FP64 re-solve")
+    aa["aa_samples"] = 4
+    log("antialiased frame", aa)
+    spec = variant_measure(tr, torch, gs, cam,
+                           dataclasses.replace(params, specular=0.3, shininess=30.0), prec,
+                           "protein-like 26,318 objects, 3860x4548, 16 AO samples, Phong "
+                           "highlight k_s 0.3, n 30, FP32 + FP64 re-solve")
+    log("highlight frame", spec)
+    glass = tr.Scene(scenegen.Scene(**{**scene.__dict__, "sph_opacity":
+                                       np.full(scene.n_spheres, 0.5, np.float32)}))
+    trans = variant_measure(tr, torch, glass, cam, dataclasses.replace(params, max_layers=4), prec,
+                            "protein-like 26,318 objects, spheres at opacity 0.5 (cylinders "
+                            "opaque), up to 4 surfaces per pixel, 3860x4548, 16 AO samples per "
+                            "surface, FP32 + FP64 re-solve")
+    del glass
+    log("transparent frame", trans)
+    surf_scene = scenegen.surface_scene()
+    surf = tr.Scene(surf_scene)
+    tris = variant_measure(tr, torch, surf, cam, params, prec,
+                           "molecular-surface stand-in: 83 closed icosphere blobs on the protein "
+                           "walk, 26,560 triangles, 3860x4548, 16 AO samples, FP32 + FP64 "
+                           "re-solve")
+    tris["build_ms"] = scene_ingest_measure(tr, torch, surf_scene, "surface")["build_from_arrays_ms"]
+    del surf
+    log("triangle surface frame", tris)
+    return aa, spec, trans, tris
+
+
 def serving_measure(tr, torch, scenegen, seconds: float, rate: float = 50.0) -> dict:
     """Poisson arrivals (mean `rate` per second) of render jobs over a pool
     of 16 resident walk scenes of 2k-200k objects, resolutions uniform over
@@ -237,6 +271,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson serving run (0 = skip)")
     ap.add_argument("--no-orbit", action="store_true", help="skip the 1M-object orbit run")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the shading-variant and triangle frames (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -335,34 +371,11 @@ def main():
         del f64
         log("fp64 plain path", fp64)
 
-    import dataclasses
-    aa = variant_measure(tr, torch, gs, cam, dataclasses.replace(params, aa_samples=4), prec,
-                         "protein-like 26,318 objects, 3860x4548, 4 primary samples per pixel, "
-                         "16 AO samples each, FP32 + FP64 re-solve")
-    aa["aa_samples"] = 4
-    log("antialiased frame", aa)
-    spec = variant_measure(tr, torch, gs, cam,
-                           dataclasses.replace(params, specular=0.3, shininess=30.0), prec,
-                           "protein-like 26,318 objects, 3860x4548, 16 AO samples, Phong "
-                           "highlight k_s 0.3, n 30, FP32 + FP64 re-solve")
-    log("highlight frame", spec)
-    glass = tr.Scene(scenegen.Scene(**{**scene.__dict__, "sph_opacity":
-                                       np.full(scene.n_spheres, 0.5, np.float32)}))
-    trans = variant_measure(tr, torch, glass, cam, dataclasses.replace(params, max_layers=4), prec,
-                            "protein-like 26,318 objects, spheres at opacity 0.5 (cylinders "
-                            "opaque), up to 4 surfaces per pixel, 3860x4548, 16 AO samples per "
-                            "surface, FP32 + FP64 re-solve")
-    del glass
-    log("transparent frame", trans)
-    surf_scene = scenegen.surface_scene()
-    surf = tr.Scene(surf_scene)
-    tris = variant_measure(tr, torch, surf, cam, params, prec,
-                           "molecular-surface stand-in: 83 closed icosphere blobs on the protein "
-                           "walk, 26,560 triangles, 3860x4548, 16 AO samples, FP32 + FP64 "
-                           "re-solve")
-    tris["build_ms"] = scene_ingest_measure(tr, torch, surf_scene, "surface")["build_from_arrays_ms"]
-    del surf
-    log("triangle surface frame", tris)
+    aa = spec = trans = tris = None
+    if not args.no_variants:
+        aa, spec, trans, tris = variants_measure(tr, torch, scenegen, np, gs, scene, cam, params,
+                                                 prec, log)
+
 
     frame_out = frame_output_measure(tr, torch, frame)
     log("frame output", frame_out)

@@ -34,7 +34,7 @@ __device__ __forceinline__ double boundary_t(const SceneDev &S, int q, int32_t i
 
 // Nearest hit (lexicographic min of (t, id)) or any hit with t in
 // (tmin, tmax], walking the grid cells along the ray (3D-DDA).
-template <bool ANY>
+template <bool ANY, bool TRI>
 __device__ int trace_f64(const SceneDev &S, const double o[3], const double d[3], double tmin,
                          double tmax, int32_t skip, double &bt, int32_t &bk, Cnt &c) {
   c.rays++;
@@ -88,7 +88,7 @@ __device__ int trace_f64(const SceneDev &S, const double o[3], const double d[3]
         c.st++;
         h = hit_sphere_f64(S.sph64[k], o, d, tmin, tmax, t);
         c.sh += h;
-      } else if (k >= S.n_s + S.n_c) {
+      } else if (TRI && k >= S.n_s + S.n_c) {
         const int32_t m = k - S.n_s - S.n_c;
         c.tt++;
         h = hit_triangle_f64(S.triA64[m], S.triB64[m], S.triC64[m], o, d, tmin, tmax, t);
@@ -123,6 +123,7 @@ __device__ int trace_f64(const SceneDev &S, const double o[3], const double d[3]
   }
 }
 
+template <bool TRI>
 __device__ __forceinline__ void normal_f64(const SceneDev &S, int32_t k, const double o[3],
                                            const double d[3], double t, double n[3]) {
   if (k < S.n_s) {
@@ -131,7 +132,7 @@ __device__ __forceinline__ void normal_f64(const SceneDev &S, int32_t k, const d
     n[0] = (P[0] - s.x) / s.w;
     n[1] = (P[1] - s.y) / s.w;
     n[2] = (P[2] - s.z) / s.w;
-  } else if (k >= S.n_s + S.n_c) {
+  } else if (TRI && k >= S.n_s + S.n_c) {
     const int32_t m = k - S.n_s - S.n_c;
     triangle_normal_f64(S.triA64[m], S.triB64[m], S.triC64[m], n);
   } else {
@@ -144,7 +145,9 @@ __device__ __forceinline__ void normal_f64(const SceneDev &S, int32_t k, const d
   }
 }
 
-template <bool STATS>
+// Variants: layered compositing and triangles are compiled in only for jobs
+// that need them (either costs registers, and so occupancy, in the others).
+template <bool STATS, bool LAYERED, bool TRI>
 __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64_t *stats) {
   __shared__ uint32_t red[TR_STAT_COUNT];
   if (STATS) {
@@ -172,17 +175,18 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
     int32_t k0 = -1;
     uint32_t amask = 0;
     uint32_t lmask = 0;
-    for (int32_t layer = 0; layer < J.layers; ++layer) {
+    const int32_t layers = LAYERED ? J.layers : 1;
+    for (int32_t layer = 0; layer < layers; ++layer) {
       double t;
       int32_t k;
-      if (!trace_f64<false>(S, o, d, tmin, INFINITY, pskip, t, k, c)) break;
+      if (!trace_f64<false, TRI>(S, o, d, tmin, INFINITY, pskip, t, k, c)) break;
       if (layer == 0) {
         hit = 1;
         k0 = k;
         n_hit = 1;
       }
       double N[3], P[3];
-      normal_f64(S, k, o, d, t, N);
+      normal_f64<TRI>(S, k, o, d, t, N);
 #pragma unroll
       for (int q = 0; q < 3; ++q) P[q] = o[q] + t * d[q];
       const bool front = dot3d(N, d) < 0.0;
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
         n_sh++;
         double tt;
         int32_t kk;
-        if (trace_f64<true>(S, P, J.ldir[l], kEps, INFINITY, skip, tt, kk, c)) {
+        if (trace_f64<true, TRI>(S, P, J.ldir[l], kEps, INFINITY, skip, tt, kk, c)) {
           lm |= 1u << l;
         } else {
 #pragma unroll
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
           n_ao++;
           double tt;
           int32_t kk;
-          if (trace_f64<true>(S, P, w, kEps, J.ao_maxdist, skip, tt, kk, c)) {
+          if (trace_f64<true, TRI>(S, P, w, kEps, J.ao_maxdist, skip, tt, kk, c)) {
             aocc++;
             if (s < 32) am |= 1u << s;
           }
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
       }
       const float4 alb = S.albedo[k];
       const double albv[3] = {(double)alb.x, (double)alb.y, (double)alb.z};
-      const double alpha = J.layers > 1 ? (double)alb.w : 1.0;
+      const double alpha = LAYERED ? (double)alb.w : 1.0;
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         const double v = albv[ch] * (D[ch] + J.sky * ao) + Hs[ch];
@@ -295,10 +299,16 @@ namespace trh {
 
 hipError_t launch_render_plain_f64(const trd::JobDev &job, uint64_t *stats, hipStream_t st) {
   dim3 grid((unsigned)((job.W + 15) / 16), (unsigned)((job.H + 15) / 16));
-  if (stats)
-    k_render_plain_f64<true><<<grid, 256, 0, st>>>(job, stats);
-  else
-    k_render_plain_f64<false><<<grid, 256, 0, st>>>(job, nullptr);
+  const bool lay = job.layers > 1, tri = job.sc.n_t > 0;
+#define TR_PLAIN(S, L, T) k_render_plain_f64<S, L, T><<<grid, 256, 0, st>>>(job, S ? stats : nullptr)
+  if (stats) {
+    if (lay) { if (tri) TR_PLAIN(true, true, true); else TR_PLAIN(true, true, false); }
+    else { if (tri) TR_PLAIN(true, false, true); else TR_PLAIN(true, false, false); }
+  } else {
+    if (lay) { if (tri) TR_PLAIN(false, true, true); else TR_PLAIN(false, true, false); }
+    else { if (tri) TR_PLAIN(false, false, true); else TR_PLAIN(false, false, false); }
+  }
+#undef TR_PLAIN
   return hipGetLastError();
 }
 
