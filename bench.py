@@ -119,10 +119,15 @@ def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
     st = dict(zip(tr.STAT_NAMES, stats.cpu().tolist()))
     rays = (st["pixels"] + st["ao_rays"]) / launches
     g.destroy()
+    # the sparse scene with and without empty-space skipping: 8 views per batch
+    sub = [tr.alloc_frame(c, ("rgb",), stats=False) for c in cams[:8]]
+    walks = walk_compare(tr, torch, gs, lambda: tr.render_batch_into(
+        [gs] * 8, cams[:8], params[:8], sub), [(24.0, 32), (24.0, 1), (4.0, 32), (4.0, 1)], reps=2)
     return {"workload": "1,000,000-object walk (ball radius 250), 64 views of 1920x1080 per "
                         "graph launch, 32 AO samples, FP32 + FP64 re-solve",
             "ms_per_launch": ms, "views_per_s": 64 * 1000.0 / ms, "rays_per_launch": rays,
-            "rays_per_s": rays / (ms * 1e-3)}
+            "rays_per_s": rays / (ms * 1e-3),
+            "walk_8_views": walks}
 
 
 def scene_ingest_measure(tr, torch, scene, name: str) -> dict:
@@ -202,6 +207,32 @@ def variant_measure(tr, torch, gs, cam, p, prec, workload: str, frames: int = 3)
     rays = (st["pixels"] + st["ao_rays"]) / frames
     return {"workload": workload, "ms_per_frame": ms, "frames_per_s": 1000.0 / ms,
             "rays_per_frame": rays, "rays_per_s": rays / (ms * 1e-3)}
+
+
+def walk_compare(tr, torch, gs, render, configs, reps: int = 3) -> list:
+    """Render time of the same frame(s) under other grid shapes: grid density
+    (cells per primitive) and empty-space skipping cap (1 = the plain
+    uniform-grid walk, no jumps).  The scene is rebuilt for each shape and
+    restored to the defaults (24, 32) afterwards."""
+    import numpy as np
+    out = []
+    for lam, cap in configs:
+        gs.rebuild(lam)
+        gs.set_max_skip(cap)
+        render()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            render()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append({"cells_per_prim": lam, "max_skip": cap,
+                    "grid_cells": int(np.prod(gs.grid_info()[2])),
+                    "ms": e0.elapsed_time(e1) / reps})
+    gs.rebuild(24.0)
+    gs.set_max_skip(32)
+    return out
 
 
 def variants_measure(tr, torch, scenegen, np, gs, scene, cam, params, prec, log):
@@ -371,8 +402,13 @@ def main():
         del f64
         log("fp64 plain path", fp64)
 
-    aa = spec = trans = tris = None
+    aa = spec = trans = tris = walks = None
     if not args.no_variants:
+        wf = tr.alloc_frame(cam, ("rgb",))
+        walks = walk_compare(tr, torch, gs, lambda: tr.render_into(gs, cam, params, wf, prec),
+                             [(24.0, 32), (24.0, 1), (4.0, 32), (4.0, 1)])
+        del wf
+        log("grid shapes", walks)
         aa, spec, trans, tris = variants_measure(tr, torch, scenegen, np, gs, scene, cam, params,
                                                  prec, log)
 
@@ -420,6 +456,7 @@ def main():
         "hit_pixels": st["hit_pixels"], "op_counts": st,
         "render_only_rays_per_s": rays_frame / (render_ms.mean() * 1e-3),
         "fp64_plain": fp64,
+        "walk_shapes": walks,
         "antialias": aa,
         "specular": spec,
         "transparency": trans,

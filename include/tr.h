@@ -94,6 +94,11 @@ typedef struct {
   const double *tri_v2;
   const float *tri_rgb;      /* [n_triangles*3] albedo                      */
   const float *tri_opacity;  /* [n_triangles] opacity in (0, 1], or NULL     */
+  int32_t max_skip;          /* empty-space skipping: the walk jumps over empty
+                                cells using each empty cell's Chebyshev distance
+                                to the nearest occupied cell, stored up to this
+                                cap, 1..32; 0 => 32; 1 => no jumps (a plain
+                                3D-DDA).  Speed only.                          */
 } tr_scene_desc;
 
 /* Pinhole camera, one ray through each pixel centre (more with
@@ -227,6 +232,12 @@ tr_status tr_scene_build(const tr_scene_desc *desc, void *hip_stream, tr_scene *
  * failed rebuild the scene renders nothing (TR_EINVAL) until a rebuild
  * succeeds. */
 tr_status tr_scene_rebuild(tr_scene *scene, double cells_per_prim, void *hip_stream);
+
+/* Set the empty-space skipping cap (tr_scene_desc.max_skip, 0..32) and
+ * rebuild the grid as tr_scene_rebuild does.  Rendered results do not
+ * depend on it; 1 gives the plain uniform-grid walk for comparison.
+ * TR_EINVAL on a NULL scene or a cap outside 0..32. */
+tr_status tr_scene_set_max_skip(tr_scene *scene, int32_t max_skip, void *hip_stream);
 
 /* Device bytes held by the scene (arrays + grid). */
 tr_status tr_scene_footprint(const tr_scene *scene, size_t *bytes);

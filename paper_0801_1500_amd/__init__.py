@@ -43,7 +43,8 @@ class SceneDesc(C.Structure):
         ("n_lights", C.c_int32), ("light_dir", C.c_void_p), ("light_rgb", C.c_void_p),
         ("cells_per_prim", C.c_double), ("sph_opacity", C.c_void_p), ("cyl_opacity", C.c_void_p),
         ("n_triangles", C.c_int64), ("tri_v0", C.c_void_p), ("tri_v1", C.c_void_p),
-        ("tri_v2", C.c_void_p), ("tri_rgb", C.c_void_p), ("tri_opacity", C.c_void_p)]
+        ("tri_v2", C.c_void_p), ("tri_rgb", C.c_void_p), ("tri_opacity", C.c_void_p),
+        ("max_skip", C.c_int32)]
 
 
 class Camera(C.Structure):
@@ -92,6 +93,7 @@ def lib():
     sig = {
         "tr_scene_build": ([C.POINTER(SceneDesc), vp, C.POINTER(vp)], st),
         "tr_scene_rebuild": ([vp, C.c_double, vp], st),
+        "tr_scene_set_max_skip": ([vp, C.c_int32, vp], st),
         "tr_scene_footprint": ([vp, C.POINTER(C.c_size_t)], st),
         "tr_scene_grid_info": ([vp, vp, vp, vp, C.POINTER(i64)], st),
         "tr_scene_grid_arrays": ([vp, vp, vp, vp], st),
@@ -175,7 +177,7 @@ def make_tune(tune) -> Optional[Tune]:
 class Scene:
     """A scene resident on the current GPU (arrays + uniform grid)."""
 
-    def __init__(self, scene, cells_per_prim: float = 0.0, stream=None):
+    def __init__(self, scene, cells_per_prim: float = 0.0, stream=None, max_skip: int = 0):
         f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
         f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
         arrs = [f64(scene.sph_center), f64(scene.sph_radius), f32(scene.sph_rgb),
@@ -195,7 +197,7 @@ class Scene:
         desc = SceneDesc(int(arrs[1].shape[0]), p[0], p[1], p[2], int(arrs[5].shape[0]), p[3],
                          p[4], p[5], p[6], int(arrs[7].reshape(-1, 3).shape[0]), p[7], p[8],
                          float(cells_per_prim), p[9], p[10], n_t, p[11], p[12], p[13], p[14],
-                         p[15])
+                         p[15], int(max_skip))
         h = C.c_void_p()
         _check(lib().tr_scene_build(C.byref(desc), _stream(stream), C.byref(h)))
         self.handle = h
@@ -233,6 +235,10 @@ class Scene:
                 f.seek(at)
                 self.n_triangles = struct.unpack("<q", f.read(8))[0]
         return self
+
+    def set_max_skip(self, max_skip: int, stream=None):
+        """Empty-space skipping cap (1 = plain 3D-DDA); rebuilds the grid."""
+        _check(lib().tr_scene_set_max_skip(self.handle, int(max_skip), _stream(stream)))
 
     def rebuild(self, cells_per_prim: float = 0.0, stream=None):
         _check(lib().tr_scene_rebuild(self.handle, float(cells_per_prim), _stream(stream)))

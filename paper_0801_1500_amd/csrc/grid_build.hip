@@ -319,20 +319,21 @@ __global__ __launch_bounds__(kBlock) void k_sort_cells(const uint32_t *cell_begi
 
 // ---- empty-space distance field for the FP32 traversal
 // dist(c) = Chebyshev distance, in cells, from c to the nearest occupied
-// cell, capped at kDistCap (0 for occupied cells).  Computed as three
+// cell, capped at cap <= kDistCap (0 for occupied cells; cap 1 turns the
+// jumps off: the walk is then a plain 3D-DDA).  Computed as three
 // separable passes g(x) = min_r max(|r|, g(x + r e_axis)): the L-infinity
 // distance is the min over occupied y of max over axes of |x_a - y_a|, and
 // max distributes over min, so the axes can be taken one at a time.
 constexpr int kDistCap = 32;
 
-__global__ void k_dist_init(const uint32_t *cell_begin, int64_t n_cells, uint8_t *d) {
+__global__ void k_dist_init(const uint32_t *cell_begin, int64_t n_cells, uint8_t *d, int32_t cap) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_cells) return;
-  d[c] = cell_begin[c + 1] > cell_begin[c] ? 0 : kDistCap;
+  d[c] = cell_begin[c + 1] > cell_begin[c] ? 0 : (uint8_t)cap;
 }
 
 __global__ void k_dist_pass(const uint8_t *in, uint8_t *out, int32_t rx, int32_t ry, int32_t rz,
-                            int axis) {
+                            int axis, int32_t cap) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)rx * ry * rz;
   if (c >= n) return;
@@ -344,8 +345,8 @@ __global__ void k_dist_pass(const uint8_t *in, uint8_t *out, int32_t rx, int32_t
   const int64_t stride = axis == 0 ? 1 : (axis == 1 ? (int64_t)rx : (int64_t)rx * ry);
   int32_t best = in[c];
   for (int32_t r = 1; r < best; ++r) {  // a neighbour r away can only give >= r
-    const int32_t a = p - r >= 0 ? (int32_t)in[c - r * stride] : kDistCap;
-    const int32_t b = p + r < len ? (int32_t)in[c + r * stride] : kDistCap;
+    const int32_t a = p - r >= 0 ? (int32_t)in[c - r * stride] : cap;
+    const int32_t b = p + r < len ? (int32_t)in[c + r * stride] : cap;
     const int32_t v = max(r, min(a, b));
     best = min(best, v);
   }
@@ -533,15 +534,17 @@ hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32
 }
 
 hipError_t launch_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, const int32_t res[3],
-                           uint8_t *d0, uint8_t *d1, uint32_t *wsz, uint32_t *scan_scratch,
-                           uint32_t *wrefs, trd::CellInfo *info, hipStream_t st) {
+                           int32_t cap, uint8_t *d0, uint8_t *d1, uint32_t *wsz,
+                           uint32_t *scan_scratch, uint32_t *wrefs, trd::CellInfo *info,
+                           hipStream_t st) {
   const int64_t n = (int64_t)res[0] * res[1] * res[2];
   if (n <= 0) return hipSuccess;
   const unsigned nb = blocks_for(n);
-  k_dist_init<<<nb, kBlock, 0, st>>>(cell_begin, n, d0);
-  k_dist_pass<<<nb, kBlock, 0, st>>>(d0, d1, res[0], res[1], res[2], 0);
-  k_dist_pass<<<nb, kBlock, 0, st>>>(d1, d0, res[0], res[1], res[2], 1);
-  k_dist_pass<<<nb, kBlock, 0, st>>>(d0, d1, res[0], res[1], res[2], 2);
+  if (cap < 1 || cap > kDistCap) cap = kDistCap;
+  k_dist_init<<<nb, kBlock, 0, st>>>(cell_begin, n, d0, cap);
+  k_dist_pass<<<nb, kBlock, 0, st>>>(d0, d1, res[0], res[1], res[2], 0, cap);
+  k_dist_pass<<<nb, kBlock, 0, st>>>(d1, d0, res[0], res[1], res[2], 1, cap);
+  k_dist_pass<<<nb, kBlock, 0, st>>>(d0, d1, res[0], res[1], res[2], 2, cap);
   k_walk_sizes<<<blocks_for(n + 1), kBlock, 0, st>>>(cell_begin, n, wsz);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

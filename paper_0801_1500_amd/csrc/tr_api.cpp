@@ -58,6 +58,7 @@ struct tr_scene {
   double ldir_in[8][3] = {};  // light directions as given (saved by tr_scene_save)
   double lrgb[8][3] = {};
   double lambda = 24.0;
+  int32_t max_skip = 32;  // cap of the empty-space distance field (1 = plain 3D-DDA)
   // device arrays
   double4 *sph64 = nullptr, *cylA64 = nullptr, *cylW64 = nullptr, *cylB64 = nullptr;
   float4 *sph32 = nullptr, *cylA32 = nullptr, *cylW32 = nullptr, *albedo = nullptr;
@@ -267,8 +268,8 @@ static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
   HIP_TRY(trh::launch_fill_u32(s->count, nc, 0u, st));
   HIP_TRY(trh::launch_scatter(a, s->cell_begin, s->count, s->refs, st));
   HIP_TRY(trh::launch_sort_cells(s->cell_begin, nc, s->refs, st));
-  HIP_TRY(trh::launch_cellinfo(s->cell_begin, s->refs, s->gp.res, s->dist0, s->dist1, s->count,
-                               s->scan_scratch, s->wrefs, s->cellinfo, st));
+  HIP_TRY(trh::launch_cellinfo(s->cell_begin, s->refs, s->gp.res, s->max_skip, s->dist0, s->dist1,
+                               s->count, s->scan_scratch, s->wrefs, s->cellinfo, st));
   fill_scene_dev(s);
   return TR_OK;
 }
@@ -291,6 +292,7 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   if (d->n_lights < 0 || d->n_lights > 8) return fail(TR_EINVAL, "n_lights must be 0..8");
   if (!(d->cells_per_prim >= 0.0) || !std::isfinite(d->cells_per_prim))
     return fail(TR_EINVAL, "cells_per_prim must be finite and >= 0");
+  if (d->max_skip < 0 || d->max_skip > 32) return fail(TR_EINVAL, "max_skip must be 0..32");
   if (d->n_spheres > 0 && (!d->sph_center || !d->sph_radius || !d->sph_rgb))
     return fail(TR_EINVAL, "NULL sphere array");
   if (d->n_cylinders > 0 && (!d->cyl_a || !d->cyl_b || !d->cyl_radius || !d->cyl_rgb))
@@ -342,6 +344,7 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   s->n_lights = d->n_lights;
   s->has_trans = has_trans;
   s->lambda = d->cells_per_prim > 0.0 ? d->cells_per_prim : 24.0;
+  s->max_skip = d->max_skip > 0 ? d->max_skip : 32;
   for (int l = 0; l < d->n_lights; ++l) {
     const double *v = d->light_dir + 3 * l;
     for (int a = 0; a < 3; ++a) s->ldir_in[l][a] = v[a];
@@ -484,6 +487,13 @@ extern "C" tr_status tr_scene_rebuild(tr_scene *s, double cells_per_prim, void *
   if (!(cells_per_prim >= 0.0) || !std::isfinite(cells_per_prim))
     return fail(TR_EINVAL, "cells_per_prim must be finite and >= 0");
   if (cells_per_prim > 0.0) s->lambda = cells_per_prim;
+  return build_grid(s, (hipStream_t)hip_stream);
+}
+
+extern "C" tr_status tr_scene_set_max_skip(tr_scene *s, int32_t max_skip, void *hip_stream) {
+  if (!s) return fail(TR_EINVAL, "tr_scene_set_max_skip: NULL scene");
+  if (max_skip < 0 || max_skip > 32) return fail(TR_EINVAL, "max_skip must be 0..32");
+  s->max_skip = max_skip > 0 ? max_skip : 32;
   return build_grid(s, (hipStream_t)hip_stream);
 }
 

@@ -53,9 +53,11 @@ hipError_t launch_scatter(const BuildArgs &a, const uint32_t *cell_begin, uint32
 // empty-space distance field + per-cell traversal words (d0, d1: n_cells bytes each)
 // Empty-space distances, walk lists (wsz: n_cells + 1 scratch words, scanned
 // in place with scan_scratch) and the per-cell traversal records.
+// cap: largest stored distance, 1..32 (1 = no jumps); anything else = 32
 hipError_t launch_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, const int32_t res[3],
-                           uint8_t *d0, uint8_t *d1, uint32_t *wsz, uint32_t *scan_scratch,
-                           uint32_t *wrefs, trd::CellInfo *info, hipStream_t st);
+                           int32_t cap, uint8_t *d0, uint8_t *d1, uint32_t *wsz,
+                           uint32_t *scan_scratch, uint32_t *wrefs, trd::CellInfo *info,
+                           hipStream_t st);
 hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32_t *refs,
                              hipStream_t st);
 
