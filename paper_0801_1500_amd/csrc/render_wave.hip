@@ -292,8 +292,9 @@ __device__ __forceinline__ int32_t find_job(const TR_CONST JobDev *jobs, int32_t
 
 template <int BANKS, bool RESOLVE, bool COUNT, bool TRANS, bool TRI>
 // Occupancy targets: 5 waves per SIMD for the plain two-bank kernel (96
-// VGPRs); compositing adds LDS state that allows fewer waves anyway.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : (BANKS == 2 && !COUNT ? 5 : 4)))) void k_render_wave(const WaveArgs A) {
+// VGPRs); compositing adds LDS state that allows fewer waves anyway, and the
+// triangle test needs more registers than 96 without spilling.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : (BANKS == 2 && !COUNT && !TRI ? 5 : 4)))) void k_render_wave(const WaveArgs A) {
   __shared__ Lds<BANKS, TRANS> L;
   constexpr int NS = BANKS * 64;
   constexpr int kMinIters = 2;
