@@ -133,6 +133,12 @@ class Server:
                    if k in self.outputs) or 1
 
     def prepare(self, job: Job):
+        if int(getattr(job.params, "aa_samples", 1)) > 1:
+            # tile ranges carry one sample per pixel; an antialiased frame is
+            # the ordered mean of its sample frames, rendered whole
+            raise ValueError("job %d: the server renders tile ranges, which take one primary "
+                             "sample per pixel; render antialiased frames with tr.render"
+                             % job.job_id)
         job.n_tiles = tr.tile_count(job.camera.width, job.camera.height, SERVE_TILE_W)
         job.footprint = tr.frame_footprint(job.camera, job.params, self._flags())
         job.next_tile = 0

@@ -79,3 +79,13 @@ def test_realtime_stream(tr, pool):
     assert all(j.done >= j.arrival for j in jobs)
     assert s["latency_ms_p50"] <= s["latency_ms_p99"] < 5000
     assert st.rays > 0
+
+
+def test_rejects_antialiased_jobs(tr, pool):
+    from paper_0801_1500_amd.serve import Job, Server
+    scenes, gscenes = pool
+    job = _jobs(scenes, 1, 5)[0]
+    job = Job(job.job_id, 0.0, job.scene, job.camera,
+              scenegen.Params(**{**job.params.__dict__, "aa_samples": 2}))
+    with pytest.raises(ValueError, match="one primary sample"):
+        Server(gscenes).run([job], realtime=False)

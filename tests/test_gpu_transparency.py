@@ -177,3 +177,17 @@ def test_errors(tr):
         with pytest.raises(tr.TRError) as e:
             tr.render(gs, c, scenegen.Params(ao_samples=4, max_layers=L), outputs=("rgb",))
         assert e.value.status == -1, L
+
+
+def test_graphs_render_opaque_only(tr):
+    st, c, p = _tiny_glass()
+    gst = tr.Scene(st)
+    fr = tr.alloc_frame(c, ("rgb",), False)
+    with pytest.raises(tr.TRError) as e:
+        tr.Graph([gst], [c], [scenegen.Params(**{**p.__dict__, "max_layers": 4})], [fr])
+    assert e.value.status == -4
+    g = tr.Graph([gst], [c], [p], [fr])  # opaque rendering of the same scene is fine
+    with pytest.raises(tr.TRError) as e:
+        g.update(params=[scenegen.Params(**{**p.__dict__, "max_layers": 4})])
+    assert e.value.status == -4
+    g.destroy()
