@@ -197,6 +197,7 @@ enum {
   TR_STAT_CYCLES_TOTAL,      /* wavefront kernel: shader clocks from wave start to end (summed) */
   TR_STAT_TRI_TESTS,
   TR_STAT_TRI_HITS,
+  TR_STAT_STACK_OVERFLOWS,   /* BVH walk: children dropped on a full stack (0 unless the tree is too deep) */
   TR_STAT_COUNT
 };
 
@@ -211,6 +212,10 @@ typedef struct {
   int32_t cyl_wait;          /* cylinder tests run when at least busy/cyl_wait lanes need one, 1..64 */
   int32_t mix;               /* a work type (step, sphere test, cylinder test) runs in an iteration
                                 when its lanes are >= mix/64 of the largest type's, 1..64 */
+  int32_t accel;             /* 0 = walk the uniform grid; 1 = walk the scene's
+                                BVH (tr_scene_build_bvh first; FP32 precisions,
+                                opaque rendering, two banks).  Results do not
+                                depend on it. */
 } tr_tune;
 
 /* ---------------------------------------------------------------- scenes */
@@ -238,6 +243,23 @@ tr_status tr_scene_rebuild(tr_scene *scene, double cells_per_prim, void *hip_str
  * depend on it; 1 gives the plain uniform-grid walk for comparison.
  * TR_EINVAL on a NULL scene or a cap outside 0..32. */
 tr_status tr_scene_set_max_skip(tr_scene *scene, int32_t max_skip, void *hip_stream);
+
+/* Build (or rebuild) a linear BVH over the scene's primitives for the BVH
+ * walk (tr_tune.accel = 1), the alternative to the uniform grid: primitives
+ * ordered by the 30-bit Morton code of their box centres over the grid box,
+ * the hierarchy of Karras (HPG 2012), node boxes bottom-up (widened by the
+ * grid's insertion margin, rounded outwards to FP32).  Synchronises the
+ * stream.  TR_EINVAL on a NULL scene or an invalid grid; TR_EUNSUPPORTED from
+ * 2^26 primitives on. */
+tr_status tr_scene_build_bvh(tr_scene *scene, void *hip_stream);
+
+/* Copy the BVH's records to a HOST buffer (may be NULL) of 16 floats per
+ * internal node: left child box (lo xyz, hi xyz), right child box, then the
+ * two children as int32 bit patterns (node index >= 0, or -(primitive id) - 1
+ * for a leaf) and two zero words.  Boxes are in the FP32 frame (relative to
+ * the grid box centre).  *n_nodes = primitives - 1 (0 below two). */
+tr_status tr_scene_bvh_nodes(const tr_scene *scene, float *nodes, int64_t *n_nodes,
+                             void *hip_stream);
 
 /* Device bytes held by the scene (arrays + grid). */
 tr_status tr_scene_footprint(const tr_scene *scene, size_t *bytes);

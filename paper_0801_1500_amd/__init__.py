@@ -24,7 +24,7 @@ PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "fp32_resolve": PREC_FP32_RE
 STAT_NAMES = ["pixels", "hit_pixels", "ao_rays", "shadow_rays", "rays_traced", "cells",
               "sph_tests", "sph_hits", "cyl_tests", "cyl_hits", "resolves", "wave_iters",
               "lane_iters", "refills", "jumps", "cycles_traverse", "cycles_total", "tri_tests",
-              "tri_hits"]
+              "tri_hits", "stack_overflows"]
 STAT_COUNT = len(STAT_NAMES)
 
 
@@ -68,7 +68,7 @@ class Frame(C.Structure):
 class Tune(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("banks", C.c_int32), ("waves_per_cu", C.c_int32),
                 ("refill_below", C.c_int32), ("count_ops", C.c_int32), ("cyl_wait", C.c_int32),
-                ("mix", C.c_int32)]
+                ("mix", C.c_int32), ("accel", C.c_int32)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -94,6 +94,8 @@ def lib():
         "tr_scene_build": ([C.POINTER(SceneDesc), vp, C.POINTER(vp)], st),
         "tr_scene_rebuild": ([vp, C.c_double, vp], st),
         "tr_scene_set_max_skip": ([vp, C.c_int32, vp], st),
+        "tr_scene_build_bvh": ([vp, vp], st),
+        "tr_scene_bvh_nodes": ([vp, vp, C.POINTER(i64), vp], st),
         "tr_scene_footprint": ([vp, C.POINTER(C.c_size_t)], st),
         "tr_scene_grid_info": ([vp, vp, vp, vp, C.POINTER(i64)], st),
         "tr_scene_grid_arrays": ([vp, vp, vp, vp], st),
@@ -171,7 +173,7 @@ def make_tune(tune) -> Optional[Tune]:
     return Tune(int(tune.get("tile_w", 0)), int(tune.get("banks", 0)),
                 int(tune.get("waves_per_cu", 0)), int(tune.get("refill_below", 0)),
                 int(tune.get("count_ops", 0)), int(tune.get("cyl_wait", 0)),
-                int(tune.get("mix", 0)))
+                int(tune.get("mix", 0)), int(tune.get("accel", 0)))
 
 
 class Scene:
@@ -235,6 +237,20 @@ class Scene:
                 f.seek(at)
                 self.n_triangles = struct.unpack("<q", f.read(8))[0]
         return self
+
+    def build_bvh(self, stream=None):
+        """Linear BVH for the BVH walk (tune accel=1)."""
+        _check(lib().tr_scene_build_bvh(self.handle, _stream(stream)))
+
+    def bvh_nodes(self, stream=None):
+        """BVH records: float32 [n_nodes, 16] (see tr_scene_bvh_nodes)."""
+        n = C.c_int64(0)
+        _check(lib().tr_scene_bvh_nodes(self.handle, None, C.byref(n), _stream(stream)))
+        out = np.zeros((max(n.value, 0), 16), dtype=np.float32)
+        if n.value > 0:
+            _check(lib().tr_scene_bvh_nodes(self.handle, out.ctypes.data, C.byref(n),
+                                            _stream(stream)))
+        return out
 
     def set_max_skip(self, max_skip: int, stream=None):
         """Empty-space skipping cap (1 = plain 3D-DDA); rebuilds the grid."""

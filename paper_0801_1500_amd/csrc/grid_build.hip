@@ -440,6 +440,175 @@ inline unsigned blocks_for(int64_t n, int b = kBlock) {
   return (unsigned)((n + b - 1) / b);
 }
 
+// ---- linear BVH (Karras, "Maximizing parallelism in the construction of
+// BVHs, octrees, and k-d trees", HPG 2012).  Primitives are ordered by the
+// 30-bit Morton code of their box centres (10 bits per axis over the grid
+// box); the N - 1 internal nodes then follow from the sorted codes alone:
+// node i covers the run of leaves that share the longest common prefix with
+// leaf i, split where that prefix grows.  Equal codes are told apart by
+// their position in the sorted order.
+
+__device__ __forceinline__ uint32_t morton30(uint32_t x, uint32_t y, uint32_t z) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int b = 0; b < 10; ++b)
+    m |= (((x >> b) & 1u) << (3 * b + 2)) | (((y >> b) & 1u) << (3 * b + 1)) | (((z >> b) & 1u) << (3 * b));
+  return m;
+}
+
+__global__ void k_bvh_morton(const trh::BuildArgs a, int64_t n, double lx, double ly, double lz,
+                             double sx, double sy, double sz, uint32_t *keys, uint32_t *vals) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double lo[3], hi[3];
+  prim_box(a, k, lo, hi);
+  const double c[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
+  const double l[3] = {lx, ly, lz}, sc[3] = {sx, sy, sz};
+  uint32_t q[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double f = floor((c[i] - l[i]) * sc[i]);
+    f = f < 0.0 ? 0.0 : (f > 1023.0 ? 1023.0 : f);
+    q[i] = (uint32_t)f;
+  }
+  keys[k] = morton30(q[0], q[1], q[2]);
+  vals[k] = (uint32_t)k;
+}
+
+// One pass of a stable LSD radix sort on one bit: zeros keep their order in
+// front, ones keep theirs behind.  zpos = exclusive scan of the zero flags.
+__global__ void k_bvh_zero_flags(const uint32_t *keys, int64_t n, int bit, uint32_t *flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = ((keys[i] >> bit) & 1u) ? 0u : 1u;
+  else if (i == n) flags[i] = 0u;
+}
+
+__global__ void k_bvh_split(const uint32_t *keys, const uint32_t *vals, int64_t n, int bit,
+                            const uint32_t *zpos, uint32_t *keys2, uint32_t *vals2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t z = zpos[i];
+  const uint32_t dst = ((keys[i] >> bit) & 1u) ? zpos[n] + (uint32_t)i - z : z;
+  keys2[dst] = keys[i];
+  vals2[dst] = vals[i];
+}
+
+// Child encoding: c >= 0 internal node c; c < 0 leaf at sorted position -c - 1.
+__device__ __forceinline__ int prefix_len(const uint32_t *keys, int64_t n, int64_t i, int64_t j) {
+  if (j < 0 || j >= n) return -1;
+  const uint32_t a = keys[i], b = keys[j];
+  if (a == b) return 32 + __clz((uint32_t)(i ^ j));
+  return __clz(a ^ b);
+}
+
+__global__ void k_bvh_internal(const uint32_t *keys, int64_t n, int32_t *left, int32_t *right,
+                               int32_t *parent_i, int32_t *parent_l) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const int64_t d = prefix_len(keys, n, i, i + 1) - prefix_len(keys, n, i, i - 1) >= 0 ? 1 : -1;
+  const int dmin = prefix_len(keys, n, i, i - d);
+  int64_t lmax = 2;
+  while (lmax < 2 * n && prefix_len(keys, n, i, i + lmax * d) > dmin) lmax *= 2;
+  int64_t l = 0;
+  for (int64_t t = lmax / 2; t >= 1; t /= 2)
+    if (prefix_len(keys, n, i, i + (l + t) * d) > dmin) l += t;
+  const int64_t j = i + l * d;
+  const int dnode = prefix_len(keys, n, i, j);
+  int64_t s = 0, t = 0, div = 2;
+  do {
+    t = (l + div - 1) / div;
+    if (prefix_len(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    div *= 2;
+  } while (t > 1);
+  const int64_t g = i + s * d + (d < 0 ? -1 : 0);
+  const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+  const int32_t lc = lo == g ? (int32_t)(-g - 1) : (int32_t)g;
+  const int32_t rc = hi == g + 1 ? (int32_t)(-(g + 1) - 1) : (int32_t)(g + 1);
+  left[i] = lc;
+  right[i] = rc;
+  if (lc >= 0) parent_i[lc] = (int32_t)i; else parent_l[-lc - 1] = (int32_t)i;
+  if (rc >= 0) parent_i[rc] = (int32_t)i; else parent_l[-rc - 1] = (int32_t)i;
+  if (i == 0) parent_i[0] = -1;
+}
+
+// Box of a child: a leaf's primitive box widened by margin, or the stored
+// box of an internal node (read past the L1 cache: another thread wrote it).
+__device__ __forceinline__ void child_box(const trh::BuildArgs &a, const uint32_t *vals,
+                                          const double *ibox, int32_t c, double margin,
+                                          double lo[3], double hi[3]) {
+  if (c < 0) {
+    prim_box(a, (int64_t)vals[-c - 1], lo, hi);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      lo[q] -= margin;
+      hi[q] += margin;
+    }
+  } else {
+    const volatile double *b = ibox + 6 * (int64_t)c;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      lo[q] = b[q];
+      hi[q] = b[3 + q];
+    }
+  }
+}
+
+// Boxes bottom-up: each leaf climbs towards the root; at every node the
+// first of the two arriving threads stops and the second, which then knows
+// both children's boxes, stores their union and climbs on.
+__global__ void k_bvh_bounds(const trh::BuildArgs a, const uint32_t *vals, int64_t n,
+                             const int32_t *left, const int32_t *right, const int32_t *parent_i,
+                             const int32_t *parent_l, uint32_t *arrivals, double *ibox,
+                             double margin) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  int32_t p = parent_l[q];
+  for (int64_t guard = 0; p >= 0 && guard < n; ++guard) {
+    __threadfence();
+    if (atomicAdd(&arrivals[p], 1u) == 0u) return;
+    __threadfence();
+    double l0[3], h0[3], l1[3], h1[3];
+    child_box(a, vals, ibox, left[p], margin, l0, h0);
+    child_box(a, vals, ibox, right[p], margin, l1, h1);
+    volatile double *b = ibox + 6 * (int64_t)p;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      b[k] = l0[k] < l1[k] ? l0[k] : l1[k];
+      b[3 + k] = h0[k] > h1[k] ? h0[k] : h1[k];
+    }
+    p = parent_i[p];
+  }
+}
+
+// Traversal records, one per internal node (64 bytes): both children's
+// boxes in the FP32 frame, rounded outwards, then the children (an internal
+// node index, or -(primitive id) - 1 for a leaf).
+__global__ void k_bvh_pack(const trh::BuildArgs a, const uint32_t *vals, int64_t n,
+                           const int32_t *left, const int32_t *right, const double *ibox,
+                           double margin, double ox, double oy, double oz, float4 *nodes) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const double o[3] = {ox, oy, oz};
+  float f[12];
+  int32_t ch[2] = {left[i], right[i]};
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    double lo[3], hi[3];
+    child_box(a, vals, ibox, ch[c], margin, lo, hi);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      f[6 * c + q] = __double2float_rd(lo[q] - o[q]);
+      f[6 * c + 3 + q] = __double2float_ru(hi[q] - o[q]);
+    }
+    if (ch[c] < 0) ch[c] = -(int32_t)vals[-ch[c] - 1] - 1;
+  }
+  float4 *r = nodes + 4 * i;
+  r[0] = make_float4(f[0], f[1], f[2], f[3]);
+  r[1] = make_float4(f[4], f[5], f[6], f[7]);
+  r[2] = make_float4(f[8], f[9], f[10], f[11]);
+  r[3] = make_float4(__int_as_float(ch[0]), __int_as_float(ch[1]), 0.0f, 0.0f);
+}
+
 }  // namespace
 
 namespace trh {
@@ -523,6 +692,37 @@ hipError_t launch_scatter(const BuildArgs &a, const uint32_t *cell_begin, uint32
   const int64_t N = (int64_t)a.n_s + a.n_c + a.n_t;
   if (N == 0) return hipSuccess;
   k_scatter<<<blocks_for(N * kLanes), kBlock, 0, st>>>(a, cell_begin, cursor, refs);
+  return hipGetLastError();
+}
+
+hipError_t launch_bvh(const BuildArgs &a, const double lo[3], const double hi[3], double margin,
+                      const double origin[3], BvhScratch &w, float4 *nodes, hipStream_t st) {
+  const int64_t n = (int64_t)a.n_s + a.n_c + a.n_t;
+  if (n < 2) return hipSuccess;
+  const unsigned nb = blocks_for(n), nb1 = blocks_for(n + 1);
+  double sc[3];
+  for (int q = 0; q < 3; ++q) sc[q] = hi[q] > lo[q] ? 1024.0 / (hi[q] - lo[q]) : 0.0;
+  k_bvh_morton<<<nb, kBlock, 0, st>>>(a, n, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], w.keys, w.vals);
+  uint32_t *k0 = w.keys, *v0 = w.vals, *k1 = w.keys2, *v1 = w.vals2;
+  for (int bit = 0; bit < 30; ++bit) {
+    k_bvh_zero_flags<<<nb1, kBlock, 0, st>>>(k0, n, bit, w.flags);
+    hipError_t e = launch_scan(w.flags, n + 1, w.scan_scratch, st);
+    if (e != hipSuccess) return e;
+    k_bvh_split<<<nb, kBlock, 0, st>>>(k0, v0, n, bit, w.flags, k1, v1);
+    uint32_t *tk = k0, *tv = v0;
+    k0 = k1;
+    v0 = v1;
+    k1 = tk;
+    v1 = tv;
+  }
+  // 30 passes: the sorted arrays are back in keys / vals
+  k_bvh_internal<<<blocks_for(n - 1), kBlock, 0, st>>>(k0, n, w.left, w.right, w.parent_i, w.parent_l);
+  hipError_t e = launch_fill_u32(w.arrivals, n - 1, 0u, st);
+  if (e != hipSuccess) return e;
+  k_bvh_bounds<<<nb, kBlock, 0, st>>>(a, v0, n, w.left, w.right, w.parent_i, w.parent_l, w.arrivals,
+                                      w.ibox, margin);
+  k_bvh_pack<<<blocks_for(n - 1), kBlock, 0, st>>>(a, v0, n, w.left, w.right, w.ibox, margin,
+                                                   origin[0], origin[1], origin[2], nodes);
   return hipGetLastError();
 }
 

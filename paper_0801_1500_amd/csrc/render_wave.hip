@@ -81,7 +81,9 @@ __device__ __forceinline__ void bank_pixel(const BankInfo &B, int32_t q, int32_t
   y = B.y0 + qy;
 }
 
-template <int BANKS, bool TRANS>
+constexpr int kStack = 48;  // BVH traversal stack entries per lane
+
+template <int BANKS, bool TRANS, bool BVH>
 struct Lds {
   static constexpr int NS = BANKS * 64;
   static constexpr int NT = TRANS ? NS : 1;  // transparency state only when compositing
@@ -97,12 +99,14 @@ struct Lds {
   uint32_t lmask[NS];
   uint8_t fifo[NS];
   BankInfo bank[BANKS];
-  uint32_t cnt[13];
+  uint32_t cnt[14];
   // compositing across surfaces: colour so far, transmittance in front of the
   // current surface, its index, and whether the FIFO entry is a continuation
   float acc_r[NT], acc_g[NT], acc_b[NT], trn[NT];
   uint8_t layer[NT];
   uint8_t cont[NT];
+  // BVH walk: per lane a stack of node / leaf items, entry e at e * 64 + lane
+  int32_t stk[BVH ? 64 * kStack : 1];
 };
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
@@ -182,6 +186,8 @@ struct SceneHot {
   const TR_GLOBAL trd::CellInfo *cellinfo;
   const TR_GLOBAL vf4 *sph32, *cylA32, *cylW32, *albedo;
   const TR_GLOBAL vf4 *triV32, *triE1_32, *triE2_32;
+  const TR_GLOBAL vf4 *bvh;  // 4 records per internal node
+  int32_t bvh_n;             // primitives in the BVH
   int32_t n_s;
   int32_t n_sc;  // first triangle id (spheres + cylinders)
   int32_t res[3];
@@ -204,6 +210,8 @@ __device__ __forceinline__ SceneHot load_hot(const JobDev *Jg) {
   H.triV32 = (const TR_GLOBAL vf4 *)J->sc.triV32;
   H.triE1_32 = (const TR_GLOBAL vf4 *)J->sc.triE1_32;
   H.triE2_32 = (const TR_GLOBAL vf4 *)J->sc.triE2_32;
+  H.bvh = (const TR_GLOBAL vf4 *)J->sc.bvh;
+  H.bvh_n = J->sc.bvh_n;
   H.n_s = J->sc.n_s;
   H.n_sc = J->sc.n_s + J->sc.n_c;
 #pragma unroll
@@ -271,6 +279,21 @@ __device__ __forceinline__ bool ray_setup(Ray &R, const SceneHot &S) {
   return true;
 }
 
+// BVH walk state in the ray's grid fields: hx/hy/hz = 1/d, cx = stack depth,
+// rc = node to visit (-1 none), nk = primitive to test (-1 none); t1 = tmax.
+__device__ __forceinline__ bool bvh_setup(Ray &R, const SceneHot &S) {
+  R.hx = rcpf(R.dx);
+  R.hy = rcpf(R.dy);
+  R.hz = rcpf(R.dz);
+  R.t1 = R.tmax;
+  R.bt = INFINITY;
+  R.bk = -1;
+  R.cx = 0;
+  R.rc = S.bvh_n >= 2 ? 0 : -1;
+  R.nk = S.bvh_n == 1 ? 0 : -1;
+  return S.bvh_n > 0;
+}
+
 struct WaveArgs {
   const JobDev *jobs;
   int32_t n_jobs;
@@ -290,18 +313,19 @@ __device__ __forceinline__ int32_t find_job(const TR_CONST JobDev *jobs, int32_t
   return lo;
 }
 
-template <int BANKS, bool RESOLVE, bool COUNT, bool TRANS, bool TRI>
+template <int BANKS, bool RESOLVE, bool COUNT, bool TRANS, bool TRI, bool BVH>
 // Occupancy targets: 5 waves per SIMD for the plain two-bank kernel (96
 // VGPRs); compositing adds LDS state that allows fewer waves anyway, and the
-// triangle test needs more registers than 96 without spilling.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : (BANKS == 2 && !COUNT && !TRI ? 5 : 4)))) void k_render_wave(const WaveArgs A) {
-  __shared__ Lds<BANKS, TRANS> L;
+// triangle test needs more registers than 96 without spilling; the BVH
+// walk's per-lane stacks (12 KB of LDS per wave) leave room for 2.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (TRANS ? 3 : (BANKS == 2 && !COUNT && !TRI ? 5 : 4))))) void k_render_wave(const WaveArgs A) {
+  __shared__ Lds<BANKS, TRANS, BVH> L;
   constexpr int NS = BANKS * 64;
   constexpr int kMinIters = 2;
   const int32_t lane = threadIdx.x;
   const int32_t TW = A.tile_w;
   const int32_t TH = 64 / TW;
-  if (lane < 13) L.cnt[lane] = 0;
+  if (lane < 14) L.cnt[lane] = 0;
 
   // ---- wave-uniform control state
   int32_t q_head = 0, q_tail = 0, head_issued = 0;
@@ -317,7 +341,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
   // ---- counters (wave-uniform)
   uint64_t c_rays = 0;
   uint32_t l_cells = 0, l_st = 0, l_sh = 0, l_ct = 0, l_ch = 0, l_res = 0, l_jumps = 0;  // per lane
-  uint32_t l_tt = 0, l_th = 0;
+  uint32_t l_tt = 0, l_th = 0, l_ovf = 0;
   uint64_t c_iters = 0, c_lanes = 0, c_refills = 0;
   uint64_t c_cyc_trav = 0;
   const uint64_t c_cyc_start = COUNT ? clock64() : 0;
@@ -795,7 +819,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
               R.tmax = INFINITY;
             }
           }
-          setup_ok = ray_setup(R, H);
+          setup_ok = BVH ? bvh_setup(R, H) : ray_setup(R, H);
           st = setup_ok ? kRun : kDone;
         }
       }
@@ -872,7 +896,53 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
         vf4 sdat;  // (read only where is_sph)
         if (is_sph) sdat = ldg(H.sph32, (uint32_t)nk);
         bool enter = false;  // the step moved into a cell inside the grid
-        if (is_step) {
+        if (BVH && is_step) {
+          // ---- BVH node: test both children's boxes against (tmin, min(t1,
+          // best t)); go to the nearer hit child, stack the other; with no
+          // child hit take the next stacked item, or stop.  Items are node
+          // indices, or -(primitive id) - 1 for a leaf.  Every index is
+          // checked before use, and a full stack drops the child (counted).
+          const bool valid = (uint32_t)R.rc < (uint32_t)(H.bvh_n - 1);
+          const uint32_t nb = valid ? 4u * (uint32_t)R.rc : 0u;
+          const vf4 n0 = ldg(H.bvh, nb), n1 = ldg(H.bvh, nb + 1u), n2 = ldg(H.bvh, nb + 2u),
+                    n3 = ldg(H.bvh, nb + 3u);
+          const float tc = vminf(R.t1, R.bt);
+          const float la0 = (n0.x - R.ox) * R.hx, lb0 = (n0.w - R.ox) * R.hx;
+          const float la1 = (n0.y - R.oy) * R.hy, lb1 = (n1.x - R.oy) * R.hy;
+          const float la2 = (n0.z - R.oz) * R.hz, lb2 = (n1.y - R.oz) * R.hz;
+          const float ra0 = (n1.z - R.ox) * R.hx, rb0 = (n2.y - R.ox) * R.hx;
+          const float ra1 = (n1.w - R.oy) * R.hy, rb1 = (n2.z - R.oy) * R.hy;
+          const float ra2 = (n2.x - R.oz) * R.hz, rb2 = (n2.w - R.oz) * R.hz;
+          const float tnL = fmaxf(fmaxf(fminf(la0, lb0), fminf(la1, lb1)), fmaxf(fminf(la2, lb2), R.tmin));
+          const float tfL = fminf(fminf(fmaxf(la0, lb0), fmaxf(la1, lb1)), fminf(fmaxf(la2, lb2), tc));
+          const float tnR = fmaxf(fmaxf(fminf(ra0, rb0), fminf(ra1, rb1)), fmaxf(fminf(ra2, rb2), R.tmin));
+          const float tfR = fminf(fminf(fmaxf(ra0, rb0), fmaxf(ra1, rb1)), fminf(fmaxf(ra2, rb2), tc));
+          const bool hitL = valid && tnL <= tfL, hitR = valid && tnR <= tfR;
+          const int32_t cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
+          const bool lfirst = !hitR || (hitL && tnL <= tnR);
+          int32_t sp = R.cx;
+          if (hitL && hitR) {
+            if (sp < kStack) {
+              L.stk[sp * 64 + lane] = lfirst ? cr : cl;
+              ++sp;
+            } else if (COUNT) {
+              ++l_ovf;
+            }
+          }
+          int32_t item = lfirst ? cl : cr;
+          bool have = hitL || hitR;
+          if (!have && sp > 0) {
+            --sp;
+            item = L.stk[sp * 64 + lane];
+            have = true;
+          }
+          R.cx = sp;
+          R.rc = have && item >= 0 ? item : -1;
+          R.nk = have && item < 0 && -item - 1 < H.bvh_n ? -item - 1 : -1;
+          if (R.rc < 0 && R.nk < 0) st = kDone;
+          if (COUNT) ++l_cells;
+        }
+        if (!BVH && is_step) {
           // ---- cell exhausted: stop, or leave it.  An empty cell carries the
           // Chebyshev distance k to the nearest occupied cell, so the whole
           // cube of half-size k-1 around it is empty and the walk jumps to
@@ -1017,12 +1087,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
             st = graze ? kPaused : st;
             gk = graze ? nk : gk;
           }
-          // next reference (after the last use of this one, so the load can land
-          // in its register and stay in flight into the next iteration)
-          ++R.rc;
-          R.nk = (int32_t)ldg(H.refs, (uint32_t)R.rc);  // -1 past the cell's last reference
+          if (BVH) {  // next stacked item, or the walk is over
+            int32_t sp = R.cx;
+            int32_t item = -1;
+            const bool have = sp > 0;
+            if (have) {
+              --sp;
+              item = L.stk[sp * 64 + lane];
+            }
+            R.cx = sp;
+            R.rc = have && item >= 0 ? item : -1;
+            R.nk = have && item < 0 && -item - 1 < H.bvh_n ? -item - 1 : -1;
+            if (R.rc < 0 && R.nk < 0 && st == kRun) st = kDone;
+          } else {
+            // next reference (after the last use of this one, so the load can
+            // land in its register and stay in flight into the next iteration)
+            ++R.rc;
+            R.nk = (int32_t)ldg(H.refs, (uint32_t)R.rc);  // -1 past the cell's last reference
+          }
         }
-        if (enter) load_cell(R, H);
+        if (!BVH && enter) load_cell(R, H);
         }  // work
       }
       (void)anyhit;
@@ -1044,6 +1128,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
         atomicAdd(&L.cnt[11], l_tt);
         atomicAdd(&L.cnt[12], l_th);
       }
+      if (BVH) atomicAdd(&L.cnt[13], l_ovf);
     }
     __syncthreads();
     if (lane == 0) {
@@ -1066,6 +1151,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TRANS ? 3 : 
         atomicAdd(&st[TR_STAT_JUMPS], (unsigned long long)L.cnt[10]);
         atomicAdd(&st[TR_STAT_TRI_TESTS], (unsigned long long)L.cnt[11]);
         atomicAdd(&st[TR_STAT_TRI_HITS], (unsigned long long)L.cnt[12]);
+        atomicAdd(&st[TR_STAT_STACK_OVERFLOWS], (unsigned long long)L.cnt[13]);
         atomicAdd(&st[TR_STAT_CYCLES_TRAVERSE], (unsigned long long)c_cyc_trav);
         atomicAdd(&st[TR_STAT_CYCLES_TOTAL], (unsigned long long)(clock64() - c_cyc_start));
       }
@@ -1099,7 +1185,7 @@ __global__ void k_debug_ao_dirs(int64_t n, const float *nrm, const uint32_t *pix
 
 namespace trh {
 
-template <int BANKS, bool RES, bool CNT, bool TRANS, bool TRI>
+template <int BANKS, bool RES, bool CNT, bool TRANS, bool TRI, bool BVH = false>
 static hipError_t launch_t(const WaveLaunch &L, hipStream_t st) {
   WaveArgs a;
   a.jobs = L.jobs;
@@ -1111,7 +1197,7 @@ static hipError_t launch_t(const WaveLaunch &L, hipStream_t st) {
   a.refill_below = L.refill_below;
   a.cyl_wait = L.cyl_wait;
   a.mix = L.mix;
-  k_render_wave<BANKS, RES, CNT, TRANS, TRI><<<L.n_waves, 64, 0, st>>>(a);
+  k_render_wave<BANKS, RES, CNT, TRANS, TRI, BVH><<<L.n_waves, 64, 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -1127,6 +1213,17 @@ static hipError_t launch_bt(const WaveLaunch &L, hipStream_t st) {
 
 // Variants: compositing (transparency) and triangles are compiled in only
 // for launches that need them, so the common kernel keeps its registers.
+// BVH walk: two banks, opaque rendering
+template <bool TRI>
+static hipError_t launch_bvh_walk(const WaveLaunch &L, hipStream_t st) {
+  const bool cnt = L.count_ops != 0 && L.stats != nullptr;
+  if (L.resolve)
+    return cnt ? launch_t<2, true, true, false, TRI, true>(L, st)
+               : launch_t<2, true, false, false, TRI, true>(L, st);
+  return cnt ? launch_t<2, false, true, false, TRI, true>(L, st)
+             : launch_t<2, false, false, false, TRI, true>(L, st);
+}
+
 template <int BANKS>
 static hipError_t launch_b(const WaveLaunch &L, hipStream_t st) {
   if (L.trans) return L.tri ? launch_bt<BANKS, true, true>(L, st) : launch_bt<BANKS, true, false>(L, st);
@@ -1134,6 +1231,7 @@ static hipError_t launch_b(const WaveLaunch &L, hipStream_t st) {
 }
 
 hipError_t launch_render_wave(const WaveLaunch &L, hipStream_t st) {
+  if (L.bvh) return L.tri ? launch_bvh_walk<true>(L, st) : launch_bvh_walk<false>(L, st);
   if (L.banks == 3) return launch_b<3>(L, st);
   return launch_b<2>(L, st);
 }

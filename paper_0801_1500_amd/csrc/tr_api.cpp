@@ -63,6 +63,8 @@ struct tr_scene {
   double4 *sph64 = nullptr, *cylA64 = nullptr, *cylW64 = nullptr, *cylB64 = nullptr;
   float4 *sph32 = nullptr, *cylA32 = nullptr, *cylW32 = nullptr, *albedo = nullptr;
   double4 *triA64 = nullptr, *triB64 = nullptr, *triC64 = nullptr;
+  float4 *bvh_nodes = nullptr;  // linear BVH (tr_scene_build_bvh), 4 per internal node
+  int64_t bvh_n = 0;            // primitives it covers (0 = not built)
   float4 *triV32 = nullptr, *triE1_32 = nullptr, *triE2_32 = nullptr;
   uint32_t *cell_begin = nullptr, *refs = nullptr, *count = nullptr, *scan_scratch = nullptr;
   uint32_t *wrefs = nullptr;  // FP32 walk lists: per occupied cell its references, then -1
@@ -89,7 +91,8 @@ static void free_scene_arrays(tr_scene *s) {
   void *ptrs[] = {s->sph64, s->cylA64, s->cylW64, s->cylB64, s->sph32,       s->cylA32,
                   s->cylW32, s->albedo, s->cell_begin, s->refs, s->count, s->scan_scratch,
                   s->bounds_scratch, s->bounds, s->cellinfo, s->dist0, s->dist1, s->wrefs,
-                  s->triA64, s->triB64, s->triC64, s->triV32, s->triE1_32, s->triE2_32};
+                  s->triA64, s->triB64, s->triC64, s->triV32, s->triE1_32, s->triE2_32,
+                  s->bvh_nodes};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_bounds) (void)hipHostFree(s->h_bounds);
@@ -146,6 +149,8 @@ static void fill_scene_dev(tr_scene *s) {
   d.triV32 = s->triV32;
   d.triE1_32 = s->triE1_32;
   d.triE2_32 = s->triE2_32;
+  d.bvh = s->bvh_nodes;
+  d.bvh_n = (int32_t)s->bvh_n;
   d.sph64 = s->sph64;
   d.cylA64 = s->cylA64;
   d.cylW64 = s->cylW64;
@@ -490,6 +495,78 @@ extern "C" tr_status tr_scene_rebuild(tr_scene *s, double cells_per_prim, void *
   return build_grid(s, (hipStream_t)hip_stream);
 }
 
+// Linear BVH over the resident primitives, for the BVH walk (tr_tune.accel).
+// Needs the grid's box and margins, so a scene whose grid failed cannot build one.
+extern "C" tr_status tr_scene_build_bvh(tr_scene *s, void *hip_stream) {
+  if (!s) return fail(TR_EINVAL, "tr_scene_build_bvh: NULL scene");
+  if (!s->grid_ok) return fail(TR_EINVAL, "scene grid is invalid (its last rebuild failed)");
+  const int64_t n = s->n_s + s->n_c + s->n_t;
+  // node records are addressed with 32-bit byte offsets (64 bytes per node)
+  if (n >= ((int64_t)1 << 26)) return fail(TR_EUNSUPPORTED, "BVH needs fewer than 2^26 primitives");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (s->bvh_nodes) {
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipFree(s->bvh_nodes));
+    s->bvh_nodes = nullptr;
+    s->bvh_n = 0;
+  }
+  if (n >= 2) {
+    HIP_TRY(dmalloc(&s->bvh_nodes, 4 * (n - 1)));
+    trh::BvhScratch w{};
+    std::vector<void *> tmp;
+    hipError_t e = hipSuccess;
+    auto get = [&](auto **p, int64_t cnt) {
+      if (e == hipSuccess) e = dmalloc(p, cnt);
+      if (e == hipSuccess) tmp.push_back((void *)*p);
+    };
+    get(&w.keys, n);
+    get(&w.vals, n);
+    get(&w.keys2, n);
+    get(&w.vals2, n);
+    get(&w.parent_l, n);
+    get(&w.flags, n + 1);
+    get(&w.left, n - 1);
+    get(&w.right, n - 1);
+    get(&w.parent_i, n - 1);
+    get(&w.arrivals, n - 1);
+    get(&w.ibox, 6 * (n - 1));
+    get(&w.scan_scratch, trh::scan_scratch_u32(n + 1));
+    trh::BuildArgs a{};
+    a.n_s = (int32_t)s->n_s;
+    a.n_c = (int32_t)s->n_c;
+    a.n_t = (int32_t)s->n_t;
+    a.sph64 = s->sph64;
+    a.cylA64 = s->cylA64;
+    a.cylB64 = s->cylB64;
+    a.triA64 = s->triA64;
+    a.triB64 = s->triB64;
+    a.triC64 = s->triC64;
+    if (e == hipSuccess) e = trh::launch_bvh(a, s->gp.lo, s->gp.hi, s->gp.delta, s->org, w, s->bvh_nodes, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    for (void *p : tmp) (void)hipFree(p);
+    if (e != hipSuccess) {
+      (void)hipFree(s->bvh_nodes);
+      s->bvh_nodes = nullptr;
+      return fail(e == hipErrorOutOfMemory ? TR_ENOMEM : TR_EDEVICE, "BVH build: %s", hipGetErrorString(e));
+    }
+  }
+  s->bvh_n = n;
+  fill_scene_dev(s);
+  return TR_OK;
+}
+
+extern "C" tr_status tr_scene_bvh_nodes(const tr_scene *s, float *nodes, int64_t *n_nodes,
+                                        void *hip_stream) {
+  if (!s || !n_nodes) return fail(TR_EINVAL, "tr_scene_bvh_nodes: NULL scene or n_nodes");
+  *n_nodes = s->bvh_n >= 2 ? s->bvh_n - 1 : 0;
+  if (nodes && *n_nodes > 0) {
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipMemcpyAsync(nodes, s->bvh_nodes, (size_t)*n_nodes * 64, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return TR_OK;
+}
+
 extern "C" tr_status tr_scene_set_max_skip(tr_scene *s, int32_t max_skip, void *hip_stream) {
   if (!s) return fail(TR_EINVAL, "tr_scene_set_max_skip: NULL scene");
   if (max_skip < 0 || max_skip > 32) return fail(TR_EINVAL, "max_skip must be 0..32");
@@ -745,6 +822,7 @@ static tr_status default_tune(tr_tune *t) {
   t->count_ops = 0;
   t->cyl_wait = 64;
   t->mix = 16;
+  t->accel = 0;
   return TR_OK;
 }
 
@@ -755,6 +833,7 @@ static tr_status check_tune(const tr_tune &t) {
   if (t.refill_below < 1 || t.refill_below > 64) return fail(TR_EINVAL, "tune.refill_below must be 1..64");
   if (t.cyl_wait < 1 || t.cyl_wait > 64) return fail(TR_EINVAL, "tune.cyl_wait must be 1..64");
   if (t.mix < 1 || t.mix > 64) return fail(TR_EINVAL, "tune.mix must be 1..64");
+  if (t.accel != 0 && t.accel != 1) return fail(TR_EINVAL, "tune.accel must be 0 or 1");
   return TR_OK;
 }
 
@@ -1051,6 +1130,14 @@ static tr_status run_aa_means(const std::vector<AAMean> &means, hipStream_t st) 
 // Launch the wavefront kernel over the jobs (already filled, tiles set).
 static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, uint64_t *stats,
                                   hipStream_t st) {
+  if (t.accel) {
+    for (const JobDev &J : jobs) {
+      if (J.sc.bvh_n != (int64_t)J.sc.n_s + J.sc.n_c + J.sc.n_t)
+        return fail(TR_EINVAL, "tune.accel = 1 needs tr_scene_build_bvh on every scene");
+      if (J.layers > 1)
+        return fail(TR_EUNSUPPORTED, "the BVH walk renders opaque frames (max_layers <= 1)");
+    }
+  }
   int64_t total = 0;
   for (auto &J : jobs) {
     J.queue_begin = total;
@@ -1086,6 +1173,7 @@ static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, u
     L.trans |= J.layers > 1;
     L.tri |= J.sc.n_t > 0;
   }
+  L.bvh = t.accel;
   HIP_TRY(trh::launch_render_wave(L, st));
   HIP_TRY(hipEventRecord(ls->done, st));
   return TR_OK;

@@ -61,6 +61,18 @@ hipError_t launch_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, con
 hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32_t *refs,
                              hipStream_t st);
 
+// Linear BVH over all primitives (n >= 2): 4 float4 per internal node (see
+// k_bvh_pack); node 0 is the root.  Scratch sizes: keys, vals, keys2, vals2,
+// parent_l: n; flags: n + 1; left, right, parent_i, arrivals: n - 1; ibox:
+// 6 (n - 1) doubles; scan_scratch: scan_scratch_u32(n + 1).
+struct BvhScratch {
+  uint32_t *keys, *vals, *keys2, *vals2, *flags, *scan_scratch, *arrivals;
+  int32_t *left, *right, *parent_i, *parent_l;
+  double *ibox;
+};
+hipError_t launch_bvh(const BuildArgs &a, const double lo[3], const double hi[3], double margin,
+                      const double origin[3], BvhScratch &w, float4 *nodes, hipStream_t st);
+
 // ---- frame output (frame_out.hip) ----
 // values -> bytes, floor(clamp(v, 0, 1) * 255 + 1/2); any alignment
 hipError_t launch_quantize_rgb8(const float *in, int64_t n, uint8_t *out, hipStream_t st);
@@ -83,6 +95,7 @@ struct WaveLaunch {
   int32_t resolve;
   int32_t trans;             // some job composites transparent layers
   int32_t tri;               // some job's scene has triangles
+  int32_t bvh;               // walk the scenes' BVHs instead of their grids
 };
 hipError_t launch_render_wave(const WaveLaunch &L, hipStream_t st);
 hipError_t launch_zero_counter(uint32_t *p, hipStream_t st);

@@ -1,0 +1,128 @@
+"""The BVH walk (tune accel=1), the alternative acceleration structure: the
+linear BVH built on the GPU is a valid tree over every primitive (checked on
+the host: each node and primitive reached once, every box holding what is
+below it); renders through it meet the FP32 bar against the oracle, match the
+grid walk, and never overflow the traversal stack; argument errors."""
+import numpy as np
+import pytest
+
+import scenegen
+from parity_util import assert_fp32_parity, compare, frame_to_numpy
+
+pytestmark = pytest.mark.gpu
+
+OUT = ("rgb", "hit_id", "ao_mask", "light_mask")
+
+
+@pytest.fixture(scope="module")
+def tr():
+    import paper_0801_1500_amd as tr
+    tr.lib()
+    return tr
+
+
+def _prim_boxes(s):
+    c, r = np.asarray(s.sph_center, np.float64).reshape(-1, 3), np.asarray(s.sph_radius, np.float64)
+    boxes = [np.concatenate([c - r[:, None], c + r[:, None]], axis=1)]
+    a, b = np.asarray(s.cyl_a, np.float64).reshape(-1, 3), np.asarray(s.cyl_b, np.float64).reshape(-1, 3)
+    rho = np.asarray(s.cyl_radius, np.float64)[:, None]
+    boxes.append(np.concatenate([np.minimum(a, b) - rho, np.maximum(a, b) + rho], axis=1))
+    if s.n_triangles:
+        tv = np.asarray(s.tri_v, np.float64).reshape(-1, 3, 3)
+        boxes.append(np.concatenate([tv.min(axis=1), tv.max(axis=1)], axis=1))
+    return np.concatenate(boxes)
+
+
+def check_bvh(gs, s):
+    nodes = gs.bvh_nodes()
+    n = s.n_prims
+    assert nodes.shape == (n - 1, 16)
+    kids = nodes[:, 12:14].copy().view(np.int32)
+    internal = kids[kids >= 0]
+    leaves = -kids[kids < 0] - 1
+    # every internal node but the root is a child exactly once; every
+    # primitive is a leaf exactly once
+    assert np.array_equal(np.sort(internal), np.arange(1, n - 1))
+    assert np.array_equal(np.sort(leaves), np.arange(n))
+    lo, hi, _, _ = gs.grid_info()
+    org = 0.5 * (lo + hi)
+    pb = _prim_boxes(s) - np.concatenate([org, org])
+    box = [nodes[:, 0:6].astype(np.float64), nodes[:, 6:12].astype(np.float64)]
+    for side in (0, 1):
+        k = kids[:, side]
+        b = box[side]
+        leaf = k < 0
+        # a leaf box holds its primitive's box
+        p = pb[-k[leaf] - 1]
+        assert np.all(b[leaf, :3] <= p[:, :3]) and np.all(b[leaf, 3:] >= p[:, 3:])
+        # an internal child's box holds both of its own child boxes
+        c = k[~leaf]
+        for sub in (0, 1):
+            inner = box[sub][c]
+            assert np.all(b[~leaf, :3] <= inner[:, :3]) and np.all(b[~leaf, 3:] >= inner[:, 3:])
+    return nodes
+
+
+@pytest.mark.parametrize("which", ["tiny", "protein", "mixed"])
+def test_bvh_structure(tr, which):
+    s = {"tiny": lambda: scenegen.tiny_scene(seed=1), "protein": scenegen.protein_scene,
+         "mixed": scenegen.mixed_tiny_scene}[which]()
+    print("bvh structure", which, flush=True)
+    gs = tr.Scene(s)
+    gs.build_bvh()
+    check_bvh(gs, s)
+
+
+def _render(tr, gs, c, p, accel, prec="fp32_resolve"):
+    import torch
+    fr = tr.render(gs, c, p, precision=prec, outputs=OUT, stats=True,
+                   tune={"accel": accel, "count_ops": 1})
+    torch.cuda.synchronize()
+    return frame_to_numpy(fr)
+
+
+@pytest.mark.parametrize("which", ["protein", "mixed"])
+def test_bvh_walk_matches_oracle_and_grid(tr, oracle_mod, which):
+    if which == "protein":
+        s = scenegen.protein_scene()
+        c0 = scenegen.protein_camera(scenegen.RES_1MP)
+        c = scenegen.Camera(c0.eye, c0.lookat, c0.up, c0.fovy_deg, 241, 284)
+    else:
+        s = scenegen.mixed_tiny_scene()
+        c = scenegen.Camera((0.0, 4.0, 30.0), (0.0, -2.0, 0.0), (0.0, 1.0, 0.0), 50.0, 128, 112)
+    p = scenegen.Params(ao_samples=8, seed=2)
+    gs = tr.Scene(s)
+    gs.build_bvh()
+    print("bvh walk", which, flush=True)
+    got = _render(tr, gs, c, p, 1)
+    st = dict(zip(tr.STAT_NAMES, got["stats"].tolist()))
+    assert st["stack_overflows"] == 0
+    ref = oracle_mod.render(s, c, p, grid=4.0)
+    m = compare(got, ref, 8, s.n_lights)
+    print(m)
+    assert_fp32_parity(m)
+    grid = _render(tr, gs, c, p, 0)
+    same = (grid["hit_id"] == got["hit_id"]) & (grid["ao_mask"] == got["ao_mask"]) & \
+           (grid["light_mask"] == got["light_mask"])
+    assert same.mean() >= 0.9999
+    # the same primitive tests give the same colours
+    assert np.array_equal(grid["rgb"][same], got["rgb"][same])
+
+
+def test_errors(tr):
+    s = scenegen.tiny_scene(seed=1)
+    gs = tr.Scene(s)
+    c = scenegen.Camera((0.0, 0.0, 30.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 50.0, 32, 32)
+    with pytest.raises(tr.TRError) as e:
+        tr.render(gs, c, scenegen.Params(ao_samples=4), tune={"accel": 1})
+    assert e.value.status == -1
+    gs.build_bvh()
+    st = scenegen.Scene(**{**s.__dict__, "sph_opacity": np.full(s.n_spheres, 0.5, np.float32)})
+    gt = tr.Scene(st)
+    gt.build_bvh()
+    with pytest.raises(tr.TRError) as e:
+        tr.render(gt, c, scenegen.Params(ao_samples=4, max_layers=3), tune={"accel": 1})
+    assert e.value.status == -4
+    with pytest.raises(tr.TRError) as e:
+        tr.render(gs, c, scenegen.Params(ao_samples=4), tune={"accel": 2})
+    assert e.value.status == -1
