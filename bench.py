@@ -123,11 +123,14 @@ def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
     sub = [tr.alloc_frame(c, ("rgb",), stats=False) for c in cams[:8]]
     walks = walk_compare(tr, torch, gs, lambda: tr.render_batch_into(
         [gs] * 8, cams[:8], params[:8], sub), [(24.0, 32), (24.0, 1), (4.0, 32), (4.0, 1)], reps=2)
+    bvh = bvh_measure(tr, torch, gs, lambda a: tr.render_batch_tiles_into(
+        [gs] * 8, cams[:8], params[:8], sub, [0] * 8, [tr.tile_count(c.width, c.height, 8) for c in cams[:8]],
+        tune={"accel": a}), reps=2)
     return {"workload": "1,000,000-object walk (ball radius 250), 64 views of 1920x1080 per "
                         "graph launch, 32 AO samples, FP32 + FP64 re-solve",
             "ms_per_launch": ms, "views_per_s": 64 * 1000.0 / ms, "rays_per_launch": rays,
             "rays_per_s": rays / (ms * 1e-3),
-            "walk_8_views": walks}
+            "walk_8_views": walks, "bvh_8_views": bvh}
 
 
 def scene_ingest_measure(tr, torch, scene, name: str) -> dict:
@@ -232,6 +235,27 @@ def walk_compare(tr, torch, gs, render, configs, reps: int = 3) -> list:
                     "ms": e0.elapsed_time(e1) / reps})
     gs.rebuild(24.0)
     gs.set_max_skip(32)
+    return out
+
+
+def bvh_measure(tr, torch, gs, render_with, reps: int = 3) -> dict:
+    """The BVH walk against the grid walk on the same frame(s): BVH build
+    time (GPU, to completion) and render time of each walk."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gs.build_bvh()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    out = {"bvh_build_ms": build_ms}
+    for name, accel in (("grid_ms", 0), ("bvh_ms", 1)):
+        render_with(accel)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            render_with(accel)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
     return out
 
 
@@ -402,13 +426,16 @@ def main():
         del f64
         log("fp64 plain path", fp64)
 
-    aa = spec = trans = tris = walks = None
+    aa = spec = trans = tris = walks = bvh = None
     if not args.no_variants:
         wf = tr.alloc_frame(cam, ("rgb",))
+
         walks = walk_compare(tr, torch, gs, lambda: tr.render_into(gs, cam, params, wf, prec),
                              [(24.0, 32), (24.0, 1), (4.0, 32), (4.0, 1)])
-        del wf
         log("grid shapes", walks)
+        bvh = bvh_measure(tr, torch, gs, lambda a: tr.render_into(gs, cam, params, wf, prec,
+                                                                  tune={"accel": a}))
+        log("bvh walk", bvh)
         aa, spec, trans, tris = variants_measure(tr, torch, scenegen, np, gs, scene, cam, params,
                                                  prec, log)
 
@@ -457,6 +484,7 @@ def main():
         "render_only_rays_per_s": rays_frame / (render_ms.mean() * 1e-3),
         "fp64_plain": fp64,
         "walk_shapes": walks,
+        "bvh_walk": bvh,
         "antialias": aa,
         "specular": spec,
         "transparency": trans,
