@@ -240,13 +240,17 @@ def walk_compare(tr, torch, gs, render, configs, reps: int = 3) -> list:
 
 def bvh_measure(tr, torch, gs, render_with, reps: int = 3) -> dict:
     """The BVH walk against the grid walk on the same frame(s): BVH build
-    time (GPU, to completion) and render time of each walk."""
+    time (GPU, to completion), the tree's depth and render time of each walk
+    (the BVH walk is refused on a tree deeper than its stack)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gs.build_bvh()
     build_ms = (time.perf_counter() - t0) * 1e3
-    out = {"bvh_build_ms": build_ms}
+    out = {"bvh_build_ms": build_ms, "bvh_depth": gs.bvh_depth()}
     for name, accel in (("grid_ms", 0), ("bvh_ms", 1)):
+        if accel and out["bvh_depth"] > 48:
+            out[name] = None
+            continue
         render_with(accel)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

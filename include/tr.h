@@ -250,16 +250,21 @@ tr_status tr_scene_set_max_skip(tr_scene *scene, int32_t max_skip, void *hip_str
  * the hierarchy of Karras (HPG 2012), node boxes bottom-up (widened by the
  * grid's insertion margin, rounded outwards to FP32).  Synchronises the
  * stream.  TR_EINVAL on a NULL scene or an invalid grid; TR_EUNSUPPORTED from
- * 2^26 primitives on. */
+ * 2^26 primitives on.  The walk keeps one deferred sibling per level on a
+ * 48-entry stack per ray: rendering through a tree deeper than 48 internal
+ * nodes (tr_scene_bvh_nodes reports the depth) fails with TR_EUNSUPPORTED
+ * before any launch. */
 tr_status tr_scene_build_bvh(tr_scene *scene, void *hip_stream);
 
 /* Copy the BVH's records to a HOST buffer (may be NULL) of 16 floats per
  * internal node: left child box (lo xyz, hi xyz), right child box, then the
  * two children as int32 bit patterns (node index >= 0, or -(primitive id) - 1
  * for a leaf) and two zero words.  Boxes are in the FP32 frame (relative to
- * the grid box centre).  *n_nodes = primitives - 1 (0 below two). */
+ * the grid box centre).  *n_nodes = primitives - 1 (0 below two); *depth
+ * (may be NULL) = internal nodes on the longest root-to-leaf path (0 when no
+ * BVH is built).  TR_EINVAL on a NULL scene or n_nodes. */
 tr_status tr_scene_bvh_nodes(const tr_scene *scene, float *nodes, int64_t *n_nodes,
-                             void *hip_stream);
+                             int32_t *depth, void *hip_stream);
 
 /* Device bytes held by the scene (arrays + grid). */
 tr_status tr_scene_footprint(const tr_scene *scene, size_t *bytes);

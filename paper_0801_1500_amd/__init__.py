@@ -95,7 +95,7 @@ def lib():
         "tr_scene_rebuild": ([vp, C.c_double, vp], st),
         "tr_scene_set_max_skip": ([vp, C.c_int32, vp], st),
         "tr_scene_build_bvh": ([vp, vp], st),
-        "tr_scene_bvh_nodes": ([vp, vp, C.POINTER(i64), vp], st),
+        "tr_scene_bvh_nodes": ([vp, vp, C.POINTER(i64), C.POINTER(C.c_int32), vp], st),
         "tr_scene_footprint": ([vp, C.POINTER(C.c_size_t)], st),
         "tr_scene_grid_info": ([vp, vp, vp, vp, C.POINTER(i64)], st),
         "tr_scene_grid_arrays": ([vp, vp, vp, vp], st),
@@ -245,12 +245,18 @@ class Scene:
     def bvh_nodes(self, stream=None):
         """BVH records: float32 [n_nodes, 16] (see tr_scene_bvh_nodes)."""
         n = C.c_int64(0)
-        _check(lib().tr_scene_bvh_nodes(self.handle, None, C.byref(n), _stream(stream)))
+        _check(lib().tr_scene_bvh_nodes(self.handle, None, C.byref(n), None, _stream(stream)))
         out = np.zeros((max(n.value, 0), 16), dtype=np.float32)
         if n.value > 0:
-            _check(lib().tr_scene_bvh_nodes(self.handle, out.ctypes.data, C.byref(n),
+            _check(lib().tr_scene_bvh_nodes(self.handle, out.ctypes.data, C.byref(n), None,
                                             _stream(stream)))
         return out
+
+    def bvh_depth(self) -> int:
+        """Internal nodes on the BVH's longest root-to-leaf path (0: none built)."""
+        n, d = C.c_int64(0), C.c_int32(0)
+        _check(lib().tr_scene_bvh_nodes(self.handle, None, C.byref(n), C.byref(d), None))
+        return d.value
 
     def set_max_skip(self, max_skip: int, stream=None):
         """Empty-space skipping cap (1 = plain 3D-DDA); rebuilds the grid."""

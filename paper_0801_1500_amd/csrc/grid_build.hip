@@ -559,7 +559,7 @@ __device__ __forceinline__ void child_box(const trh::BuildArgs &a, const uint32_
 __global__ void k_bvh_bounds(const trh::BuildArgs a, const uint32_t *vals, int64_t n,
                              const int32_t *left, const int32_t *right, const int32_t *parent_i,
                              const int32_t *parent_l, uint32_t *arrivals, double *ibox,
-                             double margin) {
+                             int32_t *height, double margin) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   int32_t p = parent_l[q];
@@ -576,6 +576,9 @@ __global__ void k_bvh_bounds(const trh::BuildArgs a, const uint32_t *vals, int64
       b[k] = l0[k] < l1[k] ? l0[k] : l1[k];
       b[3 + k] = h0[k] > h1[k] ? h0[k] : h1[k];
     }
+    const volatile int32_t *hv = height;
+    const int32_t hl = left[p] >= 0 ? hv[left[p]] : 0, hr = right[p] >= 0 ? hv[right[p]] : 0;
+    ((volatile int32_t *)height)[p] = 1 + (hl > hr ? hl : hr);
     p = parent_i[p];
   }
 }
@@ -720,7 +723,7 @@ hipError_t launch_bvh(const BuildArgs &a, const double lo[3], const double hi[3]
   hipError_t e = launch_fill_u32(w.arrivals, n - 1, 0u, st);
   if (e != hipSuccess) return e;
   k_bvh_bounds<<<nb, kBlock, 0, st>>>(a, v0, n, w.left, w.right, w.parent_i, w.parent_l, w.arrivals,
-                                      w.ibox, margin);
+                                      w.ibox, w.height, margin);
   k_bvh_pack<<<blocks_for(n - 1), kBlock, 0, st>>>(a, v0, n, w.left, w.right, w.ibox, margin,
                                                    origin[0], origin[1], origin[2], nodes);
   return hipGetLastError();

@@ -81,7 +81,7 @@ __device__ __forceinline__ void bank_pixel(const BankInfo &B, int32_t q, int32_t
   y = B.y0 + qy;
 }
 
-constexpr int kStack = 48;  // BVH traversal stack entries per lane
+constexpr int kStack = trh::kBvhStack;  // BVH traversal stack entries per lane
 
 template <int BANKS, bool TRANS, bool BVH>
 struct Lds {

@@ -65,6 +65,7 @@ struct tr_scene {
   double4 *triA64 = nullptr, *triB64 = nullptr, *triC64 = nullptr;
   float4 *bvh_nodes = nullptr;  // linear BVH (tr_scene_build_bvh), 4 per internal node
   int64_t bvh_n = 0;            // primitives it covers (0 = not built)
+  int32_t bvh_depth = 0;        // internal nodes on its longest root-to-leaf path
   float4 *triV32 = nullptr, *triE1_32 = nullptr, *triE2_32 = nullptr;
   uint32_t *cell_begin = nullptr, *refs = nullptr, *count = nullptr, *scan_scratch = nullptr;
   uint32_t *wrefs = nullptr;  // FP32 walk lists: per occupied cell its references, then -1
@@ -151,6 +152,7 @@ static void fill_scene_dev(tr_scene *s) {
   d.triE2_32 = s->triE2_32;
   d.bvh = s->bvh_nodes;
   d.bvh_n = (int32_t)s->bvh_n;
+  d.bvh_depth = s->bvh_depth;
   d.sph64 = s->sph64;
   d.cylA64 = s->cylA64;
   d.cylW64 = s->cylW64;
@@ -509,7 +511,9 @@ extern "C" tr_status tr_scene_build_bvh(tr_scene *s, void *hip_stream) {
     HIP_TRY(hipFree(s->bvh_nodes));
     s->bvh_nodes = nullptr;
     s->bvh_n = 0;
+    s->bvh_depth = 0;
   }
+  int32_t depth = 0;
   if (n >= 2) {
     HIP_TRY(dmalloc(&s->bvh_nodes, 4 * (n - 1)));
     trh::BvhScratch w{};
@@ -529,6 +533,7 @@ extern "C" tr_status tr_scene_build_bvh(tr_scene *s, void *hip_stream) {
     get(&w.right, n - 1);
     get(&w.parent_i, n - 1);
     get(&w.arrivals, n - 1);
+    get(&w.height, n - 1);
     get(&w.ibox, 6 * (n - 1));
     get(&w.scan_scratch, trh::scan_scratch_u32(n + 1));
     trh::BuildArgs a{};
@@ -542,7 +547,9 @@ extern "C" tr_status tr_scene_build_bvh(tr_scene *s, void *hip_stream) {
     a.triB64 = s->triB64;
     a.triC64 = s->triC64;
     if (e == hipSuccess) e = trh::launch_bvh(a, s->gp.lo, s->gp.hi, s->gp.delta, s->org, w, s->bvh_nodes, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->h_total, w.height, sizeof(int32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) std::memcpy(&depth, s->h_total, sizeof(int32_t));
     for (void *p : tmp) (void)hipFree(p);
     if (e != hipSuccess) {
       (void)hipFree(s->bvh_nodes);
@@ -551,14 +558,16 @@ extern "C" tr_status tr_scene_build_bvh(tr_scene *s, void *hip_stream) {
     }
   }
   s->bvh_n = n;
+  s->bvh_depth = depth;
   fill_scene_dev(s);
   return TR_OK;
 }
 
 extern "C" tr_status tr_scene_bvh_nodes(const tr_scene *s, float *nodes, int64_t *n_nodes,
-                                        void *hip_stream) {
+                                        int32_t *depth, void *hip_stream) {
   if (!s || !n_nodes) return fail(TR_EINVAL, "tr_scene_bvh_nodes: NULL scene or n_nodes");
   *n_nodes = s->bvh_n >= 2 ? s->bvh_n - 1 : 0;
+  if (depth) *depth = s->bvh_n >= 2 ? s->bvh_depth : 0;
   if (nodes && *n_nodes > 0) {
     hipStream_t st = (hipStream_t)hip_stream;
     HIP_TRY(hipMemcpyAsync(nodes, s->bvh_nodes, (size_t)*n_nodes * 64, hipMemcpyDeviceToHost, st));
@@ -1136,6 +1145,9 @@ static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, u
         return fail(TR_EINVAL, "tune.accel = 1 needs tr_scene_build_bvh on every scene");
       if (J.layers > 1)
         return fail(TR_EUNSUPPORTED, "the BVH walk renders opaque frames (max_layers <= 1)");
+      if (J.sc.bvh_depth > trh::kBvhStack)
+        return fail(TR_EUNSUPPORTED, "BVH depth %d exceeds the walk's stack of %d entries",
+                    (int)J.sc.bvh_depth, trh::kBvhStack);
     }
   }
   int64_t total = 0;

@@ -41,7 +41,7 @@ struct SceneDev {
   const float4 *triV32, *triE1_32, *triE2_32;  // (v0 - org, |e1 x e2|), (e1, 0), (e2, 0)
   const float4 *bvh;   // linear BVH records (4 float4 per internal node), or null
   int32_t bvh_n;       // primitives covered by the BVH (0 = none built)
-  int32_t pad_bvh_;
+  int32_t bvh_depth;   // internal nodes on the BVH's longest root-to-leaf path
   const float4 *albedo;
   const uint32_t *cell_begin, *refs;
   const uint32_t *wrefs;  // walk lists (see CellInfo)

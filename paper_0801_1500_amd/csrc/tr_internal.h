@@ -63,13 +63,19 @@ hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32
 
 // Linear BVH over all primitives (n >= 2): 4 float4 per internal node (see
 // k_bvh_pack); node 0 is the root.  Scratch sizes: keys, vals, keys2, vals2,
-// parent_l: n; flags: n + 1; left, right, parent_i, arrivals: n - 1; ibox:
-// 6 (n - 1) doubles; scan_scratch: scan_scratch_u32(n + 1).
+// parent_l: n; flags: n + 1; left, right, parent_i, arrivals, height: n - 1;
+// ibox: 6 (n - 1) doubles; scan_scratch: scan_scratch_u32(n + 1).  height[i]
+// = internal nodes on the longest path from node i down to a leaf, so
+// height[0] is the tree's depth.
 struct BvhScratch {
   uint32_t *keys, *vals, *keys2, *vals2, *flags, *scan_scratch, *arrivals;
-  int32_t *left, *right, *parent_i, *parent_l;
+  int32_t *left, *right, *parent_i, *parent_l, *height;
   double *ibox;
 };
+// Entries of the BVH walk's per-lane traversal stack.  A walk that visits a
+// node at depth d holds at most d deferred siblings, so a tree of depth
+// <= kBvhStack never overflows it; deeper trees are refused before launch.
+constexpr int kBvhStack = 48;
 hipError_t launch_bvh(const BuildArgs &a, const double lo[3], const double hi[3], double margin,
                       const double origin[3], BvhScratch &w, float4 *nodes, hipStream_t st);
 

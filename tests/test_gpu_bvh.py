@@ -60,6 +60,18 @@ def check_bvh(gs, s):
         for sub in (0, 1):
             inner = box[sub][c]
             assert np.all(b[~leaf, :3] <= inner[:, :3]) and np.all(b[~leaf, 3:] >= inner[:, 3:])
+    # the depth the build reports (internal nodes on the longest root-to-leaf
+    # path, which bounds the walk's stack) is the tree's, found top-down here
+    depth = np.zeros(n - 1, np.int64)
+    depth[0] = 1
+    order = [0]
+    for i in order:
+        for c in kids[i]:
+            if c >= 0:
+                depth[c] = depth[i] + 1
+                order.append(int(c))
+    assert gs.bvh_depth() == int(depth.max())
+    assert gs.bvh_depth() <= 48
     return nodes
 
 
@@ -126,3 +138,33 @@ def test_errors(tr):
     with pytest.raises(tr.TRError) as e:
         tr.render(gs, c, scenegen.Params(ao_samples=4), tune={"accel": 2})
     assert e.value.status == -1
+
+
+def _spheres(centres, radii):
+    c = np.array(centres, dtype=np.float64).reshape(-1, 3)
+    z3 = np.zeros((0, 3))
+    ld = np.array([[0.3, 0.4, 1.0]])
+    return scenegen.Scene(c, np.array(radii, dtype=np.float64),
+                          np.full((len(radii), 3), 0.6, np.float32), z3, z3.copy(), np.zeros(0),
+                          np.zeros((0, 3), np.float32), ld, np.ones_like(ld))
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_bvh_one_and_two_primitives(tr, oracle_mod, n):
+    # one primitive: no internal node, the walk tests it directly; two: the
+    # root alone
+    s = _spheres([[0.0, 0.0, 0.0], [2.5, 1.0, -3.0]][:n], [2.0, 1.5][:n])
+    gs = tr.Scene(s)
+    gs.build_bvh()
+    assert gs.bvh_nodes().shape == (n - 1, 16)
+    assert gs.bvh_depth() == n - 1
+    c = scenegen.Camera((0.0, 0.0, 30.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 20.0, 64, 48)
+    p = scenegen.Params(ao_samples=8, seed=4)
+    print("bvh tiny", n, flush=True)
+    got = _render(tr, gs, c, p, 1)
+    ref = oracle_mod.render(s, c, p, grid=None)
+    assert (ref["hit_id"] >= 0).sum() > 200
+    assert_fp32_parity(compare(got, ref, 8, s.n_lights))
+    grid = _render(tr, gs, c, p, 0)
+    for k in OUT:
+        assert np.array_equal(grid[k], got[k]), k
