@@ -47,19 +47,38 @@ def algorithmic_flops(st: dict, n_lights: int, ao_on: bool) -> float:
                  + c["ao_dir"] * st["ao_rays"] + c["shade"] * st["pixels"])
 
 
-def measured_traffic():
-    """HBM bytes per render launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary (each scaled by a plain copy's reading), valid only
-    while the kernel source is the one that was profiled; else None."""
+def _current_profile(name: str):
+    """A committed rocprofv3 summary under profiles/, or None when it is
+    missing or was taken on another version of the kernel source."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "render_wave_p17_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     prof = json.load(open(path))
     src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in prof["kernel_source_files"])
     if hashlib.sha256(src).hexdigest() != prof["kernel_source_sha256"]:
         return None
-    return prof["hbm_bytes_per_launch"]
+    return prof
+
+
+def measured_traffic():
+    """HBM bytes per render launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (each scaled by a plain copy's reading), valid only
+    while the kernel source is the one that was profiled; else None."""
+    prof = _current_profile("render_wave_p17_traffic.json")
+    return None if prof is None else prof["hbm_bytes_per_launch"]
+
+
+def measured_issue():
+    """Instruction-issue figures of the render kernel from the committed
+    rocprofv3 SQ counter passes (same source-version rule): the share of
+    VALU and SALU issue slots used and the active lanes per VALU
+    instruction; else None."""
+    prof = _current_profile("render_wave_p17_issue.json")
+    if prof is None:
+        return None
+    d = prof["derived"]
+    return {k: d[k] for k in ("valu_issue_frac", "salu_issue_frac", "active_lanes_per_valu_inst")}
 
 
 def cpu_baseline(scene, cam, params, target_s: float = 15.0) -> dict:
@@ -410,7 +429,8 @@ def main():
                 "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
                 "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
                 "kernel": "k_render_wave", "kernel_ms": float(render_ms.mean()),
-                "flop_per_frame": flops_frame, "flop_per_counted_ray": flops_frame / rays_frame}
+                "flop_per_frame": flops_frame, "flop_per_counted_ray": flops_frame / rays_frame,
+                "issue": measured_issue()}
 
     # plain FP64 GPU path on the same frame
     fp64 = None
