@@ -431,6 +431,9 @@ def main():
                 "kernel": "k_render_wave", "kernel_ms": float(render_ms.mean()),
                 "flop_per_frame": flops_frame, "flop_per_counted_ray": flops_frame / rays_frame,
                 "issue": measured_issue()}
+    if roofline["traffic"] is not None:  # measured HBM bytes over the live kernel time
+        roofline["hbm_GBps"] = roofline["traffic"] / (render_ms.mean() * 1e-3) / 1e9
+        roofline["hbm_frac"] = roofline["hbm_GBps"] / PEAK_HBM_GBS
 
     # plain FP64 GPU path on the same frame
     fp64 = None
