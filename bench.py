@@ -145,11 +145,22 @@ def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
     bvh = bvh_measure(tr, torch, gs, lambda a: tr.render_batch_tiles_into(
         [gs] * 8, cams[:8], params[:8], sub, [0] * 8, [tr.tile_count(c.width, c.height, 8) for c in cams[:8]],
         tune={"accel": a}), reps=2)
+    # FP32 (+ FP64 re-solve) against the plain FP64 path, same 8-view batch
+    prec = {}
+    for name in ("fp32_resolve", "fp64"):
+        tr.render_batch_into([gs] * 8, cams[:8], params[:8], sub, precision=name)
+        torch.cuda.synchronize()
+        e0.record()
+        tr.render_batch_into([gs] * 8, cams[:8], params[:8], sub, precision=name)
+        e1.record()
+        torch.cuda.synchronize()
+        prec[name + "_ms"] = e0.elapsed_time(e1)
+    prec["fp64_over_fp32"] = prec["fp64_ms"] / prec["fp32_resolve_ms"]
     return {"workload": "1,000,000-object walk (ball radius 250), 64 views of 1920x1080 per "
                         "graph launch, 32 AO samples, FP32 + FP64 re-solve",
             "ms_per_launch": ms, "views_per_s": 64 * 1000.0 / ms, "rays_per_launch": rays,
             "rays_per_s": rays / (ms * 1e-3),
-            "walk_8_views": walks, "bvh_8_views": bvh}
+            "walk_8_views": walks, "bvh_8_views": bvh, "precision_8_views": prec}
 
 
 def scene_ingest_measure(tr, torch, scene, name: str) -> dict:
