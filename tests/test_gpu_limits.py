@@ -1,0 +1,75 @@
+"""The largest frame the boundary accepts: 46340 x 46340 = 2,147,395,600
+pixels, just under the W*H < 2^31 - 1 limit (25.8 GB of RGB).  Both GPU
+paths render it in one launch; sampled pixels (the first, the last, and a
+seeded spread) meet the FP32 and FP64 bars against the oracle; every pixel is
+counted; the 8-bit output of the whole frame matches its definition on the
+samples.  A frame past the limit is rejected before any launch."""
+import numpy as np
+import pytest
+
+import scenegen
+from parity_util import assert_fp32_parity, compare
+
+pytestmark = pytest.mark.gpu
+
+OUT = ("rgb", "hit_id", "ao_mask", "light_mask")
+SIDE = 46340
+
+
+@pytest.fixture(scope="module")
+def tr():
+    import paper_0801_1500_amd as tr
+    tr.lib()
+    return tr
+
+
+def _gather(torch, fr, idx):
+    return {"rgb": fr["rgb"].view(-1, 3)[idx].cpu().numpy(),
+            "hit_id": fr["hit_id"].view(-1)[idx].cpu().numpy(),
+            "ao_mask": fr["ao_mask"].view(-1)[idx].cpu().numpy().view(np.uint32),
+            "light_mask": fr["light_mask"].view(-1)[idx].cpu().numpy()}
+
+
+def test_largest_frame(tr, oracle_mod):
+    import torch
+    s = scenegen.protein_scene()
+    gs = tr.Scene(s)
+    c0 = scenegen.protein_camera(scenegen.RES_1MP)
+    c = scenegen.Camera(c0.eye, c0.lookat, c0.up, c0.fovy_deg, SIDE, SIDE)
+    n = SIDE * SIDE
+    assert n < 2 ** 31 - 1
+    p = scenegen.Params(ao_samples=4, seed=11)
+    pix = np.unique(np.concatenate([[0, n - 1], scenegen.sample_pixels(SIDE, SIDE, 20000, 23)]))
+    ref = oracle_mod.render(s, c, p, grid=4.0, pix=pix)
+    assert (ref["hit_id"] >= 0).mean() > 0.1
+    idx = torch.from_numpy(pix).cuda()
+    fr = tr.alloc_frame(c, OUT, stats=True)
+    for prec in ("fp32_resolve", "fp64"):
+        print("largest frame", SIDE, "x", SIDE, prec, flush=True)
+        fr["stats"].zero_()
+        tr.render_into(gs, c, p, fr, prec)
+        torch.cuda.synchronize()
+        st = dict(zip(tr.STAT_NAMES, fr["stats"].cpu().tolist()))
+        assert st["pixels"] == n, st
+        m = compare(_gather(torch, fr, idx), ref, 4, s.n_lights)
+        print(m, flush=True)
+        if prec == "fp64":
+            assert m["hit_mismatch"] == 0, m
+            assert m["decision_flips"] <= max(2, m["decisions"] // 1000000), m
+            assert m["max_abs_agree"] <= 1.2e-7, m
+        else:
+            assert_fp32_parity(m)
+    # 8-bit output of the whole frame (6.4 G values): floor(clamp(v) * 255 + 1/2)
+    q = tr.quantize_rgb8(fr["rgb"])
+    torch.cuda.synchronize()
+    v = fr["rgb"].view(-1, 3)[idx].cpu().numpy().astype(np.float64)
+    want = np.floor(np.clip(v, 0.0, 1.0) * 255.0 + 0.5).astype(np.uint8)
+    assert np.array_equal(q.view(-1, 3)[idx].cpu().numpy(), want)
+    del fr, q
+    torch.cuda.empty_cache()
+    # one more row and column put W*H past the limit
+    assert (SIDE + 1) ** 2 > 2 ** 31 - 2
+    big = scenegen.Camera(c0.eye, c0.lookat, c0.up, c0.fovy_deg, SIDE + 1, SIDE + 1)
+    with pytest.raises(tr.TRError) as e:
+        tr.render_into(gs, big, p, {"rgb": torch.empty(3, device="cuda")}, "fp32_resolve")
+    assert e.value.status == -1
