@@ -376,20 +376,32 @@ tr_status tr_frame_quantize(const float *values, int64_t n, uint8_t *out, void *
 /* ------------------------------------------------ graphs (batched views) */
 
 /* A captured, replayable batch render: the tile-counter reset and the
- * persistent launch recorded once into a hipGraph.  Cameras live in a
- * device job table, so tr_graph_set_cameras changes views without
- * re-capturing.  Same restrictions as tr_render_batch. */
+ * persistent launch recorded once into a hipGraph.  Cameras and parameters
+ * live in a device job table, so tr_graph_update changes views without
+ * re-capturing.  The jobs follow tr_render_batch's rules, and in addition
+ * need an FP32 precision, aa_samples <= 1 and max_layers <= 1 (else
+ * TR_EUNSUPPORTED).  The tuning (tune may be NULL) is fixed at capture;
+ * tune->accel = 1 walks the scenes' BVHs (tr_scene_build_bvh first).
+ * The graph reads its scenes' device arrays as they were at creation or at
+ * the last tr_graph_update: after tr_scene_rebuild, tr_scene_set_max_skip
+ * or tr_scene_build_bvh on one of its scenes, call tr_graph_update before
+ * the next launch.  Scenes and frames must outlive the graph. */
 typedef struct tr_graph tr_graph;
 
 tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,
                           const tr_params *params, const tr_frame *frames, const tr_tune *tune,
                           void *hip_stream, tr_graph **out);
 /* Update the n cameras (same resolutions as at creation) and/or params
- * (either may be NULL); the job table upload is enqueued on the stream
- * before any later tr_graph_launch on that stream. */
+ * (either may be NULL; both NULL re-reads the scenes only).  The job table
+ * upload is enqueued on the stream after every replay already enqueued, on
+ * any stream, and every later tr_graph_launch, on any stream, waits for it.
+ * TR_EINVAL on a changed resolution or precision or an invalid camera or
+ * params (the graph is then unchanged). */
 tr_status tr_graph_update(tr_graph *g, const tr_camera *cams, const tr_params *params,
                           void *hip_stream);
+/* Replay the graph on the stream (after the latest tr_graph_update). */
 tr_status tr_graph_launch(tr_graph *g, void *hip_stream);
+/* Waits for the device to finish, then frees the graph.  NULL is a no-op. */
 void tr_graph_destroy(tr_graph *g);
 
 /* ----------------------------------------------------------- autotuning */

@@ -1136,19 +1136,26 @@ static tr_status run_aa_means(const std::vector<AAMean> &means, hipStream_t st) 
   return TR_OK;
 }
 
+// What the wavefront kernel needs of a job under the tuning: with the BVH
+// walk, a built BVH that its stack can hold, and opaque rendering.
+static tr_status check_wave_job(const JobDev &J, const tr_tune &t) {
+  if (!t.accel) return TR_OK;
+  if (J.sc.bvh_n != (int64_t)J.sc.n_s + J.sc.n_c + J.sc.n_t)
+    return fail(TR_EINVAL, "tune.accel = 1 needs tr_scene_build_bvh on every scene");
+  if (J.layers > 1)
+    return fail(TR_EUNSUPPORTED, "the BVH walk renders opaque frames (max_layers <= 1)");
+  if (J.sc.bvh_depth > trh::kBvhStack)
+    return fail(TR_EUNSUPPORTED, "BVH depth %d exceeds the walk's stack of %d entries",
+                (int)J.sc.bvh_depth, trh::kBvhStack);
+  return TR_OK;
+}
+
 // Launch the wavefront kernel over the jobs (already filled, tiles set).
 static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, uint64_t *stats,
                                   hipStream_t st) {
-  if (t.accel) {
-    for (const JobDev &J : jobs) {
-      if (J.sc.bvh_n != (int64_t)J.sc.n_s + J.sc.n_c + J.sc.n_t)
-        return fail(TR_EINVAL, "tune.accel = 1 needs tr_scene_build_bvh on every scene");
-      if (J.layers > 1)
-        return fail(TR_EUNSUPPORTED, "the BVH walk renders opaque frames (max_layers <= 1)");
-      if (J.sc.bvh_depth > trh::kBvhStack)
-        return fail(TR_EUNSUPPORTED, "BVH depth %d exceeds the walk's stack of %d entries",
-                    (int)J.sc.bvh_depth, trh::kBvhStack);
-    }
+  for (const JobDev &J : jobs) {
+    const tr_status rc = check_wave_job(J, t);
+    if (rc != TR_OK) return rc;
   }
   int64_t total = 0;
   for (auto &J : jobs) {
@@ -1200,6 +1207,7 @@ extern "C" tr_status tr_render_tuned(const tr_scene *s, const tr_camera *c, cons
   if (rc != TR_OK) return rc;
   JobDev J;
   rc = make_job(s, c, p, f, t.tile_w, J);
+  if (rc == TR_OK && p->precision != TR_PREC_FP64) rc = check_wave_job(J, t);
   if (rc != TR_OK) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
   std::vector<JobDev> jobs(1, J);
@@ -1236,10 +1244,13 @@ static tr_status batch_impl(int32_t n, const tr_scene *const *scenes, const tr_c
   tr_status rc = check_tune(t);
   if (rc != TR_OK) return rc;
   const int res = params[0].precision == TR_PREC_FP32_RESOLVE;
-  std::vector<JobDev> jobs;
-  std::vector<int32_t> aa;
+  std::vector<JobDev> jobs, f64;
+  std::vector<int32_t> aa, aa64;
+  std::vector<uint64_t *> stats64;
   jobs.reserve(n);
   uint64_t *stats = frames[0].stats;
+  // every job is checked before anything is enqueued: a failing batch
+  // renders nothing
   for (int32_t i = 0; i < n; ++i) {
     JobDev J;
     rc = make_job(scenes[i], &cams[i], &params[i], &frames[i], t.tile_w, J);
@@ -1247,13 +1258,9 @@ static tr_status batch_impl(int32_t n, const tr_scene *const *scenes, const tr_c
     if (tb && aa_count(params[i]) > 1) return fail(TR_EUNSUPPORTED, "tile ranges need aa_samples <= 1");
     if (params[i].precision == TR_PREC_FP64) {
       if (tb) return fail(TR_EUNSUPPORTED, "tile ranges need an FP32 precision");
-      std::vector<JobDev> one(1, J);
-      std::vector<AAMean> means;
-      rc = expand_aa(one, std::vector<int32_t>(1, aa_count(params[i])), st, means);
-      if (rc != TR_OK) return rc;
-      for (const JobDev &Js : one) HIP_TRY(trh::launch_render_plain_f64(Js, frames[i].stats, st));
-      rc = run_aa_means(means, st);
-      if (rc != TR_OK) return rc;
+      f64.push_back(J);
+      aa64.push_back(aa_count(params[i]));
+      stats64.push_back(frames[i].stats);
       continue;
     }
     if ((params[i].precision == TR_PREC_FP32_RESOLVE) != (res != 0))
@@ -1267,8 +1274,24 @@ static tr_status batch_impl(int32_t n, const tr_scene *const *scenes, const tr_c
       J.tile_begin = tb[i];
       J.tile_end = te[i];
     }
+    rc = check_wave_job(J, t);
+    if (rc != TR_OK) return fail(rc, "job %d: %s", i, g_err.c_str());
     jobs.push_back(J);
     aa.push_back(aa_count(params[i]));
+  }
+  {
+    int64_t tiles = 0;
+    for (size_t k = 0; k < jobs.size(); ++k) tiles += (jobs[k].tile_end - jobs[k].tile_begin) * aa[k];
+    if (tiles > (int64_t)UINT32_MAX - 1) return fail(TR_EINVAL, "too many tiles in one launch");
+  }
+  for (size_t k = 0; k < f64.size(); ++k) {  // plain FP64 jobs: one launch each
+    std::vector<JobDev> one(1, f64[k]);
+    std::vector<AAMean> means;
+    rc = expand_aa(one, std::vector<int32_t>(1, aa64[k]), st, means);
+    if (rc != TR_OK) return rc;
+    for (const JobDev &Js : one) HIP_TRY(trh::launch_render_plain_f64(Js, stats64[k], st));
+    rc = run_aa_means(means, st);
+    if (rc != TR_OK) return rc;
   }
   if (jobs.empty()) return TR_OK;
   std::vector<AAMean> means;
@@ -1329,7 +1352,8 @@ struct tr_graph {
   tr_tune tune{};
   JobDev *h_jobs = nullptr, *d_jobs = nullptr;
   uint32_t *d_counter = nullptr;
-  hipEvent_t staged = nullptr;
+  hipEvent_t staged = nullptr;    // the last job-table upload has run
+  hipEvent_t launched = nullptr;  // the last replay has run
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t total_tiles = 0;
@@ -1343,12 +1367,16 @@ static void free_graph(tr_graph *g) {
   if (g->d_jobs) (void)hipFree(g->d_jobs);
   if (g->d_counter) (void)hipFree(g->d_counter);
   if (g->staged) (void)hipEventDestroy(g->staged);
+  if (g->launched) (void)hipEventDestroy(g->launched);
   delete g;
 }
 
+// Stage the host job table and copy it to the device on the stream, after
+// any replay already enqueued (on whatever stream) has finished reading it.
 static tr_status graph_upload(tr_graph *g, hipStream_t st) {
   HIP_TRY(hipEventSynchronize(g->staged));  // previous staging copy has run
   std::memcpy(g->h_jobs, g->jobs.data(), sizeof(JobDev) * g->jobs.size());
+  HIP_TRY(hipStreamWaitEvent(st, g->launched, 0));
   HIP_TRY(hipMemcpyAsync(g->d_jobs, g->h_jobs, sizeof(JobDev) * g->jobs.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipEventRecord(g->staged, st));
   return TR_OK;
@@ -1384,6 +1412,7 @@ extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, c
       rc = fail(TR_EINVAL, "all jobs of one graph must use the same precision");
     if (rc == TR_OK && frames[i].stats != frames[0].stats)
       rc = fail(TR_EINVAL, "all jobs of one graph must share one stats buffer");
+    if (rc == TR_OK) rc = check_wave_job(J, g->tune);
     if (rc != TR_OK) {
       free_graph(g);
       return rc;
@@ -1402,7 +1431,9 @@ extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, c
   if (e == hipSuccess) e = hipMalloc((void **)&g->d_jobs, sizeof(JobDev) * n);
   if (e == hipSuccess) e = hipMalloc((void **)&g->d_counter, 2 * sizeof(uint32_t));
   if (e == hipSuccess) e = hipEventCreateWithFlags(&g->staged, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&g->launched, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(g->staged, st);
+  if (e == hipSuccess) e = hipEventRecord(g->launched, st);
   if (e != hipSuccess) {
     free_graph(g);
     return fail(TR_EDEVICE, "graph resources: %s", hipGetErrorString(e));
@@ -1437,6 +1468,7 @@ extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, c
     L.trans = 0;
     L.tri = 0;
     for (int32_t i = 0; i < n; ++i) L.tri |= g->jobs[i].sc.n_t > 0;
+    L.bvh = g->tune.accel;
     if (e == hipSuccess) e = trh::launch_render_wave(L, cap);
     hipError_t e2 = hipStreamEndCapture(cap, &g->graph);
     if (e == hipSuccess) e = e2;
@@ -1454,7 +1486,8 @@ extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, c
 extern "C" tr_status tr_graph_update(tr_graph *g, const tr_camera *cams, const tr_params *params,
                                      void *hip_stream) {
   if (!g) return fail(TR_EINVAL, "NULL graph");
-  if (!cams && !params) return TR_OK;
+  // (with both NULL the job table is rebuilt from the scenes as they are
+  // now, which picks up rebuilt grids and BVHs)
   std::vector<JobDev> nj(g->n);
   for (int32_t i = 0; i < g->n; ++i) {
     const tr_camera &c = cams ? cams[i] : g->cams[i];
@@ -1468,6 +1501,8 @@ extern "C" tr_status tr_graph_update(tr_graph *g, const tr_camera *cams, const t
     if (rc != TR_OK) return fail(rc, "job %d: %s", i, g_err.c_str());
     if (nj[i].layers > 1)
       return fail(TR_EUNSUPPORTED, "job %d: graphs render opaque frames (max_layers <= 1)", i);
+    rc = check_wave_job(nj[i], g->tune);
+    if (rc != TR_OK) return fail(rc, "job %d: %s", i, g_err.c_str());
     nj[i].queue_begin = g->jobs[i].queue_begin;
   }
   for (int32_t i = 0; i < g->n; ++i) {
@@ -1480,7 +1515,10 @@ extern "C" tr_status tr_graph_update(tr_graph *g, const tr_camera *cams, const t
 
 extern "C" tr_status tr_graph_launch(tr_graph *g, void *hip_stream) {
   if (!g) return fail(TR_EINVAL, "NULL graph");
-  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)hip_stream));
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIP_TRY(hipStreamWaitEvent(st, g->staged, 0));  // the latest job table is on the device
+  HIP_TRY(hipGraphLaunch(g->exec, st));
+  HIP_TRY(hipEventRecord(g->launched, st));
   return TR_OK;
 }
 

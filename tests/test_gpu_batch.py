@@ -120,3 +120,71 @@ def test_autotune_choice_is_bit_identical(tr, scenes):
     p = scenegen.Params(ao_samples=8, seed=3)
     best, ms = tr.autotune(sc, c, p)
     assert ms > 0 and best["tile_w"] in (4, 8, 16, 32)
+
+
+def test_failing_batch_renders_nothing(tr, scenes):
+    # every job is checked before anything is enqueued: an FP64 job ahead of
+    # an invalid one is not rendered either
+    import torch
+    cams, params, which = _jobs()
+    bad = scenegen.Camera(cams[1].eye, cams[1].lookat, cams[1].up, 0.0, 96, 200)  # fovy 0
+    p64 = scenegen.Params(**{**params[0].__dict__})
+    frames = [tr.alloc_frame(c, OUT) for c in (cams[0], bad)]
+    for f in frames:
+        f["rgb"].fill_(-7.0)
+    with pytest.raises(tr.TRError) as e:
+        tr.render_batch_into([scenes[0], scenes[1]], [cams[0], bad], [p64, params[1]], frames,
+                             precision="fp64")
+    assert e.value.status == -1
+    torch.cuda.synchronize()
+    assert bool((frames[0]["rgb"] == -7.0).all())
+
+
+def test_graph_bvh_cross_stream_and_refresh(tr, scenes):
+    import torch
+    sc = tr.Scene(scenegen.random_walk_scene(3000, scenegen.serving_radius(6000), 101))
+    sc.build_bvh()
+    cams = scenegen.orbit_cameras(4, dist=60.0, res=(128, 96))
+    params = [scenegen.Params(ao_samples=8, seed=6, view_id=k) for k in range(4)]
+    frames = [tr.alloc_frame(c, OUT) for c in cams]
+    # the BVH walk in a graph equals the BVH walk rendered alone
+    g = tr.Graph([sc] * 4, cams, params, frames, tune={"accel": 1})
+    alone = []
+    for c, p in zip(cams, params):
+        alone.append(frame_to_numpy(tr.render(sc, c, p, outputs=OUT, tune={"accel": 1})))
+    torch.cuda.synchronize()
+    g.launch()
+    torch.cuda.synchronize()
+    for i, f in enumerate(frames):
+        _same(frame_to_numpy(f), alone[i], ("bvh", i))
+    # update on one stream, replay on another: the replay sees the new table
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    cams2 = cams[2:] + cams[:2]
+    alone2 = []
+    for c, p in zip(cams2, params):
+        alone2.append(frame_to_numpy(tr.render(sc, c, p, outputs=OUT, tune={"accel": 1})))
+    torch.cuda.synchronize()
+    g.update(cams=cams2, stream=s1)
+    g.launch(stream=s2)
+    torch.cuda.synchronize()
+    for i, f in enumerate(frames):
+        _same(frame_to_numpy(f), alone2[i], ("streams", i))
+    # rebuilding the scene's grid and BVH, then re-reading the scenes (update
+    # with no arguments), gives the same frames
+    sc.rebuild(cells_per_prim=6.0)
+    sc.build_bvh()
+    g.update()
+    for f in frames:
+        f["rgb"].zero_()
+    g.launch()
+    torch.cuda.synchronize()
+    for i, f in enumerate(frames):
+        _same(frame_to_numpy(f), alone2[i], ("refresh", i))
+    g.destroy()
+    # a graph asking for the BVH walk of a scene without one is refused
+    plain = tr.Scene(scenegen.tiny_scene(seed=1))
+    c = scenegen.Camera((0.0, 0.0, 30.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 50.0, 32, 32)
+    with pytest.raises(tr.TRError) as e:
+        tr.Graph([plain], [c], [scenegen.Params(ao_samples=4)], [tr.alloc_frame(c, OUT)],
+                 tune={"accel": 1})
+    assert e.value.status == -1
