@@ -115,6 +115,9 @@ class Server:
                  outputs: Sequence[str] = ("rgb",), keep_frames: bool = False,
                  max_inflight: int = 2, stream=None):
         import torch
+        if precision not in ("fp32", "fp32_resolve"):
+            raise ValueError("the server renders tile ranges, which need an FP32 precision "
+                             "('fp32' or 'fp32_resolve'), not %r" % (precision,))
         self.torch = torch
         self.scenes = list(scenes)
         self.budget = int(hbm_budget)
@@ -170,7 +173,7 @@ class Server:
                 ev.synchronize()
                 t_done = start_ev.elapsed_time(ev) * 1e-3
                 for job in finishing:
-                    job.done = t_done if realtime else t_done
+                    job.done = t_done
                     st.latencies.append(job.done - (job.arrival if realtime else 0.0))
                     active.remove(job)
                     used -= job.footprint

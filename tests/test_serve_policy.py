@@ -1,5 +1,6 @@
 """Host-side serving policies (no GPU): admission by slots and HBM
 footprint in arrival order, and oldest-first tile budgeting."""
+import pytest
 import scenegen
 from paper_0801_1500_amd.serve import Job, admit, plan_step
 
@@ -38,3 +39,11 @@ def test_plan_step_oldest_first_and_bounded():
     assert sum(p[2] - p[1] for p in plan) == 6 + 10 + 10
     a.next_tile = 10
     assert [p[0].job_id for p in plan_step([a], 5)] == []
+
+
+def test_server_refuses_fp64():
+    # tile ranges need an FP32 precision; the server says so before touching
+    # the device
+    from paper_0801_1500_amd import serve
+    with pytest.raises(ValueError):
+        serve.Server([], precision="fp64")
