@@ -1550,23 +1550,30 @@ extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr
   const size_t px = (size_t)c->width * c->height;
   float *rgb_ref = nullptr, *rgb = nullptr;
   int32_t *hid_ref = nullptr, *hid = nullptr;
-  HIP_TRY(hipMalloc((void **)&rgb_ref, px * 12));
-  HIP_TRY(hipMalloc((void **)&rgb, px * 12));
-  HIP_TRY(hipMalloc((void **)&hid_ref, px * 4));
-  HIP_TRY(hipMalloc((void **)&hid, px * 4));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (rgb_ref) (void)hipFree(rgb_ref);
+    if (rgb) (void)hipFree(rgb);
+    if (hid_ref) (void)hipFree(hid_ref);
+    if (hid) (void)hipFree(hid);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  {
+    hipError_t e = hipMalloc((void **)&rgb_ref, px * 12);
+    if (e == hipSuccess) e = hipMalloc((void **)&rgb, px * 12);
+    if (e == hipSuccess) e = hipMalloc((void **)&hid_ref, px * 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&hid, px * 4);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+      cleanup();
+      return fail(e == hipErrorOutOfMemory ? TR_ENOMEM : TR_EDEVICE, "autotune buffers: %s",
+                  hipGetErrorString(e));
+    }
+  }
   std::vector<float> h_a(px * 3), h_b(px * 3);
   std::vector<int32_t> i_a(px), i_b(px);
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  auto cleanup = [&]() {
-    (void)hipFree(rgb_ref);
-    (void)hipFree(rgb);
-    (void)hipFree(hid_ref);
-    (void)hipFree(hid);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-  };
   auto run = [&](const tr_tune &t, float *out_rgb, int32_t *out_hid, double &ms) -> tr_status {
     tr_frame fr{out_rgb, out_hid, nullptr, nullptr, nullptr};
     tr_status r = tr_render_tuned(s, c, p, &fr, &t, st);  // warm-up
