@@ -104,6 +104,8 @@ def lib():
         L.or_render.restype = C.c_int
         L.or_max_threads.restype = C.c_int32
         L.or_quantize_rgb8.argtypes = [i64, vp, vp]
+        L.or_tga_encode.argtypes = [vp, C.c_int32, C.c_int32, vp, i64]
+        L.or_tga_encode.restype = i64
         _lib = L
     return _lib
 
@@ -328,3 +330,19 @@ def quantize_rgb8(values: np.ndarray) -> np.ndarray:
 
 def max_threads() -> int:
     return int(lib().or_max_threads())
+
+
+def tga_encode(rgb8: np.ndarray) -> bytes:
+    """Run-length Targa file of an 8-bit RGB image [H, W, 3] (definition in
+    oracle.h)."""
+    a = np.ascontiguousarray(rgb8, dtype=np.uint8)
+    if a.ndim != 3 or a.shape[2] != 3:
+        raise ValueError("image must be [H, W, 3] uint8")
+    h, w = int(a.shape[0]), int(a.shape[1])
+    n = lib().or_tga_encode(a.ctypes.data, w, h, None, 0)
+    if n < 0:
+        raise ValueError("width and height must be 1..65535")
+    out = np.zeros(n, np.uint8)
+    got = lib().or_tga_encode(a.ctypes.data, w, h, out.ctypes.data, n)
+    assert got == n
+    return out.tobytes()

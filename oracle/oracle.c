@@ -890,3 +890,72 @@ void or_quantize_rgb8(int64_t n, const float *in, uint8_t *out) {
     out[i] = (uint8_t)floor(v * 255.0 + 0.5);
   }
 }
+
+/* ---- Targa file (definition in oracle.h) -------------------------------- */
+
+static int px_eq(const uint8_t *row, int32_t a, int32_t b) {
+  return row[3 * a] == row[3 * b] && row[3 * a + 1] == row[3 * b + 1] &&
+         row[3 * a + 2] == row[3 * b + 2];
+}
+
+/* length of the run of pixels equal to pixel i, starting at i */
+static int32_t run_from(const uint8_t *row, int32_t w, int32_t i) {
+  int32_t j = i + 1;
+  while (j < w && px_eq(row, j, i)) ++j;
+  return j - i;
+}
+
+static void put(uint8_t *out, int64_t *at, uint8_t v) {
+  if (out) out[*at] = v;
+  ++*at;
+}
+
+static void put_px(uint8_t *out, int64_t *at, const uint8_t *p) {
+  put(out, at, p[2]); /* B */
+  put(out, at, p[1]); /* G */
+  put(out, at, p[0]); /* R */
+}
+
+/* one row's packets; counts bytes only when out is NULL */
+static void tga_row(const uint8_t *row, int32_t w, uint8_t *out, int64_t *at) {
+  int32_t i = 0;
+  while (i < w) {
+    const int32_t r = run_from(row, w, i);
+    if (r >= 2) { /* run packets */
+      for (int32_t left = r; left > 0;) {
+        const int32_t c = left < 128 ? left : 128;
+        put(out, at, (uint8_t)(0x80 | (c - 1)));
+        put_px(out, at, row + 3 * (int64_t)i);
+        left -= c;
+      }
+      i += r;
+    } else { /* raw packets over the stretch of pixels that start no run */
+      int32_t j = i;
+      while (j < w && run_from(row, w, j) == 1) ++j;
+      for (int32_t k = i; k < j;) {
+        const int32_t c = j - k < 128 ? j - k : 128;
+        put(out, at, (uint8_t)(c - 1));
+        for (int32_t q = 0; q < c; ++q) put_px(out, at, row + 3 * (int64_t)(k + q));
+        k += c;
+      }
+      i = j;
+    }
+  }
+}
+
+int64_t or_tga_encode(const uint8_t *rgb, int32_t w, int32_t h, uint8_t *out, int64_t cap) {
+  if (w < 1 || w > 65535 || h < 1 || h > 65535) return -1;
+  int64_t size = 18 + 26;
+  for (int32_t y = 0; y < h; ++y) tga_row(rgb + (int64_t)y * w * 3, w, NULL, &size);
+  if (!out || cap < size) return size;
+  static const char sig[18] = "TRUEVISION-XFILE.";
+  int64_t at = 0;
+  const uint8_t head[18] = {0, 0, 10, 0, 0, 0, 0, 0, 0, 0, 0, 0,
+                            (uint8_t)(w & 255), (uint8_t)(w >> 8), (uint8_t)(h & 255),
+                            (uint8_t)(h >> 8), 24, 0x20};
+  for (int k = 0; k < 18; ++k) put(out, &at, head[k]);
+  for (int32_t y = 0; y < h; ++y) tga_row(rgb + (int64_t)y * w * 3, w, out, &at);
+  for (int k = 0; k < 8; ++k) put(out, &at, 0);
+  for (int k = 0; k < 18; ++k) put(out, &at, (uint8_t)sig[k]);
+  return at;
+}

@@ -162,6 +162,24 @@ int32_t or_max_threads(void);
  * where v * 255 of a float is exact), NaN becoming 0. */
 void or_quantize_rgb8(int64_t n, const float *in, uint8_t *out);
 
+/* Targa (TGA 2.0) file of an 8-bit RGB image rgb[h][w][3], row 0 at the top
+ * (the "Image I/O" phase, Table 5; the paper names no file format, so this
+ * is a reading).  Layout: the 18-byte header (no image id, no colour map,
+ * image type 10 = run-length true colour, origin 0 0, width, height, 24 bits
+ * per pixel, descriptor 0x20 = rows stored top first), the packets of each
+ * row in turn, then the 26-byte TGA 2.0 footer (two zero offsets and the
+ * signature "TRUEVISION-XFILE." with its terminating zero).  Pixels are
+ * stored B, G, R.  Packets never cross a row:
+ *   - a maximal run of two or more equal pixels becomes run packets (header
+ *     0x80 | (count - 1), then the pixel) of 128 pixels, and a last one of
+ *     the rest;
+ *   - a maximal stretch of pixels equal to neither neighbour becomes raw
+ *     packets (header count - 1, then the pixels) of 128, and a last one of
+ *     the rest.
+ * Returns the file size in bytes (-1 if w or h is outside 1..65535); writes
+ * the file only when out is not NULL and cap >= the size. */
+int64_t or_tga_encode(const uint8_t *rgb, int32_t w, int32_t h, uint8_t *out, int64_t cap);
+
 #ifdef __cplusplus
 }
 #endif
