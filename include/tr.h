@@ -373,6 +373,32 @@ size_t tr_frame_footprint(const tr_camera *cam, const tr_params *params, uint32_
  * TR_EINVAL on n < 0 or a NULL pointer with n > 0; n = 0 does nothing. */
 tr_status tr_frame_quantize(const float *values, int64_t n, uint8_t *out, void *hip_stream);
 
+/* A Targa (TGA 2.0) file of an 8-bit RGB image, encoded on the GPU (the
+ * "Image I/O" phase of Table 5; the paper names no format).  rgb8: device
+ * bytes [height][width][3], R G B, row 0 at the top (tr_frame_quantize's
+ * output for a frame).  The file: an 18-byte header (image type 10,
+ * run-length true colour; 24 bits per pixel; descriptor 0x20, rows stored
+ * top first), each row's packets, and the 26-byte TGA 2.0 footer (zero
+ * extension and developer offsets, "TRUEVISION-XFILE." and a zero byte).
+ * Pixels are stored B G R.  Packets never cross a row: a maximal run of two
+ * or more equal pixels becomes run packets (header 0x80 | (count - 1), then
+ * the pixel) of 128 pixels and a last one of the rest; a maximal stretch of
+ * pixels equal to neither neighbour becomes raw packets (header count - 1,
+ * then the pixels) of 128 and a last one of the rest.
+ * out: device buffer of capacity bytes (tr_tga_max_bytes is always enough).
+ * The call waits for the size pass on the stream and sets *size to the file
+ * length; the file itself is written asynchronously on the stream.
+ * TR_EINVAL when width or height is outside 1..65535, on a NULL image or
+ * size, or when the file needs more than capacity bytes (then *size still
+ * holds the length and nothing is written). */
+tr_status tr_frame_encode_tga(const uint8_t *rgb8, int32_t width, int32_t height, uint8_t *out,
+                              int64_t capacity, int64_t *size, void *hip_stream);
+
+/* Bytes that always hold tr_frame_encode_tga's file of a width x height
+ * image (4 per pixel plus header and footer), or -1 when either side is
+ * outside 1..65535.  Host only. */
+int64_t tr_tga_max_bytes(int32_t width, int32_t height);
+
 /* ------------------------------------------------ graphs (batched views) */
 
 /* A captured, replayable batch render: the tile-counter reset and the

@@ -101,6 +101,8 @@ def lib():
         "tr_scene_grid_arrays": ([vp, vp, vp, vp], st),
         "tr_scene_walk_arrays": ([vp, vp, vp, C.POINTER(i64), vp], st),
         "tr_frame_quantize": ([vp, i64, vp, vp], st),
+        "tr_frame_encode_tga": ([vp, i32, i32, vp, i64, C.POINTER(i64), vp], st),
+        "tr_tga_max_bytes": ([i32, i32], i64),
         "tr_scene_save": ([vp, C.c_char_p, vp], st),
         "tr_scene_load": ([C.c_char_p, vp, C.POINTER(vp)], st),
         "tr_scene_destroy": ([vp], None),
@@ -429,6 +431,33 @@ def render_batch_tiles_into(scenes, cams, params, frames, tile_begin, tile_end,
     _check(lib().tr_render_batch_tiles(n, sc, cm, pr, fr, tb, te,
                                        C.byref(t) if t is not None else None, _stream(stream)))
     return frames
+
+
+def tga_max_bytes(width: int, height: int) -> int:
+    """Bytes that always hold the Targa file of a width x height image."""
+    n = lib().tr_tga_max_bytes(int(width), int(height))
+    if n < 0:
+        raise ValueError("Targa width and height must be 1..65535")
+    return int(n)
+
+
+def encode_tga(rgb8, out=None, stream=None):
+    """Run-length Targa file of an 8-bit RGB image, on the GPU
+    (tr_frame_encode_tga).  rgb8: a contiguous CUDA uint8 tensor [H, W, 3]
+    (e.g. quantize_rgb8's output); out: optional CUDA uint8 buffer.  Returns
+    a CUDA uint8 tensor holding exactly the file's bytes (a view of out when
+    given), written on the stream."""
+    torch = _torch()
+    if rgb8.dtype != torch.uint8 or not rgb8.is_cuda or rgb8.dim() != 3 or rgb8.shape[2] != 3:
+        raise TypeError("rgb8 must be a CUDA uint8 tensor [H, W, 3]")
+    rgb8 = rgb8.contiguous()
+    H, W = int(rgb8.shape[0]), int(rgb8.shape[1])
+    if out is None:
+        out = torch.empty(tga_max_bytes(W, H), dtype=torch.uint8, device=rgb8.device)
+    n = C.c_int64(0)
+    _check(lib().tr_frame_encode_tga(rgb8.data_ptr(), W, H, out.data_ptr(), out.numel(),
+                                     C.byref(n), _stream(stream)))
+    return out[:n.value]
 
 
 def tile_count(width: int, height: int, tile_w: int = 0) -> int:

@@ -11,7 +11,8 @@
 // are far below the memory time).
 //
 // Also here: the mean over an antialiased frame's sample planes, another
-// streaming pass (A * 4 bytes read and 4 written per value).
+// streaming pass (A * 4 bytes read and 4 written per value), and the
+// run-length Targa file of an 8-bit image (see k_tga_rows).
 #include "tr_internal.h"
 
 namespace {
@@ -70,6 +71,145 @@ __global__ __launch_bounds__(kThreads) void k_aa_mean(float *rgb, const float *p
   }
 }
 
+// ---- Targa file, run-length true colour (the packet rule is written out
+// with the host-side declaration).  One wave per image row, one pixel per
+// lane, 64 pixels per step.  A pixel's role follows from its neighbours
+// alone: it belongs to a run when it equals a neighbour; a segment (a
+// maximal run of one colour, or a maximal stretch of pixels in no run)
+// starts where the role changes or a run changes colour; packets are the
+// 128-pixel pieces of segments.  A run packet's 4 bytes belong to its last
+// pixel, a raw packet's header byte to its first, so a pixel's byte position
+// is the exclusive prefix sum of these sizes along the row.  Pass 1 sums
+// each row, a scan turns the sums into row offsets, pass 2 recomputes the
+// roles and writes.  The file is 18 header bytes, the rows, 26 footer bytes.
+
+constexpr int kTgaHead = 18, kTgaFoot = 26;
+__constant__ char kTgaSig[18] = "TRUEVISION-XFILE.";  // footer signature (with its zero)
+
+__device__ __forceinline__ uint32_t px3(const uint8_t *row, int32_t x) {
+  const uint8_t *p = row + 3 * (int64_t)x;
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(64) void k_tga_rows(const uint8_t *__restrict__ rgb, int32_t W,
+                                                 int64_t *__restrict__ row_bytes,
+                                                 const int64_t *__restrict__ row_off,
+                                                 uint8_t *__restrict__ out) {
+  const int32_t y = blockIdx.x;
+  const int32_t lane = threadIdx.x;
+  const uint8_t *row = rgb + (int64_t)y * W * 3;
+  const int64_t base = WRITE ? row_off[y] : 0;
+  int64_t done = 0;      // bytes of the row before this step's pixels
+  int32_t open_seg = 0;  // first pixel of the segment still open at the step's start
+  for (int32_t x0 = 0; x0 < W; x0 += 64) {
+    const int32_t x = x0 + lane;
+    const bool valid = x < W;
+    uint32_t p0 = 0;
+    bool run = false, start = false, end = false;
+    if (valid) {
+      const bool has_l = x > 0, has_l2 = x > 1, has_r = x + 1 < W, has_r2 = x + 2 < W;
+      p0 = px3(row, x);
+      const uint32_t pl = has_l ? px3(row, x - 1) : 0u, pl2 = has_l2 ? px3(row, x - 2) : 0u;
+      const uint32_t pr = has_r ? px3(row, x + 1) : 0u, pr2 = has_r2 ? px3(row, x + 2) : 0u;
+      const bool eq_l = has_l && p0 == pl, eq_r = has_r && p0 == pr;
+      run = eq_l || eq_r;
+      const bool run_l = has_l && (eq_l || (has_l2 && pl == pl2));  // pixel x - 1 in a run
+      const bool run_r = has_r && (eq_r || (has_r2 && pr == pr2));  // pixel x + 1 in a run
+      start = !has_l || run != run_l || (run && !eq_l);
+      end = !has_r || run != run_r || (run_r && !eq_r);  // pixel x + 1 starts a segment
+    }
+    const uint64_t sm = __ballot(start);
+    const uint64_t upto = lane == 63 ? sm : (sm & ((1ull << (lane + 1)) - 1ull));
+    const int32_t seg = upto ? x0 + 63 - (int32_t)__clzll(upto) : open_seg;
+    const int32_t kk = (x - seg) & 127;  // position in its packet
+    const bool first = kk == 0, last = kk == 127 || end;
+    const int32_t bytes = !valid ? 0 : (run ? (last ? 4 : 0) : (first ? 4 : 3));
+    int32_t incl = bytes;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    if (WRITE && valid) {
+      const int64_t pos = base + done + (incl - bytes);
+      const uint8_t r = (uint8_t)(p0 & 255u), g = (uint8_t)((p0 >> 8) & 255u),
+                    b = (uint8_t)(p0 >> 16);
+      if (run) {
+        if (last) {
+          out[pos] = (uint8_t)(0x80 | kk);
+          out[pos + 1] = b;
+          out[pos + 2] = g;
+          out[pos + 3] = r;
+        }
+      } else {
+        const int64_t q = pos + (first ? 1 : 0);
+        out[q] = b;
+        out[q + 1] = g;
+        out[q + 2] = r;
+        // the header sits before the packet's first pixel: 1 + 3 kk bytes back
+        if (last) out[first ? pos : pos - 1 - 3 * (int64_t)kk] = (uint8_t)kk;
+      }
+    }
+    done += __shfl(incl, 63);
+    if (sm) open_seg = x0 + 63 - (int32_t)__clzll(sm);
+  }
+  if (!WRITE && lane == 0) row_bytes[y] = done;
+}
+
+// Row offsets (exclusive sum of row sizes, after the header) and the file
+// size, in one workgroup: each thread sums a contiguous block of rows, the
+// block sums are scanned in LDS, then each thread writes its rows' offsets.
+__global__ __launch_bounds__(1024) void k_tga_offsets(const int64_t *__restrict__ row_bytes,
+                                                      int32_t H, int64_t *__restrict__ row_off,
+                                                      int64_t *__restrict__ total) {
+  __shared__ int64_t part[1024];
+  const int32_t t = threadIdx.x;
+  const int32_t per = (H + 1023) / 1024;
+  const int32_t b = min(H, t * per), e = min(H, b + per);
+  int64_t s = 0;
+  for (int32_t i = b; i < e; ++i) s += row_bytes[i];
+  part[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int64_t v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t at = kTgaHead + (t ? part[t - 1] : 0);
+  for (int32_t i = b; i < e; ++i) {
+    row_off[i] = at;
+    at += row_bytes[i];
+  }
+  if (t == 1023) *total = kTgaHead + part[1023] + kTgaFoot;
+}
+
+// Header (no image id or colour map, type 10, width, height, 24 bits, rows
+// top first) and footer (no extension or developer area, the signature).
+__global__ __launch_bounds__(64) void k_tga_frame(int32_t W, int32_t H,
+                                                  const int64_t *__restrict__ total,
+                                                  uint8_t *__restrict__ out) {
+  const int32_t t = threadIdx.x;
+  if (t < kTgaHead) {
+    uint8_t v = 0;
+    switch (t) {
+      case 2: v = 10; break;
+      case 12: v = (uint8_t)(W & 255); break;
+      case 13: v = (uint8_t)(W >> 8); break;
+      case 14: v = (uint8_t)(H & 255); break;
+      case 15: v = (uint8_t)(H >> 8); break;
+      case 16: v = 24; break;
+      case 17: v = 0x20; break;
+      default: break;
+    }
+    out[t] = v;
+  } else if (t < kTgaHead + kTgaFoot) {
+    const int32_t k = t - kTgaHead;  // footer byte
+    out[*total - kTgaFoot + k] = k < 8 ? (uint8_t)0 : (uint8_t)kTgaSig[k - 8];
+  }
+}
+
 }  // namespace
 
 namespace trh {
@@ -102,6 +242,24 @@ hipError_t launch_quantize_rgb8(const float *in, int64_t n, uint8_t *out, hipStr
     const int64_t blocks = (rest + kThreads - 1) / kThreads;
     k_quantize_scalar<<<(unsigned)blocks, kThreads, 0, st>>>(in + done, out + done, rest);
   }
+  return hipGetLastError();
+}
+
+}  // namespace trh
+
+namespace trh {
+
+hipError_t launch_tga_sizes(const uint8_t *rgb, int32_t W, int32_t H, int64_t *row_bytes,
+                            int64_t *row_off, int64_t *total, hipStream_t st) {
+  k_tga_rows<false><<<(unsigned)H, 64, 0, st>>>(rgb, W, row_bytes, nullptr, nullptr);
+  k_tga_offsets<<<1, 1024, 0, st>>>(row_bytes, H, row_off, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_tga_write(const uint8_t *rgb, int32_t W, int32_t H, const int64_t *row_off,
+                            const int64_t *total, uint8_t *out, hipStream_t st) {
+  k_tga_rows<true><<<(unsigned)H, 64, 0, st>>>(rgb, W, nullptr, row_off, out);
+  k_tga_frame<<<1, 64, 0, st>>>(W, H, total, out);
   return hipGetLastError();
 }
 

@@ -1329,6 +1329,59 @@ extern "C" tr_status tr_frame_quantize(const float *values, int64_t n, uint8_t *
   return TR_OK;
 }
 
+// ------------------------------------------------------------ Targa file
+extern "C" int64_t tr_tga_max_bytes(int32_t width, int32_t height) {
+  if (width < 1 || width > 65535 || height < 1 || height > 65535) return -1;
+  // a pixel costs at most 4 bytes (a raw packet's header and first pixel)
+  return 18 + 26 + (int64_t)height * 4 * (int64_t)width;
+}
+
+// Per-stream scratch of the encoder: row sizes, row offsets, the file size
+// (device) and its pinned read-back.
+struct TgaWork {
+  int64_t *rows = nullptr;  // [2 * cap + 1]: sizes, offsets, total
+  int64_t *h_total = nullptr;
+  int32_t cap = 0;
+};
+static std::map<std::pair<int, hipStream_t>, TgaWork> g_tga_work;
+
+extern "C" tr_status tr_frame_encode_tga(const uint8_t *rgb8, int32_t width, int32_t height,
+                                         uint8_t *out, int64_t capacity, int64_t *size,
+                                         void *hip_stream) {
+  if (!size) return fail(TR_EINVAL, "tr_frame_encode_tga: NULL size");
+  *size = 0;
+  if (width < 1 || width > 65535 || height < 1 || height > 65535)
+    return fail(TR_EINVAL, "Targa width and height must be 1..65535");
+  if (!rgb8) return fail(TR_EINVAL, "tr_frame_encode_tga: NULL image");
+  if (capacity < 0 || (!out && capacity > 0)) return fail(TR_EINVAL, "tr_frame_encode_tga: bad output buffer");
+  hipStream_t st = (hipStream_t)hip_stream;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  TgaWork &w = g_tga_work[{dev, st}];
+  if (w.cap < height) {
+    if (w.rows) {  // earlier work on this stream may still use the old scratch
+      HIP_TRY(hipStreamSynchronize(st));
+      HIP_TRY(hipFree(w.rows));
+      w.rows = nullptr;
+      w.cap = 0;
+    }
+    HIP_TRY(hipMalloc((void **)&w.rows, (2 * (size_t)height + 1) * sizeof(int64_t)));
+    w.cap = height;
+  }
+  if (!w.h_total) HIP_TRY(hipHostMalloc((void **)&w.h_total, sizeof(int64_t), hipHostMallocDefault));
+  int64_t *row_bytes = w.rows, *row_off = w.rows + w.cap, *total = w.rows + 2 * (int64_t)w.cap;
+  HIP_TRY(trh::launch_tga_sizes(rgb8, width, height, row_bytes, row_off, total, st));
+  HIP_TRY(hipMemcpyAsync(w.h_total, total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *size = *w.h_total;
+  if (*size > capacity)
+    return fail(TR_EINVAL, "Targa file needs %lld bytes, the buffer holds %lld", (long long)*size,
+                (long long)capacity);
+  HIP_TRY(trh::launch_tga_write(rgb8, width, height, row_off, total, out, st));
+  return TR_OK;
+}
+
 extern "C" size_t tr_frame_footprint(const tr_camera *c, const tr_params *p, uint32_t flags) {
   if (!c || c->width <= 0 || c->height <= 0) return 0;
   (void)p;

@@ -82,6 +82,14 @@ hipError_t launch_bvh(const BuildArgs &a, const double lo[3], const double hi[3]
 // ---- frame output (frame_out.hip) ----
 // values -> bytes, floor(clamp(v, 0, 1) * 255 + 1/2); any alignment
 hipError_t launch_quantize_rgb8(const float *in, int64_t n, uint8_t *out, hipStream_t st);
+// Run-length Targa file of an 8-bit RGB image [H][W][3] (1 <= W, H <= 65535):
+// sizes computes row_bytes[H], row_off[H] (absolute file offsets of the rows)
+// and *total (the file size); write then fills out[0, *total), which must
+// hold *total bytes.
+hipError_t launch_tga_sizes(const uint8_t *rgb, int32_t W, int32_t H, int64_t *row_bytes,
+                            int64_t *row_off, int64_t *total, hipStream_t st);
+hipError_t launch_tga_write(const uint8_t *rgb, int32_t W, int32_t H, const int64_t *row_off,
+                            const int64_t *total, uint8_t *out, hipStream_t st);
 // rgb[i] = (rgb[i] + planes[0][i] + ... + planes[n_planes - 1][i]) / (n_planes + 1),
 // summed in that order; planes are n floats apart
 hipError_t launch_aa_mean(float *rgb, const float *planes, int32_t n_planes, int64_t n,

@@ -50,6 +50,26 @@ def test_tile_count(tr):
         tr.tile_count(10, 10, 7)
 
 
+def test_tga_bound_and_argument_errors(tr):
+    # host-only: the size bound, and the checks that precede any device work
+    import ctypes as C
+    assert tr.tga_max_bytes(1, 1) == 44 + 4
+    assert tr.tga_max_bytes(3860, 4548) == 44 + 4 * 3860 * 4548
+    assert tr.tga_max_bytes(65535, 65535) == 44 + 4 * 65535 * 65535
+    for w, h in ((0, 1), (1, 0), (65536, 1), (1, 65536), (-5, 3)):
+        assert tr.lib().tr_tga_max_bytes(w, h) == -1
+    L = tr.lib()
+    n = C.c_int64(123)
+    assert L.tr_frame_encode_tga(None, 4, 4, None, 0, C.byref(n), None) == -1  # NULL image
+    assert n.value == 0
+    assert L.tr_frame_encode_tga(None, 4, 4, None, 0, None, None) == -1       # NULL size
+    buf = (C.c_uint8 * 16)()
+    for w, h in ((0, 4), (4, 0), (65536, 1)):
+        assert L.tr_frame_encode_tga(C.addressof(buf), w, h, None, 0, C.byref(n), None) == -1
+    assert L.tr_frame_encode_tga(C.addressof(buf), 1, 1, None, 8, C.byref(n), None) == -1  # NULL out
+    assert L.tr_frame_encode_tga(C.addressof(buf), 1, 1, C.addressof(buf), -1, C.byref(n), None) == -1
+
+
 def test_frame_footprint(tr):
     import scenegen
     c = scenegen.protein_camera(scenegen.RES_17MP)

@@ -1,6 +1,9 @@
 """GPU 8-bit frame output (tr_frame_quantize) against the oracle, bit for bit:
 ragged sizes, unaligned buffers, edge values, a rendered frame, the full
-17.6 MP frame size, and the host download + PPM encoding."""
+17.6 MP frame size, and the host download + PPM encoding; the GPU Targa
+writer (tr_frame_encode_tga) against the oracle's, byte for byte, on images
+of every run structure and size limit and on rendered 1.1 MP and 17.6 MP
+frames."""
 import numpy as np
 import pytest
 
@@ -79,3 +82,84 @@ def test_quantize_full_frame_and_rendered(tr, oracle_mod):
     ppm = tr.encode_ppm(host)
     head = b"P6\n%d %d\n255\n" % (c.width, c.height)
     assert ppm[:len(head)] == head and ppm[len(head):] == want.tobytes()
+
+
+# ---- Targa file (tr_frame_encode_tga) against the oracle's writer, byte for byte
+
+def _tga_images():
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_oracle_tga import _random_image
+    rng = np.random.default_rng(77)
+    out = []
+    for h, w in ((1, 1), (1, 2), (2, 3), (3, 63), (2, 64), (2, 65), (4, 127), (3, 128), (3, 129),
+                 (5, 300), (9, 1000), (1, 65535), (65535, 1), (64, 4097)):
+        out.append(("runs", h, w, _random_image(rng, h, w)))
+        out.append(("noise", h, w, rng.integers(0, 256, (h, w, 3), dtype=np.uint8)))
+        out.append(("flat", h, w, np.full((h, w, 3), 17, np.uint8)))
+    return out
+
+
+def test_tga_bit_exact(tr, oracle_mod):
+    import torch
+    for kind, h, w, img in _tga_images():
+        print("tga case", kind, h, w, flush=True)
+        got = tr.encode_tga(torch.from_numpy(img).cuda())
+        torch.cuda.synchronize()
+        want = oracle_mod.tga_encode(img)
+        assert got.numel() == len(want), (kind, h, w)
+        assert got.cpu().numpy().tobytes() == want, (kind, h, w)
+
+
+def test_tga_rendered_frames(tr, oracle_mod):
+    # the full path: render, quantise, encode, all on the GPU; the oracle
+    # encodes the same 8-bit image; an independent decoder reads the file
+    import io
+
+    import torch
+    from PIL import Image
+    s = scenegen.protein_scene()
+    gs = tr.Scene(s)
+    for res in (scenegen.RES_1MP, scenegen.RES_17MP):
+        cam = scenegen.protein_camera(res)
+        print("tga frame", res, flush=True)
+        fr = tr.render(gs, cam, scenegen.Params(ao_samples=16, seed=2), outputs=("rgb",))
+        q = tr.quantize_rgb8(fr["rgb"])
+        f = tr.encode_tga(q)
+        torch.cuda.synchronize()
+        img = q.cpu().numpy()
+        data = f.cpu().numpy().tobytes()
+        assert data == oracle_mod.tga_encode(img)
+        assert len(data) < img.size  # the background compresses
+        if res == scenegen.RES_1MP:
+            assert np.array_equal(np.asarray(Image.open(io.BytesIO(data))), img)
+
+
+def test_tga_errors_and_reuse(tr, oracle_mod):
+    import torch
+    img = np.zeros((4, 300, 3), np.uint8)
+    img[:, ::2] = 200
+    d = torch.from_numpy(img).cuda()
+    want = oracle_mod.tga_encode(img)
+    small = torch.empty(len(want) - 1, dtype=torch.uint8, device="cuda").fill_(9)
+    with pytest.raises(tr.TRError) as e:
+        tr.encode_tga(d, out=small)
+    assert e.value.status == -1
+    torch.cuda.synchronize()
+    assert bool((small == 9).all())  # nothing written
+    exact = torch.empty(len(want), dtype=torch.uint8, device="cuda")
+    assert tr.encode_tga(d, out=exact).cpu().numpy().tobytes() == want
+    with pytest.raises(ValueError):
+        tr.tga_max_bytes(65536, 1)
+    wide = torch.zeros((1, 65536, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):  # no buffer size exists for it
+        tr.encode_tga(wide)
+    with pytest.raises(tr.TRError) as e:  # the library refuses it too
+        tr.encode_tga(wide, out=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    assert e.value.status == -1
+    # the per-stream scratch grows and shrinks across calls on one stream
+    for h in (3, 700, 2):
+        im = np.random.default_rng(h).integers(0, 3, (h, 50, 3), dtype=np.uint8) * 100
+        assert tr.encode_tga(torch.from_numpy(im).cuda()).cpu().numpy().tobytes() == \
+            oracle_mod.tga_encode(im)
