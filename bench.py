@@ -192,7 +192,9 @@ def scene_ingest_measure(tr, torch, scene, name: str) -> dict:
 def frame_output_measure(tr, torch, frame, reps: int = 20) -> dict:
     """8-bit output of the 17.6 MP frame on the GPU (tr_frame_quantize: 12 B
     read + 3 B written per pixel, HBM-bound), its asynchronous download to
-    pinned host memory, and the host PPM encoding."""
+    pinned host memory, the host PPM encoding, and the run-length Targa file
+    written on the GPU (tr_frame_encode_tga, wall time per call including its
+    wait for the size pass) with the download of the file."""
     rgb = frame["rgb"]
     q = tr.quantize_rgb8(rgb)
     torch.cuda.synchronize()
@@ -216,10 +218,28 @@ def frame_output_measure(tr, torch, frame, reps: int = 20) -> dict:
     t0 = time.perf_counter()
     ppm = tr.encode_ppm(host)
     enc_ms = (time.perf_counter() - t0) * 1e3
+    # Targa file on the GPU, then its download
+    H, W = int(q.shape[0]), int(q.shape[1])
+    buf = torch.empty(tr.tga_max_bytes(W, H), dtype=torch.uint8, device=q.device)
+    tga = tr.encode_tga(q, out=buf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        tga = tr.encode_tga(q, out=buf)
+    torch.cuda.synchronize()
+    tga_ms = (time.perf_counter() - t0) * 1e3 / reps
+    tga_host = torch.empty(tga.numel(), dtype=torch.uint8, pin_memory=True)
+    d0.record()
+    tga_host.copy_(tga, non_blocking=True)
+    d1.record()
+    torch.cuda.synchronize()
+    tga_d2h_ms = d0.elapsed_time(d1)
     return {"quantize_ms": ms, "quantize_GBps": nbytes / (ms * 1e-3) / 1e9,
             "quantize_hbm_frac": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "bytes": nbytes, "d2h_ms": d2h_ms, "d2h_GBps": q.numel() / (d2h_ms * 1e-3) / 1e9,
-            "ppm_encode_ms": enc_ms, "ppm_bytes": len(ppm)}
+            "ppm_encode_ms": enc_ms, "ppm_bytes": len(ppm),
+            "tga_encode_ms": tga_ms, "tga_bytes": int(tga.numel()),
+            "tga_ratio": tga.numel() / float(q.numel()), "tga_d2h_ms": tga_d2h_ms}
 
 
 def variant_measure(tr, torch, gs, cam, p, prec, workload: str, frames: int = 3) -> dict:
