@@ -72,18 +72,23 @@ __global__ __launch_bounds__(kThreads) void k_aa_mean(float *rgb, const float *p
 }
 
 // ---- Targa file, run-length true colour (the packet rule is written out
-// with the host-side declaration).  One wave per image row, one pixel per
-// lane, 64 pixels per step.  A pixel's role follows from its neighbours
-// alone: it belongs to a run when it equals a neighbour; a segment (a
-// maximal run of one colour, or a maximal stretch of pixels in no run)
-// starts where the role changes or a run changes colour; packets are the
-// 128-pixel pieces of segments.  A run packet's 4 bytes belong to its last
-// pixel, a raw packet's header byte to its first, so a pixel's byte position
-// is the exclusive prefix sum of these sizes along the row.  Pass 1 sums
-// each row, a scan turns the sums into row offsets, pass 2 recomputes the
-// roles and writes.  The file is 18 header bytes, the rows, 26 footer bytes.
+// with the host-side declaration).  One wave per image row; each lane takes
+// kTgaPx adjacent pixels, so a step covers 64 * kTgaPx pixels and issues all
+// its byte loads at once.  A pixel's role follows from its neighbours alone:
+// it belongs to a run when it equals a neighbour; a segment (a maximal run
+// of one colour, or a maximal stretch of pixels in no run) starts where the
+// role changes or a run changes colour; packets are the 128-pixel pieces of
+// segments.  A pixel's segment starts at the last start at or before it: in
+// its own lane, else the last one of the lower lanes (a max scan), else the
+// segment still open from the previous step.  A run packet's 4 bytes belong
+// to its last pixel, a raw packet's header byte to its first, so a pixel's
+// byte position is the exclusive prefix sum of these sizes along the row.
+// Pass 1 sums each row, a scan turns the sums into row offsets, pass 2
+// recomputes the roles and writes.  The file is 18 header bytes, the rows,
+// 26 footer bytes.
 
 constexpr int kTgaHead = 18, kTgaFoot = 26;
+constexpr int kTgaPx = 8;  // pixels per lane per step
 __constant__ char kTgaSig[18] = "TRUEVISION-XFILE.";  // footer signature (with its zero)
 
 __device__ __forceinline__ uint32_t px3(const uint8_t *row, int32_t x) {
@@ -102,57 +107,89 @@ __global__ __launch_bounds__(64) void k_tga_rows(const uint8_t *__restrict__ rgb
   const int64_t base = WRITE ? row_off[y] : 0;
   int64_t done = 0;      // bytes of the row before this step's pixels
   int32_t open_seg = 0;  // first pixel of the segment still open at the step's start
-  for (int32_t x0 = 0; x0 < W; x0 += 64) {
-    const int32_t x = x0 + lane;
-    const bool valid = x < W;
-    uint32_t p0 = 0;
-    bool run = false, start = false, end = false;
-    if (valid) {
-      const bool has_l = x > 0, has_l2 = x > 1, has_r = x + 1 < W, has_r2 = x + 2 < W;
-      p0 = px3(row, x);
-      const uint32_t pl = has_l ? px3(row, x - 1) : 0u, pl2 = has_l2 ? px3(row, x - 2) : 0u;
-      const uint32_t pr = has_r ? px3(row, x + 1) : 0u, pr2 = has_r2 ? px3(row, x + 2) : 0u;
-      const bool eq_l = has_l && p0 == pl, eq_r = has_r && p0 == pr;
-      run = eq_l || eq_r;
-      const bool run_l = has_l && (eq_l || (has_l2 && pl == pl2));  // pixel x - 1 in a run
-      const bool run_r = has_r && (eq_r || (has_r2 && pr == pr2));  // pixel x + 1 in a run
-      start = !has_l || run != run_l || (run && !eq_l);
-      end = !has_r || run != run_r || (run_r && !eq_r);  // pixel x + 1 starts a segment
+  for (int32_t x0 = 0; x0 < W; x0 += 64 * kTgaPx) {
+    const int32_t xb = x0 + kTgaPx * lane;  // this lane's first pixel
+    // the lane's pixels and two neighbours on each side
+    uint32_t w[kTgaPx + 4];
+    bool has[kTgaPx + 4];
+#pragma unroll
+    for (int k = 0; k < kTgaPx + 4; ++k) {
+      const int32_t x = xb - 2 + k;
+      has[k] = x >= 0 && x < W;
+      w[k] = has[k] ? px3(row, x) : 0u;
     }
-    const uint64_t sm = __ballot(start);
-    const uint64_t upto = lane == 63 ? sm : (sm & ((1ull << (lane + 1)) - 1ull));
-    const int32_t seg = upto ? x0 + 63 - (int32_t)__clzll(upto) : open_seg;
-    const int32_t kk = (x - seg) & 127;  // position in its packet
-    const bool first = kk == 0, last = kk == 127 || end;
-    const int32_t bytes = !valid ? 0 : (run ? (last ? 4 : 0) : (first ? 4 : 3));
-    int32_t incl = bytes;
+    bool run[kTgaPx], start[kTgaPx], end[kTgaPx];
+    int32_t last_start = -1;
+#pragma unroll
+    for (int j = 0; j < kTgaPx; ++j) {
+      const bool valid = has[j + 2];
+      const bool eq_l = valid && has[j + 1] && w[j + 2] == w[j + 1];
+      const bool eq_r = valid && has[j + 3] && w[j + 2] == w[j + 3];
+      run[j] = eq_l || eq_r;
+      const bool run_l = has[j + 1] && (eq_l || (has[j] && w[j + 1] == w[j]));  // pixel before
+      const bool run_r = has[j + 3] && (eq_r || (has[j + 4] && w[j + 3] == w[j + 4]));  // after
+      start[j] = valid && (!has[j + 1] || run[j] != run_l || (run[j] && !eq_l));
+      end[j] = valid && (!has[j + 3] || run[j] != run_r || (run_r && !eq_r));  // next one starts
+      if (start[j]) last_start = xb + j;
+    }
+    // last segment start of the lanes below (exclusive max scan) and of the wave
+    int32_t m = last_start;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t v = __shfl_up(m, d);
+      if (lane >= d) m = max(m, v);
+    }
+    int32_t below = __shfl_up(m, 1);
+    if (lane == 0) below = -1;
+    const int32_t wave_last = __shfl(m, 63);
+    const int32_t seg_before = below >= 0 ? below : open_seg;
+    int32_t kk[kTgaPx], bytes[kTgaPx];
+    int32_t seg_in = -1, lane_sum = 0;
+#pragma unroll
+    for (int j = 0; j < kTgaPx; ++j) {
+      if (start[j]) seg_in = xb + j;
+      const int32_t seg = seg_in >= 0 ? seg_in : seg_before;
+      kk[j] = (xb + j - seg) & 127;  // position in its packet
+      const bool first = kk[j] == 0, last = kk[j] == 127 || end[j];
+      bytes[j] = !has[j + 2] ? 0 : (run[j] ? (last ? 4 : 0) : (first ? 4 : 3));
+      lane_sum += bytes[j];
+    }
+    int32_t incl = lane_sum;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const int32_t v = __shfl_up(incl, d);
       if (lane >= d) incl += v;
     }
-    if (WRITE && valid) {
-      const int64_t pos = base + done + (incl - bytes);
-      const uint8_t r = (uint8_t)(p0 & 255u), g = (uint8_t)((p0 >> 8) & 255u),
-                    b = (uint8_t)(p0 >> 16);
-      if (run) {
-        if (last) {
-          out[pos] = (uint8_t)(0x80 | kk);
-          out[pos + 1] = b;
-          out[pos + 2] = g;
-          out[pos + 3] = r;
+    if (WRITE) {
+      int64_t pos = base + done + (incl - lane_sum);
+#pragma unroll
+      for (int j = 0; j < kTgaPx; ++j) {
+        if (has[j + 2]) {
+          const uint32_t p0 = w[j + 2];
+          const uint8_t r = (uint8_t)(p0 & 255u), g = (uint8_t)((p0 >> 8) & 255u),
+                        b = (uint8_t)(p0 >> 16);
+          const bool first = kk[j] == 0, last = kk[j] == 127 || end[j];
+          if (run[j]) {
+            if (last) {
+              out[pos] = (uint8_t)(0x80 | kk[j]);
+              out[pos + 1] = b;
+              out[pos + 2] = g;
+              out[pos + 3] = r;
+            }
+          } else {
+            const int64_t q = pos + (first ? 1 : 0);
+            out[q] = b;
+            out[q + 1] = g;
+            out[q + 2] = r;
+            // the header sits before the packet's first pixel: 1 + 3 kk bytes back
+            if (last) out[first ? pos : pos - 1 - 3 * (int64_t)kk[j]] = (uint8_t)kk[j];
+          }
         }
-      } else {
-        const int64_t q = pos + (first ? 1 : 0);
-        out[q] = b;
-        out[q + 1] = g;
-        out[q + 2] = r;
-        // the header sits before the packet's first pixel: 1 + 3 kk bytes back
-        if (last) out[first ? pos : pos - 1 - 3 * (int64_t)kk] = (uint8_t)kk;
+        pos += bytes[j];
       }
     }
     done += __shfl(incl, 63);
-    if (sm) open_seg = x0 + 63 - (int32_t)__clzll(sm);
+    if (wave_last >= 0) open_seg = wave_last;
   }
   if (!WRITE && lane == 0) row_bytes[y] = done;
 }
