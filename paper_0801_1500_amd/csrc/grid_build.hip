@@ -475,22 +475,70 @@ __global__ void k_bvh_morton(const trh::BuildArgs a, int64_t n, double lx, doubl
   vals[k] = (uint32_t)k;
 }
 
-// One pass of a stable LSD radix sort on one bit: zeros keep their order in
-// front, ones keep theirs behind.  zpos = exclusive scan of the zero flags.
-__global__ void k_bvh_zero_flags(const uint32_t *keys, int64_t n, int bit, uint32_t *flags) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flags[i] = ((keys[i] >> bit) & 1u) ? 0u : 1u;
-  else if (i == n) flags[i] = 0u;
+// Stable LSD radix sort of the codes (with their primitive ids), 8 bits a
+// pass.  A block takes a tile of 1024 keys in four chunks of 256.  Pass
+// structure: count each digit per tile, scan the digit-major count table (so
+// a tile's slot for digit d follows every smaller digit and every earlier
+// tile's d), then scatter: a key's place is its tile's slot for its digit,
+// plus the keys of that digit in earlier chunks, in lower waves of its chunk
+// (per-wave counts in LDS) and in lower lanes of its wave (the lanes whose
+// digit matches, from 8 ballots).
+constexpr int kRadixTile = 1024;
+
+__global__ __launch_bounds__(256) void k_radix_count(const uint32_t *keys, int64_t n, int shift,
+                                                     int64_t nb, uint32_t *cnt) {
+  __shared__ uint32_t hist[256];
+  const int t = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  hist[t] = 0u;
+  __syncthreads();
+  for (int c = 0; c < 4; ++c) {
+    const int64_t i = b * kRadixTile + c * 256 + t;
+    if (i < n) atomicAdd(&hist[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  cnt[(int64_t)t * nb + b] = hist[t];
+  if (b == 0 && t == 0) cnt[256 * nb] = 0u;
 }
 
-__global__ void k_bvh_split(const uint32_t *keys, const uint32_t *vals, int64_t n, int bit,
-                            const uint32_t *zpos, uint32_t *keys2, uint32_t *vals2) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t z = zpos[i];
-  const uint32_t dst = ((keys[i] >> bit) & 1u) ? zpos[n] + (uint32_t)i - z : z;
-  keys2[dst] = keys[i];
-  vals2[dst] = vals[i];
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *keys, const uint32_t *vals,
+                                                       int64_t n, int shift, int64_t nb,
+                                                       const uint32_t *off, uint32_t *keys2,
+                                                       uint32_t *vals2) {
+  __shared__ uint32_t run[256];      // next place of each digit in this tile
+  __shared__ uint32_t wcnt[4][256];  // keys of each digit in each wave of the chunk
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t b = blockIdx.x;
+  run[t] = off[(int64_t)t * nb + b];
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wcnt[q][t] = 0u;
+    __syncthreads();
+    const int64_t i = b * kRadixTile + c * 256 + t;
+    const bool valid = i < n;
+    const uint32_t key = valid ? keys[i] : 0u;
+    const uint32_t d = (key >> shift) & 255u;
+    uint64_t m = __ballot(valid);  // valid lanes with the same digit
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const uint64_t bb = __ballot((d >> bit) & 1u);
+      m &= ((d >> bit) & 1u) ? bb : ~bb;
+    }
+    const uint64_t below = m & ((1ull << lane) - 1ull);
+    if (valid && below == 0) wcnt[w][d] = (uint32_t)__popcll(m);  // the digit's lowest lane
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + (uint32_t)__popcll(below);
+      for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+      if ((int64_t)pos < n) {
+        keys2[pos] = key;
+        vals2[pos] = vals[i];
+      }
+    }
+    __syncthreads();
+    run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+    __syncthreads();
+  }
 }
 
 // Child encoding: c >= 0 internal node c; c < 0 leaf at sorted position -c - 1.
@@ -532,7 +580,7 @@ __global__ void k_bvh_internal(const uint32_t *keys, int64_t n, int32_t *left, i
 }
 
 // Box of a child: a leaf's primitive box widened by margin, or the stored
-// box of an internal node (read past the L1 cache: another thread wrote it).
+// box of an internal node (written by an earlier launch).
 __device__ __forceinline__ void child_box(const trh::BuildArgs &a, const uint32_t *vals,
                                           const double *ibox, int32_t c, double margin,
                                           double lo[3], double hi[3]) {
@@ -544,7 +592,7 @@ __device__ __forceinline__ void child_box(const trh::BuildArgs &a, const uint32_
       hi[q] += margin;
     }
   } else {
-    const volatile double *b = ibox + 6 * (int64_t)c;
+    const double *b = ibox + 6 * (int64_t)c;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       lo[q] = b[q];
@@ -553,33 +601,52 @@ __device__ __forceinline__ void child_box(const trh::BuildArgs &a, const uint32_
   }
 }
 
-// Boxes bottom-up: each leaf climbs towards the root; at every node the
-// first of the two arriving threads stops and the second, which then knows
-// both children's boxes, stores their union and climbs on.
-__global__ void k_bvh_bounds(const trh::BuildArgs a, const uint32_t *vals, int64_t n,
-                             const int32_t *left, const int32_t *right, const int32_t *parent_i,
-                             const int32_t *parent_l, uint32_t *arrivals, double *ibox,
-                             int32_t *height, double margin) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
-  int32_t p = parent_l[q];
-  for (int64_t guard = 0; p >= 0 && guard < n; ++guard) {
-    __threadfence();
-    if (atomicAdd(&arrivals[p], 1u) == 0u) return;
-    __threadfence();
-    double l0[3], h0[3], l1[3], h1[3];
-    child_box(a, vals, ibox, left[p], margin, l0, h0);
-    child_box(a, vals, ibox, right[p], margin, l1, h1);
-    volatile double *b = ibox + 6 * (int64_t)p;
+// Depth of every internal node (links from the root), by pointer jumping
+// over the parent links: after r rounds each node has summed 2^r links of its
+// path (the root links to itself with 0).  A path's split lengths rise
+// strictly through at most 62 values (30 code bits, then position bits), so
+// depths stay below 64 and 6 rounds give them exactly.  Links are clamped to
+// the node range.
+__global__ void k_bvh_depth_init(const int32_t *parent_i, int64_t m, int32_t *dep, int32_t *nxt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t p = i ? parent_i[i] : 0;
+  dep[i] = i ? 1 : 0;
+  nxt[i] = (uint32_t)p < (uint32_t)m ? p : 0;
+}
+
+__global__ void k_bvh_depth_jump(const int32_t *dep, const int32_t *nxt, int64_t m, int32_t *dep2,
+                                 int32_t *nxt2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t j = nxt[i];
+  dep2[i] = dep[i] + dep[j];
+  nxt2[i] = nxt[j];
+}
+
+__global__ void k_bvh_depth_max(const int32_t *dep, int64_t m, uint32_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t v = i < m ? dep[i] : 0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      b[k] = l0[k] < l1[k] ? l0[k] : l1[k];
-      b[3 + k] = h0[k] > h1[k] ? h0[k] : h1[k];
-    }
-    const volatile int32_t *hv = height;
-    const int32_t hl = left[p] >= 0 ? hv[left[p]] : 0, hr = right[p] >= 0 ? hv[right[p]] : 0;
-    ((volatile int32_t *)height)[p] = 1 + (hl > hr ? hl : hr);
-    p = parent_i[p];
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (uint32_t)v);
+}
+
+// Boxes of the internal nodes at depth d: the union of their children's
+// boxes (a deeper level's, stored by the previous launch, or a leaf's).
+__global__ void k_bvh_level(const trh::BuildArgs a, const uint32_t *vals, int64_t m,
+                            const int32_t *dep, int32_t d, const int32_t *left,
+                            const int32_t *right, double *ibox, double margin) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m || dep[i] != d) return;
+  double l0[3], h0[3], l1[3], h1[3];
+  child_box(a, vals, ibox, left[i], margin, l0, h0);
+  child_box(a, vals, ibox, right[i], margin, l1, h1);
+  double *b = ibox + 6 * i;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    b[k] = l0[k] < l1[k] ? l0[k] : l1[k];
+    b[3 + k] = h0[k] > h1[k] ? h0[k] : h1[k];
   }
 }
 
@@ -698,34 +765,60 @@ hipError_t launch_scatter(const BuildArgs &a, const uint32_t *cell_begin, uint32
   return hipGetLastError();
 }
 
-hipError_t launch_bvh(const BuildArgs &a, const double lo[3], const double hi[3], double margin,
-                      const double origin[3], BvhScratch &w, float4 *nodes, hipStream_t st) {
+int64_t bvh_sort_counts(int64_t n) { return 256 * ((n + kRadixTile - 1) / kRadixTile) + 1; }
+
+hipError_t launch_bvh_tree(const BuildArgs &a, const double lo[3], const double hi[3],
+                           BvhScratch &w, hipStream_t st) {
   const int64_t n = (int64_t)a.n_s + a.n_c + a.n_t;
   if (n < 2) return hipSuccess;
-  const unsigned nb = blocks_for(n), nb1 = blocks_for(n + 1);
+  const unsigned nb = blocks_for(n);
   double sc[3];
   for (int q = 0; q < 3; ++q) sc[q] = hi[q] > lo[q] ? 1024.0 / (hi[q] - lo[q]) : 0.0;
   k_bvh_morton<<<nb, kBlock, 0, st>>>(a, n, lo[0], lo[1], lo[2], sc[0], sc[1], sc[2], w.keys, w.vals);
   uint32_t *k0 = w.keys, *v0 = w.vals, *k1 = w.keys2, *v1 = w.vals2;
-  for (int bit = 0; bit < 30; ++bit) {
-    k_bvh_zero_flags<<<nb1, kBlock, 0, st>>>(k0, n, bit, w.flags);
-    hipError_t e = launch_scan(w.flags, n + 1, w.scan_scratch, st);
+  const int64_t tiles = (n + kRadixTile - 1) / kRadixTile;
+  for (int shift = 0; shift < 30; shift += 8) {
+    k_radix_count<<<(unsigned)tiles, 256, 0, st>>>(k0, n, shift, tiles, w.flags);
+    hipError_t e = launch_scan(w.flags, 256 * tiles + 1, w.scan_scratch, st);
     if (e != hipSuccess) return e;
-    k_bvh_split<<<nb, kBlock, 0, st>>>(k0, v0, n, bit, w.flags, k1, v1);
+    k_radix_scatter<<<(unsigned)tiles, 256, 0, st>>>(k0, v0, n, shift, tiles, w.flags, k1, v1);
     uint32_t *tk = k0, *tv = v0;
     k0 = k1;
     v0 = v1;
     k1 = tk;
     v1 = tv;
   }
-  // 30 passes: the sorted arrays are back in keys / vals
-  k_bvh_internal<<<blocks_for(n - 1), kBlock, 0, st>>>(k0, n, w.left, w.right, w.parent_i, w.parent_l);
-  hipError_t e = launch_fill_u32(w.arrivals, n - 1, 0u, st);
+  // 4 passes: the sorted arrays are back in keys / vals; keys2 / vals2 are free
+  const int64_t m = n - 1;
+  const unsigned nbm = blocks_for(m);
+  k_bvh_internal<<<nbm, kBlock, 0, st>>>(w.keys, n, w.left, w.right, w.parent_i, w.parent_l);
+  int32_t *dep = w.height, *nxt = (int32_t *)w.arrivals;
+  int32_t *dep2 = (int32_t *)w.keys2, *nxt2 = (int32_t *)w.vals2;
+  k_bvh_depth_init<<<nbm, kBlock, 0, st>>>(w.parent_i, m, dep, nxt);
+  for (int r = 0; r < 6; ++r) {  // even: the depths end in dep
+    k_bvh_depth_jump<<<nbm, kBlock, 0, st>>>(dep, nxt, m, dep2, nxt2);
+    int32_t *td = dep, *tn = nxt;
+    dep = dep2;
+    nxt = nxt2;
+    dep2 = td;
+    nxt2 = tn;
+  }
+  hipError_t e = launch_fill_u32(w.flags, 1, 0u, st);
   if (e != hipSuccess) return e;
-  k_bvh_bounds<<<nb, kBlock, 0, st>>>(a, v0, n, w.left, w.right, w.parent_i, w.parent_l, w.arrivals,
-                                      w.ibox, w.height, margin);
-  k_bvh_pack<<<blocks_for(n - 1), kBlock, 0, st>>>(a, v0, n, w.left, w.right, w.ibox, margin,
-                                                   origin[0], origin[1], origin[2], nodes);
+  k_bvh_depth_max<<<nbm, kBlock, 0, st>>>(w.height, m, w.flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_bvh_boxes(const BuildArgs &a, const BvhScratch &w, int32_t max_depth,
+                            double margin, const double origin[3], float4 *nodes, hipStream_t st) {
+  const int64_t n = (int64_t)a.n_s + a.n_c + a.n_t;
+  if (n < 2) return hipSuccess;
+  const int64_t m = n - 1;
+  const unsigned nbm = blocks_for(m);
+  for (int32_t d = max_depth; d >= 0; --d)
+    k_bvh_level<<<nbm, kBlock, 0, st>>>(a, w.vals, m, w.height, d, w.left, w.right, w.ibox, margin);
+  k_bvh_pack<<<nbm, kBlock, 0, st>>>(a, w.vals, n, w.left, w.right, w.ibox, margin, origin[0],
+                                     origin[1], origin[2], nodes);
   return hipGetLastError();
 }
 

@@ -65,6 +65,7 @@ struct tr_scene {
   double4 *triA64 = nullptr, *triB64 = nullptr, *triC64 = nullptr;
   float4 *bvh_nodes = nullptr;  // linear BVH (tr_scene_build_bvh), 4 per internal node
   int64_t bvh_n = 0;            // primitives it covers (0 = not built)
+  int64_t bvh_cap = 0;          // internal-node records the buffer holds
   int32_t bvh_depth = 0;        // internal nodes on its longest root-to-leaf path
   float4 *triV32 = nullptr, *triE1_32 = nullptr, *triE2_32 = nullptr;
   uint32_t *cell_begin = nullptr, *refs = nullptr, *count = nullptr, *scan_scratch = nullptr;
@@ -506,36 +507,54 @@ extern "C" tr_status tr_scene_build_bvh(tr_scene *s, void *hip_stream) {
   // node records are addressed with 32-bit byte offsets (64 bytes per node)
   if (n >= ((int64_t)1 << 26)) return fail(TR_EUNSUPPORTED, "BVH needs fewer than 2^26 primitives");
   hipStream_t st = (hipStream_t)hip_stream;
-  if (s->bvh_nodes) {
-    HIP_TRY(hipStreamSynchronize(st));
+  // renders on any stream may still read the old records
+  if (s->bvh_nodes) HIP_TRY(hipDeviceSynchronize());
+  s->bvh_n = 0;
+  s->bvh_depth = 0;
+  const int64_t n_nodes = n >= 2 ? n - 1 : 0;
+  if (s->bvh_nodes && s->bvh_cap != n_nodes) {
     HIP_TRY(hipFree(s->bvh_nodes));
     s->bvh_nodes = nullptr;
-    s->bvh_n = 0;
-    s->bvh_depth = 0;
+    s->bvh_cap = 0;
   }
   int32_t depth = 0;
   if (n >= 2) {
-    HIP_TRY(dmalloc(&s->bvh_nodes, 4 * (n - 1)));
+    if (!s->bvh_nodes) {
+      HIP_TRY(dmalloc(&s->bvh_nodes, 4 * n_nodes));
+      s->bvh_cap = n_nodes;
+    }
+    // all scratch in one allocation, each array 256-byte aligned
     trh::BvhScratch w{};
-    std::vector<void *> tmp;
-    hipError_t e = hipSuccess;
-    auto get = [&](auto **p, int64_t cnt) {
-      if (e == hipSuccess) e = dmalloc(p, cnt);
-      if (e == hipSuccess) tmp.push_back((void *)*p);
+    size_t total = 0;
+    auto carve = [&](size_t bytes) {
+      const size_t at = total;
+      total += (bytes + 255) & ~(size_t)255;
+      return at;
     };
-    get(&w.keys, n);
-    get(&w.vals, n);
-    get(&w.keys2, n);
-    get(&w.vals2, n);
-    get(&w.parent_l, n);
-    get(&w.flags, n + 1);
-    get(&w.left, n - 1);
-    get(&w.right, n - 1);
-    get(&w.parent_i, n - 1);
-    get(&w.arrivals, n - 1);
-    get(&w.height, n - 1);
-    get(&w.ibox, 6 * (n - 1));
-    get(&w.scan_scratch, trh::scan_scratch_u32(n + 1));
+    const size_t o_keys = carve(4 * n), o_vals = carve(4 * n), o_keys2 = carve(4 * n),
+                 o_vals2 = carve(4 * n), o_pl = carve(4 * n),
+                 o_flags = carve(4 * (size_t)trh::bvh_sort_counts(n)),
+                 o_left = carve(4 * n_nodes), o_right = carve(4 * n_nodes),
+                 o_pi = carve(4 * n_nodes), o_arr = carve(4 * n_nodes), o_h = carve(4 * n_nodes),
+                 o_ibox = carve(48 * n_nodes),
+                 o_scan = carve(4 * (size_t)trh::scan_scratch_u32(trh::bvh_sort_counts(n)));
+    char *base = nullptr;
+    hipError_t e = hipMalloc((void **)&base, total);
+    if (e == hipSuccess) {
+      w.keys = (uint32_t *)(base + o_keys);
+      w.vals = (uint32_t *)(base + o_vals);
+      w.keys2 = (uint32_t *)(base + o_keys2);
+      w.vals2 = (uint32_t *)(base + o_vals2);
+      w.parent_l = (int32_t *)(base + o_pl);
+      w.flags = (uint32_t *)(base + o_flags);
+      w.left = (int32_t *)(base + o_left);
+      w.right = (int32_t *)(base + o_right);
+      w.parent_i = (int32_t *)(base + o_pi);
+      w.arrivals = (uint32_t *)(base + o_arr);
+      w.height = (int32_t *)(base + o_h);
+      w.ibox = (double *)(base + o_ibox);
+      w.scan_scratch = (uint32_t *)(base + o_scan);
+    }
     trh::BuildArgs a{};
     a.n_s = (int32_t)s->n_s;
     a.n_c = (int32_t)s->n_c;
@@ -546,14 +565,23 @@ extern "C" tr_status tr_scene_build_bvh(tr_scene *s, void *hip_stream) {
     a.triA64 = s->triA64;
     a.triB64 = s->triB64;
     a.triC64 = s->triC64;
-    if (e == hipSuccess) e = trh::launch_bvh(a, s->gp.lo, s->gp.hi, s->gp.delta, s->org, w, s->bvh_nodes, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(s->h_total, w.height, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    // hierarchy and node depths, then the boxes level by level (the host
+    // reads the largest depth in between), then the records
+    int32_t max_dep = -1;
+    if (e == hipSuccess) e = trh::launch_bvh_tree(a, s->gp.lo, s->gp.hi, w, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->h_total, w.flags, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e == hipSuccess) std::memcpy(&depth, s->h_total, sizeof(int32_t));
-    for (void *p : tmp) (void)hipFree(p);
+    if (e == hipSuccess) std::memcpy(&max_dep, s->h_total, sizeof(int32_t));
+    if (e == hipSuccess && (max_dep < 0 || max_dep > 63)) e = hipErrorUnknown;  // cannot happen
+    if (e == hipSuccess)
+      e = trh::launch_bvh_boxes(a, w, max_dep, s->gp.delta, s->org, s->bvh_nodes, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    depth = max_dep + 1;  // internal nodes on the longest root-to-leaf path
+    if (base) (void)hipFree(base);
     if (e != hipSuccess) {
       (void)hipFree(s->bvh_nodes);
       s->bvh_nodes = nullptr;
+      s->bvh_cap = 0;
       return fail(e == hipErrorOutOfMemory ? TR_ENOMEM : TR_EDEVICE, "BVH build: %s", hipGetErrorString(e));
     }
   }

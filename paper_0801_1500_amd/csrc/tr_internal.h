@@ -63,10 +63,13 @@ hipError_t launch_sort_cells(const uint32_t *cell_begin, int64_t n_cells, uint32
 
 // Linear BVH over all primitives (n >= 2): 4 float4 per internal node (see
 // k_bvh_pack); node 0 is the root.  Scratch sizes: keys, vals, keys2, vals2,
-// parent_l: n; flags: n + 1; left, right, parent_i, arrivals, height: n - 1;
-// ibox: 6 (n - 1) doubles; scan_scratch: scan_scratch_u32(n + 1).  height[i]
-// = internal nodes on the longest path from node i down to a leaf, so
-// height[0] is the tree's depth.
+// parent_l: n; flags (the sort's digit counts): bvh_sort_counts(n); left,
+// right, parent_i, arrivals, height: n - 1; ibox: 6 (n - 1) doubles;
+// scan_scratch: scan_scratch_u32(bvh_sort_counts(n)).
+// launch_bvh_tree sorts, builds the hierarchy and leaves each internal
+// node's depth (links from the root) in height[] and the largest depth in
+// flags[0]; launch_bvh_boxes then computes the boxes level by level from
+// that depth up and packs the records.
 struct BvhScratch {
   uint32_t *keys, *vals, *keys2, *vals2, *flags, *scan_scratch, *arrivals;
   int32_t *left, *right, *parent_i, *parent_l, *height;
@@ -76,8 +79,11 @@ struct BvhScratch {
 // node at depth d holds at most d deferred siblings, so a tree of depth
 // <= kBvhStack never overflows it; deeper trees are refused before launch.
 constexpr int kBvhStack = 48;
-hipError_t launch_bvh(const BuildArgs &a, const double lo[3], const double hi[3], double margin,
-                      const double origin[3], BvhScratch &w, float4 *nodes, hipStream_t st);
+int64_t bvh_sort_counts(int64_t n);
+hipError_t launch_bvh_tree(const BuildArgs &a, const double lo[3], const double hi[3],
+                           BvhScratch &w, hipStream_t st);
+hipError_t launch_bvh_boxes(const BuildArgs &a, const BvhScratch &w, int32_t max_depth,
+                            double margin, const double origin[3], float4 *nodes, hipStream_t st);
 
 // ---- frame output (frame_out.hip) ----
 // values -> bytes, floor(clamp(v, 0, 1) * 255 + 1/2); any alignment
