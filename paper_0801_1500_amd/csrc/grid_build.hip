@@ -624,12 +624,22 @@ __global__ void k_bvh_depth_jump(const int32_t *dep, const int32_t *nxt, int64_t
   nxt2[i] = nxt[j];
 }
 
-__global__ void k_bvh_depth_max(const int32_t *dep, int64_t m, uint32_t *out) {
+// Largest depth: a wave maximum, then the workgroup's in LDS, then one
+// atomic per workgroup (one per wave contends on the single word).
+__global__ __launch_bounds__(kBlock) void k_bvh_depth_max(const int32_t *dep, int64_t m,
+                                                          uint32_t *out) {
+  __shared__ int32_t wmax[kBlock / 64];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int32_t v = i < m ? dep[i] : 0;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, (uint32_t)v);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t b = wmax[0];
+    for (int k = 1; k < kBlock / 64; ++k) b = max(b, wmax[k]);
+    atomicMax(out, (uint32_t)b);
+  }
 }
 
 // Boxes of the internal nodes at depth d: the union of their children's
