@@ -75,10 +75,23 @@ def check_bvh(gs, s):
     return nodes
 
 
-@pytest.mark.parametrize("which", ["tiny", "protein", "mixed"])
+def _duplicates_scene():
+    # 3 x 1000 spheres on three points (equal Morton codes, split by their
+    # sorted position) plus 200 spread ones
+    rng = np.random.default_rng(12)
+    pts = np.repeat(np.array([[0.0, 0.0, 0.0], [4.0, 1.0, -2.0], [-3.0, 2.5, 1.0]]), 1000, axis=0)
+    c = np.concatenate([pts, rng.uniform(-12.0, 12.0, (200, 3))])
+    r = np.concatenate([np.full(3000, 1.0), rng.uniform(0.4, 1.2, 200)])
+    z3 = np.zeros((0, 3))
+    ld = np.array([[0.3, 0.4, 1.0]])
+    return scenegen.Scene(c, r, np.full((len(r), 3), 0.6, np.float32), z3, z3.copy(), np.zeros(0),
+                          np.zeros((0, 3), np.float32), ld, np.ones_like(ld))
+
+
+@pytest.mark.parametrize("which", ["tiny", "protein", "mixed", "duplicates"])
 def test_bvh_structure(tr, which):
     s = {"tiny": lambda: scenegen.tiny_scene(seed=1), "protein": scenegen.protein_scene,
-         "mixed": scenegen.mixed_tiny_scene}[which]()
+         "mixed": scenegen.mixed_tiny_scene, "duplicates": _duplicates_scene}[which]()
     print("bvh structure", which, flush=True)
     gs = tr.Scene(s)
     gs.build_bvh()
@@ -166,5 +179,22 @@ def test_bvh_one_and_two_primitives(tr, oracle_mod, n):
     assert (ref["hit_id"] >= 0).sum() > 200
     assert_fp32_parity(compare(got, ref, 8, s.n_lights))
     grid = _render(tr, gs, c, p, 0)
+    for k in OUT:
+        assert np.array_equal(grid[k], got[k]), k
+
+
+def test_bvh_duplicates_walk_equals_grid(tr):
+    # equal codes and equal spheres: the BVH walk finds the same nearest hits
+    # (ties to the lowest id) and occlusions as the grid walk
+    s = _duplicates_scene()
+    gs = tr.Scene(s)
+    gs.build_bvh()
+    assert 10 <= gs.bvh_depth() <= 48
+    c = scenegen.Camera((0.0, 5.0, 40.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 45.0, 96, 80)
+    p = scenegen.Params(ao_samples=8, seed=3)
+    print("bvh duplicates", flush=True)
+    got = _render(tr, gs, c, p, 1)
+    grid = _render(tr, gs, c, p, 0)
+    assert (grid["hit_id"] >= 0).sum() > 500
     for k in OUT:
         assert np.array_equal(grid[k], got[k]), k
