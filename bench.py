@@ -189,6 +189,46 @@ def scene_ingest_measure(tr, torch, scene, name: str) -> dict:
             "load_MBps": nbytes / (load_ms * 1e-3) / 1e6}
 
 
+def end_to_end_measure(tr, torch, scene, cam, params, prec, reps: int = 3) -> dict:
+    """One 17.6 MP frame from a scene file to an image file in host memory,
+    in the phases of Table 5: scene load (file read, upload and GPU grid
+    build: the paper's parse + preprocess), ray tracing, and image I/O
+    (8-bit conversion, Targa file on the GPU, download into pinned memory).
+    Each phase is timed to completion; the best of reps runs is kept."""
+    import tempfile
+    best = None
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "scene.trs")
+        tr.Scene(scene).save(path)
+        frame = tr.alloc_frame(cam, ("rgb",))
+        H, W = cam.height, cam.width
+        buf = torch.empty(tr.tga_max_bytes(W, H), dtype=torch.uint8, device="cuda")
+        host = torch.empty(tr.tga_max_bytes(W, H), dtype=torch.uint8, pin_memory=True)
+        for k in range(reps + 1):  # run 0 warms the caches and the allocator
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gs = tr.Scene.load(path)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            tr.render_into(gs, cam, params, frame, prec)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            q = tr.quantize_rgb8(frame["rgb"])
+            tga = tr.encode_tga(q, out=buf)
+            host[:tga.numel()].copy_(tga, non_blocking=True)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            run = {"scene_load_ms": (t1 - t0) * 1e3, "ray_tracing_ms": (t2 - t1) * 1e3,
+                   "image_io_ms": (t3 - t2) * 1e3, "total_ms": (t3 - t0) * 1e3,
+                   "image_bytes": int(tga.numel())}
+            del gs
+            if k > 0 and (best is None or run["total_ms"] < best["total_ms"]):
+                best = run
+    best["workload"] = ("protein-like 26,318 objects from a binary scene file to a Targa file in "
+                        "host memory, 3860x4548, 16 AO samples")
+    return best
+
+
 def frame_output_measure(tr, torch, frame, reps: int = 20) -> dict:
     """8-bit output of the 17.6 MP frame on the GPU (tr_frame_quantize: 12 B
     read + 3 B written per pixel, HBM-bound), its asynchronous download to
@@ -500,6 +540,8 @@ def main():
 
     frame_out = frame_output_measure(tr, torch, frame)
     log("frame output", frame_out)
+    e2e = end_to_end_measure(tr, torch, scene, cam, params, prec)
+    log("end to end", e2e)
     ingest = [scene_ingest_measure(tr, torch, scene, "protein-like 26,318 objects")]
     if not args.no_orbit:
         ingest.append(scene_ingest_measure(tr, torch, scenegen.orbit_scene(),
@@ -549,6 +591,7 @@ def main():
         "triangles": tris,
         "frame_output": frame_out,
         "scene_ingest": ingest,
+        "end_to_end": e2e,
         "orbit": orbit,
         "serving": serving,
         "roofline": roofline,
