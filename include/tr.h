@@ -338,8 +338,12 @@ tr_status tr_render_tuned(const tr_scene *scene, const tr_camera *cam, const tr_
 
 /* Render n frames in ONE persistent launch whose tile queue spans all n
  * jobs (scenes may differ; job i uses scenes[i], cams[i], params[i],
- * frames[i]).  All jobs must use an FP32 precision; TR_PREC_FP64 jobs are
- * rendered one launch each.  1 <= n <= 4096. */
+ * frames[i]).  The FP32 jobs share one launch: they must all use the first
+ * FP32 job's precision and its stats buffer (which may be NULL), and that
+ * job picks the launch shape.  TR_PREC_FP64 jobs are rendered one launch
+ * each.  Every job is checked before anything is enqueued: on an error
+ * nothing is rendered.  Each frame equals the same job rendered alone.
+ * 1 <= n <= 4096. */
 tr_status tr_render_batch(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,
                           const tr_params *params, const tr_frame *frames, void *hip_stream);
 

@@ -1268,15 +1268,18 @@ static tr_status batch_impl(int32_t n, const tr_scene *const *scenes, const tr_c
                             const int64_t *te, const tr_tune *tune, hipStream_t st) {
   if (n < 1 || n > 4096) return fail(TR_EINVAL, "batch size must be 1..4096");
   if (!scenes || !cams || !params || !frames) return fail(TR_EINVAL, "NULL batch array");
-  tr_tune t = pick_tune(scenes[0], &cams[0], &params[0], tune);
+  // the first FP32 job sets the batch's FP32 precision and its tuning
+  int32_t f0 = 0;
+  while (f0 < n - 1 && params[f0].precision == TR_PREC_FP64) ++f0;
+  tr_tune t = pick_tune(scenes[f0], &cams[f0], &params[f0], tune);
   tr_status rc = check_tune(t);
   if (rc != TR_OK) return rc;
-  const int res = params[0].precision == TR_PREC_FP32_RESOLVE;
+  const int res = params[f0].precision == TR_PREC_FP32_RESOLVE;
   std::vector<JobDev> jobs, f64;
   std::vector<int32_t> aa, aa64;
   std::vector<uint64_t *> stats64;
   jobs.reserve(n);
-  uint64_t *stats = frames[0].stats;
+  uint64_t *stats = frames[f0].stats;  // shared by the FP32 jobs
   // every job is checked before anything is enqueued: a failing batch
   // renders nothing
   for (int32_t i = 0; i < n; ++i) {

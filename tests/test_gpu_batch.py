@@ -188,3 +188,23 @@ def test_graph_bvh_cross_stream_and_refresh(tr, scenes):
         tr.Graph([plain], [c], [scenegen.Params(ao_samples=4)], [tr.alloc_frame(c, OUT)],
                  tune={"accel": 1})
     assert e.value.status == -1
+
+
+def test_mixed_precision_batch(tr, scenes):
+    # plain FP64 jobs (one launch each) and FP32 jobs (one wavefront launch)
+    # in one batch call, antialiased jobs among them: each frame equals the
+    # same job rendered alone
+    import torch
+    cams, params, which = _jobs()
+    params = list(params)
+    params[2] = scenegen.Params(**{**params[2].__dict__, "aa_samples": 3})
+    params[3] = scenegen.Params(**{**params[3].__dict__, "aa_samples": 2})
+    prec = ["fp64", "fp32_resolve", "fp64", "fp32_resolve"]
+    frames = [tr.alloc_frame(c, OUT) for c in cams]
+    print("mixed precision batch", flush=True)
+    tr.render_batch_into([scenes[w] for w in which], cams, params, frames, precision=prec)
+    torch.cuda.synchronize()
+    for i, (c, p, w) in enumerate(zip(cams, params, which)):
+        alone = frame_to_numpy(tr.render(scenes[w], c, p, precision=prec[i], outputs=OUT))
+        torch.cuda.synchronize()
+        _same(frame_to_numpy(frames[i]), alone, ("mixed", i))
