@@ -198,6 +198,9 @@ enum {
   TR_STAT_TRI_TESTS,
   TR_STAT_TRI_HITS,
   TR_STAT_STACK_OVERFLOWS,   /* BVH walk: children dropped on a full stack (0 unless the tree is too deep) */
+  TR_STAT_STALLS,            /* wavefront kernel: waves that left with work outstanding (an
+                                internal-error guard: always 0 unless the queue bookkeeping broke,
+                                and then the frame is incomplete) */
   TR_STAT_COUNT
 };
 

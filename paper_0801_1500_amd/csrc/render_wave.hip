@@ -337,6 +337,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
   int32_t cur_key = -1;   // scene loaded in this wave
   int32_t scene_job = 0;  // a job whose scene is the current one
   int32_t idle_rounds = 0;
+  bool stalled = false;  // left with work outstanding (reported in the stats)
 
   // ---- counters (wave-uniform)
   uint64_t c_rays = 0;
@@ -835,6 +836,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         if (!tiles_left && held_tile < 0 && bank_busy == 0 && q_head == q_tail) break;
         if (++idle_rounds > 4) {  // cannot happen when the bookkeeping is right
           if (lane == 0) atomicAdd(A.tile_counter + 1, 1u);
+          stalled = true;
           break;
         }
         continue;
@@ -1138,6 +1140,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       atomicAdd(&st[TR_STAT_AO_RAYS], (unsigned long long)L.cnt[2]);
       atomicAdd(&st[TR_STAT_SHADOW_RAYS], (unsigned long long)L.cnt[3]);
       atomicAdd(&st[TR_STAT_RAYS_TRACED], (unsigned long long)c_rays);
+      if (stalled) atomicAdd(&st[TR_STAT_STALLS], 1ull);
       if (COUNT) {
         atomicAdd(&st[TR_STAT_CELLS], (unsigned long long)L.cnt[4]);
         atomicAdd(&st[TR_STAT_SPH_TESTS], (unsigned long long)L.cnt[5]);

@@ -42,6 +42,19 @@ def test_every_declared_symbol_exported(tr):
     assert tr.abi_version() == 2
 
 
+def test_stat_names_follow_the_header(tr):
+    # the binding's stat names are the header's enum, in order
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "include", "tr.h")).read()
+    start = hdr.index("TR_STAT_PIXELS = 0")
+    body = hdr[start:hdr.index("TR_STAT_COUNT", start)]
+    names = re.findall(r"^\s*TR_STAT_([A-Z_]+)", body, re.M)
+    assert [n.lower() for n in names] == tr.STAT_NAMES
+    assert tr.STAT_COUNT == len(names)
+
+
 def test_tile_count(tr):
     assert tr.tile_count(128, 128) == 256
     assert tr.tile_count(3860, 4548, 8) == 483 * 569

@@ -121,7 +121,7 @@ def test_bvh_walk_matches_oracle_and_grid(tr, oracle_mod, which):
     print("bvh walk", which, flush=True)
     got = _render(tr, gs, c, p, 1)
     st = dict(zip(tr.STAT_NAMES, got["stats"].tolist()))
-    assert st["stack_overflows"] == 0
+    assert st["stack_overflows"] == 0 and st["stalls"] == 0
     ref = oracle_mod.render(s, c, p, grid=4.0)
     m = compare(got, ref, 8, s.n_lights)
     print(m)

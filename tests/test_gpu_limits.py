@@ -50,7 +50,7 @@ def test_largest_frame(tr, oracle_mod):
         tr.render_into(gs, c, p, fr, prec)
         torch.cuda.synchronize()
         st = dict(zip(tr.STAT_NAMES, fr["stats"].cpu().tolist()))
-        assert st["pixels"] == n, st
+        assert st["pixels"] == n and st["stalls"] == 0, st
         m = compare(_gather(torch, fr, idx), ref, 4, s.n_lights)
         print(m, flush=True)
         if prec == "fp64":

@@ -218,6 +218,7 @@ def test_stats_counts(tr, oracle_mod, protein):
         st = dict(zip(tr.STAT_NAMES, fr["stats"].cpu().tolist()))
         hits = int((fr["hit_id"] >= 0).sum().item())
         assert st["pixels"] == 200 * 150
+        assert st["stalls"] == 0
         assert st["hit_pixels"] == hits
         assert st["ao_rays"] == 16 * hits
         assert st["rays_traced"] == st["pixels"] + st["ao_rays"] + st["shadow_rays"]
