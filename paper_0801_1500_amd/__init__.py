@@ -460,6 +460,24 @@ def encode_tga(rgb8, out=None, stream=None):
     return out[:n.value]
 
 
+def write_tga(frame, path: str, stream=None) -> int:
+    """Write a rendered frame (a frame dict or its float rgb tensor) as a
+    run-length Targa file: 8-bit conversion and encoding on the GPU, then
+    the file's bytes are copied to host memory and written.  Returns the
+    file size in bytes."""
+    torch = _torch()
+    rgb = frame["rgb"] if isinstance(frame, dict) else frame
+    tga = encode_tga(quantize_rgb8(rgb, stream=stream), stream=stream)
+    host = torch.empty(tga.numel(), dtype=torch.uint8, pin_memory=True)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(s):
+        host.copy_(tga, non_blocking=True)
+    s.synchronize()
+    with open(path, "wb") as f:
+        f.write(host.numpy().tobytes())
+    return int(tga.numel())
+
+
 def tile_count(width: int, height: int, tile_w: int = 0) -> int:
     n = lib().tr_tile_count(int(width), int(height), int(tile_w))
     if n < 0:

@@ -163,3 +163,19 @@ def test_tga_errors_and_reuse(tr, oracle_mod):
         im = np.random.default_rng(h).integers(0, 3, (h, 50, 3), dtype=np.uint8) * 100
         assert tr.encode_tga(torch.from_numpy(im).cuda()).cpu().numpy().tobytes() == \
             oracle_mod.tga_encode(im)
+
+
+def test_write_tga_file(tr, oracle_mod, tmp_path):
+    # render -> Targa file on disk; an independent decoder reads it back as
+    # the 8-bit image of the frame
+    import torch
+    from PIL import Image
+    s, c, p = scenegen.tiny_workload()
+    fr = tr.render(tr.Scene(s), c, p, outputs=("rgb",))
+    path = str(tmp_path / "tiny.tga")
+    n = tr.write_tga(fr, path)
+    torch.cuda.synchronize()
+    q = tr.quantize_rgb8(fr["rgb"]).cpu().numpy()
+    data = open(path, "rb").read()
+    assert len(data) == n and data == oracle_mod.tga_encode(q)
+    assert np.array_equal(np.asarray(Image.open(path)), q)
