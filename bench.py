@@ -115,7 +115,8 @@ def cpu_baseline(scene, cam, params, target_s: float = 15.0) -> dict:
 
 def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
     """64 views of the 1,000,000-object walk scene at 1920x1080, 32 AO
-    samples, captured once into a hipGraph; time graph launches."""
+    samples, captured once into a hipGraph with the launch shape autotuned on
+    one view; time graph launches (and the same with the default shape)."""
     scene = scenegen.orbit_scene()
     gs = tr.Scene(scene)
     cams = scenegen.orbit_cameras()
@@ -124,20 +125,27 @@ def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
     stats = torch.zeros(tr.STAT_COUNT, dtype=torch.int64, device="cuda")
     for f in frames:
         f["stats"] = stats
-    g = tr.Graph([gs] * len(cams), cams, params, frames)
-    g.launch()
-    torch.cuda.synchronize()
-    stats.zero_()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(launches):
+
+    def time_graph(tune):
+        g = tr.Graph([gs] * len(cams), cams, params, frames, tune=tune)
         g.launch()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / launches
-    st = dict(zip(tr.STAT_NAMES, stats.cpu().tolist()))
+        torch.cuda.synchronize()
+        stats.zero_()
+        e0.record()
+        for _ in range(launches):
+            g.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        g.destroy()
+        return e0.elapsed_time(e1) / launches, dict(zip(tr.STAT_NAMES, stats.cpu().tolist()))
+
+    # the launch shape autotuned on one view (frames are bit-identical for
+    # every shape; the tuner checks it), against the default shape
+    tuned, _ = tr.autotune(gs, cams[0], params[0])
+    ms_default, _ = time_graph(tr.default_tune())
+    ms, st = time_graph(tuned)
     rays = (st["pixels"] + st["ao_rays"]) / launches
-    g.destroy()
     # the sparse scene with and without empty-space skipping: 8 views per batch
     sub = [tr.alloc_frame(c, ("rgb",), stats=False) for c in cams[:8]]
     walks = walk_compare(tr, torch, gs, lambda: tr.render_batch_into(
@@ -159,6 +167,7 @@ def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
     return {"workload": "1,000,000-object walk (ball radius 250), 64 views of 1920x1080 per "
                         "graph launch, 32 AO samples, FP32 + FP64 re-solve",
             "ms_per_launch": ms, "views_per_s": 64 * 1000.0 / ms, "rays_per_launch": rays,
+            "tune": tuned, "ms_per_launch_default_tune": ms_default,
             "rays_per_s": rays / (ms * 1e-3),
             "walk_8_views": walks, "bvh_8_views": bvh, "precision_8_views": prec}
 
