@@ -204,8 +204,10 @@ enum {
   TR_STAT_COUNT
 };
 
-/* Launch shape of the persistent-wavefront kernel.  Any valid choice gives
- * bit-identical frames; only speed changes.  Zero fields take defaults. */
+/* Launch shape of the persistent-wavefront kernel.  Any valid choice of the
+ * shape fields gives bit-identical frames; only speed changes.  accel picks
+ * the acceleration structure instead (see there).  Zero fields take
+ * defaults. */
 typedef struct {
   int32_t tile_w;            /* tile width in pixels: 4, 8, 16 or 32; tiles hold 64 pixels */
   int32_t banks;             /* pixel banks (tiles in flight) per wave: 2 or 3 (queue depth) */
@@ -217,8 +219,12 @@ typedef struct {
                                 when its lanes are >= mix/64 of the largest type's, 1..64 */
   int32_t accel;             /* 0 = walk the uniform grid; 1 = walk the scene's
                                 BVH (tr_scene_build_bvh first; FP32 precisions,
-                                opaque rendering, two banks).  Results do not
-                                depend on it. */
+                                opaque rendering, two banks).  Both walks meet
+                                the same FP32 bar against the FP64 reference;
+                                they test primitives in different orders, so a
+                                near-tie in FP32 can settle differently (tested:
+                                >= 99.99% of pixels with the same hit and masks,
+                                the same colour wherever they agree). */
 } tr_tune;
 
 /* ---------------------------------------------------------------- scenes */
