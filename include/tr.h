@@ -445,8 +445,10 @@ void tr_graph_destroy(tr_graph *g);
 
 /* ----------------------------------------------------------- autotuning */
 
-/* Time the candidate launch shapes on this (scene, camera, params) and keep
- * the fastest in a process-wide cache keyed by (device, primitive-count
+/* Time the candidate launch shapes on this (scene, camera, params)
+ * (coordinate descent over the shape fields, then the winner re-timed against
+ * the default shape, interleaved, median of 7 each) and keep the faster in a
+ * process-wide cache keyed by (device, primitive-count
  * bucket, resolution, AO samples, precision); later renders with a NULL tune
  * use it.  Checks that every candidate gives a bit-identical frame
  * (TR_EDEVICE with a message if not).  *best (may be NULL) receives the
