@@ -115,8 +115,9 @@ def cpu_baseline(scene, cam, params, target_s: float = 15.0) -> dict:
 
 def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
     """64 views of the 1,000,000-object walk scene at 1920x1080, 32 AO
-    samples, captured once into a hipGraph with the launch shape autotuned on
-    one view; time graph launches (and the same with the default shape)."""
+    samples, captured once into a hipGraph; time graph launches with the
+    default launch shape and with the shape autotuned on one view, and report
+    the faster."""
     scene = scenegen.orbit_scene()
     gs = tr.Scene(scene)
     cams = scenegen.orbit_cameras()
@@ -142,9 +143,15 @@ def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
 
     # the launch shape autotuned on one view (frames are bit-identical for
     # every shape; the tuner checks it), against the default shape
+    # The tuner decides on one view; the graph renders 64, so both graphs are
+    # timed and the faster one is the orbit's figure.
     tuned, _ = tr.autotune(gs, cams[0], params[0])
-    ms_default, _ = time_graph(tr.default_tune())
-    ms, st = time_graph(tuned)
+    ms_default, st_default = time_graph(tr.default_tune())
+    ms_tuned, st_tuned = time_graph(tuned)
+    if ms_tuned < ms_default:
+        ms, st, used = ms_tuned, st_tuned, tuned
+    else:
+        ms, st, used = ms_default, st_default, tr.default_tune()
     rays = (st["pixels"] + st["ao_rays"]) / launches
     # the sparse scene with and without empty-space skipping: 8 views per batch
     sub = [tr.alloc_frame(c, ("rgb",), stats=False) for c in cams[:8]]
@@ -167,7 +174,8 @@ def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
     return {"workload": "1,000,000-object walk (ball radius 250), 64 views of 1920x1080 per "
                         "graph launch, 32 AO samples, FP32 + FP64 re-solve",
             "ms_per_launch": ms, "views_per_s": 64 * 1000.0 / ms, "rays_per_launch": rays,
-            "tune": tuned, "ms_per_launch_default_tune": ms_default,
+            "tune": used, "tune_from_one_view": tuned, "ms_per_launch_default_tune": ms_default,
+            "ms_per_launch_one_view_tune": ms_tuned,
             "rays_per_s": rays / (ms * 1e-3),
             "walk_8_views": walks, "bvh_8_views": bvh, "precision_8_views": prec}
 
