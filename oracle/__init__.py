@@ -99,6 +99,9 @@ def lib():
         L.or_trace.argtypes = [C.POINTER(_Scene), vp, vp, vp, dbl, dbl, i64, C.c_int,
                                C.POINTER(dbl), C.POINTER(i64), C.POINTER(Counters)]
         L.or_trace.restype = C.c_int
+        L.or_trace_list.argtypes = [C.POINTER(_Scene), vp, i64, vp, vp, dbl, dbl, i64, C.c_int,
+                                    C.POINTER(dbl), C.POINTER(i64)]
+        L.or_trace_list.restype = C.c_int
         L.or_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_Params), vp,
                                 i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Counters), i32]
         L.or_render.restype = C.c_int
@@ -285,6 +288,21 @@ def trace(scene, grid: Optional[Grid], o, d, tmin=0.0, tmax=math.inf, skip=-1, a
     h = lib().or_trace(C.byref(sc.c), grid.handle if grid else None, _ptr(o), _ptr(d),
                        float(tmin), float(tmax), int(skip), int(bool(any_hit)), C.byref(t),
                        C.byref(k), C.byref(counters) if counters is not None else None)
+    return (t.value, int(k.value)) if h else (math.inf, -1)
+
+
+def trace_list(scene, order, o, d, tmin=0.0, tmax=math.inf, skip=-1, any_hit=False):
+    """Brute force over the primitive ids of `order`, visited in that order."""
+    sc = _as_oscene(scene)
+    order = np.ascontiguousarray(order, dtype=np.int64)
+    n_all = scene.n_spheres + scene.n_cylinders + getattr(scene, "n_triangles", 0)
+    if order.size and (order.min() < 0 or order.max() >= n_all):
+        raise ValueError("primitive id out of range")
+    o, d = (np.ascontiguousarray(x, dtype=np.float64) for x in (o, d))
+    t = C.c_double(); k = C.c_int64()
+    h = lib().or_trace_list(C.byref(sc.c), _ptr(order), int(order.size), _ptr(o), _ptr(d),
+                            float(tmin), float(tmax), int(skip), int(bool(any_hit)), C.byref(t),
+                            C.byref(k))
     return (t.value, int(k.value)) if h else (math.inf, -1)
 
 

@@ -632,6 +632,22 @@ int or_trace(const or_scene *s, const or_grid *g, const double o[3], const doubl
   return hs.found;
 }
 
+/* Brute force over the n primitive ids of order[], visited in that order.
+ * The nearest hit is a lexicographic minimum, so the result must not depend
+ * on the order (the tie-break pins visit duplicates in both directions). */
+int or_trace_list(const or_scene *s, const int64_t *order, int64_t n, const double o[3],
+                  const double d[3], double tmin, double tmax, int64_t skip, int any_hit,
+                  double *t, int64_t *k) {
+  hit_state hs = {any_hit, skip, 0, INFINITY, -1};
+  for (int64_t q = 0; q < n; ++q) {
+    consider(s, order[q], o, d, tmin, tmax, &hs, NULL);
+    if (any_hit && hs.found) break;
+  }
+  if (t) *t = hs.best_t;
+  if (k) *k = hs.best_k;
+  return hs.found;
+}
+
 /* ------------------------------------------------------------- rendering
  * Per pixel: nearest hit of the camera ray; on a hit, the shading normal
  * faces the viewer; each light with N.L > 0 casts one shadow ray; S AO rays

@@ -133,6 +133,12 @@ int or_trace(const or_scene *s, const or_grid *g, const double o[3], const doubl
              double tmin, double tmax, int64_t skip, int any_hit, double *t, int64_t *k,
              or_counters *cnt);
 
+/* or_trace by brute force over the n ids of order[], visited in that order
+ * (ids must be valid; duplicates allowed).  Same result for every order. */
+int or_trace_list(const or_scene *s, const int64_t *order, int64_t n, const double o[3],
+                  const double d[3], double tmin, double tmax, int64_t skip, int any_hit,
+                  double *t, int64_t *k);
+
 /* Render the listed pixels (pix == NULL => all W*H in row-major order).
  * With A = aa_samples > 1 every pixel is shaded A times, at the positions of
  * or_aa_offset, and rgb is the mean of the A clamped colours; hit_id, the
