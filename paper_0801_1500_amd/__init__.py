@@ -145,6 +145,16 @@ def _torch():
     return torch
 
 
+def _torch_stream(stream):
+    """A torch stream object for a torch stream, a raw hipStream_t or None."""
+    torch = _torch()
+    if stream is None:
+        return torch.cuda.current_stream()
+    if hasattr(stream, "cuda_stream"):
+        return stream
+    return torch.cuda.ExternalStream(int(stream))
+
+
 def _stream(stream) -> Optional[int]:
     torch = _torch()
     if stream is None:
@@ -330,7 +340,37 @@ def alloc_frame(cam, outputs: Sequence[str] = ("rgb",), stats: bool = False, dev
     return out
 
 
-def frame_struct(frame: dict) -> Frame:
+# Element type and values per pixel of each frame buffer (tr.h, tr_frame);
+# ao_mask holds uint32 bits and may come as int32.
+_FRAME_FIELDS = {"rgb": (("float32",), 3), "hit_id": (("int32",), 1),
+                 "ao_mask": (("int32", "uint32"), 1), "light_mask": (("uint8",), 1)}
+
+
+def frame_struct(frame: dict, cam=None) -> Frame:
+    """The tr_frame of a dict of device tensors.  With the camera, every
+    buffer present is checked before its address reaches the library: a CUDA
+    tensor on the current device, contiguous, of the element type tr.h names
+    and with W * H (* 3 for rgb) elements; stats needs STAT_COUNT 64-bit
+    integers.  ValueError otherwise."""
+    if cam is not None:
+        import torch
+        n_px = int(cam.width) * int(cam.height)
+        want = {k: (dt, n_px * per) for k, (dt, per) in _FRAME_FIELDS.items()}
+        want["stats"] = (("int64", "uint64"), STAT_COUNT)
+        for k, v in frame.items():
+            if v is None or k not in want:
+                continue
+            dts, numel = want[k]
+            if str(v.dtype).replace("torch.", "") not in dts:
+                raise ValueError("frame[%r]: dtype %s, expected %s" % (k, v.dtype, " or ".join(dts)))
+            if not v.is_contiguous():
+                raise ValueError("frame[%r] must be contiguous" % k)
+            if v.numel() != numel:
+                raise ValueError("frame[%r] has %d elements, expected %d" % (k, v.numel(), numel))
+        for k, v in frame.items():
+            if v is not None and k in want and (
+                    not v.is_cuda or v.device.index != torch.cuda.current_device()):
+                raise ValueError("frame[%r] must be a CUDA tensor on the current device" % k)
     g = lambda k: frame[k].data_ptr() if frame.get(k) is not None else None
     return Frame(g("rgb"), g("hit_id"), g("ao_mask"), g("light_mask"), g("stats"))
 
@@ -343,12 +383,19 @@ def quantize_rgb8(values, out=None, stream=None):
     torch = _torch()
     if values.dtype != torch.float32 or not values.is_cuda:
         raise TypeError("values must be a CUDA float32 tensor")
-    v = values.contiguous()
-    if out is None:
-        out = torch.empty(v.shape, dtype=torch.uint8, device=v.device)
-    elif out.dtype != torch.uint8 or out.numel() != v.numel() or not out.is_contiguous():
-        raise ValueError("out must be a contiguous uint8 tensor of values' size")
-    _check(lib().tr_frame_quantize(v.data_ptr(), v.numel(), out.data_ptr(), _stream(stream)))
+    s = _torch_stream(stream)
+    # allocations are made on the stream that uses them, so the caching
+    # allocator does not hand their blocks out while that stream's work is
+    # pending
+    with torch.cuda.stream(s):
+        v = values.contiguous()
+        if out is None:
+            out = torch.empty(v.shape, dtype=torch.uint8, device=v.device)
+        elif out.dtype != torch.uint8 or out.numel() != v.numel() or not out.is_contiguous():
+            raise ValueError("out must be a contiguous uint8 tensor of values' size")
+    if v is not values:
+        v.record_stream(s)
+    _check(lib().tr_frame_quantize(v.data_ptr(), v.numel(), out.data_ptr(), _stream(s)))
     return out
 
 
@@ -357,14 +404,17 @@ def frame_to_host_rgb8(frame: dict, host=None, stream=None):
     memory (asynchronous on the stream).  Returns (host uint8 [H, W, 3],
     event): wait on the event before reading host."""
     torch = _torch()
-    dev = quantize_rgb8(frame["rgb"], stream=stream)
+    s = _torch_stream(stream)
+    dev = quantize_rgb8(frame["rgb"], stream=s)
     if host is None:
         host = torch.empty(dev.shape, dtype=torch.uint8, pin_memory=True)
-    s = stream if stream is not None else torch.cuda.current_stream()
     with torch.cuda.stream(s):
         host.copy_(dev, non_blocking=True)
         ev = torch.cuda.Event()
         ev.record(s)
+    # the 8-bit device image is freed on return: its block must not be
+    # reused before the copy on s has read it
+    dev.record_stream(s)
     return host, ev
 
 
@@ -380,7 +430,7 @@ def render_into(scene: Scene, cam, params, frame: dict, precision="fp32_resolve"
                 stream=None):
     c = make_camera(cam)
     p = make_params(params, precision)
-    f = frame_struct(frame)
+    f = frame_struct(frame, cam)
     t = make_tune(tune)
     if t is None:
         _check(lib().tr_render(scene.handle, C.byref(c), C.byref(p), C.byref(f), _stream(stream)))
@@ -411,7 +461,7 @@ def _arrays(scenes, cams, params, frames, precision):
         pr = (Params * n)(*[make_params(p, q) for p, q in zip(params, precision)])
     else:
         pr = (Params * n)(*[make_params(p, precision) for p in params])
-    fr = (Frame * n)(*[frame_struct(f) for f in frames])
+    fr = (Frame * n)(*[frame_struct(f, c) for f, c in zip(frames, cams)])
     return n, sc, cm, pr, fr
 
 

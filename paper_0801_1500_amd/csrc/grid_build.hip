@@ -247,11 +247,26 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
     p[i] = v;
 }
 
-__global__ void k_count(trh::BuildArgs a, uint32_t *count) {
+// Per-cell counts, and the reference total summed in 64 bits (total64, zero
+// on entry): the 32-bit counts are exact (a cell holds fewer than 2^28
+// primitives), but their sum may pass 2^32, which the scan would wrap; the
+// host reads total64 and refuses the grid before the scatter.
+__global__ __launch_bounds__(kBlock) void k_count(trh::BuildArgs a, uint32_t *count,
+                                                  unsigned long long *total64) {
+  __shared__ unsigned long long blk;
+  if (threadIdx.x == 0) blk = 0ull;
+  __syncthreads();
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t k = t / kLanes;
-  if (k >= (int64_t)a.n_s + a.n_c + a.n_t) return;
-  for_prim_cells(a, k, (int)(t % kLanes), [&](uint32_t c) { atomicAdd(&count[c], 1u); });
+  unsigned long long mine = 0ull;
+  if (k < (int64_t)a.n_s + a.n_c + a.n_t)
+    for_prim_cells(a, k, (int)(t % kLanes), [&](uint32_t c) {
+      atomicAdd(&count[c], 1u);
+      ++mine;
+    });
+  if (mine) atomicAdd(&blk, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && blk) atomicAdd(total64, blk);
 }
 
 __global__ void k_scatter(trh::BuildArgs a, const uint32_t *cell_begin, uint32_t *cursor,
@@ -734,10 +749,11 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_count(const BuildArgs &a, uint32_t *count, hipStream_t st) {
+hipError_t launch_count(const BuildArgs &a, uint32_t *count, unsigned long long *total64,
+                        hipStream_t st) {
   const int64_t N = (int64_t)a.n_s + a.n_c + a.n_t;
   if (N == 0) return hipSuccess;
-  k_count<<<blocks_for(N * kLanes), kBlock, 0, st>>>(a, count);
+  k_count<<<blocks_for(N * kLanes), kBlock, 0, st>>>(a, count, total64);
   return hipGetLastError();
 }
 

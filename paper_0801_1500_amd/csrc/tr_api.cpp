@@ -73,11 +73,12 @@ struct tr_scene {
   trd::CellInfo *cellinfo = nullptr;
   uint8_t *dist0 = nullptr, *dist1 = nullptr;
   double *bounds_scratch = nullptr, *bounds = nullptr;
+  unsigned long long *total64 = nullptr;  // reference total of the count pass (device)
   int64_t cap_cells = 0, cap_refs = 0, cap_scan = 0, cap_wrefs = 0;
   size_t bytes_arrays = 0;
   // pinned readback
   double *h_bounds = nullptr;
-  uint32_t *h_total = nullptr;
+  unsigned long long *h_total = nullptr;
   trh::GridParams gp{};
   int64_t n_refs = 0;
   bool grid_ok = false;  // false after a failed (re)build: the scene cannot render
@@ -94,7 +95,7 @@ static void free_scene_arrays(tr_scene *s) {
                   s->cylW32, s->albedo, s->cell_begin, s->refs, s->count, s->scan_scratch,
                   s->bounds_scratch, s->bounds, s->cellinfo, s->dist0, s->dist1, s->wrefs,
                   s->triA64, s->triB64, s->triC64, s->triV32, s->triE1_32, s->triE2_32,
-                  s->bvh_nodes};
+                  s->bvh_nodes, s->total64};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->h_bounds) (void)hipHostFree(s->h_bounds);
@@ -248,18 +249,23 @@ static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
   }
   a.delta = s->gp.delta;
   HIP_TRY(trh::launch_fill_u32(s->cell_begin, nc + 1, 0u, st));
-  HIP_TRY(trh::launch_count(a, s->cell_begin, st));
-  HIP_TRY(trh::launch_scan(s->cell_begin, nc + 1, s->scan_scratch, st));
-  HIP_TRY(hipMemcpyAsync(s->h_total, s->cell_begin + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(trh::launch_fill_u32((uint32_t *)s->total64, 2, 0u, st));
+  HIP_TRY(trh::launch_count(a, s->cell_begin, s->total64, st));
+  HIP_TRY(hipMemcpyAsync(s->h_total, s->total64, sizeof(*s->h_total), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  const int64_t R = (int64_t)*s->h_total;
-  // walk lists (references plus one end marker per occupied cell) are
-  // addressed with 32-bit byte offsets by the traversal
-  const int64_t W = R + nc + 1;  // bound on the walk-list total
-  if (W > ((int64_t)1 << 30))
+  // The total is summed in 64 bits: overlapping large primitives can list
+  // more than 2^32 references, which the 32-bit scan would wrap.  Walk lists
+  // (references plus one end marker per occupied cell) are addressed with
+  // 32-bit byte offsets by the traversal, so the limit is checked before the
+  // scan and the scatter run.
+  const unsigned long long R64 = *s->h_total;
+  if (R64 + (unsigned long long)nc + 1ull > (1ull << 30))
     return fail(TR_EUNSUPPORTED,
-                "grid has %lld references and %lld cells (limit 2^30 together); lower cells_per_prim",
-                (long long)R, (long long)nc);
+                "grid has %llu references and %lld cells (limit 2^30 together); lower cells_per_prim",
+                R64, (long long)nc);
+  const int64_t R = (int64_t)R64;
+  const int64_t W = R + nc + 1;  // bound on the walk-list total
+  HIP_TRY(trh::launch_scan(s->cell_begin, nc + 1, s->scan_scratch, st));
   if (R > s->cap_refs) {
     if (s->refs) (void)hipFree(s->refs);
     s->refs = nullptr;
@@ -389,9 +395,10 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   ALLOC(s->triE2_32, s->n_t);
   ALLOC(s->bounds_scratch, trh::bounds_scratch_doubles(N));
   ALLOC(s->bounds, 6);
+  ALLOC(s->total64, 1);
 #undef ALLOC
   if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_bounds, 6 * sizeof(double), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_total, sizeof(uint32_t), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_total, sizeof(*s->h_total), hipHostMallocDefault);
   if (e != hipSuccess)
     return bail(fail(e == hipErrorOutOfMemory ? TR_ENOMEM : TR_EDEVICE, "scene allocation: %s",
                      hipGetErrorString(e)));
@@ -829,9 +836,12 @@ extern "C" tr_status tr_scene_walk_arrays(const tr_scene *s, int32_t *cellinfo, 
   hipStream_t st = (hipStream_t)hip_stream;
   const int64_t nc = s->gp.n_cells;
   // the walk-list total is the last entry of the scanned sizes (kept in count)
+  *s->h_total = 0ull;
   HIP_TRY(hipMemcpyAsync(s->h_total, s->count + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  *n_walk = (int64_t)*s->h_total;
+  uint32_t n_w = 0;
+  std::memcpy(&n_w, s->h_total, sizeof(n_w));
+  *n_walk = (int64_t)n_w;
   if (cellinfo)
     HIP_TRY(hipMemcpyAsync(cellinfo, s->cellinfo, (size_t)nc * sizeof(trd::CellInfo),
                            hipMemcpyDeviceToHost, st));

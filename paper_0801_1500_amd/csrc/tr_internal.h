@@ -44,7 +44,9 @@ hipError_t launch_pack32(const BuildArgs &a, const double4 *cylW64, const double
 int64_t bounds_scratch_doubles(int64_t n_prims);
 hipError_t launch_bounds(const BuildArgs &a, double *scratch, double *out6, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
-hipError_t launch_count(const BuildArgs &a, uint32_t *count, hipStream_t st);
+// per-cell counts (count zeroed) and their 64-bit total added to *total64 (zeroed)
+hipError_t launch_count(const BuildArgs &a, uint32_t *count, unsigned long long *total64,
+                        hipStream_t st);
 // exclusive scan of n+1 entries in place (data[n] must be 0 on entry)
 int64_t scan_scratch_u32(int64_t n);
 hipError_t launch_scan(uint32_t *data, int64_t n_plus_1, uint32_t *scratch, hipStream_t st);

@@ -249,6 +249,19 @@ def with_triangles(scene: Scene, tri_v: np.ndarray, tri_rgb=None, tri_opacity=No
                     "tri_opacity": tri_opacity})
 
 
+def stacked_cylinders(n: int = 14000, half: float = 100.0, radius: float = 1.0) -> Scene:
+    """n identical cylinders along the diagonal of a cube of half-size
+    `half`, no spheres: every cylinder's box is the whole scene box, so each
+    is listed in every grid cell (n x cells references in all; a grid-size
+    limit case)."""
+    a = np.full((n, 3), -half)
+    b = np.full((n, 3), half)
+    ld, lc = _lights(1)
+    e3 = _empty3()
+    return Scene(e3, np.zeros(0), _empty3(np.float32), a, b, np.full(n, radius),
+                 PALETTE[np.arange(n) % 4].astype(np.float32), ld, lc)
+
+
 def mixed_tiny_scene(seed: int = 5) -> Scene:
     """Small scene with all three primitive types: 24 spheres and 12
     cylinders in a ball of radius 10, four icosphere blobs (80 triangles

@@ -194,3 +194,34 @@ def test_scene_load_rejects_bad_files(tr, tmp_path):
     assert L.tr_scene_load(str(opq).encode(), None, C.byref(h)) == tr.TR_EINVAL
     assert b"its counts need" in L.tr_last_error()
     assert not h.value
+
+
+def test_frame_buffers_checked_before_the_call(tr):
+    """frame_struct with the camera refuses buffers whose dtype, layout or
+    size do not match the frame (their addresses would let the kernel write
+    out of bounds), before anything reaches the library; on this CPU-only
+    host a well-formed tensor still fails the device check."""
+    import torch
+    cam = tr.Camera((C.c_double * 3)(0, 0, 30), (C.c_double * 3)(0, 0, 0), (C.c_double * 3)(0, 1, 0),
+                    50.0, 7, 5)
+    good = {"rgb": torch.zeros(5, 7, 3), "hit_id": torch.zeros(5, 7, dtype=torch.int32),
+            "ao_mask": torch.zeros(5, 7, dtype=torch.int32),
+            "light_mask": torch.zeros(5, 7, dtype=torch.uint8),
+            "stats": torch.zeros(tr.STAT_COUNT, dtype=torch.int64)}
+    bad = [
+        ("rgb", torch.zeros(5, 7, 3, dtype=torch.float64), "dtype"),
+        ("rgb", torch.zeros(5, 7, 2), "elements"),
+        ("rgb", torch.zeros(7, 5, 3).transpose(0, 1), "contiguous"),
+        ("hit_id", torch.zeros(5, 7), "dtype"),
+        ("hit_id", torch.zeros(5, 8, dtype=torch.int32), "elements"),
+        ("ao_mask", torch.zeros(5, 7, dtype=torch.int64), "dtype"),
+        ("light_mask", torch.zeros(5, 7, dtype=torch.uint8)[:, :6], "contiguous"),
+        ("stats", torch.zeros(3, dtype=torch.int64), "elements"),
+    ]
+    for key, val, what in bad:
+        with pytest.raises(ValueError, match=what):
+            tr.frame_struct({**good, key: val}, cam)
+    with pytest.raises(ValueError, match="CUDA"):
+        tr.frame_struct(good, cam)
+    # without the camera (no check) only the addresses are taken
+    tr.frame_struct(good)

@@ -73,3 +73,19 @@ def test_largest_frame(tr, oracle_mod):
     with pytest.raises(tr.TRError) as e:
         tr.render_into(gs, big, p, {"rgb": torch.empty(3, device="cuda")}, "fp32_resolve")
     assert e.value.status == -1
+
+
+def test_reference_total_past_32_bits_refused(tr):
+    """14,000 identical cylinders spanning the scene list 4.8 G references
+    at 24 cells per primitive: more than 2^32, whose 32-bit wrap (0.51 G)
+    would pass the 2^30 limit (tests/test_grid_limits.py).  The build sums
+    the total in 64 bits and refuses before the scan and the scatter; a
+    normal scene still builds afterwards."""
+    s = scenegen.stacked_cylinders()
+    print("stacked cylinders", s.n_prims, flush=True)
+    with pytest.raises(tr.TRError) as e:
+        tr.Scene(s, cells_per_prim=24.0)
+    assert e.value.status == -4
+    assert "references" in str(e.value)
+    gs = tr.Scene(scenegen.tiny_scene())
+    gs.destroy()
