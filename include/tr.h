@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define TR_ABI_VERSION 2
+#define TR_ABI_VERSION 3
 
 typedef enum {
   TR_OK = 0,
@@ -142,7 +142,7 @@ typedef struct {
                                 white, to the albedo-scaled colour before the
                                 clamp; R_l is the light direction mirrored about
                                 N, V the unit direction back to the eye, and the
-                                sum runs over the lights with N.L_l > 0. */
+                                sum runs over the lights with N.L_l > 2^-40. */
   int32_t max_layers;        /* transparency (the -trans_vmd option, Sec. 2),
                                 0..64; 0 and 1 = opaque rendering.  With L > 1 a
                                 primary ray that hits a primitive of opacity
@@ -181,7 +181,7 @@ enum {
   TR_STAT_PIXELS = 0,        /* primary rays                                */
   TR_STAT_HIT_PIXELS,        /* primary rays that hit                       */
   TR_STAT_AO_RAYS,           /* AO rays cast                                */
-  TR_STAT_SHADOW_RAYS,       /* light shadow rays cast (N.L > 0)            */
+  TR_STAT_SHADOW_RAYS,       /* light shadow rays cast (N.L > 2^-40)        */
   TR_STAT_RAYS_TRACED,       /* all rays handed to a traversal              */
   TR_STAT_CELLS,             /* grid cells visited (the FP32 walk skips runs of empty cells) */
   TR_STAT_SPH_TESTS,
@@ -201,6 +201,13 @@ enum {
   TR_STAT_STALLS,            /* wavefront kernel: waves that left with work outstanding (an
                                 internal-error guard: always 0 unless the queue bookkeeping broke,
                                 and then the frame is incomplete) */
+  TR_STAT_RESOLVES_SPH,      /* FP64 re-solves split by primitive kind ... */
+  TR_STAT_RESOLVES_CYL,
+  TR_STAT_RESOLVES_TRI,
+  TR_STAT_RESOLVES_NEAREST,  /* ... and those of nearest-hit (primary, continuation) rays;
+                                the rest are shadow and AO rays */
+  TR_STAT_SIGNS_F64,         /* triangle hits whose facing, N.L and AO-basis signs were
+                                decided from the FP64 vertices (a sign within 2^-12 of 0) */
   TR_STAT_COUNT
 };
 
@@ -325,7 +332,9 @@ void tr_scene_destroy(tr_scene *scene);
 
 /* Render one frame (the "Ray Tracing" phase, Table 5): per pixel, the
  * nearest hit of the camera ray; on a hit, the viewer-facing normal, one
- * shadow ray per light with N.L > 0, and params->ao_samples AO rays drawn
+ * shadow ray per light with N.L > 2^-40 (at or below, N.L is rounding noise of
+ * a light in the plane of the surface, and the light adds nothing), and
+ * params->ao_samples AO rays drawn
  * from the cosine-weighted hemisphere with Philox4x32-10 uniforms keyed by
  * (pixel, sample, view_id) and seed; colour = clamp(albedo * (light_rescale
  * * sum_l I_l (N.L_l) V_l + skylight * AO) + highlight, 0, 1) (highlight:

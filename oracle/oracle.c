@@ -650,7 +650,7 @@ int or_trace_list(const or_scene *s, const int64_t *order, int64_t n, const doub
 
 /* ------------------------------------------------------------- rendering
  * Per pixel: nearest hit of the camera ray; on a hit, the shading normal
- * faces the viewer; each light with N.L > 0 casts one shadow ray; S AO rays
+ * faces the viewer; each light with N.L > 2^-40 casts one shadow ray; S AO rays
  * sample the cosine-weighted hemisphere with Philox uniforms keyed by
  * (pixel, sample); secondary rays start at the hit point with t in
  * (1e-4, ...] and skip the hit primitive when it was hit on its outside.
@@ -658,10 +658,17 @@ int or_trace_list(const or_scene *s, const int64_t *order, int64_t n, const doub
  * + H, 0, 1) per channel, AO = unoccluded fraction (1 if no AO rays are
  * cast).  H is the optional Phong highlight (a shading option of the
  * renderer the paper drives, not used in its runs): rescale * sum_l I_l V_l
- * k_s max(0, R_l.V)^n over the lights with N.L_l > 0, R_l the light
+ * k_s max(0, R_l.V)^n over the lights with N.L_l > 2^-40, R_l the light
  * direction mirrored about N and V = -d the direction back to the eye; it is
  * white (not scaled by the albedo) and 0 when k_s = 0. */
 #define OR_EPS 1e-4
+/* A light counts, and casts its shadow ray, when N.L exceeds 2^-40 (reading
+ * A8).  N.L at or below that is rounding noise of a light in the plane of the
+ * surface (a flat face exactly perpendicular to a light): its term would add
+ * at most 2^-40 of the light, invisible in the output, while its shadow ray
+ * runs along the surface, where being blocked depends only on the rounding of
+ * the hit point, in any precision. */
+#define OR_LIGHT_MIN 0x1p-40
 
 static void add_counters(or_counters *dst, const or_counters *src) {
   dst->pixels += src->pixels;
@@ -736,7 +743,7 @@ static void shade_surface(const or_scene *s, const or_grid *g, const or_params *
   double Hs[3] = {0.0, 0.0, 0.0}; /* specular highlights (white, after albedo) */
   for (int l = 0; l < s->n_lights; ++l) {
     double c = dot3(N, ldir[l]);
-    if (!(c > 0.0)) continue;
+    if (!(c > OR_LIGHT_MIN)) continue;
     loc->shadow_rays++;
     if (or_trace(s, g, P, ldir[l], OR_EPS, INFINITY, skip, 1, NULL, NULL, loc)) {
       *lmask |= (uint8_t)(1u << l);

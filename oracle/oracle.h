@@ -79,7 +79,7 @@ typedef struct {
   uint64_t pixels;
   uint64_t primary_rays;
   uint64_t hit_pixels;
-  uint64_t shadow_rays;  /* light rays actually traced (N.L > 0) */
+  uint64_t shadow_rays;  /* light rays actually traced (N.L > 2^-40) */
   uint64_t ao_rays;
   uint64_t rays_traced;  /* every ray handed to a traversal */
   uint64_t cells;        /* grid cells visited */

@@ -24,7 +24,8 @@ PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "fp32_resolve": PREC_FP32_RE
 STAT_NAMES = ["pixels", "hit_pixels", "ao_rays", "shadow_rays", "rays_traced", "cells",
               "sph_tests", "sph_hits", "cyl_tests", "cyl_hits", "resolves", "wave_iters",
               "lane_iters", "refills", "jumps", "cycles_traverse", "cycles_total", "tri_tests",
-              "tri_hits", "stack_overflows", "stalls"]
+              "tri_hits", "stack_overflows", "stalls", "resolves_sph", "resolves_cyl",
+              "resolves_tri", "resolves_nearest", "signs_f64"]
 STAT_COUNT = len(STAT_NAMES)
 
 

@@ -2,9 +2,11 @@
 
 Each translation unit is compiled with its own floating-point contract
 setting: the grid build, the plain FP64 kernel and the host ABI code must
-round exactly as written (-ffp-contract=off); the FP32 wavefront kernel may
-fuse multiply-adds.  Packed FP32 instructions are disabled for all device
-code.
+round exactly as written (-ffp-contract=off); the FP32 wavefront kernel
+fuses the multiply-adds within each expression (-ffp-contract=on, which
+honours the source's contraction pragmas: its FP64 helpers round exactly
+as written; =fast would fuse at code generation regardless).  Packed FP32
+instructions are disabled for all device code.
 """
 from __future__ import annotations
 
@@ -22,7 +24,7 @@ ARCH = "gfx950"
 SOURCES = {
     "grid_build.hip": ["-ffp-contract=off"],
     "render_plain.hip": ["-ffp-contract=off"],
-    "render_wave.hip": ["-ffp-contract=fast"],
+    "render_wave.hip": ["-ffp-contract=on"],
     "frame_out.hip": ["-ffp-contract=off"],
     "tr_api.cpp": ["-ffp-contract=off", "-x", "hip"],
 }

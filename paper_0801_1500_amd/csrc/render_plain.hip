@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_render_plain_f64(const JobDev J, uint64
       double Hs[3] = {0.0, 0.0, 0.0};  // Phong highlight (white, after the albedo)
       for (int l = 0; l < J.n_lights; ++l) {
         const double cl = dot3d(N, J.ldir[l]);
-        if (!(cl > 0.0)) continue;
+        if (!(cl > kLightMin)) continue;
         n_sh++;
         double tt;
         int32_t kk;

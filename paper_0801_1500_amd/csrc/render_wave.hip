@@ -29,6 +29,10 @@
 // FP64 from their pixel) and the walk resumes.  Keeping all FP64 code out of
 // the traversal loop keeps the loop's register footprint, and so the
 // occupancy, that of the FP32 path.
+// This unit fuses the multiply-adds of each expression (-ffp-contract=on);
+// the FP64 helpers of tr_device.h keep their exact rounding (the header
+// turns contraction off for them and back on after them).
+#define TR_CONTRACT_ON 1
 #include "tr_internal.h"
 
 namespace {
@@ -90,7 +94,8 @@ struct Lds {
   float px[NS], py[NS], pz[NS];
   float nx[NS], ny[NS], nz[NS];
   int32_t prim[NS];     // hit primitive
-  int32_t skip[NS];     // primitive skipped by secondary rays (-1 = none)
+  int32_t skip[NS];     // secondary rays: k >= 0 skip primitive k; -2 - k: k is the surface
+                        // they leave from inside (far root only); -1 = none
   int32_t pending[NS];  // secondary rays not yet finished
   int32_t nrays[NS];    // secondary rays of the slot
   uint32_t lvalid[NS];  // lights with N.L > 0
@@ -99,7 +104,7 @@ struct Lds {
   uint32_t lmask[NS];
   uint8_t fifo[NS];
   BankInfo bank[BANKS];
-  uint32_t cnt[14];
+  uint32_t cnt[19];
   // compositing across surfaces: colour so far, transmittance in front of the
   // current surface, its index, and whether the FIFO entry is a continuation
   float acc_r[NT], acc_g[NT], acc_b[NT], trn[NT];
@@ -128,16 +133,11 @@ __device__ __forceinline__ int32_t cvt_floor(float x) {
   return r;
 }
 
-// IEEE min/max of two floats without the operand canonicalisation the
-// compiler adds to fminf/fmaxf when it cannot see where a value came from
+// IEEE min of two floats without the operand canonicalisation the compiler
+// adds to fminf when it cannot see where a value came from
 __device__ __forceinline__ float vminf(float a, float b) {
   float r;
   asm volatile("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-__device__ __forceinline__ float vmaxf(float a, float b) {
-  float r;
-  asm volatile("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
   return r;
 }
 
@@ -170,7 +170,8 @@ struct Ray {
   int32_t nk;          // wrefs[rc]: the next reference, -1 at the list end (loaded ahead)
   float bt;            // best t
   int32_t bk;          // best id (-1 = none)
-  int32_t skip;
+  int32_t skip;         // k >= 0: never report k; -2 - k: k is the ray's own surface,
+                        // left from inside; -1: none
 };
 
 // Scene fields used by the traversal, loaded (wave-uniform) from the job
@@ -294,6 +295,54 @@ __device__ __forceinline__ bool bvh_setup(Ray &R, const SceneHot &S) {
   return S.bvh_n > 0;
 }
 
+// Sign decisions of a triangle hit in FP64, in the reference's order of
+// operations: the unit normal e1 x e2 from the FP64 vertices, its facing
+// against the ray (a primary ray regenerated in FP64 from its pixel; a
+// continuation ray's FP32 direction promoted), N.L > 0 per light, and the
+// sign of N.z, which picks the AO basis.  The FP32 normal becomes the FP64
+// one rounded, so every sign (of a zero too) is the FP64 one.
+__device__ __forceinline__ void tri_signs_f64(const JobDev &J, int32_t m, bool primary, int32_t px,
+                                              int32_t py, float dx, float dy, float dz, float &Nx,
+                                              float &Ny, float &Nz, bool &front, uint32_t &lv) {
+  const SceneDev &S = J.sc;
+  double n[3], o[3], d[3];
+  triangle_normal_f64(S.triA64[m], S.triB64[m], S.triC64[m], n);
+  if (primary) {
+    primary_ray_f64(J, px, py, o, d);
+  } else {
+    const double v[3] = {(double)dx, (double)dy, (double)dz};
+    const double nv = sqrt(dot3d(v, v));
+    d[0] = v[0] / nv;
+    d[1] = v[1] / nv;
+    d[2] = v[2] / nv;
+  }
+  front = dot3d(n, d) < 0.0;
+  if (!front) {
+    n[0] = -n[0];
+    n[1] = -n[1];
+    n[2] = -n[2];
+  }
+  uint32_t m_l = 0;
+  for (int l = 0; l < J.n_lights; ++l)
+    if (dot3d(n, J.ldir[l]) > kLightMin) m_l |= 1u << l;
+  lv = m_l;
+  Nx = (float)n[0];
+  Ny = (float)n[1];
+  Nz = (float)n[2];
+}
+
+// FP64 test of primitive k (global id) against the ray: 1 and its root.
+template <bool TRI>
+__device__ __forceinline__ int hit_prim_f64(const SceneDev &S, int32_t k, const double o[3],
+                                            const double d[3], double tmin, double tmax, double &t) {
+  if (k < S.n_s) return hit_sphere_f64(S.sph64[k], o, d, tmin, tmax, t);
+  if (TRI && k >= S.n_s + S.n_c) {
+    const int32_t m = k - S.n_s - S.n_c;
+    return hit_triangle_f64(S.triA64[m], S.triB64[m], S.triC64[m], o, d, tmin, tmax, t);
+  }
+  return hit_cylinder_f64(S.cylA64[k - S.n_s], S.cylW64[k - S.n_s], o, d, tmin, tmax, t);
+}
+
 struct WaveArgs {
   const JobDev *jobs;
   int32_t n_jobs;
@@ -325,7 +374,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
   const int32_t lane = threadIdx.x;
   const int32_t TW = A.tile_w;
   const int32_t TH = 64 / TW;
-  if (lane < 14) L.cnt[lane] = 0;
+  if (lane < 19) L.cnt[lane] = 0;
 
   // ---- wave-uniform control state
   int32_t q_head = 0, q_tail = 0, head_issued = 0;
@@ -343,6 +392,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
   uint64_t c_rays = 0;
   uint32_t l_cells = 0, l_st = 0, l_sh = 0, l_ct = 0, l_ch = 0, l_res = 0, l_jumps = 0;  // per lane
   uint32_t l_tt = 0, l_th = 0, l_ovf = 0;
+  uint32_t l_rs = 0, l_rc = 0, l_rt = 0, l_rn = 0;  // re-solves: sphere, cylinder, triangle, nearest-hit rays
+  uint32_t l_sg = 0;  // triangle hits whose sign decisions were taken in FP64
   uint64_t c_iters = 0, c_lanes = 0, c_refills = 0;
   uint64_t c_cyc_trav = 0;
   const uint64_t c_cyc_start = COUNT ? clock64() : 0;
@@ -383,14 +434,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         const double tmin = kind == kPrimary ? 0.0 : kEpsD;
         const double tmax = kind == kAO ? J->ao_maxdist : INFINITY;
         double t = 0.0;
-        int h;
-        if (gk < S.n_s)
-          h = hit_sphere_f64(S.sph64[gk], o, d, tmin, tmax, t);
-        else if (TRI && gk >= S.n_s + S.n_c)
-          h = hit_triangle_f64(S.triA64[gk - S.n_s - S.n_c], S.triB64[gk - S.n_s - S.n_c],
-                               S.triC64[gk - S.n_s - S.n_c], o, d, tmin, tmax, t);
-        else
-          h = hit_cylinder_f64(S.cylA64[gk - S.n_s], S.cylW64[gk - S.n_s], o, d, tmin, tmax, t);
+        const int h = hit_prim_f64<TRI>(S, gk, o, d, tmin, tmax, t);
         int32_t nst = kRun;
         if (h) {
           const float tf = (float)t;
@@ -446,18 +490,36 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         Nx *= inv;
         Ny *= inv;
         Nz *= inv;
-        const bool front = (Nx * R.dx + Ny * R.dy + Nz * R.dz) < 0.0f;
+        const float nd = Nx * R.dx + Ny * R.dy + Nz * R.dz;
+        bool front = nd < 0.0f;
         if (!front) {
           Nx = -Nx;
           Ny = -Ny;
           Nz = -Nz;
         }
         uint32_t lv = 0;
+        bool near0 = false;  // a sign decision within 2^-12 of zero
         const BankInfo &Bk = bank_of(L.bank, bk);
         const int32_t nl = Bk.n_lights;
         for (int l = 0; l < nl; ++l) {
           const float cl = Nx * Bk.ldir[l][0] + Ny * Bk.ldir[l][1] + Nz * Bk.ldir[l][2];
-          if (cl > 0.0f) lv |= 1u << l;
+          if (cl > (float)kLightMin) lv |= 1u << l;
+          near0 |= fabsf(cl) <= kKappa;
+        }
+        if (TRI && k >= S.n_sc) {
+          // A triangle's normal is the same over the whole face, so a sign
+          // decided by FP32 rounding (a normal exactly perpendicular to a
+          // light, a zero z component choosing the AO basis, a face seen
+          // edge-on) would flip the face as a whole: near zero, the normal
+          // and its decisions come from the FP64 vertices instead.
+          near0 |= fabsf(nd) <= kKappa || fabsf(Nz) <= kKappa;
+          if (near0) {
+            if (COUNT) ++l_sg;
+            int32_t px = 0, py = 0;
+            bank_pixel(Bk, slot & 63, px, py);
+            tri_signs_f64(A.jobs[Bk.job], k - S.n_sc, kind == kPrimary, px, py, R.dx, R.dy, R.dz,
+                          Nx, Ny, Nz, front, lv);
+          }
         }
         nr = (uint32_t)Bk.S + (uint32_t)__popc(lv);
         L.px[slot] = Px;
@@ -467,7 +529,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         L.ny[slot] = Ny;
         L.nz[slot] = Nz;
         L.prim[slot] = k;
-        L.skip[slot] = front ? k : -1;
+        // A ray leaving a convex surface outward cannot meet it again: skip
+        // it.  Leaving from inside, the ray's start is one root of its own
+        // primitive; in FP32 that root lands anywhere within the hit
+        // point's rounding (which can pass the 1e-4 lower limit at grazing
+        // angles), so the walk takes only the other root of its own sphere
+        // or cylinder, and never its own (flat) triangle -- the result in
+        // exact arithmetic.
+        L.skip[slot] = front ? k : -2 - k;
         L.pending[slot] = (int32_t)nr;
         L.nrays[slot] = (int32_t)nr;
         L.lvalid[slot] = lv;
@@ -574,7 +643,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             L.acc_b[slot] = ab;
             L.trn[slot] = Tn;
             L.layer[slot] = (uint8_t)(layer + 1);
-            L.skip[slot] = L.skip[slot] >= 0 ? -1 : L.prim[slot];
+            // entering it: its own far side counts, its start does not
+            L.skip[slot] = L.skip[slot] >= 0 ? -2 - L.prim[slot] : L.prim[slot];
             L.nrays[slot] = 1;
             L.pending[slot] = 1;
             L.cont[slot] = 1;
@@ -988,6 +1058,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         }
         bool tested = false, hit = false, graze = false;
         float t = 0.0f;
+        const bool own = nk == -2 - R.skip;  // the surface this ray leaves from inside
         if (is_sph) {
           tested = true;
           const vf4 s = sdat;
@@ -1001,8 +1072,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           const float sq = sqrtf_fast(fmaxf(disc, 0.0f));
           const float t0 = b - sq, t1 = b + sq;
           const bool ok = disc >= 0.0f && !graze;
-          // nearer root if it is past tmin, else the farther (t0 <= t1)
-          t = t0 > R.tmin ? t0 : t1;
+          // nearer root if it is past tmin, else the farther (t0 <= t1);
+          // only the farther on the ray's own sphere
+          t = t0 > R.tmin && !own ? t0 : t1;
           hit = ok && t > R.tmin && t <= R.t1;
         }
         if (TRI && is_cyl && nk >= H.n_sc) {
@@ -1039,20 +1111,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           const float Dw = Dx * w.x + Dy * w.y + Dz * w.z;
           const float dpx = R.dx - dw * w.x, dpy = R.dy - dw * w.y, dpz = R.dz - dw * w.z;
           const float Dpx = Dx - Dw * w.x, Dpy = Dy - Dw * w.y, Dpz = Dz - Dw * w.z;
+          // |perp(D + t d)|^2 = rho^2 about the closest approach of the
+          // perpendicular motion, t_c = -B / A, where the perpendicular
+          // offset is l = perp(D) + t_c perp(d): the discriminant (B^2 -
+          // A C) / A = rho^2 - |l|^2 then carries no cancellation of the
+          // eye's distance (as the sphere test's), and the grazing test
+          // compares it with rho^2 + |l|^2.
           const float Aq = dpx * dpx + dpy * dpy + dpz * dpz;
           const float Bq = dpx * Dpx + dpy * Dpy + dpz * Dpz;
-          const float Cq = (Dpx * Dpx + Dpy * Dpy + Dpz * Dpz) - a.w * a.w;
-          const float disc = Bq * Bq - Aq * Cq;
           const bool nonpar = Aq > 1e-12f;
-          const bool g0 = RESOLVE && nonpar && fabsf(disc) <= kKappa * (Bq * Bq + fabsf(Aq * Cq));
-          const float sq = sqrtf_fast(fmaxf(disc, 0.0f));
-          const float qq = -(Bq + __builtin_copysignf(sq, Bq));
-          const bool ok = nonpar && !g0 && disc >= 0.0f && qq != 0.0f;
-          const float r0 = qq * rcpf(Aq), r1 = Cq * rcpf(qq);
-          const float tl = vminf(r0, r1), th = vmaxf(r0, r1);
+          const float iA = rcpf(Aq);
+          const float tc = -Bq * iA;
+          const float lx = Dpx + tc * dpx, ly = Dpy + tc * dpy, lz = Dpz + tc * dpz;
+          const float ll = lx * lx + ly * ly + lz * lz;
+          const float rr = a.w * a.w;
+          const float disc = rr - ll;
+          const bool g0 = RESOLVE && nonpar && fabsf(disc) <= kKappa * (rr + ll);
+          const float sq = sqrtf_fast(fmaxf(disc, 0.0f) * iA);
+          const bool ok = nonpar && !g0 && disc >= 0.0f;
+          const float tl = tc - sq, th = tc + sq;
           const float kL = kKappa * w.w;
           const float sl = Dw + tl * dw, sh = Dw + th * dw;
-          const bool inl = ok && tl > R.tmin && tl <= R.t1;
+          const bool inl = ok && !own && tl > R.tmin && tl <= R.t1;  // own: far root only
           const bool inh = ok && th > R.tmin && th <= R.t1;
           const bool gl = RESOLVE && inl && (fabsf(sl) <= kL || fabsf(sl - w.w) <= kL);
           const bool gh = RESOLVE && inh && (fabsf(sh) <= kL || fabsf(sh - w.w) <= kL);
@@ -1064,7 +1144,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           t = hl ? tl : th;
         }
         if (tested) {
-          const bool live = nk != R.skip;
+          // skipped: the surface an outward ray leaves, and the own triangle
+          const bool live = nk != R.skip && !(TRI && own && nk >= H.n_sc);
           hit = hit && live;
           graze = graze && live;
           if (COUNT && live) {
@@ -1079,6 +1160,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
               l_ch += hit;
             }
             l_res += graze;
+            if (nk < H.n_s) l_rs += graze;
+            else if (TRI && nk >= H.n_sc) l_rt += graze;
+            else l_rc += graze;
+            l_rn += graze && !anyhit;
           }
           // nearest hit (ties to the lower id); any hit ends a shadow/AO ray
           const bool take = hit && (anyhit || t < R.bt || (t == R.bt && nk < R.bk));
@@ -1131,6 +1216,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         atomicAdd(&L.cnt[12], l_th);
       }
       if (BVH) atomicAdd(&L.cnt[13], l_ovf);
+      if (RESOLVE) {
+        atomicAdd(&L.cnt[14], l_rs);
+        atomicAdd(&L.cnt[15], l_rc);
+        atomicAdd(&L.cnt[16], l_rt);
+        atomicAdd(&L.cnt[17], l_rn);
+      }
+      if (TRI) atomicAdd(&L.cnt[18], l_sg);
     }
     __syncthreads();
     if (lane == 0) {
@@ -1155,6 +1247,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         atomicAdd(&st[TR_STAT_TRI_TESTS], (unsigned long long)L.cnt[11]);
         atomicAdd(&st[TR_STAT_TRI_HITS], (unsigned long long)L.cnt[12]);
         atomicAdd(&st[TR_STAT_STACK_OVERFLOWS], (unsigned long long)L.cnt[13]);
+        atomicAdd(&st[TR_STAT_RESOLVES_SPH], (unsigned long long)L.cnt[14]);
+        atomicAdd(&st[TR_STAT_RESOLVES_CYL], (unsigned long long)L.cnt[15]);
+        atomicAdd(&st[TR_STAT_RESOLVES_TRI], (unsigned long long)L.cnt[16]);
+        atomicAdd(&st[TR_STAT_RESOLVES_NEAREST], (unsigned long long)L.cnt[17]);
+        atomicAdd(&st[TR_STAT_SIGNS_F64], (unsigned long long)L.cnt[18]);
         atomicAdd(&st[TR_STAT_CYCLES_TRAVERSE], (unsigned long long)c_cyc_trav);
         atomicAdd(&st[TR_STAT_CYCLES_TOTAL], (unsigned long long)(clock64() - c_cyc_start));
       }

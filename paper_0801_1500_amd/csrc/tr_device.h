@@ -32,6 +32,11 @@ struct CellInfo {
 };
 static_assert(sizeof(CellInfo) == 8, "CellInfo is two words");
 
+// A light counts, and casts its shadow ray, when N.L exceeds 2^-40: below
+// that, N.L is rounding noise of a light in the plane of the surface, whose
+// term is invisible and whose shadow ray runs along the surface.
+constexpr double kLightMin = 0x1p-40;
+
 // ----------------------------------------------------------------- scene
 struct SceneDev {
   int32_t n_s, n_c, n_t;  // ids: spheres, then cylinders, then triangles
@@ -157,6 +162,15 @@ __device__ __forceinline__ void ao_dir_f32(float nx, float ny, float nz, uint32_
   wy = lx * ty + ly * by + lz * ny;
   wz = lx * tz + ly * bz + lz * nz;
 }
+
+// ------------------------------------------------------------- FP64 code
+// Everything below rounds exactly as written (no fused multiply-adds), in
+// every translation unit: the plain FP64 path reproduces the reference
+// order of operations, and the FP32 kernel's FP64 re-solves and sign
+// decisions must round like it.  A unit compiled with -ffp-contract=on
+// restores it after this header (TR_CONTRACT_ON).  (-ffp-contract=fast
+// would fuse at code generation regardless of this pragma.)
+#pragma clang fp contract(off)
 
 // FP64 version in the operation order of the plain double-precision path.
 __device__ __forceinline__ void ao_dir_f64(const double n[3], uint32_t b1, uint32_t b2,
@@ -309,3 +323,7 @@ __device__ __forceinline__ void triangle_normal_f64(const double4 A, const doubl
 }
 
 }  // namespace trd
+
+#ifdef TR_CONTRACT_ON
+#pragma clang fp contract(on)
+#endif

@@ -226,18 +226,70 @@ def _random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
     return q
 
 
-def blob_mesh(centres: np.ndarray, radius: float, subdiv: int, seed: int = 0) -> np.ndarray:
-    """Closed icosphere meshes of the given radius around each centre, each
-    turned by its own random rotation (the icosahedron's symmetric faces
-    would otherwise have normals with exact zero components or exactly
-    perpendicular to a light, where a whole face's decisions hang on
-    rounding): triangle vertices [n * F, 3, 3]."""
+def blob_mesh(centres: np.ndarray, radius: float, subdiv: int, seed: int = 0,
+              rotate: bool = True) -> np.ndarray:
+    """Closed icosphere meshes of the given radius around each centre:
+    triangle vertices [n * F, 3, 3].  With rotate, each blob is turned by
+    its own random rotation; without, every blob keeps the icosahedron's
+    axis-aligned symmetry, whose faces have normals with (rounded) zero
+    components and normals perpendicular to a light or nearly so, where a
+    whole face's sign decisions rest on rounding."""
     verts, faces = icosphere(subdiv)
     unit = verts[faces]  # [F, 3, 3]
     c = np.asarray(centres, dtype=np.float64).reshape(-1, 1, 1, 3)
-    rot = _random_rotations(np.random.default_rng(seed), c.shape[0])
-    turned = np.einsum("nij,fvj->nfvi", rot, unit)
+    if rotate:
+        rot = _random_rotations(np.random.default_rng(seed), c.shape[0])
+        turned = np.einsum("nij,fvj->nfvi", rot, unit)
+    else:
+        turned = np.broadcast_to(unit, (c.shape[0],) + unit.shape)
     return (c + radius * turned).reshape(-1, 3, 3)
+
+
+def voxel_mesh(centres: np.ndarray, radius: float, cell: float,
+               offset=(0.125, 0.375, 0.25)) -> np.ndarray:
+    """The boundary of the voxels (cubes of side `cell` on a lattice through
+    `offset`) whose centres lie within `radius` of a centre: each face
+    between a voxel inside and one outside becomes two triangles, wound
+    counter-clockwise seen from outside.  Every normal is an axis direction
+    and every vertex a multiple of `cell` (exact for a power of two), like
+    the blocky surfaces of a marching-cubes mesh at its lattice directions:
+    triangle vertices [n, 3, 3].  The default offset keeps lattice planes
+    off the coordinate planes (and so off a camera's axis through the
+    origin)."""
+    out = []
+    off = np.asarray(offset, dtype=np.float64)
+    for c in np.asarray(centres, dtype=np.float64).reshape(-1, 3):
+        c = c - off
+        base = np.floor(c / cell).astype(np.int64)
+        m = int(math.ceil(radius / cell)) + 1
+        idx = np.arange(-m, m + 1)
+        g = np.stack(np.meshgrid(idx, idx, idx, indexing="ij"), axis=-1) + base  # voxel lattice index
+        ctr = (g + 0.5) * cell
+        inside = ((ctr - c) ** 2).sum(axis=-1) <= radius * radius
+        inside = np.pad(inside, 1)
+        gp = np.pad(g, ((1, 1), (1, 1), (1, 1), (0, 0)), mode="edge")
+        n = inside.shape[0]
+        for a in range(3):
+            b, e = (a + 1) % 3, (a + 2) % 3
+            for sgn in (1, -1):
+                sl_in = [slice(1, n - 1)] * 3
+                sl_out = list(sl_in)
+                sl_out[a] = slice(1 + sgn, n - 1 + sgn)
+                face = inside[tuple(sl_in)] & ~inside[tuple(sl_out)]
+                vox = gp[tuple(sl_in)][face]  # lattice index of each voxel with that face
+                p00 = vox.astype(np.float64)
+                p00[:, a] += 1 if sgn > 0 else 0
+                p00 = p00 * cell + off
+                eb = np.zeros(3)
+                eb[b] = cell
+                ec = np.zeros(3)
+                ec[e] = cell
+                p10, p11, p01 = p00 + eb, p00 + eb + ec, p00 + ec
+                if sgn > 0:
+                    out += [np.stack([p00, p10, p11], 1), np.stack([p00, p11, p01], 1)]
+                else:
+                    out += [np.stack([p00, p11, p10], 1), np.stack([p00, p01, p11], 1)]
+    return np.concatenate(out, axis=0)
 
 
 def with_triangles(scene: Scene, tri_v: np.ndarray, tri_rgb=None, tri_opacity=None) -> Scene:
@@ -280,13 +332,14 @@ def mixed_tiny_scene(seed: int = 5) -> Scene:
 
 
 def surface_scene(seed: int = 2, every: int = 160, radius: float = 4.0,
-                  subdiv: int = 2) -> Scene:
+                  subdiv: int = 2, rotate: bool = False) -> Scene:
     """Molecular-surface stand-in: closed icosphere blobs (320 triangles at
     subdivision 2) of radius 4 around every 160th position of the protein
     walk -- 83 blobs, 26,560 triangles, about the protein scene's object
-    count -- with the protein scene's two lights."""
+    count -- with the protein scene's two lights.  The blobs keep the
+    icosahedron's orientation unless rotate."""
     pos, _ = random_walk(PROTEIN_SPHERES + 1, PROTEIN_RADIUS, seed)
-    tri = blob_mesh(pos[::every], radius, subdiv, seed=seed)
+    tri = blob_mesh(pos[::every], radius, subdiv, seed=seed, rotate=rotate)
     ld, lc = _lights(2)
     e3 = _empty3()
     s = Scene(e3, np.zeros(0), _empty3(np.float32), e3.copy(), e3.copy(), np.zeros(0),
@@ -294,6 +347,24 @@ def surface_scene(seed: int = 2, every: int = 160, radius: float = 4.0,
     per = 20 * 4 ** subdiv
     rgb = PALETTE[(np.arange(tri.shape[0]) // per) % 4]
     return with_triangles(s, tri, rgb)
+
+
+def voxel_surface_scene(seed: int = 2, every: int = 1100, radius: float = 4.0,
+                        cell: float = 0.5, axis_light: bool = True) -> Scene:
+    """Axis-aligned surface stand-in: voxel surfaces (voxel_mesh, cubes of
+    side 0.5) of radius 4 around every 1100th position of the protein walk
+    (12 blobs).  Lights: the protein scene's two, plus (with axis_light) one
+    along +z, to which the faces along x and y are exactly perpendicular."""
+    pos, _ = random_walk(PROTEIN_SPHERES + 1, PROTEIN_RADIUS, seed)
+    tri = voxel_mesh(pos[::every], radius, cell)
+    ld, lc = _lights(2)
+    if axis_light:
+        ld = np.concatenate([ld, [[0.0, 0.0, 1.0]]])
+        lc = np.concatenate([lc, [[0.5, 0.5, 0.5]]])
+    e3 = _empty3()
+    s = Scene(e3, np.zeros(0), _empty3(np.float32), e3.copy(), e3.copy(), np.zeros(0),
+              _empty3(np.float32), ld, lc)
+    return with_triangles(s, tri)
 
 
 # ---------------------------------------------------------------------------

@@ -93,19 +93,28 @@ def test_protein_1mp_fp32_resolve(tr, oracle_mod, protein):
     assert m["hit_agree"] >= 0.99999
 
 
+@pytest.fixture(scope="module")
+def protein_17mp_ref(oracle_mod, protein):
+    """The oracle's whole 3860x4548 frame (all 17,555,280 pixels)."""
+    s, _ = protein
+    c = scenegen.protein_camera(scenegen.RES_17MP)
+    p = scenegen.Params(ao_samples=16, seed=2)
+    print("oracle 17.6MP full frame", flush=True)
+    return _ref(oracle_mod, s, c, p)
+
+
 @pytest.mark.parametrize("prec", ["fp32_resolve", "fp64"])
-def test_protein_17mp_sampled(tr, oracle_mod, protein, prec):
-    # full 3860x4548 frame in the launch shape the benchmark uses; the oracle
-    # computes a seeded sample of its pixels one by one
+def test_protein_17mp_full(tr, protein, protein_17mp_ref, prec):
+    # the whole 3860x4548 frame, in the launch shape the benchmark times,
+    # against the oracle's whole frame, pixel by pixel
     s, gs = protein
     c = scenegen.protein_camera(scenegen.RES_17MP)
     p = scenegen.Params(ao_samples=16, seed=2)
     print("protein 17.6MP", prec, flush=True)
     got = _gpu(tr, gs, c, p, prec)
-    pix = scenegen.sample_pixels(c.width, c.height, 40000, 17)
-    ref = _ref(oracle_mod, s, c, p, pix=pix)
-    m = compare(flat_at(got, pix), ref, 16, s.n_lights)
-    print(m)
+    m = compare(got, protein_17mp_ref, 16, s.n_lights)
+    print(m, flush=True)
+    assert m["n"] == 3860 * 4548
     if prec == "fp64":
         _fp64_exact(m, None, None)
     else:
@@ -229,6 +238,20 @@ def test_stats_counts(tr, oracle_mod, protein):
             assert st["cells"] < ref["cells"] and st["jumps"] > 0
         for k in keys:
             assert abs(st[k] - ref[k]) <= tol * ref[k] + 2, (prec, k, st[k], ref[k])
+        # hits: the FP32 walk counts the hits it decides itself; a re-solved
+        # test is counted as a re-solve, not as a hit
+        for k in ("sph_hits", "cyl_hits"):
+            assert ref[k] > 0
+            assert abs(st[k] - ref[k]) <= tol * ref[k] + st["resolves"] + 2, (prec, k, st[k], ref[k])
+        if prec == "fp64":
+            assert st["resolves"] == 0
+        else:
+            n_tests = st["sph_tests"] + st["cyl_tests"]
+            print("re-solves", st["resolves"], "of", n_tests, "tests", {
+                k: st[k] for k in ("resolves_sph", "resolves_cyl", "resolves_nearest")})
+            assert st["resolves"] <= 1e-3 * n_tests, st
+            assert st["resolves_sph"] + st["resolves_cyl"] + st["resolves_tri"] == st["resolves"]
+            assert st["resolves_nearest"] <= st["resolves"]
         if prec != "fp64":
             assert st["lane_iters"] <= 64 * st["wave_iters"]
             # every unit of work takes one lane-iteration; only the first cell of
