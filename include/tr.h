@@ -365,6 +365,28 @@ tr_status tr_render_tuned(const tr_scene *scene, const tr_camera *cam, const tr_
 tr_status tr_render_batch(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,
                           const tr_params *params, const tr_frame *frames, void *hip_stream);
 
+/* tr_render_batch for callers that cannot allocate memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same frames as tr_render_batch, bit for bit (same kernels, same rules: one
+ * FP32 precision and one stats buffer for the FP32 jobs, the first FP32 job's
+ * tuning or `tune` when non-NULL; FP64 jobs are rendered one launch each).
+ * The job table and tile counter live in a fixed array of the library's
+ * static device memory, about 21 KB per device (TR_NOALLOC_MAX_JOBS job
+ * records and a counter), held until the process
+ * ends; its address is looked up on the first call on each device.  The
+ * call allocates nothing (no hipMalloc, hipFree, host staging or library
+ * workspace): the table is written by kernels from their arguments, the
+ * counter cleared by a kernel.  Every call on one device shares that array
+ * and leaves its contents behind: calls ordered on one stream are safe;
+ * calls that overlap on one device (unordered streams) race.
+ * TR_EINVAL: n outside 1..TR_NOALLOC_MAX_JOBS, or tr_render_batch's errors;
+ * TR_EUNSUPPORTED: aa_samples > 1 (antialiasing needs a workspace).  Every
+ * job is checked before anything is enqueued. */
+#define TR_NOALLOC_MAX_JOBS 16
+tr_status tr_render_batch_noalloc(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,
+                                  const tr_params *params, const tr_frame *frames,
+                                  const tr_tune *tune, void *hip_stream);
+
 /* Number of 64-pixel tiles of a width x height frame for tile width tile_w
  * (0 = default).  Returns -1 on invalid arguments. */
 int64_t tr_tile_count(int32_t width, int32_t height, int32_t tile_w);

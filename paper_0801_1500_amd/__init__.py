@@ -112,6 +112,7 @@ def lib():
                              C.POINTER(Tune), vp], st),
         "tr_render_batch": ([i32, vp, vp, vp, vp, vp], st),
         "tr_render_batch_tiles": ([i32, vp, vp, vp, vp, vp, vp, C.POINTER(Tune), vp], st),
+        "tr_render_batch_noalloc": ([i32, vp, vp, vp, vp, C.POINTER(Tune), vp], st),
         "tr_tile_count": ([i32, i32, i32], i64),
         "tr_frame_footprint": ([C.POINTER(Camera), C.POINTER(Params), C.c_uint32], C.c_size_t),
         "tr_graph_create": ([i32, vp, vp, vp, vp, C.POINTER(Tune), vp, C.POINTER(vp)], st),
@@ -470,6 +471,21 @@ def render_batch_into(scenes: List[Scene], cams, params, frames: List[dict],
                       precision="fp32_resolve", stream=None):
     n, sc, cm, pr, fr = _arrays(scenes, cams, params, frames, precision)
     _check(lib().tr_render_batch(n, sc, cm, pr, fr, _stream(stream)))
+    return frames
+
+
+NOALLOC_MAX_JOBS = 16  # TR_NOALLOC_MAX_JOBS
+
+
+def render_batch_noalloc_into(scenes: List[Scene], cams, params, frames: List[dict],
+                              precision="fp32_resolve", tune=None, stream=None):
+    """tr_render_batch_noalloc: the batch render that allocates nothing (job
+    table in the library's static device memory; at most NOALLOC_MAX_JOBS
+    jobs, no antialiasing)."""
+    n, sc, cm, pr, fr = _arrays(scenes, cams, params, frames, precision)
+    t = make_tune(tune)
+    _check(lib().tr_render_batch_noalloc(n, sc, cm, pr, fr, C.byref(t) if t is not None else None,
+                                         _stream(stream)))
     return frames
 
 

@@ -1261,6 +1261,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
 
 __global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
 
+// One job table entry written from a kernel argument (the caller's job needs
+// no host staging buffer): the wave copies its 4-byte words.
+static_assert(sizeof(JobDev) % 4 == 0, "JobDev is copied as words");
+__global__ __launch_bounds__(64) void k_put_job(const JobDev J, JobDev *dst) {
+  const uint32_t *src = (const uint32_t *)&J;
+  uint32_t *d = (uint32_t *)dst;
+  for (uint32_t i = threadIdx.x; i < (uint32_t)(sizeof(JobDev) / 4); i += 64) d[i] = src[i];
+}
+
 __global__ void k_debug_philox(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -1334,6 +1343,11 @@ hipError_t launch_render_wave(const WaveLaunch &L, hipStream_t st) {
   if (L.bvh) return L.tri ? launch_bvh_walk<true>(L, st) : launch_bvh_walk<false>(L, st);
   if (L.banks == 3) return launch_b<3>(L, st);
   return launch_b<2>(L, st);
+}
+
+hipError_t launch_put_job(const JobDev &J, JobDev *dst, hipStream_t st) {
+  k_put_job<<<1, 64, 0, st>>>(J, dst);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_counter(uint32_t *p, hipStream_t st) {

@@ -1188,31 +1188,25 @@ static tr_status check_wave_job(const JobDev &J, const tr_tune &t) {
   return TR_OK;
 }
 
-// Launch the wavefront kernel over the jobs (already filled, tiles set).
-static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, uint64_t *stats,
-                                  hipStream_t st) {
-  for (const JobDev &J : jobs) {
-    const tr_status rc = check_wave_job(J, t);
-    if (rc != TR_OK) return rc;
-  }
+// Queue positions of the jobs' tiles; the total tile count.
+static int64_t set_queue(JobDev *jobs, int32_t n) {
   int64_t total = 0;
-  for (auto &J : jobs) {
-    J.queue_begin = total;
-    total += J.tile_end - J.tile_begin;
+  for (int32_t i = 0; i < n; ++i) {
+    jobs[i].queue_begin = total;
+    total += jobs[i].tile_end - jobs[i].tile_begin;
   }
-  if (total == 0) return TR_OK;
-  if (total > (int64_t)UINT32_MAX - 1) return fail(TR_EINVAL, "too many tiles in one launch");
-  LaunchSlot *ls = nullptr;
-  tr_status rc = acquire_slot(st, (int32_t)jobs.size(), &ls);
-  if (rc != TR_OK) return rc;
-  std::memcpy(ls->h_jobs, jobs.data(), sizeof(JobDev) * jobs.size());
-  HIP_TRY(hipMemcpyAsync(ls->d_jobs, ls->h_jobs, sizeof(JobDev) * jobs.size(), hipMemcpyHostToDevice, st));
-  HIP_TRY(trh::launch_fill_u32(ls->d_counter, 2, 0u, st));
+  return total;
+}
+
+// The launch of the wavefront kernel over n jobs (queue set) whose device
+// table and tile counter are given.
+static trh::WaveLaunch wave_launch(const JobDev *jobs, int32_t n, int64_t total, const tr_tune &t,
+                                   uint64_t *stats, const JobDev *d_jobs, uint32_t *d_counter) {
   trh::WaveLaunch L{};
-  L.jobs = ls->d_jobs;
-  L.n_jobs = (int32_t)jobs.size();
+  L.jobs = d_jobs;
+  L.n_jobs = n;
   L.n_tiles = total;
-  L.tile_counter = ls->d_counter;
+  L.tile_counter = d_counter;
   L.stats = stats;
   L.tile_w = t.tile_w;
   L.banks = t.banks;
@@ -1226,11 +1220,32 @@ static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, u
   L.resolve = jobs[0].resolve;
   L.trans = 0;
   L.tri = 0;
-  for (const JobDev &J : jobs) {
-    L.trans |= J.layers > 1;
-    L.tri |= J.sc.n_t > 0;
+  for (int32_t i = 0; i < n; ++i) {
+    L.trans |= jobs[i].layers > 1;
+    L.tri |= jobs[i].sc.n_t > 0;
   }
   L.bvh = t.accel;
+  return L;
+}
+
+// Launch the wavefront kernel over the jobs (already filled, tiles set).
+static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, uint64_t *stats,
+                                  hipStream_t st) {
+  for (const JobDev &J : jobs) {
+    const tr_status rc = check_wave_job(J, t);
+    if (rc != TR_OK) return rc;
+  }
+  const int64_t total = set_queue(jobs.data(), (int32_t)jobs.size());
+  if (total == 0) return TR_OK;
+  if (total > (int64_t)UINT32_MAX - 1) return fail(TR_EINVAL, "too many tiles in one launch");
+  LaunchSlot *ls = nullptr;
+  tr_status rc = acquire_slot(st, (int32_t)jobs.size(), &ls);
+  if (rc != TR_OK) return rc;
+  std::memcpy(ls->h_jobs, jobs.data(), sizeof(JobDev) * jobs.size());
+  HIP_TRY(hipMemcpyAsync(ls->d_jobs, ls->h_jobs, sizeof(JobDev) * jobs.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(trh::launch_fill_u32(ls->d_counter, 2, 0u, st));
+  const trh::WaveLaunch L = wave_launch(jobs.data(), (int32_t)jobs.size(), total, t, stats,
+                                        ls->d_jobs, ls->d_counter);
   HIP_TRY(trh::launch_render_wave(L, st));
   HIP_TRY(hipEventRecord(ls->done, st));
   return TR_OK;
@@ -1344,6 +1359,99 @@ static tr_status batch_impl(int32_t n, const tr_scene *const *scenes, const tr_c
   rc = launch_wave_jobs(jobs, t, stats, st);
   if (rc != TR_OK) return rc;
   return run_aa_means(means, st);
+}
+
+// ----------------------------------------------- allocation-free batches
+// tr_render_batch_noalloc keeps its job table and tile counter in this
+// array of the library's static device memory (each device holds its own
+// copy until the process ends).  In host code `scratch` names a host-side
+// stand-in: its device address is looked up once per device and used
+// instead, everywhere.
+struct NoAllocScratch {
+  JobDev jobs[TR_NOALLOC_MAX_JOBS];
+  uint32_t counter[2];  // tile counter, stall flag
+};
+static __device__ __align__(256) unsigned char scratch[sizeof(NoAllocScratch)];
+constexpr int kMaxDevices = 64;
+static NoAllocScratch *g_scratch[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on each device, with that device current).
+static tr_status scratch_on_device(NoAllocScratch **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(TR_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(TR_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch[dev] = (NoAllocScratch *)ptr;
+  }
+  *out = g_scratch[dev];
+  return TR_OK;
+}
+
+extern "C" tr_status tr_render_batch_noalloc(int32_t n, const tr_scene *const *scenes,
+                                             const tr_camera *cams, const tr_params *params,
+                                             const tr_frame *frames, const tr_tune *tune,
+                                             void *hip_stream) {
+  if (n < 1 || n > TR_NOALLOC_MAX_JOBS)
+    return fail(TR_EINVAL, "tr_render_batch_noalloc: %d jobs (1..%d)", (int)n, TR_NOALLOC_MAX_JOBS);
+  if (!scenes || !cams || !params || !frames) return fail(TR_EINVAL, "NULL batch array");
+  hipStream_t st = (hipStream_t)hip_stream;
+  // the first FP32 job sets the batch's FP32 precision, stats and tuning
+  int32_t f0 = 0;
+  while (f0 < n - 1 && params[f0].precision == TR_PREC_FP64) ++f0;
+  const tr_tune t = pick_tune(scenes[f0], &cams[f0], &params[f0], tune);
+  tr_status rc = check_tune(t);
+  if (rc != TR_OK) return rc;
+  const int res = params[f0].precision == TR_PREC_FP32_RESOLVE;
+  uint64_t *stats = frames[f0].stats;
+  // fixed-size tables on the stack: nothing is allocated
+  JobDev jobs[TR_NOALLOC_MAX_JOBS], f64[TR_NOALLOC_MAX_JOBS];
+  uint64_t *stats64[TR_NOALLOC_MAX_JOBS];
+  int32_t nw = 0, n64 = 0;
+  for (int32_t i = 0; i < n; ++i) {  // every job is checked before anything is enqueued
+    JobDev J;
+    rc = make_job(scenes[i], &cams[i], &params[i], &frames[i], t.tile_w, J);
+    if (rc != TR_OK) return fail(rc, "job %d: %s", i, g_err.c_str());
+    if (aa_count(params[i]) > 1)
+      return fail(TR_EUNSUPPORTED, "job %d: antialiasing needs a workspace (aa_samples <= 1 here)", i);
+    if (params[i].precision == TR_PREC_FP64) {
+      stats64[n64] = frames[i].stats;
+      f64[n64++] = J;
+      continue;
+    }
+    if ((params[i].precision == TR_PREC_FP32_RESOLVE) != (res != 0))
+      return fail(TR_EINVAL, "all FP32 jobs of one batch must use the same precision");
+    if (frames[i].stats != stats) return fail(TR_EINVAL, "all jobs of one batch must share one stats buffer");
+    rc = check_wave_job(J, t);
+    if (rc != TR_OK) return fail(rc, "job %d: %s", i, g_err.c_str());
+    jobs[nw++] = J;
+  }
+  // jobs of one scene adjacent (a stable insertion sort), as in tr_render_batch
+  for (int32_t i = 1; i < nw; ++i)
+    for (int32_t j = i; j > 0 && jobs[j - 1].scene_key > jobs[j].scene_key; --j) std::swap(jobs[j - 1], jobs[j]);
+  const int64_t total = set_queue(jobs, nw);
+  if (total > (int64_t)UINT32_MAX - 1) return fail(TR_EINVAL, "too many tiles in one launch");
+  NoAllocScratch *S = nullptr;
+  if (nw > 0 && total > 0) {
+    rc = scratch_on_device(&S);
+    if (rc != TR_OK) return rc;
+  }
+  for (int32_t k = 0; k < n64; ++k) HIP_TRY(trh::launch_render_plain_f64(f64[k], stats64[k], st));
+  if (!S) return TR_OK;
+  // clear the counter with a kernel (no memset node under graph capture),
+  // write the table from kernel arguments, then render
+  HIP_TRY(trh::launch_fill_u32(S->counter, 2, 0u, st));
+  for (int32_t k = 0; k < nw; ++k) HIP_TRY(trh::launch_put_job(jobs[k], &S->jobs[k], st));
+  const trh::WaveLaunch L = wave_launch(jobs, nw, total, t, stats, S->jobs, S->counter);
+  HIP_TRY(trh::launch_render_wave(L, st));
+  return TR_OK;
 }
 
 extern "C" tr_status tr_render_batch(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,

@@ -121,6 +121,8 @@ struct WaveLaunch {
 };
 hipError_t launch_render_wave(const WaveLaunch &L, hipStream_t st);
 hipError_t launch_zero_counter(uint32_t *p, hipStream_t st);
+// write one job table entry (device memory) from the host's job, by a kernel
+hipError_t launch_put_job(const trd::JobDev &J, trd::JobDev *dst, hipStream_t st);
 
 hipError_t launch_debug_philox(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out,
                                hipStream_t st);
