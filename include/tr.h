@@ -208,6 +208,14 @@ enum {
                                 the rest are shadow and AO rays */
   TR_STAT_SIGNS_F64,         /* triangle hits whose facing, N.L and AO-basis signs were
                                 decided from the FP64 vertices (a sign within 2^-12 of 0) */
+  TR_STAT_CELLS_AO,          /* wavefront kernel: cells entered and primitive tests (with the */
+  TR_STAT_TESTS_AO,          /*   skipped ones) by AO rays ...                               */
+  TR_STAT_CELLS_SHADOW,      /* ... and by light shadow rays (the rest: nearest-hit rays)   */
+  TR_STAT_TESTS_SHADOW,
+  TR_STAT_TESTS_OWN,         /* tests that met the primitive a secondary ray leaves (skipped) */
+  TR_STAT_CYCLES_RESOLVE,    /* wavefront kernel: shader clocks (summed over waves) in the FP64 */
+  TR_STAT_CYCLES_FINISH,     /*   re-solve, finish (shading, write) and refill (queue, ray */
+  TR_STAT_CYCLES_REFILL,     /*   setup) phases; the traversal loop is TR_STAT_CYCLES_TRAVERSE */
   TR_STAT_COUNT
 };
 

@@ -25,7 +25,9 @@ STAT_NAMES = ["pixels", "hit_pixels", "ao_rays", "shadow_rays", "rays_traced", "
               "sph_tests", "sph_hits", "cyl_tests", "cyl_hits", "resolves", "wave_iters",
               "lane_iters", "refills", "jumps", "cycles_traverse", "cycles_total", "tri_tests",
               "tri_hits", "stack_overflows", "stalls", "resolves_sph", "resolves_cyl",
-              "resolves_tri", "resolves_nearest", "signs_f64"]
+              "resolves_tri", "resolves_nearest", "signs_f64", "cells_ao", "tests_ao",
+              "cells_shadow", "tests_shadow", "tests_own", "cycles_resolve", "cycles_finish",
+              "cycles_refill"]
 STAT_COUNT = len(STAT_NAMES)
 
 

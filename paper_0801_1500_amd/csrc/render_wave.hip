@@ -104,7 +104,7 @@ struct Lds {
   uint32_t lmask[NS];
   uint8_t fifo[NS];
   BankInfo bank[BANKS];
-  uint32_t cnt[19];
+  uint32_t cnt[24];
   // compositing across surfaces: colour so far, transmittance in front of the
   // current surface, its index, and whether the FIFO entry is a continuation
   float acc_r[NT], acc_g[NT], acc_b[NT], trn[NT];
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
   const int32_t lane = threadIdx.x;
   const int32_t TW = A.tile_w;
   const int32_t TH = 64 / TW;
-  if (lane < 19) L.cnt[lane] = 0;
+  if (lane < 24) L.cnt[lane] = 0;
 
   // ---- wave-uniform control state
   int32_t q_head = 0, q_tail = 0, head_issued = 0;
@@ -394,8 +394,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
   uint32_t l_tt = 0, l_th = 0, l_ovf = 0;
   uint32_t l_rs = 0, l_rc = 0, l_rt = 0, l_rn = 0;  // re-solves: sphere, cylinder, triangle, nearest-hit rays
   uint32_t l_sg = 0;  // triangle hits whose sign decisions were taken in FP64
+  // by ray kind: cells entered and tests by AO and shadow rays; tests of the
+  // primitive a secondary ray leaves (skipped, but an iteration spent)
+  uint32_t l_cells_ao = 0, l_tests_ao = 0, l_cells_sh = 0, l_tests_sh = 0, l_own = 0;
   uint64_t c_iters = 0, c_lanes = 0, c_refills = 0;
-  uint64_t c_cyc_trav = 0;
+  uint64_t c_cyc_trav = 0, c_cyc_res = 0, c_cyc_fin = 0, c_cyc_ref = 0;  // shader clocks by phase
   const uint64_t c_cyc_start = COUNT ? clock64() : 0;
 
   // ---- per-lane state
@@ -411,6 +414,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
 
   for (;;) {
     // ============================================================ re-solve
+    const uint64_t cyc_r0 = COUNT ? clock64() : 0;
     if (RESOLVE && ballot(st == kPaused)) {
       if (st == kPaused) {
         const int32_t bk = slot >> 6;
@@ -451,6 +455,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       }
     }
 
+    const uint64_t cyc_f0 = COUNT ? clock64() : 0;
+    if (COUNT) c_cyc_res += cyc_f0 - cyc_r0;
     // ================================================================ finish
     if (ballot(kind != kIdle && st == kDone)) {
       const bool fin = kind != kIdle && st == kDone;
@@ -690,6 +696,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       }
     }
 
+    const uint64_t cyc_q0 = COUNT ? clock64() : 0;
+    if (COUNT) c_cyc_fin += cyc_q0 - cyc_f0;
     // ================================================================ refill
     {
       const uint64_t idle = ballot(kind == kIdle);
@@ -896,9 +904,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       }
       c_rays += (uint64_t)assigned;
       if (COUNT) ++c_refills;
-      if (COUNT) l_cells += (me_idle && kind != kIdle && setup_ok) ? 1u : 0u;
+      if (COUNT) {
+        const uint32_t entered = (me_idle && kind != kIdle && setup_ok) ? 1u : 0u;
+        l_cells += entered;
+        l_cells_ao += kind == kAO ? entered : 0u;
+        l_cells_sh += kind == kShadow ? entered : 0u;
+      }
     }
 
+    if (COUNT) c_cyc_ref += clock64() - cyc_q0;
     // ================================================================ exit
     {
       const uint64_t busy = ballot(kind != kIdle);
@@ -1051,7 +1065,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
                 (uint32_t)R.cy >= (uint32_t)H.res[1] || (uint32_t)R.cz >= (uint32_t)H.res[2]) {
               st = kDone;
             } else {
-              if (COUNT) ++l_cells;
+              if (COUNT) {
+                ++l_cells;
+                l_cells_ao += kind == kAO;
+                l_cells_sh += kind == kShadow;
+              }
               enter = true;
             }
           }
@@ -1148,6 +1166,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           const bool live = nk != R.skip && !(TRI && own && nk >= H.n_sc);
           hit = hit && live;
           graze = graze && live;
+          if (COUNT) {
+            l_own += !live;
+            l_tests_ao += kind == kAO;
+            l_tests_sh += kind == kShadow;
+          }
           if (COUNT && live) {
             if (nk < H.n_s) {
               ++l_st;
@@ -1223,6 +1246,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         atomicAdd(&L.cnt[17], l_rn);
       }
       if (TRI) atomicAdd(&L.cnt[18], l_sg);
+      atomicAdd(&L.cnt[19], l_cells_ao);
+      atomicAdd(&L.cnt[20], l_tests_ao);
+      atomicAdd(&L.cnt[21], l_cells_sh);
+      atomicAdd(&L.cnt[22], l_tests_sh);
+      atomicAdd(&L.cnt[23], l_own);
     }
     __syncthreads();
     if (lane == 0) {
@@ -1252,8 +1280,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         atomicAdd(&st[TR_STAT_RESOLVES_TRI], (unsigned long long)L.cnt[16]);
         atomicAdd(&st[TR_STAT_RESOLVES_NEAREST], (unsigned long long)L.cnt[17]);
         atomicAdd(&st[TR_STAT_SIGNS_F64], (unsigned long long)L.cnt[18]);
+        atomicAdd(&st[TR_STAT_CELLS_AO], (unsigned long long)L.cnt[19]);
+        atomicAdd(&st[TR_STAT_TESTS_AO], (unsigned long long)L.cnt[20]);
+        atomicAdd(&st[TR_STAT_CELLS_SHADOW], (unsigned long long)L.cnt[21]);
+        atomicAdd(&st[TR_STAT_TESTS_SHADOW], (unsigned long long)L.cnt[22]);
+        atomicAdd(&st[TR_STAT_TESTS_OWN], (unsigned long long)L.cnt[23]);
         atomicAdd(&st[TR_STAT_CYCLES_TRAVERSE], (unsigned long long)c_cyc_trav);
         atomicAdd(&st[TR_STAT_CYCLES_TOTAL], (unsigned long long)(clock64() - c_cyc_start));
+        atomicAdd(&st[TR_STAT_CYCLES_RESOLVE], (unsigned long long)c_cyc_res);
+        atomicAdd(&st[TR_STAT_CYCLES_FINISH], (unsigned long long)c_cyc_fin);
+        atomicAdd(&st[TR_STAT_CYCLES_REFILL], (unsigned long long)c_cyc_ref);
       }
     }
   }
