@@ -97,19 +97,20 @@ struct Lds {
   int32_t skip[NS];     // secondary rays: k >= 0 skip primitive k; -2 - k: k is the surface
                         // they leave from inside (far root only); -1 = none
   int32_t pending[NS];  // secondary rays not yet finished
-  int32_t nrays[NS];    // secondary rays of the slot
   uint32_t lvalid[NS];  // lights with N.L > 0
   uint32_t aomask[NS];
   int32_t aocnt[NS];
   uint32_t lmask[NS];
-  uint8_t fifo[NS];
+  // FIFO of slots with secondary rays to issue, one word each: slot (bits
+  // 0-7), lights with N.L > 0 (8-11), continuation (12), AO rays (16-31);
+  // the refill reads an entry with one load
+  uint32_t fifo[NS];
   BankInfo bank[BANKS];
   uint32_t cnt[24];
   // compositing across surfaces: colour so far, transmittance in front of the
   // current surface, its index, and whether the FIFO entry is a continuation
   float acc_r[NT], acc_g[NT], acc_b[NT], trn[NT];
   uint8_t layer[NT];
-  uint8_t cont[NT];
   // BVH walk: per lane a stack of node / leaf items, entry e at e * 64 + lane
   int32_t stk[BVH ? 64 * kStack : 1];
 };
@@ -465,6 +466,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       const bool fin_prim_miss = fin && nearest && R.bk < 0;
       bool finalize = fin_prim_miss;
       uint32_t nr = 0;
+      uint32_t fifo_e = 0;  // FIFO word of a hit slot with secondary rays
       // every bank in flight renders the wave's current scene
       const SceneHot S = load_hot(&A.jobs[uni(scene_job)]);
       if (fin_prim_hit) {
@@ -528,6 +530,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           }
         }
         nr = (uint32_t)Bk.S + (uint32_t)__popc(lv);
+        fifo_e = (uint32_t)slot | ((uint32_t)__popc(lv) << 8) | ((uint32_t)Bk.S << 16);
         L.px[slot] = Px;
         L.py[slot] = Py;
         L.pz[slot] = Pz;
@@ -544,18 +547,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         // exact arithmetic.
         L.skip[slot] = front ? k : -2 - k;
         L.pending[slot] = (int32_t)nr;
-        L.nrays[slot] = (int32_t)nr;
         L.lvalid[slot] = lv;
         L.aomask[slot] = 0;
         L.aocnt[slot] = 0;
         L.lmask[slot] = 0;
-        if (TRANS) L.cont[slot] = 0;
         if (nr == 0) finalize = true;
       }
-      {  // queue hit slots that have secondary rays
+      {  // queue hit slots that have secondary rays: S AO rays, then one per lit light
         const bool enq = fin_prim_hit && nr > 0;
         const uint64_t m = ballot(enq);
-        if (enq) L.fifo[(q_tail + (int32_t)lane_rank(m)) % NS] = (uint8_t)slot;
+        if (enq) L.fifo[(q_tail + (int32_t)lane_rank(m)) % NS] = fifo_e;
         q_tail += __popcll(m);
       }
       if (fin && kind >= kShadow) {  // secondary results
@@ -651,9 +652,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             L.layer[slot] = (uint8_t)(layer + 1);
             // entering it: its own far side counts, its start does not
             L.skip[slot] = L.skip[slot] >= 0 ? -2 - L.prim[slot] : L.prim[slot];
-            L.nrays[slot] = 1;
             L.pending[slot] = 1;
-            L.cont[slot] = 1;
             cont_next = true;
           } else {
             cr = ar + Tn * B.bg[0];
@@ -671,7 +670,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       }
       if (TRANS) {  // continuations join the FIFO like slots with secondary rays
         const uint64_t m = ballot(cont_next);
-        if (cont_next) L.fifo[(q_tail + (int32_t)lane_rank(m)) % NS] = (uint8_t)slot;
+        if (cont_next)  // one continuation ray
+          L.fifo[(q_tail + (int32_t)lane_rank(m)) % NS] = (uint32_t)slot | (1u << 8) | (1u << 12);
         q_tail += __popcll(m);
       }
       {  // pixel counters live in LDS (registers are the scarce resource here)
@@ -710,10 +710,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       int32_t n_ao = 0;    // AO rays among the secondary rays issued this round
       int32_t n_cont = 0;  // continuations through transparent surfaces
       while (assigned < n_idle && q_head != q_tail) {
-        const int32_t s = uni((int32_t)L.fifo[q_head % NS]);
-        const int32_t nr = uni(L.nrays[s]);
-        const bool cs = TRANS && uni((int32_t)L.cont[s]) != 0;
-        const int32_t S_s = cs ? 0 : uni(L.bank[s >> 6].S);
+        const uint32_t e = (uint32_t)uni((int32_t)L.fifo[q_head % NS]);
+        const int32_t s = (int32_t)(e & 0xFFu);
+        const bool cs = TRANS && ((e >> 12) & 1u) != 0;
+        const int32_t S_s = (int32_t)(e >> 16);
+        const int32_t nr = S_s + (int32_t)((e >> 8) & 0xFu);
         const int32_t take = min(nr - head_issued, n_idle - assigned);
         if (me_idle && rank >= assigned && rank < assigned + take) {
           slot = s;
