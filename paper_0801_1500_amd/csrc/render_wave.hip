@@ -85,6 +85,26 @@ __device__ __forceinline__ void bank_pixel(const BankInfo &B, int32_t q, int32_t
   y = B.y0 + qy;
 }
 
+// Write bank b's finished tile to the frame from the colours its slots hold
+// in px, py, pz.  Lane l stores floats l, l + 64, l + 128 of the tile taken
+// row by row, so each tile row is one contiguous run of 12 vw bytes written
+// together (one 12-byte store per pixel as pixels finish, spread over many
+// rounds, leaves the L2 to write partly filled lines back several times).
+template <typename LdsT>
+__device__ __forceinline__ void write_tile(const LdsT &L, int32_t b, int32_t lane) {
+  const BankInfo &B = L.bank[b];
+  const int32_t nf = 3 * B.n;
+  float *const base = B.rgb + ((int64_t)B.y0 * B.W + B.x0) * 3;
+  for (int32_t f = lane; f < nf; f += 64) {
+    const int32_t q = f / 3, c = f - 3 * q;  // pixel of the bank, colour channel
+    const int32_t qy = (int32_t)(__umul24((uint32_t)q, (uint32_t)B.vmagic) >> 16);
+    const int32_t qx = q - (int32_t)__umul24((uint32_t)qy, (uint32_t)B.vw);
+    const int32_t s = b * 64 + q;
+    const float v = c == 0 ? L.px[s] : (c == 1 ? L.py[s] : L.pz[s]);
+    base[((int64_t)qy * B.W + qx) * 3 + c] = v;
+  }
+}
+
 constexpr int kStack = trh::kBvhStack;  // BVH traversal stack entries per lane
 
 template <int BANKS, bool TRANS, bool BVH>
@@ -382,6 +402,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
   int32_t issue_bank = -1, issue_next = 0;
   uint32_t bank_busy = 0;
   bool tiles_left = true;
+  int32_t xq = (int32_t)(blockIdx.x % kQueueXcds);  // tile queue drawn from: this XCD's first
+  int32_t xq_left = kQueueXcds;                       // queues not yet found drained
   int64_t held_tile = -1;
   int32_t held_job = 0, held_key = -1;
   int32_t cur_key = -1;   // scene loaded in this wave
@@ -661,10 +683,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           }
         }
         if (!cont_next) {
-          float *rgb = B.rgb + pid * 3;
-          rgb[0] = cr;
-          rgb[1] = cg;
-          rgb[2] = cb;
+          // the colour waits in the slot, whose hit point is spent, until the
+          // whole tile goes out at once
+          L.px[slot] = cr;
+          L.py[slot] = cg;
+          L.pz[slot] = cb;
           atomicAdd(&B.done, 1);
         }
       }
@@ -690,6 +713,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         const int32_t n_b = uni(L.bank[b].n);
         const bool all_issued = issue_bank != b || issue_next == n_b;
         if (all_issued && uni(L.bank[b].done) == n_b) {
+          write_tile(L, b, lane);
           bank_busy &= ~(1u << b);
           if (issue_bank == b) issue_bank = -1;
         }
@@ -740,14 +764,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           const uint32_t free_banks = ~bank_busy & ((1u << BANKS) - 1u);
           if (!free_banks) break;
           if (held_tile < 0) {
-            if (!tiles_left) break;
-            uint32_t t = 0;
-            if (lane == 0) t = atomicAdd(A.tile_counter, 1u);
-            t = (uint32_t)uni((int32_t)t);
-            if ((int64_t)t >= A.n_tiles) {
-              tiles_left = false;
-              break;
+            int64_t t = -1;
+            while (tiles_left) {
+              // the j-th tile of XCD queue q: stripe j / stripe of q's share
+              uint32_t j = 0;
+              if (lane == 0) j = atomicAdd(A.tile_counter + xq * kQueueStride, 1u);
+              j = (uint32_t)uni((int32_t)j);
+              const int64_t g = ((int64_t)(j / kQueueStripe) * kQueueXcds + xq) * kQueueStripe +
+                                (int64_t)(j % kQueueStripe);
+              if (g < A.n_tiles) {
+                t = g;
+                break;
+              }
+              // this queue is drained for good (its tiles only grow with j)
+              if (--xq_left == 0) tiles_left = false;
+              xq = xq + 1 == kQueueXcds ? 0 : xq + 1;
             }
+            if (t < 0) break;
             held_tile = t;
             held_job = uni(find_job((const TR_CONST JobDev *)A.jobs, A.n_jobs, held_tile));
             held_key = uni(A.jobs[held_job].scene_key);
@@ -920,7 +953,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       if (!busy) {
         if (!tiles_left && held_tile < 0 && bank_busy == 0 && q_head == q_tail) break;
         if (++idle_rounds > 4) {  // cannot happen when the bookkeeping is right
-          if (lane == 0) atomicAdd(A.tile_counter + 1, 1u);
+          if (lane == 0) atomicAdd(A.tile_counter + kQueueXcds * kQueueStride, 1u);
           stalled = true;
           break;
         }

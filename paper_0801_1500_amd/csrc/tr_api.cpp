@@ -1006,7 +1006,7 @@ static tr_status make_job(const tr_scene *s, const tr_camera *c, const tr_params
 struct LaunchSlot {
   JobDev *h_jobs = nullptr;
   JobDev *d_jobs = nullptr;
-  uint32_t *d_counter = nullptr;  // [0] tile counter, [1] stall flag
+  uint32_t *d_counter = nullptr;  // tile queue counters + stall flag (kQueueWords)
   int32_t cap = 0;
   hipEvent_t done = nullptr;
   bool used = false;
@@ -1049,7 +1049,7 @@ static tr_status acquire_slot(hipStream_t st, int32_t n, LaunchSlot **out) {
     HIP_TRY(hipMalloc((void **)&ls.d_jobs, sizeof(JobDev) * cap));
     ls.cap = cap;
   }
-  if (!ls.d_counter) HIP_TRY(hipMalloc((void **)&ls.d_counter, 2 * sizeof(uint32_t)));
+  if (!ls.d_counter) HIP_TRY(hipMalloc((void **)&ls.d_counter, trd::kQueueWords * sizeof(uint32_t)));
   ls.used = true;
   *out = &ls;
   return TR_OK;
@@ -1243,7 +1243,7 @@ static tr_status launch_wave_jobs(std::vector<JobDev> &jobs, const tr_tune &t, u
   if (rc != TR_OK) return rc;
   std::memcpy(ls->h_jobs, jobs.data(), sizeof(JobDev) * jobs.size());
   HIP_TRY(hipMemcpyAsync(ls->d_jobs, ls->h_jobs, sizeof(JobDev) * jobs.size(), hipMemcpyHostToDevice, st));
-  HIP_TRY(trh::launch_fill_u32(ls->d_counter, 2, 0u, st));
+  HIP_TRY(trh::launch_fill_u32(ls->d_counter, trd::kQueueWords, 0u, st));
   const trh::WaveLaunch L = wave_launch(jobs.data(), (int32_t)jobs.size(), total, t, stats,
                                         ls->d_jobs, ls->d_counter);
   HIP_TRY(trh::launch_render_wave(L, st));
@@ -1369,7 +1369,7 @@ static tr_status batch_impl(int32_t n, const tr_scene *const *scenes, const tr_c
 // instead, everywhere.
 struct NoAllocScratch {
   JobDev jobs[TR_NOALLOC_MAX_JOBS];
-  uint32_t counter[2];  // tile counter, stall flag
+  uint32_t counter[trd::kQueueWords];  // tile queue counters, stall flag
 };
 static __device__ __align__(256) unsigned char scratch[sizeof(NoAllocScratch)];
 constexpr int kMaxDevices = 64;
@@ -1447,7 +1447,7 @@ extern "C" tr_status tr_render_batch_noalloc(int32_t n, const tr_scene *const *s
   if (!S) return TR_OK;
   // clear the counter with a kernel (no memset node under graph capture),
   // write the table from kernel arguments, then render
-  HIP_TRY(trh::launch_fill_u32(S->counter, 2, 0u, st));
+  HIP_TRY(trh::launch_fill_u32(S->counter, trd::kQueueWords, 0u, st));
   for (int32_t k = 0; k < nw; ++k) HIP_TRY(trh::launch_put_job(jobs[k], &S->jobs[k], st));
   const trh::WaveLaunch L = wave_launch(jobs, nw, total, t, stats, S->jobs, S->counter);
   HIP_TRY(trh::launch_render_wave(L, st));
@@ -1631,7 +1631,7 @@ extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, c
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t e = hipHostMalloc((void **)&g->h_jobs, sizeof(JobDev) * n, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc((void **)&g->d_jobs, sizeof(JobDev) * n);
-  if (e == hipSuccess) e = hipMalloc((void **)&g->d_counter, 2 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc((void **)&g->d_counter, trd::kQueueWords * sizeof(uint32_t));
   if (e == hipSuccess) e = hipEventCreateWithFlags(&g->staged, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&g->launched, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(g->staged, st);
@@ -1650,7 +1650,7 @@ extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, c
   e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    e = trh::launch_fill_u32(g->d_counter, 2, 0u, cap);
+    e = trh::launch_fill_u32(g->d_counter, trd::kQueueWords, 0u, cap);
     trh::WaveLaunch L{};
     L.jobs = g->d_jobs;
     L.n_jobs = n;

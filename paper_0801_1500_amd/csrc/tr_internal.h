@@ -110,7 +110,7 @@ struct WaveLaunch {
   const trd::JobDev *jobs;   // device array
   int32_t n_jobs;
   int64_t n_tiles;           // total tiles in the queue
-  uint32_t *tile_counter;    // device, zeroed before the launch
+  uint32_t *tile_counter;    // device, trd::kQueueWords words zeroed before the launch
   uint64_t *stats;           // device or null
   int32_t tile_w, banks, refill_below, count_ops, cyl_wait, mix;
   int32_t n_waves;           // persistent waves launched
