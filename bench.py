@@ -27,18 +27,27 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Algorithmic flop model of the grid method (FP32-equivalent operations; FMA
-# = 2; add, mul, min, max, compare, sqrt, rcp, sin, cos = 1), per counted event.
-FLOP_COST = dict(ray_setup=40, cell=4, jump=16, sph_test=22, sph_hit=4, cyl_test=45, cyl_hit=12,
+# = 2; add, mul, min, max, compare, sqrt, rcp, sin, cos = 1), per counted
+# event: ray setup + DDA init, DDA step (a cell entered), sphere test (+ hit),
+# cylinder test (+ hit), primary ray generation, normal + facing, per light,
+# orthonormal basis, AO direction, final shade.
+FLOP_COST = dict(ray_setup=40, cell=4, sph_test=22, sph_hit=4, cyl_test=45, cyl_hit=12,
                  primary_gen=20, normal=10, per_light=8, onb=12, ao_dir=23, shade=10)
+# An empty-space jump (skipping up to 32 empty cells at once) is not in the
+# table; the variant that prices each jump as a re-initialised DDA step is
+# reported beside the table's figure, never in its place.
+JUMP_COST = 16
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6  # without packed-FP32 issue
 PEAK_HBM_GBS = 8000.0
+GRID_LAMBDA = 24.0  # grid cells per primitive of the benchmarked scene (the library default)
+ORBIT_LAMBDAS = (8.0, 16.0, 24.0, 32.0, 48.0)  # grid densities the orbit graph is tuned over
 
 
-def algorithmic_flops(st: dict, n_lights: int, ao_on: bool) -> float:
+def algorithmic_flops(st: dict, n_lights: int, ao_on: bool, jump_cost: int = 0) -> float:
     c = FLOP_COST
     return float(c["ray_setup"] * st["rays_traced"] + c["cell"] * st["cells"]
-                 + c["jump"] * st.get("jumps", 0)
+                 + jump_cost * st.get("jumps", 0)
                  + c["sph_test"] * st["sph_tests"] + c["sph_hit"] * st["sph_hits"]
                  + c["cyl_test"] * st["cyl_tests"] + c["cyl_hit"] * st["cyl_hits"]
                  + c["primary_gen"] * st["pixels"] + c["normal"] * st["hit_pixels"]
@@ -81,43 +90,76 @@ def measured_issue():
     return {k: d[k] for k in ("valu_issue_frac", "salu_issue_frac", "active_lanes_per_valu_inst")}
 
 
-def cpu_baseline(scene, cam, params, target_s: float = 15.0) -> dict:
-    """The oracle, as it stands, on a bounded sample of the same frame: evenly
-    spaced full rows, sized to about target_s seconds of CPU work."""
-    import numpy as np
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    import oracle
-    oracle.build(force=False)
-    grid = oracle.Grid(scene, 4.0)
+
+def _rows_sample(oracle, scene, cam, params, grid, target_s: float, n_threads: int):
+    """Render evenly spaced full rows sized to about target_s seconds."""
+    import numpy as np
     W, H = cam.width, cam.height
-    threads = oracle.max_threads()
-    # calibrate on a few rows
-    rows = np.arange(0, H, max(H // 16, 1))[:16]
+    rows = np.arange(0, H, max(H // 8, 1))[:8]
     pix = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
     t0 = time.perf_counter()
-    r = oracle.render(scene, cam, params, grid=grid, pix=pix)
-    dt = time.perf_counter() - t0
-    per_row = dt / len(rows)
+    oracle.render(scene, cam, params, grid=grid, pix=pix, n_threads=n_threads)
+    per_row = (time.perf_counter() - t0) / len(rows)
     n_rows = int(min(H, max(len(rows), target_s / max(per_row, 1e-9))))
     rows = np.unique(np.linspace(0, H - 1, n_rows).round().astype(np.int64))
     pix = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
     t0 = time.perf_counter()
-    r = oracle.render(scene, cam, params, grid=grid, pix=pix)
-    dt = time.perf_counter() - t0
-    cnt = r["counters"]
+    r = oracle.render(scene, cam, params, grid=grid, pix=pix, n_threads=n_threads)
+    return r, time.perf_counter() - t0, len(rows)
+
+
+def cpu_baseline(scene, cam, params, cells_per_prim: float, target_s: float = 20.0,
+                 one_thread_s: float = 8.0) -> tuple:
+    """The oracle, as it stands, on the same frame with the GPU's grid density:
+    the whole frame on every host thread when that takes under target_s
+    (else evenly spaced full rows sized to it), then evenly spaced rows on one
+    thread for the per-core rate.  Returns (baseline record, the oracle's
+    frame or None when sampled, its traversal counters)."""
+    import oracle
+    oracle.build(force=False)
+    grid = oracle.Grid(scene, cells_per_prim)
+    W, H = cam.width, cam.height
+    threads = oracle.max_threads()
+    # one calibration row batch decides whether the whole frame fits
+    _, dt_rows, n_rows = _rows_sample(oracle, scene, cam, params, grid, 0.5, threads)
+    if dt_rows / n_rows * H <= target_s:
+        t0 = time.perf_counter()
+        ref = oracle.render(scene, cam, params, grid=grid)
+        dt, rows_used = time.perf_counter() - t0, H
+    else:
+        ref, dt, rows_used = _rows_sample(oracle, scene, cam, params, grid, target_s, threads)
+    cnt = ref["counters"]
     rays = cnt["primary_rays"] + cnt["ao_rays"]
-    return {"value": rays / dt, "unit": "rays/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d of %d rows (every ~%d-th row, %d pixels) of the same 3860x4548 frame, "
-                      "FP64, OpenMP over pixels, %.1f s" % (len(rows), H, max(H // len(rows), 1),
-                                                            len(pix), dt),
-            "seconds": dt, "rays": rays, "shadow_rays": cnt["shadow_rays"]}
+    r1, dt1, rows1 = _rows_sample(oracle, scene, cam, params, grid, one_thread_s, 1)
+    c1 = r1["counters"]
+    rays1 = c1["primary_rays"] + c1["ao_rays"]
+    out = {"value": rays / dt, "unit": "rays/s", "cores": int(threads), "kind": "oracle",
+           "sample": "%s of the same %dx%d frame (%d of %d rows), FP64 oracle on its uniform "
+                     "grid at %g cells per primitive (the GPU's), OpenMP over pixels on %d "
+                     "threads, %.1f s" % ("the whole" if rows_used == H else "evenly spaced rows",
+                                           W, H, rows_used, H, cells_per_prim, threads, dt),
+           "seconds": dt, "rays": rays, "shadow_rays": cnt["shadow_rays"],
+           "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+           "one_thread": {"value": rays1 / dt1, "unit": "rays/s", "rows": rows1,
+                          "seconds": dt1, "rays": rays1}}
+    return out, (ref if rows_used == H else None), cnt, dt
 
 
-def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
+def orbit_measure(tr, torch, scenegen, launches: int = 3) -> dict:
     """64 views of the 1,000,000-object walk scene at 1920x1080, 32 AO
-    samples, captured once into a hipGraph; time graph launches with the
-    default launch shape and with the shape autotuned on one view, and report
-    the faster."""
+    samples, captured once into a hipGraph; the graph is timed with the
+    default launch shape, then tuned on itself (grid density over ORBIT_LAMBDAS
+    and launch shape, tr_graph_autotune) and timed again: the tuned figure is
+    the orbit's."""
     scene = scenegen.orbit_scene()
     gs = tr.Scene(scene)
     cams = scenegen.orbit_cameras()
@@ -128,8 +170,7 @@ def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
         f["stats"] = stats
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    def time_graph(tune):
-        g = tr.Graph([gs] * len(cams), cams, params, frames, tune=tune)
+    def time_graph(g):
         g.launch()
         torch.cuda.synchronize()
         stats.zero_()
@@ -138,20 +179,16 @@ def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
             g.launch()
         e1.record()
         torch.cuda.synchronize()
-        g.destroy()
         return e0.elapsed_time(e1) / launches, dict(zip(tr.STAT_NAMES, stats.cpu().tolist()))
 
-    # the launch shape autotuned on one view (frames are bit-identical for
-    # every shape; the tuner checks it), against the default shape
-    # The tuner decides on one view; the graph renders 64, so both graphs are
-    # timed and the faster one is the orbit's figure.
-    tuned, _ = tr.autotune(gs, cams[0], params[0])
-    ms_default, st_default = time_graph(tr.default_tune())
-    ms_tuned, st_tuned = time_graph(tuned)
-    if ms_tuned < ms_default:
-        ms, st, used = ms_tuned, st_tuned, tuned
-    else:
-        ms, st, used = ms_default, st_default, tr.default_tune()
+    g = tr.Graph([gs] * len(cams), cams, params, frames)
+    ms_default, _ = time_graph(g)
+    t0 = time.perf_counter()
+    used, lam, _ = g.autotune(lambdas=ORBIT_LAMBDAS)
+    tune_s = time.perf_counter() - t0
+    ms, st = time_graph(g)
+    g.destroy()
+    gs.rebuild(GRID_LAMBDA)
     rays = (st["pixels"] + st["ao_rays"]) / launches
     # the sparse scene with and without empty-space skipping: 8 views per batch
     sub = [tr.alloc_frame(c, ("rgb",), stats=False) for c in cams[:8]]
@@ -174,8 +211,9 @@ def orbit_measure(tr, torch, scenegen, launches: int = 2) -> dict:
     return {"workload": "1,000,000-object walk (ball radius 250), 64 views of 1920x1080 per "
                         "graph launch, 32 AO samples, FP32 + FP64 re-solve",
             "ms_per_launch": ms, "views_per_s": 64 * 1000.0 / ms, "rays_per_launch": rays,
-            "tune": used, "tune_from_one_view": tuned, "ms_per_launch_default_tune": ms_default,
-            "ms_per_launch_one_view_tune": ms_tuned,
+            "tune": used, "cells_per_prim": lam if lam > 0 else GRID_LAMBDA,
+            "lambdas_tried": list(ORBIT_LAMBDAS), "tuning_s": tune_s,
+            "ms_per_launch_default_tune": ms_default,
             "rays_per_s": rays / (ms * 1e-3),
             "walk_8_views": walks, "bvh_8_views": bvh, "precision_8_views": prec}
 
@@ -404,25 +442,53 @@ def variants_measure(tr, torch, scenegen, np, gs, scene, cam, params, prec, log)
     return aa, spec, trans, tris
 
 
-def serving_measure(tr, torch, scenegen, seconds: float, rate: float = 50.0) -> dict:
-    """Poisson arrivals (mean `rate` per second) of render jobs over a pool
-    of 16 resident walk scenes of 2k-200k objects, resolutions uniform over
-    {256x256, 965x1137, 1920x1080}, 4-32 AO samples, 64 GB frame budget."""
+def serving_measure(tr, torch, scenegen, seconds: float, warmup: float = 5.0,
+                    rate: float = 50.0, small_seconds: float = 20.0,
+                    small_budget: int = 1920 * 1080 * 12, burst_jobs: int = 400) -> dict:
+    """Render serving over a pool of 16 resident walk scenes of 2k-200k
+    objects, requests at resolutions uniform over {256x256, 965x1137,
+    1920x1080} with 4-32 AO samples:
+    - Poisson arrivals (mean `rate` per second) at the 64 GB frame budget:
+      `warmup` seconds of the stream, not reported, then `seconds` seconds;
+    - the same arrival process for `small_seconds` under a forced small frame
+      budget (`small_budget` bytes, one 1920x1080 frame), where a request
+      that arrives while others are on the GPU waits for memory;
+    - a burst of `burst_jobs` requests arriving at once, which keeps the GPU
+      saturated: continuous batching under full load (latency here is the
+      time from the burst to each job's completion)."""
     from paper_0801_1500_amd.serve import Job, Server
     pool = scenegen.serving_pool()
     gpool = [tr.Scene(s) for s in pool]
     radii = [scenegen.serving_radius(s.n_prims) for s in pool]
-    n_jobs = int(round(seconds * rate))
-    reqs = scenegen.serving_requests(radii, n_jobs, rate_hz=rate, seed=3)
-    jobs = [Job(i, t, si, cam, p) for i, (t, si, cam, p) in enumerate(reqs)]
+
+    def jobs_of(reqs, t_shift=0.0, at_once=False):
+        return [Job(i, 0.0 if at_once else t - t_shift, si, cam, p)
+                for i, (t, si, cam, p) in enumerate(reqs)]
+
+    n_warm, n_main = int(round(warmup * rate)), int(round(seconds * rate))
+    reqs = scenegen.serving_requests(radii, n_warm + n_main, rate_hz=rate, seed=3)
     srv = Server(gpool, hbm_budget=64 << 30)
-    # warm-up on a few jobs, then the timed stream
-    srv.run([Job(-1 - i, 0.0, j.scene, j.camera, j.params) for i, j in enumerate(jobs[:8])],
-            realtime=False)
-    st = srv.run(jobs, realtime=True)
-    out = st.summary()
-    out["workload"] = ("Poisson %.0f req/s, %d jobs, 16 resident scenes of 2k-200k objects, "
-                       "256x256 / 965x1137 / 1920x1080, 4-32 AO samples" % (rate, n_jobs))
+    if n_warm:
+        srv.run(jobs_of(reqs[:n_warm]), realtime=True)
+    t_start = reqs[n_warm - 1][0] if n_warm else 0.0
+    out = srv.run(jobs_of(reqs[n_warm:], t_shift=t_start), realtime=True).summary()
+    out["workload"] = ("Poisson %.0f req/s, %d jobs over %.0f s after a %.0f s warm-up of %d jobs, "
+                       "64 GB frame budget, 16 resident scenes of 2k-200k objects, 256x256 / "
+                       "965x1137 / 1920x1080, 4-32 AO samples" % (rate, n_main, seconds, warmup,
+                                                                   n_warm))
+    if small_seconds > 0:
+        sreqs = scenegen.serving_requests(radii, int(round(small_seconds * rate)), rate_hz=rate,
+                                          seed=4)
+        small = Server(gpool, hbm_budget=small_budget).run(jobs_of(sreqs), realtime=True).summary()
+        small["workload"] = ("Poisson %.0f req/s, %d jobs, forced %.1f MiB frame budget "
+                             "(one 1920x1080 frame)" % (rate, len(sreqs), small_budget / 2**20))
+        out["small_budget"] = small
+    if burst_jobs > 0:
+        breqs = scenegen.serving_requests(radii, burst_jobs, rate_hz=rate, seed=5)
+        burst = Server(gpool, hbm_budget=64 << 30).run(jobs_of(breqs, at_once=True),
+                                                       realtime=False).summary()
+        burst["workload"] = "%d requests arriving at once, 64 GB frame budget" % burst_jobs
+        out["burst"] = burst
     return out
 
 
@@ -434,7 +500,11 @@ def main():
     ap.add_argument("--fp64-frames", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape first")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-warmup", type=float, default=5.0,
+                    help="seconds of the serving stream before the measured window")
+    ap.add_argument("--serve-small-seconds", type=float, default=20.0,
+                    help="length of the forced small-budget serving run (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson serving run (0 = skip)")
     ap.add_argument("--no-orbit", action="store_true", help="skip the 1M-object orbit run")
     ap.add_argument("--no-variants", action="store_true",
@@ -457,7 +527,7 @@ def main():
     cam = scenegen.protein_camera(scenegen.RES_17MP)
     params = scenegen.Params(ao_samples=16, seed=2)
     prec = "fp32_resolve"
-    gs = tr.Scene(scene)
+    gs = tr.Scene(scene, cells_per_prim=GRID_LAMBDA)
     stream = torch.cuda.current_stream()
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
     log("scene built", gs.grid_info()[2].tolist(), "refs", gs.grid_info()[3])
@@ -512,16 +582,10 @@ def main():
     ms_per_step = wall * 1000.0 / K
     value = rays_timed / wall
 
-    achieved = flops_frame / (render_ms.mean() * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
-                "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
-                "kernel": "k_render_wave", "kernel_ms": float(render_ms.mean()),
-                "flop_per_frame": flops_frame, "flop_per_counted_ray": flops_frame / rays_frame,
-                "issue": measured_issue()}
-    if roofline["traffic"] is not None:  # measured HBM bytes over the live kernel time
-        roofline["hbm_GBps"] = roofline["traffic"] / (render_ms.mean() * 1e-3) / 1e9
-        roofline["hbm_frac"] = roofline["hbm_GBps"] / PEAK_HBM_GBS
+    kernel_ms = float(render_ms.mean())
+    gpu_rgb = frame["rgb"].cpu().numpy()  # the last timed frame, for the parity block
+    peak = tr.measure_fp32_peak()
+    log("measured FP32 FMA peak", peak)
 
     # plain FP64 GPU path on the same frame
     fp64 = None
@@ -573,14 +637,57 @@ def main():
     serving = None
     if args.serve_seconds > 0:
         log("serving stream ...")
-        serving = serving_measure(tr, torch, scenegen, args.serve_seconds)
+        serving = serving_measure(tr, torch, scenegen, args.serve_seconds, args.serve_warmup,
+                                  small_seconds=args.serve_small_seconds)
         log("serving", serving)
 
-    cpu = None
+    cpu = ref = ocnt = None
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(scene, cam, params)
-        log("cpu baseline", cpu["value"], "rays/s on", cpu["cores"], "threads")
+        cpu, ref, ocnt, _ = cpu_baseline(scene, cam, params, GRID_LAMBDA)
+        log("cpu baseline", cpu)
+
+    # roofline of the render kernel: the flop table over the kernel's own
+    # counters, over the kernel's mean duration in the timed steps
+    achieved = flops_frame / (kernel_ms * 1e-3) / 1e12
+    flops_jump = algorithmic_flops(st, scene.n_lights, ao_on, JUMP_COST)
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
+                "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+                "peak_measured": peak["tflops"], "frac_measured": achieved / peak["tflops"],
+                "peak_measured_how": "non-packed FP32 FMA chains on every lane, 32 waves per CU "
+                                     "(tr_measure_fp32_peak), reported clock %.0f MHz, %d CUs"
+                                     % (peak["clock_mhz"], peak["n_cus"]),
+                "kernel": "k_render_wave", "kernel_ms": kernel_ms,
+                "flop_per_frame": flops_frame, "flop_per_counted_ray": flops_frame / rays_frame,
+                "flop_model": "cost table per op over the kernel's own counters: cells entered, "
+                              "sphere/cylinder tests and hits, rays, pixels, hit pixels, lights, "
+                              "AO directions; empty-space jumps not priced",
+                "with_jump_cost": {"jump_cost": JUMP_COST, "flop_per_frame": flops_jump,
+                                   "achieved": flops_jump / (kernel_ms * 1e-3) / 1e12,
+                                   "frac": flops_jump / (kernel_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS},
+                "oracle_counts": None, "issue": measured_issue()}
+    if ocnt is not None:
+        # the same table over the oracle's plain-DDA counts at the GPU's grid
+        # density (every cell on a ray's path is a step there), per counted ray
+        o_rays = ocnt["primary_rays"] + ocnt["ao_rays"]
+        f_ray = algorithmic_flops(ocnt, scene.n_lights, ao_on) / o_rays
+        o_ach = f_ray * rays_frame / (kernel_ms * 1e-3) / 1e12
+        roofline["oracle_counts"] = {"flop_per_counted_ray": f_ray,
+                                     "flop_per_frame": f_ray * rays_frame, "achieved": o_ach,
+                                     "frac": o_ach / PEAK_FP32_TFLOPS,
+                                     "cells_per_counted_ray": ocnt["cells"] / o_rays,
+                                     "counted_rays": o_rays}
+    if roofline["traffic"] is not None:  # measured HBM bytes over the live kernel time
+        roofline["hbm_GBps"] = roofline["traffic"] / (kernel_ms * 1e-3) / 1e9
+        roofline["hbm_frac"] = roofline["hbm_GBps"] / PEAK_HBM_GBS
+    parity = None
+    if ref is not None:  # the GPU frame against the oracle's, whole frame
+        d = np.abs(gpu_rgb.astype(np.float64) - ref["rgb"])
+        parity = {"pixels": int(d.shape[0] * d.shape[1]), "max_abs_all": float(d.max()),
+                  "rms_all": float(np.sqrt(np.mean(d * d))),
+                  "frac_pixels_over_1e-3": float(np.mean(d.max(axis=2) > 1e-3))}
+        del d, ref
 
     out = {
         "metric": "rays/sec (primary+AO) and frames/s at 17.6 MP AO; p50/p99 frame latency",
@@ -612,6 +719,7 @@ def main():
         "orbit": orbit,
         "serving": serving,
         "roofline": roofline,
+        "parity_vs_oracle": parity,
         "cpu_baseline": cpu,
         "paper_context": "Tachyon on 6144 Blue Gene/L processors: 2.6416 s per 17.6 MP AO frame "
                          "(0.379 frames/s), 822x a 3 GHz Pentium IV (Table 3)",

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define TR_ABI_VERSION 3
+#define TR_ABI_VERSION 4
 
 typedef enum {
   TR_OK = 0,
@@ -240,6 +240,9 @@ typedef struct {
                                 near-tie in FP32 can settle differently (tested:
                                 >= 99.99% of pixels with the same hit and masks,
                                 the same colour wherever they agree). */
+  int32_t stripe;            /* tiles per stripe of the tile queue, a power of two 1..1024:
+                                stripe s of the frame's row-major tiles goes to XCD s mod 8,
+                                whose waves take it before the other XCDs' stripes */
 } tr_tune;
 
 /* ---------------------------------------------------------------- scenes */
@@ -495,8 +498,45 @@ void tr_graph_destroy(tr_graph *g);
 tr_status tr_autotune(const tr_scene *scene, const tr_camera *cam, const tr_params *params,
                       void *hip_stream, tr_tune *best, double *best_ms);
 
+/* Tune a captured graph on itself (all its views, as it replays): the
+ * scenes' grid density, which changes speed only (the paper leaves the grid
+ * resolution free, Sec. 2), then the launch shape.  Each density in
+ * lambdas[0 .. n_lambdas) (cells per primitive, finite and > 0; n_lambdas
+ * 0..64) is tried by rebuilding every scene of the graph at it (a density
+ * whose grid cannot be built is skipped); the fastest is kept, or the
+ * scenes' own densities when none beats them.  Then one pass of coordinate
+ * descent over tile width {4, 8, 16}, banks {2, 3}, waves per compute unit
+ * {12, 16, 20, 24}, refill threshold {24, 32, 40, 48} and queue stripe {16,
+ * 32, 64, 128, 256}, and the winner re-timed against the default shape,
+ * interleaved, median of 5 each; the faster is kept.  Every candidate is
+ * timed as the median of 3 replays after a warm-up and must leave the first
+ * and last frames bit-identical to the starting graph's (else TR_EDEVICE).
+ * Afterwards the graph is re-captured with the choice and its scenes are at
+ * the chosen density; the frames hold the last replay's images and the stats
+ * buffer (if any) has accumulated every replay.  Nothing else may use the
+ * graph's scenes meanwhile.  *best (the shape), *best_lambda (0 = the
+ * scenes' own densities kept) and *best_ms (its replay time) may be NULL.
+ * Synchronises the stream; TR_EINVAL on a NULL graph or a bad density list. */
+tr_status tr_graph_autotune(tr_graph *g, int32_t n_lambdas, const double *lambdas,
+                            void *hip_stream, tr_tune *best, double *best_lambda, double *best_ms);
+
 /* Default launch shape for the current device. */
 tr_status tr_default_tune(tr_tune *out);
+
+/* ---------------------------------------------------------- measurement */
+
+/* Measured FP32 multiply-add rate of the current device, in TFLOP/s (FMA = 2
+ * flops): every lane of 32 waves per compute unit runs 16 independent chains
+ * of non-packed FMAs (the form the render kernel issues; packed FP32 is
+ * disabled in all of the library's device code), best of 5 timed launches
+ * after a warm-up.  Not part of the paper's method: the measured peak that
+ * the render kernel's FP32 throughput is reported against, beside the chip's
+ * published 157.3 (packed) and 78.6 (non-packed) TFLOP/s.  *clock_mhz (may
+ * be NULL) receives the device's reported peak engine clock and *n_cus its
+ * compute units (may be NULL).  Synchronises the stream; allocates and frees
+ * a small device buffer.  TR_EINVAL on a NULL tflops. */
+tr_status tr_measure_fp32_peak(void *hip_stream, double *tflops, double *clock_mhz,
+                               int32_t *n_cus);
 
 /* ---------------------------------------------------------------- debug */
 

@@ -71,7 +71,7 @@ class Frame(C.Structure):
 class Tune(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("banks", C.c_int32), ("waves_per_cu", C.c_int32),
                 ("refill_below", C.c_int32), ("count_ops", C.c_int32), ("cyl_wait", C.c_int32),
-                ("mix", C.c_int32), ("accel", C.c_int32)]
+                ("mix", C.c_int32), ("accel", C.c_int32), ("stripe", C.c_int32)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -121,9 +121,13 @@ def lib():
         "tr_graph_update": ([vp, vp, vp, vp], st),
         "tr_graph_launch": ([vp, vp], st),
         "tr_graph_destroy": ([vp], None),
+        "tr_graph_autotune": ([vp, i32, vp, vp, C.POINTER(Tune), C.POINTER(C.c_double),
+                               C.POINTER(C.c_double)], st),
         "tr_autotune": ([vp, C.POINTER(Camera), C.POINTER(Params), vp, C.POINTER(Tune),
                          C.POINTER(C.c_double)], st),
         "tr_default_tune": ([C.POINTER(Tune)], st),
+        "tr_measure_fp32_peak": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.POINTER(i32)], st),
         "tr_debug_philox": ([i64, vp, vp, vp, vp], st),
         "tr_debug_ao_dirs": ([i64, vp, vp, vp, C.c_uint32, C.c_uint64, vp, vp], st),
         "tr_last_error": ([], C.c_char_p),
@@ -189,7 +193,8 @@ def make_tune(tune) -> Optional[Tune]:
     return Tune(int(tune.get("tile_w", 0)), int(tune.get("banks", 0)),
                 int(tune.get("waves_per_cu", 0)), int(tune.get("refill_below", 0)),
                 int(tune.get("count_ops", 0)), int(tune.get("cyl_wait", 0)),
-                int(tune.get("mix", 0)), int(tune.get("accel", 0)))
+                int(tune.get("mix", 0)), int(tune.get("accel", 0)),
+                int(tune.get("stripe", 0)))
 
 
 class Scene:
@@ -585,6 +590,17 @@ class Graph:
     def launch(self, stream=None):
         _check(lib().tr_graph_launch(self.handle, _stream(stream)))
 
+    def autotune(self, lambdas=(), stream=None):
+        """Tune the graph on itself: its scenes' grid density over `lambdas`
+        (cells per primitive), then the launch shape.  Returns (tune dict,
+        chosen density or 0.0 when the scenes kept their own, ms per replay);
+        the graph and its scenes keep the choice."""
+        lam = (C.c_double * max(len(lambdas), 1))(*[float(x) for x in lambdas])
+        t, bl, ms = Tune(), C.c_double(), C.c_double()
+        _check(lib().tr_graph_autotune(self.handle, len(lambdas), lam, _stream(stream),
+                                       C.byref(t), C.byref(bl), C.byref(ms)))
+        return t.as_dict(), float(bl.value), float(ms.value)
+
     def destroy(self):
         if getattr(self, "handle", None):
             lib().tr_graph_destroy(self.handle)
@@ -611,6 +627,14 @@ def default_tune() -> dict:
     t = Tune()
     _check(lib().tr_default_tune(C.byref(t)))
     return t.as_dict()
+
+
+def measure_fp32_peak(stream=None) -> dict:
+    """Measured non-packed FP32 FMA rate of the current device (TFLOP/s),
+    with the device's reported peak clock (MHz) and compute units."""
+    tf, mhz, cus = C.c_double(), C.c_double(), C.c_int32()
+    _check(lib().tr_measure_fp32_peak(_stream(stream), C.byref(tf), C.byref(mhz), C.byref(cus)))
+    return {"tflops": float(tf.value), "clock_mhz": float(mhz.value), "n_cus": int(cus.value)}
 
 
 def debug_philox(ctr, key, stream=None):

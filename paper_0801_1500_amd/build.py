@@ -26,6 +26,7 @@ SOURCES = {
     "render_plain.hip": ["-ffp-contract=off"],
     "render_wave.hip": ["-ffp-contract=on"],
     "frame_out.hip": ["-ffp-contract=off"],
+    "measure.hip": ["-ffp-contract=off"],
     "tr_api.cpp": ["-ffp-contract=off", "-x", "hip"],
 }
 

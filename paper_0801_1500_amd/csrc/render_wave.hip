@@ -371,6 +371,7 @@ struct WaveArgs {
   uint32_t *tile_counter;
   uint64_t *stats;
   int32_t tile_w, refill_below, cyl_wait, mix;
+  int32_t stripe_log2;  // tiles per stripe of the tile queue, log2
 };
 
 __device__ __forceinline__ int32_t find_job(const TR_CONST JobDev *jobs, int32_t n, int64_t tile) {
@@ -766,12 +767,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           if (held_tile < 0) {
             int64_t t = -1;
             while (tiles_left) {
-              // the j-th tile of XCD queue q: stripe j / stripe of q's share
+              // the j-th tile of queue xq: tile j mod stripe of the queue's
+              // stripe j / stripe, which is stripe (j / stripe) 8 + xq overall
               uint32_t j = 0;
               if (lane == 0) j = atomicAdd(A.tile_counter + xq * kQueueStride, 1u);
               j = (uint32_t)uni((int32_t)j);
-              const int64_t g = ((int64_t)(j / kQueueStripe) * kQueueXcds + xq) * kQueueStripe +
-                                (int64_t)(j % kQueueStripe);
+              const int32_t sl = A.stripe_log2;
+              const int64_t g = ((((int64_t)(j >> sl)) * kQueueXcds + xq) << sl) +
+                                (int64_t)(j & ((1u << sl) - 1u));
               if (g < A.n_tiles) {
                 t = g;
                 break;
@@ -1375,6 +1378,7 @@ static hipError_t launch_t(const WaveLaunch &L, hipStream_t st) {
   a.tile_w = L.tile_w;
   a.refill_below = L.refill_below;
   a.cyl_wait = L.cyl_wait;
+  a.stripe_log2 = __builtin_ctz((unsigned)L.stripe);
   a.mix = L.mix;
   k_render_wave<BANKS, RES, CNT, TRANS, TRI, BVH><<<L.n_waves, 64, 0, st>>>(a);
   return hipGetLastError();

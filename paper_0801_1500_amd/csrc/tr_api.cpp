@@ -870,6 +870,7 @@ static tr_status default_tune(tr_tune *t) {
   t->cyl_wait = 64;
   t->mix = 16;
   t->accel = 0;
+  t->stripe = 64;
   return TR_OK;
 }
 
@@ -881,6 +882,8 @@ static tr_status check_tune(const tr_tune &t) {
   if (t.cyl_wait < 1 || t.cyl_wait > 64) return fail(TR_EINVAL, "tune.cyl_wait must be 1..64");
   if (t.mix < 1 || t.mix > 64) return fail(TR_EINVAL, "tune.mix must be 1..64");
   if (t.accel != 0 && t.accel != 1) return fail(TR_EINVAL, "tune.accel must be 0 or 1");
+  if (t.stripe < 1 || t.stripe > 1024 || (t.stripe & (t.stripe - 1)))
+    return fail(TR_EINVAL, "tune.stripe must be a power of two 1..1024");
   return TR_OK;
 }
 
@@ -1089,6 +1092,7 @@ static tr_tune pick_tune(const tr_scene *s, const tr_camera *c, const tr_params 
     if (!t.refill_below) t.refill_below = d.refill_below;
     if (!t.cyl_wait) t.cyl_wait = d.cyl_wait;
     if (!t.mix) t.mix = d.mix;
+    if (!t.stripe) t.stripe = d.stripe;
     return t;
   }
   if (s && c && p) {
@@ -1214,6 +1218,7 @@ static trh::WaveLaunch wave_launch(const JobDev *jobs, int32_t n, int64_t total,
   L.count_ops = t.count_ops;
   L.cyl_wait = t.cyl_wait;
   L.mix = t.mix;
+  L.stripe = t.stripe;
   int64_t waves = (int64_t)num_cus() * t.waves_per_cu;
   if (waves > total) waves = total;
   L.n_waves = (int32_t)waves;
@@ -1584,6 +1589,74 @@ static tr_status graph_upload(tr_graph *g, hipStream_t st) {
   return TR_OK;
 }
 
+// Capture the graph's launch for its current jobs and tune: the counter
+// reset (a kernel, not a memset node) and the persistent launch.  Any
+// previous capture is dropped once its replays have run.
+static tr_status graph_capture(tr_graph *g) {
+  HIP_TRY(hipEventSynchronize(g->launched));
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  g->exec = nullptr;
+  g->graph = nullptr;
+  const int32_t n = g->n;
+  hipStream_t cap = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    e = trh::launch_fill_u32(g->d_counter, trd::kQueueWords, 0u, cap);
+    trh::WaveLaunch L{};
+    L.jobs = g->d_jobs;
+    L.n_jobs = n;
+    L.n_tiles = g->total_tiles;
+    L.tile_counter = g->d_counter;
+    L.stats = g->frames[0].stats;
+    L.tile_w = g->tune.tile_w;
+    L.banks = g->tune.banks;
+    L.refill_below = g->tune.refill_below;
+    L.count_ops = g->tune.count_ops;
+    L.cyl_wait = g->tune.cyl_wait;
+    L.mix = g->tune.mix;
+    L.stripe = g->tune.stripe;
+    int64_t waves = (int64_t)num_cus() * g->tune.waves_per_cu;
+    if (waves > g->total_tiles) waves = g->total_tiles;
+    L.n_waves = (int32_t)std::max<int64_t>(waves, 1);
+    L.resolve = g->params[0].precision == TR_PREC_FP32_RESOLVE;
+    L.trans = 0;
+    L.tri = 0;
+    for (int32_t i = 0; i < n; ++i) L.tri |= g->jobs[i].sc.n_t > 0;
+    L.bvh = g->tune.accel;
+    if (e == hipSuccess) e = trh::launch_render_wave(L, cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &g->graph);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (cap) (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) return fail(TR_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  return TR_OK;
+}
+
+// Re-make the graph's jobs for tune t (its tile width sets the tile grid and
+// the queue offsets), upload the table and capture the launch anew.
+static tr_status graph_retune(tr_graph *g, const tr_tune &t, hipStream_t st) {
+  tr_status rc = check_tune(t);
+  if (rc != TR_OK) return rc;
+  std::vector<JobDev> nj(g->n);
+  int64_t total = 0;
+  for (int32_t i = 0; i < g->n; ++i) {
+    rc = make_job(g->scenes[i], &g->cams[i], &g->params[i], &g->frames[i], t.tile_w, nj[i]);
+    if (rc == TR_OK) rc = check_wave_job(nj[i], t);
+    if (rc != TR_OK) return fail(rc, "job %d: %s", i, g_err.c_str());
+    nj[i].queue_begin = total;
+    total += nj[i].tile_end;
+  }
+  g->jobs = nj;
+  g->total_tiles = total;
+  g->tune = t;
+  rc = graph_upload(g, st);
+  if (rc != TR_OK) return rc;
+  return graph_capture(g);
+}
+
 extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, const tr_camera *cams,
                                      const tr_params *params, const tr_frame *frames,
                                      const tr_tune *tune, void *hip_stream, tr_graph **out) {
@@ -1645,41 +1718,10 @@ extern "C" tr_status tr_graph_create(int32_t n, const tr_scene *const *scenes, c
     free_graph(g);
     return rc;
   }
-  // capture: counter reset (a kernel, not a memset node) + persistent launch
-  hipStream_t cap = nullptr;
-  e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    e = trh::launch_fill_u32(g->d_counter, trd::kQueueWords, 0u, cap);
-    trh::WaveLaunch L{};
-    L.jobs = g->d_jobs;
-    L.n_jobs = n;
-    L.n_tiles = total;
-    L.tile_counter = g->d_counter;
-    L.stats = frames[0].stats;
-    L.tile_w = g->tune.tile_w;
-    L.banks = g->tune.banks;
-    L.refill_below = g->tune.refill_below;
-    L.count_ops = g->tune.count_ops;
-    L.cyl_wait = g->tune.cyl_wait;
-    L.mix = g->tune.mix;
-    int64_t waves = (int64_t)num_cus() * g->tune.waves_per_cu;
-    if (waves > total) waves = total;
-    L.n_waves = (int32_t)std::max<int64_t>(waves, 1);
-    L.resolve = res;
-    L.trans = 0;
-    L.tri = 0;
-    for (int32_t i = 0; i < n; ++i) L.tri |= g->jobs[i].sc.n_t > 0;
-    L.bvh = g->tune.accel;
-    if (e == hipSuccess) e = trh::launch_render_wave(L, cap);
-    hipError_t e2 = hipStreamEndCapture(cap, &g->graph);
-    if (e == hipSuccess) e = e2;
-  }
-  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-  if (cap) (void)hipStreamDestroy(cap);
-  if (e != hipSuccess) {
+  rc = graph_capture(g);
+  if (rc != TR_OK) {
     free_graph(g);
-    return fail(TR_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    return rc;
   }
   *out = g;
   return TR_OK;
@@ -1734,6 +1776,192 @@ extern "C" void tr_graph_destroy(tr_graph *g) {
 extern "C" tr_status tr_default_tune(tr_tune *out) {
   if (!out) return fail(TR_EINVAL, "NULL out");
   return default_tune(out);
+}
+
+// Tuning a captured graph on itself: grid density first, then the launch
+// shape by coordinate descent, then the winner against the default shape.
+namespace {
+struct GraphTuner {
+  tr_graph *g;
+  hipStream_t st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  size_t px0 = 0, pxn = 0;
+  std::vector<float> ref0, refn, cur0, curn;
+  ~GraphTuner() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+  tr_status init() {
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    px0 = (size_t)g->cams[0].width * g->cams[0].height;
+    pxn = (size_t)g->cams[g->n - 1].width * g->cams[g->n - 1].height;
+    ref0.resize(3 * px0);
+    refn.resize(3 * pxn);
+    cur0.resize(3 * px0);
+    curn.resize(3 * pxn);
+    return TR_OK;
+  }
+  // one warm-up replay, then the median of 3 timed replays
+  tr_status time(double &ms) {
+    tr_status rc = tr_graph_launch(g, st);
+    if (rc != TR_OK) return rc;
+    double t[3];
+    for (int k = 0; k < 3; ++k) {
+      HIP_TRY(hipEventRecord(e0, st));
+      rc = tr_graph_launch(g, st);
+      if (rc != TR_OK) return rc;
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float f = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&f, e0, e1));
+      t[k] = f;
+    }
+    std::sort(t, t + 3);
+    ms = t[1];
+    return TR_OK;
+  }
+  tr_status read(std::vector<float> &a, std::vector<float> &b) {
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpy(a.data(), g->frames[0].rgb, 12 * px0, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(b.data(), g->frames[g->n - 1].rgb, 12 * pxn, hipMemcpyDeviceToHost));
+    return TR_OK;
+  }
+  // time the graph as it stands and check its first and last frames
+  tr_status trial(double &ms, const char *what) {
+    tr_status rc = time(ms);
+    if (rc == TR_OK) rc = read(cur0, curn);
+    if (rc != TR_OK) return rc;
+    if (std::memcmp(cur0.data(), ref0.data(), 12 * px0) != 0 ||
+        std::memcmp(curn.data(), refn.data(), 12 * pxn) != 0)
+      return fail(TR_EDEVICE, "graph autotune: %s changed the frames", what);
+    return TR_OK;
+  }
+};
+}  // namespace
+
+extern "C" tr_status tr_graph_autotune(tr_graph *g, int32_t n_lambdas, const double *lambdas,
+                                       void *hip_stream, tr_tune *best, double *best_lambda,
+                                       double *best_ms) {
+  if (!g) return fail(TR_EINVAL, "NULL graph");
+  if (n_lambdas < 0 || n_lambdas > 64 || (n_lambdas > 0 && !lambdas))
+    return fail(TR_EINVAL, "tr_graph_autotune: n_lambdas must be 0..64 with a lambda array");
+  for (int32_t i = 0; i < n_lambdas; ++i)
+    if (!(lambdas[i] > 0.0) || !std::isfinite(lambdas[i]))
+      return fail(TR_EINVAL, "tr_graph_autotune: lambda %d must be finite and > 0", i);
+  GraphTuner T{g, (hipStream_t)hip_stream};
+  tr_status rc = T.init();
+  if (rc != TR_OK) return rc;
+  // the graph's scenes, each once, with their own densities
+  std::vector<tr_scene *> uniq;
+  std::vector<double> own;
+  for (const tr_scene *s : g->scenes) {
+    tr_scene *m = const_cast<tr_scene *>(s);
+    if (std::find(uniq.begin(), uniq.end(), m) == uniq.end()) {
+      uniq.push_back(m);
+      own.push_back(m->lambda);
+    }
+  }
+  double cur_ms = 0.0;
+  rc = T.time(cur_ms);
+  if (rc == TR_OK) rc = T.read(T.ref0, T.refn);
+  if (rc != TR_OK) return rc;
+  // grid density: every scene at one candidate density (0 = their own)
+  double lam = 0.0;
+  auto set_lambda = [&](double l) -> tr_status {
+    HIP_TRY(hipStreamSynchronize(T.st));
+    for (size_t k = 0; k < uniq.size(); ++k) {
+      const tr_status r = tr_scene_rebuild(uniq[k], l > 0.0 ? l : own[k], T.st);
+      if (r != TR_OK) return r;
+    }
+    return tr_graph_update(g, nullptr, nullptr, T.st);
+  };
+  for (int32_t i = 0; i < n_lambdas; ++i) {
+    rc = set_lambda(lambdas[i]);
+    double ms = 0.0;
+    if (rc == TR_OK) rc = T.trial(ms, "a grid density");
+    else if (rc == TR_EUNSUPPORTED || rc == TR_ENOMEM) {  // that grid cannot be built: skip it
+      rc = set_lambda(lam);
+      if (rc != TR_OK) return rc;
+      continue;
+    }
+    if (rc != TR_OK) return rc;
+    if (ms < cur_ms) {
+      cur_ms = ms;
+      lam = lambdas[i];
+    }
+  }
+  rc = set_lambda(lam);
+  if (rc != TR_OK) return rc;
+  // launch shape: one pass of coordinate descent
+  tr_tune cur = g->tune;
+  const std::vector<std::vector<int32_t>> axes = {
+      {4, 8, 16}, {2, 3}, {12, 16, 20, 24}, {24, 32, 40, 48}, {16, 32, 64, 128, 256}};
+  rc = T.trial(cur_ms, "the starting shape");  // re-time after the density change
+  if (rc != TR_OK) return rc;
+  for (size_t ax = 0; ax < axes.size(); ++ax) {
+    for (int32_t v : axes[ax]) {
+      tr_tune t = cur;
+      int32_t *field = ax == 0   ? &t.tile_w
+                       : ax == 1 ? &t.banks
+                       : ax == 2 ? &t.waves_per_cu
+                       : ax == 3 ? &t.refill_below
+                                 : &t.stripe;
+      if (*field == v) continue;
+      *field = v;
+      rc = graph_retune(g, t, T.st);
+      double ms = 0.0;
+      if (rc == TR_OK) rc = T.trial(ms, "a launch shape");
+      if (rc != TR_OK) return rc;
+      if (ms < cur_ms) {
+        cur_ms = ms;
+        cur = t;
+      }
+    }
+  }
+  // the winner against the default shape, interleaved, median of 5 each
+  tr_tune def;
+  default_tune(&def);
+  def.count_ops = cur.count_ops;
+  def.accel = cur.accel;
+  if (std::memcmp(&def, &cur, sizeof(tr_tune)) != 0) {
+    double a[5], b[5];
+    for (int rep = 0; rep < 5; ++rep) {
+      rc = graph_retune(g, def, T.st);
+      if (rc == TR_OK) rc = T.trial(a[rep], "the default shape");
+      if (rc == TR_OK) rc = graph_retune(g, cur, T.st);
+      if (rc == TR_OK) rc = T.trial(b[rep], "a launch shape");
+      if (rc != TR_OK) return rc;
+    }
+    std::sort(a, a + 5);
+    std::sort(b, b + 5);
+    if (a[2] <= b[2]) {
+      cur = def;
+      cur_ms = a[2];
+    } else {
+      cur_ms = b[2];
+    }
+  }
+  rc = graph_retune(g, cur, T.st);
+  if (rc != TR_OK) return rc;
+  HIP_TRY(hipStreamSynchronize(T.st));
+  if (best) *best = cur;
+  if (best_lambda) *best_lambda = lam;
+  if (best_ms) *best_ms = cur_ms;
+  return TR_OK;
+}
+
+extern "C" tr_status tr_measure_fp32_peak(void *hip_stream, double *tflops, double *clock_mhz,
+                                          int32_t *n_cus) {
+  if (!tflops) return fail(TR_EINVAL, "tr_measure_fp32_peak: NULL tflops");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  HIP_TRY(trh::measure_fma_rate((hipStream_t)hip_stream, prop.multiProcessorCount, tflops));
+  if (clock_mhz) *clock_mhz = prop.clockRate * 1e-3;
+  if (n_cus) *n_cus = prop.multiProcessorCount;
+  return TR_OK;
 }
 
 extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr_params *p,
@@ -1810,7 +2038,8 @@ extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr
   }
   // coordinate descent over the launch-shape axes
   const std::vector<std::vector<int32_t>> axes = {
-      {4, 8, 16, 32}, {2, 3}, {8, 12, 16, 20, 24, 32}, {16, 24, 32, 40, 48, 56}, {2, 8, 64}, {1, 16, 32, 48, 64}};
+      {4, 8, 16, 32}, {2, 3}, {8, 12, 16, 20, 24, 32}, {16, 24, 32, 40, 48, 56}, {2, 8, 64}, {1, 16, 32, 48, 64},
+      {16, 32, 64, 128, 256}};
   for (int pass = 0; pass < 2; ++pass) {
     for (size_t ax = 0; ax < axes.size(); ++ax) {
       for (int32_t v : axes[ax]) {
@@ -1820,7 +2049,8 @@ extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr
                          : ax == 2 ? &t.waves_per_cu
                          : ax == 3 ? &t.refill_below
                          : ax == 4 ? &t.cyl_wait
-                                   : &t.mix;
+                         : ax == 5 ? &t.mix
+                                   : &t.stripe;
         if (*field == v) continue;
         *field = v;
         double ms = 0;
@@ -1837,8 +2067,8 @@ extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr
         if (std::memcmp(h_a.data(), h_b.data(), px * 12) != 0 ||
             std::memcmp(i_a.data(), i_b.data(), px * 4) != 0) {
           cleanup();
-          return fail(TR_EDEVICE, "autotune: launch shape (%d,%d,%d,%d,%d,%d) changed the frame",
-                      t.tile_w, t.banks, t.waves_per_cu, t.refill_below, t.cyl_wait, t.mix);
+          return fail(TR_EDEVICE, "autotune: launch shape (%d,%d,%d,%d,%d,%d,%d) changed the frame",
+                      t.tile_w, t.banks, t.waves_per_cu, t.refill_below, t.cyl_wait, t.mix, t.stripe);
         }
         if (ms < cur_ms) {
           cur_ms = ms;

@@ -40,8 +40,8 @@ constexpr double kLightMin = 0x1p-40;
 // ------------------------------------------------------------ tile queue
 // Workgroups are dispatched to the chip's 8 XCDs in turn (workgroup i on XCD
 // i mod 8), and each XCD has an L2 of its own.  The wavefront kernel's tile
-// queue deals the tiles out in stripes of kQueueStripe consecutive tiles,
-// stripe s to XCD s mod 8, with one counter per XCD (each on a 128-byte line
+// queue deals the tiles out in stripes of consecutive tiles (a power of two,
+// tuned; 64 by default), stripe s to XCD s mod 8, with one counter per XCD (each on a 128-byte line
 // of its own), so tiles side by side -- which share cache lines of the frame
 // and most of the cells their rays visit -- go through the same L2.  A wave
 // drains its own XCD's counter first and then the others' in turn: the
@@ -49,7 +49,6 @@ constexpr double kLightMin = 0x1p-40;
 // dispatch order.  The word after the counters' lines is the stall flag.
 constexpr int kQueueXcds = 8;
 constexpr int kQueueStride = 32;  // words from one counter to the next
-constexpr int kQueueStripe = 64;
 constexpr int kQueueWords = (kQueueXcds + 1) * kQueueStride;
 
 // ----------------------------------------------------------------- scene

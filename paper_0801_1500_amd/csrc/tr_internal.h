@@ -113,6 +113,7 @@ struct WaveLaunch {
   uint32_t *tile_counter;    // device, trd::kQueueWords words zeroed before the launch
   uint64_t *stats;           // device or null
   int32_t tile_w, banks, refill_below, count_ops, cyl_wait, mix;
+  int32_t stripe;            // tiles per tile-queue stripe (a power of two)
   int32_t n_waves;           // persistent waves launched
   int32_t resolve;
   int32_t trans;             // some job composites transparent layers
@@ -123,6 +124,9 @@ hipError_t launch_render_wave(const WaveLaunch &L, hipStream_t st);
 hipError_t launch_zero_counter(uint32_t *p, hipStream_t st);
 // write one job table entry (device memory) from the host's job, by a kernel
 hipError_t launch_put_job(const trd::JobDev &J, trd::JobDev *dst, hipStream_t st);
+
+// FP32 FMA rate (TFLOP/s) of non-packed v_fma_f32 over the whole device
+hipError_t measure_fma_rate(hipStream_t st, int32_t n_cus, double *tflops);
 
 hipError_t launch_debug_philox(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *out,
                                hipStream_t st);

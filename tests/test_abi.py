@@ -39,7 +39,7 @@ def test_every_declared_symbol_exported(tr):
     L = tr.lib()
     for n in _declared():
         assert hasattr(L, n), n
-    assert tr.abi_version() == 3
+    assert tr.abi_version() == 4
 
 
 def test_stat_names_follow_the_header(tr):

@@ -122,6 +122,51 @@ def test_autotune_choice_is_bit_identical(tr, scenes):
     assert ms > 0 and best["tile_w"] in (4, 8, 16, 32)
 
 
+def test_graph_autotune_keeps_frames(tr):
+    # the graph is tuned on itself (grid density, then launch shape): every
+    # candidate must leave the frames bit-identical, and the re-captured graph
+    # renders the same frames as each job alone
+    import torch
+    walk = scenegen.random_walk_scene(3000, scenegen.serving_radius(6000), 101)
+    prot = scenegen.protein_scene()
+    a, b = tr.Scene(walk), tr.Scene(prot)
+    cams = scenegen.orbit_cameras(4, dist=90.0, res=(160, 96))
+    params = [scenegen.Params(ao_samples=8, seed=6, view_id=k) for k in range(4)]
+    which = [a, b, a, b]
+    alone = [frame_to_numpy(tr.render(s, c, p, outputs=OUT)) for s, c, p in zip(which, cams, params)]
+    torch.cuda.synchronize()
+    frames = [tr.alloc_frame(c, OUT) for c in cams]
+    g = tr.Graph(which, cams, params, frames)
+    tune, lam, ms = g.autotune(lambdas=(6.0, 24.0, 48.0))
+    print("graph tune", tune, lam, ms, flush=True)
+    assert ms > 0 and lam in (0.0, 6.0, 24.0, 48.0)
+    assert tune["tile_w"] in (4, 8, 16) and tune["banks"] in (2, 3)
+    assert tune["stripe"] in (16, 32, 64, 128, 256)
+    if lam > 0:  # the scenes were left at the chosen density
+        for s, src in ((a, walk), (b, prot)):
+            assert np.array_equal(s.grid_info()[2], tr.Scene(src, cells_per_prim=lam).grid_info()[2])
+    for f in frames:
+        f["rgb"].zero_()
+    g.launch()
+    torch.cuda.synchronize()
+    for i, f in enumerate(frames):
+        _same(frame_to_numpy(f), alone[i], ("tuned graph", i))
+    for bad in ((0.0,), (float("nan"),), (-3.0,)):
+        with pytest.raises(tr.TRError) as e:
+            g.autotune(lambdas=bad)
+        assert e.value.status == -1
+    g.destroy()
+
+
+def test_measured_fp32_peak(tr):
+    # non-packed FP32 FMAs: at most 128 flops per compute unit per clock
+    m = tr.measure_fp32_peak()
+    print("fp32 peak", m, flush=True)
+    assert m["n_cus"] > 0 and m["clock_mhz"] > 0
+    derived = m["n_cus"] * m["clock_mhz"] * 1e6 * 128 / 1e12
+    assert 0.3 * derived < m["tflops"] <= 1.05 * derived, (m, derived)
+
+
 def test_failing_batch_renders_nothing(tr, scenes):
     # every job is checked before anything is enqueued: an FP64 job ahead of
     # an invalid one is not rendered either

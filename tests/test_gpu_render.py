@@ -198,12 +198,20 @@ def test_deterministic_and_tune_independent(tr, protein):
     again = _gpu(tr, gs, c, p, "fp32_resolve")
     for k in OUT:
         assert np.array_equal(base[k], again[k]), k
+    # the tile queue's stripe only changes which XCD takes a tile: 1 deals
+    # single tiles round the XCDs, 1024 leaves six XCDs' queues empty (the
+    # frame has 1200 tiles), so their waves take every tile from the others'
     for tune in ({"tile_w": 4, "banks": 3, "waves_per_cu": 8, "refill_below": 16},
                  {"tile_w": 32, "banks": 2, "waves_per_cu": 32, "refill_below": 64},
-                 {"tile_w": 16, "banks": 3, "waves_per_cu": 1, "refill_below": 1}):
+                 {"tile_w": 16, "banks": 3, "waves_per_cu": 1, "refill_below": 1},
+                 {"stripe": 1}, {"stripe": 1024, "waves_per_cu": 2}):
         other = _gpu(tr, gs, c, p, "fp32_resolve", tune=tune)
         for k in OUT:
             assert np.array_equal(base[k], other[k]), (tune, k)
+    for bad in (3, 2048, -4):
+        with pytest.raises(tr.TRError) as e:
+            _gpu(tr, gs, c, p, "fp32_resolve", tune={"stripe": bad})
+        assert e.value.status == -1 and "stripe" in str(e.value), bad
     # grid density never changes the frame
     gs2 = tr.Scene(s, cells_per_prim=3.0)
     other = _gpu(tr, gs2, c, p, "fp32_resolve")
