@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import scenegen
-from parity_util import frame_to_numpy
+from parity_util import DECISION_AGREE_MIN, HIT_AGREE_MIN, MAX_ABS, RMS, compare, frame_to_numpy
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +65,40 @@ def test_served_equals_alone_under_contention(tr, pool):
         torch.cuda.synchronize()
         for k in OUT:
             assert np.array_equal(got[k], alone[k]), (j.job_id, k)
+
+
+def test_served_frames_match_oracle(tr, pool, oracle_mod):
+    # frames served several to a launch, with admission waiting on memory,
+    # meet the FP32 bar against the oracle over all their pixels together
+    # (one small frame alone is too few pixels for a 1e-4 share)
+    from paper_0801_1500_amd.serve import Server
+    scenes, gscenes = pool
+    jobs = _jobs(scenes, 10, 13)
+    one = tr.frame_footprint(scenegen.Camera((0, 0, 1), (0, 0, 0), (0, 1, 0), 50, 320, 240),
+                             scenegen.Params(), 15)
+    srv = Server(gscenes, hbm_budget=3 * one, max_slots=8, tile_budget=90, outputs=OUT,
+                 keep_frames=True)
+    st = srv.run(jobs, realtime=False)
+    print(st.summary(), flush=True)
+    assert st.max_launch_jobs >= 2 and len(st.latencies) == len(jobs)
+    n = mism = dec = flips = agree = 0
+    max_abs, sq = 0.0, 0.0
+    for j in jobs:
+        got = frame_to_numpy(j.frame)
+        ref = oracle_mod.render(scenes[j.scene], j.camera, j.params, grid=4.0)
+        m = compare(got, ref, j.params.ao_samples, scenes[j.scene].n_lights)
+        n += m["n"]
+        mism += m["hit_mismatch"]
+        dec += m["decisions"]
+        flips += m["decision_flips"]
+        agree += m["agree_pixels"]
+        max_abs = max(max_abs, m["max_abs_agree"])
+        sq += m["rms_agree"] ** 2 * m["agree_pixels"]
+    print("served vs oracle: pixels", n, "hit mismatches", mism, "decision flips", flips, "of", dec,
+          "max abs", max_abs, flush=True)
+    assert 1.0 - mism / n >= HIT_AGREE_MIN
+    assert 1.0 - flips / dec >= DECISION_AGREE_MIN
+    assert max_abs <= MAX_ABS and (sq / agree) ** 0.5 <= RMS
 
 
 def test_realtime_stream(tr, pool):
