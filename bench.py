@@ -196,7 +196,7 @@ def orbit_measure(tr, torch, scenegen, launches: int = 3) -> dict:
         [gs] * 8, cams[:8], params[:8], sub), [(24.0, 32), (24.0, 1), (4.0, 32), (4.0, 1)], reps=2)
     bvh = bvh_measure(tr, torch, gs, lambda a: tr.render_batch_tiles_into(
         [gs] * 8, cams[:8], params[:8], sub, [0] * 8, [tr.tile_count(c.width, c.height, 8) for c in cams[:8]],
-        tune={"accel": a}), reps=2)
+        tune={"accel": a, "tile_w": 8}), reps=2)
     # FP32 (+ FP64 re-solve) against the plain FP64 path, same 8-view batch
     prec = {}
     for name in ("fp32_resolve", "fp64"):

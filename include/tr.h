@@ -224,7 +224,7 @@ enum {
  * the acceleration structure instead (see there).  Zero fields take
  * defaults. */
 typedef struct {
-  int32_t tile_w;            /* tile width in pixels: 4, 8, 16 or 32; tiles hold 64 pixels */
+  int32_t tile_w;            /* tile width in pixels: 4, 8, 16, 32 or 64; tiles hold 64 pixels */
   int32_t banks;             /* pixel banks (tiles in flight) per wave: 2 or 3 (queue depth) */
   int32_t waves_per_cu;      /* persistent waves launched per compute unit, 1..32 */
   int32_t refill_below;      /* refill when fewer than this many lanes are busy, 1..64 */
@@ -505,7 +505,7 @@ tr_status tr_autotune(const tr_scene *scene, const tr_camera *cam, const tr_para
  * 0..64) is tried by rebuilding every scene of the graph at it (a density
  * whose grid cannot be built is skipped); the fastest is kept, or the
  * scenes' own densities when none beats them.  Then one pass of coordinate
- * descent over tile width {4, 8, 16}, banks {2, 3}, waves per compute unit
+ * descent over tile width {8, 16, 64}, banks {2, 3}, waves per compute unit
  * {12, 16, 20, 24}, refill threshold {24, 32, 40, 48} and queue stripe {16,
  * 32, 64, 128, 256}, and the winner re-timed against the default shape,
  * interleaved, median of 5 each; the faster is kept.  Every candidate is

@@ -859,7 +859,7 @@ extern "C" void tr_scene_destroy(tr_scene *s) {
 }
 
 // ------------------------------------------------------------------- jobs
-static bool valid_tile_w(int32_t w) { return w == 4 || w == 8 || w == 16 || w == 32; }
+static bool valid_tile_w(int32_t w) { return w == 4 || w == 8 || w == 16 || w == 32 || w == 64; }
 
 static tr_status default_tune(tr_tune *t) {
   t->tile_w = 8;
@@ -875,7 +875,7 @@ static tr_status default_tune(tr_tune *t) {
 }
 
 static tr_status check_tune(const tr_tune &t) {
-  if (!valid_tile_w(t.tile_w)) return fail(TR_EINVAL, "tune.tile_w must be 4, 8, 16 or 32");
+  if (!valid_tile_w(t.tile_w)) return fail(TR_EINVAL, "tune.tile_w must be 4, 8, 16, 32 or 64");
   if (t.banks != 2 && t.banks != 3) return fail(TR_EINVAL, "tune.banks must be 2 or 3");
   if (t.waves_per_cu < 1 || t.waves_per_cu > 32) return fail(TR_EINVAL, "tune.waves_per_cu must be 1..32");
   if (t.refill_below < 1 || t.refill_below > 64) return fail(TR_EINVAL, "tune.refill_below must be 1..64");
@@ -1896,7 +1896,7 @@ extern "C" tr_status tr_graph_autotune(tr_graph *g, int32_t n_lambdas, const dou
   // launch shape: one pass of coordinate descent
   tr_tune cur = g->tune;
   const std::vector<std::vector<int32_t>> axes = {
-      {4, 8, 16}, {2, 3}, {12, 16, 20, 24}, {24, 32, 40, 48}, {16, 32, 64, 128, 256}};
+      {8, 16, 64}, {2, 3}, {12, 16, 20, 24}, {24, 32, 40, 48}, {16, 32, 64, 128, 256}};
   rc = T.trial(cur_ms, "the starting shape");  // re-time after the density change
   if (rc != TR_OK) return rc;
   for (size_t ax = 0; ax < axes.size(); ++ax) {
@@ -2038,7 +2038,7 @@ extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr
   }
   // coordinate descent over the launch-shape axes
   const std::vector<std::vector<int32_t>> axes = {
-      {4, 8, 16, 32}, {2, 3}, {8, 12, 16, 20, 24, 32}, {16, 24, 32, 40, 48, 56}, {2, 8, 64}, {1, 16, 32, 48, 64},
+      {4, 8, 16, 32, 64}, {2, 3}, {8, 12, 16, 20, 24, 32}, {16, 24, 32, 40, 48, 56}, {2, 8, 64}, {1, 16, 32, 48, 64},
       {16, 32, 64, 128, 256}};
   for (int pass = 0; pass < 2; ++pass) {
     for (size_t ax = 0; ax < axes.size(); ++ax) {

@@ -59,6 +59,8 @@ def test_tile_count(tr):
     assert tr.tile_count(128, 128) == 256
     assert tr.tile_count(3860, 4548, 8) == 483 * 569
     assert tr.tile_count(65, 9, 16) == 5 * 3
+    assert tr.tile_count(3860, 4548) == 483 * 569  # default: 8 x 8 tiles
+    assert tr.tile_count(3860, 4548, 64) == 61 * 4548
     with pytest.raises(ValueError):
         tr.tile_count(10, 10, 7)
 
@@ -149,7 +151,7 @@ def test_render_validation_rejects(tr):
 
 def test_default_tune(tr):
     t = tr.default_tune()
-    assert t["tile_w"] in (4, 8, 16, 32) and t["banks"] in (2, 3)
+    assert t["tile_w"] in (4, 8, 16, 32, 64) and t["banks"] in (2, 3)
 
 
 def test_scene_load_rejects_bad_files(tr, tmp_path):

@@ -181,7 +181,7 @@ def test_errors(tr, protein):
             tr.render(gs, c, scenegen.Params(ao_samples=4, aa_samples=a), outputs=("rgb",))
         assert e.value.status == -1
     fr = tr.alloc_frame(c, ("rgb",), False)
-    n = tr.tile_count(c.width, c.height, 8)
+    n = tr.tile_count(c.width, c.height)
     with pytest.raises(tr.TRError) as e:
         tr.render_batch_tiles_into([gs], [c], [scenegen.Params(aa_samples=2)], [fr], [0], [n])
     assert e.value.status == -4

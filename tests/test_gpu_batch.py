@@ -119,7 +119,7 @@ def test_autotune_choice_is_bit_identical(tr, scenes):
     c = scenegen.Camera((0.0, 0.0, 70.0), (0, 0, 0), (0, 1, 0), 50.0, 256, 256)
     p = scenegen.Params(ao_samples=8, seed=3)
     best, ms = tr.autotune(sc, c, p)
-    assert ms > 0 and best["tile_w"] in (4, 8, 16, 32)
+    assert ms > 0 and best["tile_w"] in (4, 8, 16, 32, 64)
 
 
 def test_graph_autotune_keeps_frames(tr):
@@ -140,7 +140,7 @@ def test_graph_autotune_keeps_frames(tr):
     tune, lam, ms = g.autotune(lambdas=(6.0, 24.0, 48.0))
     print("graph tune", tune, lam, ms, flush=True)
     assert ms > 0 and lam in (0.0, 6.0, 24.0, 48.0)
-    assert tune["tile_w"] in (4, 8, 16) and tune["banks"] in (2, 3)
+    assert tune["tile_w"] in (8, 16, 64) and tune["banks"] in (2, 3)
     assert tune["stripe"] in (16, 32, 64, 128, 256)
     if lam > 0:  # the scenes were left at the chosen density
         for s, src in ((a, walk), (b, prot)):

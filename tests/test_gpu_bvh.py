@@ -224,7 +224,7 @@ def test_bvh_walk_with_options_and_batches(tr):
     print("bvh batch tiles", flush=True)
     tr.render_batch_tiles_into([gs] * 3, cams, ps, frames, [0] * 3,
                                [tr.tile_count(cm.width, cm.height, 8) for cm in cams],
-                               tune={"accel": 1})
+                               tune={"accel": 1, "tile_w": 8})
     torch.cuda.synchronize()
     for cm, pp, fr in zip(cams, ps, frames):
         alone = frame_to_numpy(tr.render(gs, cm, pp, outputs=OUT, tune={"accel": 1}))

@@ -125,7 +125,7 @@ def test_protein_17mp_full(tr, protein, protein_17mp_ref, prec):
 
 
 @pytest.mark.parametrize("W,H,tile_w", [(131, 77, 8), (67, 45, 16), (1, 1, 8), (5, 300, 32),
-                                        (300, 5, 4)])
+                                        (300, 5, 4), (131, 77, 64), (5, 300, 64)])
 def test_ragged_frames(tr, oracle_mod, protein, W, H, tile_w):
     s, gs = protein
     c = scenegen.Camera((10.0, 20.0, 70.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 35.0, W, H)
@@ -201,7 +201,7 @@ def test_deterministic_and_tune_independent(tr, protein):
     # the tile queue's stripe only changes which XCD takes a tile: 1 deals
     # single tiles round the XCDs, 1024 leaves six XCDs' queues empty (the
     # frame has 1200 tiles), so their waves take every tile from the others'
-    for tune in ({"tile_w": 4, "banks": 3, "waves_per_cu": 8, "refill_below": 16},
+    for tune in ({"tile_w": 8}, {"tile_w": 4, "banks": 3, "waves_per_cu": 8, "refill_below": 16},
                  {"tile_w": 32, "banks": 2, "waves_per_cu": 32, "refill_below": 64},
                  {"tile_w": 16, "banks": 3, "waves_per_cu": 1, "refill_below": 1},
                  {"stripe": 1}, {"stripe": 1024, "waves_per_cu": 2}):
