@@ -19,21 +19,17 @@ struct Cnt {
   uint32_t rays, cells, st, sh, ct, ch, tt, th;
 };
 
-__device__ __forceinline__ int32_t cell_coord(const SceneDev &S, int q, double x) {
-  const double f = floor((x - S.lo[q]) * S.inv[q]);
-  if (!(f >= 0.0)) return 0;
-  if (f > (double)(S.res[q] - 1)) return S.res[q] - 1;
-  return (int32_t)f;
-}
-
-__device__ __forceinline__ double boundary_t(const SceneDev &S, int q, int32_t idx, int step,
-                                             const double o[3], const double d[3]) {
-  const int32_t plane = step > 0 ? idx + 1 : idx;
-  return ((S.lo[q] + (double)plane * S.h[q]) - o[q]) / d[q];
-}
-
 // Nearest hit (lexicographic min of (t, id)) or any hit with t in
-// (tmin, tmax], walking the grid cells along the ray (3D-DDA).
+// (tmin, tmax], visiting the grid cells the ray crosses in order.
+//
+// On axis a the ray meets the grid plane of index p (at lo + p h) at
+// t = b_a + p g_a, with b_a = (lo_a - o_a) / d_a and g_a = h_a / d_a: the
+// first crossing is one FMA from the entry cell's plane, and each later one
+// |g_a| further.  The walk keeps, per axis, the next crossing, the cells
+// left before the grid's side and the step of the cell's linear index.  Any
+// walk that visits every cell the segment crosses gives the same nearest
+// hit: the lists hold every primitive within the insertion margin of a cell,
+// far above the FP64 rounding of the crossings.
 template <bool ANY, bool TRI>
 __device__ int trace_f64(const SceneDev &S, const double o[3], const double d[3], double tmin,
                          double tmax, int32_t skip, double &bt, int32_t &bk, Cnt &c) {
@@ -41,45 +37,57 @@ __device__ int trace_f64(const SceneDev &S, const double o[3], const double d[3]
   bool found = false;
   bt = INFINITY;
   bk = -1;
-  double t0 = tmin, t1 = tmax;
+  // the part of (tmin, tmax] inside the grid box, axis by axis
+  double tin = tmin, tout = tmax;
+  double b[3], g[3];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    if (d[q] != 0.0) {
-      double ta = (S.lo[q] - o[q]) / d[q];
-      double tb = (S.hi[q] - o[q]) / d[q];
-      if (ta > tb) {
-        const double x = ta;
-        ta = tb;
-        tb = x;
-      }
-      if (ta > t0) t0 = ta;
-      if (tb < t1) t1 = tb;
-    } else if (o[q] < S.lo[q] || o[q] > S.hi[q]) {
-      return 0;
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] == 0.0) {
+      if (o[a] < S.lo[a] || o[a] > S.hi[a]) return 0;
+      b[a] = g[a] = 0.0;
+      continue;
     }
+    b[a] = (S.lo[a] - o[a]) / d[a];
+    g[a] = S.h[a] / d[a];
+    const double tl = b[a], th = (S.hi[a] - o[a]) / d[a];
+    tin = fmax(tin, fmin(tl, th));
+    tout = fmin(tout, fmax(tl, th));
   }
-  if (t0 > t1) return 0;
-  int32_t idx[3], step[3];
-  double tn[3];
+  if (tin > tout) return 0;
+  // entry cell (clamped into the grid); per axis the next crossing, the
+  // time between crossings, the cells left to the grid's side and the step
+  // of the linear index (a grid has at most 512^3 cells: 32-bit indices)
+  int32_t left[3], stride[3];
+  double tn[3], dt[3];
+  const int32_t plane_cells[3] = {1, S.res[0], S.res[0] * S.res[1]};
+  int32_t cell = 0;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    idx[q] = cell_coord(S, q, o[q] + t0 * d[q]);
-    if (d[q] > 0.0) {
-      step[q] = 1;
-      tn[q] = boundary_t(S, q, idx[q], 1, o, d);
-    } else if (d[q] < 0.0) {
-      step[q] = -1;
-      tn[q] = boundary_t(S, q, idx[q], -1, o, d);
+  for (int a = 0; a < 3; ++a) {
+    const double f = floor((o[a] + tin * d[a] - S.lo[a]) * S.inv[a]);
+    const int32_t i = f >= 0.0 ? (f < (double)S.res[a] ? (int32_t)f : S.res[a] - 1) : 0;
+    cell += i * plane_cells[a];
+    if (d[a] > 0.0) {
+      tn[a] = fma((double)(i + 1), g[a], b[a]);
+      dt[a] = g[a];
+      left[a] = S.res[a] - 1 - i;
+      stride[a] = plane_cells[a];
+    } else if (d[a] < 0.0) {
+      tn[a] = fma((double)i, g[a], b[a]);
+      dt[a] = -g[a];
+      left[a] = i;
+      stride[a] = -plane_cells[a];
     } else {
-      step[q] = 0;
-      tn[q] = INFINITY;
+      tn[a] = INFINITY;
+      dt[a] = 0.0;
+      left[a] = 0;
+      stride[a] = 0;
     }
   }
+  const double t1 = tout;
   for (;;) {
     c.cells++;
-    const int64_t cell = ((int64_t)idx[2] * S.res[1] + idx[1]) * S.res[0] + idx[0];
-    const uint32_t e = S.cell_begin[cell + 1];
-    for (uint32_t r = S.cell_begin[cell]; r < e; ++r) {
+    const uint32_t e = S.cell_begin[(uint32_t)cell + 1u];
+    for (uint32_t r = S.cell_begin[(uint32_t)cell]; r < e; ++r) {
       const int32_t k = (int32_t)S.refs[r];
       if (k == skip) continue;
       double t;
@@ -111,15 +119,14 @@ __device__ int trace_f64(const SceneDev &S, const double o[3], const double d[3]
         }
       }
     }
-    int a = 0;
-    if (tn[1] < tn[a]) a = 1;
-    if (tn[2] < tn[a]) a = 2;
-    const double t_exit = tn[a] < t1 ? tn[a] : t1;
-    if (!ANY && found && bt <= t_exit) return 1;
-    if (tn[a] >= t1) return found;
-    idx[a] += step[a];
-    if (idx[a] < 0 || idx[a] >= S.res[a]) return found;
-    tn[a] = boundary_t(S, a, idx[a], step[a], o, d);
+    // leave through the nearest plane; stop once the best hit lies in the
+    // cells already seen, or at the end of the segment or the grid
+    const int a = tn[0] <= tn[1] ? (tn[0] <= tn[2] ? 0 : 2) : (tn[1] <= tn[2] ? 1 : 2);
+    if (!ANY && found && bt <= fmin(tn[a], t1)) return 1;
+    if (!(tn[a] < t1) || left[a] == 0) return found;
+    --left[a];
+    cell += stride[a];
+    tn[a] += dt[a];
   }
 }
 
