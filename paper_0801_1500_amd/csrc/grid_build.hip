@@ -141,7 +141,8 @@ __global__ void k_pack(const trh::PackArgs P) {
 
 // FP32 copies for the wavefront walk, with positions relative to the centre of
 // the grid box (the FP32 frame: the smallest magnitudes, so the least rounding,
-// wherever the scene sits).
+// wherever the scene sits).  Spheres and cylinders carry their squared radius
+// (squared in FP64, then rounded), which is all the FP32 tests use.
 __global__ void k_pack32(const trh::BuildArgs a, const double4 *cylW64, double ox, double oy,
                          double oz, float4 *sph32, float4 *cylA32, float4 *cylW32, float4 *triV32,
                          float4 *triE1_32, float4 *triE2_32) {
@@ -165,11 +166,11 @@ __global__ void k_pack32(const trh::BuildArgs a, const double4 *cylW64, double o
   }
   if (k < n_s) {
     const double4 s = sph64[k];
-    sph32[k] = make_float4((float)(s.x - ox), (float)(s.y - oy), (float)(s.z - oz), (float)s.w);
+    sph32[k] = make_float4((float)(s.x - ox), (float)(s.y - oy), (float)(s.z - oz), (float)(s.w * s.w));
   } else if (k < n_s + n_c) {
     const int64_t m = k - n_s;
     const double4 a = cylA64[m], w = cylW64[m];
-    cylA32[m] = make_float4((float)(a.x - ox), (float)(a.y - oy), (float)(a.z - oz), (float)a.w);
+    cylA32[m] = make_float4((float)(a.x - ox), (float)(a.y - oy), (float)(a.z - oz), (float)(a.w * a.w));
     cylW32[m] = make_float4((float)w.x, (float)w.y, (float)w.z, (float)w.w);
   }
 }

@@ -186,7 +186,7 @@ struct Ray {
   float bx, by, bz;  // the walk enters cell i of axis a at t = b_a + i * h_a
   float hx, hy, hz;
   int32_t cx, cy, cz;
-  int32_t sx, sy, sz;  // step signs
+  int32_t sx, sy, sz;  // minus the step signs (-1, 0, 1 for d > 0, = 0, < 0)
   int32_t rc;          // cursor into the cell's walk list; -(distance) in an empty cell
   int32_t nk;          // wrefs[rc]: the next reference, -1 at the list end (loaded ahead)
   float bt;            // best t
@@ -284,19 +284,22 @@ __device__ __forceinline__ bool ray_setup(Ray &R, const SceneHot &S) {
   R.cx = min(max(cvt_floor((ex - S.lo32[0]) * S.inv32[0]), 0), S.res[0] - 1);
   R.cy = min(max(cvt_floor((ey - S.lo32[1]) * S.inv32[1]), 0), S.res[1] - 1);
   R.cz = min(max(cvt_floor((ez - S.lo32[2]) * S.inv32[2]), 0), S.res[2] - 1);
-  R.sx = R.dx > 0.0f ? 1 : (R.dx < 0.0f ? -1 : 0);
-  R.sy = R.dy > 0.0f ? 1 : (R.dy < 0.0f ? -1 : 0);
-  R.sz = R.dz > 0.0f ? 1 : (R.dz < 0.0f ? -1 : 0);
+  const int32_t sx = R.dx > 0.0f ? 1 : (R.dx < 0.0f ? -1 : 0);
+  const int32_t sy = R.dy > 0.0f ? 1 : (R.dy < 0.0f ? -1 : 0);
+  const int32_t sz = R.dz > 0.0f ? 1 : (R.dz < 0.0f ? -1 : 0);
+  R.sx = -sx;
+  R.sy = -sy;
+  R.sz = -sz;
   // Plane of the grid crossed when the walk enters cell i of axis a: at
   // b_a + i * h_a, with b_a taken one cell up for negative steps (the plane
   // between cells i and i + 1).  An axis with d_a = 0 gets b_a = inf, h_a = 0:
   // its plane is never the next one.
-  R.hx = R.sx ? S.h32[0] * ix : 0.0f;
-  R.hy = R.sy ? S.h32[1] * iy : 0.0f;
-  R.hz = R.sz ? S.h32[2] * iz : 0.0f;
-  R.bx = R.sx > 0 ? ax : (R.sx < 0 ? ax + R.hx : INFINITY);
-  R.by = R.sy > 0 ? ay : (R.sy < 0 ? ay + R.hy : INFINITY);
-  R.bz = R.sz > 0 ? az : (R.sz < 0 ? az + R.hz : INFINITY);
+  R.hx = sx ? S.h32[0] * ix : 0.0f;
+  R.hy = sy ? S.h32[1] * iy : 0.0f;
+  R.hz = sz ? S.h32[2] * iz : 0.0f;
+  R.bx = sx > 0 ? ax : (sx < 0 ? ax + R.hx : INFINITY);
+  R.by = sy > 0 ? ay : (sy < 0 ? ay + R.hy : INFINITY);
+  R.bz = sz > 0 ? az : (sz < 0 ? az + R.hz : INFINITY);
   load_cell(R, S);
   return true;
 }
@@ -974,6 +977,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       const SceneHot H = load_hot(&A.jobs[uni(scene_job)]);
       const int32_t thresh = uni(can_refill ? A.refill_below : 1);
       const bool anyhit = kind >= kShadow;
+      // grid-frame offsets of the jump step, held in VGPRs for the whole
+      // loop: the step's FMAs take the scale from an SGPR, and one VOP3
+      // instruction reads at most one SGPR (else a copy every iteration)
+      float gorg0 = H.org32[0], gorg1 = H.org32[1], gorg2 = H.org32[2];
+      asm volatile("" : "+v"(gorg0), "+v"(gorg1), "+v"(gorg2));
       const uint64_t cyc0 = COUNT ? clock64() : 0;
       for (int32_t it = 0;; ++it) {
         const bool work = st == kRun;
@@ -1001,17 +1009,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         // also need busy/cyl_wait lanes) -- so the wave does not pay for every
         // code path each iteration; the other lanes wait.  The decisions are
         // wave-uniform; each lane's type is one compare.
-        const int32_t n_sph = __popcll(ballot((uint32_t)nk < (uint32_t)H.n_s));  // nk = -1: no
-        const int32_t n_cyl = __popcll(ballot(nk >= H.n_s));
+        const bool want_sph = (uint32_t)nk < (uint32_t)H.n_s;  // nk = -1: no
+        const bool want_cyl = nk >= H.n_s;
+        const int32_t n_sph = __popcll(ballot(want_sph));
+        const int32_t n_cyl = __popcll(ballot(want_cyl));
         const int32_t n_step = nwork - n_sph - n_cyl;
         const int32_t n_max = max(n_step, max(n_sph, n_cyl));
         const int32_t bar = (n_max * A.mix + 63) >> 6;
         const bool go_sph = n_sph >= bar;
         const bool go_step = n_step >= bar;
         const bool go_cyl = n_cyl > 0 && ((n_cyl >= bar && n_cyl * A.cyl_wait >= nwork) || (!go_sph && !go_step));
-        const bool is_sph = go_sph && (uint32_t)nk < (uint32_t)H.n_s;
-        const bool is_cyl = go_cyl && nk >= H.n_s;
-        const bool is_step = go_step && nk < 0;
+        const bool is_sph = go_sph && want_sph;
+        const bool is_cyl = go_cyl && want_cyl;
+        const bool is_step = go_step && !want_sph && !want_cyl;  // nk < 0
         // Sphere records are fetched first and the step's arithmetic runs
         // meanwhile (the two lane sets are disjoint), so the load latency hides
         // behind it; the step's own cell load is issued last, after the tests
@@ -1071,13 +1081,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           // cube of half-size k-1 around it is empty and the walk jumps to
           // where the ray leaves that cube (k = 1: an ordinary DDA step).
           // Branch-free: the k = 1 step is the jump with a cube of size 0.
-          const int32_t kk = max(-R.rc, 1);  // rc = -distance in an empty cell, >= 0 otherwise
-          const int32_t m = kk - 1;
+          // nk = -k: rc = -distance in an empty cell, >= 0 otherwise
+          const int32_t nk1 = min(R.rc, -1);
+          const int32_t m = -1 - nk1;  // k - 1
           // cell just beyond the cube on each axis; its near plane is crossed at
-          // b_a + i * h_a (b_a is shifted one cell for negative steps at setup)
-          const int32_t ix1 = R.cx + __mul24(R.sx, kk);
-          const int32_t iy1 = R.cy + __mul24(R.sy, kk);
-          const int32_t iz1 = R.cz + __mul24(R.sz, kk);
+          // b_a + i * h_a (b_a is shifted one cell for negative steps at setup);
+          // (-sign) (-k) is the offset
+          const int32_t ix1 = R.cx + __mul24(R.sx, nk1);
+          const int32_t iy1 = R.cy + __mul24(R.sy, nk1);
+          const int32_t iz1 = R.cz + __mul24(R.sz, nk1);
           const float tx = fmaf((float)ix1, R.hx, R.bx);  // inf when d_x = 0
           const float ty = fmaf((float)iy1, R.hy, R.by);
           const float tz = fmaf((float)iz1, R.hz, R.bz);
@@ -1090,10 +1102,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             const bool ay = !ax && ty == tn;
             const bool az = !ax && !ay;
             // the other axes land in the cell of the exit point, kept inside the cube
-            const int32_t nx = R.cx + med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], H.org32[0])) - R.cx, -m, m);
-            const int32_t ny = R.cy + med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], H.org32[1])) - R.cy, -m, m);
-            const int32_t nz = R.cz + med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], H.org32[2])) - R.cz, -m, m);
-            if (COUNT && kk > 1) ++l_jumps;
+            const int32_t nx = R.cx + med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], gorg0)) - R.cx, -m, m);
+            const int32_t ny = R.cy + med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], gorg1)) - R.cy, -m, m);
+            const int32_t nz = R.cz + med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], gorg2)) - R.cz, -m, m);
+            if (COUNT && nk1 < -1) ++l_jumps;
             R.cx = ax ? ix1 : nx;
             R.cy = ay ? iy1 : ny;
             R.cz = az ? iz1 : nz;
@@ -1112,7 +1124,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           }
         }
         bool tested = false, hit = false, graze = false;
-        float t = 0.0f;
+        float t;  // set by every test; read only on a tested lane
+        asm volatile("" : "=v"(t));
         const bool own = nk == -2 - R.skip;  // the surface this ray leaves from inside
         if (is_sph) {
           tested = true;
@@ -1121,12 +1134,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           const float b = qx * R.dx + qy * R.dy + qz * R.dz;
           const float lx = qx - b * R.dx, ly = qy - b * R.dy, lz = qz - b * R.dz;
           const float ll = lx * lx + ly * ly + lz * lz;
-          const float rr = s.w * s.w;
+          const float rr = s.w;  // squared radius
           const float disc = rr - ll;
-          graze = RESOLVE && fabsf(disc) <= kKappa * (rr + ll);
-          const float sq = sqrtf_fast(fmaxf(disc, 0.0f));
+          const float sg = kKappa * (rr + ll);
+          graze = RESOLVE && fabsf(disc) <= sg;
+          // decidable real roots: disc >= 0 and not grazing, i.e. disc > sg
+          // (disc < 0 gives NaN roots, which no compare accepts)
+          const bool ok = RESOLVE ? disc > sg : disc >= 0.0f;
+          const float sq = sqrtf_fast(disc);
           const float t0 = b - sq, t1 = b + sq;
-          const bool ok = disc >= 0.0f && !graze;
           // nearer root if it is past tmin, else the farther (t0 <= t1);
           // only the farther on the ray's own sphere
           t = t0 > R.tmin && !own ? t0 : t1;
@@ -1179,11 +1195,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           const float tc = -Bq * iA;
           const float lx = Dpx + tc * dpx, ly = Dpy + tc * dpy, lz = Dpz + tc * dpz;
           const float ll = lx * lx + ly * ly + lz * lz;
-          const float rr = a.w * a.w;
+          const float rr = a.w;  // squared radius
           const float disc = rr - ll;
-          const bool g0 = RESOLVE && nonpar && fabsf(disc) <= kKappa * (rr + ll);
-          const float sq = sqrtf_fast(fmaxf(disc, 0.0f) * iA);
-          const bool ok = nonpar && !g0 && disc >= 0.0f;
+          const float sg = kKappa * (rr + ll);
+          const bool g0 = RESOLVE && nonpar && fabsf(disc) <= sg;
+          const bool ok = nonpar && (RESOLVE ? disc > sg : disc >= 0.0f);  // (as for spheres)
+          const float sq = sqrtf_fast(disc * iA);
           const float tl = tc - sq, th = tc + sq;
           const float kL = kKappa * w.w;
           const float sl = Dw + tl * dw, sh = Dw + th * dw;

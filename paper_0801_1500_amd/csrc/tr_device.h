@@ -5,8 +5,10 @@
 //   cylA64 double4[n_c]  (ax, ay, az, rho)
 //   cylW64 double4[n_c]  (wx, wy, wz, L)           unit axis and length, w = (b - a) / L
 //   cylB64 double4[n_c]  (bx, by, bz, 0)           second end point (grid rebuild)
-//   sph32  float4[n_s]   rounded copies for the FP32 traversal: one 16-byte load per sphere
-//   cylA32 float4[n_c], cylW32 float4[n_c]         two 16-byte loads per cylinder
+//   sph32  float4[n_s]   (cx, cy, cz, r^2) rounded copies for the FP32 traversal: one
+//                        16-byte load per sphere
+//   cylA32 float4[n_c], cylW32 float4[n_c]  (ax, ay, az, rho^2), (wx, wy, wz, L): two
+//                        16-byte loads per cylinder
 //   triA64/triB64/triC64 double4[n_t]  triangle vertices (FP64)
 //   triV32, triE1_32, triE2_32 float4[n_t]  (v0, |e1 x e2|), e1, e2: three loads per triangle
 //                        (FP32 positions are relative to org, the centre of the grid
