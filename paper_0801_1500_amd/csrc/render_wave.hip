@@ -256,6 +256,82 @@ __device__ __forceinline__ T ldg(const TR_GLOBAL T *base, uint32_t i) {
   return *(const TR_GLOBAL T *)((const TR_GLOBAL char *)base + i * (uint32_t)sizeof(T));
 }
 
+// Colour of a finished hit pixel from its slot: the lights whose shadow rays
+// got through, the unoccluded share of its AO rays, its albedo and the
+// optional highlight, clamped (the first surface, or the current one when
+// compositing).  alpha: the primitive's opacity.
+template <typename LdsT>
+__device__ __forceinline__ void shade_slot(const LdsT &L, const BankInfo &B, int32_t slot,
+                                           int32_t k, const TR_GLOBAL vf4 *albedo, float &cr,
+                                           float &cg, float &cb, float &alpha) {
+  const float Nx = L.nx[slot], Ny = L.ny[slot], Nz = L.nz[slot];
+  const uint32_t lv = L.lvalid[slot];
+  const uint32_t lm = L.lmask[slot];
+  float Dr = 0.0f, Dg = 0.0f, Db = 0.0f;
+  float Hr = 0.0f, Hg = 0.0f, Hb = 0.0f;  // Phong highlight (white, after the albedo)
+  for (int l = 0; l < B.n_lights; ++l) {
+    if (!((lv >> l) & 1u) || ((lm >> l) & 1u)) continue;
+    const float cl = Nx * B.ldir[l][0] + Ny * B.ldir[l][1] + Nz * B.ldir[l][2];
+    Dr += B.lcol[l][0] * cl;
+    Dg += B.lcol[l][1] * cl;
+    Db += B.lcol[l][2] * cl;
+    if (B.ks > 0.0f) {
+      // light direction mirrored about N, against the way back to the eye
+      const float vx = B.eye[0] - L.px[slot], vy = B.eye[1] - L.py[slot],
+                  vz = B.eye[2] - L.pz[slot];
+      const float rv = ((2.0f * cl * Nx - B.ldir[l][0]) * vx +
+                        (2.0f * cl * Ny - B.ldir[l][1]) * vy +
+                        (2.0f * cl * Nz - B.ldir[l][2]) * vz) *
+                       __builtin_amdgcn_rsqf(vx * vx + vy * vy + vz * vz);
+      if (rv > 0.0f) {
+        // rv^n as 2^(n log2 rv) on the hardware log and exp (about
+        // 1 ulp each; rv <= 1, so the error is ~ n |log2 rv| ulp)
+        const float f = B.ks * __builtin_amdgcn_exp2f(B.shin * __builtin_amdgcn_logf(rv));
+        Hr += B.lcol[l][0] * f;
+        Hg += B.lcol[l][1] * f;
+        Hb += B.lcol[l][2] * f;
+      }
+    }
+  }
+  float ao = 1.0f;
+  if (B.S > 0) ao = (float)(B.S - L.aocnt[slot]) * B.rS;
+  const vf4 alb = ldg(albedo, (uint32_t)k);
+  const float sk = B.sky * ao;
+  cr = fminf(fmaxf(alb.x * (Dr + sk) + Hr, 0.0f), 1.0f);
+  cg = fminf(fmaxf(alb.y * (Dg + sk) + Hg, 0.0f), 1.0f);
+  cb = fminf(fmaxf(alb.z * (Db + sk) + Hb, 0.0f), 1.0f);
+  alpha = alb.w;
+}
+
+// Opaque rendering: a bank's pixels are shaded when its last one finishes,
+// one lane per pixel (shading as pixels finish would run the shading code
+// for the few lanes that finish in each round); the colours then wait in the
+// slots' hit-point words for write_tile, and hit ids and masks go out here.
+template <typename LdsT>
+__device__ __forceinline__ void shade_tile(LdsT &L, int32_t b, int32_t lane,
+                                           const TR_GLOBAL vf4 *albedo) {
+  const BankInfo &B = L.bank[b];
+  if (lane < B.n) {
+    const int32_t slot = b * 64 + lane;
+    const int32_t k = L.prim[slot];  // -1: the primary ray missed
+    float cr = B.bg[0], cg = B.bg[1], cb = B.bg[2], alpha;
+    if (k >= 0) shade_slot(L, B, slot, k, albedo, cr, cg, cb, alpha);
+    if (B.hit_id || B.ao_mask || B.light_mask) {
+      int32_t x, y;
+      bank_pixel(B, lane, x, y);
+      const int64_t pid = (int64_t)y * B.W + x;
+      if (B.hit_id) B.hit_id[pid] = k;
+      if (B.ao_mask) B.ao_mask[pid] = k >= 0 ? L.aomask[slot] : 0u;
+      if (B.light_mask) B.light_mask[pid] = k >= 0 ? (uint8_t)L.lmask[slot] : (uint8_t)0;
+    }
+    L.px[slot] = cr;
+    L.py[slot] = cg;
+    L.pz[slot] = cb;
+  }
+  __syncthreads();
+}
+
+
 __device__ __forceinline__ void load_cell(Ray &R, const SceneHot &S) {
   // res <= 512 per axis: the products fit the 24-bit multiplier
   const uint32_t cell = mad24(mad24((uint32_t)R.cz, (uint32_t)S.res[1], (uint32_t)R.cy),
@@ -600,7 +676,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       __syncthreads();
       bool cont_next = false;  // the pixel goes on through a transparent surface
       int32_t layer = 0;
-      if (finalize) {
+      if (!TRANS && finalize) {
+        // shaded with the whole tile (shade_tile); a miss is marked here
+        if (fin_prim_miss) L.prim[slot] = -1;
+        atomicAdd(&bank_of(L.bank, slot >> 6).done, 1);
+      }
+      if (TRANS && finalize) {
         float alpha = 1.0f;
         const int32_t bk = slot >> 6;
         BankInfo &B = bank_of(L.bank, bk);
@@ -613,52 +694,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         if (!fin_prim_miss) {
           const int32_t k = L.prim[slot];
           hid = k;
-          const float Nx = L.nx[slot], Ny = L.ny[slot], Nz = L.nz[slot];
-          const uint32_t lv = L.lvalid[slot];
           lm = L.lmask[slot];
           am = L.aomask[slot];
-          float Dr = 0.0f, Dg = 0.0f, Db = 0.0f;
-          float Hr = 0.0f, Hg = 0.0f, Hb = 0.0f;  // Phong highlight (white, after the albedo)
-          for (int l = 0; l < B.n_lights; ++l) {
-            if (!((lv >> l) & 1u) || ((lm >> l) & 1u)) continue;
-            const float cl = Nx * B.ldir[l][0] + Ny * B.ldir[l][1] + Nz * B.ldir[l][2];
-            Dr += B.lcol[l][0] * cl;
-            Dg += B.lcol[l][1] * cl;
-            Db += B.lcol[l][2] * cl;
-            if (B.ks > 0.0f) {
-              // light direction mirrored about N, against the way back to the eye
-              const float vx = B.eye[0] - L.px[slot], vy = B.eye[1] - L.py[slot],
-                          vz = B.eye[2] - L.pz[slot];
-              const float rv = ((2.0f * cl * Nx - B.ldir[l][0]) * vx +
-                                (2.0f * cl * Ny - B.ldir[l][1]) * vy +
-                                (2.0f * cl * Nz - B.ldir[l][2]) * vz) *
-                               __builtin_amdgcn_rsqf(vx * vx + vy * vy + vz * vz);
-              if (rv > 0.0f) {
-                // rv^n as 2^(n log2 rv) on the hardware log and exp (about
-                // 1 ulp each; rv <= 1, so the error is ~ n |log2 rv| ulp)
-                const float f = B.ks * __builtin_amdgcn_exp2f(B.shin * __builtin_amdgcn_logf(rv));
-                Hr += B.lcol[l][0] * f;
-                Hg += B.lcol[l][1] * f;
-                Hb += B.lcol[l][2] * f;
-              }
-            }
-          }
-          float ao = 1.0f;
-          if (B.S > 0) ao = (float)(B.S - L.aocnt[slot]) * B.rS;
-          const vf4 alb = ldg(S.albedo, (uint32_t)k);
-          const float sk = B.sky * ao;
-          cr = fminf(fmaxf(alb.x * (Dr + sk) + Hr, 0.0f), 1.0f);
-          cg = fminf(fmaxf(alb.y * (Dg + sk) + Hg, 0.0f), 1.0f);
-          cb = fminf(fmaxf(alb.z * (Db + sk) + Hb, 0.0f), 1.0f);
-          if (TRANS && B.layers > 1) alpha = alb.w;
+          float a = 1.0f;
+          shade_slot(L, B, slot, k, S.albedo, cr, cg, cb, a);
+          if (B.layers > 1) alpha = a;
         }
-        if (TRANS) layer = L.layer[slot];
-        if (!TRANS || layer == 0) {  // hit id and masks: the first surface's
+        layer = L.layer[slot];
+        if (layer == 0) {  // hit id and masks: the first surface's
           if (B.hit_id) B.hit_id[pid] = hid;
           if (B.ao_mask) B.ao_mask[pid] = am;
           if (B.light_mask) B.light_mask[pid] = (uint8_t)lm;
         }
-        if (TRANS) {
+        {
           // composite front to back; what is left after the last surface (a
           // miss counts as an opaque background surface) shows the background
           const float T = layer ? L.trn[slot] : 1.0f;
@@ -717,6 +765,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         const int32_t n_b = uni(L.bank[b].n);
         const bool all_issued = issue_bank != b || issue_next == n_b;
         if (all_issued && uni(L.bank[b].done) == n_b) {
+          if (!TRANS) shade_tile(L, b, lane, S.albedo);
           write_tile(L, b, lane);
           bank_busy &= ~(1u << b);
           if (issue_bank == b) issue_bank = -1;
