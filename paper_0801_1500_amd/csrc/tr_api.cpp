@@ -868,7 +868,7 @@ static tr_status default_tune(tr_tune *t) {
   t->refill_below = 32;
   t->count_ops = 0;
   t->cyl_wait = 64;
-  t->mix = 16;
+  t->mix = 8;
   t->accel = 0;
   t->stripe = 64;
   return TR_OK;
@@ -2038,7 +2038,7 @@ extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr
   }
   // coordinate descent over the launch-shape axes
   const std::vector<std::vector<int32_t>> axes = {
-      {4, 8, 16, 32, 64}, {2, 3}, {8, 12, 16, 20, 24, 32}, {16, 24, 32, 40, 48, 56}, {2, 8, 64}, {1, 16, 32, 48, 64},
+      {4, 8, 16, 32, 64}, {2, 3}, {8, 12, 16, 20, 24, 32}, {16, 24, 32, 40, 48, 56}, {2, 8, 64}, {1, 8, 16, 32, 64},
       {16, 32, 64, 128, 256}};
   for (int pass = 0; pass < 2; ++pass) {
     for (size_t ax = 0; ax < axes.size(); ++ax) {
