@@ -516,7 +516,9 @@ tr_status tr_autotune(const tr_scene *scene, const tr_camera *cam, const tr_para
  * buffer (if any) has accumulated every replay.  Nothing else may use the
  * graph's scenes meanwhile.  *best (the shape), *best_lambda (0 = the
  * scenes' own densities kept) and *best_ms (its replay time) may be NULL.
- * Synchronises the stream; TR_EINVAL on a NULL graph or a bad density list. */
+ * Synchronises the stream; TR_EINVAL on a NULL graph or a bad density list.
+ * On any later error the scenes are rebuilt at their own densities and the
+ * graph re-captured with its starting shape before the error is returned. */
 tr_status tr_graph_autotune(tr_graph *g, int32_t n_lambdas, const double *lambdas,
                             void *hip_stream, tr_tune *best, double *best_lambda, double *best_ms);
 

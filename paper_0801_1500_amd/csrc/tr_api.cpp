@@ -1862,93 +1862,106 @@ extern "C" tr_status tr_graph_autotune(tr_graph *g, int32_t n_lambdas, const dou
       own.push_back(m->lambda);
     }
   }
-  double cur_ms = 0.0;
-  rc = T.time(cur_ms);
-  if (rc == TR_OK) rc = T.read(T.ref0, T.refn);
-  if (rc != TR_OK) return rc;
-  // grid density: every scene at one candidate density (0 = their own)
-  double lam = 0.0;
-  auto set_lambda = [&](double l) -> tr_status {
-    HIP_TRY(hipStreamSynchronize(T.st));
-    for (size_t k = 0; k < uniq.size(); ++k) {
-      const tr_status r = tr_scene_rebuild(uniq[k], l > 0.0 ? l : own[k], T.st);
-      if (r != TR_OK) return r;
-    }
-    return tr_graph_update(g, nullptr, nullptr, T.st);
-  };
-  for (int32_t i = 0; i < n_lambdas; ++i) {
-    rc = set_lambda(lambdas[i]);
-    double ms = 0.0;
-    if (rc == TR_OK) rc = T.trial(ms, "a grid density");
-    else if (rc == TR_EUNSUPPORTED || rc == TR_ENOMEM) {  // that grid cannot be built: skip it
-      rc = set_lambda(lam);
-      if (rc != TR_OK) return rc;
-      continue;
-    }
+  const tr_tune orig = g->tune;
+  auto tune_all = [&]() -> tr_status {
+    double cur_ms = 0.0;
+    rc = T.time(cur_ms);
+    if (rc == TR_OK) rc = T.read(T.ref0, T.refn);
     if (rc != TR_OK) return rc;
-    if (ms < cur_ms) {
-      cur_ms = ms;
-      lam = lambdas[i];
-    }
-  }
-  rc = set_lambda(lam);
-  if (rc != TR_OK) return rc;
-  // launch shape: one pass of coordinate descent
-  tr_tune cur = g->tune;
-  const std::vector<std::vector<int32_t>> axes = {
-      {8, 16, 64}, {2, 3}, {12, 16, 20, 24}, {24, 32, 40, 48}, {16, 32, 64, 128, 256}};
-  rc = T.trial(cur_ms, "the starting shape");  // re-time after the density change
-  if (rc != TR_OK) return rc;
-  for (size_t ax = 0; ax < axes.size(); ++ax) {
-    for (int32_t v : axes[ax]) {
-      tr_tune t = cur;
-      int32_t *field = ax == 0   ? &t.tile_w
-                       : ax == 1 ? &t.banks
-                       : ax == 2 ? &t.waves_per_cu
-                       : ax == 3 ? &t.refill_below
-                                 : &t.stripe;
-      if (*field == v) continue;
-      *field = v;
-      rc = graph_retune(g, t, T.st);
+    // grid density: every scene at one candidate density (0 = their own)
+    double lam = 0.0;
+    auto set_lambda = [&](double l) -> tr_status {
+      HIP_TRY(hipStreamSynchronize(T.st));
+      for (size_t k = 0; k < uniq.size(); ++k) {
+        const tr_status r = tr_scene_rebuild(uniq[k], l > 0.0 ? l : own[k], T.st);
+        if (r != TR_OK) return r;
+      }
+      return tr_graph_update(g, nullptr, nullptr, T.st);
+    };
+    for (int32_t i = 0; i < n_lambdas; ++i) {
+      rc = set_lambda(lambdas[i]);
       double ms = 0.0;
-      if (rc == TR_OK) rc = T.trial(ms, "a launch shape");
+      if (rc == TR_OK) rc = T.trial(ms, "a grid density");
+      else if (rc == TR_EUNSUPPORTED || rc == TR_ENOMEM) {  // that grid cannot be built: skip it
+        rc = set_lambda(lam);
+        if (rc != TR_OK) return rc;
+        continue;
+      }
       if (rc != TR_OK) return rc;
       if (ms < cur_ms) {
         cur_ms = ms;
-        cur = t;
+        lam = lambdas[i];
       }
     }
-  }
-  // the winner against the default shape, interleaved, median of 5 each
-  tr_tune def;
-  default_tune(&def);
-  def.count_ops = cur.count_ops;
-  def.accel = cur.accel;
-  if (std::memcmp(&def, &cur, sizeof(tr_tune)) != 0) {
-    double a[5], b[5];
-    for (int rep = 0; rep < 5; ++rep) {
-      rc = graph_retune(g, def, T.st);
-      if (rc == TR_OK) rc = T.trial(a[rep], "the default shape");
-      if (rc == TR_OK) rc = graph_retune(g, cur, T.st);
-      if (rc == TR_OK) rc = T.trial(b[rep], "a launch shape");
-      if (rc != TR_OK) return rc;
+    rc = set_lambda(lam);
+    if (rc != TR_OK) return rc;
+    // launch shape: one pass of coordinate descent
+    tr_tune cur = g->tune;
+    const std::vector<std::vector<int32_t>> axes = {
+        {8, 16, 64}, {2, 3}, {12, 16, 20, 24}, {24, 32, 40, 48}, {16, 32, 64, 128, 256}};
+    rc = T.trial(cur_ms, "the starting shape");  // re-time after the density change
+    if (rc != TR_OK) return rc;
+    for (size_t ax = 0; ax < axes.size(); ++ax) {
+      for (int32_t v : axes[ax]) {
+        tr_tune t = cur;
+        int32_t *field = ax == 0   ? &t.tile_w
+                         : ax == 1 ? &t.banks
+                         : ax == 2 ? &t.waves_per_cu
+                         : ax == 3 ? &t.refill_below
+                                   : &t.stripe;
+        if (*field == v) continue;
+        *field = v;
+        rc = graph_retune(g, t, T.st);
+        double ms = 0.0;
+        if (rc == TR_OK) rc = T.trial(ms, "a launch shape");
+        if (rc != TR_OK) return rc;
+        if (ms < cur_ms) {
+          cur_ms = ms;
+          cur = t;
+        }
+      }
     }
-    std::sort(a, a + 5);
-    std::sort(b, b + 5);
-    if (a[2] <= b[2]) {
-      cur = def;
-      cur_ms = a[2];
-    } else {
-      cur_ms = b[2];
+    // the winner against the default shape, interleaved, median of 5 each
+    tr_tune def;
+    default_tune(&def);
+    def.count_ops = cur.count_ops;
+    def.accel = cur.accel;
+    if (std::memcmp(&def, &cur, sizeof(tr_tune)) != 0) {
+      double a[5], b[5];
+      for (int rep = 0; rep < 5; ++rep) {
+        rc = graph_retune(g, def, T.st);
+        if (rc == TR_OK) rc = T.trial(a[rep], "the default shape");
+        if (rc == TR_OK) rc = graph_retune(g, cur, T.st);
+        if (rc == TR_OK) rc = T.trial(b[rep], "a launch shape");
+        if (rc != TR_OK) return rc;
+      }
+      std::sort(a, a + 5);
+      std::sort(b, b + 5);
+      if (a[2] <= b[2]) {
+        cur = def;
+        cur_ms = a[2];
+      } else {
+        cur_ms = b[2];
+      }
     }
+    rc = graph_retune(g, cur, T.st);
+    if (rc != TR_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(T.st));
+    if (best) *best = cur;
+    if (best_lambda) *best_lambda = lam;
+    if (best_ms) *best_ms = cur_ms;
+    return TR_OK;
+  };
+  rc = tune_all();
+  if (rc != TR_OK) {
+    // put the graph and its scenes back as they were, keeping the error
+    const std::string err = g_err;
+    (void)hipStreamSynchronize(T.st);
+    for (size_t k = 0; k < uniq.size(); ++k) (void)tr_scene_rebuild(uniq[k], own[k], T.st);
+    (void)graph_retune(g, orig, T.st);
+    g_err = err;
   }
-  rc = graph_retune(g, cur, T.st);
-  if (rc != TR_OK) return rc;
-  HIP_TRY(hipStreamSynchronize(T.st));
-  if (best) *best = cur;
-  if (best_lambda) *best_lambda = lam;
-  if (best_ms) *best_ms = cur_ms;
-  return TR_OK;
+  return rc;
 }
 
 extern "C" tr_status tr_measure_fp32_peak(void *hip_stream, double *tflops, double *clock_mhz,
