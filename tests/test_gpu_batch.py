@@ -156,6 +156,23 @@ def test_graph_autotune_keeps_frames(tr):
             g.autotune(lambdas=bad)
         assert e.value.status == -1
     g.destroy()
+    # a BVH-walk graph: the grid rebuilds of the density search leave the
+    # BVH valid, and the tuned graph still renders the frames of the walk
+    a.build_bvh()
+    b.build_bvh()
+    alone = [frame_to_numpy(tr.render(s, c, p, outputs=OUT, tune={"accel": 1}))
+             for s, c, p in zip(which, cams, params)]
+    torch.cuda.synchronize()
+    g = tr.Graph(which, cams, params, frames, tune={"accel": 1})
+    tune, lam, ms = g.autotune(lambdas=(6.0,))
+    assert tune["accel"] == 1 and ms > 0
+    for f in frames:
+        f["rgb"].zero_()
+    g.launch()
+    torch.cuda.synchronize()
+    for i, f in enumerate(frames):
+        _same(frame_to_numpy(f), alone[i], ("tuned bvh graph", i))
+    g.destroy()
 
 
 def test_measured_fp32_peak(tr):
