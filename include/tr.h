@@ -381,9 +381,9 @@ tr_status tr_render_batch(int32_t n, const tr_scene *const *scenes, const tr_cam
  * Same frames as tr_render_batch, bit for bit (same kernels, same rules: one
  * FP32 precision and one stats buffer for the FP32 jobs, the first FP32 job's
  * tuning or `tune` when non-NULL; FP64 jobs are rendered one launch each).
- * The job table and tile counter live in a fixed array of the library's
- * static device memory, about 21 KB per device (TR_NOALLOC_MAX_JOBS job
- * records and a counter), held until the process
+ * The job table and tile queue live in a fixed array of the library's
+ * static device memory, about 22 KB per device (TR_NOALLOC_MAX_JOBS job
+ * records and the queue's counters), held until the process
  * ends; its address is looked up on the first call on each device.  The
  * call allocates nothing (no hipMalloc, hipFree, host staging or library
  * workspace): the table is written by kernels from their arguments, the
