@@ -1143,33 +1143,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           const float ty = fmaf((float)iy1, R.hy, R.by);
           const float tz = fmaf((float)iz1, R.hz, R.bz);
           const float tn = fminf(tx, fminf(ty, tz));
-          // stop at the box exit, or when the best hit so far is not beyond the plane
-          if (!(tn < vminf(R.t1, R.bt))) {
-            st = kDone;
-          } else {
-            const bool ax = tx == tn;
-            const bool ay = !ax && ty == tn;
-            const bool az = !ax && !ay;
-            // the other axes land in the cell of the exit point, kept inside the cube
-            const int32_t nx = R.cx + med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], gorg0)) - R.cx, -m, m);
-            const int32_t ny = R.cy + med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], gorg1)) - R.cy, -m, m);
-            const int32_t nz = R.cz + med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], gorg2)) - R.cz, -m, m);
-            if (COUNT && nk1 < -1) ++l_jumps;
-            R.cx = ax ? ix1 : nx;
-            R.cy = ay ? iy1 : ny;
-            R.cz = az ? iz1 : nz;
-            // (tn < t1 is finite, so the crossed axis has a nonzero step)
-            if ((uint32_t)R.cx >= (uint32_t)H.res[0] ||
-                (uint32_t)R.cy >= (uint32_t)H.res[1] || (uint32_t)R.cz >= (uint32_t)H.res[2]) {
-              st = kDone;
-            } else {
-              if (COUNT) {
-                ++l_cells;
-                l_cells_ao += kind == kAO;
-                l_cells_sh += kind == kShadow;
-              }
-              enter = true;
-            }
+          // Go on unless the plane is the box exit or lies beyond the best hit
+          // so far.  Branch-free: a lane that stops computes a cell it never
+          // enters (its coordinates are reset when the lane takes a new ray).
+          const bool adv = tn < vminf(R.t1, R.bt);
+          const bool ax = tx == tn;
+          const bool ay = !ax & (ty == tn);
+          const bool az = !ax & !ay;
+          // the other axes land in the cell of the exit point, kept inside the cube
+          const int32_t nx = R.cx + med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], gorg0)) - R.cx, -m, m);
+          const int32_t ny = R.cy + med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], gorg1)) - R.cy, -m, m);
+          const int32_t nz = R.cz + med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], gorg2)) - R.cz, -m, m);
+          R.cx = ax ? ix1 : nx;
+          R.cy = ay ? iy1 : ny;
+          R.cz = az ? iz1 : nz;
+          // (tn < t1 is finite, so the crossed axis has a nonzero step)
+          const bool inb = ((uint32_t)R.cx < (uint32_t)H.res[0]) & ((uint32_t)R.cy < (uint32_t)H.res[1]) &
+                           ((uint32_t)R.cz < (uint32_t)H.res[2]);
+          enter = adv & inb;
+          st = enter ? st : kDone;
+          if (COUNT) {
+            l_jumps += adv & (nk1 < -1);
+            l_cells += enter;
+            l_cells_ao += enter & (kind == kAO);
+            l_cells_sh += enter & (kind == kShadow);
           }
         }
         bool tested = false, hit = false, graze = false;
@@ -1186,7 +1183,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           const float rr = s.w;  // squared radius
           const float disc = rr - ll;
           const float sg = kKappa * (rr + ll);
-          graze = RESOLVE && fabsf(disc) <= sg;
+          graze = RESOLVE & (fabsf(disc) <= sg);
           // decidable real roots: disc >= 0 and not grazing, i.e. disc > sg
           // (disc < 0 gives NaN roots, which no compare accepts)
           const bool ok = RESOLVE ? disc > sg : disc >= 0.0f;
@@ -1194,8 +1191,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           const float t0 = b - sq, t1 = b + sq;
           // nearer root if it is past tmin, else the farther (t0 <= t1);
           // only the farther on the ray's own sphere
-          t = t0 > R.tmin && !own ? t0 : t1;
-          hit = ok && t > R.tmin && t <= R.t1;
+          t = ((t0 > R.tmin) & !own) ? t0 : t1;
+          hit = ok & (t > R.tmin) & (t <= R.t1);
         }
         if (TRI && is_cyl && nk >= H.n_sc) {
           // ---- triangle (two-sided, Moller-Trumbore).  Undecidable in FP32,
@@ -1247,28 +1244,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           const float rr = a.w;  // squared radius
           const float disc = rr - ll;
           const float sg = kKappa * (rr + ll);
-          const bool g0 = RESOLVE && nonpar && fabsf(disc) <= sg;
-          const bool ok = nonpar && (RESOLVE ? disc > sg : disc >= 0.0f);  // (as for spheres)
+          const bool g0 = RESOLVE & nonpar & (fabsf(disc) <= sg);
+          const bool ok = nonpar & (RESOLVE ? disc > sg : disc >= 0.0f);  // (as for spheres)
           const float sq = sqrtf_fast(disc * iA);
           const float tl = tc - sq, th = tc + sq;
           const float kL = kKappa * w.w;
           const float sl = Dw + tl * dw, sh = Dw + th * dw;
-          const bool inl = ok && !own && tl > R.tmin && tl <= R.t1;  // own: far root only
-          const bool inh = ok && th > R.tmin && th <= R.t1;
-          const bool gl = RESOLVE && inl && (fabsf(sl) <= kL || fabsf(sl - w.w) <= kL);
-          const bool gh = RESOLVE && inh && (fabsf(sh) <= kL || fabsf(sh - w.w) <= kL);
-          const bool hl = inl && !gl && sl >= 0.0f && sl <= w.w;
-          const bool hh = inh && !gh && sh >= 0.0f && sh <= w.w;
+          // (predicates combined with & and |: no short-circuit branches)
+          const bool inl = ok & !own & (tl > R.tmin) & (tl <= R.t1);  // own: far root only
+          const bool inh = ok & (th > R.tmin) & (th <= R.t1);
+          const float el0 = fabsf(sl), el1 = fabsf(sl - w.w), eh0 = fabsf(sh), eh1 = fabsf(sh - w.w);
+          const bool gl = RESOLVE & inl & ((el0 <= kL) | (el1 <= kL));
+          const bool gh = RESOLVE & inh & ((eh0 <= kL) | (eh1 <= kL));
+          const bool hl = inl & !gl & (sl >= 0.0f) & (sl <= w.w);
+          const bool hh = inh & !gh & (sh >= 0.0f) & (sh <= w.w);
           // the near root decides first; an undecidable root defers to FP64
-          graze = g0 || gl || (!hl && gh);
-          hit = !graze && (hl || hh);
+          graze = g0 | gl | (!hl & gh);
+          hit = !graze & (hl | hh);
           t = hl ? tl : th;
         }
         if (tested) {
           // skipped: the surface an outward ray leaves, and the own triangle
-          const bool live = nk != R.skip && !(TRI && own && nk >= H.n_sc);
-          hit = hit && live;
-          graze = graze && live;
+          const bool live = (nk != R.skip) & !(TRI & own & (nk >= H.n_sc));
+          hit = hit & live;
+          graze = graze & live;
           if (COUNT) {
             l_own += !live;
             l_tests_ao += kind == kAO;
@@ -1292,10 +1291,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             l_rn += graze && !anyhit;
           }
           // nearest hit (ties to the lower id); any hit ends a shadow/AO ray
-          const bool take = hit && (anyhit || t < R.bt || (t == R.bt && nk < R.bk));
+          const bool take = hit & (anyhit | (t < R.bt) | ((t == R.bt) & (nk < R.bk)));
           R.bt = take ? t : R.bt;
           R.bk = take ? nk : R.bk;
-          st = (anyhit && hit) ? kDone : st;
+          st = (anyhit & hit) ? kDone : st;
           if (RESOLVE) {
             st = graze ? kPaused : st;
             gk = graze ? nk : gk;
