@@ -224,7 +224,8 @@ enum {
  * the acceleration structure instead (see there).  Zero fields take
  * defaults. */
 typedef struct {
-  int32_t tile_w;            /* tile width in pixels: 4, 8, 16, 32 or 64; tiles hold 64 pixels */
+  int32_t tile_w;            /* tile width in pixels: 4, 8, 16, 32 or 64; tiles hold 64
+                                pixels (default 64: one row segment per tile) */
   int32_t banks;             /* pixel banks (tiles in flight) per wave: 2 or 3 (queue depth) */
   int32_t waves_per_cu;      /* persistent waves launched per compute unit, 1..32 */
   int32_t refill_below;      /* refill when fewer than this many lanes are busy, 1..64 */

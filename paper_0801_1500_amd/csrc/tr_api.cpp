@@ -861,8 +861,13 @@ extern "C" void tr_scene_destroy(tr_scene *s) {
 // ------------------------------------------------------------------- jobs
 static bool valid_tile_w(int32_t w) { return w == 4 || w == 8 || w == 16 || w == 32 || w == 64; }
 
+// Tiles of one 64-pixel row segment by default: a tile's frame write is one
+// 768-byte run, so few cache lines are shared between tiles (finished at
+// different times, a shared line tends to leave the L2 twice).
+constexpr int32_t kDefaultTileW = 64;
+
 static tr_status default_tune(tr_tune *t) {
-  t->tile_w = 8;
+  t->tile_w = kDefaultTileW;
   t->banks = 2;
   t->waves_per_cu = 20;
   t->refill_below = 32;
@@ -1287,7 +1292,7 @@ extern "C" tr_status tr_render(const tr_scene *s, const tr_camera *c, const tr_p
 }
 
 extern "C" int64_t tr_tile_count(int32_t width, int32_t height, int32_t tile_w) {
-  if (tile_w == 0) tile_w = 8;
+  if (tile_w == 0) tile_w = kDefaultTileW;
   if (!valid_tile_w(tile_w) || width <= 0 || height <= 0) return -1;
   const int32_t th = 64 / tile_w;
   return (int64_t)((width + tile_w - 1) / tile_w) * ((height + th - 1) / th);

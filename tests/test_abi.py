@@ -59,7 +59,7 @@ def test_tile_count(tr):
     assert tr.tile_count(128, 128) == 256
     assert tr.tile_count(3860, 4548, 8) == 483 * 569
     assert tr.tile_count(65, 9, 16) == 5 * 3
-    assert tr.tile_count(3860, 4548) == 483 * 569  # default: 8 x 8 tiles
+    assert tr.tile_count(3860, 4548) == 61 * 4548  # default: 64 x 1 tiles
     assert tr.tile_count(3860, 4548, 64) == 61 * 4548
     with pytest.raises(ValueError):
         tr.tile_count(10, 10, 7)
