@@ -1026,6 +1026,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       const SceneHot H = load_hot(&A.jobs[uni(scene_job)]);
       const int32_t thresh = uni(can_refill ? A.refill_below : 1);
       const bool anyhit = kind >= kShadow;
+      const uint64_t near_m = ballot(!anyhit);  // lanes with a nearest-hit ray (or idle)
       // grid-frame offsets of the jump step, held in VGPRs for the whole
       // loop: the step's FMAs take the scale from an SGPR, and one VOP3
       // instruction reads at most one SGPR (else a copy every iteration)
@@ -1290,8 +1291,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             else l_rc += graze;
             l_rn += graze && !anyhit;
           }
-          // nearest hit (ties to the lower id); any hit ends a shadow/AO ray
-          const bool take = hit & (anyhit | (t < R.bt) | ((t == R.bt) & (nk < R.bk)));
+          // nearest hit (ties to the lower id); any hit ends a shadow/AO ray.
+          // Most iterations test only shadow and AO rays (about nine rays in
+          // ten are), so the nearest-hit order is decided only when a tested
+          // lane carries a nearest-hit ray: a wave-uniform branch on the
+          // execution mask (the tested lanes) against the phase's mask of
+          // such lanes.  (The empty asm statement keeps the compiler from
+          // executing the body unconditionally and selecting its result.)
+          bool take = hit;
+          if (__builtin_amdgcn_read_exec() & near_m) {
+            asm volatile("");
+            take = hit & (anyhit | (t < R.bt) | ((t == R.bt) & (nk < R.bk)));
+          }
           R.bt = take ? t : R.bt;
           R.bk = take ? nk : R.bk;
           st = (anyhit & hit) ? kDone : st;
