@@ -1024,11 +1024,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           q_head != q_tail || (issue_bank >= 0 && issue_next < uni(L.bank[issue_bank].n)) ||
           (free_banks && ((held_tile < 0 && tiles_left) || (held_tile >= 0 && (held_key == cur_key || !bank_busy))));
       const SceneHot H = load_hot(&A.jobs[uni(scene_job)]);
-      // (>= 1, so the loop also ends when no lane works)
+      // (>= 1, so the loop also ends when no lane works).  Lanes paused for
+      // an FP64 re-solve wait for the loop's end: with a refill pending that
+      // comes when fewer than refill_below lanes work, else when none does.
       const int32_t thresh = uni(can_refill ? A.refill_below : 1);
-      // With nothing to refill, paused lanes end the loop once fewer than
-      // refill_below lanes work (with a refill pending, thresh does that)
-      const int32_t pthresh = uni(can_refill ? 0 : A.refill_below);
       const bool anyhit = kind >= kShadow;
       const uint64_t near_m = ballot(!anyhit);  // lanes with a nearest-hit ray (or idle)
       // grid-frame offsets of the jump step, held in VGPRs for the whole
@@ -1041,7 +1040,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         const bool work = st == kRun;
         const int32_t nwork = __popcll(ballot(work));
         if (nwork < (it >= kMinIters ? thresh : 1)) break;
-        if (RESOLVE && nwork < pthresh && it >= kMinIters && ballot(st == kPaused)) break;
         if (COUNT) {
           ++c_iters;
           c_lanes += (uint64_t)nwork;
