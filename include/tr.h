@@ -86,7 +86,7 @@ typedef struct {
                                 used only by renders with tr_params.max_layers > 1 */
   int64_t n_triangles;       /* triangles (surface representations), ids
                                 n_spheres + n_cylinders + [0, n_triangles);
-                                n_spheres + n_cylinders + n_triangles < 2^28   */
+                                n_spheres + n_cylinders + n_triangles < 2^27   */
   const double *tri_v0;      /* [n_triangles*3] vertices, finite; two-sided,
                                 hit by the Moller-Trumbore test with the edges
                                 inside; a zero-area triangle is never hit     */
@@ -256,8 +256,8 @@ typedef struct {
  * scene; TR_EINVAL on a NULL required pointer, negative count, non-finite
  * coordinate, radius <= 0, zero-length cylinder, n_lights outside 0..8, an
  * opacity outside (0, 1], cells_per_prim < 0 or n_spheres + n_cylinders +
- * n_triangles >= 2^28; TR_EUNSUPPORTED when
- * the grid would hold more than 2^30 - 64 primitive references. */
+ * n_triangles >= 2^27; TR_EUNSUPPORTED when the grid's primitive
+ * references and cells together would pass 2^29 - 1. */
 tr_status tr_scene_build(const tr_scene_desc *desc, void *hip_stream, tr_scene **out);
 
 /* Rebuild the grid from the resident device arrays (same result as the
@@ -327,11 +327,12 @@ tr_status tr_scene_save(const tr_scene *scene, const char *path, void *hip_strea
 tr_status tr_scene_load(const char *path, void *hip_stream, tr_scene **out);
 
 /* Copy the FP32 walk's view of the grid to HOST buffers (either may be NULL):
- * cellinfo [2 * n_cells], per cell (start of its list in wrefs, the list's
- * first reference), or (-distance to the nearest occupied cell, -1) for an
+ * cellinfo [2 * n_cells], per cell (byte offset of its list in wrefs, the
+ * list's first entry), or (-distance to the nearest occupied cell, -1) for an
  * empty cell, the distance Chebyshev in cells, capped at 32; and wrefs
- * [*n_walk], per occupied cell in cell order its references in ascending id
- * then 0xFFFFFFFF.  *n_walk (required) receives the wrefs length.  Derived
+ * [*n_walk], per occupied cell in cell order its references in ascending id,
+ * each stored as 16 x id (the byte offset of the primitive's 16-byte FP32
+ * records), then 0xFFFFFFFF.  *n_walk (required) receives the wrefs length.  Derived
  * from the canonical grid of tr_scene_grid_arrays; synchronises the stream. */
 tr_status tr_scene_walk_arrays(const tr_scene *scene, int32_t *cellinfo, uint32_t *wrefs,
                                int64_t *n_walk, void *hip_stream);

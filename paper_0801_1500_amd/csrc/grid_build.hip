@@ -380,9 +380,13 @@ __global__ void k_walk_sizes(const uint32_t *cell_begin, int64_t n_cells, uint32
 
 // Traversal view of a cell, after the scan of the walk-list sizes: an
 // occupied cell copies its sorted references to its walk list, appends -1,
-// and records (list start, first reference); an empty cell records
+// and records (byte offset of the list, first entry); an empty cell records
 // (-distance, -1).  One 8-byte load gives the walk the cell's first unit of
-// work, and the end marker ends the list without an end index.
+// work, and the end marker ends the list without an end index.  The lists
+// hold each primitive as its record offset, 16 x its id (the byte offset of
+// its 16-byte FP32 records), and the walk moves through them by byte offset:
+// neither needs a multiply on the walk.  (The host keeps ids below 2^27 and
+// the lists below 2^29 words, so both fit a signed 32-bit word.)
 __global__ void k_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, const uint32_t *wbegin,
                            const uint8_t *d, int64_t n_cells, uint32_t *wrefs,
                            trd::CellInfo *info) {
@@ -392,10 +396,10 @@ __global__ void k_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, con
   trd::CellInfo r;
   if (b < e) {
     const uint32_t w = wbegin[c];
-    for (uint32_t i = 0; i < e - b; ++i) wrefs[w + i] = refs[b + i];
+    for (uint32_t i = 0; i < e - b; ++i) wrefs[w + i] = refs[b + i] << 4;
     wrefs[w + (e - b)] = 0xFFFFFFFFu;
-    r.a = (int32_t)w;
-    r.c = (int32_t)refs[b];
+    r.a = (int32_t)(w << 2);
+    r.c = (int32_t)(refs[b] << 4);
   } else {
     r.a = -(int32_t)max((uint32_t)d[c], 1u);
     r.c = -1;

@@ -187,12 +187,13 @@ struct Ray {
   float hx, hy, hz;
   int32_t cx, cy, cz;
   int32_t sx, sy, sz;  // minus the step signs (-1, 0, 1 for d > 0, = 0, < 0)
-  int32_t rc;          // cursor into the cell's walk list; -(distance) in an empty cell
-  int32_t nk;          // wrefs[rc]: the next reference, -1 at the list end (loaded ahead)
+  int32_t rc;          // byte offset of the cursor in the cell's walk list; -(distance) in an empty cell
+  int32_t nk;          // the entry at rc: the next primitive (record offset, 16 x id),
+                       // -1 at the list end (loaded ahead)
   float bt;            // best t
-  int32_t bk;          // best id (-1 = none)
+  int32_t bk;          // best primitive, record offset (-1 = none)
   int32_t skip;         // k >= 0: never report k; -2 - k: k is the ray's own surface,
-                        // left from inside; -1: none
+                        // left from inside; -1: none (k: record offsets)
 };
 
 // Scene fields used by the traversal, loaded (wave-uniform) from the job
@@ -203,6 +204,10 @@ struct Ray {
 #define TR_CONST __attribute__((address_space(4)))
 typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef uint32_t vu2 __attribute__((ext_vector_type(2)));
+// A primitive's record offset: 16 x its global id, the byte offset of its
+// 16-byte FP32 records (the form the walk lists store ids in).
+constexpr int kRecShift = 4;
+static_assert(sizeof(vf4) == (1 << kRecShift), "FP32 primitive records are 16 bytes");
 struct SceneHot {
   const TR_GLOBAL uint32_t *refs;
   const TR_GLOBAL trd::CellInfo *cellinfo;
@@ -210,8 +215,12 @@ struct SceneHot {
   const TR_GLOBAL vf4 *triV32, *triE1_32, *triE2_32;
   const TR_GLOBAL vf4 *bvh;  // 4 records per internal node
   int32_t bvh_n;             // primitives in the BVH
-  int32_t n_s;
-  int32_t n_sc;  // first triangle id (spheres + cylinders)
+  // Inside this kernel a primitive is named by its record offset, 16 x its
+  // global id (every FP32 record is 16 bytes; the walk lists store ids that
+  // way), so an id addresses its record without a multiply: spheres are the
+  // offsets below s_end, cylinders those below c_end, triangles the rest.
+  int32_t s_end;  // 16 n_s
+  int32_t c_end;  // 16 (n_s + n_c)
   int32_t res[3];
   float lo32[3], hi32[3], inv32[3], h32[3];
   float org32[3];  // cell coordinate of the FP32 frame's origin
@@ -234,8 +243,8 @@ __device__ __forceinline__ SceneHot load_hot(const JobDev *Jg) {
   H.triE2_32 = (const TR_GLOBAL vf4 *)J->sc.triE2_32;
   H.bvh = (const TR_GLOBAL vf4 *)J->sc.bvh;
   H.bvh_n = J->sc.bvh_n;
-  H.n_s = J->sc.n_s;
-  H.n_sc = J->sc.n_s + J->sc.n_c;
+  H.s_end = J->sc.n_s << kRecShift;
+  H.c_end = (J->sc.n_s + J->sc.n_c) << kRecShift;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     H.res[q] = J->sc.res[q];
@@ -254,6 +263,11 @@ __device__ __forceinline__ SceneHot load_hot(const JobDev *Jg) {
 template <class T>
 __device__ __forceinline__ T ldg(const TR_GLOBAL T *base, uint32_t i) {
   return *(const TR_GLOBAL T *)((const TR_GLOBAL char *)base + i * (uint32_t)sizeof(T));
+}
+// base at a byte offset (no scaling)
+template <class T>
+__device__ __forceinline__ T ldgb(const TR_GLOBAL T *base, uint32_t off) {
+  return *(const TR_GLOBAL T *)((const TR_GLOBAL char *)base + off);
 }
 
 // Colour of a finished hit pixel from its slot: the lights whose shadow rays
@@ -295,7 +309,7 @@ __device__ __forceinline__ void shade_slot(const LdsT &L, const BankInfo &B, int
   }
   float ao = 1.0f;
   if (B.S > 0) ao = (float)(B.S - L.aocnt[slot]) * B.rS;
-  const vf4 alb = ldg(albedo, (uint32_t)k);
+  const vf4 alb = ldgb(albedo, (uint32_t)k);  // (k: record offset)
   const float sk = B.sky * ao;
   cr = fminf(fmaxf(alb.x * (Dr + sk) + Hr, 0.0f), 1.0f);
   cg = fminf(fmaxf(alb.y * (Dg + sk) + Hg, 0.0f), 1.0f);
@@ -320,7 +334,7 @@ __device__ __forceinline__ void shade_tile(LdsT &L, int32_t b, int32_t lane,
       int32_t x, y;
       bank_pixel(B, lane, x, y);
       const int64_t pid = (int64_t)y * B.W + x;
-      if (B.hit_id) B.hit_id[pid] = k;
+      if (B.hit_id) B.hit_id[pid] = k >> kRecShift;  // the global id (-1 stays -1)
       if (B.ao_mask) B.ao_mask[pid] = k >= 0 ? L.aomask[slot] : 0u;
       if (B.light_mask) B.light_mask[pid] = k >= 0 ? (uint8_t)L.lmask[slot] : (uint8_t)0;
     }
@@ -336,7 +350,8 @@ __device__ __forceinline__ void load_cell(Ray &R, const SceneHot &S) {
   // res <= 512 per axis: the products fit the 24-bit multiplier
   const uint32_t cell = mad24(mad24((uint32_t)R.cz, (uint32_t)S.res[1], (uint32_t)R.cy),
                               (uint32_t)S.res[0], (uint32_t)R.cx);
-  // one 8-byte load: list start (or -distance) and first reference (-1 if empty)
+  // one 8-byte load: byte offset of the cell's list in wrefs (or -distance)
+  // and its first entry (-1 if empty)
   const vu2 ci = ldg((const TR_GLOBAL vu2 *)S.cellinfo, cell);
   R.rc = (int32_t)ci.x;
   R.nk = (int32_t)ci.y;
@@ -541,7 +556,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         const double tmin = kind == kPrimary ? 0.0 : kEpsD;
         const double tmax = kind == kAO ? J->ao_maxdist : INFINITY;
         double t = 0.0;
-        const int h = hit_prim_f64<TRI>(S, gk, o, d, tmin, tmax, t);
+        const int h = hit_prim_f64<TRI>(S, gk >> kRecShift, o, d, tmin, tmax, t);
         int32_t nst = kRun;
         if (h) {
           const float tf = (float)t;
@@ -577,19 +592,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         const float t = R.bt;
         const float Px = R.ox + t * R.dx, Py = R.oy + t * R.dy, Pz = R.oz + t * R.dz;
         float Nx, Ny, Nz;
-        if (k < S.n_s) {
-          const vf4 s = ldg(S.sph32, (uint32_t)k);
+        if (k < S.s_end) {
+          const vf4 s = ldgb(S.sph32, (uint32_t)k);
           Nx = Px - s.x;
           Ny = Py - s.y;
           Nz = Pz - s.z;
-        } else if (TRI && k >= S.n_sc) {  // triangle: e1 x e2
-          const vf4 e1 = ldg(S.triE1_32, (uint32_t)(k - S.n_sc));
-          const vf4 e2 = ldg(S.triE2_32, (uint32_t)(k - S.n_sc));
+        } else if (TRI && k >= S.c_end) {  // triangle: e1 x e2
+          const vf4 e1 = ldgb(S.triE1_32, (uint32_t)(k - S.c_end));
+          const vf4 e2 = ldgb(S.triE2_32, (uint32_t)(k - S.c_end));
           Nx = e1.y * e2.z - e1.z * e2.y;
           Ny = e1.z * e2.x - e1.x * e2.z;
           Nz = e1.x * e2.y - e1.y * e2.x;
         } else {
-          const vf4 a = ldg(S.cylA32, (uint32_t)(k - S.n_s)), w = ldg(S.cylW32, (uint32_t)(k - S.n_s));
+          const vf4 a = ldgb(S.cylA32, (uint32_t)(k - S.s_end)), w = ldgb(S.cylW32, (uint32_t)(k - S.s_end));
           const float Dx = R.ox - a.x, Dy = R.oy - a.y, Dz = R.oz - a.z;
           const float sax = (Dx * w.x + Dy * w.y + Dz * w.z) + t * (R.dx * w.x + R.dy * w.y + R.dz * w.z);
           Nx = (Dx + t * R.dx) - sax * w.x;
@@ -616,7 +631,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           if (cl > (float)kLightMin) lv |= 1u << l;
           near0 |= fabsf(cl) <= kKappa;
         }
-        if (TRI && k >= S.n_sc) {
+        if (TRI && k >= S.c_end) {
           // A triangle's normal is the same over the whole face, so a sign
           // decided by FP32 rounding (a normal exactly perpendicular to a
           // light, a zero z component choosing the AO basis, a face seen
@@ -627,7 +642,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             if (COUNT) ++l_sg;
             int32_t px = 0, py = 0;
             bank_pixel(Bk, slot & 63, px, py);
-            tri_signs_f64(A.jobs[Bk.job], k - S.n_sc, kind == kPrimary, px, py, R.dx, R.dy, R.dz,
+            tri_signs_f64(A.jobs[Bk.job], (k - S.c_end) >> kRecShift, kind == kPrimary, px, py, R.dx, R.dy, R.dz,
                           Nx, Ny, Nz, front, lv);
           }
         }
@@ -702,7 +717,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         }
         layer = L.layer[slot];
         if (layer == 0) {  // hit id and masks: the first surface's
-          if (B.hit_id) B.hit_id[pid] = hid;
+          if (B.hit_id) B.hit_id[pid] = hid >> kRecShift;  // the global id (-1 stays -1)
           if (B.ao_mask) B.ao_mask[pid] = am;
           if (B.light_mask) B.light_mask[pid] = (uint8_t)lm;
         }
@@ -1058,8 +1073,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         // also need busy/cyl_wait lanes) -- so the wave does not pay for every
         // code path each iteration; the other lanes wait.  The decisions are
         // wave-uniform; each lane's type is one compare.
-        const bool want_sph = (uint32_t)nk < (uint32_t)H.n_s;  // nk = -1: no
-        const bool want_cyl = nk >= H.n_s;
+        const bool want_sph = (uint32_t)nk < (uint32_t)H.s_end;  // nk = -1: no
+        const bool want_cyl = nk >= H.s_end;
         const int32_t n_sph = __popcll(ballot(want_sph));
         const int32_t n_cyl = __popcll(ballot(want_cyl));
         const int32_t n_step = nwork - n_sph - n_cyl;
@@ -1076,7 +1091,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         // behind it; the step's own cell load is issued last, after the tests
         // have waited for their data, and is consumed next iteration.
         vf4 sdat;  // (read only where is_sph)
-        if (is_sph) sdat = ldg(H.sph32, (uint32_t)nk);
+        if (is_sph) sdat = ldgb(H.sph32, (uint32_t)nk);
         bool enter = false;  // the step moved into a cell inside the grid
         if (BVH && is_step) {
           // ---- BVH node: test both children's boxes against (tmin, min(t1,
@@ -1120,7 +1135,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           }
           R.cx = sp;
           R.rc = have && item >= 0 ? item : -1;
-          R.nk = have && item < 0 && -item - 1 < H.bvh_n ? -item - 1 : -1;
+          R.nk = have && item < 0 && -item - 1 < H.bvh_n ? (-item - 1) << kRecShift : -1;
           if (R.rc < 0 && R.nk < 0) st = kDone;
           if (COUNT) ++l_cells;
         }
@@ -1194,14 +1209,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           t = ((t0 > R.tmin) & !own) ? t0 : t1;
           hit = ok & (t > R.tmin) & (t <= R.t1);
         }
-        if (TRI && is_cyl && nk >= H.n_sc) {
+        if (TRI && is_cyl && nk >= H.c_end) {
           // ---- triangle (two-sided, Moller-Trumbore).  Undecidable in FP32,
           // and so re-solved in FP64: a ray within 2^-12 of the triangle's
           // plane (|det| against |e1 x e2|), or a hit point within 2^-12 of an
           // edge in barycentric terms.
           tested = true;
-          const uint32_t m = (uint32_t)(nk - H.n_sc);
-          const vf4 V = ldg(H.triV32, m), E1 = ldg(H.triE1_32, m), E2 = ldg(H.triE2_32, m);
+          const uint32_t m = (uint32_t)(nk - H.c_end);  // byte offset of its records
+          const vf4 V = ldgb(H.triV32, m), E1 = ldgb(H.triE1_32, m), E2 = ldgb(H.triE2_32, m);
           const float Px = R.dy * E2.z - R.dz * E2.y, Py = R.dz * E2.x - R.dx * E2.z,
                       Pz = R.dx * E2.y - R.dy * E2.x;
           const float det = E1.x * Px + E1.y * Py + E1.z * Pz;
@@ -1221,8 +1236,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           hit = !graze && det != 0.0f && u >= 0.0f && v >= 0.0f && w >= 0.0f && in_t;
         } else if (is_cyl) {
           tested = true;
-          const vf4 a = ldg(H.cylA32, (uint32_t)(nk - H.n_s));
-          const vf4 w = ldg(H.cylW32, (uint32_t)(nk - H.n_s));
+          const vf4 a = ldgb(H.cylA32, (uint32_t)(nk - H.s_end));
+          const vf4 w = ldgb(H.cylW32, (uint32_t)(nk - H.s_end));
           const float Dx = R.ox - a.x, Dy = R.oy - a.y, Dz = R.oz - a.z;
           const float dw = R.dx * w.x + R.dy * w.y + R.dz * w.z;
           const float Dw = Dx * w.x + Dy * w.y + Dz * w.z;
@@ -1265,7 +1280,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         }
         if (tested) {
           // skipped: the surface an outward ray leaves, and the own triangle
-          const bool live = (nk != R.skip) & !(TRI & own & (nk >= H.n_sc));
+          const bool live = (nk != R.skip) & !(TRI & own & (nk >= H.c_end));
           hit = hit & live;
           graze = graze & live;
           if (COUNT) {
@@ -1274,10 +1289,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             l_tests_sh += kind == kShadow;
           }
           if (COUNT && live) {
-            if (nk < H.n_s) {
+            if (nk < H.s_end) {
               ++l_st;
               l_sh += hit;
-            } else if (TRI && nk >= H.n_sc) {
+            } else if (TRI && nk >= H.c_end) {
               ++l_tt;
               l_th += hit;
             } else {
@@ -1285,8 +1300,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
               l_ch += hit;
             }
             l_res += graze;
-            if (nk < H.n_s) l_rs += graze;
-            else if (TRI && nk >= H.n_sc) l_rt += graze;
+            if (nk < H.s_end) l_rs += graze;
+            else if (TRI && nk >= H.c_end) l_rt += graze;
             else l_rc += graze;
             l_rn += graze && !anyhit;
           }
@@ -1319,13 +1334,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             }
             R.cx = sp;
             R.rc = have && item >= 0 ? item : -1;
-            R.nk = have && item < 0 && -item - 1 < H.bvh_n ? -item - 1 : -1;
+            R.nk = have && item < 0 && -item - 1 < H.bvh_n ? (-item - 1) << kRecShift : -1;
             if (R.rc < 0 && R.nk < 0 && st == kRun) st = kDone;
           } else {
             // next reference (after the last use of this one, so the load can
             // land in its register and stay in flight into the next iteration)
-            ++R.rc;
-            R.nk = (int32_t)ldg(H.refs, (uint32_t)R.rc);  // -1 past the cell's last reference
+            R.rc += 4;  // (a byte offset into wrefs)
+            R.nk = (int32_t)ldgb(H.refs, (uint32_t)R.rc);  // -1 past the cell's last reference
           }
         }
         if (!BVH && enter) load_cell(R, H);

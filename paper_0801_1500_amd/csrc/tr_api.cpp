@@ -256,12 +256,12 @@ static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
   // The total is summed in 64 bits: overlapping large primitives can list
   // more than 2^32 references, which the 32-bit scan would wrap.  Walk lists
   // (references plus one end marker per occupied cell) are addressed with
-  // 32-bit byte offsets by the traversal, so the limit is checked before the
-  // scan and the scatter run.
+  // signed 32-bit byte offsets by the traversal, so the limit is checked
+  // before the scan and the scatter run.
   const unsigned long long R64 = *s->h_total;
-  if (R64 + (unsigned long long)nc + 1ull > (1ull << 30))
+  if (R64 + (unsigned long long)nc + 1ull > (1ull << 29))
     return fail(TR_EUNSUPPORTED,
-                "grid has %llu references and %lld cells (limit 2^30 together); lower cells_per_prim",
+                "grid has %llu references and %lld cells (limit 2^29 together); lower cells_per_prim",
                 R64, (long long)nc);
   const int64_t R = (int64_t)R64;
   const int64_t W = R + nc + 1;  // bound on the walk-list total
@@ -301,8 +301,9 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   if (d->n_spheres < 0 || d->n_cylinders < 0 || d->n_triangles < 0)
     return fail(TR_EINVAL, "negative primitive count");
   const int64_t n_all = d->n_spheres + d->n_cylinders + d->n_triangles;
-  // the traversal addresses primitive records (16 B) with 32-bit byte offsets
-  if (n_all >= (int64_t)1 << 28) return fail(TR_EINVAL, "too many primitives (limit 2^28 - 1)");
+  // the traversal names a primitive by its record offset, 16 x its id (the
+  // byte offset of its 16-byte FP32 records), in a signed 32-bit word
+  if (n_all >= (int64_t)1 << 27) return fail(TR_EINVAL, "too many primitives (limit 2^27 - 1)");
   if (d->n_lights < 0 || d->n_lights > 8) return fail(TR_EINVAL, "n_lights must be 0..8");
   if (!(d->cells_per_prim >= 0.0) || !std::isfinite(d->cells_per_prim))
     return fail(TR_EINVAL, "cells_per_prim must be finite and >= 0");

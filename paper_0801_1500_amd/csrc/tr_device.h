@@ -15,10 +15,10 @@
 //                        box: lo32 = lo - org, hi32 = hi - org, eye32 = eye - org)
 //   albedo float4[N]     (r, g, b, opacity) by global id
 //   cell_begin uint32[n_cells + 1], refs uint32[n_refs + 64]   the uniform grid
-//   cellinfo CellInfo[n_cells] (list start, first reference) of an occupied cell,
+//   cellinfo CellInfo[n_cells] (list byte offset, first entry) of an occupied cell,
 //                            or (-distance to the nearest occupied cell, -1) of an
 //                            empty one: the FP32 walk's view, one load
-//   wrefs uint32[n_refs + occupied cells]  per occupied cell its references then -1
+//   wrefs uint32[n_refs + occupied cells]  per occupied cell its references (16 x id) then -1
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -29,8 +29,8 @@ namespace trd {
 // walk reads an occupied cell's references from its own list in wrefs: the
 // cell's sorted references followed by -1, so the walk needs no end index.
 struct CellInfo {
-  int32_t a;  // occupied: index of the cell's list in wrefs; empty: -(Chebyshev distance)
-  int32_t c;  // occupied: the list's first reference; empty: -1
+  int32_t a;  // occupied: byte offset of the cell's list in wrefs; empty: -(Chebyshev distance)
+  int32_t c;  // occupied: the list's first entry (16 x id); empty: -1
 };
 static_assert(sizeof(CellInfo) == 8, "CellInfo is two words");
 
@@ -66,7 +66,7 @@ struct SceneDev {
   const float4 *albedo;
   const uint32_t *cell_begin, *refs;
   const uint32_t *wrefs;  // walk lists (see CellInfo)
-  const CellInfo *cellinfo;  // per cell: (list start, first ref) or (-distance, -1)
+  const CellInfo *cellinfo;  // per cell: (list byte offset, first entry) or (-distance, -1)
   double lo[3], hi[3], h[3], inv[3];
   double org[3];  // origin of the FP32 frame (centre of the grid box)
   float lo32[3], hi32[3], h32[3], inv32[3];

@@ -125,10 +125,10 @@ def test_scene_validation_rejects(tr):
     assert b"zero length" in L.tr_last_error()
     h = C.c_void_p()
     assert L.tr_scene_build(None, None, C.byref(h)) == tr.TR_EINVAL
-    # 2^28 primitives exceed the 32-bit byte offsets of the traversal (the count
-    # is checked before any array is read)
-    big = tr.SceneDesc(1 << 27, good_c.ctypes.data, good_r.ctypes.data, rgb.ctypes.data,
-                       1 << 27, good_c.ctypes.data, good_c.ctypes.data, good_r.ctypes.data,
+    # 2^27 primitives exceed the traversal's record offsets (16 x id in a
+    # signed 32-bit word; the count is checked before any array is read)
+    big = tr.SceneDesc(1 << 26, good_c.ctypes.data, good_r.ctypes.data, rgb.ctypes.data,
+                       1 << 26, good_c.ctypes.data, good_c.ctypes.data, good_r.ctypes.data,
                        rgb.ctypes.data, 0, None, None, 0.0)
     assert L.tr_scene_build(C.byref(big), None, C.byref(h)) == tr.TR_EINVAL
     assert b"too many primitives" in L.tr_last_error()

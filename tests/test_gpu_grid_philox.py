@@ -63,17 +63,19 @@ def test_walk_view_matches_grid(tr, which, lam):
     # empty cells: (-distance, -1)
     assert np.array_equal(ci[~occ, 0], -np.maximum(dist[~occ], 1))
     assert np.all(ci[~occ, 1] == -1)
-    # occupied cells: list start (exclusive prefix of list lengths + 1) and first id
+    # occupied cells: byte offset of the list (4 x the exclusive prefix of
+    # list lengths + 1) and its first entry, 16 x the first id
     size = np.where(occ, cnt + 1, 0)
     start = np.cumsum(size) - size
-    assert np.array_equal(ci[occ, 0], start[occ])
-    assert np.array_equal(ci[occ, 1], refs[cb[:-1][occ]].astype(np.int64))
-    # lists: the canonical references in cell order, each list closed by ~0
+    assert np.array_equal(ci[occ, 0], 4 * start[occ])
+    assert np.array_equal(ci[occ, 1], 16 * refs[cb[:-1][occ]].astype(np.int64))
+    # lists: the canonical references in cell order as 16 x id, each list
+    # closed by ~0
     want = np.empty(len(wr), dtype=np.uint32)
     end = np.zeros(len(wr), dtype=bool)
     end[(start + cnt)[occ]] = True
     want[end] = 0xFFFFFFFF
-    want[~end] = refs
+    want[~end] = refs * 16
     assert np.array_equal(wr, want)
 
 

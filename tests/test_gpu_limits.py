@@ -85,7 +85,7 @@ def test_largest_frame(tr, oracle_mod):
 def test_reference_total_past_32_bits_refused(tr):
     """14,000 identical cylinders spanning the scene list 4.8 G references
     at 24 cells per primitive: more than 2^32, whose 32-bit wrap (0.51 G)
-    would pass the 2^30 limit (tests/test_grid_limits.py).  The build sums
+    would pass the 2^29 limit (tests/test_grid_limits.py).  The build sums
     the total in 64 bits and refuses before the scan and the scatter; a
     normal scene still builds afterwards."""
     s = scenegen.stacked_cylinders()

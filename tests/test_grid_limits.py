@@ -1,7 +1,7 @@
 """Host-side check of the grid's reference-count limit.
 
-The walk addresses its per-cell lists with 32-bit byte offsets, so the
-library refuses a grid whose references and cells together pass 2^30
+The walk addresses its per-cell lists with signed 32-bit byte offsets, so
+the library refuses a grid whose references and cells together pass 2^29
 (TR_EUNSUPPORTED).  The total has to be summed in 64 bits: overlapping large
 primitives can list more than 2^32 references, and a 32-bit sum wraps to a
 value that passes the limit.  This test computes, from the grid's definition
@@ -39,7 +39,7 @@ def test_stacked_cylinders_wrap_a_32_bit_total():
     total = s.n_prims * n_cells
     assert total > 2 ** 32
     wrapped = total % 2 ** 32
-    # a 32-bit total would pass the 2^30 limit on references + cells
-    assert wrapped + n_cells + 1 <= 2 ** 30
+    # a 32-bit total would pass the 2^29 limit on references + cells
+    assert wrapped + n_cells + 1 <= 2 ** 29
     # the true total does not
-    assert total + n_cells + 1 > 2 ** 30
+    assert total + n_cells + 1 > 2 ** 29
