@@ -1312,12 +1312,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           // execution mask (the tested lanes) against the phase's mask of
           // such lanes.  (The empty asm statement keeps the compiler from
           // executing the body unconditionally and selecting its result.)
+          // A shadow or AO ray reads only bk (hit or not) once it ends, so
+          // bt is kept only here too.
           bool take = hit;
           if (__builtin_amdgcn_read_exec() & near_m) {
             asm volatile("");
             take = hit & (anyhit | (t < R.bt) | ((t == R.bt) & (nk < R.bk)));
+            R.bt = take ? t : R.bt;
           }
-          R.bt = take ? t : R.bt;
           R.bk = take ? nk : R.bk;
           st = (anyhit & hit) ? kDone : st;
           if (RESOLVE) {
