@@ -143,12 +143,24 @@ __global__ void k_pack(const trh::PackArgs P) {
 // the grid box (the FP32 frame: the smallest magnitudes, so the least rounding,
 // wherever the scene sits).  Spheres and cylinders carry their squared radius
 // (squared in FP64, then rounded), which is all the FP32 tests use.
+//
+// The same pass takes the scene's bounding radius about that centre: the
+// largest distance from it of any point of any primitive (a sphere's centre
+// distance plus its radius, a cylinder's farther end plus its radius, a
+// triangle's farthest vertex), in FP64, as the bit pattern of a non-negative
+// double (whose order is the integer order of its bits) maxed into *rmax64
+// (zero on entry): one atomic per wave.
+__device__ __forceinline__ double dist3(double x, double y, double z) {
+  return sqrt((x * x + y * y) + z * z);
+}
+
 __global__ void k_pack32(const trh::BuildArgs a, const double4 *cylW64, double ox, double oy,
                          double oz, float4 *sph32, float4 *cylA32, float4 *cylW32, float4 *triV32,
-                         float4 *triE1_32, float4 *triE2_32) {
+                         float4 *triE1_32, float4 *triE2_32, unsigned long long *rmax64) {
   const int64_t n_s = a.n_s, n_c = a.n_c;
-  const double4 *sph64 = a.sph64, *cylA64 = a.cylA64;
+  const double4 *sph64 = a.sph64, *cylA64 = a.cylA64, *cylB64 = a.cylB64;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double ext = 0.0;  // this primitive's farthest point from the centre
   if (k >= n_s + n_c && k < n_s + n_c + a.n_t) {
     // triangle: v0 in the FP32 frame, its edges (differences taken in FP64),
     // and |e1 x e2| (the scale of the determinant) in v0's fourth word
@@ -161,18 +173,27 @@ __global__ void k_pack32(const trh::BuildArgs a, const double4 *cylW64, double o
     const double nz = e1[0] * e2[1] - e1[1] * e2[0];
     triV32[m] = make_float4((float)(A.x - ox), (float)(A.y - oy), (float)(A.z - oz),
                             (float)sqrt((nx * nx + ny * ny) + nz * nz));
+    ext = fmax(dist3(A.x - ox, A.y - oy, A.z - oz),
+               fmax(dist3(B.x - ox, B.y - oy, B.z - oz), dist3(C.x - ox, C.y - oy, C.z - oz)));
     triE1_32[m] = make_float4((float)e1[0], (float)e1[1], (float)e1[2], 0.0f);
     triE2_32[m] = make_float4((float)e2[0], (float)e2[1], (float)e2[2], 0.0f);
   }
   if (k < n_s) {
     const double4 s = sph64[k];
     sph32[k] = make_float4((float)(s.x - ox), (float)(s.y - oy), (float)(s.z - oz), (float)(s.w * s.w));
+    ext = dist3(s.x - ox, s.y - oy, s.z - oz) + s.w;
   } else if (k < n_s + n_c) {
     const int64_t m = k - n_s;
     const double4 a = cylA64[m], w = cylW64[m];
     cylA32[m] = make_float4((float)(a.x - ox), (float)(a.y - oy), (float)(a.z - oz), (float)(a.w * a.w));
     cylW32[m] = make_float4((float)w.x, (float)w.y, (float)w.z, (float)w.w);
+    const double4 b = cylB64[m];
+    ext = fmax(dist3(a.x - ox, a.y - oy, a.z - oz), dist3(b.x - ox, b.y - oy, b.z - oz)) + a.w;
   }
+  // every lane gets here (no early return): the wave's maximum, one atomic
+  for (int off = 32; off > 0; off >>= 1) ext = fmax(ext, __shfl_xor(ext, off, 64));
+  if ((threadIdx.x & 63) == 0 && ext > 0.0)
+    atomicMax(rmax64, (unsigned long long)__double_as_longlong(ext));
 }
 
 // Per-block min/max of primitive boxes -> scratch[block*6 .. +6].
@@ -722,11 +743,12 @@ hipError_t launch_pack(const PackArgs &p, hipStream_t st) {
 
 hipError_t launch_pack32(const BuildArgs &a, const double4 *cylW64, const double origin[3],
                          float4 *sph32, float4 *cylA32, float4 *cylW32, float4 *triV32,
-                         float4 *triE1_32, float4 *triE2_32, hipStream_t st) {
+                         float4 *triE1_32, float4 *triE2_32, unsigned long long *rmax64,
+                         hipStream_t st) {
   const int64_t N = (int64_t)a.n_s + a.n_c + a.n_t;
   if (N == 0) return hipSuccess;
   k_pack32<<<blocks_for(N), kBlock, 0, st>>>(a, cylW64, origin[0], origin[1], origin[2], sph32,
-                                             cylA32, cylW32, triV32, triE1_32, triE2_32);
+                                             cylA32, cylW32, triV32, triE1_32, triE2_32, rmax64);
   return hipGetLastError();
 }
 

@@ -224,6 +224,7 @@ struct SceneHot {
   int32_t res[3];
   float lo32[3], hi32[3], inv32[3], h32[3];
   float org32[3];  // cell coordinate of the FP32 frame's origin
+  float rb2, rguard2;  // bounding sphere (see SceneDev)
 };
 
 // The job table is read-only for the whole launch, so it is read through the
@@ -254,6 +255,8 @@ __device__ __forceinline__ SceneHot load_hot(const JobDev *Jg) {
     H.h32[q] = J->sc.h32[q];
     H.org32[q] = J->sc.org32[q];
   }
+  H.rb2 = J->sc.rb2_32;
+  H.rguard2 = J->sc.rguard2_32;
   return H;
 }
 
@@ -357,16 +360,37 @@ __device__ __forceinline__ void load_cell(Ray &R, const SceneHot &S) {
   R.nk = (int32_t)ci.y;
 }
 
-// Clip to the grid box and position the walk at the entry cell.
-// Returns false when the ray misses the box.
+// Clip to the grid box and to the scene's bounding sphere, and position the
+// walk at the entry cell.  Returns false when the ray misses either.
 __device__ __forceinline__ bool ray_setup(Ray &R, const SceneHot &S) {
   const float ix = rcpf(R.dx), iy = rcpf(R.dy), iz = rcpf(R.dz);
   // slab times of the box's lower and upper planes on each axis
   const float ax = (S.lo32[0] - R.ox) * ix, bx = (S.hi32[0] - R.ox) * ix;
   const float ay = (S.lo32[1] - R.oy) * iy, by = (S.hi32[1] - R.oy) * iy;
   const float az = (S.lo32[2] - R.oz) * iz, bz = (S.hi32[2] - R.oz) * iz;
-  const float t0 = fmaxf(R.tmin, fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz)));
-  const float t1 = fminf(R.tmax, fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz)));
+  float t0 = fmaxf(R.tmin, fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz)));
+  float t1 = fminf(R.tmax, fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz)));
+  {
+    // Every hit lies inside the bounding sphere about the FP32 frame's
+    // origin (the box centre), so the walk runs only over the ray's chord of
+    // it: the box's corners beyond the sphere hold nothing, and escaping
+    // shadow and AO rays would otherwise cross them by empty-space jumps.
+    // Closest-approach form (as the sphere test): b = t of the closest point,
+    // l = its offset, chord half-length sqrt(rb^2 - |l|^2), with no
+    // cancellation of the origin's distance.  The padding (2^-10 of the
+    // radius) covers the FP32 rounding while the origin lies within 2^10
+    // radii of the centre (|o|^2 = b^2 + |l|^2); farther out the box alone
+    // clips.  (d is a unit vector.)
+    const float b = -(R.ox * R.dx + R.oy * R.dy + R.oz * R.dz);
+    const float lx = fmaf(b, R.dx, R.ox), ly = fmaf(b, R.dy, R.oy), lz = fmaf(b, R.dz, R.oz);
+    const float ll = lx * lx + ly * ly + lz * lz;
+    const float disc = S.rb2 - ll;
+    if (fmaf(b, b, ll) < S.rguard2) {
+      const float sq = sqrtf_fast(fmaxf(disc, 0.0f));
+      t0 = fmaxf(t0, b - sq);
+      t1 = disc >= 0.0f ? fminf(t1, b + sq) : -INFINITY;
+    }
+  }
   R.t1 = t1;
   R.bt = INFINITY;
   R.bk = -1;

@@ -73,7 +73,8 @@ struct tr_scene {
   trd::CellInfo *cellinfo = nullptr;
   uint8_t *dist0 = nullptr, *dist1 = nullptr;
   double *bounds_scratch = nullptr, *bounds = nullptr;
-  unsigned long long *total64 = nullptr;  // reference total of the count pass (device)
+  // device: [0] reference total of the count pass, [1] bounding radius (FP64 bits)
+  unsigned long long *total64 = nullptr;
   int64_t cap_cells = 0, cap_refs = 0, cap_scan = 0, cap_wrefs = 0;
   size_t bytes_arrays = 0;
   // pinned readback
@@ -84,6 +85,7 @@ struct tr_scene {
   bool grid_ok = false;  // false after a failed (re)build: the scene cannot render
   bool has_trans = false;  // some primitive has opacity < 1 (kept in albedo.w)
   double org[3] = {0, 0, 0};  // origin of the FP32 frame: centre of the grid box
+  double rbound = 0.0;  // largest distance from org of any point of any primitive
   SceneDev dev{};
 };
 
@@ -181,6 +183,10 @@ static void fill_scene_dev(tr_scene *s) {
     d.inv32[a] = (float)s->gp.inv[a];
     d.res[a] = s->gp.res[a];
   }
+  // the bounding sphere, padded by 2^-10 and rounded up (squares in FP64)
+  const double rp = s->rbound * (1.0 + 0x1p-10);
+  d.rb2_32 = std::nextafter((float)(rp * rp), INFINITY);
+  d.rguard2_32 = (float)(rp * rp * 0x1p20);
 }
 
 // Bounds -> parameters -> count -> scan -> scatter -> sort, from the resident
@@ -215,8 +221,10 @@ static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
     grid_params(s->h_bounds, s->h_bounds + 3, N, s->lambda, s->gp);
   }
   for (int a = 0; a < 3; ++a) s->org[a] = 0.5 * (s->gp.lo[a] + s->gp.hi[a]);
+  // reference total and bounding radius, both read back after the count pass
+  HIP_TRY(trh::launch_fill_u32((uint32_t *)s->total64, 4, 0u, st));
   HIP_TRY(trh::launch_pack32(a, s->cylW64, s->org, s->sph32, s->cylA32, s->cylW32, s->triV32,
-                             s->triE1_32, s->triE2_32, st));
+                             s->triE1_32, s->triE2_32, s->total64 + 1, st));
   const int64_t nc = s->gp.n_cells;
   if (nc + 1 > s->cap_cells) {
     if (s->cell_begin) (void)hipFree(s->cell_begin);
@@ -249,16 +257,16 @@ static tr_status build_grid_impl(tr_scene *s, hipStream_t st) {
   }
   a.delta = s->gp.delta;
   HIP_TRY(trh::launch_fill_u32(s->cell_begin, nc + 1, 0u, st));
-  HIP_TRY(trh::launch_fill_u32((uint32_t *)s->total64, 2, 0u, st));
   HIP_TRY(trh::launch_count(a, s->cell_begin, s->total64, st));
-  HIP_TRY(hipMemcpyAsync(s->h_total, s->total64, sizeof(*s->h_total), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(s->h_total, s->total64, 2 * sizeof(*s->h_total), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   // The total is summed in 64 bits: overlapping large primitives can list
   // more than 2^32 references, which the 32-bit scan would wrap.  Walk lists
   // (references plus one end marker per occupied cell) are addressed with
   // signed 32-bit byte offsets by the traversal, so the limit is checked
   // before the scan and the scatter run.
-  const unsigned long long R64 = *s->h_total;
+  const unsigned long long R64 = s->h_total[0];
+  std::memcpy(&s->rbound, s->h_total + 1, sizeof(double));  // (0 for an empty scene)
   if (R64 + (unsigned long long)nc + 1ull > (1ull << 29))
     return fail(TR_EUNSUPPORTED,
                 "grid has %llu references and %lld cells (limit 2^29 together); lower cells_per_prim",
@@ -396,10 +404,10 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   ALLOC(s->triE2_32, s->n_t);
   ALLOC(s->bounds_scratch, trh::bounds_scratch_doubles(N));
   ALLOC(s->bounds, 6);
-  ALLOC(s->total64, 1);
+  ALLOC(s->total64, 2);
 #undef ALLOC
   if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_bounds, 6 * sizeof(double), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_total, sizeof(*s->h_total), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_total, 2 * sizeof(*s->h_total), hipHostMallocDefault);
   if (e != hipSuccess)
     return bail(fail(e == hipErrorOutOfMemory ? TR_ENOMEM : TR_EDEVICE, "scene allocation: %s",
                      hipGetErrorString(e)));

@@ -72,6 +72,11 @@ struct SceneDev {
   float lo32[3], hi32[3], h32[3], inv32[3];
   float org32[3];  // (org - lo) * inv: FP32 cell coordinate of x is floor(x * inv32 + org32)
   int32_t res[3];
+  // Bounding sphere about org holding every point of every primitive, its
+  // radius padded by 2^-10 of itself: rb2_32 = the padded radius squared;
+  // rguard2_32 = (2^10 x the padded radius) squared, the distance from org
+  // up to which a ray origin's FP32 rounding stays below the padding.
+  float rb2_32, rguard2_32;
 };
 
 // One render job: scene + camera + parameters + outputs + its tile range.

@@ -36,10 +36,13 @@ struct PackArgs {
   float4 *albedo;
 };
 hipError_t launch_pack(const PackArgs &p, hipStream_t st);
-// FP32 copies with positions relative to origin (the centre of the grid box)
+// FP32 copies with positions relative to origin (the centre of the grid box);
+// also maxes the scene's bounding radius about origin (FP64 bits) into
+// *rmax64, which must be zero on entry
 hipError_t launch_pack32(const BuildArgs &a, const double4 *cylW64, const double origin[3],
                          float4 *sph32, float4 *cylA32, float4 *cylW32, float4 *triV32,
-                         float4 *triE1_32, float4 *triE2_32, hipStream_t st);
+                         float4 *triE1_32, float4 *triE2_32, unsigned long long *rmax64,
+                         hipStream_t st);
 // bounds: out6 = (lo xyz, hi xyz); scratch >= bounds_scratch_doubles(N) doubles
 int64_t bounds_scratch_doubles(int64_t n_prims);
 hipError_t launch_bounds(const BuildArgs &a, double *scratch, double *out6, hipStream_t st);
