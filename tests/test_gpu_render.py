@@ -265,3 +265,44 @@ def test_stats_counts(tr, oracle_mod, protein):
             # each ray is entered outside the loop
             assert st["lane_iters"] >= (st["cells"] + st["sph_tests"] + st["cyl_tests"]
                                         - st["rays_traced"])
+
+
+def _limb_scene():
+    # The farthest points from the grid box's centre, which the FP32 walk's
+    # bounding sphere passes through (up to its padding), are a cylinder's
+    # far end (+y) and, within 0.2% of it, a sphere's outer limb (-y); the
+    # rest sits near the centre.
+    centers = np.array([[0.0, 0.0, 0.0], [0.5, -7.0, 0.0], [1.0, 1.0, 0.5]])
+    radius = np.array([1.0, 2.0, 0.75])
+    cyl_a = np.array([[0.0, 1.5, 0.0], [0.5, 0.0, -0.5]])
+    cyl_b = np.array([[0.0, 8.0, 0.0], [1.0, 1.0, 0.5]])
+    cyl_r = np.array([0.5, 0.3])
+    rng = np.random.default_rng(7)
+    ld = np.array([[-0.5, 0.5, 1.0], [1.0, 2.0, 0.5]])
+    ld /= np.linalg.norm(ld, axis=1, keepdims=True)
+    return scenegen.Scene(centers, radius, rng.uniform(0.3, 1.0, (3, 3)).astype(np.float32),
+                          cyl_a, cyl_b, cyl_r, rng.uniform(0.3, 1.0, (2, 3)).astype(np.float32),
+                          ld, np.ones((2, 3)))
+
+
+@pytest.mark.parametrize("view", ["cylinder_end", "sphere_limb"])
+def test_bounding_sphere_limb(tr, oracle_mod, view):
+    """Rays that graze the outermost surfaces of the scene, where the walk's
+    clip to the bounding sphere is tightest, find the oracle's hits: both
+    FP32 precisions against brute force at the usual bar."""
+    s = _limb_scene()
+    if view == "cylinder_end":  # the far end's rim, seen from the side
+        c = scenegen.Camera((0.0, 8.0, 14.0), (0.0, 8.0, 0.0), (0.0, 1.0, 0.0), 12.0, 96, 96)
+    else:  # the far sphere's outer limb, seen from the side
+        c = scenegen.Camera((0.5, -8.5, 15.0), (0.5, -8.5, 0.0), (0.0, 1.0, 0.0), 12.0, 96, 96)
+    p = scenegen.Params(ao_samples=8, seed=3)
+    print("limb", view, flush=True)
+    ref = _ref(oracle_mod, s, c, p, grid=None)
+    hits = (ref["hit_id"] >= 0).sum()
+    assert 0.1 * 96 * 96 < hits < 0.9 * 96 * 96  # the silhouette crosses the frame
+    gs = tr.Scene(s)
+    for prec in ("fp32", "fp32_resolve"):
+        got = _gpu(tr, gs, c, p, prec)
+        m = compare(got, ref, p.ao_samples, s.n_lights)
+        print(prec, m, flush=True)
+        assert_fp32_parity(m)
