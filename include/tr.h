@@ -332,7 +332,7 @@ tr_status tr_scene_load(const char *path, void *hip_stream, tr_scene **out);
  * empty cell, the distance Chebyshev in cells, capped at 32; and wrefs
  * [*n_walk], per occupied cell in cell order its references in ascending id,
  * each stored as 16 x id (the byte offset of the primitive's 16-byte FP32
- * records), then 0xFFFFFFFF.  *n_walk (required) receives the wrefs length.  Derived
+ * records) with bit 0 set on the list's last entry, then 0xFFFFFFFF.  *n_walk (required) receives the wrefs length.  Derived
  * from the canonical grid of tr_scene_grid_arrays; synchronises the stream. */
 tr_status tr_scene_walk_arrays(const tr_scene *scene, int32_t *cellinfo, uint32_t *wrefs,
                                int64_t *n_walk, void *hip_stream);

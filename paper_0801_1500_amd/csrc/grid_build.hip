@@ -405,8 +405,9 @@ __global__ void k_walk_sizes(const uint32_t *cell_begin, int64_t n_cells, uint32
 // (-distance, -1).  One 8-byte load gives the walk the cell's first unit of
 // work, and the end marker ends the list without an end index.  The lists
 // hold each primitive as its record offset, 16 x its id (the byte offset of
-// its 16-byte FP32 records), and the walk moves through them by byte offset:
-// neither needs a multiply on the walk.  (The host keeps ids below 2^27 and
+// its 16-byte FP32 records), with bit 0 set on a list's last entry, and the
+// walk moves through them by byte offset: neither needs a multiply on the
+// walk, and the walk knows a cell's last test when it makes it.  (The host keeps ids below 2^27 and
 // the lists below 2^29 words, so both fit a signed 32-bit word.)
 __global__ void k_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, const uint32_t *wbegin,
                            const uint8_t *d, int64_t n_cells, uint32_t *wrefs,
@@ -417,10 +418,11 @@ __global__ void k_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, con
   trd::CellInfo r;
   if (b < e) {
     const uint32_t w = wbegin[c];
-    for (uint32_t i = 0; i < e - b; ++i) wrefs[w + i] = refs[b + i] << 4;
+    // bit 0 (free: record offsets are multiples of 16) flags a list's last entry
+    for (uint32_t i = 0; i < e - b; ++i) wrefs[w + i] = (refs[b + i] << 4) | (i + 1 == e - b ? 1u : 0u);
     wrefs[w + (e - b)] = 0xFFFFFFFFu;
     r.a = (int32_t)(w << 2);
-    r.c = (int32_t)(refs[b] << 4);
+    r.c = (int32_t)((refs[b] << 4) | (e - b == 1 ? 1u : 0u));
   } else {
     r.a = -(int32_t)max((uint32_t)d[c], 1u);
     r.c = -1;

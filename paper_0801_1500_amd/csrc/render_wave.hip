@@ -188,8 +188,9 @@ struct Ray {
   int32_t cx, cy, cz;
   int32_t sx, sy, sz;  // minus the step signs (-1, 0, 1 for d > 0, = 0, < 0)
   int32_t rc;          // byte offset of the cursor in the cell's walk list; -(distance) in an empty cell
-  int32_t nk;          // the entry at rc: the next primitive (record offset, 16 x id),
-                       // -1 at the list end (loaded ahead)
+  int32_t nk;          // the entry at rc: the next primitive (record offset, 16 x id;
+                       // bit 0 set on the cell's last), -1 once the cell is done
+                       // (loaded ahead)
   float bt;            // best t
   int32_t bk;          // best primitive, record offset (-1 = none)
   int32_t skip;         // k >= 0: never report k; -2 - k: k is the ray's own surface,
@@ -1091,7 +1092,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         // meet again at the loop head for its ballot).  Ballots inside count
         // the working lanes.
         if (work) {
+        // The entry held: a record offset (a multiple of 16) whose bit 0
+        // flags the last entry of its cell's list, or -1 (cell done).
         const int32_t nk = R.nk;
+        const int32_t nkr = nk & ~15;  // the record offset (negative stays negative)
         // Work-type scheduling: a unit type runs this iteration only if enough
         // lanes want it -- at least `mix`/64 of the largest group (cylinders
         // also need busy/cyl_wait lanes) -- so the wave does not pay for every
@@ -1110,12 +1114,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         const bool is_sph = go_sph && want_sph;
         const bool is_cyl = go_cyl && want_cyl;
         const bool is_step = go_step && !want_sph && !want_cyl;  // nk < 0
-        // Sphere records are fetched first and the step's arithmetic runs
-        // meanwhile (the two lane sets are disjoint), so the load latency hides
-        // behind it; the step's own cell load is issued last, after the tests
-        // have waited for their data, and is consumed next iteration.
+        // Sphere records are fetched first; the tests run, then the step, which
+        // takes both the lanes with no entry left (empty cells) and the lanes
+        // that just tested their cell's last entry and go on: a cell costs one
+        // iteration per entry, none extra to leave it.  The step's cell load
+        // is issued last and consumed next iteration.
         vf4 sdat;  // (read only where is_sph)
-        if (is_sph) sdat = ldgb(H.sph32, (uint32_t)nk);
+        if (is_sph) sdat = ldgb(H.sph32, (uint32_t)nkr);
         bool enter = false;  // the step moved into a cell inside the grid
         if (BVH && is_step) {
           // ---- BVH node: test both children's boxes against (tmin, min(t1,
@@ -1163,55 +1168,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           if (R.rc < 0 && R.nk < 0) st = kDone;
           if (COUNT) ++l_cells;
         }
-        if (!BVH && is_step) {
-          // ---- cell exhausted: stop, or leave it.  An empty cell carries the
-          // Chebyshev distance k to the nearest occupied cell, so the whole
-          // cube of half-size k-1 around it is empty and the walk jumps to
-          // where the ray leaves that cube (k = 1: an ordinary DDA step).
-          // Branch-free: the k = 1 step is the jump with a cube of size 0.
-          // nk = -k: rc = -distance in an empty cell, >= 0 otherwise
-          const int32_t nk1 = min(R.rc, -1);
-          const int32_t m = -1 - nk1;  // k - 1
-          // cell just beyond the cube on each axis; its near plane is crossed at
-          // b_a + i * h_a (b_a is shifted one cell for negative steps at setup);
-          // (-sign) (-k) is the offset
-          const int32_t ix1 = R.cx + __mul24(R.sx, nk1);
-          const int32_t iy1 = R.cy + __mul24(R.sy, nk1);
-          const int32_t iz1 = R.cz + __mul24(R.sz, nk1);
-          const float tx = fmaf((float)ix1, R.hx, R.bx);  // inf when d_x = 0
-          const float ty = fmaf((float)iy1, R.hy, R.by);
-          const float tz = fmaf((float)iz1, R.hz, R.bz);
-          const float tn = fminf(tx, fminf(ty, tz));
-          // Go on unless the plane is the box exit or lies beyond the best hit
-          // so far.  Branch-free: a lane that stops computes a cell it never
-          // enters (its coordinates are reset when the lane takes a new ray).
-          const bool adv = tn < vminf(R.t1, R.bt);
-          const bool ax = tx == tn;
-          const bool ay = !ax & (ty == tn);
-          const bool az = !ax & !ay;
-          // the other axes land in the cell of the exit point, kept inside the cube
-          const int32_t nx = R.cx + med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], gorg0)) - R.cx, -m, m);
-          const int32_t ny = R.cy + med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], gorg1)) - R.cy, -m, m);
-          const int32_t nz = R.cz + med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], gorg2)) - R.cz, -m, m);
-          R.cx = ax ? ix1 : nx;
-          R.cy = ay ? iy1 : ny;
-          R.cz = az ? iz1 : nz;
-          // (tn < t1 is finite, so the crossed axis has a nonzero step)
-          const bool inb = ((uint32_t)R.cx < (uint32_t)H.res[0]) & ((uint32_t)R.cy < (uint32_t)H.res[1]) &
-                           ((uint32_t)R.cz < (uint32_t)H.res[2]);
-          enter = adv & inb;
-          st = enter ? st : kDone;
-          if (COUNT) {
-            l_jumps += adv & (nk1 < -1);
-            l_cells += enter;
-            l_cells_ao += enter & (kind == kAO);
-            l_cells_sh += enter & (kind == kShadow);
-          }
-        }
         bool tested = false, hit = false, graze = false;
         float t;  // set by every test; read only on a tested lane
         asm volatile("" : "=v"(t));
-        const bool own = nk == -2 - R.skip;  // the surface this ray leaves from inside
+        const bool own = nkr == -2 - R.skip;  // the surface this ray leaves from inside
+        const bool last = !BVH & (nk != nkr) & (nk >= 0);  // the cell's last entry
         if (is_sph) {
           tested = true;
           const vf4 s = sdat;
@@ -1233,13 +1194,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           t = ((t0 > R.tmin) & !own) ? t0 : t1;
           hit = ok & (t > R.tmin) & (t <= R.t1);
         }
-        if (TRI && is_cyl && nk >= H.c_end) {
+        if (TRI && is_cyl && nkr >= H.c_end) {
           // ---- triangle (two-sided, Moller-Trumbore).  Undecidable in FP32,
           // and so re-solved in FP64: a ray within 2^-12 of the triangle's
           // plane (|det| against |e1 x e2|), or a hit point within 2^-12 of an
           // edge in barycentric terms.
           tested = true;
-          const uint32_t m = (uint32_t)(nk - H.c_end);  // byte offset of its records
+          const uint32_t m = (uint32_t)(nkr - H.c_end);  // byte offset of its records
           const vf4 V = ldgb(H.triV32, m), E1 = ldgb(H.triE1_32, m), E2 = ldgb(H.triE2_32, m);
           const float Px = R.dy * E2.z - R.dz * E2.y, Py = R.dz * E2.x - R.dx * E2.z,
                       Pz = R.dx * E2.y - R.dy * E2.x;
@@ -1260,8 +1221,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           hit = !graze && det != 0.0f && u >= 0.0f && v >= 0.0f && w >= 0.0f && in_t;
         } else if (is_cyl) {
           tested = true;
-          const vf4 a = ldgb(H.cylA32, (uint32_t)(nk - H.s_end));
-          const vf4 w = ldgb(H.cylW32, (uint32_t)(nk - H.s_end));
+          const vf4 a = ldgb(H.cylA32, (uint32_t)(nkr - H.s_end));
+          const vf4 w = ldgb(H.cylW32, (uint32_t)(nkr - H.s_end));
           const float Dx = R.ox - a.x, Dy = R.oy - a.y, Dz = R.oz - a.z;
           const float dw = R.dx * w.x + R.dy * w.y + R.dz * w.z;
           const float Dw = Dx * w.x + Dy * w.y + Dz * w.z;
@@ -1304,7 +1265,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         }
         if (tested) {
           // skipped: the surface an outward ray leaves, and the own triangle
-          const bool live = (nk != R.skip) & !(TRI & own & (nk >= H.c_end));
+          const bool live = (nkr != R.skip) & !(TRI & own & (nkr >= H.c_end));
           hit = hit & live;
           graze = graze & live;
           if (COUNT) {
@@ -1313,10 +1274,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             l_tests_sh += kind == kShadow;
           }
           if (COUNT && live) {
-            if (nk < H.s_end) {
+            if (nkr < H.s_end) {
               ++l_st;
               l_sh += hit;
-            } else if (TRI && nk >= H.c_end) {
+            } else if (TRI && nkr >= H.c_end) {
               ++l_tt;
               l_th += hit;
             } else {
@@ -1324,8 +1285,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
               l_ch += hit;
             }
             l_res += graze;
-            if (nk < H.s_end) l_rs += graze;
-            else if (TRI && nk >= H.c_end) l_rt += graze;
+            if (nkr < H.s_end) l_rs += graze;
+            else if (TRI && nkr >= H.c_end) l_rt += graze;
             else l_rc += graze;
             l_rn += graze && !anyhit;
           }
@@ -1341,14 +1302,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           bool take = hit;
           if (__builtin_amdgcn_read_exec() & near_m) {
             asm volatile("");
-            take = hit & (anyhit | (t < R.bt) | ((t == R.bt) & (nk < R.bk)));
+            take = hit & (anyhit | (t < R.bt) | ((t == R.bt) & (nkr < R.bk)));
             R.bt = take ? t : R.bt;
           }
-          R.bk = take ? nk : R.bk;
+          R.bk = take ? nkr : R.bk;
           st = (anyhit & hit) ? kDone : st;
           if (RESOLVE) {
             st = graze ? kPaused : st;
-            gk = graze ? nk : gk;
+            gk = graze ? nkr : gk;
           }
           if (BVH) {  // next stacked item, or the walk is over
             int32_t sp = R.cx;
@@ -1363,10 +1324,62 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             R.nk = have && item < 0 && -item - 1 < H.bvh_n ? (-item - 1) << kRecShift : -1;
             if (R.rc < 0 && R.nk < 0 && st == kRun) st = kDone;
           } else {
-            // next reference (after the last use of this one, so the load can
-            // land in its register and stay in flight into the next iteration)
-            R.rc += 4;  // (a byte offset into wrefs)
-            R.nk = (int32_t)ldgb(H.refs, (uint32_t)R.rc);  // -1 past the cell's last reference
+            // next entry (after the last use of this one, so the load can land
+            // in its register and stay in flight into the next iteration);
+            // after the cell's last entry none: the lane steps now, or (paused
+            // or done) finds -1
+            if (last) {
+              R.nk = -1;
+            } else {
+              R.rc += 4;  // (a byte offset into wrefs)
+              R.nk = (int32_t)ldgb(H.refs, (uint32_t)R.rc);
+            }
+          }
+        }
+        // lanes with nothing left in their cell: stepping on
+        if (!BVH && (is_step | (tested & last & (st == kRun)))) {
+          // ---- cell exhausted: stop, or leave it.  An empty cell carries the
+          // Chebyshev distance k to the nearest occupied cell, so the whole
+          // cube of half-size k-1 around it is empty and the walk jumps to
+          // where the ray leaves that cube (k = 1: an ordinary DDA step).
+          // Branch-free: the k = 1 step is the jump with a cube of size 0.
+          // nk = -k: rc = -distance in an empty cell, >= 0 otherwise
+          const int32_t nk1 = min(R.rc, -1);
+          const int32_t m = -1 - nk1;  // k - 1
+          // cell just beyond the cube on each axis; its near plane is crossed at
+          // b_a + i * h_a (b_a is shifted one cell for negative steps at setup);
+          // (-sign) (-k) is the offset
+          const int32_t ix1 = R.cx + __mul24(R.sx, nk1);
+          const int32_t iy1 = R.cy + __mul24(R.sy, nk1);
+          const int32_t iz1 = R.cz + __mul24(R.sz, nk1);
+          const float tx = fmaf((float)ix1, R.hx, R.bx);  // inf when d_x = 0
+          const float ty = fmaf((float)iy1, R.hy, R.by);
+          const float tz = fmaf((float)iz1, R.hz, R.bz);
+          const float tn = fminf(tx, fminf(ty, tz));
+          // Go on unless the plane is the box exit or lies beyond the best hit
+          // so far.  Branch-free: a lane that stops computes a cell it never
+          // enters (its coordinates are reset when the lane takes a new ray).
+          const bool adv = tn < vminf(R.t1, R.bt);
+          const bool ax = tx == tn;
+          const bool ay = !ax & (ty == tn);
+          const bool az = !ax & !ay;
+          // the other axes land in the cell of the exit point, kept inside the cube
+          const int32_t nx = R.cx + med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], gorg0)) - R.cx, -m, m);
+          const int32_t ny = R.cy + med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], gorg1)) - R.cy, -m, m);
+          const int32_t nz = R.cz + med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], gorg2)) - R.cz, -m, m);
+          R.cx = ax ? ix1 : nx;
+          R.cy = ay ? iy1 : ny;
+          R.cz = az ? iz1 : nz;
+          // (tn < t1 is finite, so the crossed axis has a nonzero step)
+          const bool inb = ((uint32_t)R.cx < (uint32_t)H.res[0]) & ((uint32_t)R.cy < (uint32_t)H.res[1]) &
+                           ((uint32_t)R.cz < (uint32_t)H.res[2]);
+          enter = adv & inb;
+          st = enter ? st : kDone;
+          if (COUNT) {
+            l_jumps += adv & (nk1 < -1);
+            l_cells += enter;
+            l_cells_ao += enter & (kind == kAO);
+            l_cells_sh += enter & (kind == kShadow);
           }
         }
         if (!BVH && enter) load_cell(R, H);

@@ -18,7 +18,8 @@
 //   cellinfo CellInfo[n_cells] (list byte offset, first entry) of an occupied cell,
 //                            or (-distance to the nearest occupied cell, -1) of an
 //                            empty one: the FP32 walk's view, one load
-//   wrefs uint32[n_refs + occupied cells]  per occupied cell its references (16 x id) then -1
+//   wrefs uint32[n_refs + occupied cells]  per occupied cell its references (16 x id,
+//                        bit 0 set on the last) then -1
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -30,7 +31,7 @@ namespace trd {
 // cell's sorted references followed by -1, so the walk needs no end index.
 struct CellInfo {
   int32_t a;  // occupied: byte offset of the cell's list in wrefs; empty: -(Chebyshev distance)
-  int32_t c;  // occupied: the list's first entry (16 x id); empty: -1
+  int32_t c;  // occupied: the list's first entry (16 x id, bit 0: the only one); empty: -1
 };
 static_assert(sizeof(CellInfo) == 8, "CellInfo is two words");
 

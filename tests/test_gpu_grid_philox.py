@@ -64,18 +64,22 @@ def test_walk_view_matches_grid(tr, which, lam):
     assert np.array_equal(ci[~occ, 0], -np.maximum(dist[~occ], 1))
     assert np.all(ci[~occ, 1] == -1)
     # occupied cells: byte offset of the list (4 x the exclusive prefix of
-    # list lengths + 1) and its first entry, 16 x the first id
+    # list lengths + 1) and its first entry, 16 x the first id, bit 0 set
+    # when that entry is the list's only one
     size = np.where(occ, cnt + 1, 0)
     start = np.cumsum(size) - size
     assert np.array_equal(ci[occ, 0], 4 * start[occ])
-    assert np.array_equal(ci[occ, 1], 16 * refs[cb[:-1][occ]].astype(np.int64))
-    # lists: the canonical references in cell order as 16 x id, each list
-    # closed by ~0
+    assert np.array_equal(ci[occ, 1], 16 * refs[cb[:-1][occ]].astype(np.int64) + (cnt[occ] == 1))
+    # lists: the canonical references in cell order as 16 x id, the last of
+    # each with bit 0 set, each list closed by ~0
     want = np.empty(len(wr), dtype=np.uint32)
     end = np.zeros(len(wr), dtype=bool)
     end[(start + cnt)[occ]] = True
+    last = np.zeros(len(wr), dtype=bool)
+    last[(start + cnt - 1)[occ]] = True
     want[end] = 0xFFFFFFFF
     want[~end] = refs * 16
+    want[last] |= 1
     assert np.array_equal(wr, want)
 
 
