@@ -261,10 +261,14 @@ def test_stats_counts(tr, oracle_mod, protein):
             assert st["resolves_nearest"] <= st["resolves"]
         if prec != "fp64":
             assert st["lane_iters"] <= 64 * st["wave_iters"]
-            # every unit of work takes one lane-iteration; only the first cell of
-            # each ray is entered outside the loop
-            assert st["lane_iters"] >= (st["cells"] + st["sph_tests"] + st["cyl_tests"]
-                                        - st["rays_traced"])
+            # a lane-iteration makes at most one test and at most one step (the
+            # two together when the test is its cell's last); only the first
+            # cell of each ray is entered outside the loop.  (Lane-iterations
+            # also count lanes waiting for their work type to run.)
+            assert st["lane_iters"] >= st["sph_tests"] + st["cyl_tests"]
+            assert st["lane_iters"] >= st["cells"] - st["rays_traced"]
+            assert 2 * st["lane_iters"] >= (st["cells"] + st["sph_tests"] + st["cyl_tests"]
+                                            - st["rays_traced"])
 
 
 def _limb_scene():
