@@ -113,14 +113,15 @@ struct Lds {
   static constexpr int NT = TRANS ? NS : 1;  // transparency state only when compositing
   float px[NS], py[NS], pz[NS];
   float nx[NS], ny[NS], nz[NS];
-  int32_t prim[NS];     // hit primitive
-  int32_t skip[NS];     // secondary rays: k >= 0 skip primitive k; -2 - k: k is the surface
-                        // they leave from inside (far root only); -1 = none
-  int32_t pending[NS];  // secondary rays not yet finished
-  uint32_t lvalid[NS];  // lights with N.L > 0
-  uint32_t aomask[NS];
-  int32_t aocnt[NS];
-  uint32_t lmask[NS];
+  int32_t prim[NS];     // hit primitive (record offset)
+  // Secondary rays not yet finished (bits 0-30), and in bit 31 whether the
+  // rays leave the surface outward (then they skip prim; from inside they
+  // take only its far root): see slot_skip.  Decrements never reach bit 31.
+  int32_t pend[NS];
+  // Lights with N.L > 0 (bits 0-7), lights occluded (8-15) and AO rays
+  // occluded (16-31: at most 65535), updated by atomics on disjoint bits.
+  uint32_t acc[NS];
+  uint32_t aomask[NS];  // AO sample s occluded (bit s < 32; the optional output)
   // FIFO of slots with secondary rays to issue, one word each: slot (bits
   // 0-7), lights with N.L > 0 (8-11), continuation (12), AO rays (16-31);
   // the refill reads an entry with one load
@@ -133,6 +134,11 @@ struct Lds {
   uint8_t layer[NT];
   // BVH walk: per lane a stack of node / leaf items, entry e at e * 64 + lane
   int32_t stk[BVH ? 64 * kStack : 1];
+  // the skip rule of the slot's secondary rays (see Ray::skip)
+  __device__ __forceinline__ int32_t slot_skip(int32_t slot) const {
+    const int32_t k = prim[slot];
+    return pend[slot] < 0 ? k : -2 - k;
+  }
 };
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
@@ -283,8 +289,8 @@ __device__ __forceinline__ void shade_slot(const LdsT &L, const BankInfo &B, int
                                            int32_t k, const TR_GLOBAL vf4 *albedo, float &cr,
                                            float &cg, float &cb, float &alpha) {
   const float Nx = L.nx[slot], Ny = L.ny[slot], Nz = L.nz[slot];
-  const uint32_t lv = L.lvalid[slot];
-  const uint32_t lm = L.lmask[slot];
+  const uint32_t ac = L.acc[slot];
+  const uint32_t lv = ac & 0xFFu, lm = (ac >> 8) & 0xFFu;
   float Dr = 0.0f, Dg = 0.0f, Db = 0.0f;
   float Hr = 0.0f, Hg = 0.0f, Hb = 0.0f;  // Phong highlight (white, after the albedo)
   for (int l = 0; l < B.n_lights; ++l) {
@@ -312,7 +318,7 @@ __device__ __forceinline__ void shade_slot(const LdsT &L, const BankInfo &B, int
     }
   }
   float ao = 1.0f;
-  if (B.S > 0) ao = (float)(B.S - L.aocnt[slot]) * B.rS;
+  if (B.S > 0) ao = (float)(B.S - (int32_t)(ac >> 16)) * B.rS;
   const vf4 alb = ldgb(albedo, (uint32_t)k);  // (k: record offset)
   const float sk = B.sky * ao;
   cr = fminf(fmaxf(alb.x * (Dr + sk) + Hr, 0.0f), 1.0f);
@@ -340,7 +346,7 @@ __device__ __forceinline__ void shade_tile(LdsT &L, int32_t b, int32_t lane,
       const int64_t pid = (int64_t)y * B.W + x;
       if (B.hit_id) B.hit_id[pid] = k >> kRecShift;  // the global id (-1 stays -1)
       if (B.ao_mask) B.ao_mask[pid] = k >= 0 ? L.aomask[slot] : 0u;
-      if (B.light_mask) B.light_mask[pid] = k >= 0 ? (uint8_t)L.lmask[slot] : (uint8_t)0;
+      if (B.light_mask) B.light_mask[pid] = k >= 0 ? (uint8_t)(L.acc[slot] >> 8) : (uint8_t)0;
     }
     L.px[slot] = cr;
     L.py[slot] = cg;
@@ -687,12 +693,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         // angles), so the walk takes only the other root of its own sphere
         // or cylinder, and never its own (flat) triangle -- the result in
         // exact arithmetic.
-        L.skip[slot] = front ? k : -2 - k;
-        L.pending[slot] = (int32_t)nr;
-        L.lvalid[slot] = lv;
+        L.pend[slot] = (int32_t)(nr | (front ? 0x80000000u : 0u));
+        L.acc[slot] = lv;
         L.aomask[slot] = 0;
-        L.aocnt[slot] = 0;
-        L.lmask[slot] = 0;
         if (nr == 0) finalize = true;
       }
       {  // queue hit slots that have secondary rays: S AO rays, then one per lit light
@@ -705,13 +708,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         if (R.bk >= 0) {
           if (kind == kAO) {
             if (ridx < 32) atomicOr(&L.aomask[slot], 1u << ridx);
-            atomicAdd(&L.aocnt[slot], 1);
+            atomicAdd(&L.acc[slot], 1u << 16);
           } else {
-            atomicOr(&L.lmask[slot], 1u << ridx);
+            atomicOr(&L.acc[slot], 1u << (8 + ridx));
           }
         }
-        const int32_t old = atomicSub(&L.pending[slot], 1);
-        if (old == 1) finalize = true;
+        const int32_t old = atomicSub(&L.pend[slot], 1);
+        if ((old & 0x7FFFFFFF) == 1) finalize = true;
       }
       __syncthreads();
       bool cont_next = false;  // the pixel goes on through a transparent surface
@@ -734,7 +737,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         if (!fin_prim_miss) {
           const int32_t k = L.prim[slot];
           hid = k;
-          lm = L.lmask[slot];
+          lm = (L.acc[slot] >> 8) & 0xFFu;
           am = L.aomask[slot];
           float a = 1.0f;
           shade_slot(L, B, slot, k, S.albedo, cr, cg, cb, a);
@@ -764,9 +767,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             L.acc_b[slot] = ab;
             L.trn[slot] = Tn;
             L.layer[slot] = (uint8_t)(layer + 1);
-            // entering it: its own far side counts, its start does not
-            L.skip[slot] = L.skip[slot] >= 0 ? -2 - L.prim[slot] : L.prim[slot];
-            L.pending[slot] = 1;
+            // entering it: its own far side counts, its start does not (the
+            // skip rule flips: leaving outward becomes leaving from inside)
+            L.pend[slot] = L.pend[slot] < 0 ? 1 : (int32_t)(1u | 0x80000000u);
             cont_next = true;
           } else {
             cr = ar + Tn * B.bg[0];
@@ -998,7 +1001,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
               R.oy = L.py[slot];
               R.oz = L.pz[slot];
               R.tmin = kEps;
-              R.skip = L.skip[slot];
+              R.skip = L.slot_skip(slot);
             } else {
               R.ox = B.eye[0];
               R.oy = B.eye[1];
@@ -1011,13 +1014,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             R.ox = L.px[slot];
             R.oy = L.py[slot];
             R.oz = L.pz[slot];
-            R.skip = L.skip[slot];
+            R.skip = L.slot_skip(slot);
             R.tmin = kEps;
             if (kind == kAO) {
               ao_dir_f32(L.nx[slot], L.ny[slot], L.nz[slot], b1, b2, R.dx, R.dy, R.dz);
               R.tmax = B.maxd;
             } else {
-              uint32_t lv = L.lvalid[slot];  // the (ridx - S)-th light with N.L > 0
+              uint32_t lv = L.acc[slot] & 0xFFu;  // the (ridx - S)-th light with N.L > 0
               for (int32_t n = ridx - B.S; n > 0; --n) lv &= lv - 1;
               const int32_t l = __ffs(lv) - 1;
               ridx = l;
