@@ -197,7 +197,8 @@ struct Ray {
   int32_t nk;          // the entry at rc: the next primitive (record offset, 16 x id;
                        // bit 0 set on the cell's last), -1 once the cell is done
                        // (loaded ahead)
-  float bt;            // best t
+  float bt;            // best t; before a hit the float just above t1, so the
+                       // walk ends at min(t1, best t) with one compare
   int32_t bk;          // best primitive, record offset (-1 = none)
   int32_t skip;         // k >= 0: never report k; -2 - k: k is the ray's own surface,
                         // left from inside; -1: none (k: record offsets)
@@ -399,9 +400,9 @@ __device__ __forceinline__ bool ray_setup(Ray &R, const SceneHot &S) {
     }
   }
   R.t1 = t1;
-  R.bt = INFINITY;
   R.bk = -1;
   if (!(t0 <= t1)) return false;
+  R.bt = __int_as_float(__float_as_int(t1) + 1);  // (0 <= t1 < inf here)
   const float ex = fmaf(t0, R.dx, R.ox), ey = fmaf(t0, R.dy, R.oy), ez = fmaf(t0, R.dz, R.oz);
   R.cx = min(max(cvt_floor((ex - S.lo32[0]) * S.inv32[0]), 0), S.res[0] - 1);
   R.cy = min(max(cvt_floor((ey - S.lo32[1]) * S.inv32[1]), 0), S.res[1] - 1);
@@ -1175,7 +1176,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         float t;  // set by every test; read only on a tested lane
         asm volatile("" : "=v"(t));
         const bool own = nkr == -2 - R.skip;  // the surface this ray leaves from inside
-        const bool last = !BVH & (nk != nkr) & (nk >= 0);  // the cell's last entry
+        // the cell's last entry (read only on a tested lane, where nk >= 0)
+        const bool last = !BVH & (nk != nkr);
         if (is_sph) {
           tested = true;
           const vf4 s = sdat;
@@ -1362,7 +1364,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           // Go on unless the plane is the box exit or lies beyond the best hit
           // so far.  Branch-free: a lane that stops computes a cell it never
           // enters (its coordinates are reset when the lane takes a new ray).
-          const bool adv = tn < vminf(R.t1, R.bt);
+          const bool adv = tn < R.bt;  // (bt is at most just above t1)
           const bool ax = tx == tn;
           const bool ay = !ax & (ty == tn);
           const bool az = !ax & !ay;
