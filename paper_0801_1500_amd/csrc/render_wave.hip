@@ -1369,13 +1369,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           const bool ay = !ax & (ty == tn);
           const bool az = !ax & !ay;
           // the other axes land in the cell of the exit point, kept inside the cube
-          const int32_t nx = R.cx + med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], gorg0)) - R.cx, -m, m);
-          const int32_t ny = R.cy + med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], gorg1)) - R.cy, -m, m);
-          const int32_t nz = R.cz + med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], gorg2)) - R.cz, -m, m);
+          const int32_t nx = med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], gorg0)), R.cx - m, R.cx + m);
+          const int32_t ny = med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], gorg1)), R.cy - m, R.cy + m);
+          const int32_t nz = med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], gorg2)), R.cz - m, R.cz + m);
           R.cx = ax ? ix1 : nx;
           R.cy = ay ? iy1 : ny;
           R.cz = az ? iz1 : nz;
-          // (tn < t1 is finite, so the crossed axis has a nonzero step)
+          // (tn < bt is finite, so the crossed axis has a nonzero step)
           const bool inb = ((uint32_t)R.cx < (uint32_t)H.res[0]) & ((uint32_t)R.cy < (uint32_t)H.res[1]) &
                            ((uint32_t)R.cz < (uint32_t)H.res[2]);
           enter = adv & inb;
