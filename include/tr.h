@@ -230,9 +230,6 @@ typedef struct {
   int32_t waves_per_cu;      /* persistent waves launched per compute unit, 1..32 */
   int32_t refill_below;      /* refill when fewer than this many lanes are busy, 1..64 */
   int32_t count_ops;         /* 1 = also fill the traversal counters of tr_frame.stats */
-  int32_t cyl_wait;          /* cylinder tests run when at least busy/cyl_wait lanes need one, 1..64 */
-  int32_t mix;               /* a work type (step, sphere test, cylinder test) runs in an iteration
-                                when its lanes are >= mix/64 of the largest type's, 1..64 */
   int32_t accel;             /* 0 = walk the uniform grid; 1 = walk the scene's
                                 BVH (tr_scene_build_bvh first; FP32 precisions,
                                 opaque rendering, two banks).  Both walks meet

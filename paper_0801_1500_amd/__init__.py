@@ -70,8 +70,8 @@ class Frame(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("banks", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("refill_below", C.c_int32), ("count_ops", C.c_int32), ("cyl_wait", C.c_int32),
-                ("mix", C.c_int32), ("accel", C.c_int32), ("stripe", C.c_int32)]
+                ("refill_below", C.c_int32), ("count_ops", C.c_int32),
+                ("accel", C.c_int32), ("stripe", C.c_int32)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -192,8 +192,8 @@ def make_tune(tune) -> Optional[Tune]:
         return tune
     return Tune(int(tune.get("tile_w", 0)), int(tune.get("banks", 0)),
                 int(tune.get("waves_per_cu", 0)), int(tune.get("refill_below", 0)),
-                int(tune.get("count_ops", 0)), int(tune.get("cyl_wait", 0)),
-                int(tune.get("mix", 0)), int(tune.get("accel", 0)),
+                int(tune.get("count_ops", 0)),
+                int(tune.get("accel", 0)),
                 int(tune.get("stripe", 0)))
 
 

@@ -496,7 +496,7 @@ struct WaveArgs {
   int64_t n_tiles;
   uint32_t *tile_counter;
   uint64_t *stats;
-  int32_t tile_w, refill_below, cyl_wait, mix;
+  int32_t tile_w, refill_below;
   int32_t stripe_log2;  // tiles per stripe of the tile queue, log2
 };
 
@@ -1089,9 +1089,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           c_lanes += (uint64_t)nwork;
         }
         // The next reference id is already loaded (R.nk, -1 = cell done), so
-        // each lane knows its unit of work before touching memory.  Cylinder
-        // tests, the long path, run only when enough lanes want one; the
-        // other lanes keep stepping and testing spheres meanwhile.
+        // each lane knows its unit of work before touching memory.
         // Working lanes only from here (an if, not a continue: the lanes must
         // meet again at the loop head for its ballot).  Ballots inside count
         // the working lanes.
@@ -1100,24 +1098,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         // flags the last entry of its cell's list, or -1 (cell done).
         const int32_t nk = R.nk;
         const int32_t nkr = nk & ~15;  // the record offset (negative stays negative)
-        // Work-type scheduling: a unit type runs this iteration only if enough
-        // lanes want it -- at least `mix`/64 of the largest group (cylinders
-        // also need busy/cyl_wait lanes) -- so the wave does not pay for every
-        // code path each iteration; the other lanes wait.  The decisions are
-        // wave-uniform; each lane's type is one compare.
-        const bool want_sph = (uint32_t)nk < (uint32_t)H.s_end;  // nk = -1: no
-        const bool want_cyl = nk >= H.s_end;
-        const int32_t n_sph = __popcll(ballot(want_sph));
-        const int32_t n_cyl = __popcll(ballot(want_cyl));
-        const int32_t n_step = nwork - n_sph - n_cyl;
-        const int32_t n_max = max(n_step, max(n_sph, n_cyl));
-        const int32_t bar = (n_max * A.mix + 63) >> 6;
-        const bool go_sph = n_sph >= bar;
-        const bool go_step = n_step >= bar;
-        const bool go_cyl = n_cyl > 0 && ((n_cyl >= bar && n_cyl * A.cyl_wait >= nwork) || (!go_sph && !go_step));
-        const bool is_sph = go_sph && want_sph;
-        const bool is_cyl = go_cyl && want_cyl;
-        const bool is_step = go_step && !want_sph && !want_cyl;  // nk < 0
+        // Each lane's unit of work, one compare each: a sphere test, a
+        // cylinder (or triangle) test, or a step out of an empty or finished
+        // cell.  Every unit some lane wants runs in this iteration; holding a
+        // unit back until more lanes want it (thresholds on the lane counts)
+        // cost more in scalar decisions per iteration than it saved.
+        const bool is_sph = (uint32_t)nk < (uint32_t)H.s_end;  // nk = -1: no
+        const bool is_cyl = nk >= H.s_end;
+        const bool is_step = !is_sph && !is_cyl;  // nk < 0
         // Sphere records are fetched first; the tests run, then the step, which
         // takes both the lanes with no entry left (empty cells) and the lanes
         // that just tested their cell's last entry and go on: a cell costs one
@@ -1511,9 +1499,7 @@ static hipError_t launch_t(const WaveLaunch &L, hipStream_t st) {
   a.stats = L.stats;
   a.tile_w = L.tile_w;
   a.refill_below = L.refill_below;
-  a.cyl_wait = L.cyl_wait;
   a.stripe_log2 = __builtin_ctz((unsigned)L.stripe);
-  a.mix = L.mix;
   k_render_wave<BANKS, RES, CNT, TRANS, TRI, BVH><<<L.n_waves, 64, 0, st>>>(a);
   return hipGetLastError();
 }

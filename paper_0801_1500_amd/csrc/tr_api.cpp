@@ -881,8 +881,6 @@ static tr_status default_tune(tr_tune *t) {
   t->waves_per_cu = 20;
   t->refill_below = 32;
   t->count_ops = 0;
-  t->cyl_wait = 64;
-  t->mix = 8;
   t->accel = 0;
   t->stripe = 64;
   return TR_OK;
@@ -893,8 +891,6 @@ static tr_status check_tune(const tr_tune &t) {
   if (t.banks != 2 && t.banks != 3) return fail(TR_EINVAL, "tune.banks must be 2 or 3");
   if (t.waves_per_cu < 1 || t.waves_per_cu > 32) return fail(TR_EINVAL, "tune.waves_per_cu must be 1..32");
   if (t.refill_below < 1 || t.refill_below > 64) return fail(TR_EINVAL, "tune.refill_below must be 1..64");
-  if (t.cyl_wait < 1 || t.cyl_wait > 64) return fail(TR_EINVAL, "tune.cyl_wait must be 1..64");
-  if (t.mix < 1 || t.mix > 64) return fail(TR_EINVAL, "tune.mix must be 1..64");
   if (t.accel != 0 && t.accel != 1) return fail(TR_EINVAL, "tune.accel must be 0 or 1");
   if (t.stripe < 1 || t.stripe > 1024 || (t.stripe & (t.stripe - 1)))
     return fail(TR_EINVAL, "tune.stripe must be a power of two 1..1024");
@@ -1104,8 +1100,6 @@ static tr_tune pick_tune(const tr_scene *s, const tr_camera *c, const tr_params 
     if (!t.banks) t.banks = d.banks;
     if (!t.waves_per_cu) t.waves_per_cu = d.waves_per_cu;
     if (!t.refill_below) t.refill_below = d.refill_below;
-    if (!t.cyl_wait) t.cyl_wait = d.cyl_wait;
-    if (!t.mix) t.mix = d.mix;
     if (!t.stripe) t.stripe = d.stripe;
     return t;
   }
@@ -1230,8 +1224,6 @@ static trh::WaveLaunch wave_launch(const JobDev *jobs, int32_t n, int64_t total,
   L.banks = t.banks;
   L.refill_below = t.refill_below;
   L.count_ops = t.count_ops;
-  L.cyl_wait = t.cyl_wait;
-  L.mix = t.mix;
   L.stripe = t.stripe;
   int64_t waves = (int64_t)num_cus() * t.waves_per_cu;
   if (waves > total) waves = total;
@@ -1628,8 +1620,6 @@ static tr_status graph_capture(tr_graph *g) {
     L.banks = g->tune.banks;
     L.refill_below = g->tune.refill_below;
     L.count_ops = g->tune.count_ops;
-    L.cyl_wait = g->tune.cyl_wait;
-    L.mix = g->tune.mix;
     L.stripe = g->tune.stripe;
     int64_t waves = (int64_t)num_cus() * g->tune.waves_per_cu;
     if (waves > g->total_tiles) waves = g->total_tiles;
@@ -2065,7 +2055,7 @@ extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr
   }
   // coordinate descent over the launch-shape axes
   const std::vector<std::vector<int32_t>> axes = {
-      {4, 8, 16, 32, 64}, {2, 3}, {8, 12, 16, 20, 24, 32}, {16, 24, 32, 40, 48, 56}, {2, 8, 64}, {1, 8, 16, 32, 64},
+      {4, 8, 16, 32, 64}, {2, 3}, {8, 12, 16, 20, 24, 32}, {16, 24, 32, 40, 48, 56},
       {16, 32, 64, 128, 256}};
   for (int pass = 0; pass < 2; ++pass) {
     for (size_t ax = 0; ax < axes.size(); ++ax) {
@@ -2075,8 +2065,6 @@ extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr
                          : ax == 1 ? &t.banks
                          : ax == 2 ? &t.waves_per_cu
                          : ax == 3 ? &t.refill_below
-                         : ax == 4 ? &t.cyl_wait
-                         : ax == 5 ? &t.mix
                                    : &t.stripe;
         if (*field == v) continue;
         *field = v;
@@ -2094,8 +2082,8 @@ extern "C" tr_status tr_autotune(const tr_scene *s, const tr_camera *c, const tr
         if (std::memcmp(h_a.data(), h_b.data(), px * 12) != 0 ||
             std::memcmp(i_a.data(), i_b.data(), px * 4) != 0) {
           cleanup();
-          return fail(TR_EDEVICE, "autotune: launch shape (%d,%d,%d,%d,%d,%d,%d) changed the frame",
-                      t.tile_w, t.banks, t.waves_per_cu, t.refill_below, t.cyl_wait, t.mix, t.stripe);
+          return fail(TR_EDEVICE, "autotune: launch shape (%d,%d,%d,%d,%d) changed the frame",
+                      t.tile_w, t.banks, t.waves_per_cu, t.refill_below, t.stripe);
         }
         if (ms < cur_ms) {
           cur_ms = ms;

@@ -115,7 +115,7 @@ struct WaveLaunch {
   int64_t n_tiles;           // total tiles in the queue
   uint32_t *tile_counter;    // device, trd::kQueueWords words zeroed before the launch
   uint64_t *stats;           // device or null
-  int32_t tile_w, banks, refill_below, count_ops, cyl_wait, mix;
+  int32_t tile_w, banks, refill_below, count_ops;
   int32_t stripe;            // tiles per tile-queue stripe (a power of two)
   int32_t n_waves;           // persistent waves launched
   int32_t resolve;

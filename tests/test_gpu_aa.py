@@ -161,7 +161,7 @@ def test_batch_and_tunes_are_bitwise(tr, protein):
             assert np.array_equal(a[k], f[k]), k
     # a different launch shape gives the same bits
     t = _gpu(tr, gs, c, ps[0], "fp32_resolve",
-             tune=dict(tile_w=16, banks=3, waves_per_cu=12, refill_below=40, mix=16))
+             tune=dict(tile_w=16, banks=3, waves_per_cu=12, refill_below=40, stripe=8))
     for k in OUT:
         assert np.array_equal(alone[0][k], t[k]), k
     # FP64 jobs of a batch take the plain path, antialiased as alone
