@@ -188,6 +188,14 @@ __global__ void k_pack32(const trh::BuildArgs a, const double4 *cylW64, double o
     cylA32[m] = make_float4((float)(a.x - ox), (float)(a.y - oy), (float)(a.z - oz), (float)(a.w * a.w));
     cylW32[m] = make_float4((float)w.x, (float)w.y, (float)w.z, (float)w.w);
     const double4 b = cylB64[m];
+    // The bounding sphere of the (open) cylinder, after the spheres: centre
+    // the axis midpoint, squared radius (L/2)^2 + rho^2, padded by 2^-9 and
+    // rounded up, so the cylinder stays inside the FP32 sphere by a margin
+    // far above the FP32 rounding of the test against it.
+    const double hl = 0.5 * w.w;
+    const float bb = (float)((hl * hl + a.w * a.w) * (1.0 + 0x1p-9));
+    sph32[k] = make_float4((float)(0.5 * (a.x + b.x) - ox), (float)(0.5 * (a.y + b.y) - oy),
+                           (float)(0.5 * (a.z + b.z) - oz), nextafterf(bb, INFINITY));
     ext = fmax(dist3(a.x - ox, a.y - oy, a.z - oz), dist3(b.x - ox, b.y - oy, b.z - oz)) + a.w;
   }
   // every lane gets here (no early return): the wave's maximum, one atomic

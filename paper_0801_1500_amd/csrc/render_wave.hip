@@ -1098,20 +1098,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         // flags the last entry of its cell's list, or -1 (cell done).
         const int32_t nk = R.nk;
         const int32_t nkr = nk & ~15;  // the record offset (negative stays negative)
-        // Each lane's unit of work, one compare each: a sphere test, a
-        // cylinder (or triangle) test, or a step out of an empty or finished
-        // cell.  Every unit some lane wants runs in this iteration; holding a
-        // unit back until more lanes want it (thresholds on the lane counts)
-        // cost more in scalar decisions per iteration than it saved.
-        const bool is_sph = (uint32_t)nk < (uint32_t)H.s_end;  // nk = -1: no
-        const bool is_cyl = nk >= H.s_end;
-        const bool is_step = !is_sph && !is_cyl;  // nk < 0
+        // Each lane's unit of work, one compare each: a sphere test (for a
+        // cylinder, first the test of its bounding sphere, in the same code),
+        // a triangle test, or a step out of an empty or finished cell.  Every
+        // unit some lane wants runs in this iteration; holding a unit back
+        // until more lanes want it (thresholds on the lane counts) cost more
+        // in scalar decisions per iteration than it saved.
+        const bool is_sph = (uint32_t)nk < (uint32_t)H.c_end;  // nk = -1: no
+        const bool is_tri = TRI && nk >= H.c_end;
+        const bool is_step = !is_sph && !is_tri;  // nk < 0
         // Sphere records are fetched first; the tests run, then the step, which
         // takes both the lanes with no entry left (empty cells) and the lanes
         // that just tested their cell's last entry and go on: a cell costs one
         // iteration per entry, none extra to leave it.  The step's cell load
         // is issued last and consumed next iteration.
-        vf4 sdat;  // (read only where is_sph)
+        vf4 sdat;  // (read only where is_sph; a cylinder's bounding sphere follows the spheres)
         if (is_sph) sdat = ldgb(H.sph32, (uint32_t)nkr);
         bool enter = false;  // the step moved into a cell inside the grid
         if (BVH && is_step) {
@@ -1164,6 +1165,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         float t;  // set by every test; read only on a tested lane
         asm volatile("" : "=v"(t));
         const bool own = nkr == -2 - R.skip;  // the surface this ray leaves from inside
+        const bool ball = nkr >= H.s_end;     // (where is_sph) the sphere bounds a cylinder
+        bool pass = false;                    // the ray may meet that cylinder
         // the cell's last entry (read only on a tested lane, where nk >= 0)
         const bool last = !BVH & (nk != nkr);
         if (is_sph) {
@@ -1185,9 +1188,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           // nearer root if it is past tmin, else the farther (t0 <= t1);
           // only the farther on the ray's own sphere
           t = ((t0 > R.tmin) & !own) ? t0 : t1;
-          hit = ok & (t > R.tmin) & (t <= R.t1);
+          hit = ok & (t > R.tmin) & (t <= R.t1) & !ball;
+          // A bounding sphere passes unless the ray misses it decidably (a
+          // cylinder hit lies inside it, and its padding is far above the
+          // FP32 rounding); only then is the cylinder itself tested.
+          pass = ok | graze;
+          graze = graze & !ball;
         }
-        if (TRI && is_cyl && nkr >= H.c_end) {
+        // skipped: the surface an outward ray leaves, and the own triangle
+        const bool live = (nkr != R.skip) & !(TRI & own & (nkr >= H.c_end));
+        if (is_tri) {
           // ---- triangle (two-sided, Moller-Trumbore).  Undecidable in FP32,
           // and so re-solved in FP64: a ray within 2^-12 of the triangle's
           // plane (|det| against |e1 x e2|), or a hit point within 2^-12 of an
@@ -1212,8 +1222,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
                             (fabsf(u) <= kKappa || fabsf(v) <= kKappa || fabsf(w) <= kKappa);
           graze = RESOLVE && (par || (edge && in_t));
           hit = !graze && det != 0.0f && u >= 0.0f && v >= 0.0f && w >= 0.0f && in_t;
-        } else if (is_cyl) {
-          tested = true;
+        } else if (is_sph & ball & pass & live) {
           const vf4 a = ldgb(H.cylA32, (uint32_t)(nkr - H.s_end));
           const vf4 w = ldgb(H.cylW32, (uint32_t)(nkr - H.s_end));
           const float Dx = R.ox - a.x, Dy = R.oy - a.y, Dz = R.oz - a.z;
@@ -1257,8 +1266,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           t = hl ? tl : th;
         }
         if (tested) {
-          // skipped: the surface an outward ray leaves, and the own triangle
-          const bool live = (nkr != R.skip) & !(TRI & own & (nkr >= H.c_end));
           hit = hit & live;
           graze = graze & live;
           if (COUNT) {

@@ -389,7 +389,7 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
 #define ALLOC(p, n)                                                      \
   if (e == hipSuccess) e = dmalloc(&(p), (n));
   ALLOC(s->sph64, s->n_s);
-  ALLOC(s->sph32, s->n_s);
+  ALLOC(s->sph32, s->n_s + s->n_c);  // spheres, then the cylinders' bounding spheres
   ALLOC(s->cylA64, s->n_c);
   ALLOC(s->cylW64, s->n_c);
   ALLOC(s->cylB64, s->n_c);
@@ -411,7 +411,7 @@ extern "C" tr_status tr_scene_build(const tr_scene_desc *d, void *hip_stream, tr
   if (e != hipSuccess)
     return bail(fail(e == hipErrorOutOfMemory ? TR_ENOMEM : TR_EDEVICE, "scene allocation: %s",
                      hipGetErrorString(e)));
-  s->bytes_arrays = (size_t)s->n_s * (32 + 16) + (size_t)s->n_c * (3 * 32 + 2 * 16) +
+  s->bytes_arrays = (size_t)s->n_s * (32 + 16) + (size_t)s->n_c * (3 * 32 + 3 * 16) +
                     (size_t)s->n_t * (3 * 32 + 3 * 16) + (size_t)N * 16;
   // upload the caller's arrays (temporary device copies), then pack
   double *t_sc = nullptr, *t_sr = nullptr, *t_ca = nullptr, *t_cb = nullptr, *t_cr = nullptr;

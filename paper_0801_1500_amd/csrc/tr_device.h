@@ -5,8 +5,10 @@
 //   cylA64 double4[n_c]  (ax, ay, az, rho)
 //   cylW64 double4[n_c]  (wx, wy, wz, L)           unit axis and length, w = (b - a) / L
 //   cylB64 double4[n_c]  (bx, by, bz, 0)           second end point (grid rebuild)
-//   sph32  float4[n_s]   (cx, cy, cz, r^2) rounded copies for the FP32 traversal: one
-//                        16-byte load per sphere
+//   sph32  float4[n_s + n_c]  (cx, cy, cz, r^2) rounded copies for the FP32 traversal: one
+//                        16-byte load per sphere; then per cylinder its bounding
+//                        sphere (axis midpoint, padded squared radius), which the
+//                        walk tests first, like a sphere, at the same record offset
 //   cylA32 float4[n_c], cylW32 float4[n_c]  (ax, ay, az, rho^2), (wx, wy, wz, L): two
 //                        16-byte loads per cylinder
 //   triA64/triB64/triC64 double4[n_t]  triangle vertices (FP64)

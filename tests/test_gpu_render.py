@@ -289,14 +289,19 @@ def _limb_scene():
                           ld, np.ones((2, 3)))
 
 
-@pytest.mark.parametrize("view", ["cylinder_end", "sphere_limb"])
+@pytest.mark.parametrize("view", ["cylinder_end", "sphere_limb", "cylinder_rim"])
 def test_bounding_sphere_limb(tr, oracle_mod, view):
     """Rays that graze the outermost surfaces of the scene, where the walk's
     clip to the bounding sphere is tightest, find the oracle's hits: both
-    FP32 precisions against brute force at the usual bar."""
+    FP32 precisions against brute force at the usual bar.  The rim view
+    also aims at a cylinder's rim, where the cylinder touches its own
+    bounding sphere (the walk's first test of a cylinder): the pixels are
+    0.0013 apart, finer than that sphere's padding (0.003 in radius)."""
     s = _limb_scene()
     if view == "cylinder_end":  # the far end's rim, seen from the side
         c = scenegen.Camera((0.0, 8.0, 14.0), (0.0, 8.0, 0.0), (0.0, 1.0, 0.0), 12.0, 96, 96)
+    elif view == "cylinder_rim":  # one point of that rim, rays tangent to the bounding sphere
+        c = scenegen.Camera((0.5, 8.0, 14.0), (0.5, 8.0, 0.0), (0.0, 1.0, 0.0), 0.5, 96, 96)
     else:  # the far sphere's outer limb, seen from the side
         c = scenegen.Camera((0.5, -8.5, 15.0), (0.5, -8.5, 0.0), (0.0, 1.0, 0.0), 12.0, 96, 96)
     p = scenegen.Params(ao_samples=8, seed=3)
