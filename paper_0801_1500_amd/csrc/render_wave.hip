@@ -830,8 +830,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       // primary rays; each idle lane learns (kind, slot, ray index)
       int32_t n_ao = 0;    // AO rays among the secondary rays issued this round
       int32_t n_cont = 0;  // continuations through transparent surfaces
-      while (assigned < n_idle && q_head != q_tail) {
-        const uint32_t e = (uint32_t)uni((int32_t)L.fifo[q_head % NS]);
+      // The FIFO's first entries, one per lane, in one LDS read: the pops
+      // below take them with readlane instead of an LDS round trip each.  A
+      // round takes at most 64 entries (each has a ray, and at most 64 lanes
+      // are idle).
+      const int32_t q_n = min(q_tail - q_head, 64);
+      uint32_t q_e = 0;
+      if (lane < q_n) q_e = L.fifo[(q_head + lane) % NS];
+      int32_t q_i = 0;
+      while (assigned < n_idle && q_i < q_n) {
+        const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int32_t)q_e, q_i);
         const int32_t s = (int32_t)(e & 0xFFu);
         const bool cs = TRANS && ((e >> 12) & 1u) != 0;
         const int32_t S_s = (int32_t)(e >> 16);
@@ -847,10 +855,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         head_issued += take;
         assigned += take;
         if (head_issued == nr) {
-          ++q_head;
+          ++q_i;
           head_issued = 0;
         }
       }
+      q_head += q_i;
       if (A.stats && lane == 0 && assigned > 0) {  // ray counters live in LDS
         L.cnt[2] += (uint32_t)n_ao;
         L.cnt[3] += (uint32_t)(assigned - n_ao - n_cont);
