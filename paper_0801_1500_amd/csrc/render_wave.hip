@@ -1089,10 +1089,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
       float gorg0 = H.org32[0], gorg1 = H.org32[1], gorg2 = H.org32[2];
       asm volatile("" : "+v"(gorg0), "+v"(gorg1), "+v"(gorg2));
       const uint64_t cyc0 = COUNT ? clock64() : 0;
-      for (int32_t it = 0;; ++it) {
-        const bool work = st == kRun;
-        const int32_t nwork = __popcll(ballot(work));
-        if (nwork < (it >= kMinIters ? thresh : 1)) break;
+      // (the exit test sits at the loop's end, where it is a scalar branch)
+      bool work = st == kRun;
+      int32_t nwork = __popcll(ballot(work));
+      for (int32_t it = 0; nwork >= (it >= kMinIters ? thresh : 1); ++it) {
         if (COUNT) {
           ++c_iters;
           c_lanes += (uint64_t)nwork;
@@ -1393,6 +1393,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
         }
         if (!BVH && enter) load_cell(R, H);
         }  // work
+        work = st == kRun;
+        nwork = __popcll(ballot(work));
       }
       (void)anyhit;
       if (COUNT) c_cyc_trav += clock64() - cyc0;
