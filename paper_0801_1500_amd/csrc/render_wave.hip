@@ -1354,7 +1354,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           // Branch-free: the k = 1 step is the jump with a cube of size 0.
           // nk = -k: rc = -distance in an empty cell, >= 0 otherwise
           const int32_t nk1 = min(R.rc, -1);
-          const int32_t m = -1 - nk1;  // k - 1
           // cell just beyond the cube on each axis; its near plane is crossed at
           // b_a + i * h_a (b_a is shifted one cell for negative steps at setup);
           // (-sign) (-k) is the offset
@@ -1372,10 +1371,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           const bool ax = tx == tn;
           const bool ay = !ax & (ty == tn);
           const bool az = !ax & !ay;
-          // the other axes land in the cell of the exit point, kept inside the cube
-          const int32_t nx = med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], gorg0)), R.cx - m, R.cx + m);
-          const int32_t ny = med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], gorg1)), R.cy - m, R.cy + m);
-          const int32_t nz = med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], gorg2)), R.cz - m, R.cz + m);
+          // The other axes land in the cell of the exit point, kept within the
+          // cube's half ahead of the ray: from the current cell to the last
+          // one before i1 (i1 + sign is that cell; the ray moves forward and
+          // crosses no other face first, so only rounding could leave it).
+          const int32_t nx = med3i(cvt_floor(fmaf(fmaf(tn, R.dx, R.ox), H.inv32[0], gorg0)), R.cx, ix1 + R.sx);
+          const int32_t ny = med3i(cvt_floor(fmaf(fmaf(tn, R.dy, R.oy), H.inv32[1], gorg1)), R.cy, iy1 + R.sy);
+          const int32_t nz = med3i(cvt_floor(fmaf(fmaf(tn, R.dz, R.oz), H.inv32[2], gorg2)), R.cz, iz1 + R.sz);
           R.cx = ax ? ix1 : nx;
           R.cy = ay ? iy1 : ny;
           R.cz = az ? iz1 : nz;
