@@ -193,9 +193,12 @@ struct Ray {
   float hx, hy, hz;
   int32_t cx, cy, cz;
   int32_t sx, sy, sz;  // minus the step signs (-1, 0, 1 for d > 0, = 0, < 0)
+  int32_t o3;          // 3 x the octant of d (bit a set for d_a < 0): the position of
+                       // its jump extension in an empty cell's record
   int32_t rc;          // byte offset of the cursor in the cell's walk list; -(distance) in an empty cell
   int32_t nk;          // the entry at rc: the next primitive (record offset, 16 x id;
-                       // bit 0 set on the cell's last), -1 once the cell is done
+                       // bit 0 set on the cell's last), or negative: an empty cell's
+                       // second record word, or bit 31 alone once the cell is done
                        // (loaded ahead)
   float bt;            // best t; before a hit the float just above t1, so the
                        // walk ends at min(t1, best t) with one compare
@@ -413,6 +416,7 @@ __device__ __forceinline__ bool ray_setup(Ray &R, const SceneHot &S) {
   R.sx = -sx;
   R.sy = -sy;
   R.sz = -sz;
+  R.o3 = 3 * ((sx < 0 ? 1 : 0) | (sy < 0 ? 2 : 0) | (sz < 0 ? 4 : 0));
   // Plane of the grid crossed when the walk enters cell i of axis a: at
   // b_a + i * h_a, with b_a taken one cell up for negative steps (the plane
   // between cells i and i + 1).  An axis with d_a = 0 gets b_a = inf, h_a = 0:
@@ -1336,9 +1340,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             // next entry (after the last use of this one, so the load can land
             // in its register and stay in flight into the next iteration);
             // after the cell's last entry none: the lane steps now, or (paused
-            // or done) finds -1
+            // or done) finds the cell done
             if (last) {
-              R.nk = -1;
+              R.nk = (int32_t)0x80000000u;  // (no jump extension)
             } else {
               R.rc += 4;  // (a byte offset into wrefs)
               R.nk = (int32_t)ldgb(H.refs, (uint32_t)R.rc);
@@ -1352,8 +1356,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           // cube of half-size k-1 around it is empty and the walk jumps to
           // where the ray leaves that cube (k = 1: an ordinary DDA step).
           // Branch-free: the k = 1 step is the jump with a cube of size 0.
-          // nk = -k: rc = -distance in an empty cell, >= 0 otherwise
-          const int32_t nk1 = min(R.rc, -1);
+          // nk1 = -k: rc = -distance in an empty cell, >= 0 otherwise; an
+          // empty cell's record also holds, for the ray's octant, how much
+          // farther the block ahead of it is empty (0 once a cell is done)
+          const int32_t nk1 =
+              min(R.rc, -1) - (int32_t)__builtin_amdgcn_ubfe((uint32_t)R.nk, (uint32_t)R.o3, 3u);
           // cell just beyond the cube on each axis; its near plane is crossed at
           // b_a + i * h_a (b_a is shifted one cell for negative steps at setup);
           // (-sign) (-k) is the offset

@@ -18,8 +18,9 @@
 //   albedo float4[N]     (r, g, b, opacity) by global id
 //   cell_begin uint32[n_cells + 1], refs uint32[n_refs + 64]   the uniform grid
 //   cellinfo CellInfo[n_cells] (list byte offset, first entry) of an occupied cell,
-//                            or (-distance to the nearest occupied cell, -1) of an
-//                            empty one: the FP32 walk's view, one load
+//                            or (-distance to the nearest occupied cell, bit 31 and
+//                            eight 3-bit jump extensions by octant) of an empty one:
+//                            the FP32 walk's view, one load
 //   wrefs uint32[n_refs + occupied cells]  per occupied cell its references (16 x id,
 //                        bit 0 set on the last) then -1
 #pragma once
@@ -33,7 +34,9 @@ namespace trd {
 // cell's sorted references followed by -1, so the walk needs no end index.
 struct CellInfo {
   int32_t a;  // occupied: byte offset of the cell's list in wrefs; empty: -(Chebyshev distance)
-  int32_t c;  // occupied: the list's first entry (16 x id, bit 0: the only one); empty: -1
+  int32_t c;  // occupied: the list's first entry (16 x id, bit 0: the only one); empty: bit 31
+              // set, and in bits 3o..3o+2 how many cells farther than the distance a ray
+              // in octant o (bit a of o: direction negative on axis a) may jump
 };
 static_assert(sizeof(CellInfo) == 8, "CellInfo is two words");
 
