@@ -327,13 +327,13 @@ tr_status tr_scene_load(const char *path, void *hip_stream, tr_scene **out);
  * cellinfo [2 * n_cells], per cell (byte offset of its list in wrefs, the
  * list's first entry), or for an empty cell (-d, x): d the Chebyshev
  * distance in cells to the nearest occupied cell, capped at the scene's
- * max_skip (32 by default), and x with bit 31 set and, in bits 3o..3o+2, the
- * jump extension e_o for octant o of a ray's direction (bit a of o set when
- * the direction is negative on axis a): with M the largest m such that for
- * every m' in 1..m the cell m' steps along the octant's diagonal lies in the
- * grid with distance >= m' + 1, e_o = min(7, max_skip - d, max(0, 2M + 1 - d))
- * (the block of 2M + 1 cells per axis ahead of the cell in that octant is
- * empty); and wrefs
+ * max_skip (32 by default), and x with bit 31 set and, in bits 3o..3o+2, M_o
+ * for octant o of a ray's direction (bit a of o set when the direction is
+ * negative on axis a): the largest m <= min(7, (max_skip - 1) / 2) such that
+ * for every m' in 1..m the cell m' steps along the octant's diagonal lies in
+ * the grid with distance >= m' + 1, i.e. the block of 2m + 1 cells per axis
+ * ahead of the cell in that octant is empty (a ray in that octant jumps
+ * max(d, 2 M_o + 1) cells); and wrefs
  * [*n_walk], per occupied cell in cell order its references in ascending id,
  * each stored as 16 x id (the byte offset of the primitive's 16-byte FP32
  * records) with bit 0 set on the list's last entry, then 0xFFFFFFFF.  *n_walk (required) receives the wrefs length.  Derived

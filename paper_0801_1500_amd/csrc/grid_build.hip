@@ -433,36 +433,33 @@ __global__ void k_cellinfo(const uint32_t *cell_begin, const uint32_t *refs, con
     r.c = (int32_t)((refs[b] << 4) | (e - b == 1 ? 1u : 0u));
   } else {
     // An empty cell: its Chebyshev distance dc (the cube of half-size dc - 1
-    // about it is empty), and per octant of a ray's direction how much
-    // farther a jump may go.  From the cell, the block of side 2m + 1 that
-    // extends ahead in octant o (axis a towards -a where bit a of o is set)
-    // is the cube of half-size m about the cell m steps along that octant's
-    // diagonal, so it is empty when that cell's distance is at least m + 1.
-    // Such blocks grow with m while the condition holds; the largest, M,
-    // lets a ray in that octant jump max(dc, 2M + 1) cells ahead, and the
-    // record keeps the excess over dc, at most 7 and within the cap, in
-    // three bits per octant.  (The walk is clamped to the part of the cube
-    // ahead of it, so a block that is empty ahead of the cell is enough.)
-    // The scan stays inside the grid.
+    // about it is empty), and per octant of a ray's direction the block
+    // ahead of it that is empty.  From the cell, the block of side 2m + 1
+    // that extends ahead in octant o (axis a towards -a where bit a of o is
+    // set) is the cube of half-size m about the cell m steps along that
+    // octant's diagonal, so it is empty when that cell's distance is at
+    // least m + 1.  Such blocks grow with m while the condition holds; the
+    // record keeps the largest m, M <= 7 (and 2M + 1 within the cap), in
+    // three bits per octant, and a ray in that octant jumps max(dc, 2M + 1)
+    // cells ahead.  (The walk is clamped to the part of the cube ahead of
+    // it, so a block that is empty ahead of the cell is enough.)  The scan
+    // stays inside the grid.
     const int32_t dc = max((int32_t)d[c], 1);
     const int32_t ix = (int32_t)(c % rx), iy = (int32_t)((c / rx) % ry),
                   iz = (int32_t)(c / ((int64_t)rx * ry));
     const int32_t rz = (int32_t)(n_cells / ((int64_t)rx * ry));
-    const int32_t lim = min(7, cap - dc);
+    const int32_t mcap = min(7, (cap - 1) / 2);
     uint32_t ext = 0;
-    if (lim > 0) {
-      const int32_t mmax = (dc + lim) / 2;  // from there on 2m + 1 - dc >= lim
-      for (int32_t o = 0; o < 8; ++o) {
-        const int32_t sx = (o & 1) ? -1 : 1, sy = (o & 2) ? -1 : 1, sz = (o & 4) ? -1 : 1;
-        int32_t m = 0;
-        while (m < mmax) {
-          const int32_t jx = ix + (m + 1) * sx, jy = iy + (m + 1) * sy, jz = iz + (m + 1) * sz;
-          if (jx < 0 || jx >= rx || jy < 0 || jy >= ry || jz < 0 || jz >= rz) break;
-          if ((int32_t)d[((int64_t)jz * ry + jy) * rx + jx] < m + 2) break;
-          ++m;
-        }
-        ext |= (uint32_t)min(lim, max(0, 2 * m + 1 - dc)) << (3 * o);
+    for (int32_t o = 0; o < 8; ++o) {
+      const int32_t sx = (o & 1) ? -1 : 1, sy = (o & 2) ? -1 : 1, sz = (o & 4) ? -1 : 1;
+      int32_t m = 0;
+      while (m < mcap) {
+        const int32_t jx = ix + (m + 1) * sx, jy = iy + (m + 1) * sy, jz = iz + (m + 1) * sz;
+        if (jx < 0 || jx >= rx || jy < 0 || jy >= ry || jz < 0 || jz >= rz) break;
+        if ((int32_t)d[((int64_t)jz * ry + jy) * rx + jx] < m + 2) break;
+        ++m;
       }
+      ext |= (uint32_t)m << (3 * o);
     }
     r.a = -dc;
     r.c = (int32_t)(0x80000000u | ext);

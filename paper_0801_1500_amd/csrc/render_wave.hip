@@ -194,7 +194,7 @@ struct Ray {
   int32_t cx, cy, cz;
   int32_t sx, sy, sz;  // minus the step signs (-1, 0, 1 for d > 0, = 0, < 0)
   int32_t o3;          // 3 x the octant of d (bit a set for d_a < 0): the position of
-                       // its jump extension in an empty cell's record
+                       // its empty block ahead in an empty cell's record
   int32_t rc;          // byte offset of the cursor in the cell's walk list; -(distance) in an empty cell
   int32_t nk;          // the entry at rc: the next primitive (record offset, 16 x id;
                        // bit 0 set on the cell's last), or negative: an empty cell's
@@ -1342,7 +1342,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
             // after the cell's last entry none: the lane steps now, or (paused
             // or done) finds the cell done
             if (last) {
-              R.nk = (int32_t)0x80000000u;  // (no jump extension)
+              R.nk = (int32_t)0x80000000u;  // (no block ahead: a unit step)
             } else {
               R.rc += 4;  // (a byte offset into wrefs)
               R.nk = (int32_t)ldgb(H.refs, (uint32_t)R.rc);
@@ -1357,10 +1357,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BVH ? 2 : (T
           // where the ray leaves that cube (k = 1: an ordinary DDA step).
           // Branch-free: the k = 1 step is the jump with a cube of size 0.
           // nk1 = -k: rc = -distance in an empty cell, >= 0 otherwise; an
-          // empty cell's record also holds, for the ray's octant, how much
-          // farther the block ahead of it is empty (0 once a cell is done)
-          const int32_t nk1 =
-              min(R.rc, -1) - (int32_t)__builtin_amdgcn_ubfe((uint32_t)R.nk, (uint32_t)R.o3, 3u);
+          // empty cell's record also holds, for the ray's octant, the M of the
+          // empty block of 2M + 1 cells per axis ahead of it (0 once a cell is
+          // done), and the jump takes the larger
+          const int32_t mo = (int32_t)__builtin_amdgcn_ubfe((uint32_t)R.nk, (uint32_t)R.o3, 3u);
+          const int32_t nk1 = min(min(R.rc, -1), -1 - 2 * mo);
           // cell just beyond the cube on each axis; its near plane is crossed at
           // b_a + i * h_a (b_a is shifted one cell for negative steps at setup);
           // (-sign) (-k) is the offset

@@ -19,7 +19,7 @@
 //   cell_begin uint32[n_cells + 1], refs uint32[n_refs + 64]   the uniform grid
 //   cellinfo CellInfo[n_cells] (list byte offset, first entry) of an occupied cell,
 //                            or (-distance to the nearest occupied cell, bit 31 and
-//                            eight 3-bit jump extensions by octant) of an empty one:
+//                            eight 3-bit empty blocks ahead, by octant) of an empty one:
 //                            the FP32 walk's view, one load
 //   wrefs uint32[n_refs + occupied cells]  per occupied cell its references (16 x id,
 //                        bit 0 set on the last) then -1
@@ -35,8 +35,9 @@ namespace trd {
 struct CellInfo {
   int32_t a;  // occupied: byte offset of the cell's list in wrefs; empty: -(Chebyshev distance)
   int32_t c;  // occupied: the list's first entry (16 x id, bit 0: the only one); empty: bit 31
-              // set, and in bits 3o..3o+2 how many cells farther than the distance a ray
-              // in octant o (bit a of o: direction negative on axis a) may jump
+              // set, and in bits 3o..3o+2 the M of the empty block of 2M + 1 cells per
+              // axis ahead of the cell for a ray in octant o (bit a of o: direction
+              // negative on axis a)
 };
 static_assert(sizeof(CellInfo) == 8, "CellInfo is two words");
 

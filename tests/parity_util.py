@@ -110,28 +110,26 @@ def chebyshev_capped(occ, cap=32):
     return dist
 
 
-def octant_extensions(occ, dist, cap=32):
-    """Per empty cell, the 3-bit jump extensions of the FP32 walk's cell
+def octant_blocks(occ, cap=32):
+    """Per empty cell, the octant fields of the FP32 walk's empty-cell
     record, packed by octant o (bit a of o: direction negative on axis a),
-    from the plain definition: M is the largest m for which the cell m steps
-    along the octant's diagonal lies in the grid and the block of 2m + 1
-    cells per axis ahead of the cell in that octant (clipped to the grid)
-    holds no occupied cell; e = min(7, cap - d, max(0, 2M + 1 - d)) with d
-    the cell's capped Chebyshev distance.  Block sums come from a
-    summed-volume table of the occupancy, not from the distance field.
-    occ, dist: [z][y][x]; returns uint32 [z][y][x] (0 on occupied cells)."""
+    from the plain definition: M is the largest m <= min(7, (cap - 1) // 2)
+    for which the cell m steps along the octant's diagonal lies in the grid
+    and the block of 2m + 1 cells per axis ahead of the cell in that octant
+    (clipped to the grid) holds no occupied cell.  Block sums come from a
+    summed-volume table of the occupancy, not from a distance field.
+    occ: [z][y][x]; returns uint32 [z][y][x] (0 on occupied cells)."""
     nz, ny, nx = occ.shape
     sv = np.zeros((nz + 1, ny + 1, nx + 1), dtype=np.int64)
     sv[1:, 1:, 1:] = occ.astype(np.int64).cumsum(0).cumsum(1).cumsum(2)
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    d = np.maximum(dist, 1)
-    lim = np.minimum(7, cap - d)
+    mcap = min(7, (cap - 1) // 2)
     out = np.zeros(occ.shape, dtype=np.uint32)
     for o in range(8):
         s = [(-1 if (o >> a) & 1 else 1) for a in range(3)]  # x, y, z
         M = np.zeros(occ.shape, dtype=np.int64)
         alive = ~occ
-        for m in range(1, 21):
+        for m in range(1, mcap + 1):
             ends = []
             inside = np.ones(occ.shape, dtype=bool)
             for c, sa, n in ((x, s[0], nx), (y, s[1], ny), (z, s[2], nz)):
@@ -145,8 +143,7 @@ def octant_extensions(occ, dist, cap=32):
                    + sv[z0, y0, x1] + sv[z0, y1, x0] + sv[z1, y0, x0] - sv[z0, y0, x0])
             alive = alive & inside & (tot == 0)
             M[alive] = m
-        e = np.minimum(lim, np.maximum(0, 2 * M + 1 - d))
-        out |= np.where(occ, 0, e).astype(np.uint32) << np.uint32(3 * o)
+        out |= np.where(occ, 0, M).astype(np.uint32) << np.uint32(3 * o)
     return out
 
 

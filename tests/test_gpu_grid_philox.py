@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import scenegen
-from parity_util import chebyshev_capped, octant_extensions
+from parity_util import chebyshev_capped, octant_blocks
 
 pytestmark = pytest.mark.gpu
 
@@ -60,13 +60,12 @@ def test_walk_view_matches_grid(tr, which, lam):
     occ = cnt > 0
     dist = chebyshev_capped(occ.reshape(res[2], res[1], res[0])).ravel()
     assert len(wr) == n_refs + int(occ.sum())
-    # empty cells: (-distance, bit 31 and the jump extension of each octant)
+    # empty cells: (-distance, bit 31 and the empty block ahead per octant)
     assert np.array_equal(ci[~occ, 0], -np.maximum(dist[~occ], 1))
-    ext = octant_extensions(occ.reshape(res[2], res[1], res[0]),
-                            dist.reshape(res[2], res[1], res[0])).ravel()
+    ext = octant_blocks(occ.reshape(res[2], res[1], res[0])).ravel()
     want_c = (ext[~occ] | np.uint32(0x80000000)).view(np.int32)
     assert np.array_equal(ci[~occ, 1], want_c)
-    print("empty cells", int((~occ).sum()), "with an extension", int((ext[~occ] != 0).sum()), flush=True)
+    print("empty cells", int((~occ).sum()), "with a block ahead", int((ext[~occ] != 0).sum()), flush=True)
     # occupied cells: byte offset of the list (4 x the exclusive prefix of
     # list lengths + 1) and its first entry, 16 x the first id, bit 0 set
     # when that entry is the list's only one
