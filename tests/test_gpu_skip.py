@@ -76,3 +76,56 @@ def test_errors(tr):
     with pytest.raises(tr.TRError) as e:
         gs.set_max_skip(40)
     assert e.value.status == -1
+
+
+def _sparse_scene():
+    # spheres and bonds scattered through a box many cells wide, so most
+    # cells are empty and the octant blocks ahead of them are long
+    rng = np.random.default_rng(11)
+    cen = rng.uniform(-20.0, 20.0, (40, 3))
+    rad = rng.uniform(0.4, 1.2, 40)
+    a = cen[:12] + rng.normal(0.0, 1.0, (12, 3))
+    b = a + rng.normal(0.0, 3.0, (12, 3))
+    ld = np.array([[-0.5, 0.5, 1.0], [1.0, -2.0, 0.5]])
+    ld /= np.linalg.norm(ld, axis=1, keepdims=True)
+    return scenegen.Scene(cen, rad, rng.uniform(0.3, 1.0, (40, 3)).astype(np.float32),
+                          a, b, np.full(12, 0.3), rng.uniform(0.3, 1.0, (12, 3)).astype(np.float32),
+                          ld, np.ones((2, 3)))
+
+
+@pytest.mark.parametrize("view", ["corners", "axis"])
+def test_octant_jumps_sparse(tr, oracle_mod, view):
+    """Jumps over the empty blocks ahead of a ray, per octant: camera rays
+    from the 8 corners of a sparse scene (every octant of directions), or
+    along an axis (direction components at or near 0), with AO rays in all
+    directions, meet the FP32 bar against brute force and agree with the
+    plain walk (max_skip 1), and the jumps are taken."""
+    import torch
+    s = _sparse_scene()
+    p = scenegen.Params(ao_samples=4, seed=5)
+    if view == "corners":
+        cams = [scenegen.Camera((sx * 45.0, sy * 45.0, sz * 45.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0),
+                                40.0, 48, 48)
+                for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)]
+    else:
+        cams = [scenegen.Camera((-60.0, 0.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 45.0, 65, 65)]
+    on, off = tr.Scene(s), tr.Scene(s, max_skip=1)
+    for i, c in enumerate(cams):
+        print("octant view", view, i, flush=True)
+        ref = oracle_mod.render(s, c, p, grid=None)
+        assert (ref["hit_id"] >= 0).mean() > 0.02  # the view sees geometry
+        got = {}
+        for name, gs in (("on", on), ("off", off)):
+            fr = tr.render(gs, c, p, precision="fp32_resolve", outputs=OUT, stats=True,
+                           tune={"count_ops": 1})
+            torch.cuda.synchronize()
+            g = frame_to_numpy(fr)
+            m = compare(g, ref, p.ao_samples, s.n_lights)
+            print(name, m, flush=True)
+            assert_fp32_parity(m)
+            got[name] = g
+        st = dict(zip(tr.STAT_NAMES, got["on"]["stats"].tolist()))
+        st1 = dict(zip(tr.STAT_NAMES, got["off"]["stats"].tolist()))
+        assert st["jumps"] > 0 and st1["jumps"] == 0
+        assert st["cells"] < st1["cells"]
+        assert (got["on"]["hit_id"] == got["off"]["hit_id"]).mean() >= 0.9999
